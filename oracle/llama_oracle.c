@@ -1,0 +1,485 @@
+/*
+ * llama_oracle.c -- CPU oracle for the layout-aware copy.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+ * GPU library is checked against.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load it; the library never does.  It shares
+ * no code, header, table or helper with the GPU path: it has its own record
+ * parser, its own flattening and its own mapping formulas.
+ *
+ * What it computes (LLAMA paper, section 3 "Design" and section 4.2):
+ *
+ *  - Record dimension (sec. 3.3 "Describing a data structure", Listings 1-2):
+ *    a nested record of fields; a field is an elemental type or another
+ *    record; a field of static array type T[n] is a record of n fields of T.
+ *    Leaves are enumerated depth first in declaration order, which is the order
+ *    forEachLeaf visits record coordinates (sec. 3.6 "C++ integration").
+ *
+ *  - Array dimensions: N-D extents; coordinates are visited in row-major order,
+ *    last index fastest (ArrayDimsIndexRange, sec. 3.6), and a coordinate is
+ *    linearised row-major (the index linearisation in Listing 4).
+ *
+ *  - Mappings (sec. 3.7 "Mappings"), each a function
+ *    (array coordinate, leaf) -> (blob number, byte offset):
+ *      AoS      fields one after another, repeated once per record; the fields
+ *               either tightly packed or each padded to its type's alignment.
+ *      SoA      per field, all records' values contiguous; either one blob per
+ *               field (multi-blob) or all fields in one blob (single-blob),
+ *               without padding between the sub-arrays (sec. 4.4 notes that
+ *               SoA inserts no padding between its sub-arrays).
+ *      AoSoA L  like AoS but each field repeated L times before the next
+ *               field; the linear index i splits as (i / L, i mod L)
+ *               (sec. 4.1).
+ *
+ *  - Copy (sec. 3.9 "Copying between views", sec. 4.2 "Layout changing
+ *    copying"): the naive copy, nested loops over the array dimensions (outer)
+ *    and the record leaves (inner), copying field by field through both
+ *    mappings.  Bytes are copied verbatim, never as typed values.
+ *
+ * Readings where the paper is silent (each is listed with its reason in the
+ * design notes of the repository):
+ *   - aligned AoS follows the C struct rule on the flattened leaves: each leaf
+ *     offset rounds up to the leaf's alignment, and the record stride rounds up
+ *     to the largest leaf alignment (Listings 1 and 2 are declared equivalent);
+ *     nested records add no padding of their own;
+ *   - AoSoA blocks are packed: the chunk of leaf f starts at L * (packed offset
+ *     of f), a block is L * (packed record size) bytes, the blob holds
+ *     ceil(N / L) blocks;
+ *   - multi-blob SoA has one blob per leaf, in leaf order;
+ *   - destination bytes that no (coordinate, leaf) pair maps to (alignment gaps
+ *     of aligned AoS, unused lanes of the last AoSoA block) are set to zero.
+ *
+ * Arithmetic: plain unsigned 64-bit integers, plain '/' and '%'.  No shifts,
+ * masks, tiling, blocking or reordering.
+ */
+#include <stdint.h>
+#include <stddef.h>
+#include <string.h>
+
+#define ORC_MAX_RANK 8
+
+/* mapping kinds */
+#define ORC_AOS_PACKED 0
+#define ORC_AOS_ALIGNED 1
+#define ORC_SOA_SINGLE 2
+#define ORC_SOA_MULTI 3
+#define ORC_AOSOA 4
+
+/* error codes */
+#define ORC_OK 0
+#define ORC_E_PARSE -1
+#define ORC_E_TOO_MANY -2
+#define ORC_E_ARG -3
+
+typedef struct {
+    int32_t nleaves;
+    const uint64_t* size;  /* bytes of each leaf, in leaf order */
+    const uint64_t* align; /* alignment of each leaf */
+} orc_record;
+
+typedef struct {
+    int32_t kind;
+    int32_t rank;
+    uint64_t extents[ORC_MAX_RANK];
+    uint64_t lanes; /* AoSoA only */
+} orc_mapping;
+
+/* ---------------------------------------------------------------------------
+ * Record parsing and flattening (sec. 3.3, Listings 1-2).
+ *
+ * Grammar:  record := '{' member (',' member)* '}'
+ *           member := (type | record) ('[' count ']')?
+ * type names: u8 i8 bool  (1 byte)   u16 i16 f16 bf16 (2 bytes)
+ *             u32 i32 f32 (4 bytes)  u64 i64 f64      (8 bytes);
+ * every elemental type is aligned to its own size.
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    const char* p;
+    uint64_t* size;
+    uint64_t* align;
+    int max;
+    int n;
+    int err;
+} orc_parser;
+
+static void skip_space(orc_parser* ps)
+{
+    while (*ps->p == ' ' || *ps->p == '\t' || *ps->p == '\n')
+        ps->p++;
+}
+
+static int elemental_size(const char* name, size_t len, uint64_t* out)
+{
+    static const struct { const char* name; uint64_t size; } types[] = {
+        {"u8", 1},  {"i8", 1},  {"bool", 1}, {"u16", 2}, {"i16", 2},
+        {"f16", 2}, {"bf16", 2}, {"u32", 4}, {"i32", 4}, {"f32", 4},
+        {"u64", 8}, {"i64", 8}, {"f64", 8},
+    };
+    for (size_t k = 0; k < sizeof(types) / sizeof(types[0]); k++) {
+        if (strlen(types[k].name) == len && strncmp(types[k].name, name, len) == 0) {
+            *out = types[k].size;
+            return 1;
+        }
+    }
+    return 0;
+}
+
+static void parse_record(orc_parser* ps);
+
+/* Parses one member and appends its leaves; a trailing [n] repeats them n
+ * times (a static array becomes a record of n fields, sec. 3.3). */
+static void parse_member(orc_parser* ps)
+{
+    skip_space(ps);
+    int first = ps->n;
+    if (*ps->p == '{') {
+        parse_record(ps);
+    } else {
+        const char* start = ps->p;
+        while ((*ps->p >= 'a' && *ps->p <= 'z') || (*ps->p >= '0' && *ps->p <= '9'))
+            ps->p++;
+        uint64_t s;
+        if (!elemental_size(start, (size_t)(ps->p - start), &s)) {
+            ps->err = ORC_E_PARSE;
+            return;
+        }
+        if (ps->n >= ps->max) {
+            ps->err = ORC_E_TOO_MANY;
+            return;
+        }
+        ps->size[ps->n] = s;
+        ps->align[ps->n] = s;
+        ps->n++;
+    }
+    if (ps->err)
+        return;
+    skip_space(ps);
+    if (*ps->p == '[') {
+        ps->p++;
+        uint64_t count = 0;
+        int digits = 0;
+        while (*ps->p >= '0' && *ps->p <= '9') {
+            count = count * 10 + (uint64_t)(*ps->p - '0');
+            ps->p++;
+            digits++;
+        }
+        skip_space(ps);
+        if (!digits || count == 0 || *ps->p != ']') {
+            ps->err = ORC_E_PARSE;
+            return;
+        }
+        ps->p++;
+        int one = ps->n - first; /* leaves of a single element */
+        for (uint64_t c = 1; c < count; c++) {
+            for (int k = 0; k < one; k++) {
+                if (ps->n >= ps->max) {
+                    ps->err = ORC_E_TOO_MANY;
+                    return;
+                }
+                ps->size[ps->n] = ps->size[first + k];
+                ps->align[ps->n] = ps->align[first + k];
+                ps->n++;
+            }
+        }
+    }
+}
+
+static void parse_record(orc_parser* ps)
+{
+    skip_space(ps);
+    if (*ps->p != '{') {
+        ps->err = ORC_E_PARSE;
+        return;
+    }
+    ps->p++;
+    for (;;) {
+        parse_member(ps);
+        if (ps->err)
+            return;
+        skip_space(ps);
+        if (*ps->p == ',') {
+            ps->p++;
+            continue;
+        }
+        if (*ps->p == '}') {
+            ps->p++;
+            return;
+        }
+        ps->err = ORC_E_PARSE;
+        return;
+    }
+}
+
+/* Flattens a record spec into leaf sizes and alignments in depth-first
+ * declaration order.  Returns the leaf count, or a negative error. */
+int orc_parse_record(const char* spec, uint64_t* size, uint64_t* align, int max_leaves)
+{
+    orc_parser ps = {spec, size, align, max_leaves, 0, 0};
+    parse_record(&ps);
+    if (ps.err)
+        return ps.err;
+    skip_space(&ps);
+    if (*ps.p != '\0')
+        return ORC_E_PARSE;
+    return ps.n;
+}
+
+/* ---------------------------------------------------------------------------
+ * Record-dimension sizes and offsets (sec. 3.7: "computing sizes and offsets
+ * in the record dimension").
+ * ------------------------------------------------------------------------- */
+
+static uint64_t round_up(uint64_t x, uint64_t a)
+{
+    return (x + a - 1) / a * a;
+}
+
+/* packed offset of leaf f: the sum of the sizes of the leaves before it */
+uint64_t orc_packed_offset(const orc_record* r, int f)
+{
+    uint64_t off = 0;
+    for (int g = 0; g < f; g++)
+        off += r->size[g];
+    return off;
+}
+
+/* packed record size: the sum of all leaf sizes */
+uint64_t orc_packed_size(const orc_record* r)
+{
+    return orc_packed_offset(r, r->nleaves);
+}
+
+/* aligned offset of leaf f: each leaf starts at the next multiple of its own
+ * alignment after the end of the previous leaf */
+uint64_t orc_aligned_offset(const orc_record* r, int f)
+{
+    uint64_t off = 0;
+    for (int g = 0; g <= f; g++) {
+        off = round_up(off, r->align[g]);
+        if (g < f)
+            off += r->size[g];
+    }
+    return off;
+}
+
+/* aligned record stride: end of the last leaf rounded up to the largest
+ * alignment, so that the next record is aligned as well */
+uint64_t orc_aligned_size(const orc_record* r)
+{
+    uint64_t max_align = 1;
+    for (int g = 0; g < r->nleaves; g++)
+        if (r->align[g] > max_align)
+            max_align = r->align[g];
+    if (r->nleaves == 0)
+        return 0;
+    uint64_t end = orc_aligned_offset(r, r->nleaves - 1) + r->size[r->nleaves - 1];
+    return round_up(end, max_align);
+}
+
+/* ---------------------------------------------------------------------------
+ * Array dimensions (sec. 3.6 ArrayDimsIndexRange; Listing 4 linearisation).
+ * ------------------------------------------------------------------------- */
+
+uint64_t orc_record_count(const orc_mapping* m)
+{
+    uint64_t n = 1;
+    for (int d = 0; d < m->rank; d++)
+        n *= m->extents[d];
+    return n;
+}
+
+/* row-major linear index of a coordinate, last index fastest */
+uint64_t orc_linearize(const orc_mapping* m, const uint64_t* coord)
+{
+    uint64_t i = 0;
+    for (int d = 0; d < m->rank; d++)
+        i = i * m->extents[d] + coord[d];
+    return i;
+}
+
+/* advances a coordinate to the next one in row-major order; returns 0 after
+ * the last coordinate */
+static int next_coord(const orc_mapping* m, uint64_t* coord)
+{
+    for (int d = m->rank - 1; d >= 0; d--) {
+        coord[d]++;
+        if (coord[d] < m->extents[d])
+            return 1;
+        coord[d] = 0;
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Mappings (sec. 3.7): blob count, blob sizes, blobNrAndOffset.
+ * ------------------------------------------------------------------------- */
+
+int orc_blob_count(const orc_mapping* m, const orc_record* r)
+{
+    if (m->kind == ORC_SOA_MULTI)
+        return r->nleaves;
+    return 1;
+}
+
+uint64_t orc_blob_size(const orc_mapping* m, const orc_record* r, int blob)
+{
+    uint64_t n = orc_record_count(m);
+    switch (m->kind) {
+    case ORC_AOS_PACKED:
+        return n * orc_packed_size(r);
+    case ORC_AOS_ALIGNED:
+        return n * orc_aligned_size(r);
+    case ORC_SOA_SINGLE:
+        return n * orc_packed_size(r);
+    case ORC_SOA_MULTI:
+        return n * r->size[blob];
+    case ORC_AOSOA: {
+        uint64_t blocks = (n + m->lanes - 1) / m->lanes;
+        return blocks * m->lanes * orc_packed_size(r);
+    }
+    }
+    return 0;
+}
+
+/* The mapping function: where leaf f of the record at `coord` lives. */
+int orc_blob_nr_and_offset(const orc_mapping* m, const orc_record* r, const uint64_t* coord,
+                           int f, uint64_t* blob, uint64_t* offset)
+{
+    if (f < 0 || f >= r->nleaves)
+        return ORC_E_ARG;
+    uint64_t n = orc_record_count(m);
+    uint64_t i = orc_linearize(m, coord);
+    switch (m->kind) {
+    case ORC_AOS_PACKED: /* record i at i * S, leaf f at its packed offset */
+        *blob = 0;
+        *offset = i * orc_packed_size(r) + orc_packed_offset(r, f);
+        return ORC_OK;
+    case ORC_AOS_ALIGNED: /* record i at i * R, leaf f at its aligned offset */
+        *blob = 0;
+        *offset = i * orc_aligned_size(r) + orc_aligned_offset(r, f);
+        return ORC_OK;
+    case ORC_SOA_SINGLE: /* sub-array of leaf f after the sub-arrays of 0..f-1 */
+        *blob = 0;
+        *offset = n * orc_packed_offset(r, f) + i * r->size[f];
+        return ORC_OK;
+    case ORC_SOA_MULTI: /* sub-array of leaf f in blob f */
+        *blob = (uint64_t)f;
+        *offset = i * r->size[f];
+        return ORC_OK;
+    case ORC_AOSOA: { /* block i / L; inside it leaf f's L values, lane i mod L */
+        uint64_t L = m->lanes;
+        uint64_t block = i / L;
+        uint64_t lane = i % L;
+        *blob = 0;
+        *offset = block * (L * orc_packed_size(r)) + L * orc_packed_offset(r, f) + lane * r->size[f];
+        return ORC_OK;
+    }
+    }
+    return ORC_E_ARG;
+}
+
+/* ---------------------------------------------------------------------------
+ * Validation shared by the entry points below.
+ * ------------------------------------------------------------------------- */
+
+static int valid_mapping(const orc_mapping* m)
+{
+    if (m->rank < 1 || m->rank > ORC_MAX_RANK)
+        return 0;
+    if (m->kind < ORC_AOS_PACKED || m->kind > ORC_AOSOA)
+        return 0;
+    if (m->kind == ORC_AOSOA && m->lanes == 0)
+        return 0;
+    return 1;
+}
+
+static int same_extents(const orc_mapping* a, const orc_mapping* b)
+{
+    if (a->rank != b->rank)
+        return 0;
+    for (int d = 0; d < a->rank; d++)
+        if (a->extents[d] != b->extents[d])
+            return 0;
+    return 1;
+}
+
+/* ---------------------------------------------------------------------------
+ * The copy (sec. 3.9, sec. 4.2 naive copy).
+ * ------------------------------------------------------------------------- */
+
+/* Copies every (coordinate, leaf) value of the source view into the
+ * destination view.  Destination bytes that no value maps to are zero. */
+int orc_copy(const orc_record* r, const orc_mapping* src, uint8_t* const* src_blobs,
+             const orc_mapping* dst, uint8_t* const* dst_blobs)
+{
+    if (!valid_mapping(src) || !valid_mapping(dst) || !same_extents(src, dst))
+        return ORC_E_ARG;
+    /* padding policy: the whole destination starts at zero */
+    for (int b = 0; b < orc_blob_count(dst, r); b++)
+        memset(dst_blobs[b], 0, (size_t)orc_blob_size(dst, r, b));
+    if (orc_record_count(src) == 0)
+        return ORC_OK;
+    uint64_t coord[ORC_MAX_RANK] = {0};
+    do {
+        for (int f = 0; f < r->nleaves; f++) {
+            uint64_t bs, os, bd, od;
+            orc_blob_nr_and_offset(src, r, coord, f, &bs, &os);
+            orc_blob_nr_and_offset(dst, r, coord, f, &bd, &od);
+            memcpy(dst_blobs[bd] + od, src_blobs[bs] + os, (size_t)r->size[f]);
+        }
+    } while (next_coord(src, coord));
+    return ORC_OK;
+}
+
+/* Adds one to counts[b][o] for every byte o of blob b that a (coordinate, leaf)
+ * value maps to.  Used to check that a mapping is injective and which of its
+ * bytes are padding. */
+int orc_write_counts(const orc_record* r, const orc_mapping* m, uint32_t* const* counts)
+{
+    if (!valid_mapping(m))
+        return ORC_E_ARG;
+    if (orc_record_count(m) == 0)
+        return ORC_OK;
+    uint64_t coord[ORC_MAX_RANK] = {0};
+    do {
+        for (int f = 0; f < r->nleaves; f++) {
+            uint64_t b, o;
+            orc_blob_nr_and_offset(m, r, coord, f, &b, &o);
+            for (uint64_t k = 0; k < r->size[f]; k++)
+                counts[b][o + k]++;
+        }
+    } while (next_coord(m, coord));
+    return ORC_OK;
+}
+
+/* Checks sampled values of a finished copy one by one: for each sample
+ * (linear index idx[k], leaf leaf[k]) the destination bytes must equal the
+ * source bytes, both located through the mappings.  Returns the number of
+ * mismatching samples; the first mismatch index goes to *first_bad. */
+int64_t orc_check_samples(const orc_record* r, const orc_mapping* src, uint8_t* const* src_blobs,
+                          const orc_mapping* dst, uint8_t* const* dst_blobs, const uint64_t* idx,
+                          const int32_t* leaf, int64_t nsamples, int64_t* first_bad)
+{
+    int64_t bad = 0;
+    *first_bad = -1;
+    for (int64_t k = 0; k < nsamples; k++) {
+        /* the coordinate of linear index idx[k], row-major */
+        uint64_t coord[ORC_MAX_RANK];
+        uint64_t rest = idx[k];
+        for (int d = src->rank - 1; d >= 0; d--) {
+            coord[d] = rest % src->extents[d];
+            rest /= src->extents[d];
+        }
+        uint64_t bs, os, bd, od;
+        if (orc_blob_nr_and_offset(src, r, coord, leaf[k], &bs, &os) != ORC_OK ||
+            orc_blob_nr_and_offset(dst, r, coord, leaf[k], &bd, &od) != ORC_OK)
+            return -1;
+        if (memcmp(dst_blobs[bd] + od, src_blobs[bs] + os, (size_t)r->size[leaf[k]]) != 0) {
+            if (*first_bad < 0)
+                *first_bad = k;
+            bad++;
+        }
+    }
+    return bad;
+}

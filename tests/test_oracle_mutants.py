@@ -1,0 +1,51 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake (a dropped term, a wrong index, a wrong operand) in
+a copy of the oracle's C source, builds it on the CPU, and runs the pin suite
+against that build in a subprocess.  The pin suite must fail for every mutant.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "llama_oracle.c")
+
+MUTANTS = {
+    "aligned_offset_no_rounding": ("off = round_up(off, r->align[g]);", "off = off;"),
+    "aligned_stride_no_tail_rounding": ("return round_up(end, max_align);", "return end;"),
+    "packed_offset_drops_a_leaf": ("for (int g = 0; g < f; g++)", "for (int g = 1; g < f; g++)"),
+    "linearize_wrong_extent": ("i = i * m->extents[d] + coord[d];", "i = i * m->extents[0] + coord[d];"),
+    "soa_single_wrong_element_size": ("*offset = n * orc_packed_offset(r, f) + i * r->size[f];",
+                                      "*offset = n * orc_packed_offset(r, f) + i * r->size[0];"),
+    "soa_single_base_uses_index": ("*offset = n * orc_packed_offset(r, f) + i * r->size[f];",
+                                   "*offset = i * orc_packed_offset(r, f) + i * r->size[f];"),
+    "soa_multi_one_blob": ("*blob = (uint64_t)f;", "*blob = 0;"),
+    "aosoa_lane_stride": ("lane * r->size[f];", "lane * r->size[0];"),
+    "aosoa_block_stride_aligned": ("block * (L * orc_packed_size(r))", "block * (L * orc_aligned_size(r))"),
+    "aosoa_swapped_split": ("uint64_t block = i / L;\n        uint64_t lane = i % L;",
+                            "uint64_t block = i % L;\n        uint64_t lane = i / L;"),
+    "aosoa_blob_size_no_tail": ("return blocks * m->lanes * orc_packed_size(r);", "return n * orc_packed_size(r);"),
+    "padding_not_zeroed": ("memset(dst_blobs[b], 0, (size_t)orc_blob_size(dst, r, b));", "(void)0;"),
+    "static_array_one_short": ("for (uint64_t c = 1; c < count; c++)", "for (uint64_t c = 2; c < count; c++)"),
+    "aos_aligned_uses_packed_stride": ("*offset = i * orc_aligned_size(r) + orc_aligned_offset(r, f);",
+                                       "*offset = i * orc_packed_size(r) + orc_aligned_offset(r, f);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_reject_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+    mutant_c = tmp_path / "mutant.c"
+    mutant_c.write_text(src.replace(old, new))
+    lib = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", str(mutant_c), "-o", str(lib)])
+    env = dict(os.environ, LLAMA_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0, f"pins did not catch mutant {name}:\n{r.stdout[-2000:]}"

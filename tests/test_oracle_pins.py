@@ -1,0 +1,439 @@
+"""Pins of the CPU oracle against facts fixed outside the oracle itself.
+
+Each test compares the oracle with something it does not share code with: the
+C compiler's struct layout (ctypes), numpy structured dtypes and reshapes, a
+constructive byte-by-byte serialiser written from the paper's prose definitions
+of the mappings (LLAMA sec. 3.7), the iteration order the paper prints
+(sec. 3.6, Listing 7), equivalences the paper states (sec. 4.2: SoA is AoSoA
+with L equal to the record count; sec. 3.9: identical mappings copy as memcpy),
+and invariants of a byte permutation (round trip, composition, exactly-once
+coverage).
+"""
+import ctypes
+import os
+import random
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st, HealthCheck
+
+from paper_2106_04284_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+KINDS = ["aos_packed", "aos_aligned", "soa_single", "soa_multi", "aosoa"]
+SIZES = {"u8": 1, "i8": 1, "bool": 1, "u16": 2, "i16": 2, "u32": 4, "i32": 4, "f32": 4,
+         "u64": 8, "i64": 8, "f64": 8}
+
+
+def _golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+def _layouts(lanes=(1, 2, 4, 8, 32, 64)):
+    out = [(k, 0) for k in KINDS if k != "aosoa"]
+    out += [("aosoa", L) for L in lanes]
+    return out
+
+
+def _unique_leaf_values(types, n, seed):
+    """Per-leaf arrays whose bytes are random; records stay distinguishable."""
+    return W.typed_random_values(types, n, seed)
+
+
+def _soa_multi_blobs(values):
+    return [np.ascontiguousarray(v).view(np.uint8).reshape(-1).copy() for v in values]
+
+
+def _build(orc, rec, kind, extents, lanes, values):
+    """A source blob set of the given layout holding `values` (per leaf), built
+    by the oracle from the multi-blob SoA form (whose blobs are the per-leaf
+    arrays by definition)."""
+    r = orc.Record(rec)
+    mb = orc.Mapping(r, "soa_multi", extents)
+    m = orc.Mapping(r, kind, extents, lanes)
+    return orc.copy(mb, _soa_multi_blobs(values), m)
+
+
+# --------------------------------------------------------------------------
+# Serialiser written from the paper's prose (sec. 3.7 "Mappings"), building
+# each layout by appending bytes; it computes no offsets.
+# --------------------------------------------------------------------------
+
+def _serialise(types, values, kind, n, lanes):
+    leaf_bytes = [np.ascontiguousarray(v).view(np.uint8).reshape(n, -1) if n else None for v in values]
+    maxa = max(SIZES[t] for t in types)
+
+    def val(i, f):
+        return bytes(leaf_bytes[f][i]) if n else b""
+
+    if kind in ("aos_packed", "aos_aligned"):
+        out = bytearray()
+        for i in range(n):
+            start = len(out)
+            for f, t in enumerate(types):
+                if kind == "aos_aligned":
+                    while (len(out) - start) % SIZES[t]:
+                        out.append(0)
+                out += val(i, f)
+            if kind == "aos_aligned":
+                while (len(out) - start) % maxa:
+                    out.append(0)
+        return [bytes(out)]
+    if kind == "soa_single":
+        out = bytearray()
+        for f in range(len(types)):
+            for i in range(n):
+                out += val(i, f)
+        return [bytes(out)]
+    if kind == "soa_multi":
+        blobs = []
+        for f in range(len(types)):
+            b = bytearray()
+            for i in range(n):
+                b += val(i, f)
+            blobs.append(bytes(b))
+        return blobs
+    if kind == "aosoa":
+        out = bytearray()
+        i0 = 0
+        while i0 < n:
+            for f, t in enumerate(types):
+                for lane in range(lanes):
+                    i = i0 + lane
+                    out += val(i, f) if i < n else bytes(SIZES[t])
+            i0 += lanes
+        return [bytes(out)]
+    raise ValueError(kind)
+
+
+# --------------------------------------------------------------------------
+# record flattening (sec. 3.3, Listings 1-2)
+# --------------------------------------------------------------------------
+
+def test_listing1_leaf_order_and_sizes(orc):
+    rows = _golden("listing1_particle.txt")
+    r = orc.Record(W.LISTING1)
+    assert r.nleaves == len(rows)
+    assert r.sizes == [int(row[2]) for row in rows]
+    assert W.leaf_types(W.LISTING1) == [row[1] for row in rows]
+
+
+def test_listing2_c_struct_equals_aligned_aos(orc):
+    """Listing 2's ParticleCpp, laid out by the C compiler's rules (ctypes),
+    must equal the aligned AoS record of Listing 1: leaf offsets and stride."""
+    class VecCpp(ctypes.Structure):
+        _fields_ = [("x", ctypes.c_float), ("y", ctypes.c_float)]
+
+    class ParticleCpp(ctypes.Structure):
+        _fields_ = [("id", ctypes.c_uint16), ("pos", VecCpp), ("mass", ctypes.c_double),
+                    ("flags", ctypes.c_bool * 3)]
+
+    c_offsets = [ParticleCpp.id.offset, ParticleCpp.pos.offset + VecCpp.x.offset,
+                 ParticleCpp.pos.offset + VecCpp.y.offset, ParticleCpp.mass.offset,
+                 ParticleCpp.flags.offset, ParticleCpp.flags.offset + 1, ParticleCpp.flags.offset + 2]
+    r = orc.Record(W.LISTING1)
+    assert [r.aligned_offset(f) for f in range(r.nleaves)] == c_offsets
+    assert r.aligned_size == ctypes.sizeof(ParticleCpp)
+    assert r.packed_size == sum(ctypes.sizeof(t) for t in
+                                (ctypes.c_uint16, ctypes.c_float, ctypes.c_float, ctypes.c_double)) + 3
+
+
+@pytest.mark.parametrize("name", ["particle", "lbm", "mixed", "listing1"])
+def test_record_sizes_against_numpy_dtypes(orc, name):
+    """Packed offsets/size equal a numpy packed structured dtype; aligned ones
+    equal numpy's align=True (C rule) dtype of the flattened leaves."""
+    types = W.leaf_types(W.RECORDS[name])
+    r = orc.Record(W.RECORDS[name])
+    fields = [(f"f{k}", W.NP_DTYPES[t]) for k, t in enumerate(types)]
+    packed = np.dtype(fields, align=False)
+    aligned = np.dtype(fields, align=True)
+    assert [r.packed_offset(f) for f in range(r.nleaves)] == [packed.fields[f"f{k}"][1] for k in range(len(types))]
+    assert r.packed_size == packed.itemsize
+    assert [r.aligned_offset(f) for f in range(r.nleaves)] == [aligned.fields[f"f{k}"][1] for k in range(len(types))]
+    assert r.aligned_size == aligned.itemsize
+
+
+def test_config_record_figures(orc):
+    """Sizes of the workload records, each also fixed by a numpy dtype above."""
+    p, l, m = (orc.Record(W.RECORDS[k]) for k in ("particle", "lbm", "mixed"))
+    assert (p.nleaves, p.packed_size, p.aligned_size) == (7, 28, 28)
+    assert (l.nleaves, l.packed_size, l.aligned_size) == (20, 156, 160)
+    assert (m.nleaves, m.packed_size, m.aligned_size) == (10, 49, 56)
+    assert [m.aligned_offset(f) for f in range(10)] == [0, 8, 16, 24, 28, 32, 36, 40, 44, 48]
+
+
+def test_nested_static_arrays_flatten(orc):
+    r = orc.Record([(["u8", "f64"], 2), ("u16", 3)])
+    assert r.sizes == [1, 8, 1, 8, 2, 2, 2]
+    with pytest.raises(ValueError):
+        orc.Record("{f32,}")
+    with pytest.raises(ValueError):
+        orc.Record("{f33}")
+    with pytest.raises(ValueError):
+        orc.Record("{f32[0]}")
+
+
+# --------------------------------------------------------------------------
+# array dimensions (sec. 3.6 Listing 7; Listing 4)
+# --------------------------------------------------------------------------
+
+def test_index_range_order_matches_paper(orc):
+    rows = _golden("index_range_3x3.txt")
+    m = orc.Mapping(orc.Record(W.PARTICLE), "aos_packed", [3, 3])
+    assert [m.linearize([int(a), int(b)]) for a, b in rows] == list(range(9))
+
+
+@pytest.mark.parametrize("extents", [[5, 7], [2, 3, 4], [4, 1, 6, 3], [128, 256, 32]])
+def test_linearize_equals_numpy_ravel(orc, extents):
+    m = orc.Mapping(orc.Record(W.PARTICLE), "aos_packed", extents)
+    g = np.random.default_rng(7)
+    for _ in range(50):
+        c = [int(g.integers(0, e)) for e in extents]
+        assert m.linearize(c) == int(np.ravel_multi_index(c, extents))
+
+
+def test_copy_visits_coordinates_row_major(orc):
+    """A rank-3 copy AoS -> SoA equals a rank-1 copy of the same record count:
+    both mappings linearise the same way, so only the linear index matters."""
+    rec = W.PARTICLE
+    types = W.leaf_types(rec)
+    ext = [3, 5, 7]
+    vals = _unique_leaf_values(types, 105, 11)
+    a3 = _build(orc, rec, "aos_packed", ext, 0, vals)
+    a1 = _build(orc, rec, "aos_packed", [105], 0, vals)
+    assert all(np.array_equal(x, y) for x, y in zip(a3, a1))
+    # and the AoS of a rank-3 view equals numpy's C-order structured array
+    st_dt = np.dtype([(f"f{k}", W.NP_DTYPES[t]) for k, t in enumerate(types)])
+    arr = np.zeros(ext, dtype=st_dt)
+    for k in range(len(types)):
+        arr[f"f{k}"] = vals[k].reshape(ext)
+    assert np.array_equal(a3[0], arr.view(np.uint8).reshape(-1))
+
+
+# --------------------------------------------------------------------------
+# mappings against library routines and the constructive serialiser
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["particle", "mixed", "listing1", "lbm"])
+@pytest.mark.parametrize("n", [0, 1, 5, 64, 67])
+def test_layouts_equal_serialiser(orc, name, n):
+    rec = W.RECORDS[name]
+    types = W.leaf_types(rec)
+    vals = _unique_leaf_values(types, n, 100 + n)
+    for kind, lanes in _layouts():
+        got = _build(orc, rec, kind, [n], lanes, vals)
+        want = _serialise(types, vals, kind, n, lanes)
+        assert [bytes(b) for b in got] == want, (kind, lanes)
+
+
+@pytest.mark.parametrize("name", ["particle", "mixed"])
+def test_aos_equals_numpy_structured_array(orc, name):
+    types = W.leaf_types(W.RECORDS[name])
+    n = 257
+    vals = _unique_leaf_values(types, n, 3)
+    for align, kind in ((False, "aos_packed"), (True, "aos_aligned")):
+        dt = np.dtype([(f"f{k}", W.NP_DTYPES[t]) for k, t in enumerate(types)], align=align)
+        arr = np.zeros(n, dtype=dt)
+        for k in range(len(types)):
+            arr[f"f{k}"] = vals[k]
+        got = _build(orc, W.RECORDS[name], kind, [n], 0, vals)
+        assert np.array_equal(got[0], arr.view(np.uint8).reshape(-1)), kind
+
+
+@pytest.mark.parametrize("lanes", [1, 4, 8, 32, 64])
+@pytest.mark.parametrize("n", [64, 100, 257])
+def test_aosoa_equals_numpy_reshape_transpose(orc, lanes, n):
+    """For a record of equal-size leaves, AoSoA_L is the (F, N) value matrix,
+    tail-padded to whole blocks, reshaped (F, B, L) and transposed (B, F, L)."""
+    types = ["f32"] * 7
+    vals = [v.view(np.uint32) for v in _unique_leaf_values(types, n, 5)]
+    blocks = -(-n // lanes)
+    mat = np.zeros((7, blocks * lanes), dtype=np.uint32)
+    mat[:, :n] = np.stack(vals)
+    want = mat.reshape(7, blocks, lanes).transpose(1, 0, 2).copy().view(np.uint8).reshape(-1)
+    got = _build(orc, W.PARTICLE, "aosoa", [n], lanes, vals)
+    assert np.array_equal(got[0], want)
+
+
+def test_soa_blobs_equal_concatenation(orc):
+    types = W.leaf_types(W.MIXED)
+    n = 1001
+    vals = _unique_leaf_values(types, n, 9)
+    mb = _build(orc, W.MIXED, "soa_multi", [n], 0, vals)
+    sb = _build(orc, W.MIXED, "soa_single", [n], 0, vals)
+    for blob, v in zip(mb, vals):
+        assert np.array_equal(blob, v.view(np.uint8))
+    # no padding between the sub-arrays: SoA single-blob is the concatenation
+    assert np.array_equal(sb[0], np.concatenate(mb))
+
+
+# --------------------------------------------------------------------------
+# equivalences the paper states or implies
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["particle", "mixed", "lbm"])
+@pytest.mark.parametrize("n", [1, 7, 64, 300])
+def test_soa_is_aosoa_with_n_lanes(orc, name, n):
+    """Sec. 4.2: SoA can be seen as AoSoA with L equal to the record count."""
+    types = W.leaf_types(W.RECORDS[name])
+    vals = _unique_leaf_values(types, n, n)
+    sb = _build(orc, W.RECORDS[name], "soa_single", [n], 0, vals)
+    ao = _build(orc, W.RECORDS[name], "aosoa", [n], n, vals)
+    assert np.array_equal(sb[0], ao[0])
+
+
+@pytest.mark.parametrize("name", ["particle", "mixed", "lbm"])
+def test_packed_aos_is_aosoa_1(orc, name):
+    types = W.leaf_types(W.RECORDS[name])
+    vals = _unique_leaf_values(types, 77, 1)
+    a = _build(orc, W.RECORDS[name], "aos_packed", [77], 0, vals)
+    b = _build(orc, W.RECORDS[name], "aosoa", [77], 1, vals)
+    assert np.array_equal(a[0], b[0])
+
+
+def test_particle_packed_equals_aligned(orc):
+    vals = _unique_leaf_values(["f32"] * 7, 500, 2)
+    a = _build(orc, W.PARTICLE, "aos_packed", [500], 0, vals)
+    b = _build(orc, W.PARTICLE, "aos_aligned", [500], 0, vals)
+    assert np.array_equal(a[0], b[0])
+
+
+def test_identical_mappings_copy_is_memcpy(orc):
+    """Sec. 3.9: with identical mappings a raw copy of the blobs is correct;
+    with different mappings it is not."""
+    r = orc.Record(W.MIXED)
+    for kind, lanes in _layouts():
+        m = orc.Mapping(r, kind, [333], lanes)
+        vals = _unique_leaf_values(W.leaf_types(W.MIXED), 333, 4)
+        src = _build(orc, W.MIXED, kind, [333], lanes, vals)
+        out = orc.copy(m, src, orc.Mapping(r, kind, [333], lanes))
+        assert all(np.array_equal(x, y) for x, y in zip(out, src))
+    src = _build(orc, W.MIXED, "aos_packed", [333], 0, _unique_leaf_values(W.leaf_types(W.MIXED), 333, 4))
+    out = orc.copy(orc.Mapping(r, "aos_packed", [333]), src, orc.Mapping(r, "soa_single", [333]))
+    assert not np.array_equal(out[0], src[0])
+
+
+# --------------------------------------------------------------------------
+# invariants
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["particle", "mixed", "lbm", "listing1"])
+def test_exactly_once_and_padding_complement(orc, name):
+    """Every value byte lands on a distinct, in-bounds destination byte; the
+    bytes nobody writes are exactly the layout's padding, and they are the
+    only bytes the serialiser fills with zeros on its own."""
+    r = orc.Record(W.RECORDS[name])
+    n = 45
+    data_bytes = n * r.packed_size
+    for kind, lanes in _layouts():
+        m = orc.Mapping(r, kind, [n], lanes)
+        for i in range(n):
+            for f in range(r.nleaves):
+                b, o = m.blob_nr_and_offset([i], f)
+                assert o + r.sizes[f] <= m.blob_size(b)
+        counts = orc.write_counts(m)
+        assert all(int(c.max(initial=0)) <= 1 for c in counts), (kind, lanes)
+        assert sum(int(c.sum()) for c in counts) == data_bytes
+        pad_expected = {"aos_packed": 0, "soa_single": 0, "soa_multi": 0,
+                        "aos_aligned": n * (r.aligned_size - r.packed_size),
+                        "aosoa": (-(-n // max(lanes, 1)) * max(lanes, 1) - n) * r.packed_size}[kind]
+        assert sum(int((c == 0).sum()) for c in counts) == pad_expected
+
+
+@pytest.mark.parametrize("name", ["particle", "mixed", "lbm", "listing1"])
+def test_padding_is_zero_and_round_trip(orc, name):
+    """Random source bytes, padding included: the destination's padding is zero
+    whatever the source padding holds, and A -> B -> A restores every value
+    byte (and every byte when the source padding was zero)."""
+    r = orc.Record(W.RECORDS[name])
+    n = 131
+    lay = _layouts(lanes=(1, 8, 32))
+    for ka, la in lay:
+        a = orc.Mapping(r, ka, [n], la)
+        src = [W.random_bytes(s, 17 + k) for k, s in enumerate(a.blob_sizes())]
+        pad_a = orc.padding_masks(a)
+        for kb, lb in lay:
+            b = orc.Mapping(r, kb, [n], lb)
+            mid = orc.copy(a, src, b, b.alloc(fill=0xCD))
+            for blob, pad in zip(mid, orc.padding_masks(b)):
+                assert not blob[pad].any()
+            back = orc.copy(b, mid, a)
+            for x, y, pad in zip(back, src, pad_a):
+                assert np.array_equal(x[~pad], y[~pad])
+                assert not x[pad].any()
+
+
+def test_composition(orc):
+    """A -> B -> C equals A -> C for every triple of layouts."""
+    r = orc.Record(W.MIXED)
+    n = 70
+    lay = _layouts(lanes=(8, 32))
+    first = orc.Mapping(r, lay[0][0], [n], lay[0][1])
+    vals = _unique_leaf_values(W.leaf_types(W.MIXED), n, 21)
+    base = _build(orc, W.MIXED, lay[0][0], [n], lay[0][1], vals)
+    g = random.Random(5)
+    for _ in range(30):
+        (ka, la), (kb, lb), (kc, lc) = (g.choice(lay) for _ in range(3))
+        A = orc.Mapping(r, ka, [n], la)
+        B = orc.Mapping(r, kb, [n], lb)
+        C = orc.Mapping(r, kc, [n], lc)
+        a = orc.copy(first, base, A)
+        ac = orc.copy(A, a, C)
+        abc = orc.copy(B, orc.copy(A, a, B), C)
+        assert all(np.array_equal(x, y) for x, y in zip(ac, abc))
+
+
+def test_check_samples_detects_a_wrong_byte(orc):
+    r = orc.Record(W.PARTICLE)
+    n = 200
+    a = orc.Mapping(r, "aos_packed", [n])
+    b = orc.Mapping(r, "aosoa", [n], 8)
+    src = [W.random_bytes(n * 28, 1)]
+    dst = orc.copy(a, src, b)
+    idx = np.repeat(np.arange(n), 7)
+    leaf = np.tile(np.arange(7), n)
+    assert orc.check_samples(a, src, b, dst, idx, leaf) == (0, -1)
+    dst[0][8 * 4 * 3 + 5 * 4] ^= 1  # record 5, leaf 3 in AoSoA8
+    bad, first = orc.check_samples(a, src, b, dst, idx, leaf)
+    assert bad == 1 and (idx[first], leaf[first]) == (5, 3)
+
+
+# --------------------------------------------------------------------------
+# random records (hypothesis) against the serialiser
+# --------------------------------------------------------------------------
+
+_TYPES = ["u8", "u16", "u32", "f64", "i64", "bool", "f32"]
+
+
+@st.composite
+def _records(draw, depth=0):
+    members = []
+    for _ in range(draw(st.integers(1, 4))):
+        choice = draw(st.integers(0, 9 if depth < 2 else 6))
+        if choice <= 5:
+            m = draw(st.sampled_from(_TYPES))
+        else:
+            m = draw(_records(depth=depth + 1))
+        if draw(st.integers(0, 4)) == 0:
+            m = (m, draw(st.integers(1, 3)))
+        members.append(m)
+    return members
+
+
+@settings(max_examples=60, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(rec=_records(), n=st.integers(0, 40), lanes=st.sampled_from([1, 2, 4, 8, 16, 32, 64]),
+       kind=st.sampled_from(KINDS), seed=st.integers(0, 2**31))
+def test_random_records_against_serialiser(orc, rec, n, lanes, kind, seed):
+    types = W.leaf_types(rec)
+    if len(types) > 24:
+        return
+    vals = _unique_leaf_values(types, n, seed)
+    got = _build(orc, rec, kind, [n], lanes if kind == "aosoa" else 0, vals)
+    want = _serialise(types, vals, kind, n, lanes)
+    assert [bytes(b) for b in got] == want
