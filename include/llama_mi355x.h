@@ -1,0 +1,227 @@
+/*
+ * llama_mi355x.h -- C ABI of the MI355X layout-aware copy.
+ *
+ * The library implements the layout-aware copy of LLAMA (Gruber et al.,
+ * "LLAMA: The Low-Level Abstraction for Memory Access", arXiv 2106.04284): a
+ * multi-dimensional array of nested, structured records (the paper's "data
+ * space", sec. 3.1) is held by a view, that is a mapping plus an array of
+ * blobs (sec. 3.2, sec. 3.8), and is copied into a second view of the same
+ * data space whose mapping differs (sec. 3.9).  The copy runs in HIP kernels
+ * on an AMD Instinct MI355X (gfx950).
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: LLAMA_OK (0) or a negative llama_status.  After a non-OK
+ *    status llama_last_error() describes it (thread-local string).  No C++
+ *    exception crosses this interface.
+ *  - Ownership: the caller owns every descriptor and every blob.  Descriptors
+ *    are read during the call only.  The library never allocates or frees a
+ *    blob (blobs are supplied by the user, sec. 3.8); it owns only its small
+ *    internal state (batch tables, server queues, the tuning cache).
+ *  - Asynchrony: llama_copy, llama_copy_naive, llama_copy_ex and
+ *    llama_batch_launch validate synchronously, enqueue on `stream` and return;
+ *    they behave like hipMemcpyAsync.  Blobs must stay valid until the stream
+ *    work has finished.  `stream` is a hipStream_t (NULL: the null stream).
+ *  - Errors in the arguments are reported before anything is enqueued.
+ *  - Bytes are moved verbatim: NaN payloads, -0, subnormals and non-canonical
+ *    booleans survive unchanged.
+ */
+#ifndef LLAMA_MI355X_H
+#define LLAMA_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Status codes                                                             */
+/* ------------------------------------------------------------------------ */
+
+typedef enum {
+    LLAMA_OK = 0,
+    LLAMA_E_INVALID_ARG = -1,      /* NULL pointer, bad kind, bad size/alignment/count, bad lanes */
+    LLAMA_E_RECORD_MISMATCH = -2,  /* source and destination flatten to different leaves */
+    LLAMA_E_EXTENT_MISMATCH = -3,  /* source and destination array dimensions differ */
+    LLAMA_E_BLOB_TOO_SMALL = -4,   /* a blob is smaller than the mapping needs */
+    LLAMA_E_OVERLAP = -6,          /* a source blob range overlaps a destination blob range */
+    LLAMA_E_OVERFLOW = -7,         /* a size or offset does not fit 64 bits */
+    LLAMA_E_UNSUPPORTED = -8,      /* a valid request this build cannot run */
+    LLAMA_E_HIP = -9,              /* the HIP runtime reported an error */
+    LLAMA_E_NO_BUDGET = -10,       /* a request is larger than a server's memory budget */
+    LLAMA_E_BUSY = -11             /* a server queue is full */
+} llama_status;
+
+/* Thread-local text for the last non-OK status returned on this thread. */
+const char* llama_last_error(void);
+
+/* Constant name of a status code. */
+const char* llama_status_string(int status);
+
+/* ------------------------------------------------------------------------ */
+/* Record dimension (sec. 3.3, Listings 1 and 2)                            */
+/* ------------------------------------------------------------------------ */
+
+/* One node of a record tree, listed in pre-order (a node, then its children).
+ *  - Leaf (an elemental type): size > 0 (at most 4096), children == 0.
+ *    `align` is its alignment, a power of two (at most 4096); 0 means the
+ *    largest power of two dividing `size`, capped at 16.
+ *  - Nested record: size == 0, children > 0 = number of direct child nodes,
+ *    each followed by its own subtree.
+ *  - count >= 1: the node is a static array of `count` elements (sec. 3.3:
+ *    an array field T[n] is a record of n fields of T); count applies to
+ *    leaves and to nested records alike.
+ * Leaves are numbered depth first in declaration order (forEachLeaf, sec. 3.6);
+ * that leaf number is the record coordinate used by this interface. */
+typedef struct {
+    uint32_t size;
+    uint32_t align;
+    uint32_t count;
+    uint32_t children;
+} llama_field;
+
+/* A record: the top-level members, each member's subtree in pre-order. */
+typedef struct {
+    uint32_t num_nodes;
+    const llama_field* nodes;
+} llama_record_desc;
+
+/* Leaf count, packed record size S (sum of leaf sizes) and aligned record
+ * stride R (each leaf at the next multiple of its alignment, the stride
+ * rounded up to the largest alignment: the C struct rule applied to the
+ * flattened leaves).  Any output pointer may be NULL. */
+int llama_record_info(const llama_record_desc* record, uint32_t* leaf_count, uint64_t* packed_size,
+                      uint64_t* aligned_size);
+
+/* Size, alignment, packed offset and aligned offset of leaf `leaf`.  Any
+ * output pointer may be NULL. */
+int llama_record_leaf(const llama_record_desc* record, uint32_t leaf, uint32_t* size, uint32_t* align,
+                      uint64_t* packed_offset, uint64_t* aligned_offset);
+
+/* ------------------------------------------------------------------------ */
+/* Mappings (sec. 3.7)                                                      */
+/* ------------------------------------------------------------------------ */
+
+typedef enum {
+    LLAMA_AOS_PACKED = 0,  /* records one after another, leaves tightly packed: 1 blob of N*S */
+    LLAMA_AOS_ALIGNED = 1, /* records one after another, leaves aligned: 1 blob of N*R */
+    LLAMA_SOA_SINGLE = 2,  /* per leaf f, N values contiguous at N*(packed offset of f): 1 blob of N*S */
+    LLAMA_SOA_MULTI = 3,   /* per leaf f, N values contiguous in blob f: F blobs of N*s_f */
+    LLAMA_AOSOA = 4        /* blocks of `lanes` records; inside a block leaf f's values are
+                              contiguous at lanes*(packed offset of f): 1 blob of
+                              ceil(N/lanes)*lanes*S */
+} llama_mapping_kind;
+
+#define LLAMA_MAX_RANK 8
+
+/* A mapping of the data space: record dimension, kind and array dimensions.
+ * Coordinates are linearised row-major, last index fastest (sec. 3.6). */
+typedef struct {
+    const llama_record_desc* record;
+    uint32_t kind;                    /* llama_mapping_kind */
+    uint32_t rank;                    /* 1 .. LLAMA_MAX_RANK */
+    uint64_t extents[LLAMA_MAX_RANK]; /* extents[0 .. rank-1]; zero extents allowed */
+    uint32_t lanes;                   /* LLAMA_AOSOA: lanes per block, a power of two; else ignored */
+    uint32_t reserved;                /* must be 0 */
+} llama_mapping_desc;
+
+/* Number of blobs the mapping needs (the paper's compile-time blobCount). */
+int llama_mapping_blob_count(const llama_mapping_desc* mapping, uint32_t* count);
+
+/* Bytes blob `blob` needs (the paper's blobSize). */
+int llama_mapping_blob_size(const llama_mapping_desc* mapping, uint32_t blob, uint64_t* size);
+
+/* Host-side blobNrAndOffset (sec. 3.7): where leaf `leaf` of the record at
+ * array coordinate coord[0 .. rank-1] lives.  Coordinates must be in range. */
+int llama_mapping_offset(const llama_mapping_desc* mapping, const uint64_t* coord, uint32_t leaf,
+                         uint32_t* blob, uint64_t* offset);
+
+/* ------------------------------------------------------------------------ */
+/* Blobs (sec. 3.8) and the copy (sec. 3.9)                                 */
+/* ------------------------------------------------------------------------ */
+
+/* A contiguous byte range in device memory (any alignment).  `size` may
+ * exceed what the mapping needs; bytes past the mapping's blob size are never
+ * read or written. */
+typedef struct {
+    void* ptr;
+    uint64_t size;
+} llama_blob;
+
+/* Copies the view (src, src_blobs) into the view (dst, dst_blobs).
+ *  - src and dst must flatten to the same leaves (same sizes and alignments
+ *    in the same order) and have the same rank and extents.
+ *  - src_blobs / dst_blobs hold blob_count entries of their mapping.
+ *  - No source range may overlap a destination range.
+ *  - Every byte of every destination blob up to the mapping's blob size is
+ *    written exactly once: leaf values from the source, and zero for the
+ *    destination's padding (alignment gaps of aligned AoS, lanes past the last
+ *    record in the last AoSoA block).
+ *  - A data space with zero records enqueues nothing and returns LLAMA_OK. */
+int llama_copy(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+               const llama_blob* dst_blobs, void* stream);
+
+/* The plain element-wise copy on the GPU: one thread per record, looping over
+ * the leaves, each leaf located through the run-time mapping arithmetic and
+ * moved at its own width (the naive copy of sec. 4.2, on the GPU).  Same
+ * contract and same result as llama_copy; it exists as the baseline. */
+int llama_copy_naive(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                     const llama_blob* dst_blobs, void* stream);
+
+/* Copy strategies (llama_plan_info.path, llama_copy_options.path). */
+typedef enum {
+    LLAMA_PATH_AUTO = 0,   /* options only: let the planner choose */
+    LLAMA_PATH_STREAM = 1, /* contiguous runs copied with wide vector accesses (includes identical layouts) */
+    LLAMA_PATH_TILE = 2,   /* record tiles staged through LDS, transposed, stored coalesced */
+    LLAMA_PATH_NAIVE = 3,  /* the element-wise baseline kernel */
+    LLAMA_PATH_EMPTY = 4   /* plan only: nothing to do (no records) */
+} llama_path;
+
+/* Kernel parameters.  Zero in any field means "the library's choice". */
+typedef struct {
+    uint32_t path;         /* llama_path */
+    uint32_t tile_records; /* TILE: records per tile, a power of two (16 .. 4096) */
+    uint32_t threads;      /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+    uint32_t flags;        /* reserved, must be 0 */
+} llama_copy_options;
+
+/* llama_copy with explicit kernel parameters.  The result does not depend on
+ * the options; only the speed does. */
+int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                  const llama_blob* dst_blobs, const llama_copy_options* options, void* stream);
+
+/* What llama_copy_ex would do for this pair with these options (NULL: the
+ * defaults), without touching any blob. */
+typedef struct {
+    uint32_t path;          /* llama_path chosen */
+    uint32_t tile_records;  /* TILE: records per tile */
+    uint32_t threads;       /* threads per workgroup */
+    uint32_t lds_bytes;     /* TILE: LDS bytes per workgroup */
+    uint64_t workgroups;    /* workgroups launched */
+    uint32_t runs;          /* STREAM: contiguous runs (zero runs included) */
+    uint32_t reserved;
+    uint64_t read_bytes;    /* bytes of source blobs the copy reads */
+    uint64_t write_bytes;   /* bytes of destination blobs the copy writes */
+} llama_plan_info;
+
+int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, const llama_copy_options* options,
+               llama_plan_info* info);
+
+/* ------------------------------------------------------------------------ */
+/* Batches: many independent copies in one persistent launch                */
+/* ------------------------------------------------------------------------ */
+
+/* One copy of a batch; the same contract as llama_copy's arguments. */
+typedef struct {
+    const llama_mapping_desc* src;
+    const llama_blob* src_blobs;
+    const llama_mapping_desc* dst;
+    const llama_blob* dst_blobs;
+} llama_copy_item;
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LLAMA_MI355X_H */

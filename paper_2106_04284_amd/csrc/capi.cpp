@@ -1,0 +1,192 @@
+// extern "C" entry points declared in include/llama_mi355x.h.
+#include <cstring>
+#include <exception>
+#include <string>
+
+#include "core.hpp"
+
+using namespace llama;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int set_error(int status, const std::string& message)
+{
+    g_last_error = message;
+    return status;
+}
+
+template <typename F>
+int guarded(F&& body)
+{
+    try {
+        body();
+        return LLAMA_OK;
+    } catch (const Error& e) {
+        return set_error(e.status, e.message);
+    } catch (const std::bad_alloc&) {
+        return set_error(LLAMA_E_INVALID_ARG, "host memory exhausted");
+    } catch (const std::exception& e) {
+        return set_error(LLAMA_E_INVALID_ARG, e.what());
+    } catch (...) {
+        return set_error(LLAMA_E_INVALID_ARG, "unknown error");
+    }
+}
+
+void need(const void* p, const char* what)
+{
+    if (!p)
+        fail(LLAMA_E_INVALID_ARG, std::string(what) + " is NULL");
+}
+
+} // namespace
+
+extern "C" {
+
+const char* llama_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+const char* llama_status_string(int status)
+{
+    switch (status) {
+    case LLAMA_OK: return "LLAMA_OK";
+    case LLAMA_E_INVALID_ARG: return "LLAMA_E_INVALID_ARG";
+    case LLAMA_E_RECORD_MISMATCH: return "LLAMA_E_RECORD_MISMATCH";
+    case LLAMA_E_EXTENT_MISMATCH: return "LLAMA_E_EXTENT_MISMATCH";
+    case LLAMA_E_BLOB_TOO_SMALL: return "LLAMA_E_BLOB_TOO_SMALL";
+    case LLAMA_E_OVERLAP: return "LLAMA_E_OVERLAP";
+    case LLAMA_E_OVERFLOW: return "LLAMA_E_OVERFLOW";
+    case LLAMA_E_UNSUPPORTED: return "LLAMA_E_UNSUPPORTED";
+    case LLAMA_E_HIP: return "LLAMA_E_HIP";
+    case LLAMA_E_NO_BUDGET: return "LLAMA_E_NO_BUDGET";
+    case LLAMA_E_BUSY: return "LLAMA_E_BUSY";
+    default: return "LLAMA_E_UNKNOWN";
+    }
+}
+
+int llama_record_info(const llama_record_desc* record, uint32_t* leaf_count, uint64_t* packed_size,
+                      uint64_t* aligned_size)
+{
+    return guarded([&] {
+        Record r = flatten(record);
+        if (leaf_count)
+            *leaf_count = uint32_t(r.leaves.size());
+        if (packed_size)
+            *packed_size = r.packed_size;
+        if (aligned_size)
+            *aligned_size = r.aligned_size;
+    });
+}
+
+int llama_record_leaf(const llama_record_desc* record, uint32_t leaf, uint32_t* size, uint32_t* align,
+                      uint64_t* packed_offset, uint64_t* aligned_offset)
+{
+    return guarded([&] {
+        Record r = flatten(record);
+        if (leaf >= r.leaves.size())
+            fail(LLAMA_E_INVALID_ARG, "leaf " + std::to_string(leaf) + " out of range");
+        const Leaf& l = r.leaves[leaf];
+        if (size)
+            *size = l.size;
+        if (align)
+            *align = l.align;
+        if (packed_offset)
+            *packed_offset = l.packed_offset;
+        if (aligned_offset)
+            *aligned_offset = l.aligned_offset;
+    });
+}
+
+int llama_mapping_blob_count(const llama_mapping_desc* mapping, uint32_t* count)
+{
+    return guarded([&] {
+        need(mapping, "mapping");
+        need(count, "count");
+        Record r = flatten(mapping->record);
+        Side s = make_side(mapping, r);
+        *count = uint32_t(s.blob_size.size());
+    });
+}
+
+int llama_mapping_blob_size(const llama_mapping_desc* mapping, uint32_t blob, uint64_t* size)
+{
+    return guarded([&] {
+        need(mapping, "mapping");
+        need(size, "size");
+        Record r = flatten(mapping->record);
+        Side s = make_side(mapping, r);
+        if (blob >= s.blob_size.size())
+            fail(LLAMA_E_INVALID_ARG, "blob " + std::to_string(blob) + " out of range");
+        *size = s.blob_size[blob];
+    });
+}
+
+int llama_mapping_offset(const llama_mapping_desc* mapping, const uint64_t* coord, uint32_t leaf, uint32_t* blob,
+                         uint64_t* offset)
+{
+    return guarded([&] {
+        need(mapping, "mapping");
+        need(coord, "coord");
+        need(blob, "blob");
+        need(offset, "offset");
+        Record r = flatten(mapping->record);
+        Side s = make_side(mapping, r);
+        if (leaf >= r.leaves.size())
+            fail(LLAMA_E_INVALID_ARG, "leaf " + std::to_string(leaf) + " out of range");
+        uint64_t i = 0;
+        for (uint32_t d = 0; d < s.rank; d++) {
+            if (coord[d] >= s.extents[d])
+                fail(LLAMA_E_INVALID_ARG, "coordinate out of range in dimension " + std::to_string(d));
+            i = i * s.extents[d] + coord[d];
+        }
+        *blob = s.blob[leaf];
+        *offset = s.offset(i, leaf, r);
+    });
+}
+
+int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, const llama_copy_options* options,
+               llama_plan_info* info)
+{
+    return guarded([&] {
+        need(info, "info");
+        Request rq = make_request(src, nullptr, dst, nullptr, false);
+        Plan p = make_plan(rq, options);
+        std::memset(info, 0, sizeof(*info));
+        info->path = p.path;
+        info->threads = p.threads;
+        info->tile_records = p.path == LLAMA_PATH_TILE ? (1u << p.tile.log2_tile) : 0;
+        info->lds_bytes = p.lds_bytes;
+        info->workgroups = p.workgroups;
+        info->runs = p.path == LLAMA_PATH_STREAM ? p.stream.num_runs : 0;
+        info->read_bytes = p.read_bytes;
+        info->write_bytes = p.write_bytes;
+    });
+}
+
+int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                  const llama_blob* dst_blobs, const llama_copy_options* options, void* stream)
+{
+    return guarded([&] {
+        Request rq = make_request(src, src_blobs, dst, dst_blobs, true);
+        Plan p = make_plan(rq, options);
+        launch(p, stream);
+    });
+}
+
+int llama_copy(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+               const llama_blob* dst_blobs, void* stream)
+{
+    return llama_copy_ex(src, src_blobs, dst, dst_blobs, nullptr, stream);
+}
+
+int llama_copy_naive(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                     const llama_blob* dst_blobs, void* stream)
+{
+    llama_copy_options o{LLAMA_PATH_NAIVE, 0, 0, 0};
+    return llama_copy_ex(src, src_blobs, dst, dst_blobs, &o, stream);
+}
+
+} // extern "C"

@@ -1,0 +1,552 @@
+// Host-side core: record flattening, affine mappings, validation, planning.
+#include "core.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+namespace llama {
+
+void fail(int status, const std::string& message)
+{
+    throw Error{status, message};
+}
+
+namespace {
+
+bool is_pow2(uint64_t x) { return x != 0 && (x & (x - 1)) == 0; }
+
+uint64_t lowbit(uint64_t x) { return x & (~x + 1); }
+
+uint32_t log2_exact(uint64_t x)
+{
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < x)
+        l++;
+    return l;
+}
+
+uint64_t mul(uint64_t a, uint64_t b, const char* what)
+{
+    uint64_t r;
+    if (__builtin_mul_overflow(a, b, &r))
+        fail(LLAMA_E_OVERFLOW, std::string(what) + " overflows 64 bits");
+    return r;
+}
+
+uint64_t add(uint64_t a, uint64_t b, const char* what)
+{
+    uint64_t r;
+    if (__builtin_add_overflow(a, b, &r))
+        fail(LLAMA_E_OVERFLOW, std::string(what) + " overflows 64 bits");
+    return r;
+}
+
+uint64_t round_up(uint64_t x, uint64_t a) { return add(x, a - 1, "offset") / a * a; }
+
+constexpr size_t kMaxLeaves = 1u << 16;
+
+// Parses the subtree of nodes[idx] and appends its leaves; returns the index
+// after the subtree.
+uint32_t parse_node(const llama_record_desc* d, uint32_t idx, uint32_t depth, std::vector<Leaf>& out)
+{
+    if (idx >= d->num_nodes)
+        fail(LLAMA_E_INVALID_ARG, "record: a nested record has fewer child nodes than it declares");
+    if (depth > 64)
+        fail(LLAMA_E_INVALID_ARG, "record: nesting deeper than 64 levels");
+    const llama_field& n = d->nodes[idx];
+    if (n.count == 0)
+        fail(LLAMA_E_INVALID_ARG, "record: node " + std::to_string(idx) + " has count 0");
+    size_t first = out.size();
+    uint32_t next;
+    if (n.size > 0) {
+        if (n.children != 0)
+            fail(LLAMA_E_INVALID_ARG, "record: leaf node " + std::to_string(idx) + " declares children");
+        uint32_t a = n.align ? n.align : uint32_t(std::min<uint64_t>(lowbit(n.size), 16));
+        if (!is_pow2(a) || a > 4096)
+            fail(LLAMA_E_INVALID_ARG, "record: leaf node " + std::to_string(idx) + " alignment is not a power of two");
+        if (n.size > 4096)
+            fail(LLAMA_E_INVALID_ARG, "record: leaf node " + std::to_string(idx) + " is larger than 4096 bytes");
+        out.push_back(Leaf{n.size, a, 0, 0});
+        next = idx + 1;
+    } else {
+        if (n.children == 0)
+            fail(LLAMA_E_INVALID_ARG, "record: node " + std::to_string(idx) + " is neither a leaf nor a record");
+        next = idx + 1;
+        for (uint32_t c = 0; c < n.children; c++)
+            next = parse_node(d, next, depth + 1, out);
+    }
+    size_t one = out.size() - first;
+    if (uint64_t(one) * n.count > kMaxLeaves || out.size() + one * (n.count - 1) > kMaxLeaves)
+        fail(LLAMA_E_INVALID_ARG, "record: more than 65536 leaves");
+    for (uint32_t c = 1; c < n.count; c++)
+        for (size_t k = 0; k < one; k++)
+            out.push_back(out[first + k]);
+    return next;
+}
+
+} // namespace
+
+Record flatten(const llama_record_desc* d)
+{
+    if (!d)
+        fail(LLAMA_E_INVALID_ARG, "record descriptor is NULL");
+    if (d->num_nodes == 0 || !d->nodes)
+        fail(LLAMA_E_INVALID_ARG, "record has no nodes");
+    Record r;
+    uint32_t idx = 0;
+    while (idx < d->num_nodes)
+        idx = parse_node(d, idx, 0, r.leaves);
+    uint64_t packed = 0, aligned = 0;
+    for (Leaf& l : r.leaves) {
+        l.packed_offset = packed;
+        packed = add(packed, l.size, "record size");
+        aligned = round_up(aligned, l.align);
+        l.aligned_offset = aligned;
+        aligned = add(aligned, l.size, "record size");
+        r.max_align = std::max(r.max_align, l.align);
+    }
+    r.packed_size = packed;
+    r.aligned_size = round_up(aligned, r.max_align);
+    if (r.aligned_size > (uint64_t(1) << 32))
+        fail(LLAMA_E_INVALID_ARG, "record larger than 4 GiB");
+    return r;
+}
+
+bool same_leaves(const Record& a, const Record& b)
+{
+    if (a.leaves.size() != b.leaves.size())
+        return false;
+    for (size_t f = 0; f < a.leaves.size(); f++)
+        if (a.leaves[f].size != b.leaves[f].size || a.leaves[f].align != b.leaves[f].align)
+            return false;
+    return true;
+}
+
+Side make_side(const llama_mapping_desc* m, const Record& r)
+{
+    if (!m)
+        fail(LLAMA_E_INVALID_ARG, "mapping descriptor is NULL");
+    if (m->kind > LLAMA_AOSOA)
+        fail(LLAMA_E_INVALID_ARG, "mapping kind " + std::to_string(m->kind) + " is not a llama_mapping_kind");
+    if (m->rank < 1 || m->rank > LLAMA_MAX_RANK)
+        fail(LLAMA_E_INVALID_ARG, "mapping rank must be 1..8");
+    if (m->reserved != 0)
+        fail(LLAMA_E_INVALID_ARG, "mapping reserved field must be 0");
+    Side s;
+    s.kind = m->kind;
+    s.rank = m->rank;
+    uint64_t n = 1;
+    for (uint32_t d = 0; d < m->rank; d++) {
+        s.extents[d] = m->extents[d];
+        n = mul(n, m->extents[d], "record count");
+    }
+    s.n = n;
+    s.npad = n;
+    const size_t F = r.leaves.size();
+    s.blob.assign(F, 0);
+    s.base.assign(F, 0);
+    const uint64_t S = r.packed_size, R = r.aligned_size;
+    switch (m->kind) {
+    case LLAMA_AOS_PACKED:
+        s.lanes = 1;
+        s.block = S;
+        for (size_t f = 0; f < F; f++)
+            s.base[f] = r.leaves[f].packed_offset;
+        s.blob_size = {mul(n, S, "blob size")};
+        break;
+    case LLAMA_AOS_ALIGNED: {
+        s.lanes = 1;
+        s.block = R;
+        uint64_t cur = 0;
+        for (size_t f = 0; f < F; f++) {
+            s.base[f] = r.leaves[f].aligned_offset;
+            if (s.base[f] > cur)
+                s.gaps.push_back({cur, s.base[f] - cur});
+            cur = s.base[f] + r.leaves[f].size;
+        }
+        if (R > cur)
+            s.gaps.push_back({cur, R - cur});
+        s.blob_size = {mul(n, R, "blob size")};
+        break;
+    }
+    case LLAMA_SOA_SINGLE:
+        s.lanes = 0;
+        for (size_t f = 0; f < F; f++)
+            s.base[f] = mul(n, r.leaves[f].packed_offset, "SoA sub-array offset");
+        s.blob_size = {mul(n, S, "blob size")};
+        break;
+    case LLAMA_SOA_MULTI:
+        s.lanes = 0;
+        for (size_t f = 0; f < F; f++) {
+            s.blob[f] = uint32_t(f);
+            s.blob_size.push_back(mul(n, r.leaves[f].size, "blob size"));
+        }
+        break;
+    case LLAMA_AOSOA: {
+        if (!is_pow2(m->lanes))
+            fail(LLAMA_E_INVALID_ARG, "AoSoA lanes must be a power of two, got " + std::to_string(m->lanes));
+        uint64_t L = m->lanes;
+        s.lanes = L;
+        s.block = mul(L, S, "AoSoA block size");
+        for (size_t f = 0; f < F; f++)
+            s.base[f] = mul(L, r.leaves[f].packed_offset, "AoSoA chunk offset");
+        uint64_t blocks = n / L + (n % L != 0);
+        s.npad = mul(blocks, L, "AoSoA record count");
+        s.blob_size = {mul(blocks, s.block, "blob size")};
+        break;
+    }
+    }
+    return s;
+}
+
+namespace {
+
+void check_blobs(const char* which, const Side& s, const llama_blob* blobs, std::vector<uint64_t>& ptrs)
+{
+    if (!blobs)
+        fail(LLAMA_E_INVALID_ARG, std::string(which) + " blob array is NULL");
+    ptrs.resize(s.blob_size.size());
+    for (size_t b = 0; b < s.blob_size.size(); b++) {
+        if (blobs[b].size < s.blob_size[b])
+            fail(LLAMA_E_BLOB_TOO_SMALL, std::string(which) + " blob " + std::to_string(b) + " holds " +
+                                             std::to_string(blobs[b].size) + " bytes, the mapping needs " +
+                                             std::to_string(s.blob_size[b]));
+        if (s.blob_size[b] > 0 && !blobs[b].ptr)
+            fail(LLAMA_E_INVALID_ARG, std::string(which) + " blob " + std::to_string(b) + " is NULL");
+        uint64_t p = uint64_t(uintptr_t(blobs[b].ptr));
+        add(p, s.blob_size[b], "blob end address");
+        ptrs[b] = p;
+    }
+}
+
+bool overlaps(uint64_t a, uint64_t an, uint64_t b, uint64_t bn)
+{
+    return an > 0 && bn > 0 && a < b + bn && b < a + an;
+}
+
+} // namespace
+
+Request make_request(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                     const llama_blob* dst_blobs, bool need_blobs)
+{
+    if (!src || !dst)
+        fail(LLAMA_E_INVALID_ARG, "mapping descriptor is NULL");
+    Request rq;
+    rq.record = flatten(src->record);
+    if (dst->record != src->record) {
+        Record other = flatten(dst->record);
+        if (!same_leaves(rq.record, other))
+            fail(LLAMA_E_RECORD_MISMATCH, "source and destination records flatten to different leaves");
+    }
+    rq.src = make_side(src, rq.record);
+    rq.dst = make_side(dst, rq.record);
+    if (src->rank != dst->rank)
+        fail(LLAMA_E_EXTENT_MISMATCH, "source and destination ranks differ");
+    for (uint32_t d = 0; d < src->rank; d++)
+        if (src->extents[d] != dst->extents[d])
+            fail(LLAMA_E_EXTENT_MISMATCH, "source and destination extents differ in dimension " + std::to_string(d));
+    if (need_blobs) {
+        check_blobs("source", rq.src, src_blobs, rq.src_ptr);
+        check_blobs("destination", rq.dst, dst_blobs, rq.dst_ptr);
+        for (size_t a = 0; a < rq.dst_ptr.size(); a++) {
+            for (size_t b = 0; b < rq.src_ptr.size(); b++)
+                if (overlaps(rq.dst_ptr[a], rq.dst.blob_size[a], rq.src_ptr[b], rq.src.blob_size[b]))
+                    fail(LLAMA_E_OVERLAP, "destination blob " + std::to_string(a) + " overlaps source blob " +
+                                              std::to_string(b));
+            for (size_t b = a + 1; b < rq.dst_ptr.size(); b++)
+                if (overlaps(rq.dst_ptr[a], rq.dst.blob_size[a], rq.dst_ptr[b], rq.dst.blob_size[b]))
+                    fail(LLAMA_E_OVERLAP, "destination blobs " + std::to_string(a) + " and " + std::to_string(b) +
+                                              " overlap");
+        }
+    } else {
+        rq.src_ptr.assign(rq.src.blob_size.size(), 0);
+        rq.dst_ptr.assign(rq.dst.blob_size.size(), 0);
+    }
+    return rq;
+}
+
+// ---------------------------------------------------------------------------
+// Planning
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// lanes as far as the copy can tell: a side whose single block holds every
+// record behaves as unblocked
+uint64_t effective_lanes(const Side& s)
+{
+    return (s.lanes == 0 || s.lanes >= s.n) ? 0 : s.lanes;
+}
+
+bool same_placement(const Side& a, const Side& b)
+{
+    if (effective_lanes(a) != effective_lanes(b) || a.blob_size != b.blob_size || a.blob != b.blob ||
+        a.base != b.base || a.npad != b.npad || a.gaps != b.gaps)
+        return false;
+    return effective_lanes(a) == 0 || a.block == b.block;
+}
+
+struct RunList {
+    std::vector<StreamRun> runs;
+    void add(uint64_t src, uint64_t dst, uint64_t bytes)
+    {
+        if (bytes == 0)
+            return;
+        if (!runs.empty()) {
+            StreamRun& l = runs.back();
+            bool both_zero = (l.src == 0 && src == 0);
+            bool both_data = (l.src != 0 && src != 0 && l.src + l.bytes == src);
+            if ((both_zero || both_data) && l.dst + l.bytes == dst) {
+                l.bytes += bytes;
+                return;
+            }
+        }
+        runs.push_back(StreamRun{src, dst, bytes, 0});
+    }
+};
+
+// Contiguous-chunk analysis (the run-time analysis of sec. 3.9, done on the
+// affine form): returns false when the copy does not reduce to a few long
+// runs.
+bool stream_runs(const Request& rq, RunList& out)
+{
+    const Side &s = rq.src, &d = rq.dst;
+    const Record& r = rq.record;
+    const size_t F = r.leaves.size();
+    if (!d.gaps.empty())
+        return false;
+    if (same_placement(s, d)) {
+        // identical layouts: whole blobs, except the lanes past the last
+        // record of an AoSoA block, which become zero runs
+        uint64_t L = d.lanes;
+        if (d.npad == d.n) {
+            for (size_t b = 0; b < d.blob_size.size(); b++)
+                out.add(rq.src_ptr[b], rq.dst_ptr[b], d.blob_size[b]);
+            return true;
+        }
+        uint64_t full = d.n / L;
+        uint64_t tail = d.n % L;
+        out.add(rq.src_ptr[0], rq.dst_ptr[0], full * d.block);
+        for (size_t f = 0; f < F; f++) {
+            uint64_t off = full * d.block + d.base[f];
+            out.add(rq.src_ptr[0] + off, rq.dst_ptr[0] + off, tail * r.leaves[f].size);
+            out.add(0, rq.dst_ptr[0] + off + tail * r.leaves[f].size, (L - tail) * r.leaves[f].size);
+        }
+        return true;
+    }
+    if (effective_lanes(s) != 0 || effective_lanes(d) != 0)
+        return false;
+    // every leaf is one contiguous array on both sides
+    for (size_t f = 0; f < F; f++) {
+        uint64_t sz = r.leaves[f].size;
+        uint64_t sa = rq.src_ptr[s.blob[f]] + s.base[f];
+        uint64_t da = rq.dst_ptr[d.blob[f]] + d.base[f];
+        out.add(sa, da, s.n * sz);
+        out.add(0, da + d.n * sz, (d.npad - d.n) * sz);
+    }
+    return true;
+}
+
+uint64_t total_bytes(const std::vector<uint64_t>& v)
+{
+    uint64_t t = 0;
+    for (uint64_t x : v)
+        t += x;
+    return t;
+}
+
+bool fill_stream(const Request& rq, Plan& p)
+{
+    RunList rl;
+    if (!stream_runs(rq, rl))
+        return false;
+    if (rl.runs.size() > size_t(kStreamMaxRuns))
+        return false;
+    uint64_t chunks = 0;
+    for (StreamRun& run : rl.runs) {
+        if (run.src != 0 && ((run.src ^ run.dst) & 3) != 0)
+            return false; // source and destination not congruent modulo 4
+        run.first_chunk = chunks;
+        chunks += (run.bytes + (uint64_t(1) << kStreamChunkLog2) - 1) >> kStreamChunkLog2;
+    }
+    p.path = LLAMA_PATH_STREAM;
+    std::memset(&p.stream, 0, sizeof(p.stream));
+    p.stream.num_runs = uint32_t(rl.runs.size());
+    p.stream.num_chunks = chunks;
+    for (size_t k = 0; k < rl.runs.size(); k++)
+        p.stream.r[k] = rl.runs[k];
+    p.workgroups = chunks;
+    return true;
+}
+
+uint32_t tile_side(const Side& s, const Record& r, uint32_t T, TileSide& out, std::vector<uint32_t>& leaf_lds)
+{
+    const size_t F = r.leaves.size();
+    leaf_lds.assign(F, 0);
+    out.lanes = s.lanes;
+    out.block = s.block;
+    out.log2_lanes = s.lanes ? log2_exact(s.lanes) : 0;
+    if (s.lanes >= 1 && s.lanes <= T) {
+        out.mode = kRecordMajor;
+        uint64_t span = (uint64_t(T) >> out.log2_lanes) * s.block;
+        return uint32_t(std::min<uint64_t>((span + 15 + 15) / 16 * 16, uint64_t(1) << 31));
+    }
+    out.mode = kFieldMajor;
+    uint64_t total = 0;
+    for (size_t f = 0; f < F; f++) {
+        leaf_lds[f] = uint32_t(std::min<uint64_t>(total, uint64_t(1) << 31));
+        total += (uint64_t(T) * r.leaves[f].size + 15 + 15) / 16 * 16;
+    }
+    return uint32_t(std::min<uint64_t>(total, uint64_t(1) << 31));
+}
+
+bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
+{
+    const Record& r = rq.record;
+    const size_t F = r.leaves.size();
+    if (F + rq.dst.gaps.size() > size_t(kTileMaxEntries))
+        return false;
+    TileArgs& a = p.tile;
+    std::memset(&a, 0, sizeof(a));
+    std::vector<uint32_t> src_lds, dst_lds;
+    uint32_t sb = tile_side(rq.src, r, T, a.src, src_lds);
+    uint32_t db = tile_side(rq.dst, r, T, a.dst, dst_lds);
+    uint64_t total = uint64_t(sb) + db;
+    if (total > lds_limit || total > kHardLdsBytes)
+        return false;
+    a.src.lds_base = 0;
+    a.src.lds_bytes = sb;
+    a.dst.lds_base = sb;
+    a.dst.lds_bytes = db;
+    a.src.span_base = rq.src_ptr[0];
+    a.dst.span_base = rq.dst_ptr[0];
+    a.n = rq.src.n;
+    a.npad = rq.dst.npad;
+    a.log2_tile = log2_exact(T);
+    a.num_tiles = (a.npad + T - 1) / T;
+    a.num_leaves = uint32_t(F);
+    a.lds_bytes = uint32_t(total);
+    for (size_t f = 0; f < F; f++) {
+        TileEntry& e = a.e[f];
+        e.src_addr = rq.src_ptr[rq.src.blob[f]] + rq.src.base[f];
+        e.dst_addr = rq.dst_ptr[rq.dst.blob[f]] + rq.dst.base[f];
+        e.size = r.leaves[f].size;
+        e.src_lds16 = uint16_t(src_lds[f] / 16);
+        e.dst_lds16 = uint16_t(dst_lds[f] / 16);
+    }
+    size_t k = F;
+    for (const auto& g : rq.dst.gaps) {
+        TileEntry& e = a.e[k++];
+        e.src_addr = 0;
+        e.dst_addr = rq.dst_ptr[0] + g.first;
+        e.size = uint32_t(g.second);
+    }
+    a.num_entries = uint32_t(k);
+    p.path = LLAMA_PATH_TILE;
+    p.lds_bytes = a.lds_bytes;
+    p.workgroups = a.num_tiles;
+    return true;
+}
+
+uint32_t default_tile(const Request& rq)
+{
+    uint64_t rec = std::max<uint64_t>(rq.record.packed_size, 1);
+    uint64_t T = 16;
+    while (T * 2 * rec <= 8192 && T < 4096)
+        T *= 2;
+    return uint32_t(T);
+}
+
+void fill_naive(const Request& rq, Plan& p)
+{
+    const Record& r = rq.record;
+    const size_t F = r.leaves.size();
+    if (F + rq.dst.gaps.size() > size_t(kNaiveMaxEntries))
+        fail(LLAMA_E_UNSUPPORTED, "record has more than " + std::to_string(kNaiveMaxEntries) +
+                                      " leaves and padding gaps; this build cannot copy it");
+    NaiveArgs& a = p.naive;
+    std::memset(&a, 0, sizeof(a));
+    a.n = rq.src.n;
+    a.npad = rq.dst.npad;
+    a.src.lanes = rq.src.lanes;
+    a.src.block = rq.src.block;
+    a.dst.lanes = rq.dst.lanes;
+    a.dst.block = rq.dst.block;
+    a.num_leaves = uint32_t(F);
+    auto width = [](uint64_t addr, uint64_t size, const Side& s) {
+        uint64_t w = addr | size;
+        if (s.lanes >= 1 && s.npad > s.lanes)
+            w |= s.block;
+        return uint32_t(std::min<uint64_t>(lowbit(w | 8), 8));
+    };
+    for (size_t f = 0; f < F; f++) {
+        NaiveEntry& e = a.e[f];
+        e.src_addr = rq.src_ptr[rq.src.blob[f]] + rq.src.base[f];
+        e.dst_addr = rq.dst_ptr[rq.dst.blob[f]] + rq.dst.base[f];
+        e.size = r.leaves[f].size;
+        e.width = std::min(width(e.src_addr, e.size, rq.src), width(e.dst_addr, e.size, rq.dst));
+    }
+    size_t k = F;
+    for (const auto& g : rq.dst.gaps) {
+        NaiveEntry& e = a.e[k++];
+        e.src_addr = 0;
+        e.dst_addr = rq.dst_ptr[0] + g.first;
+        e.size = uint32_t(g.second);
+        e.width = width(e.dst_addr, e.size, rq.dst);
+    }
+    a.num_entries = uint32_t(k);
+    p.path = LLAMA_PATH_NAIVE;
+    p.workgroups = (a.npad + p.threads - 1) / p.threads;
+}
+
+} // namespace
+
+Plan make_plan(const Request& rq, const llama_copy_options* opt)
+{
+    Plan p;
+    p.read_bytes = total_bytes(rq.src.blob_size);
+    p.write_bytes = total_bytes(rq.dst.blob_size);
+    uint32_t want = opt ? opt->path : uint32_t(LLAMA_PATH_AUTO);
+    if (opt && opt->flags != 0)
+        fail(LLAMA_E_INVALID_ARG, "llama_copy_options.flags must be 0");
+    if (want > LLAMA_PATH_NAIVE)
+        fail(LLAMA_E_INVALID_ARG, "llama_copy_options.path is not a llama_path");
+    uint32_t threads = (opt && opt->threads) ? opt->threads : 0;
+    if (threads && (!is_pow2(threads) || threads < 64 || threads > 1024))
+        fail(LLAMA_E_INVALID_ARG, "threads must be 64, 128, 256, 512 or 1024");
+    uint32_t T = (opt && opt->tile_records) ? opt->tile_records : 0;
+    if (T && (!is_pow2(T) || T < 16 || T > 4096))
+        fail(LLAMA_E_INVALID_ARG, "tile_records must be a power of two in 16..4096");
+    if (rq.dst.npad == 0) {
+        p.path = LLAMA_PATH_EMPTY;
+        return p;
+    }
+    p.threads = threads ? threads : kDefaultThreads;
+    if (want == LLAMA_PATH_AUTO || want == LLAMA_PATH_STREAM) {
+        if (fill_stream(rq, p))
+            return p;
+        if (want == LLAMA_PATH_STREAM)
+            fail(LLAMA_E_UNSUPPORTED, "the STREAM path needs long runs congruent modulo 4 on both sides");
+    }
+    if (want == LLAMA_PATH_AUTO || want == LLAMA_PATH_TILE) {
+        uint32_t t = T ? T : default_tile(rq);
+        if (!threads)
+            p.threads = std::min<uint32_t>(std::max<uint32_t>(t, 64), kDefaultThreads);
+        bool ok = fill_tile(rq, t, T ? kHardLdsBytes : kMaxLdsBytes, p);
+        while (!ok && !T && t > 16) {
+            t /= 2;
+            if (!threads)
+                p.threads = std::min<uint32_t>(std::max<uint32_t>(t, 64), kDefaultThreads);
+            ok = fill_tile(rq, t, kMaxLdsBytes, p);
+        }
+        if (ok)
+            return p;
+        if (want == LLAMA_PATH_TILE)
+            fail(LLAMA_E_UNSUPPORTED, "the TILE path does not fit this record in LDS with these options");
+    }
+    p.threads = threads ? threads : kDefaultThreads;
+    fill_naive(rq, p);
+    return p;
+}
+
+} // namespace llama

@@ -1,0 +1,104 @@
+// Host-side core of the layout-aware copy: record flattening, the affine form
+// of each mapping, validation and the copy planner.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "llama_mi355x.h"
+#include "kernel_args.hpp"
+
+namespace llama {
+
+// A status with its message; thrown inside the library, converted to a return
+// code and a thread-local message at the C boundary.
+struct Error {
+    int status;
+    std::string message;
+};
+[[noreturn]] void fail(int status, const std::string& message);
+
+// One leaf of a flattened record (sec. 3.3: leaves in depth-first declaration
+// order; sec. 3.7: sizes and offsets in the record dimension).
+struct Leaf {
+    uint32_t size;
+    uint32_t align;
+    uint64_t packed_offset;  // sum of the sizes of the leaves before it
+    uint64_t aligned_offset; // next multiple of align after the previous leaf's end
+};
+
+struct Record {
+    std::vector<Leaf> leaves;
+    uint64_t packed_size = 0;  // S
+    uint64_t aligned_size = 0; // R
+    uint32_t max_align = 1;
+};
+
+Record flatten(const llama_record_desc* desc);
+bool same_leaves(const Record& a, const Record& b);
+
+// The affine form of a mapping (sec. 3.7 blobNrAndOffset): leaf f of the
+// record with row-major linear index i lives in blob `blob[f]` at
+//     base[f] + (i / L) * K + (i % L) * size[f]     (blocked, L >= 1)
+//     base[f] + i * size[f]                          (unblocked, L == 0)
+// AoS packed is blocked with L = 1, K = S; AoS aligned L = 1, K = R; AoSoA
+// L = lanes, K = lanes * S; both SoA kinds are unblocked.
+struct Side {
+    uint32_t kind = 0;
+    uint32_t rank = 0;
+    uint64_t extents[LLAMA_MAX_RANK] = {};
+    uint64_t n = 0;     // records
+    uint64_t lanes = 0; // L (0: unblocked)
+    uint64_t block = 0; // K
+    uint64_t npad = 0;  // records the blob spans, trailing AoSoA lanes included
+    std::vector<uint32_t> blob;
+    std::vector<uint64_t> base;
+    std::vector<uint64_t> blob_size;
+    // byte ranges inside one record that no leaf covers (aligned AoS only):
+    // (offset, length) pairs
+    std::vector<std::pair<uint64_t, uint64_t>> gaps;
+    bool has_padding() const { return !gaps.empty() || npad != n; }
+    uint64_t offset(uint64_t i, uint32_t f, const Record& r) const
+    {
+        if (lanes == 0)
+            return base[f] + i * r.leaves[f].size;
+        return base[f] + (i / lanes) * block + (i % lanes) * r.leaves[f].size;
+    }
+};
+
+Side make_side(const llama_mapping_desc* m, const Record& r);
+
+// A validated copy request: both sides plus device addresses.
+struct Request {
+    Record record;
+    Side src, dst;
+    std::vector<uint64_t> src_ptr, dst_ptr; // device addresses of the blobs
+};
+
+// Validates descriptors (and blobs when given) and builds the request.
+Request make_request(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                     const llama_blob* dst_blobs, bool need_blobs);
+
+// A complete launch plan for one copy.
+struct Plan {
+    uint32_t path = LLAMA_PATH_EMPTY;
+    uint32_t threads = 256;
+    uint64_t workgroups = 0;
+    uint32_t lds_bytes = 0;
+    uint64_t read_bytes = 0, write_bytes = 0;
+    TileArgs tile{};     // path == TILE
+    StreamArgs stream{}; // path == STREAM
+    NaiveArgs naive{};   // path == NAIVE
+};
+
+Plan make_plan(const Request& rq, const llama_copy_options* opt);
+void launch(const Plan& p, void* stream); // kernels.hip
+
+// default kernel parameters
+constexpr uint32_t kDefaultThreads = 256;
+constexpr uint32_t kDefaultTileBytes = 16384; // target source bytes per tile
+constexpr uint32_t kMaxLdsBytes = 65536;      // LDS budget per workgroup for the default plan
+constexpr uint32_t kHardLdsBytes = 160 * 1024;
+
+} // namespace llama

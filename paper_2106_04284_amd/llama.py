@@ -1,0 +1,291 @@
+"""ctypes binding of libllama_mi355x.so (declared in include/llama_mi355x.h).
+
+Argument marshalling only: every step of the copy runs in the library's HIP
+kernels.  Blobs are passed as device pointers plus sizes; torch tensors (any
+dtype, contiguous, on the GPU) are accepted and only their data pointer and
+byte size are used.  Streams are torch.cuda.Stream objects or raw hipStream_t
+integers (the current torch stream by default).
+
+There is no fallback: if the shared library has not been built, the first
+call raises an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libllama_mi355x.so")
+
+MAX_RANK = 8
+
+AOS_PACKED, AOS_ALIGNED, SOA_SINGLE, SOA_MULTI, AOSOA = 0, 1, 2, 3, 4
+KINDS = {"aos_packed": AOS_PACKED, "aos_aligned": AOS_ALIGNED, "soa_single": SOA_SINGLE,
+         "soa_multi": SOA_MULTI, "aosoa": AOSOA}
+
+PATH_AUTO, PATH_STREAM, PATH_TILE, PATH_NAIVE, PATH_EMPTY = 0, 1, 2, 3, 4
+PATH_NAMES = {PATH_STREAM: "stream", PATH_TILE: "tile", PATH_NAIVE: "naive", PATH_EMPTY: "empty"}
+
+OK = 0
+E_INVALID_ARG, E_RECORD_MISMATCH, E_EXTENT_MISMATCH, E_BLOB_TOO_SMALL = -1, -2, -3, -4
+E_OVERLAP, E_OVERFLOW, E_UNSUPPORTED, E_HIP, E_NO_BUDGET, E_BUSY = -6, -7, -8, -9, -10, -11
+
+# elemental types of the neutral record form: (size, alignment)
+TYPES = {"u8": (1, 1), "i8": (1, 1), "bool": (1, 1), "u16": (2, 2), "i16": (2, 2), "f16": (2, 2),
+         "bf16": (2, 2), "u32": (4, 4), "i32": (4, 4), "f32": (4, 4), "u64": (8, 8), "i64": (8, 8),
+         "f64": (8, 8)}
+
+
+class LlamaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_string(status)}: {message}")
+        self.status = status
+
+
+class Field(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("align", ctypes.c_uint32), ("count", ctypes.c_uint32),
+                ("children", ctypes.c_uint32)]
+
+
+class RecordDesc(ctypes.Structure):
+    _fields_ = [("num_nodes", ctypes.c_uint32), ("nodes", ctypes.POINTER(Field))]
+
+
+class MappingDesc(ctypes.Structure):
+    _fields_ = [("record", ctypes.POINTER(RecordDesc)), ("kind", ctypes.c_uint32), ("rank", ctypes.c_uint32),
+                ("extents", ctypes.c_uint64 * MAX_RANK), ("lanes", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class Blob(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("size", ctypes.c_uint64)]
+
+
+class CopyOptions(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_uint32), ("tile_records", ctypes.c_uint32), ("threads", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_uint32), ("tile_records", ctypes.c_uint32), ("threads", ctypes.c_uint32),
+                ("lds_bytes", ctypes.c_uint32), ("workgroups", ctypes.c_uint64), ("runs", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("read_bytes", ctypes.c_uint64),
+                ("write_bytes", ctypes.c_uint64)]
+
+
+class CopyItem(ctypes.Structure):
+    _fields_ = [("src", ctypes.POINTER(MappingDesc)), ("src_blobs", ctypes.POINTER(Blob)),
+                ("dst", ctypes.POINTER(MappingDesc)), ("dst_blobs", ctypes.POINTER(Blob))]
+
+
+_lib = None
+
+# name -> (restype, argtypes) of every entry point the binding uses
+_SIGNATURES = {
+    "llama_last_error": (ctypes.c_char_p, []),
+    "llama_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "llama_record_info": (ctypes.c_int, [ctypes.POINTER(RecordDesc), ctypes.POINTER(ctypes.c_uint32),
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
+    "llama_record_leaf": (ctypes.c_int, [ctypes.POINTER(RecordDesc), ctypes.c_uint32,
+                                         ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
+    "llama_mapping_blob_count": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(ctypes.c_uint32)]),
+    "llama_mapping_blob_size": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.c_uint32,
+                                               ctypes.POINTER(ctypes.c_uint64)]),
+    "llama_mapping_offset": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(ctypes.c_uint64),
+                                            ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
+                                            ctypes.POINTER(ctypes.c_uint64)]),
+    "llama_plan": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(MappingDesc),
+                                  ctypes.POINTER(CopyOptions), ctypes.POINTER(PlanInfo)]),
+    "llama_copy": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob), ctypes.POINTER(MappingDesc),
+                                  ctypes.POINTER(Blob), ctypes.c_void_p]),
+    "llama_copy_naive": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob),
+                                        ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob), ctypes.c_void_p]),
+    "llama_copy_ex": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob), ctypes.POINTER(MappingDesc),
+                                     ctypes.POINTER(Blob), ctypes.POINTER(CopyOptions), ctypes.c_void_p]),
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2106_04284_amd.build` "
+                               "(the copy has no other implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().llama_status_string(status).decode()
+
+
+def check(status: int) -> None:
+    if status != OK:
+        raise LlamaError(status, lib().llama_last_error().decode())
+
+
+# --------------------------------------------------------------------------
+# records and mappings
+# --------------------------------------------------------------------------
+
+class Record:
+    """A record dimension in the library's pre-order node form, built from the
+    neutral nested form (see paper_2106_04284_amd.workloads)."""
+
+    def __init__(self, record):
+        nodes = []
+
+        def emit(m, count=1):
+            if isinstance(m, tuple):  # static array: a nested count multiplies
+                inner, c = m
+                emit(inner, count * int(c))
+                return
+            if isinstance(m, list):
+                nodes.append((0, 0, count, len(m)))
+                for x in m:
+                    emit(x)
+                return
+            size, align = TYPES[m]
+            nodes.append((size, align, count, 0))
+
+        for member in record:
+            emit(member)
+        self.nodes = (Field * len(nodes))(*[Field(*n) for n in nodes])
+        self.desc = RecordDesc(len(nodes), ctypes.cast(self.nodes, ctypes.POINTER(Field)))
+        self.source = record
+
+    def info(self):
+        n, s, r = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+        check(lib().llama_record_info(ctypes.byref(self.desc), ctypes.byref(n), ctypes.byref(s), ctypes.byref(r)))
+        return int(n.value), int(s.value), int(r.value)
+
+    @property
+    def leaf_count(self):
+        return self.info()[0]
+
+    @property
+    def packed_size(self):
+        return self.info()[1]
+
+    @property
+    def aligned_size(self):
+        return self.info()[2]
+
+    def leaf(self, f: int):
+        size, align = ctypes.c_uint32(), ctypes.c_uint32()
+        po, ao = ctypes.c_uint64(), ctypes.c_uint64()
+        check(lib().llama_record_leaf(ctypes.byref(self.desc), f, ctypes.byref(size), ctypes.byref(align),
+                                      ctypes.byref(po), ctypes.byref(ao)))
+        return {"size": size.value, "align": align.value, "packed_offset": po.value, "aligned_offset": ao.value}
+
+
+class Mapping:
+    def __init__(self, record: Record, kind: str, extents, lanes: int = 0):
+        ext = [int(e) for e in (extents if isinstance(extents, (list, tuple)) else [extents])]
+        self.record = record
+        self.kind = kind
+        self.extents = ext
+        self.lanes = int(lanes)
+        self.desc = MappingDesc()
+        self.desc.record = ctypes.pointer(record.desc)
+        self.desc.kind = KINDS[kind] if isinstance(kind, str) else int(kind)
+        self.desc.rank = len(ext)
+        for d, e in enumerate(ext[:MAX_RANK]):
+            self.desc.extents[d] = e
+        self.desc.lanes = self.lanes
+        self.desc.reserved = 0
+
+    @property
+    def blob_count(self) -> int:
+        n = ctypes.c_uint32()
+        check(lib().llama_mapping_blob_count(ctypes.byref(self.desc), ctypes.byref(n)))
+        return int(n.value)
+
+    def blob_size(self, b: int) -> int:
+        s = ctypes.c_uint64()
+        check(lib().llama_mapping_blob_size(ctypes.byref(self.desc), b, ctypes.byref(s)))
+        return int(s.value)
+
+    def blob_sizes(self):
+        return [self.blob_size(b) for b in range(self.blob_count)]
+
+    def offset(self, coord, leaf: int):
+        c = (ctypes.c_uint64 * MAX_RANK)(*[int(x) for x in coord])
+        b, o = ctypes.c_uint32(), ctypes.c_uint64()
+        check(lib().llama_mapping_offset(ctypes.byref(self.desc), c, leaf, ctypes.byref(b), ctypes.byref(o)))
+        return int(b.value), int(o.value)
+
+    def alloc(self, device="cuda", fill=None):
+        """Allocates the mapping's blobs as uint8 torch tensors (allocation is
+        the caller's business; this is a convenience)."""
+        import torch
+        out = []
+        for s in self.blob_sizes():
+            t = torch.empty(s, dtype=torch.uint8, device=device)
+            if fill is not None:
+                t.fill_(fill)
+            out.append(t)
+        return out
+
+
+def _blobs(blobs):
+    arr = (Blob * max(len(blobs), 1))()
+    for k, b in enumerate(blobs):
+        if isinstance(b, tuple):
+            ptr, size = b
+        else:  # a torch tensor
+            if not b.is_contiguous():
+                raise ValueError("blob tensors must be contiguous")
+            ptr, size = b.data_ptr(), b.numel() * b.element_size()
+        arr[k] = Blob(ptr, size)
+    return arr
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _options(path=PATH_AUTO, tile_records=0, threads=0):
+    if isinstance(path, str):
+        path = {"auto": PATH_AUTO, "stream": PATH_STREAM, "tile": PATH_TILE, "naive": PATH_NAIVE}[path]
+    return CopyOptions(path, tile_records, threads, 0)
+
+
+def copy(src: Mapping, src_blobs, dst: Mapping, dst_blobs, stream=None, path=PATH_AUTO, tile_records=0,
+         threads=0):
+    """llama_copy / llama_copy_ex: enqueues the copy on `stream`."""
+    sb, db = _blobs(src_blobs), _blobs(dst_blobs)
+    if path == PATH_AUTO and not tile_records and not threads:
+        check(lib().llama_copy(ctypes.byref(src.desc), sb, ctypes.byref(dst.desc), db, _stream(stream)))
+    else:
+        o = _options(path, tile_records, threads)
+        check(lib().llama_copy_ex(ctypes.byref(src.desc), sb, ctypes.byref(dst.desc), db, ctypes.byref(o),
+                                  _stream(stream)))
+
+
+def copy_naive(src: Mapping, src_blobs, dst: Mapping, dst_blobs, stream=None):
+    """llama_copy_naive: the element-wise baseline kernel."""
+    check(lib().llama_copy_naive(ctypes.byref(src.desc), _blobs(src_blobs), ctypes.byref(dst.desc),
+                                 _blobs(dst_blobs), _stream(stream)))
+
+
+def plan(src: Mapping, dst: Mapping, path=PATH_AUTO, tile_records=0, threads=0) -> dict:
+    """llama_plan: what a copy of this pair would launch."""
+    info = PlanInfo()
+    o = _options(path, tile_records, threads)
+    check(lib().llama_plan(ctypes.byref(src.desc), ctypes.byref(dst.desc), ctypes.byref(o), ctypes.byref(info)))
+    return {"path": PATH_NAMES.get(info.path, "?"), "tile_records": info.tile_records, "threads": info.threads,
+            "lds_bytes": info.lds_bytes, "workgroups": info.workgroups, "runs": info.runs,
+            "read_bytes": info.read_bytes, "write_bytes": info.write_bytes}

@@ -1,0 +1,203 @@
+"""Host-side tests of the C ABI (no GPU): the library loads and exports every
+entry point of include/llama_mi355x.h, its host mapping arithmetic agrees with
+the oracle, the planner picks the expected path, and invalid requests fail with
+the documented status before anything would be enqueued."""
+import ctypes
+import os
+import random
+import re
+
+import pytest
+
+from paper_2106_04284_amd import llama as L
+from paper_2106_04284_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LAYOUTS = W.LAYOUTS + [("aosoa", 1), ("aosoa", 2), ("aosoa", 4)]
+
+
+def _declared_functions():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            text = open(os.path.join(inc, fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(llama_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_function():
+    lib = ctypes.CDLL(L.LIB_PATH)
+    names = _declared_functions()
+    assert "llama_copy" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("name", ["particle", "lbm", "mixed", "listing1"])
+def test_record_info_matches_oracle(orc, name):
+    r = L.Record(W.RECORDS[name])
+    o = orc.Record(W.RECORDS[name])
+    assert r.info() == (o.nleaves, o.packed_size, o.aligned_size)
+    for f in range(o.nleaves):
+        leaf = r.leaf(f)
+        assert leaf["size"] == o.sizes[f]
+        assert leaf["align"] == o.aligns[f]
+        assert leaf["packed_offset"] == o.packed_offset(f)
+        assert leaf["aligned_offset"] == o.aligned_offset(f)
+
+
+def _random_record(g, depth=0):
+    types = ["u8", "u16", "u32", "f64", "bool", "f32", "i64"]
+    out = []
+    for _ in range(g.randint(1, 4)):
+        if depth < 2 and g.random() < 0.3:
+            m = _random_record(g, depth + 1)
+        else:
+            m = g.choice(types)
+        if g.random() < 0.2:
+            m = (m, g.randint(1, 3))
+        out.append(m)
+    return out
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_mapping_arithmetic_matches_oracle(orc, seed):
+    g = random.Random(seed)
+    rec = _random_record(g) if seed >= 4 else W.RECORDS[["particle", "lbm", "mixed", "listing1"][seed]]
+    r, o = L.Record(rec), orc.Record(rec)
+    ext = [g.randint(1, 6) for _ in range(g.randint(1, 3))]
+    for kind, lanes in LAYOUTS:
+        m = L.Mapping(r, kind, ext, lanes)
+        mo = orc.Mapping(o, kind, ext, lanes)
+        assert m.blob_sizes() == mo.blob_sizes(), (kind, lanes)
+        for _ in range(40):
+            c = [g.randrange(e) for e in ext]
+            f = g.randrange(o.nleaves)
+            assert m.offset(c, f) == mo.blob_nr_and_offset(c, f), (kind, lanes, c, f)
+
+
+def test_planner_paths_for_particle_pairs():
+    r = L.Record(W.PARTICLE)
+    n = 1 << 26
+    seen = {}
+    for a in W.LAYOUTS:
+        for b in W.LAYOUTS:
+            if a == b:
+                continue
+            p = L.plan(L.Mapping(r, a[0], [n], a[1]), L.Mapping(r, b[0], [n], b[1]))
+            seen[(a, b)] = p["path"]
+            assert p["read_bytes"] == p["write_bytes"] == n * 28
+    aos = {("aos_packed", 0), ("aos_aligned", 0)}
+    soa = {("soa_single", 0), ("soa_multi", 0)}
+    for (a, b), path in seen.items():
+        if {a, b} <= aos or {a, b} <= soa:
+            assert path == "stream", (a, b)  # identical bytes, or one long run per leaf
+        else:
+            assert path == "tile", (a, b)
+
+
+def test_planner_identity_and_padding():
+    r = L.Record(W.MIXED)
+    # identical aligned AoS with gaps: padding must be rewritten as zeros, so
+    # this is not a plain memcpy
+    m = L.Mapping(r, "aos_aligned", [1000])
+    assert L.plan(m, L.Mapping(r, "aos_aligned", [1000]))["path"] == "tile"
+    # identical AoSoA with a partial last block: runs plus zero runs
+    a = L.Mapping(r, "aosoa", [1000], 64)
+    p = L.plan(a, L.Mapping(r, "aosoa", [1000], 64))
+    assert p["path"] == "stream" and p["runs"] > 1
+    # SoA single-blob is AoSoA with N lanes (sec. 4.2): identical placement
+    s = L.Mapping(r, "soa_single", [1024])
+    p = L.plan(s, L.Mapping(r, "aosoa", [1024], 1024))
+    assert p["path"] == "stream" and p["runs"] == 1
+    # empty data space
+    e = L.Mapping(r, "aos_packed", [0])
+    assert L.plan(e, L.Mapping(r, "soa_multi", [0]))["path"] == "empty"
+
+
+def test_forced_paths_and_options():
+    r = L.Record(W.LBM)
+    a = L.Mapping(r, "aos_aligned", [128, 128, 128])
+    b = L.Mapping(r, "soa_multi", [128, 128, 128])
+    assert L.plan(a, b)["path"] == "tile"
+    assert L.plan(a, b, path="naive")["path"] == "naive"
+    with pytest.raises(L.LlamaError) as e:
+        L.plan(a, b, path="stream")
+    assert e.value.status == L.E_UNSUPPORTED
+    p = L.plan(a, b, path="tile", tile_records=64, threads=128)
+    assert (p["tile_records"], p["threads"]) == (64, 128)
+    for bad in ({"tile_records": 3}, {"tile_records": 8192}, {"threads": 96}, {"threads": 2048}):
+        with pytest.raises(L.LlamaError) as e:
+            L.plan(a, b, path="tile", **bad)
+        assert e.value.status == L.E_INVALID_ARG
+
+
+def _copy_status(src, sblobs, dst, dblobs):
+    try:
+        L.copy(src, sblobs, dst, dblobs, stream=0)
+    except L.LlamaError as e:
+        return e.status
+    return L.OK
+
+
+def test_validation_errors():
+    """Every one of these fails validation, so no kernel is ever launched."""
+    p, m = L.Record(W.PARTICLE), L.Record(W.MIXED)
+    n = 100
+    src = L.Mapping(p, "aos_packed", [n])
+    dst = L.Mapping(p, "soa_multi", [n])
+    sb = [(0x10000, n * 28)]
+    db = [(0x100000 + k * 4096, n * 4) for k in range(7)]
+    assert _copy_status(src, sb, L.Mapping(m, "soa_multi", [n]), db) == L.E_RECORD_MISMATCH
+    assert _copy_status(src, sb, L.Mapping(p, "soa_multi", [n + 1]), db) == L.E_EXTENT_MISMATCH
+    assert _copy_status(src, sb, L.Mapping(p, "soa_multi", [10, 10]), db) == L.E_EXTENT_MISMATCH
+    assert _copy_status(src, [(0x10000, n * 28 - 1)], dst, db) == L.E_BLOB_TOO_SMALL
+    assert _copy_status(src, [(0, n * 28)], dst, db) == L.E_INVALID_ARG
+    overlap = list(db)
+    overlap[3] = (0x10000 + 8, n * 4)
+    assert _copy_status(src, sb, dst, overlap) == L.E_OVERLAP
+    self_overlap = list(db)
+    self_overlap[5] = (db[4][0] + 4, n * 4)
+    assert _copy_status(src, sb, dst, self_overlap) == L.E_OVERLAP
+    assert _copy_status(src, sb, L.Mapping(p, "aosoa", [n], 12), [(0x100000, 4096)]) == L.E_INVALID_ARG
+    bad_kind = L.Mapping(p, "aos_packed", [n])
+    bad_kind.desc.kind = 9
+    assert _copy_status(bad_kind, sb, dst, db) == L.E_INVALID_ARG
+    bad_rank = L.Mapping(p, "aos_packed", [n])
+    bad_rank.desc.rank = 0
+    assert _copy_status(bad_rank, sb, dst, db) == L.E_INVALID_ARG
+    huge = L.Mapping(p, "aos_packed", [1 << 40, 1 << 30])
+    assert _copy_status(huge, sb, L.Mapping(p, "soa_multi", [1 << 40, 1 << 30]), db) == L.E_OVERFLOW
+    assert "overflows" in L.lib().llama_last_error().decode()
+
+
+def test_record_descriptor_errors():
+    def status(nodes):
+        arr = (L.Field * max(len(nodes), 1))(*[L.Field(*x) for x in nodes])
+        desc = L.RecordDesc(len(nodes), ctypes.cast(arr, ctypes.POINTER(L.Field)))
+        n = ctypes.c_uint32()
+        return L.lib().llama_record_info(ctypes.byref(desc), ctypes.byref(n), None, None), n.value
+
+    assert status([(4, 4, 1, 0)]) == (L.OK, 1)
+    assert status([(0, 0, 2, 2), (4, 4, 1, 0), (1, 1, 3, 0)]) == (L.OK, 8)
+    assert status([])[0] == L.E_INVALID_ARG
+    assert status([(4, 4, 0, 0)])[0] == L.E_INVALID_ARG         # count 0
+    assert status([(4, 3, 1, 0)])[0] == L.E_INVALID_ARG         # alignment not a power of two
+    assert status([(4, 4, 1, 2)])[0] == L.E_INVALID_ARG         # leaf with children
+    assert status([(0, 0, 1, 0)])[0] == L.E_INVALID_ARG         # record without children
+    assert status([(0, 0, 1, 3), (4, 4, 1, 0)])[0] == L.E_INVALID_ARG  # missing children
+
+
+def test_empty_copy_is_a_no_op():
+    r = L.Record(W.PARTICLE)
+    a = L.Mapping(r, "aos_packed", [0])
+    b = L.Mapping(r, "aosoa", [0], 32)
+    # zero-sized blobs may be NULL; nothing is enqueued, so no GPU is needed
+    assert _copy_status(a, [(0, 0)], b, [(0, 0)]) == L.OK
+
+
+def test_status_strings():
+    assert L.status_string(L.E_OVERLAP) == "LLAMA_E_OVERLAP"
+    assert L.status_string(12345) == "LLAMA_E_UNKNOWN"

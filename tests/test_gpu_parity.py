@@ -1,0 +1,199 @@
+"""GPU parity: the HIP copy through the C ABI against the CPU oracle, byte for
+byte, on seeded inputs.
+
+Sources hold random bytes everywhere, padding included; destinations start
+filled with a canary and sit between guard bytes.  A case passes only if every
+destination blob equals the oracle's (values moved, padding zero) and no byte
+outside the destination blobs changed.
+"""
+import random
+
+import numpy as np
+import pytest
+
+from paper_2106_04284_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GUARD = 64
+LAYOUTS = W.LAYOUTS
+PAIRS = [(a, b) for a in LAYOUTS for b in LAYOUTS]
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_04284_amd import llama
+    llama.lib()
+    return llama
+
+
+def _name(layout):
+    kind, lanes = layout
+    return f"{kind}{lanes}" if kind == "aosoa" else kind
+
+
+def _device_blobs(blobs, offset=0, fill=None, sizes=None):
+    """Each blob as a view at byte `offset` inside a guarded device buffer."""
+    views, bufs = [], []
+    for k, s in enumerate(sizes if sizes is not None else [b.size for b in blobs]):
+        buf = torch.empty(s + offset + GUARD, dtype=torch.uint8, device="cuda")
+        buf.fill_(0xA5 if fill is None else fill)
+        if blobs is not None:
+            buf[offset:offset + s].copy_(torch.from_numpy(blobs[k]))
+        bufs.append(buf)
+        views.append(buf[offset:offset + s])
+    return views, bufs
+
+
+def run_case(L, orc, rec, src_layout, dst_layout, extents, seed, src_off=0, dst_off=0, fill=0xCD,
+             extra_dst=0, **opts):
+    ro, rg = orc.Record(rec), L.Record(rec)
+    ms_o = orc.Mapping(ro, src_layout[0], extents, src_layout[1])
+    md_o = orc.Mapping(ro, dst_layout[0], extents, dst_layout[1])
+    ms = L.Mapping(rg, src_layout[0], extents, src_layout[1])
+    md = L.Mapping(rg, dst_layout[0], extents, dst_layout[1])
+    assert ms.blob_sizes() == ms_o.blob_sizes() and md.blob_sizes() == md_o.blob_sizes()
+    src = [W.random_bytes(s, seed * 131 + k) for k, s in enumerate(ms_o.blob_sizes())]
+    want = orc.copy(ms_o, src, md_o)
+    s_views, _ = _device_blobs(src, src_off)
+    dsizes = [s + extra_dst for s in md_o.blob_sizes()]
+    d_views, d_bufs = _device_blobs(None, dst_off, fill=fill, sizes=dsizes)
+    L.copy(ms, s_views, md, d_views, **opts)
+    torch.cuda.synchronize()
+    for k, (buf, w) in enumerate(zip(d_bufs, want)):
+        host = buf.cpu().numpy()
+        got = host[dst_off:dst_off + w.size]
+        if not np.array_equal(got, w):
+            bad = np.flatnonzero(got != w)
+            raise AssertionError(f"blob {k}: {bad.size} bytes differ, first at {bad[0]} "
+                                 f"(got {got[bad[0]]:#x}, want {w[bad[0]]:#x})")
+        untouched = np.concatenate([host[:dst_off], host[dst_off + w.size:]])
+        assert (untouched == fill).all(), f"blob {k}: bytes outside the mapping's blob changed"
+    return want
+
+
+# --------------------------------------------------------------------------
+# config 1: the n-body particle, packed AoS -> SoA single-blob -> packed AoS
+# --------------------------------------------------------------------------
+
+def test_particle_roundtrip_65536(L, orc):
+    n = 65536
+    vals = W.particle_values(n, W.BASE_SEED + 1)
+    ro = orc.Record(W.PARTICLE)
+    mb = orc.Mapping(ro, "soa_multi", [n])
+    aos_o = orc.Mapping(ro, "aos_packed", [n])
+    soa_o = orc.Mapping(ro, "soa_single", [n])
+    aos_host = orc.copy(mb, [v.view(np.uint8) for v in vals], aos_o)
+    soa_want = orc.copy(aos_o, aos_host, soa_o)
+    rg = L.Record(W.PARTICLE)
+    aos = L.Mapping(rg, "aos_packed", [n])
+    soa = L.Mapping(rg, "soa_single", [n])
+    a_dev = torch.from_numpy(aos_host[0]).cuda()
+    s_dev = torch.empty(soa.blob_size(0), dtype=torch.uint8, device="cuda")
+    back = torch.empty_like(a_dev)
+    L.copy(aos, [a_dev], soa, [s_dev])
+    L.copy(soa, [s_dev], aos, [back])
+    torch.cuda.synchronize()
+    assert np.array_equal(s_dev.cpu().numpy(), soa_want[0])
+    assert torch.equal(back, a_dev)
+    # the SoA blob is the per-field arrays one after another
+    assert np.array_equal(s_dev.cpu().numpy(), np.concatenate([v.view(np.uint8) for v in vals]))
+
+
+# --------------------------------------------------------------------------
+# every ordered layout pair (identity included), several records and sizes
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("pair", PAIRS, ids=[f"{_name(a)}-{_name(b)}" for a, b in PAIRS])
+@pytest.mark.parametrize("n", [1, 1000, 4099])
+def test_particle_pairs(L, orc, pair, n):
+    run_case(L, orc, W.PARTICLE, pair[0], pair[1], [n], seed=n)
+
+
+@pytest.mark.parametrize("pair", PAIRS, ids=[f"{_name(a)}-{_name(b)}" for a, b in PAIRS])
+@pytest.mark.parametrize("name", ["mixed", "lbm", "listing1"])
+def test_record_pairs(L, orc, pair, name):
+    run_case(L, orc, W.RECORDS[name], pair[0], pair[1], [777], seed=7)
+
+
+@pytest.mark.parametrize("pair", [(("aos_packed", 0), ("soa_multi", 0)), (("aosoa", 8), ("aos_aligned", 0)),
+                                  (("soa_single", 0), ("aosoa", 64)), (("aos_aligned", 0), ("aosoa", 32))])
+@pytest.mark.parametrize("offsets", [(1, 0), (0, 3), (5, 7), (12, 9)])
+@pytest.mark.parametrize("name", ["particle", "mixed", "listing1"])
+def test_misaligned_blobs(L, orc, pair, offsets, name):
+    run_case(L, orc, W.RECORDS[name], pair[0], pair[1], [1031], seed=3, src_off=offsets[0],
+             dst_off=offsets[1])
+
+
+@pytest.mark.parametrize("extents", [[0], [1, 0, 5], [2], [3, 5, 7], [17, 1, 13], [64, 64]])
+@pytest.mark.parametrize("pair", [(("aos_aligned", 0), ("aosoa", 32)), (("soa_multi", 0), ("aos_packed", 0)),
+                                  (("aosoa", 64), ("soa_single", 0)), (("aosoa", 8), ("aosoa", 64))])
+def test_extents_and_empty(L, orc, extents, pair):
+    run_case(L, orc, W.MIXED, pair[0], pair[1], extents, seed=11)
+
+
+def test_oversized_destination_blobs_keep_their_tail(L, orc):
+    run_case(L, orc, W.MIXED, ("aos_packed", 0), ("soa_multi", 0), [513], seed=5, extra_dst=100)
+    run_case(L, orc, W.LBM, ("soa_multi", 0), ("aosoa", 32), [100], seed=5, extra_dst=37)
+
+
+@pytest.mark.parametrize("opts", [dict(path="tile", tile_records=t, threads=th)
+                                  for t in (16, 64, 256, 1024) for th in (64, 256, 1024)]
+                         + [dict(path="naive"), dict(path="naive", threads=64)])
+@pytest.mark.parametrize("pair", [(("aos_packed", 0), ("soa_single", 0)), (("aosoa", 32), ("soa_multi", 0)),
+                                  (("aos_aligned", 0), ("aosoa", 8)), (("soa_multi", 0), ("soa_single", 0))])
+def test_kernel_options(L, orc, opts, pair):
+    """The result is the same whatever tile, workgroup size or path is used."""
+    for name, n in (("particle", 3001), ("mixed", 1500), ("lbm", 300)):
+        r = L.Record(W.RECORDS[name])
+        try:
+            L.plan(L.Mapping(r, pair[0][0], [n], pair[0][1]), L.Mapping(r, pair[1][0], [n], pair[1][1]), **opts)
+        except L.LlamaError as e:  # a tile too large for LDS is refused up front
+            assert e.status == L.E_UNSUPPORTED and opts.get("tile_records", 0) >= 512
+            continue
+        run_case(L, orc, W.RECORDS[name], pair[0], pair[1], [n], seed=n, **opts)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_records(L, orc, seed):
+    g = random.Random(seed)
+
+    def rec(depth=0):
+        out = []
+        for _ in range(g.randint(1, 4)):
+            m = rec(depth + 1) if depth < 2 and g.random() < 0.3 else g.choice(
+                ["u8", "u16", "u32", "f64", "bool", "f32", "i64"])
+            if g.random() < 0.2:
+                m = (m, g.randint(1, 3))
+            out.append(m)
+        return out
+
+    r = rec()
+    layouts = LAYOUTS + [("aosoa", 1), ("aosoa", 2), ("aosoa", 16), ("aosoa", 128)]
+    for _ in range(6):
+        a, b = g.choice(layouts), g.choice(layouts)
+        run_case(L, orc, r, a, b, [g.randint(1, 3000)], seed=seed, src_off=g.choice([0, 0, 1, 4]),
+                 dst_off=g.choice([0, 0, 2, 8]))
+
+
+def test_special_float_patterns_survive(L, orc):
+    """NaN payloads (signalling and quiet), -0, subnormals and infinities move
+    bit for bit."""
+    n = 4096
+    ro, rg = orc.Record(W.PARTICLE), L.Record(W.PARTICLE)
+    vals = W.raw_u32_values(7, n, W.BASE_SEED + 2)
+    mb = [torch.from_numpy(v.view(np.uint8)).cuda() for v in vals]
+    for a, b in [(("soa_multi", 0), ("aosoa", 32)), (("soa_multi", 0), ("aos_packed", 0))]:
+        mid = L.Mapping(rg, b[0], [n], b[1]).alloc()
+        L.copy(L.Mapping(rg, "soa_multi", [n]), mb, L.Mapping(rg, b[0], [n], b[1]), mid)
+        back = L.Mapping(rg, "soa_multi", [n]).alloc()
+        L.copy(L.Mapping(rg, b[0], [n], b[1]), mid, L.Mapping(rg, "soa_multi", [n]), back)
+        torch.cuda.synchronize()
+        for v, t in zip(vals, back):
+            assert np.array_equal(t.cpu().numpy().view(np.uint32), v)
+        for special in W.SPECIAL_U32:
+            assert any((t.cpu().numpy().view(np.uint32) == special).any() for t in back)
