@@ -38,6 +38,10 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "tile_kernel_particle_2e26_counters.json")
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _name(layout):
     kind, lanes = layout
     return f"{kind}{lanes}" if kind == "aosoa" else kind
@@ -229,9 +233,12 @@ def main():
         dtype = "u64"
         cpu_n = 1 << 17
 
+    log(f"inputs generated ({args.workload}); filling {len(layouts)} layouts on {dev.name}")
     maps, blobs = setup_layouts(L, torch, record, extents, layouts, values)
     del values
+    log(f"timing {args.steps} steps of {len(pairs)} copies after {args.warmup} warm-up steps")
     wall, total_ms, per_pair, plans = time_pairs(L, torch, maps, blobs, pairs, args.steps, args.warmup, stream)
+    log(f"timed: {total_ms / args.steps:.2f} ms per step")
     step_bytes = sum(v["bytes"] for v in per_pair.values())
     value = step_bytes * args.steps / (total_ms * 1e-3) / 1e9
 
@@ -254,6 +261,7 @@ def main():
     extras["tile_kernel_gbs_min_pair"] = round(min(per_pair[p]["gbs_median"] for p in tile), 1)
     extras["tile_kernel_gbs_max_pair"] = round(max(per_pair[p]["gbs_median"] for p in tile), 1)
     if not args.no_naive:
+        log("timing the naive element-wise kernel on a subset of pairs")
         naive_pairs = tile[:: max(1, len(tile) // 6)]
         nv = naive_reference(L, torch, maps, blobs, naive_pairs, stream)
         ours = statistics.median(per_pair[p]["gbs_median"] for p in naive_pairs)
@@ -262,6 +270,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline(record, layouts, pairs, cpu_n)
 
     line = {

@@ -182,7 +182,9 @@ typedef enum {
 typedef struct {
     uint32_t path;         /* llama_path */
     uint32_t tile_records; /* TILE: records per tile, a power of two (16 .. 4096) */
-    uint32_t threads;      /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+    uint32_t threads;      /* threads per workgroup, a multiple of 64 in 64 .. 1024 */
+    uint32_t wg_per_cu;    /* TILE: 0 launches one workgroup per tile; 1 .. 16 launches a
+                              persistent grid of that many workgroups per compute unit */
     uint32_t flags;        /* reserved, must be 0 */
 } llama_copy_options;
 
@@ -200,7 +202,8 @@ typedef struct {
     uint32_t lds_bytes;     /* TILE: LDS bytes per workgroup */
     uint64_t workgroups;    /* workgroups launched */
     uint32_t runs;          /* STREAM: contiguous runs (zero runs included) */
-    uint32_t reserved;
+    uint32_t wg_per_cu;     /* TILE: persistent workgroups per compute unit (0: one per tile) */
+    uint64_t tiles;         /* TILE: tiles of tile_records records */
     uint64_t read_bytes;    /* bytes of source blobs the copy reads */
     uint64_t write_bytes;   /* bytes of destination blobs the copy writes */
 } llama_plan_info;

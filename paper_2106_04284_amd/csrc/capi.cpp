@@ -161,6 +161,8 @@ int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, con
         info->lds_bytes = p.lds_bytes;
         info->workgroups = p.workgroups;
         info->runs = p.path == LLAMA_PATH_STREAM ? p.stream.num_runs : 0;
+        info->wg_per_cu = p.wg_per_cu;
+        info->tiles = p.tiles;
         info->read_bytes = p.read_bytes;
         info->write_bytes = p.write_bytes;
     });
@@ -185,7 +187,7 @@ int llama_copy(const llama_mapping_desc* src, const llama_blob* src_blobs, const
 int llama_copy_naive(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
                      const llama_blob* dst_blobs, void* stream)
 {
-    llama_copy_options o{LLAMA_PATH_NAIVE, 0, 0, 0};
+    llama_copy_options o{LLAMA_PATH_NAIVE, 0, 0, 0, 0};
     return llama_copy_ex(src, src_blobs, dst, dst_blobs, &o, stream);
 }
 

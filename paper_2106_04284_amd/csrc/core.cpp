@@ -388,16 +388,29 @@ uint32_t tile_side(const Side& s, const Record& r, uint32_t T, TileSide& out, st
     out.log2_lanes = s.lanes ? log2_exact(s.lanes) : 0;
     if (s.lanes >= 1 && s.lanes <= T) {
         out.mode = kRecordMajor;
-        uint64_t span = (uint64_t(T) >> out.log2_lanes) * s.block;
-        return uint32_t(std::min<uint64_t>((span + 15 + 15) / 16 * 16, uint64_t(1) << 31));
+        out.tile_bytes = (uint64_t(T) >> out.log2_lanes) * s.block;
+        out.pos_lg = out.log2_lanes;
+        out.pos_k = uint32_t(std::min<uint64_t>(s.block, UINT32_MAX));
+        out.pos_m = uint32_t(s.lanes - 1);
+        return uint32_t(std::min<uint64_t>((out.tile_bytes + 15 + 15) / 16 * 16, uint64_t(1) << 31));
     }
     out.mode = kFieldMajor;
+    out.tile_bytes = 0;
+    out.pos_lg = 31;
+    out.pos_k = 0;
+    out.pos_m = ~0u;
     uint64_t total = 0;
     for (size_t f = 0; f < F; f++) {
         leaf_lds[f] = uint32_t(std::min<uint64_t>(total, uint64_t(1) << 31));
         total += (uint64_t(T) * r.leaves[f].size + 15 + 15) / 16 * 16;
     }
     return uint32_t(std::min<uint64_t>(total, uint64_t(1) << 31));
+}
+
+uint32_t log2_move(uint64_t bits)
+{
+    uint64_t w = std::min<uint64_t>(lowbit(bits | 16), 16);
+    return log2_exact(w);
 }
 
 bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
@@ -426,33 +439,65 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
     a.num_tiles = (a.npad + T - 1) / T;
     a.num_leaves = uint32_t(F);
     a.lds_bytes = uint32_t(total);
+    // T >= 16 makes every tile stride a multiple of 16, so a span's offset
+    // modulo 16 is that of its first tile
+    const uint64_t src_rm_bits = a.src.mode == kRecordMajor ? rq.src.block : 0;
+    const uint64_t dst_rm_bits = a.dst.mode == kRecordMajor ? rq.dst.block : 0;
     for (size_t f = 0; f < F; f++) {
         TileEntry& e = a.e[f];
         e.src_addr = rq.src_ptr[rq.src.blob[f]] + rq.src.base[f];
         e.dst_addr = rq.dst_ptr[rq.dst.blob[f]] + rq.dst.base[f];
         e.size = r.leaves[f].size;
-        e.src_lds16 = uint16_t(src_lds[f] / 16);
-        e.dst_lds16 = uint16_t(dst_lds[f] / 16);
+        e.src_pos = a.src.mode == kRecordMajor
+                        ? a.src.lds_base + uint32_t(rq.src_ptr[0] & 15) + uint32_t(rq.src.base[f])
+                        : a.src.lds_base + src_lds[f] + uint32_t(e.src_addr & 15);
+        e.dst_pos = a.dst.mode == kRecordMajor
+                        ? a.dst.lds_base + uint32_t(rq.dst_ptr[0] & 15) + uint32_t(rq.dst.base[f])
+                        : a.dst.lds_base + dst_lds[f] + uint32_t(e.dst_addr & 15);
+        e.move = log2_move(uint64_t(e.src_pos) | e.dst_pos | e.size | src_rm_bits | dst_rm_bits);
     }
     size_t k = F;
-    for (const auto& g : rq.dst.gaps) {
+    for (const auto& g : rq.dst.gaps) { // only record-major (aligned AoS) destinations have gaps
         TileEntry& e = a.e[k++];
         e.src_addr = 0;
         e.dst_addr = rq.dst_ptr[0] + g.first;
         e.size = uint32_t(g.second);
+        e.src_pos = 0;
+        e.dst_pos = a.dst.lds_base + uint32_t(rq.dst_ptr[0] & 15) + uint32_t(g.first);
+        e.move = log2_move(uint64_t(e.dst_pos) | e.size | dst_rm_bits) | (1u << 31);
     }
     a.num_entries = uint32_t(k);
+    // field-major spans are short: rotate the first loading wave and the
+    // first storing thread from leaf to leaf so that every wave takes a share
+    const uint32_t nwaves = p.threads / 64;
+    uint32_t first_wave = 0, first_thread = 0;
+    for (size_t f = 0; f < F; f++) {
+        TileEntry& e = a.e[f];
+        e.move |= (first_wave << 4) | (first_thread << 8);
+        uint64_t granules = (uint64_t(T) * e.size + 30) / 16;
+        first_wave = uint32_t((first_wave + (granules + 63) / 64) % nwaves);
+        first_thread = uint32_t((first_thread + granules) % p.threads);
+    }
     p.path = LLAMA_PATH_TILE;
     p.lds_bytes = a.lds_bytes;
-    p.workgroups = a.num_tiles;
+    p.tiles = a.num_tiles;
     return true;
+}
+
+// Grid: by default one workgroup per tile (the hardware keeps as many
+// resident as LDS and wave slots allow); with wg_per_cu set, a persistent
+// grid of that many workgroups per compute unit loops over the tiles.
+void tile_grid(Plan& p, uint32_t wg_per_cu)
+{
+    p.wg_per_cu = wg_per_cu;
+    p.workgroups = wg_per_cu ? std::min<uint64_t>(p.tiles, uint64_t(device_cu_count()) * wg_per_cu) : p.tiles;
 }
 
 uint32_t default_tile(const Request& rq)
 {
     uint64_t rec = std::max<uint64_t>(rq.record.packed_size, 1);
     uint64_t T = 16;
-    while (T * 2 * rec <= 8192 && T < 4096)
+    while (T * 2 * rec <= kDefaultTileBytes && T < 4096)
         T *= 2;
     return uint32_t(T);
 }
@@ -512,11 +557,14 @@ Plan make_plan(const Request& rq, const llama_copy_options* opt)
     if (want > LLAMA_PATH_NAIVE)
         fail(LLAMA_E_INVALID_ARG, "llama_copy_options.path is not a llama_path");
     uint32_t threads = (opt && opt->threads) ? opt->threads : 0;
-    if (threads && (!is_pow2(threads) || threads < 64 || threads > 1024))
-        fail(LLAMA_E_INVALID_ARG, "threads must be 64, 128, 256, 512 or 1024");
+    if (threads && (threads % 64 != 0 || threads > 1024))
+        fail(LLAMA_E_INVALID_ARG, "threads must be a multiple of 64 in 64..1024");
     uint32_t T = (opt && opt->tile_records) ? opt->tile_records : 0;
     if (T && (!is_pow2(T) || T < 16 || T > 4096))
         fail(LLAMA_E_INVALID_ARG, "tile_records must be a power of two in 16..4096");
+    uint32_t wg_per_cu = opt ? opt->wg_per_cu : 0;
+    if (wg_per_cu > 16)
+        fail(LLAMA_E_INVALID_ARG, "wg_per_cu must be 0..16");
     if (rq.dst.npad == 0) {
         p.path = LLAMA_PATH_EMPTY;
         return p;
@@ -529,18 +577,20 @@ Plan make_plan(const Request& rq, const llama_copy_options* opt)
             fail(LLAMA_E_UNSUPPORTED, "the STREAM path needs long runs congruent modulo 4 on both sides");
     }
     if (want == LLAMA_PATH_AUTO || want == LLAMA_PATH_TILE) {
+        // four records per thread in the LDS remap
+        auto nthreads = [&](uint32_t t) { return std::min<uint32_t>(std::max<uint32_t>(t / 4, 64), kDefaultThreads); };
         uint32_t t = T ? T : default_tile(rq);
-        if (!threads)
-            p.threads = std::min<uint32_t>(std::max<uint32_t>(t, 64), kDefaultThreads);
+        p.threads = threads ? threads : nthreads(t);
         bool ok = fill_tile(rq, t, T ? kHardLdsBytes : kMaxLdsBytes, p);
         while (!ok && !T && t > 16) {
             t /= 2;
-            if (!threads)
-                p.threads = std::min<uint32_t>(std::max<uint32_t>(t, 64), kDefaultThreads);
+            p.threads = threads ? threads : nthreads(t);
             ok = fill_tile(rq, t, kMaxLdsBytes, p);
         }
-        if (ok)
+        if (ok) {
+            tile_grid(p, wg_per_cu);
             return p;
+        }
         if (want == LLAMA_PATH_TILE)
             fail(LLAMA_E_UNSUPPORTED, "the TILE path does not fit this record in LDS with these options");
     }

@@ -86,6 +86,8 @@ struct Plan {
     uint32_t threads = 256;
     uint64_t workgroups = 0;
     uint32_t lds_bytes = 0;
+    uint32_t wg_per_cu = 0;
+    uint64_t tiles = 0;
     uint64_t read_bytes = 0, write_bytes = 0;
     TileArgs tile{};     // path == TILE
     StreamArgs stream{}; // path == STREAM
@@ -93,12 +95,16 @@ struct Plan {
 };
 
 Plan make_plan(const Request& rq, const llama_copy_options* opt);
-void launch(const Plan& p, void* stream); // kernels.hip
+
+// kernels.hip
+void launch(const Plan& p, void* stream);
+uint32_t device_cu_count(); // compute units of the current device (256 when none is visible)
 
 // default kernel parameters
-constexpr uint32_t kDefaultThreads = 256;
-constexpr uint32_t kDefaultTileBytes = 16384; // target source bytes per tile
-constexpr uint32_t kMaxLdsBytes = 65536;      // LDS budget per workgroup for the default plan
-constexpr uint32_t kHardLdsBytes = 160 * 1024;
+constexpr uint32_t kDefaultThreads = 256;      // threads per workgroup
+constexpr uint32_t kDefaultTileBytes = 16384;  // TILE: target source bytes per tile
+constexpr uint32_t kMaxLdsBytes = 65536;       // TILE: LDS budget per workgroup for the default plan
+constexpr uint32_t kHardLdsBytes = 160 * 1024; // LDS of one gfx950 compute unit
+constexpr uint32_t kMaxWavesPerCu = 32;
 
 } // namespace llama

@@ -15,28 +15,37 @@ namespace llama {
 // L > T) it is "field-major": the tile is one span of T values per leaf.
 // ---------------------------------------------------------------------------
 
-constexpr int kTileMaxEntries = 150;
+constexpr int kTileMaxEntries = 118;
 
 enum : uint32_t { kRecordMajor = 0, kFieldMajor = 1 };
 
+// T is a power of two >= 16, so every tile starts at the same offset modulo
+// 16 inside each span; LDS positions are therefore the same for every tile
+// and are computed once on the host.
 struct TileSide {
-    uint64_t span_base; // record-major: device address of the blob
-    uint64_t lanes;     // L (0: unblocked)
-    uint64_t block;     // K: bytes per block
-    uint32_t mode;      // kRecordMajor / kFieldMajor
+    uint64_t span_base;  // record-major: device address of the blob
+    uint64_t tile_bytes; // record-major: bytes of one full tile, (T / L) * K
+    uint64_t block;      // K: bytes per block
+    uint64_t lanes;      // L (0: unblocked)
+    uint32_t mode;       // kRecordMajor / kFieldMajor
     uint32_t log2_lanes;
-    uint32_t lds_base;  // byte offset of this side's LDS region
-    uint32_t lds_bytes; // bytes of this side's LDS region
+    uint32_t lds_base;   // byte offset of this side's LDS region
+    uint32_t lds_bytes;  // bytes of this side's LDS region
+    // LDS position of record r of an entry: pos + (r >> pos_lg) * pos_k + (r & pos_m) * size
+    uint32_t pos_lg, pos_k, pos_m, pad;
 };
 
-// One entry of the remap: a leaf (source and destination), or a zero-filled
-// destination gap inside every record (aligned AoS padding, src_addr == 0).
+// One entry of the remap: a leaf, or a destination gap inside every record
+// (aligned AoS padding) that is filled with zeros.
 struct TileEntry {
-    uint64_t src_addr; // leaf: device address of blob + base offset; gap: 0
-    uint64_t dst_addr; // device address of blob + base offset
+    uint64_t src_addr; // field-major source: device address of the leaf's values (blob + base); 0 for a gap
+    uint64_t dst_addr; // field-major destination: device address of the leaf's values
+    uint32_t src_pos;  // LDS byte of record 0 in the source region (region offset and 16-byte phase included)
+    uint32_t dst_pos;  // LDS byte of record 0 in the destination region
     uint32_t size;     // bytes per record
-    uint16_t src_lds16; // field-major source: LDS offset of this leaf's span / 16
-    uint16_t dst_lds16; // field-major destination: LDS offset of this leaf's span / 16
+    uint32_t move;     // bits 0-2: log2 of the move width (1 .. 16 bytes); bits 4-7: first loading
+                       // wave of this leaf's source span; bits 8-19: first storing thread of this
+                       // leaf's destination span; bit 31: gap (write zeros)
 };
 
 struct TileArgs {
@@ -50,6 +59,7 @@ struct TileArgs {
     TileSide src, dst;
     TileEntry e[kTileMaxEntries];
 };
+static_assert(sizeof(TileArgs) <= 4096, "kernel arguments are limited to 4 KiB");
 
 // ---------------------------------------------------------------------------
 // STREAM: contiguous byte runs copied with 16-byte accesses; a run with
@@ -58,7 +68,7 @@ struct TileArgs {
 // ---------------------------------------------------------------------------
 
 constexpr int kStreamMaxRuns = 120;
-constexpr uint32_t kStreamChunkLog2 = 16; // 64 KiB per workgroup
+constexpr uint32_t kStreamChunkLog2 = 12; // 4 KiB per workgroup
 
 struct StreamRun {
     uint64_t src;
@@ -73,6 +83,7 @@ struct StreamArgs {
     uint64_t num_chunks;
     StreamRun r[kStreamMaxRuns];
 };
+static_assert(sizeof(StreamArgs) <= 4096, "kernel arguments are limited to 4 KiB");
 
 // ---------------------------------------------------------------------------
 // NAIVE: one thread per record, mapping arithmetic with run-time '/' and '%'.
@@ -100,5 +111,6 @@ struct NaiveArgs {
     NaiveSide src, dst;
     NaiveEntry e[kNaiveMaxEntries];
 };
+static_assert(sizeof(NaiveArgs) <= 4096, "kernel arguments are limited to 4 KiB");
 
 } // namespace llama

@@ -33,60 +33,66 @@ __device__ __forceinline__ uint32_t wave_id()
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// One 16-byte global load per active lane, written by the memory system
+// straight into LDS at m0 + 16 * lane (global_load_lds_dwordx4).  Issued as
+// inline assembly so that the compiler does not wait for these loads at every
+// later barrier: the only wave that issues them waits for them itself before
+// the barrier that publishes the buffer.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm" // m0 is written here and used by nothing else in these kernels
+__device__ __forceinline__ void lds_dma16(uint64_t gaddr, uint32_t lds_addr)
+{
+    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(gaddr), "s"(lds_addr) : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
 // Loads bytes [gstart, gstart + len) into LDS at lds_region + (gstart & 15):
-// whole 16-byte granules from gstart rounded down.  A granule that holds a
-// byte of the span lies in the same page as that byte, so the rounding never
-// reaches an unmapped page; the extra bytes are never used.
+// whole 16-byte granules from gstart rounded down, 64 granules (1 KiB) per
+// wave instruction; chunk c of the span goes to wave (c + first_wave) mod
+// nwaves.  A granule that holds a byte of the span lies in the same page as
+// that byte, so the rounding never reaches an unmapped page; the extra bytes
+// are never used.
 __device__ __forceinline__ void load_span(uint64_t gstart, uint32_t len, uint32_t lds_region, uint32_t wave,
-                                          uint32_t nwaves, uint32_t lane, uint8_t* lds)
+                                          uint32_t nwaves, uint32_t first_wave, uint32_t lane, uint32_t lds_base)
 {
     const uint32_t shift = uint32_t(gstart) & 15u;
     const uint64_t g0 = gstart - shift;
     const uint32_t G = (shift + len + 15u) >> 4;
-    for (uint32_t c = wave; c * 64u < G; c += nwaves) {
+    const uint32_t c0 = wave >= first_wave ? wave - first_wave : wave + nwaves - first_wave;
+    for (uint32_t c = c0; c * 64u < G; c += nwaves) {
         const uint32_t gi = c * 64u + lane;
         if (gi < G)
-            __builtin_amdgcn_global_load_lds((const void*)(g0 + uint64_t(gi) * 16u),
-                                             (lds_void_t*)(lds + lds_region + c * 1024u), 16, 0, 0);
+            lds_dma16(g0 + uint64_t(gi) * 16u, uniform(lds_base + lds_region + c * 1024u));
     }
 }
 
 // Stores LDS bytes lds_region + (gstart & 15) .. into [gstart, gstart + len):
 // whole granules with 16-byte stores, the partial first and last granule byte
-// by byte so that no byte outside the span is written.
+// by byte so that no byte outside the span is written.  Granule gi goes to
+// thread (gi + rot) mod nthr, so that short spans spread over the waves.
 __device__ __forceinline__ void store_span(uint64_t gstart, uint32_t len, uint32_t lds_region, uint32_t tid,
-                                           uint32_t nthr, const uint8_t* lds)
+                                           uint32_t nthr, uint32_t rot, const uint8_t* lds)
 {
     const uint32_t shift = uint32_t(gstart) & 15u;
     const uint64_t g0 = gstart - shift;
     const uint32_t end = shift + len;
     const uint32_t G = (end + 15u) >> 4;
-    for (uint32_t gi = tid; gi < G; gi += nthr) {
+    for (uint32_t gi = tid >= rot ? tid - rot : tid + nthr - rot; gi < G; gi += nthr) {
         const uint32_t lo = gi == 0 ? shift : 0u;
         const uint32_t hi = min(16u, end - gi * 16u);
-        GLOBAL uint8_t* gp = (GLOBAL uint8_t*)(g0 + uint64_t(gi) * 16u);
         const uint8_t* lp = lds + lds_region + gi * 16u;
         if (lo == 0 && hi == 16) {
-            *(GLOBAL u32x4*)gp = *(const u32x4*)lp;
+            *(GLOBAL u32x4*)(g0 + uint64_t(gi) * 16u) = *(const u32x4*)lp;
         } else {
+            GLOBAL uint8_t* gp = (GLOBAL uint8_t*)(g0 + uint64_t(gi) * 16u);
             for (uint32_t b = lo; b < hi; b++)
                 gp[b] = lp[b];
         }
     }
 }
 
-// Position of record r of entry e inside a side's LDS region:
-//   p0 + (r >> lg) * K + (r & m) * size
-struct Pos {
-    uint32_t p0, lg, K, m;
-};
-
-__device__ __forceinline__ uint32_t pos_of(const Pos& p, uint32_t r, uint32_t size)
-{
-    return p.p0 + (r >> p.lg) * p.K + (r & p.m) * size;
-}
-
-// Global start of a field-major span of records [i0, ...) of one leaf.
+// Global start of the field-major span of one leaf for the records of the
+// tile that starts at record i0.
 __device__ __forceinline__ uint64_t field_span_start(uint64_t addr, const TileSide& s, uint64_t i0, uint32_t size)
 {
     if (s.lanes == 0)
@@ -94,114 +100,93 @@ __device__ __forceinline__ uint64_t field_span_start(uint64_t addr, const TileSi
     return addr + (i0 >> s.log2_lanes) * s.block + (i0 & (s.lanes - 1)) * size;
 }
 
+// Moves one entry of records r0, r0 + step, r0 + 2 step, r0 + 3 step inside
+// LDS in words of type T; records >= nv, and gap entries, receive zeros.  The
+// four loads are issued before the four stores.
 template <typename T>
-__device__ __forceinline__ void move_values(uint8_t* lds, uint32_t dpos, uint32_t spos, uint32_t size, bool zero)
+__device__ __forceinline__ void move4(uint8_t* lds, uint32_t sp, uint32_t dp, const TileSide& s, const TileSide& d,
+                                      uint32_t size, uint32_t r0, uint32_t step, uint32_t nv, uint32_t nd, bool gap)
 {
     for (uint32_t k = 0; k < size; k += sizeof(T)) {
-        T v;
-        if (zero)
-            v = T{};
-        else
-            v = *(const T*)(lds + spos + k);
-        *(T*)(lds + dpos + k) = v;
-    }
-}
-
-__device__ void tile_body(const TileArgs& a, uint64_t t, uint8_t* lds)
-{
-    const uint32_t tid = threadIdx.x, nthr = blockDim.x;
-    const uint32_t lane = tid & 63u, wave = wave_id(), nwaves = nthr >> 6;
-    const uint32_t T = 1u << a.log2_tile;
-    const uint64_t i0 = t << a.log2_tile;
-    const uint32_t nv = i0 < a.n ? uint32_t(min<uint64_t>(T, a.n - i0)) : 0u; // records with values
-    const uint32_t nd = uint32_t(min<uint64_t>(T, a.npad - i0));              // records the destination spans
-
-    // ---- 1. source span(s) -> LDS
-    if (nv > 0) {
-        if (a.src.mode == kRecordMajor) {
-            const uint64_t start = a.src.span_base + (i0 >> a.src.log2_lanes) * a.src.block;
-            const uint32_t len = uint32_t(((uint64_t(nv) + a.src.lanes - 1) >> a.src.log2_lanes) * a.src.block);
-            load_span(start, len, a.src.lds_base, wave, nwaves, lane, lds);
-        } else {
-            for (uint32_t f = 0; f < a.num_leaves; f++) {
-                const TileEntry& e = a.e[f];
-                const uint64_t start = field_span_start(e.src_addr, a.src, i0, e.size);
-                load_span(start, nv * e.size, a.src.lds_base + uint32_t(e.src_lds16) * 16u, wave, nwaves, lane, lds);
-            }
+        T v[4];
+#pragma unroll
+        for (uint32_t j = 0; j < 4; j++) {
+            const uint32_t r = r0 + j * step;
+            v[j] = T{};
+            if (!gap && r < nv)
+                v[j] = *(const T*)(lds + sp + (r >> s.pos_lg) * s.pos_k + (r & s.pos_m) * size + k);
         }
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-
-    // ---- 2. move every value from its source position to its destination
-    //         position inside LDS; destination padding becomes zero
-    const uint64_t src_start = a.src.span_base + (i0 >> a.src.log2_lanes) * a.src.block;
-    const uint64_t dst_start = a.dst.span_base + (i0 >> a.dst.log2_lanes) * a.dst.block;
-    for (uint32_t k = 0; k < a.num_entries; k++) {
-        const TileEntry& e = a.e[k];
-        const uint32_t size = e.size;
-        const bool gap = e.src_addr == 0;
-        Pos sp{0, 31, 0, ~0u}, dp{0, 31, 0, ~0u};
-        uint32_t align_bits = size;
-        if (!gap) {
-            if (a.src.mode == kRecordMajor) {
-                sp.p0 = a.src.lds_base + (uint32_t(src_start) & 15u) + uint32_t(e.src_addr - a.src.span_base);
-                sp.lg = a.src.log2_lanes;
-                sp.K = uint32_t(a.src.block);
-                sp.m = uint32_t(a.src.lanes - 1);
-                align_bits |= sp.K;
-            } else {
-                const uint64_t s0 = field_span_start(e.src_addr, a.src, i0, size);
-                sp.p0 = a.src.lds_base + uint32_t(e.src_lds16) * 16u + (uint32_t(s0) & 15u);
-            }
-            align_bits |= sp.p0;
-        }
-        if (a.dst.mode == kRecordMajor) {
-            dp.p0 = a.dst.lds_base + (uint32_t(dst_start) & 15u) + uint32_t(e.dst_addr - a.dst.span_base);
-            dp.lg = a.dst.log2_lanes;
-            dp.K = uint32_t(a.dst.block);
-            dp.m = uint32_t(a.dst.lanes - 1);
-            align_bits |= dp.K;
-        } else {
-            const uint64_t d0 = field_span_start(e.dst_addr, a.dst, i0, size);
-            dp.p0 = a.dst.lds_base + uint32_t(e.dst_lds16) * 16u + (uint32_t(d0) & 15u);
-        }
-        align_bits |= dp.p0;
-        const uint32_t w = uniform(min(align_bits & (~align_bits + 1u), 16u));
-        for (uint32_t r = tid; r < nd; r += nthr) {
-            const bool zero = gap || r >= nv;
-            const uint32_t dpos = pos_of(dp, r, size);
-            const uint32_t spos = zero ? 0u : pos_of(sp, r, size);
-            switch (w) {
-            case 16: move_values<u32x4>(lds, dpos, spos, size, zero); break;
-            case 8: move_values<uint64_t>(lds, dpos, spos, size, zero); break;
-            case 4: move_values<uint32_t>(lds, dpos, spos, size, zero); break;
-            case 2: move_values<uint16_t>(lds, dpos, spos, size, zero); break;
-            default: move_values<uint8_t>(lds, dpos, spos, size, zero); break;
-            }
-        }
-    }
-    __syncthreads();
-
-    // ---- 3. LDS -> destination span(s)
-    if (a.dst.mode == kRecordMajor) {
-        const uint32_t len = uint32_t(((uint64_t(nd) + a.dst.lanes - 1) >> a.dst.log2_lanes) * a.dst.block);
-        store_span(dst_start, len, a.dst.lds_base, tid, nthr, lds);
-    } else {
-        for (uint32_t f = 0; f < a.num_leaves; f++) {
-            const TileEntry& e = a.e[f];
-            const uint64_t start = field_span_start(e.dst_addr, a.dst, i0, e.size);
-            store_span(start, nd * e.size, a.dst.lds_base + uint32_t(e.dst_lds16) * 16u, tid, nthr, lds);
+#pragma unroll
+        for (uint32_t j = 0; j < 4; j++) {
+            const uint32_t r = r0 + j * step;
+            if (r < nd)
+                *(T*)(lds + dp + (r >> d.pos_lg) * d.pos_k + (r & d.pos_m) * size + k) = v[j];
         }
     }
 }
 
+// One tile per workgroup: every wave issues its share of the source loads
+// straight into LDS, then all threads move the values to their destination
+// positions inside LDS, then all threads store the destination span(s).
 __global__ void __launch_bounds__(1024) tile_kernel(const TileArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+    const uint32_t lane = tid & 63u, wave = wave_id(), nwaves = nthr >> 6;
+    const uint32_t lds_base = uint32_t(uintptr_t((lds_void_t*)lds));
+    const uint32_t T = 1u << a.log2_tile;
     for (uint64_t t = blockIdx.x; t < a.num_tiles; t += gridDim.x) {
-        tile_body(a, t, lds);
+        const uint64_t i0 = t << a.log2_tile;
+        const uint32_t nv = i0 < a.n ? uint32_t(min<uint64_t>(T, a.n - i0)) : 0u; // records with values
+        const uint32_t nd = uint32_t(min<uint64_t>(T, a.npad - i0));              // records the destination spans
+
+        // ---- 1. source span(s) -> LDS
+        if (nv > 0) {
+            if (a.src.mode == kRecordMajor) {
+                const uint32_t len = uint32_t(((uint64_t(nv) + a.src.lanes - 1) >> a.src.log2_lanes) * a.src.block);
+                load_span(a.src.span_base + t * a.src.tile_bytes, len, a.src.lds_base, wave, nwaves, 0, lane,
+                          lds_base);
+            } else {
+                for (uint32_t f = 0; f < a.num_leaves; f++) {
+                    const TileEntry& e = a.e[f];
+                    load_span(field_span_start(e.src_addr, a.src, i0, e.size), nv * e.size, e.src_pos & ~15u, wave,
+                              nwaves, (e.move >> 4) & 15u, lane, lds_base);
+                }
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
+
+        // ---- 2. every value from its source to its destination position;
+        //         destination padding becomes zero
+        for (uint32_t k = 0; k < a.num_entries; k++) {
+            const TileEntry& e = a.e[k];
+            const bool gap = (e.move >> 31) != 0;
+            for (uint32_t r0 = tid; r0 < nd; r0 += 4u * nthr) {
+                switch (e.move & 7u) {
+                case 4: move4<u32x4>(lds, e.src_pos, e.dst_pos, a.src, a.dst, e.size, r0, nthr, nv, nd, gap); break;
+                case 3: move4<uint64_t>(lds, e.src_pos, e.dst_pos, a.src, a.dst, e.size, r0, nthr, nv, nd, gap); break;
+                case 2: move4<uint32_t>(lds, e.src_pos, e.dst_pos, a.src, a.dst, e.size, r0, nthr, nv, nd, gap); break;
+                case 1: move4<uint16_t>(lds, e.src_pos, e.dst_pos, a.src, a.dst, e.size, r0, nthr, nv, nd, gap); break;
+                default: move4<uint8_t>(lds, e.src_pos, e.dst_pos, a.src, a.dst, e.size, r0, nthr, nv, nd, gap); break;
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- 3. LDS -> destination span(s)
+        if (a.dst.mode == kRecordMajor) {
+            const uint32_t len = uint32_t(((uint64_t(nd) + a.dst.lanes - 1) >> a.dst.log2_lanes) * a.dst.block);
+            store_span(a.dst.span_base + t * a.dst.tile_bytes, len, a.dst.lds_base, tid, nthr, 0, lds);
+        } else {
+            for (uint32_t f = 0; f < a.num_leaves; f++) {
+                const TileEntry& e = a.e[f];
+                store_span(field_span_start(e.dst_addr, a.dst, i0, e.size), nd * e.size, e.dst_pos & ~15u, tid,
+                           nthr, (e.move >> 8) & 4095u, lds);
+            }
+        }
+        if (t + gridDim.x < a.num_tiles)
+            __syncthreads();
     }
 }
 
@@ -333,6 +318,27 @@ void set_attributes()
 constexpr uint64_t kMaxGrid = uint64_t(1) << 24;
 
 } // namespace
+
+uint32_t device_cu_count()
+{
+    static thread_local int cached_device = -1;
+    static thread_local uint32_t cached = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    if (dev != cached_device) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) {
+            (void)hipGetLastError();
+            return 256;
+        }
+        cached_device = dev;
+        cached = uint32_t(n);
+    }
+    return cached;
+}
 
 void launch(const Plan& p, void* stream_ptr)
 {

@@ -63,13 +63,13 @@ class Blob(ctypes.Structure):
 
 class CopyOptions(ctypes.Structure):
     _fields_ = [("path", ctypes.c_uint32), ("tile_records", ctypes.c_uint32), ("threads", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32)]
+                ("wg_per_cu", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("path", ctypes.c_uint32), ("tile_records", ctypes.c_uint32), ("threads", ctypes.c_uint32),
                 ("lds_bytes", ctypes.c_uint32), ("workgroups", ctypes.c_uint64), ("runs", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("read_bytes", ctypes.c_uint64),
+                ("wg_per_cu", ctypes.c_uint32), ("tiles", ctypes.c_uint64), ("read_bytes", ctypes.c_uint64),
                 ("write_bytes", ctypes.c_uint64)]
 
 
@@ -257,20 +257,20 @@ def _stream(stream):
     return stream.cuda_stream
 
 
-def _options(path=PATH_AUTO, tile_records=0, threads=0):
+def _options(path=PATH_AUTO, tile_records=0, threads=0, wg_per_cu=0):
     if isinstance(path, str):
         path = {"auto": PATH_AUTO, "stream": PATH_STREAM, "tile": PATH_TILE, "naive": PATH_NAIVE}[path]
-    return CopyOptions(path, tile_records, threads, 0)
+    return CopyOptions(path, tile_records, threads, wg_per_cu, 0)
 
 
 def copy(src: Mapping, src_blobs, dst: Mapping, dst_blobs, stream=None, path=PATH_AUTO, tile_records=0,
-         threads=0):
+         threads=0, wg_per_cu=0):
     """llama_copy / llama_copy_ex: enqueues the copy on `stream`."""
     sb, db = _blobs(src_blobs), _blobs(dst_blobs)
-    if path == PATH_AUTO and not tile_records and not threads:
+    if path == PATH_AUTO and not tile_records and not threads and not wg_per_cu:
         check(lib().llama_copy(ctypes.byref(src.desc), sb, ctypes.byref(dst.desc), db, _stream(stream)))
     else:
-        o = _options(path, tile_records, threads)
+        o = _options(path, tile_records, threads, wg_per_cu)
         check(lib().llama_copy_ex(ctypes.byref(src.desc), sb, ctypes.byref(dst.desc), db, ctypes.byref(o),
                                   _stream(stream)))
 
@@ -281,11 +281,12 @@ def copy_naive(src: Mapping, src_blobs, dst: Mapping, dst_blobs, stream=None):
                                  _blobs(dst_blobs), _stream(stream)))
 
 
-def plan(src: Mapping, dst: Mapping, path=PATH_AUTO, tile_records=0, threads=0) -> dict:
+def plan(src: Mapping, dst: Mapping, path=PATH_AUTO, tile_records=0, threads=0, wg_per_cu=0) -> dict:
     """llama_plan: what a copy of this pair would launch."""
     info = PlanInfo()
-    o = _options(path, tile_records, threads)
+    o = _options(path, tile_records, threads, wg_per_cu)
     check(lib().llama_plan(ctypes.byref(src.desc), ctypes.byref(dst.desc), ctypes.byref(o), ctypes.byref(info)))
     return {"path": PATH_NAMES.get(info.path, "?"), "tile_records": info.tile_records, "threads": info.threads,
             "lds_bytes": info.lds_bytes, "workgroups": info.workgroups, "runs": info.runs,
+            "wg_per_cu": info.wg_per_cu, "tiles": info.tiles,
             "read_bytes": info.read_bytes, "write_bytes": info.write_bytes}
