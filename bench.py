@@ -19,6 +19,7 @@ Other workloads (--workload): lbm (128^3 cells of 19 f64 + u32, aligned AoS
 from __future__ import annotations
 
 import argparse
+import collections
 import hashlib
 import json
 import os
@@ -188,12 +189,184 @@ def d2d_reference(torch, nbytes, stream, reps=5):
     return 2 * nbytes / (statistics.median(ms) * 1e-3) / 1e9
 
 
+# --------------------------------------------------------------------------
+# batching (1,000 arrays) and serving (Poisson requests)
+# --------------------------------------------------------------------------
+
+def _layout_maps(L, rec_name, n, src, dst, cache):
+    rg = cache.setdefault(("rec", rec_name), L.Record(W.RECORDS[rec_name]))
+    return L.Mapping(rg, src[0], [n], src[1]), L.Mapping(rg, dst[0], [n], dst[1])
+
+
+def _tune_classes(L, torch, classes, stream):
+    """Autotunes each (record, layout pair) class once at 2^20 records."""
+    cache, tuned = {}, 0
+    for rec_name, src, dst in sorted(classes):
+        ms, md = _layout_maps(L, rec_name, 1 << 20, src, dst, cache)
+        if L.tune_lookup(ms, md) is not None:
+            continue
+        sb = [torch.empty(s, dtype=torch.uint8, device="cuda").random_(0, 255) for s in ms.blob_sizes()]
+        db = md.alloc()
+        L.autotune(ms, sb, md, db, stream=stream, reps=2)
+        tuned += 1
+        del sb, db
+    return tuned
+
+
+def bench_batch(L, torch, args, dev, stream):
+    items_spec = W.batch_items()
+    log(f"batch: allocating {len(items_spec)} arrays")
+    cache, items = {}, []
+    for it in items_spec:
+        ms, md = _layout_maps(L, it["record"], it["n"], it["src"], it["dst"], cache)
+        sb = [torch.empty(s, dtype=torch.uint8, device="cuda") for s in ms.blob_sizes()]
+        for t in sb:
+            t.random_(0, 255)
+        items.append((ms, sb, md, md.alloc()))
+    total = sum(sum(i[0].blob_sizes()) + sum(i[2].blob_sizes()) for i in items)
+    torch.cuda.synchronize()
+    log(f"batch: {total / 1e9:.1f} GB read+written per pass; autotuning the record/pair classes")
+    tuned = _tune_classes(L, torch, {(it["record"], it["src"], it["dst"]) for it in items_spec}, stream)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return statistics.median(ms), min(ms)
+
+    best = None
+    for th in (128, 256):
+        b = L.Batch(items, threads=th)
+        med, mn = timed(lambda: b.launch(stream), 3)
+        log(f"batch: threads {th}: {total / (med * 1e-3) / 1e9:.1f} GB/s")
+        if best is None or med < best[1]:
+            best = (b, med, th)
+    b, _, th = best
+    med, mn = timed(lambda: b.launch(stream), args.steps)
+    info = b.info()
+    log("batch: timing 1,000 per-array naive launches and 1,000 per-array llama_copy launches")
+    naive_med, _ = timed(lambda: [L.copy_naive(i[0], i[1], i[2], i[3], stream=stream) for i in items], 2)
+    lone_med, _ = timed(lambda: [L.copy(i[0], i[1], i[2], i[3], stream=stream) for i in items], 2)
+    gbs = total / (med * 1e-3) / 1e9
+    return {"metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": 1, "ms_per_step": round(med, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "batching: 1,000 arrays, record counts log-uniform 1e3..1e7, particle or mixed "
+                                   "{f64[3],f32[4],i32[2],u8} record, random ordered layout pair of 42; one "
+                                   "persistent hipGraph-captured launch",
+                       "bytes_per_step": total, "arrays": len(items), "threads": th, "work_units": info["work_units"],
+                       "workgroups": info["workgroups"], "tuned_classes": tuned},
+            "hbm_peak_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "extras": {"batched_ms_min": round(mn, 3),
+                       "naive_per_array_gbs": round(total / (naive_med * 1e-3) / 1e9, 1),
+                       "llama_copy_per_array_gbs": round(total / (lone_med * 1e-3) / 1e9, 1),
+                       "batched_vs_naive": round(naive_med / med, 2),
+                       "batched_vs_per_array_copy": round(lone_med / med, 2)},
+            "device": dev.name}
+
+
+def bench_serve(L, torch, args, dev):
+    """Poisson requests replayed against the server with three policies:
+    continuous batching, one naive kernel per request, one llama_copy per
+    request.  Arrival rate: rho times the batched throughput measured on a
+    calibration trace."""
+    import time as _t
+    budget = 64 * 10**9
+    warm, count = 200, args.requests
+    trace = W.poisson_trace(W.BASE_SEED + 5, 1000.0, warm + count)
+    S = {"particle": 28, "mixed": 49}
+    arena_bytes = 2 * budget + 4 * 10**9
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    arena.random_(0, 255)
+    cache, reqs, off, lap = {}, [], 0, 0
+    for r in trace:
+        n = max(1, int(r["payload"] // S[r["record"]]))
+        ms, md = _layout_maps(L, r["record"], n, r["src"], r["dst"], cache)
+        need = sum(ms.blob_sizes()) + sum(md.blob_sizes()) + 256 * (ms.blob_count + md.blob_count)
+        if off + need > arena_bytes:
+            off, lap = 0, lap + 1
+        blobs, o = [], off
+        for s in ms.blob_sizes() + md.blob_sizes():
+            blobs.append((arena.data_ptr() + o, s))
+            o += (s + 255) // 256 * 256
+        sb, db = blobs[:ms.blob_count], blobs[ms.blob_count:]
+        reqs.append({"ms": ms, "md": md, "sb": sb, "db": db, "lo": off, "hi": o, "lap": lap,
+                     "bytes": sum(ms.blob_sizes()) + sum(md.blob_sizes())})
+        off = o
+    torch.cuda.synchronize()
+    log(f"serve: {len(reqs)} requests, {sum(r['bytes'] for r in reqs) / 1e9:.0f} GB in total")
+    _tune_classes(L, torch, {(r["record"], r["src"], r["dst"]) for r in trace}, torch.cuda.current_stream())
+
+    def run(policy, rate):
+        srv = L.Server(budget, policy=policy)
+        tickets, done = [], {}
+        t0 = _t.perf_counter()
+        base = trace[0]["t"]
+        # arena regions in allocation order: the ring reuses the oldest first;
+        # a region of the previous lap is retired when the new one overlaps
+        # it, anything older at once
+        users = collections.deque()
+        for k, r in enumerate(reqs):
+            due = t0 + (trace[k]["t"] - base) * (1000.0 / rate)
+            while _t.perf_counter() < due:
+                pass
+            while users and (users[0][3] < r["lap"] - 1 or (users[0][1] < r["hi"] and r["lo"] < users[0][2])):
+                j = users.popleft()[0]
+                if j not in done:
+                    done[j] = srv.wait(tickets[j])
+            tickets.append(srv.submit(r["ms"], r["sb"], r["md"], r["db"]))
+            users.append((k, r["lo"], r["hi"], r["lap"]))
+            if k == warm - 1:
+                t_meas = _t.perf_counter()
+        for j, t in enumerate(tickets):
+            if j not in done:
+                done[j] = srv.wait(t)
+        t_end = _t.perf_counter()
+        st = srv.stats()
+        srv.close()
+        lat = sorted(done[j][1] for j in range(warm, len(reqs)))
+        measured = sum(reqs[j]["bytes"] for j in range(warm, len(reqs)))
+        return {"gbs": round(measured / (t_end - t_meas) / 1e9, 1),
+                "p50_ms": round(1e3 * lat[len(lat) // 2], 3),
+                "p99_ms": round(1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))], 3),
+                "launches": st["launches"], "mean_batch": round(st["mean_batch"], 2),
+                "max_inflight_gb": round(st["max_inflight_bytes"] / 1e9, 2),
+                "failed": st["failed"]}
+
+    # calibration: everything submitted at once measures the batched throughput
+    calib = run(0, 1e9)
+    total_bytes = sum(r["bytes"] for r in reqs[warm:])
+    mean_bytes = total_bytes / count
+    rate = args.rho * calib["gbs"] * 1e9 / mean_bytes
+    log(f"serve: batched capacity {calib['gbs']} GB/s; offered load rho={args.rho} -> {rate:.0f} requests/s")
+    out = {name: run(pol, rate) for name, pol in (("batched", 0), ("naive", 1), ("per_request", 2))}
+    return {"metric": METRIC, "value": out["batched"]["gbs"], "unit": "GB/s", "n_gpus": 1, "steps": count,
+            "warmup": warm, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "serving: Poisson arrivals, payload log-uniform 64 KB..1 GB, particle or mixed "
+                                   "record, random ordered layout pair of 42, HBM admission budget 64 GB",
+                       "rho": args.rho, "rate_per_s": round(rate, 1), "requests": count, "warmup_requests": warm,
+                       "mean_request_bytes": round(mean_bytes)},
+            "p50_ms": out["batched"]["p50_ms"], "p99_ms": out["batched"]["p99_ms"],
+            "extras": {"capacity_gbs": calib["gbs"], **{k: v for k, v in out.items()}},
+            "device": dev.name}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="particle", choices=["particle", "lbm"])
+    ap.add_argument("--workload", default="particle", choices=["particle", "lbm", "batch", "serve"])
+    ap.add_argument("--requests", type=int, default=2000, help="serve: measured requests (after 200 warm-up)")
+    ap.add_argument("--rho", type=float, default=0.8, help="serve: offered load as a fraction of batched GB/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-naive", action="store_true")
     ap.add_argument("--details", default=None, help="write per-pair results to this JSON file")
@@ -212,6 +385,13 @@ def main():
         sys.exit(1)
     dev = torch.cuda.get_device_properties(0)
     stream = torch.cuda.current_stream()
+
+    if args.workload == "batch":
+        print(json.dumps(bench_batch(L, torch, args, dev, stream)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(L, torch, args, dev)), flush=True)
+        return
 
     if args.workload == "particle":
         n = 1 << 26

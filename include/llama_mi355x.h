@@ -212,6 +212,38 @@ int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, con
                llama_plan_info* info);
 
 /* ------------------------------------------------------------------------ */
+/* Autotuning                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Measures kernel parameters for this copy on its own blobs: TILE with tile
+ * sizes 16 .. 4096 records and 64/128/256 threads, and STREAM where the pair
+ * has long runs.  Each candidate first runs on a destination filled with a
+ * pattern and must produce the same bytes (compared by a 64-bit hash of the
+ * destination blobs) as the default plan; then it is timed (best of `reps`
+ * launches, 0: 3).  The fastest goes to the process-wide tuning cache, keyed
+ * by (leaf sizes and alignments, source kind and lanes, destination kind and
+ * lanes, floor(log2(record count))), and later copies of that class made with
+ * default options use it (the entry of the nearest size bucket when the
+ * exact one is missing).  Synchronous; the destination blobs end up holding
+ * the copy.  `best` and `best_gbs` (read+write GB/s) may be NULL. */
+int llama_autotune(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                   const llama_blob* dst_blobs, void* stream, uint32_t reps, llama_copy_options* best,
+                   double* best_gbs);
+
+/* The cached parameters for this pair's class; *found is 0 when there are none. */
+int llama_tune_lookup(const llama_mapping_desc* src, const llama_mapping_desc* dst, llama_copy_options* options,
+                      int* found);
+
+int llama_tune_clear(void);
+
+/* The tuning cache as a text file (one line per class). */
+int llama_tune_save(const char* path);
+
+/* Adds the classes of a file written by llama_tune_save; *entries (may be
+ * NULL) receives how many lines were read. */
+int llama_tune_load(const char* path, uint32_t* entries);
+
+/* ------------------------------------------------------------------------ */
 /* Batches: many independent copies in one persistent launch                */
 /* ------------------------------------------------------------------------ */
 
@@ -222,6 +254,119 @@ typedef struct {
     const llama_mapping_desc* dst;
     const llama_blob* dst_blobs;
 } llama_copy_item;
+
+/* A prepared batch: the items' plans in one device work table, run by one
+ * persistent kernel whose workgroups take tiles (and 4 KiB chunks of long
+ * runs) from an atomic counter.  The launch is captured into a hipGraph on
+ * the first llama_batch_launch on a non-null stream and replayed afterwards.
+ * The result equals n separate llama_copy calls.
+ *  - Validation: every item as in llama_copy; no destination range may
+ *    overlap another destination range or any source range of the batch
+ *    (items run in no fixed order).
+ *  - Ownership: the batch copies the descriptors and blob addresses; the
+ *    blobs stay the caller's and must stay valid while launches are pending.
+ *  - Options (may be NULL): tile_records (a fixed tile size for every TILE
+ *    item, 0: each item's own), threads (per workgroup, for every item),
+ *    wg_per_cu (resident workgroups per compute unit); path and flags must be 0.
+ *  - Items whose record does not fit the tiled kernel are refused with
+ *    LLAMA_E_UNSUPPORTED.
+ *  - A batch belongs to the device that was current at creation.
+ *  - Launches of one batch must not overlap in time: they share the work
+ *    counter (launch them on one stream). */
+typedef struct llama_batch llama_batch;
+
+typedef struct {
+    uint64_t items;        /* non-empty items */
+    uint64_t tile_items;   /* items copied by the tiled kernel */
+    uint64_t stream_items; /* items copied as long runs */
+    uint64_t work_units;   /* tiles plus run chunks */
+    uint64_t read_bytes;   /* source blob bytes of all items */
+    uint64_t write_bytes;  /* destination blob bytes of all items */
+    uint32_t threads;      /* threads per workgroup */
+    uint32_t wg_per_cu;    /* resident workgroups per compute unit */
+    uint32_t workgroups;   /* persistent grid size */
+    uint32_t lds_bytes;    /* LDS per workgroup */
+} llama_batch_info;
+
+int llama_batch_create(size_t n, const llama_copy_item* items, const llama_copy_options* options,
+                       llama_batch** batch);
+
+/* Enqueues one run of the whole batch on `stream`. */
+int llama_batch_launch(llama_batch* batch, void* stream);
+
+int llama_batch_get_info(const llama_batch* batch, llama_batch_info* info);
+
+/* Waits for the device to finish pending work, then frees the batch. */
+int llama_batch_destroy(llama_batch* batch);
+
+/* One-shot batch: create, launch on `stream`, and release the batch once the
+ * launch has finished.  Asynchronous like llama_copy. */
+int llama_copy_batch(size_t n, const llama_copy_item* items, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching within an HBM budget                        */
+/* ------------------------------------------------------------------------ */
+
+/* How a server runs admitted requests. */
+typedef enum {
+    LLAMA_SERVE_BATCHED = 0,    /* every admitted group is one launch of the persistent batch kernel */
+    LLAMA_SERVE_NAIVE = 1,      /* one element-wise (naive) kernel per request, one stream */
+    LLAMA_SERVE_PER_REQUEST = 2 /* one llama_copy per request, streams round robin */
+} llama_serve_policy;
+
+typedef struct {
+    uint64_t budget_bytes;   /* admission budget: source plus destination blob bytes in flight (> 0) */
+    uint32_t streams;        /* HIP streams whose launches overlap (0: 2; NAIVE: 1); at most 16 */
+    uint32_t max_batch;      /* requests per launch at most (0: 1024) */
+    uint32_t queue_capacity; /* queued requests at most before submit says LLAMA_E_BUSY (0: 2^20) */
+    uint32_t threads;        /* threads per workgroup (0: 256) */
+    uint32_t policy;         /* llama_serve_policy */
+    uint32_t reserved;
+} llama_server_config;
+
+typedef struct {
+    uint64_t submitted, completed, failed, queued;
+    uint64_t launches;           /* kernel launches (batches) so far */
+    uint64_t bytes_done;         /* source plus destination bytes of completed requests */
+    uint64_t max_inflight_bytes; /* largest admitted total seen */
+    double mean_batch;           /* requests per launch */
+    double p50_latency, p99_latency, max_latency; /* seconds, submit to observed completion */
+    double window;               /* seconds from the first submit to the last completion */
+} llama_server_stats;
+
+/* A server owns an engine thread, `streams` HIP streams on the current
+ * device, and one reusable work table per stream; it never allocates blobs.
+ *
+ * Requests keep their blobs on the device (the caller's, valid until the
+ * request completes).  The engine admits queued requests in arrival order
+ * while the bytes in flight stay within budget_bytes and no destination range
+ * meets a range of a request in flight; each admitted group is one launch on
+ * the next free stream.  Requests that arrive while launches run join the
+ * next launch as soon as a stream and budget free up.  Each result equals a
+ * lone llama_copy of the request. */
+typedef struct llama_server llama_server;
+
+int llama_server_create(const llama_server_config* config, llama_server** server);
+
+/* Validates the request (errors return here and concern this request only:
+ * LLAMA_E_NO_BUDGET when it alone exceeds the budget, LLAMA_E_BUSY when the
+ * queue is full), queues it and returns its ticket. */
+int llama_server_submit(llama_server* server, const llama_copy_item* item, uint64_t* ticket);
+
+/* *done = 1 and *status / *latency_s filled in when the request has finished,
+ * else *done = 0.  status / latency_s may be NULL. */
+int llama_server_poll(llama_server* server, uint64_t ticket, int* done, int* status, double* latency_s);
+
+/* Blocks until the request has finished. */
+int llama_server_wait(llama_server* server, uint64_t ticket, int* status, double* latency_s);
+
+int llama_server_get_stats(llama_server* server, llama_server_stats* stats);
+
+/* Clears the counters and latencies (queued and running requests continue). */
+int llama_server_reset_stats(llama_server* server);
+
+/* Finishes every queued and running request, then frees the server. */
+int llama_server_destroy(llama_server* server);
 
 #ifdef __cplusplus
 }

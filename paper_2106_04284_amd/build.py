@@ -25,7 +25,7 @@ CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-I" + INCLUDE, "
              "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__"]
 
 HIP_SOURCES = ["kernels.hip"]
-CXX_SOURCES = ["core.cpp", "capi.cpp"]
+CXX_SOURCES = ["core.cpp", "capi.cpp", "batch.cpp", "tune.cpp", "serve.cpp"]
 
 
 def _run(cmd):
@@ -48,7 +48,7 @@ def build(verbose: bool = False) -> str:
                 print(r.stdout + r.stderr)
     objs = [os.path.join(BUILD, s + ".o") for s in HIP_SOURCES + CXX_SOURCES]
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
+    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -1,0 +1,290 @@
+// Batches: many independent copies in one persistent launch, replayed from a
+// hipGraph.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "batch.hpp"
+
+namespace llama {
+
+namespace {
+
+void check_hip(hipError_t e, const char* what)
+{
+    if (e != hipSuccess)
+        fail(LLAMA_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct Range {
+    uint64_t lo, hi; // [lo, hi)
+    size_t item;
+};
+
+// Destination ranges must be disjoint from every other destination range and
+// from every source range of any item (a batch runs its items in no fixed
+// order, so a read of one item could meet a write of another).
+void check_batch_overlap(const std::vector<Request>& rqs)
+{
+    std::vector<Range> dst, src;
+    for (size_t k = 0; k < rqs.size(); k++) {
+        for (size_t b = 0; b < rqs[k].dst_ptr.size(); b++)
+            if (rqs[k].dst.blob_size[b])
+                dst.push_back({rqs[k].dst_ptr[b], rqs[k].dst_ptr[b] + rqs[k].dst.blob_size[b], k});
+        for (size_t b = 0; b < rqs[k].src_ptr.size(); b++)
+            if (rqs[k].src.blob_size[b])
+                src.push_back({rqs[k].src_ptr[b], rqs[k].src_ptr[b] + rqs[k].src.blob_size[b], k});
+    }
+    std::sort(dst.begin(), dst.end(), [](const Range& a, const Range& b) { return a.lo < b.lo; });
+    for (size_t k = 1; k < dst.size(); k++)
+        if (dst[k].lo < dst[k - 1].hi)
+            fail(LLAMA_E_OVERLAP, "batch items " + std::to_string(dst[k - 1].item) + " and " +
+                                      std::to_string(dst[k].item) + " write overlapping ranges");
+    for (const Range& s : src) {
+        // the last destination range starting before s.hi
+        auto it = std::upper_bound(dst.begin(), dst.end(), s.hi - 1, [](uint64_t v, const Range& r) { return v < r.lo; });
+        if (it != dst.begin()) {
+            --it;
+            if (it->hi > s.lo)
+                fail(LLAMA_E_OVERLAP, "batch item " + std::to_string(it->item) + " writes a range that item " +
+                                          std::to_string(s.item) + " reads");
+        }
+    }
+}
+
+std::mutex g_retired_mutex;
+std::vector<std::pair<Batch*, hipEvent_t>> g_retired; // one-shot batches waiting for their launch to end
+
+void reap_retired()
+{
+    std::lock_guard<std::mutex> lock(g_retired_mutex);
+    for (size_t k = 0; k < g_retired.size();) {
+        if (hipEventQuery(g_retired[k].second) == hipSuccess) {
+            (void)hipEventDestroy(g_retired[k].second);
+            destroy_batch(g_retired[k].first);
+            g_retired[k] = g_retired.back();
+            g_retired.pop_back();
+        } else {
+            k++;
+        }
+    }
+    (void)hipGetLastError();
+}
+
+} // namespace
+
+void BatchTable::add(const Request& rq, uint32_t threads, uint32_t tile_records)
+{
+    llama_copy_options o{LLAMA_PATH_AUTO, tile_records, threads, 0, 0};
+    Plan p = make_plan(rq, &o);
+    read_bytes += p.read_bytes;
+    write_bytes += p.write_bytes;
+    if (p.path == LLAMA_PATH_EMPTY)
+        return;
+    BatchItem it{};
+    if (p.path == LLAMA_PATH_TILE) {
+        it.kind = kItemTile;
+        it.count = p.tile.h.num_entries;
+        it.first = entries.size();
+        it.h = p.tile.h;
+        entries.insert(entries.end(), p.tile.e, p.tile.e + p.tile.h.num_entries);
+        lds_bytes = std::max(lds_bytes, p.tile.h.lds_bytes);
+        tile_items++;
+    } else if (p.path == LLAMA_PATH_STREAM) {
+        it.kind = kItemStream;
+        it.count = p.stream.num_runs;
+        it.first = runs.size();
+        it.h.num_tiles = p.stream.num_chunks;
+        runs.insert(runs.end(), p.stream.r, p.stream.r + p.stream.num_runs);
+        stream_items++;
+    } else {
+        fail(LLAMA_E_UNSUPPORTED, "its record does not fit the tiled kernel; copy it with llama_copy");
+    }
+    unit_begin.push_back(units);
+    units += it.h.num_tiles;
+    items.push_back(it);
+}
+
+namespace {
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+struct TableLayout {
+    size_t counters, begin, items, entries, runs, total;
+};
+TableLayout table_layout(const BatchTable& t)
+{
+    TableLayout l;
+    l.counters = 0;
+    l.begin = align256(2 * sizeof(unsigned long long));
+    l.items = align256(l.begin + (t.unit_begin.size() + 1) * sizeof(uint64_t));
+    l.entries = align256(l.items + std::max<size_t>(t.items.size(), 1) * sizeof(BatchItem));
+    l.runs = align256(l.entries + std::max<size_t>(t.entries.size(), 1) * sizeof(TileEntry));
+    l.total = align256(l.runs + std::max<size_t>(t.runs.size(), 1) * sizeof(StreamRun));
+    return l;
+}
+} // namespace
+
+size_t BatchTable::bytes() const
+{
+    return table_layout(*this).total;
+}
+
+void BatchTable::serialise(uint8_t* host, uint64_t device, BatchArgs& args) const
+{
+    const TableLayout l = table_layout(*this);
+    std::memset(host, 0, l.total);
+    std::memcpy(host + l.begin, unit_begin.data(), unit_begin.size() * sizeof(uint64_t));
+    std::memcpy(host + l.begin + unit_begin.size() * sizeof(uint64_t), &units, sizeof(uint64_t));
+    if (!items.empty())
+        std::memcpy(host + l.items, items.data(), items.size() * sizeof(BatchItem));
+    if (!entries.empty())
+        std::memcpy(host + l.entries, entries.data(), entries.size() * sizeof(TileEntry));
+    if (!runs.empty())
+        std::memcpy(host + l.runs, runs.data(), runs.size() * sizeof(StreamRun));
+    args.counters = (unsigned long long*)(device + l.counters);
+    args.unit_begin = (const uint64_t*)(device + l.begin);
+    args.items = (const BatchItem*)(device + l.items);
+    args.entries = (const TileEntry*)(device + l.entries);
+    args.runs = (const StreamRun*)(device + l.runs);
+    args.total_units = units;
+    args.num_items = uint32_t(items.size());
+    args.pad = 0;
+}
+
+uint32_t batch_wg_per_cu(uint32_t lds_bytes, uint32_t threads)
+{
+    const uint32_t waves = threads / 64;
+    uint32_t fit = std::min<uint32_t>(lds_bytes ? (kHardLdsBytes - 64) / lds_bytes : 16, kMaxWavesPerCu / waves);
+    return std::max<uint32_t>(1, std::min<uint32_t>(fit, 8));
+}
+
+Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_options* opt)
+{
+    reap_retired();
+    if (n > 0 && !items)
+        fail(LLAMA_E_INVALID_ARG, "batch item array is NULL");
+    if (opt && (opt->path != LLAMA_PATH_AUTO || opt->flags != 0))
+        fail(LLAMA_E_INVALID_ARG, "batch options take tile_records, threads and wg_per_cu only");
+    const uint32_t threads = (opt && opt->threads) ? opt->threads : kDefaultThreads;
+    if (threads % 64 != 0 || threads == 0 || threads > 1024)
+        fail(LLAMA_E_INVALID_ARG, "threads must be a multiple of 64 in 64..1024");
+    if (opt && opt->wg_per_cu > 16)
+        fail(LLAMA_E_INVALID_ARG, "wg_per_cu must be 0..16");
+    const uint32_t T = opt ? opt->tile_records : 0;
+    if (T && (T < 16 || T > 4096 || (T & (T - 1))))
+        fail(LLAMA_E_INVALID_ARG, "tile_records must be a power of two in 16..4096");
+
+    std::vector<Request> rqs;
+    rqs.reserve(n);
+    for (size_t k = 0; k < n; k++) {
+        try {
+            rqs.push_back(make_request(items[k].src, items[k].src_blobs, items[k].dst, items[k].dst_blobs, true));
+        } catch (const Error& e) {
+            fail(e.status, "batch item " + std::to_string(k) + ": " + e.message);
+        }
+    }
+    check_batch_overlap(rqs);
+
+    BatchTable t;
+    for (size_t k = 0; k < n; k++) {
+        try {
+            t.add(rqs[k], threads, T);
+        } catch (const Error& e) {
+            fail(e.status, "batch item " + std::to_string(k) + ": " + e.message);
+        }
+    }
+
+    std::unique_ptr<Batch> b(new Batch());
+    b->threads = threads;
+    b->total_units = t.units;
+    b->lds_bytes = t.lds_bytes;
+    b->items = t.items.size();
+    b->tile_items = t.tile_items;
+    b->stream_items = t.stream_items;
+    b->read_bytes = t.read_bytes;
+    b->write_bytes = t.write_bytes;
+    check_hip(hipGetDevice(&b->device), "hipGetDevice");
+    b->wg_per_cu = (opt && opt->wg_per_cu) ? opt->wg_per_cu : batch_wg_per_cu(t.lds_bytes, threads);
+    b->grid = uint32_t(std::min<uint64_t>(std::max<uint64_t>(t.units, 1), uint64_t(device_cu_count()) * b->wg_per_cu));
+
+    const size_t total = t.bytes();
+    std::vector<uint8_t> host(total);
+    check_hip(hipMalloc(&b->table, total), "hipMalloc(batch table)");
+    b->table_bytes = total;
+    t.serialise(host.data(), uint64_t(uintptr_t(b->table)), b->args);
+    hipError_t e = hipMemcpy(b->table, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(b->table);
+        check_hip(e, "hipMemcpy(batch table)");
+    }
+    return b.release();
+}
+
+void launch_batch(Batch* b, void* stream_ptr)
+{
+    hipStream_t stream = (hipStream_t)stream_ptr;
+    int dev = 0;
+    check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != b->device)
+        fail(LLAMA_E_INVALID_ARG, "batch was created on device " + std::to_string(b->device) +
+                                      " and launched on device " + std::to_string(dev));
+    if (b->total_units == 0)
+        return;
+    if (!stream) { // the null stream cannot be captured: launch directly
+        launch_batch_kernel(*b, stream);
+        return;
+    }
+    if (!b->graph_exec) {
+        hipGraph_t graph = nullptr;
+        check_hip(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        try {
+            launch_batch_kernel(*b, stream);
+        } catch (...) {
+            hipStreamEndCapture(stream, &graph);
+            if (graph)
+                hipGraphDestroy(graph);
+            throw;
+        }
+        check_hip(hipStreamEndCapture(stream, &graph), "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        check_hip(e, "hipGraphInstantiate");
+        b->graph_exec = exec;
+    }
+    check_hip(hipGraphLaunch((hipGraphExec_t)b->graph_exec, stream), "hipGraphLaunch");
+}
+
+void destroy_batch(Batch* b)
+{
+    if (!b)
+        return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    if (b->graph_exec)
+        (void)hipGraphExecDestroy((hipGraphExec_t)b->graph_exec);
+    if (b->table)
+        (void)hipFree(b->table);
+    (void)hipSetDevice(prev);
+    (void)hipGetLastError();
+    delete b;
+}
+
+void retire_batch(Batch* b, void* stream_ptr)
+{
+    hipEvent_t ev;
+    check_hip(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+    hipError_t e = hipEventRecord(ev, (hipStream_t)stream_ptr);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(ev);
+        check_hip(e, "hipEventRecord");
+    }
+    std::lock_guard<std::mutex> lock(g_retired_mutex);
+    g_retired.push_back({b, ev});
+}
+
+} // namespace llama

@@ -1,9 +1,12 @@
 // extern "C" entry points declared in include/llama_mi355x.h.
 #include <cstring>
+#include <memory>
 #include <exception>
 #include <string>
 
+#include "batch.hpp"
 #include "core.hpp"
+#include "serve.hpp"
 
 using namespace llama;
 
@@ -157,7 +160,7 @@ int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, con
         std::memset(info, 0, sizeof(*info));
         info->path = p.path;
         info->threads = p.threads;
-        info->tile_records = p.path == LLAMA_PATH_TILE ? (1u << p.tile.log2_tile) : 0;
+        info->tile_records = p.path == LLAMA_PATH_TILE ? (1u << p.tile.h.log2_tile) : 0;
         info->lds_bytes = p.lds_bytes;
         info->workgroups = p.workgroups;
         info->runs = p.path == LLAMA_PATH_STREAM ? p.stream.num_runs : 0;
@@ -189,6 +192,207 @@ int llama_copy_naive(const llama_mapping_desc* src, const llama_blob* src_blobs,
 {
     llama_copy_options o{LLAMA_PATH_NAIVE, 0, 0, 0, 0};
     return llama_copy_ex(src, src_blobs, dst, dst_blobs, &o, stream);
+}
+
+int llama_autotune(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                   const llama_blob* dst_blobs, void* stream, uint32_t reps, llama_copy_options* best,
+                   double* best_gbs)
+{
+    return guarded([&] {
+        if (reps > 1000)
+            fail(LLAMA_E_INVALID_ARG, "reps must be at most 1000");
+        Request rq = make_request(src, src_blobs, dst, dst_blobs, true);
+        llama_copy_options o;
+        double gbs = 0;
+        autotune(rq, stream, reps ? int(reps) : 3, o, gbs);
+        if (best)
+            *best = o;
+        if (best_gbs)
+            *best_gbs = gbs;
+    });
+}
+
+int llama_tune_lookup(const llama_mapping_desc* src, const llama_mapping_desc* dst, llama_copy_options* options,
+                      int* found)
+{
+    return guarded([&] {
+        need(options, "options");
+        need(found, "found");
+        Request rq = make_request(src, nullptr, dst, nullptr, false);
+        llama_copy_options o{0, 0, 0, 0, 0};
+        *found = tune_lookup(tune_key(rq), o) ? 1 : 0;
+        *options = o;
+    });
+}
+
+int llama_tune_clear(void)
+{
+    return guarded([&] { tune_clear(); });
+}
+
+int llama_tune_save(const char* path)
+{
+    return guarded([&] {
+        need(path, "path");
+        tune_save(path);
+    });
+}
+
+int llama_tune_load(const char* path, uint32_t* entries)
+{
+    return guarded([&] {
+        need(path, "path");
+        uint32_t n = tune_load(path);
+        if (entries)
+            *entries = n;
+    });
+}
+
+struct llama_batch {
+    llama::Batch* b;
+};
+
+int llama_batch_create(size_t n, const llama_copy_item* items, const llama_copy_options* options,
+                       llama_batch** batch)
+{
+    return guarded([&] {
+        need(batch, "batch");
+        *batch = nullptr;
+        std::unique_ptr<llama_batch> h(new llama_batch{create_batch(n, items, options)});
+        *batch = h.release();
+    });
+}
+
+int llama_batch_launch(llama_batch* batch, void* stream)
+{
+    return guarded([&] {
+        need(batch, "batch");
+        launch_batch(batch->b, stream);
+    });
+}
+
+int llama_batch_get_info(const llama_batch* batch, llama_batch_info* info)
+{
+    return guarded([&] {
+        need(batch, "batch");
+        need(info, "info");
+        const Batch& b = *batch->b;
+        info->items = b.items;
+        info->tile_items = b.tile_items;
+        info->stream_items = b.stream_items;
+        info->work_units = b.total_units;
+        info->read_bytes = b.read_bytes;
+        info->write_bytes = b.write_bytes;
+        info->threads = b.threads;
+        info->wg_per_cu = b.wg_per_cu;
+        info->workgroups = b.grid;
+        info->lds_bytes = b.lds_bytes;
+    });
+}
+
+int llama_batch_destroy(llama_batch* batch)
+{
+    return guarded([&] {
+        if (!batch)
+            return;
+        destroy_batch(batch->b);
+        delete batch;
+    });
+}
+
+int llama_copy_batch(size_t n, const llama_copy_item* items, void* stream)
+{
+    return guarded([&] {
+        Batch* b = create_batch(n, items, nullptr);
+        try {
+            if (b->total_units)
+                launch_batch_kernel(*b, stream);
+            retire_batch(b, stream);
+        } catch (...) {
+            destroy_batch(b);
+            throw;
+        }
+    });
+}
+
+struct llama_server {
+    llama::Server* s;
+};
+
+int llama_server_create(const llama_server_config* config, llama_server** server)
+{
+    return guarded([&] {
+        need(server, "server");
+        *server = nullptr;
+        if (config && config->reserved != 0)
+            fail(LLAMA_E_INVALID_ARG, "llama_server_config.reserved must be 0");
+        *server = new llama_server{create_server(config)};
+    });
+}
+
+int llama_server_submit(llama_server* server, const llama_copy_item* item, uint64_t* ticket)
+{
+    return guarded([&] {
+        need(server, "server");
+        need(ticket, "ticket");
+        *ticket = server_submit(server->s, item);
+    });
+}
+
+int llama_server_poll(llama_server* server, uint64_t ticket, int* done, int* status, double* latency_s)
+{
+    return guarded([&] {
+        need(server, "server");
+        need(done, "done");
+        int st = 0;
+        double lat = 0;
+        *done = server_poll(server->s, ticket, false, st, lat) ? 1 : 0;
+        if (*done && status)
+            *status = st;
+        if (*done && latency_s)
+            *latency_s = lat;
+    });
+}
+
+int llama_server_wait(llama_server* server, uint64_t ticket, int* status, double* latency_s)
+{
+    return guarded([&] {
+        need(server, "server");
+        int st = 0;
+        double lat = 0;
+        server_poll(server->s, ticket, true, st, lat);
+        if (status)
+            *status = st;
+        if (latency_s)
+            *latency_s = lat;
+    });
+}
+
+int llama_server_get_stats(llama_server* server, llama_server_stats* stats)
+{
+    return guarded([&] {
+        need(server, "server");
+        need(stats, "stats");
+        server_stats(server->s, *stats);
+    });
+}
+
+int llama_server_reset_stats(llama_server* server)
+{
+    return guarded([&] {
+        need(server, "server");
+        server_reset_stats(server->s);
+    });
+}
+
+int llama_server_destroy(llama_server* server)
+{
+    return guarded([&] {
+        if (!server)
+            return;
+        destroy_server(server->s);
+        delete server;
+    });
 }
 
 } // extern "C"

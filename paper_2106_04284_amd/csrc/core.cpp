@@ -419,8 +419,9 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
     const size_t F = r.leaves.size();
     if (F + rq.dst.gaps.size() > size_t(kTileMaxEntries))
         return false;
-    TileArgs& a = p.tile;
-    std::memset(&a, 0, sizeof(a));
+    TileArgs& ta = p.tile;
+    std::memset(&ta, 0, sizeof(ta));
+    TileHeader& a = ta.h;
     std::vector<uint32_t> src_lds, dst_lds;
     uint32_t sb = tile_side(rq.src, r, T, a.src, src_lds);
     uint32_t db = tile_side(rq.dst, r, T, a.dst, dst_lds);
@@ -444,7 +445,7 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
     const uint64_t src_rm_bits = a.src.mode == kRecordMajor ? rq.src.block : 0;
     const uint64_t dst_rm_bits = a.dst.mode == kRecordMajor ? rq.dst.block : 0;
     for (size_t f = 0; f < F; f++) {
-        TileEntry& e = a.e[f];
+        TileEntry& e = ta.e[f];
         e.src_addr = rq.src_ptr[rq.src.blob[f]] + rq.src.base[f];
         e.dst_addr = rq.dst_ptr[rq.dst.blob[f]] + rq.dst.base[f];
         e.size = r.leaves[f].size;
@@ -458,7 +459,7 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
     }
     size_t k = F;
     for (const auto& g : rq.dst.gaps) { // only record-major (aligned AoS) destinations have gaps
-        TileEntry& e = a.e[k++];
+        TileEntry& e = ta.e[k++];
         e.src_addr = 0;
         e.dst_addr = rq.dst_ptr[0] + g.first;
         e.size = uint32_t(g.second);
@@ -472,7 +473,7 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
     const uint32_t nwaves = p.threads / 64;
     uint32_t first_wave = 0, first_thread = 0;
     for (size_t f = 0; f < F; f++) {
-        TileEntry& e = a.e[f];
+        TileEntry& e = ta.e[f];
         e.move |= (first_wave << 4) | (first_thread << 8);
         uint64_t granules = (uint64_t(T) * e.size + 30) / 16;
         first_wave = uint32_t((first_wave + (granules + 63) / 64) % nwaves);
@@ -546,7 +547,36 @@ void fill_naive(const Request& rq, Plan& p)
 
 } // namespace
 
+namespace {
+Plan make_plan_raw(const Request& rq, const llama_copy_options* opt);
+}
+
+// The plan for `opt`; when the caller leaves the path and tile size to the
+// library, a tuning-cache entry for this class of copies supplies them (the
+// caller's threads and wg_per_cu still win).
 Plan make_plan(const Request& rq, const llama_copy_options* opt)
+{
+    if (!opt || (opt->path == LLAMA_PATH_AUTO && opt->tile_records == 0)) {
+        llama_copy_options tuned;
+        if (tune_lookup(tune_key(rq), tuned)) {
+            if (opt && opt->threads)
+                tuned.threads = opt->threads;
+            if (opt && opt->wg_per_cu)
+                tuned.wg_per_cu = opt->wg_per_cu;
+            tuned.flags = opt ? opt->flags : 0;
+            try {
+                return make_plan_raw(rq, &tuned);
+            } catch (const Error&) {
+                // the cached parameters do not apply here; plan from scratch
+            }
+        }
+    }
+    return make_plan_raw(rq, opt);
+}
+
+namespace {
+
+Plan make_plan_raw(const Request& rq, const llama_copy_options* opt)
 {
     Plan p;
     p.read_bytes = total_bytes(rq.src.blob_size);
@@ -598,5 +628,7 @@ Plan make_plan(const Request& rq, const llama_copy_options* opt)
     fill_naive(rq, p);
     return p;
 }
+
+} // namespace
 
 } // namespace llama

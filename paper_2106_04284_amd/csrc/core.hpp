@@ -99,6 +99,26 @@ Plan make_plan(const Request& rq, const llama_copy_options* opt);
 // kernels.hip
 void launch(const Plan& p, void* stream);
 uint32_t device_cu_count(); // compute units of the current device (256 when none is visible)
+// adds a 64-bit hash of bytes [p, p + len) to *acc (device memory), on `stream`
+void launch_hash(const void* p, uint64_t len, unsigned long long* acc, void* stream);
+
+// The tuning cache (tune.cpp): kernel parameters measured fastest for a class
+// of copies (same leaves, same source and destination kind and lanes, same
+// power-of-two size bucket).
+struct TuneKey {
+    uint64_t leaves;   // hash of the flattened leaf sizes and alignments
+    uint32_t src_kind, dst_kind;
+    uint64_t src_lanes, dst_lanes;
+    uint32_t bucket;   // floor(log2(records))
+    bool operator<(const TuneKey& o) const;
+};
+TuneKey tune_key(const Request& rq);
+bool tune_lookup(const TuneKey& k, llama_copy_options& out);
+void autotune(const Request& rq, void* stream, int reps, llama_copy_options& best, double& best_gbs);
+void tune_clear();
+void tune_save(const char* path);
+uint32_t tune_load(const char* path);
+uint32_t tune_size();
 
 // default kernel parameters
 constexpr uint32_t kDefaultThreads = 256;      // threads per workgroup

@@ -48,7 +48,7 @@ struct TileEntry {
                        // leaf's destination span; bit 31: gap (write zeros)
 };
 
-struct TileArgs {
+struct TileHeader {
     uint64_t n;         // records with values
     uint64_t npad;      // records the destination spans (>= n)
     uint64_t num_tiles; // ceil(npad / T)
@@ -57,6 +57,10 @@ struct TileArgs {
     uint32_t num_entries; // leaves, then gaps
     uint32_t lds_bytes;
     TileSide src, dst;
+};
+
+struct TileArgs {
+    TileHeader h;
     TileEntry e[kTileMaxEntries];
 };
 static_assert(sizeof(TileArgs) <= 4096, "kernel arguments are limited to 4 KiB");
@@ -112,5 +116,31 @@ struct NaiveArgs {
     NaiveEntry e[kNaiveMaxEntries];
 };
 static_assert(sizeof(NaiveArgs) <= 4096, "kernel arguments are limited to 4 KiB");
+
+// ---------------------------------------------------------------------------
+// BATCH: many copies in one persistent launch.  The work table lives in device
+// memory; work unit g (a tile of a TILE item, a 4 KiB chunk of a STREAM item)
+// belongs to the item j with unit_begin[j] <= g < unit_begin[j + 1].
+// ---------------------------------------------------------------------------
+
+enum : uint32_t { kItemTile = 0, kItemStream = 1 };
+
+struct BatchItem {
+    uint32_t kind;  // kItemTile / kItemStream
+    uint32_t count; // entries (TILE) or runs (STREAM)
+    uint64_t first; // index of the item's first entry or run
+    TileHeader h;   // TILE: the tile geometry; STREAM: h.num_tiles = chunks
+};
+
+struct BatchArgs {
+    const uint64_t* unit_begin; // num_items + 1 prefix sums of work units
+    const BatchItem* items;
+    const TileEntry* entries;
+    const StreamRun* runs;
+    unsigned long long* counters; // [0]: next work unit, [1]: workgroups finished
+    uint64_t total_units;
+    uint32_t num_items;
+    uint32_t pad;
+};
 
 } // namespace llama

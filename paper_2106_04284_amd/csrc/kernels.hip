@@ -14,7 +14,9 @@
 //                 located with run-time '/' and '%' and moved at its own width.
 #include <hip/hip_runtime.h>
 
+#include "batch.hpp"
 #include "core.hpp"
+#include "serve.hpp"
 
 namespace llama {
 
@@ -22,6 +24,7 @@ namespace {
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 #define GLOBAL __attribute__((address_space(1)))
+#define CONSTANT __attribute__((address_space(4))) // read-only for the whole kernel: uniform loads become scalar
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef u32x4 u32x4_a4 __attribute__((aligned(4))); // 16 bytes at a 4-byte-aligned address
@@ -32,6 +35,20 @@ __device__ __forceinline__ uint32_t wave_id()
 }
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Copies a read-only table record word by word (scalar loads for a uniform address).
+template <typename T>
+__device__ __forceinline__ T load_const(const CONSTANT T* p)
+{
+    static_assert(sizeof(T) % 4 == 0, "table records are whole words");
+    T v;
+    const CONSTANT uint32_t* src = (const CONSTANT uint32_t*)p;
+    uint32_t* dst = (uint32_t*)&v;
+#pragma unroll
+    for (uint32_t k = 0; k < sizeof(T) / 4; k++)
+        dst[k] = src[k];
+    return v;
+}
 
 // One 16-byte global load per active lane, written by the memory system
 // straight into LDS at m0 + 16 * lane (global_load_lds_dwordx4).  Issued as
@@ -125,67 +142,74 @@ __device__ __forceinline__ void move4(uint8_t* lds, uint32_t sp, uint32_t dp, co
     }
 }
 
-// One tile per workgroup: every wave issues its share of the source loads
-// straight into LDS, then all threads move the values to their destination
-// positions inside LDS, then all threads store the destination span(s).
-__global__ void __launch_bounds__(1024) tile_kernel(const TileArgs a)
+// One tile: every wave issues its share of the source loads straight into
+// LDS, then all threads move the values to their destination positions
+// inside LDS, then all threads store the destination span(s).  `ent(k)`
+// returns entry k (kernel arguments for one copy, the work table for a batch).
+template <typename Entries>
+__device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint64_t t, uint8_t* lds)
 {
-    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
     const uint32_t lane = tid & 63u, wave = wave_id(), nwaves = nthr >> 6;
     const uint32_t lds_base = uint32_t(uintptr_t((lds_void_t*)lds));
-    const uint32_t T = 1u << a.log2_tile;
-    for (uint64_t t = blockIdx.x; t < a.num_tiles; t += gridDim.x) {
-        const uint64_t i0 = t << a.log2_tile;
-        const uint32_t nv = i0 < a.n ? uint32_t(min<uint64_t>(T, a.n - i0)) : 0u; // records with values
-        const uint32_t nd = uint32_t(min<uint64_t>(T, a.npad - i0));              // records the destination spans
+    const uint32_t T = 1u << h.log2_tile;
+    const uint64_t i0 = t << h.log2_tile;
+    const uint32_t nv = i0 < h.n ? uint32_t(min<uint64_t>(T, h.n - i0)) : 0u; // records with values
+    const uint32_t nd = uint32_t(min<uint64_t>(T, h.npad - i0));              // records the destination spans
 
-        // ---- 1. source span(s) -> LDS
-        if (nv > 0) {
-            if (a.src.mode == kRecordMajor) {
-                const uint32_t len = uint32_t(((uint64_t(nv) + a.src.lanes - 1) >> a.src.log2_lanes) * a.src.block);
-                load_span(a.src.span_base + t * a.src.tile_bytes, len, a.src.lds_base, wave, nwaves, 0, lane,
-                          lds_base);
-            } else {
-                for (uint32_t f = 0; f < a.num_leaves; f++) {
-                    const TileEntry& e = a.e[f];
-                    load_span(field_span_start(e.src_addr, a.src, i0, e.size), nv * e.size, e.src_pos & ~15u, wave,
-                              nwaves, (e.move >> 4) & 15u, lane, lds_base);
-                }
-            }
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-
-        // ---- 2. every value from its source to its destination position;
-        //         destination padding becomes zero
-        for (uint32_t k = 0; k < a.num_entries; k++) {
-            const TileEntry& e = a.e[k];
-            const bool gap = (e.move >> 31) != 0;
-            for (uint32_t r0 = tid; r0 < nd; r0 += 4u * nthr) {
-                switch (e.move & 7u) {
-                case 4: move4<u32x4>(lds, e.src_pos, e.dst_pos, a.src, a.dst, e.size, r0, nthr, nv, nd, gap); break;
-                case 3: move4<uint64_t>(lds, e.src_pos, e.dst_pos, a.src, a.dst, e.size, r0, nthr, nv, nd, gap); break;
-                case 2: move4<uint32_t>(lds, e.src_pos, e.dst_pos, a.src, a.dst, e.size, r0, nthr, nv, nd, gap); break;
-                case 1: move4<uint16_t>(lds, e.src_pos, e.dst_pos, a.src, a.dst, e.size, r0, nthr, nv, nd, gap); break;
-                default: move4<uint8_t>(lds, e.src_pos, e.dst_pos, a.src, a.dst, e.size, r0, nthr, nv, nd, gap); break;
-                }
-            }
-        }
-        __syncthreads();
-
-        // ---- 3. LDS -> destination span(s)
-        if (a.dst.mode == kRecordMajor) {
-            const uint32_t len = uint32_t(((uint64_t(nd) + a.dst.lanes - 1) >> a.dst.log2_lanes) * a.dst.block);
-            store_span(a.dst.span_base + t * a.dst.tile_bytes, len, a.dst.lds_base, tid, nthr, 0, lds);
+    // ---- 1. source span(s) -> LDS
+    if (nv > 0) {
+        if (h.src.mode == kRecordMajor) {
+            const uint32_t len = uint32_t(((uint64_t(nv) + h.src.lanes - 1) >> h.src.log2_lanes) * h.src.block);
+            load_span(h.src.span_base + t * h.src.tile_bytes, len, h.src.lds_base, wave, nwaves, 0, lane, lds_base);
         } else {
-            for (uint32_t f = 0; f < a.num_leaves; f++) {
-                const TileEntry& e = a.e[f];
-                store_span(field_span_start(e.dst_addr, a.dst, i0, e.size), nd * e.size, e.dst_pos & ~15u, tid,
-                           nthr, (e.move >> 8) & 4095u, lds);
+            for (uint32_t f = 0; f < h.num_leaves; f++) {
+                const auto& e = ent(f);
+                load_span(field_span_start(e.src_addr, h.src, i0, e.size), nv * e.size, e.src_pos & ~15u, wave,
+                          nwaves, (e.move >> 4) & 15u, lane, lds_base);
             }
         }
-        if (t + gridDim.x < a.num_tiles)
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    // ---- 2. every value from its source to its destination position;
+    //         destination padding becomes zero
+    for (uint32_t k = 0; k < h.num_entries; k++) {
+        const auto& e = ent(k);
+        const bool gap = (e.move >> 31) != 0;
+        for (uint32_t r0 = tid; r0 < nd; r0 += 4u * nthr) {
+            switch (e.move & 7u) {
+            case 4: move4<u32x4>(lds, e.src_pos, e.dst_pos, h.src, h.dst, e.size, r0, nthr, nv, nd, gap); break;
+            case 3: move4<uint64_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, e.size, r0, nthr, nv, nd, gap); break;
+            case 2: move4<uint32_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, e.size, r0, nthr, nv, nd, gap); break;
+            case 1: move4<uint16_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, e.size, r0, nthr, nv, nd, gap); break;
+            default: move4<uint8_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, e.size, r0, nthr, nv, nd, gap); break;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- 3. LDS -> destination span(s)
+    if (h.dst.mode == kRecordMajor) {
+        const uint32_t len = uint32_t(((uint64_t(nd) + h.dst.lanes - 1) >> h.dst.log2_lanes) * h.dst.block);
+        store_span(h.dst.span_base + t * h.dst.tile_bytes, len, h.dst.lds_base, tid, nthr, 0, lds);
+    } else {
+        for (uint32_t f = 0; f < h.num_leaves; f++) {
+            const auto& e = ent(f);
+            store_span(field_span_start(e.dst_addr, h.dst, i0, e.size), nd * e.size, e.dst_pos & ~15u, tid, nthr,
+                       (e.move >> 8) & 4095u, lds);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(1024) tile_kernel(const TileArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    auto ent = [&](uint32_t k) -> const TileEntry& { return a.e[k]; };
+    for (uint64_t t = blockIdx.x; t < a.h.num_tiles; t += gridDim.x) {
+        tile_body(a.h, ent, t, lds);
+        if (t + gridDim.x < a.h.num_tiles)
             __syncthreads();
     }
 }
@@ -244,22 +268,82 @@ __device__ __forceinline__ void copy_run_chunk(uint64_t dst, uint64_t src, uint6
     }
 }
 
+// Work unit c of a run list: the run holding chunk c is the last run whose
+// first chunk is <= c.  `run(k)` returns run k.
+template <typename Runs>
+__device__ __forceinline__ void stream_unit(Runs run, uint32_t num_runs, uint64_t c)
+{
+    uint32_t lo = 0, hi = num_runs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (run(mid).first_chunk <= c)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const auto& r = run(lo);
+    const uint64_t off = (c - r.first_chunk) << kStreamChunkLog2;
+    const uint64_t len = min<uint64_t>(r.bytes - off, uint64_t(1) << kStreamChunkLog2);
+    copy_run_chunk(r.dst + off, r.src ? r.src + off : 0, len, threadIdx.x, blockDim.x);
+}
+
 __global__ void __launch_bounds__(1024) stream_kernel(const StreamArgs a)
 {
-    for (uint64_t c = blockIdx.x; c < a.num_chunks; c += gridDim.x) {
-        // run holding chunk c: the last run whose first chunk is <= c
-        uint32_t lo = 0, hi = a.num_runs;
+    auto run = [&](uint32_t k) -> const StreamRun& { return a.r[k]; };
+    for (uint64_t c = blockIdx.x; c < a.num_chunks; c += gridDim.x)
+        stream_unit(run, a.num_runs, c);
+}
+
+// ---------------------------------------------------------------------------
+// BATCH
+// ---------------------------------------------------------------------------
+
+// Persistent kernel over the work units of many copies.  Each workgroup takes
+// the next unit from an atomic counter until the counter passes the total;
+// the last workgroup to finish puts both counters back to zero, so the next
+// launch (a graph replay included) starts from zero without a memset.
+__global__ void __launch_bounds__(1024) batch_kernel(const BatchArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    __shared__ unsigned long long next_unit;
+    for (;;) {
+        if (threadIdx.x == 0)
+            next_unit = atomicAdd(&a.counters[0], 1ull);
+        __syncthreads();
+        const uint64_t g = __builtin_amdgcn_readfirstlane(uint32_t(next_unit)) |
+                           (uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(next_unit >> 32))) << 32);
+        __syncthreads();
+        if (g >= a.total_units)
+            break;
+        // item j: unit_begin[j] <= g < unit_begin[j + 1]
+        const CONSTANT uint64_t* begin = (const CONSTANT uint64_t*)a.unit_begin;
+        uint32_t lo = 0, hi = a.num_items;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (a.r[mid].first_chunk <= c)
+            if (begin[mid] <= g)
                 lo = mid;
             else
                 hi = mid;
         }
-        const StreamRun& run = a.r[lo];
-        const uint64_t off = (c - run.first_chunk) << kStreamChunkLog2;
-        const uint64_t len = min<uint64_t>(run.bytes - off, uint64_t(1) << kStreamChunkLog2);
-        copy_run_chunk(run.dst + off, run.src ? run.src + off : 0, len, threadIdx.x, blockDim.x);
+        const CONSTANT BatchItem* it = (const CONSTANT BatchItem*)a.items + lo;
+        const uint64_t u = g - begin[lo];
+        if (it->kind == kItemTile) {
+            const TileHeader h = load_const(&it->h);
+            const CONSTANT TileEntry* entries = (const CONSTANT TileEntry*)a.entries + it->first;
+            tile_body(h, [&](uint32_t k) -> const CONSTANT TileEntry& { return entries[k]; }, u, lds);
+        } else {
+            const CONSTANT StreamRun* runs = (const CONSTANT StreamRun*)a.runs + it->first;
+            stream_unit([&](uint32_t k) -> const CONSTANT StreamRun& { return runs[k]; }, it->count, u);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&a.counters[1], 1ull) == gridDim.x - 1ull) {
+            __threadfence();
+            atomicExch(&a.counters[0], 0ull);
+            atomicExch(&a.counters[1], 0ull);
+        }
     }
 }
 
@@ -297,6 +381,46 @@ __global__ void __launch_bounds__(1024) naive_kernel(const NaiveArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// HASH: a position-dependent 64-bit hash of a byte range, summed over
+// 16-byte granules (the autotuner compares candidates' outputs with it)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x)
+{
+    // the finaliser of splitmix64 (Steele, Lea and Flood, 2014)
+    x ^= x >> 30;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 27;
+    x *= 0x94d049bb133111ebull;
+    x ^= x >> 31;
+    return x;
+}
+
+__global__ void __launch_bounds__(256) hash_kernel(const uint8_t* p, uint64_t len, unsigned long long* acc)
+{
+    // byte k of the range contributes through the granule (k / 16) it falls in
+    const uint64_t granules = (len + 15) / 16;
+    uint64_t h = 0;
+    for (uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < granules;
+         g += uint64_t(gridDim.x) * blockDim.x) {
+        uint64_t lo = 0, hi = 0;
+        const uint64_t n = min<uint64_t>(16, len - g * 16);
+        for (uint64_t b = 0; b < n; b++) {
+            const uint64_t v = ((const GLOBAL uint8_t*)p)[g * 16 + b];
+            if (b < 8)
+                lo |= v << (8 * b);
+            else
+                hi |= v << (8 * (b - 8));
+        }
+        h += mix64(lo ^ mix64(2 * g + 1)) + mix64(hi ^ mix64(2 * g + 2));
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        h += __shfl_xor(h, off);
+    if ((threadIdx.x & 63) == 0)
+        atomicAdd(acc, (unsigned long long)h);
+}
+
 void check_hip(hipError_t e, const char* what)
 {
     if (e != hipSuccess)
@@ -312,6 +436,9 @@ void set_attributes()
     check_hip(hipFuncSetAttribute((const void*)tile_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   int(kHardLdsBytes)),
               "hipFuncSetAttribute(tile_kernel)");
+    check_hip(hipFuncSetAttribute((const void*)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(kHardLdsBytes - 64)),
+              "hipFuncSetAttribute(batch_kernel)");
     g_attr_set = true;
 }
 
@@ -349,7 +476,7 @@ void launch(const Plan& p, void* stream_ptr)
     switch (p.path) {
     case LLAMA_PATH_TILE:
         set_attributes();
-        hipLaunchKernelGGL(tile_kernel, dim3(grid), dim3(p.threads), p.tile.lds_bytes, stream, p.tile);
+        hipLaunchKernelGGL(tile_kernel, dim3(grid), dim3(p.threads), p.tile.h.lds_bytes, stream, p.tile);
         break;
     case LLAMA_PATH_STREAM:
         hipLaunchKernelGGL(stream_kernel, dim3(grid), dim3(p.threads), 0, stream, p.stream);
@@ -361,6 +488,28 @@ void launch(const Plan& p, void* stream_ptr)
         fail(LLAMA_E_INVALID_ARG, "unknown path");
     }
     check_hip(hipGetLastError(), "kernel launch");
+}
+
+void launch_hash(const void* p, uint64_t len, unsigned long long* acc, void* stream)
+{
+    if (len == 0)
+        return;
+    const uint64_t granules = (len + 15) / 16;
+    const uint32_t grid = uint32_t(std::min<uint64_t>((granules + 255) / 256, 4096));
+    hipLaunchKernelGGL(hash_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, (const uint8_t*)p, len, acc);
+    check_hip(hipGetLastError(), "hash kernel launch");
+}
+
+void launch_batch_args(const BatchArgs& args, uint32_t grid, uint32_t threads, uint32_t lds_bytes, void* stream)
+{
+    set_attributes();
+    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(threads), lds_bytes, (hipStream_t)stream, args);
+    check_hip(hipGetLastError(), "batch kernel launch");
+}
+
+void launch_batch_kernel(const Batch& b, void* stream)
+{
+    launch_batch_args(b.args, b.grid, b.threads, b.lds_bytes, stream);
 }
 
 } // namespace llama

@@ -78,6 +78,13 @@ class CopyItem(ctypes.Structure):
                 ("dst", ctypes.POINTER(MappingDesc)), ("dst_blobs", ctypes.POINTER(Blob))]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("items", ctypes.c_uint64), ("tile_items", ctypes.c_uint64), ("stream_items", ctypes.c_uint64),
+                ("work_units", ctypes.c_uint64), ("read_bytes", ctypes.c_uint64), ("write_bytes", ctypes.c_uint64),
+                ("threads", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32), ("workgroups", ctypes.c_uint32),
+                ("lds_bytes", ctypes.c_uint32)]
+
+
 _lib = None
 
 # name -> (restype, argtypes) of every entry point the binding uses
@@ -103,6 +110,29 @@ _SIGNATURES = {
                                         ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob), ctypes.c_void_p]),
     "llama_copy_ex": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob), ctypes.POINTER(MappingDesc),
                                      ctypes.POINTER(Blob), ctypes.POINTER(CopyOptions), ctypes.c_void_p]),
+    "llama_autotune": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob), ctypes.POINTER(MappingDesc),
+                                      ctypes.POINTER(Blob), ctypes.c_void_p, ctypes.c_uint32,
+                                      ctypes.POINTER(CopyOptions), ctypes.POINTER(ctypes.c_double)]),
+    "llama_tune_lookup": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(MappingDesc),
+                                         ctypes.POINTER(CopyOptions), ctypes.POINTER(ctypes.c_int)]),
+    "llama_tune_clear": (ctypes.c_int, []),
+    "llama_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "llama_tune_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint32)]),
+    "llama_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "llama_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CopyItem), ctypes.POINTER(ctypes.c_uint64)]),
+    "llama_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
+    "llama_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_double)]),
+    "llama_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "llama_server_reset_stats": (ctypes.c_int, [ctypes.c_void_p]),
+    "llama_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "llama_batch_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.POINTER(CopyItem), ctypes.POINTER(CopyOptions),
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "llama_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "llama_batch_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BatchInfo)]),
+    "llama_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "llama_copy_batch": (ctypes.c_int, [ctypes.c_size_t, ctypes.POINTER(CopyItem), ctypes.c_void_p]),
 }
 
 
@@ -290,3 +320,169 @@ def plan(src: Mapping, dst: Mapping, path=PATH_AUTO, tile_records=0, threads=0, 
             "lds_bytes": info.lds_bytes, "workgroups": info.workgroups, "runs": info.runs,
             "wg_per_cu": info.wg_per_cu, "tiles": info.tiles,
             "read_bytes": info.read_bytes, "write_bytes": info.write_bytes}
+
+
+# --------------------------------------------------------------------------
+# autotuning
+# --------------------------------------------------------------------------
+
+def _opt_dict(o: CopyOptions) -> dict:
+    return {"path": PATH_NAMES.get(o.path, "auto"), "tile_records": o.tile_records, "threads": o.threads,
+            "wg_per_cu": o.wg_per_cu}
+
+
+def autotune(src: Mapping, src_blobs, dst: Mapping, dst_blobs, stream=None, reps=3):
+    """llama_autotune: returns (best options, best GB/s) and caches them."""
+    o, g = CopyOptions(), ctypes.c_double()
+    check(lib().llama_autotune(ctypes.byref(src.desc), _blobs(src_blobs), ctypes.byref(dst.desc), _blobs(dst_blobs),
+                               _stream(stream), reps, ctypes.byref(o), ctypes.byref(g)))
+    return _opt_dict(o), g.value
+
+
+def tune_lookup(src: Mapping, dst: Mapping):
+    o, found = CopyOptions(), ctypes.c_int()
+    check(lib().llama_tune_lookup(ctypes.byref(src.desc), ctypes.byref(dst.desc), ctypes.byref(o), ctypes.byref(found)))
+    return _opt_dict(o) if found.value else None
+
+
+def tune_clear():
+    check(lib().llama_tune_clear())
+
+
+def tune_save(path: str):
+    check(lib().llama_tune_save(path.encode()))
+
+
+def tune_load(path: str) -> int:
+    n = ctypes.c_uint32()
+    check(lib().llama_tune_load(path.encode(), ctypes.byref(n)))
+    return n.value
+
+
+# --------------------------------------------------------------------------
+# batches
+# --------------------------------------------------------------------------
+
+class _Items:
+    """A CopyItem array plus every object it points into."""
+
+    def __init__(self, items):
+        self.keep = []
+        self.arr = (CopyItem * max(len(items), 1))()
+        for k, (src, sblobs, dst, dblobs) in enumerate(items):
+            sb, db = _blobs(sblobs), _blobs(dblobs)
+            self.keep += [src, dst, sb, db]
+            self.arr[k] = CopyItem(ctypes.pointer(src.desc), ctypes.cast(sb, ctypes.POINTER(Blob)),
+                                   ctypes.pointer(dst.desc), ctypes.cast(db, ctypes.POINTER(Blob)))
+        self.n = len(items)
+
+
+class Batch:
+    """llama_batch_*: a prepared batch of copies, launched as one persistent
+    kernel (captured into a hipGraph on its first launch on a stream).
+    `items` is a list of (src_mapping, src_blobs, dst_mapping, dst_blobs)."""
+
+    def __init__(self, items, tile_records=0, threads=0, wg_per_cu=0):
+        self._items = _Items(items)
+        self._h = ctypes.c_void_p()
+        o = _options(PATH_AUTO, tile_records, threads, wg_per_cu)
+        check(lib().llama_batch_create(self._items.n, self._items.arr, ctypes.byref(o), ctypes.byref(self._h)))
+
+    def launch(self, stream=None):
+        check(lib().llama_batch_launch(self._h, _stream(stream)))
+
+    def info(self) -> dict:
+        i = BatchInfo()
+        check(lib().llama_batch_get_info(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in BatchInfo._fields_}
+
+    def close(self):
+        if self._h:
+            check(lib().llama_batch_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def copy_batch(items, stream=None):
+    """llama_copy_batch: one-shot batch launched on `stream`."""
+    it = _Items(items)
+    check(lib().llama_copy_batch(it.n, it.arr, _stream(stream)))
+
+
+# --------------------------------------------------------------------------
+# serving
+# --------------------------------------------------------------------------
+
+SERVE_BATCHED, SERVE_NAIVE, SERVE_PER_REQUEST = 0, 1, 2
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("queue_capacity", ctypes.c_uint32), ("threads", ctypes.c_uint32), ("policy", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("queued", ctypes.c_uint64), ("launches", ctypes.c_uint64), ("bytes_done", ctypes.c_uint64),
+                ("max_inflight_bytes", ctypes.c_uint64), ("mean_batch", ctypes.c_double),
+                ("p50_latency", ctypes.c_double), ("p99_latency", ctypes.c_double), ("max_latency", ctypes.c_double),
+                ("window", ctypes.c_double)]
+
+
+class Server:
+    """llama_server_*: requests admitted within an HBM budget and run with
+    continuous batching.  submit() keeps the request's mappings and blobs
+    alive until its ticket has been waited for or polled done."""
+
+    def __init__(self, budget_bytes, streams=0, max_batch=0, queue_capacity=0, threads=0, policy=SERVE_BATCHED):
+        cfg = ServerConfig(int(budget_bytes), streams, max_batch, queue_capacity, threads, policy, 0)
+        self._h = ctypes.c_void_p()
+        check(lib().llama_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self._keep = {}
+
+    def submit(self, src: Mapping, src_blobs, dst: Mapping, dst_blobs) -> int:
+        it = _Items([(src, src_blobs, dst, dst_blobs)])
+        t = ctypes.c_uint64()
+        check(lib().llama_server_submit(self._h, it.arr, ctypes.byref(t)))
+        self._keep[t.value] = (it, src_blobs, dst_blobs)
+        return t.value
+
+    def poll(self, ticket):
+        done, st, lat = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        check(lib().llama_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(st), ctypes.byref(lat)))
+        if done.value:
+            self._keep.pop(ticket, None)
+            return st.value, lat.value
+        return None
+
+    def wait(self, ticket):
+        st, lat = ctypes.c_int(), ctypes.c_double()
+        check(lib().llama_server_wait(self._h, ticket, ctypes.byref(st), ctypes.byref(lat)))
+        self._keep.pop(ticket, None)
+        return st.value, lat.value
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        check(lib().llama_server_get_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def reset_stats(self):
+        check(lib().llama_server_reset_stats(self._h))
+
+    def close(self):
+        if self._h:
+            check(lib().llama_server_destroy(self._h))
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

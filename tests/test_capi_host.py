@@ -201,3 +201,32 @@ def test_empty_copy_is_a_no_op():
 def test_status_strings():
     assert L.status_string(L.E_OVERLAP) == "LLAMA_E_OVERLAP"
     assert L.status_string(12345) == "LLAMA_E_UNKNOWN"
+
+
+def test_tuning_cache_file_round_trip(tmp_path):
+    """The tuning cache saves and loads as text; an entry whose leaf hash
+    matches no record leaves plans unchanged; malformed or invalid lines are
+    refused.  (Tuning itself, and its effect on plans, is tested on the GPU.)"""
+    L.tune_clear()
+    r = L.Record(W.PARTICLE)
+    a = L.Mapping(r, "aos_packed", [1 << 20])
+    b = L.Mapping(r, "soa_multi", [1 << 20])
+    assert L.tune_lookup(a, b) is None
+    default = L.plan(a, b)
+    path = tmp_path / "tune.txt"
+    L.tune_save(str(path))
+    assert [ln for ln in path.read_text().splitlines() if not ln.startswith("#")] == []
+    probe = tmp_path / "probe.txt"
+    probe.write_text("0 0 0 3 0 20 2 64 192 0 1.0\n")
+    assert L.tune_load(str(probe)) == 1
+    L.tune_save(str(path))
+    assert "0 0 0 3 0 20 2 64 192 0 1" in path.read_text()
+    assert L.plan(a, b) == default and L.tune_lookup(a, b) is None
+    L.tune_clear()
+    for bad in ("garbage\n", "0 0 0 3 0 20 2 63 192 0 1.0\n", "0 0 0 3 0 20 2 64 100 0 1.0\n",
+                "0 0 0 3 0 20 9 64 192 0 1.0\n"):
+        probe.write_text(bad)
+        with pytest.raises(L.LlamaError):
+            L.tune_load(str(probe))
+    with pytest.raises(L.LlamaError):
+        L.tune_load(str(tmp_path / "missing.txt"))

@@ -1,0 +1,161 @@
+"""GPU parity of batched copies: one persistent launch (replayed from a
+hipGraph) must leave every item's destination exactly as the oracle's copy of
+that item, and exactly as a lone llama_copy of it."""
+import random
+
+import numpy as np
+import pytest
+
+from paper_2106_04284_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_04284_amd import llama
+    llama.lib()
+    return llama
+
+
+def make_items(L, orc, seed, count, nmax, records=("particle", "mixed"), layouts=None):
+    """Random batch items: record, size, layout pair; source bytes random, the
+    oracle's expected destination computed on the host."""
+    g = random.Random(seed)
+    layouts = layouts or (W.LAYOUTS + [("aosoa", 16)])
+    items, want = [], []
+    for k in range(count):
+        name = g.choice(records)
+        rec = W.RECORDS[name]
+        n = g.randint(0, nmax) if k % 7 else g.randint(1, 3)
+        a, b = g.choice(layouts), g.choice(layouts)
+        ro, rg = orc.Record(rec), L.Record(rec)
+        ms_o, md_o = orc.Mapping(ro, a[0], [n], a[1]), orc.Mapping(ro, b[0], [n], b[1])
+        src = [W.random_bytes(s, seed * 7919 + k * 31 + j) for j, s in enumerate(ms_o.blob_sizes())]
+        want.append(orc.copy(ms_o, src, md_o))
+        ms, md = L.Mapping(rg, a[0], [n], a[1]), L.Mapping(rg, b[0], [n], b[1])
+        sd = [torch.from_numpy(x).cuda() for x in src]
+        dd = md.alloc(fill=0xCD)
+        items.append((ms, sd, md, dd))
+    return items, want
+
+
+def check(items, want):
+    for k, ((_, _, _, dd), w) in enumerate(zip(items, want)):
+        for j, (t, x) in enumerate(zip(dd, w)):
+            got = t.cpu().numpy()
+            if not np.array_equal(got, x):
+                bad = np.flatnonzero(got != x)
+                raise AssertionError(f"item {k} blob {j}: {bad.size} bytes differ, first at {bad[0]}")
+
+
+def refill(items, value):
+    for _, _, _, dd in items:
+        for t in dd:
+            t.fill_(value)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_batch_matches_oracle_and_replays(L, orc, seed):
+    items, want = make_items(L, orc, seed, count=40, nmax=20000)
+    b = L.Batch(items)
+    info = b.info()
+    assert info["work_units"] > 0 and info["items"] <= len(items)
+    stream = torch.cuda.Stream()
+    for rep in range(3):
+        refill(items, 0xCD if rep % 2 == 0 else 0x00)  # eager work between graph replays
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            b.launch()
+        stream.synchronize()
+        check(items, want)
+    b.close()
+
+
+def test_batch_equals_lone_copies(L, orc):
+    items, want = make_items(L, orc, 9, count=30, nmax=5000, records=("particle", "mixed", "lbm", "listing1"))
+    lone = []
+    for ms, sd, md, _ in items:
+        out = md.alloc(fill=0x11)
+        L.copy(ms, sd, md, out)
+        lone.append(out)
+    b = L.Batch(items)
+    b.launch()
+    torch.cuda.synchronize()
+    for (_, _, _, dd), lo in zip(items, lone):
+        for x, y in zip(dd, lo):
+            assert torch.equal(x, y)
+    check(items, want)
+
+
+@pytest.mark.parametrize("opts", [dict(threads=64), dict(threads=512), dict(wg_per_cu=1), dict(wg_per_cu=16),
+                                  dict(tile_records=64, threads=128), dict(tile_records=16)])
+def test_batch_options(L, orc, opts):
+    items, want = make_items(L, orc, 5, count=20, nmax=8000)
+    b = L.Batch(items, **opts)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b.launch()
+        b.launch()  # a second run over the same destinations gives the same bytes
+    stream.synchronize()
+    check(items, want)
+
+
+def test_one_shot_batch_and_null_stream(L, orc):
+    items, want = make_items(L, orc, 12, count=25, nmax=3000)
+    L.copy_batch(items)
+    torch.cuda.synchronize()
+    check(items, want)
+    refill(items, 0x5A)
+    b = L.Batch(items)
+    b.launch(stream=0)  # the null stream is not captured; the kernel is launched directly
+    torch.cuda.synchronize()
+    check(items, want)
+
+
+def test_batch_rejects_overlap(L):
+    r = L.Record(W.PARTICLE)
+    a, s = L.Mapping(r, "aos_packed", [1000]), L.Mapping(r, "soa_single", [1000])
+    src = torch.empty(28000, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(28000 * 2, dtype=torch.uint8, device="cuda")
+    with pytest.raises(L.LlamaError) as e:
+        L.Batch([(a, [src], s, [dst[:28000]]), (a, [src], s, [dst[100:28100]])])
+    assert e.value.status == L.E_OVERLAP
+    with pytest.raises(L.LlamaError) as e:
+        L.Batch([(a, [src], s, [dst[:28000]]), (a, [dst[:28000]], s, [dst[28000:]])])
+    assert e.value.status == L.E_OVERLAP
+
+
+def test_autotune_caches_a_bit_exact_plan(L, orc, tmp_path):
+    """Autotuning picks a plan, every candidate having matched the default
+    plan's bytes; later default copies of the class use it and stay exact."""
+    L.tune_clear()
+    rg = L.Record(W.MIXED)
+    n = 150000
+    a, b = L.Mapping(rg, "aos_aligned", [n]), L.Mapping(rg, "aosoa", [n], 32)
+    ro = orc.Record(W.MIXED)
+    src = [W.random_bytes(s, 77) for s in orc.Mapping(ro, "aos_aligned", [n]).blob_sizes()]
+    expect = orc.copy(orc.Mapping(ro, "aos_aligned", [n]), src, orc.Mapping(ro, "aosoa", [n], 32))
+    sd = [torch.from_numpy(x).cuda() for x in src]
+    dd = b.alloc(fill=0)
+    best, gbs = L.autotune(a, sd, b, dd)
+    assert gbs > 0 and best["path"] in ("tile", "stream")
+    assert L.tune_lookup(a, b) == best
+    p = L.plan(a, b)
+    if best["path"] == "tile":
+        assert (p["tile_records"], p["threads"]) == (best["tile_records"], best["threads"])
+    for t in dd:
+        t.fill_(0xEE)
+    L.copy(a, sd, b, dd)
+    torch.cuda.synchronize()
+    assert np.array_equal(dd[0].cpu().numpy(), expect[0])
+    path = str(tmp_path / "tune.txt")
+    L.tune_save(path)
+    L.tune_clear()
+    assert L.tune_lookup(a, b) is None
+    assert L.tune_load(path) == 1 and L.tune_lookup(a, b) == best
+    L.tune_clear()
