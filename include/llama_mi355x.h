@@ -185,8 +185,13 @@ typedef struct {
     uint32_t threads;      /* threads per workgroup, a multiple of 64 in 64 .. 1024 */
     uint32_t wg_per_cu;    /* TILE: 0 launches one workgroup per tile; 1 .. 16 launches a
                               persistent grid of that many workgroups per compute unit */
-    uint32_t flags;        /* reserved, must be 0 */
+    uint32_t flags;        /* LLAMA_COPY_* bits */
 } llama_copy_options;
+
+/* TILE: always stage the destination through LDS (by default a field-major
+ * destination with 16-byte aligned leaf spans is gathered from the source
+ * tile and stored from registers). */
+#define LLAMA_COPY_NO_DIRECT 1u
 
 /* llama_copy with explicit kernel parameters.  The result does not depend on
  * the options; only the speed does. */

@@ -76,9 +76,9 @@ void reap_retired()
 
 } // namespace
 
-void BatchTable::add(const Request& rq, uint32_t threads, uint32_t tile_records)
+void BatchTable::add(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags)
 {
-    llama_copy_options o{LLAMA_PATH_AUTO, tile_records, threads, 0, 0};
+    llama_copy_options o{LLAMA_PATH_AUTO, tile_records, threads, 0, flags};
     Plan p = make_plan(rq, &o);
     read_bytes += p.read_bytes;
     write_bytes += p.write_bytes;
@@ -165,8 +165,8 @@ Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_opt
     reap_retired();
     if (n > 0 && !items)
         fail(LLAMA_E_INVALID_ARG, "batch item array is NULL");
-    if (opt && (opt->path != LLAMA_PATH_AUTO || opt->flags != 0))
-        fail(LLAMA_E_INVALID_ARG, "batch options take tile_records, threads and wg_per_cu only");
+    if (opt && (opt->path != LLAMA_PATH_AUTO || (opt->flags & ~LLAMA_COPY_NO_DIRECT) != 0))
+        fail(LLAMA_E_INVALID_ARG, "batch options take tile_records, threads, wg_per_cu and LLAMA_COPY_NO_DIRECT");
     const uint32_t threads = (opt && opt->threads) ? opt->threads : kDefaultThreads;
     if (threads % 64 != 0 || threads == 0 || threads > 1024)
         fail(LLAMA_E_INVALID_ARG, "threads must be a multiple of 64 in 64..1024");
@@ -190,7 +190,7 @@ Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_opt
     BatchTable t;
     for (size_t k = 0; k < n; k++) {
         try {
-            t.add(rqs[k], threads, T);
+            t.add(rqs[k], threads, T, opt ? opt->flags : 0u);
         } catch (const Error& e) {
             fail(e.status, "batch item " + std::to_string(k) + ": " + e.message);
         }

@@ -36,7 +36,7 @@ struct BatchTable {
 
     // plans `rq` with `threads` per workgroup and adds it; fails with
     // LLAMA_E_UNSUPPORTED for a record the tiled kernel cannot hold
-    void add(const Request& rq, uint32_t threads, uint32_t tile_records);
+    void add(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags = 0);
     // bytes of the serialised table
     size_t bytes() const;
     // writes the table to `host` (bytes() long) as it must lie at device

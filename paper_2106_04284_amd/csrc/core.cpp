@@ -468,6 +468,19 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
         e.move = log2_move(uint64_t(e.dst_pos) | e.size | dst_rm_bits) | (1u << 31);
     }
     a.num_entries = uint32_t(k);
+    // direct store: a field-major destination whose leaf spans start 16-byte
+    // aligned, with leaf sizes 1..16 (powers of two) read at their own width
+    bool direct = a.dst.mode == kFieldMajor && rq.dst.gaps.empty() && !(p.flags_in & kPlanNoDirect);
+    for (size_t f = 0; f < F && direct; f++) {
+        const TileEntry& e = ta.e[f];
+        const uint32_t sz = e.size;
+        direct = sz <= 16 && (sz & (sz - 1)) == 0 && (e.dst_addr & 15) == 0 && (1u << (e.move & 7u)) == sz;
+    }
+    if (direct) {
+        a.flags |= kTileDirectStore;
+        a.dst.lds_bytes = 0;
+        a.lds_bytes = sb;
+    }
     // field-major spans are short: rotate the first loading wave and the
     // first storing thread from leaf to leaf so that every wave takes a share
     const uint32_t nwaves = p.threads / 64;
@@ -476,6 +489,8 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
         TileEntry& e = ta.e[f];
         e.move |= (first_wave << 4) | (first_thread << 8);
         uint64_t granules = (uint64_t(T) * e.size + 30) / 16;
+        if (a.flags & kTileDirectStore)
+            granules = (uint64_t(T) * e.size + 15) / 16;
         first_wave = uint32_t((first_wave + (granules + 63) / 64) % nwaves);
         first_thread = uint32_t((first_thread + granules) % p.threads);
     }
@@ -582,8 +597,9 @@ Plan make_plan_raw(const Request& rq, const llama_copy_options* opt)
     p.read_bytes = total_bytes(rq.src.blob_size);
     p.write_bytes = total_bytes(rq.dst.blob_size);
     uint32_t want = opt ? opt->path : uint32_t(LLAMA_PATH_AUTO);
-    if (opt && opt->flags != 0)
-        fail(LLAMA_E_INVALID_ARG, "llama_copy_options.flags must be 0");
+    if (opt && (opt->flags & ~LLAMA_COPY_NO_DIRECT) != 0)
+        fail(LLAMA_E_INVALID_ARG, "unknown bits in llama_copy_options.flags");
+    p.flags_in = opt ? opt->flags : 0;
     if (want > LLAMA_PATH_NAIVE)
         fail(LLAMA_E_INVALID_ARG, "llama_copy_options.path is not a llama_path");
     uint32_t threads = (opt && opt->threads) ? opt->threads : 0;

@@ -88,6 +88,7 @@ struct Plan {
     uint32_t lds_bytes = 0;
     uint32_t wg_per_cu = 0;
     uint64_t tiles = 0;
+    uint32_t flags_in = 0; // llama_copy_options.flags of the request
     uint64_t read_bytes = 0, write_bytes = 0;
     TileArgs tile{};     // path == TILE
     StreamArgs stream{}; // path == STREAM
@@ -95,6 +96,8 @@ struct Plan {
 };
 
 Plan make_plan(const Request& rq, const llama_copy_options* opt);
+
+constexpr uint32_t kPlanNoDirect = LLAMA_COPY_NO_DIRECT;
 
 // kernels.hip
 void launch(const Plan& p, void* stream);

@@ -56,8 +56,16 @@ struct TileHeader {
     uint32_t num_leaves;
     uint32_t num_entries; // leaves, then gaps
     uint32_t lds_bytes;
+    uint32_t flags;       // kTileDirectStore
+    uint32_t pad;
     TileSide src, dst;
 };
+
+// Destination field-major with 16-byte aligned leaf spans and leaf sizes of 1,
+// 2, 4, 8 or 16 bytes: every 16-byte granule of a destination span holds whole
+// values of one leaf, gathered straight from the source region into registers
+// and stored; the tile needs no destination region in LDS.
+constexpr uint32_t kTileDirectStore = 1;
 
 struct TileArgs {
     TileHeader h;

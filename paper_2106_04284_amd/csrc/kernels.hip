@@ -142,6 +142,41 @@ __device__ __forceinline__ void move4(uint8_t* lds, uint32_t sp, uint32_t dp, co
     }
 }
 
+// Reads value r of an entry from the source region (ld = log2 of its size).
+template <typename T>
+__device__ __forceinline__ T src_value(const uint8_t* lds, uint32_t sp, const TileSide& s, uint32_t r, uint32_t size)
+{
+    return *(const T*)(lds + sp + (r >> s.pos_lg) * s.pos_k + (r & s.pos_m) * size);
+}
+
+// Direct store of one leaf: every 16-byte granule of the destination span
+// gathers 16 / size consecutive records from the source region; records >= nv
+// (AoSoA lanes past the last record) are zero; a granule that passes record nd
+// is stored value by value.
+template <typename T>
+__device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t sp, const TileSide& s, uint64_t gdst,
+                                                  uint32_t nv, uint32_t nd, uint32_t tid, uint32_t nthr, uint32_t rot)
+{
+    constexpr uint32_t per = 16 / sizeof(T);
+    const uint32_t G = (nd + per - 1) / per;
+    for (uint32_t g = tid >= rot ? tid - rot : tid + nthr - rot; g < G; g += nthr) {
+        const uint32_t r0 = g * per;
+        union {
+            u32x4 v;
+            T t[per];
+        } u;
+#pragma unroll
+        for (uint32_t j = 0; j < per; j++)
+            u.t[j] = r0 + j < nv ? src_value<T>(lds, sp, s, r0 + j, sizeof(T)) : T{};
+        if (r0 + per <= nd) {
+            *(GLOBAL u32x4*)(gdst + uint64_t(g) * 16u) = u.v;
+        } else {
+            for (uint32_t j = 0; r0 + j < nd; j++)
+                *(GLOBAL T*)(gdst + uint64_t(g) * 16u + j * sizeof(T)) = u.t[j];
+        }
+    }
+}
+
 // One tile: every wave issues its share of the source loads straight into
 // LDS, then all threads move the values to their destination positions
 // inside LDS, then all threads store the destination span(s).  `ent(k)`
@@ -172,6 +207,24 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+
+    if (h.flags & kTileDirectStore) {
+        // ---- 2'. gather each destination granule from the source region and
+        //          store it; no destination region, no second barrier
+        for (uint32_t f = 0; f < h.num_leaves; f++) {
+            const auto& e = ent(f);
+            const uint64_t gdst = field_span_start(e.dst_addr, h.dst, i0, e.size);
+            const uint32_t rot = (e.move >> 8) & 4095u;
+            switch (e.move & 7u) {
+            case 4: direct_store_leaf<u32x4>(lds, e.src_pos, h.src, gdst, nv, nd, tid, nthr, rot); break;
+            case 3: direct_store_leaf<uint64_t>(lds, e.src_pos, h.src, gdst, nv, nd, tid, nthr, rot); break;
+            case 2: direct_store_leaf<uint32_t>(lds, e.src_pos, h.src, gdst, nv, nd, tid, nthr, rot); break;
+            case 1: direct_store_leaf<uint16_t>(lds, e.src_pos, h.src, gdst, nv, nd, tid, nthr, rot); break;
+            default: direct_store_leaf<uint8_t>(lds, e.src_pos, h.src, gdst, nv, nd, tid, nthr, rot); break;
+            }
+        }
+        return;
+    }
 
     // ---- 2. every value from its source to its destination position;
     //         destination padding becomes zero

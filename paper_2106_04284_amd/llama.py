@@ -287,20 +287,23 @@ def _stream(stream):
     return stream.cuda_stream
 
 
-def _options(path=PATH_AUTO, tile_records=0, threads=0, wg_per_cu=0):
+COPY_NO_DIRECT = 1
+
+
+def _options(path=PATH_AUTO, tile_records=0, threads=0, wg_per_cu=0, flags=0):
     if isinstance(path, str):
         path = {"auto": PATH_AUTO, "stream": PATH_STREAM, "tile": PATH_TILE, "naive": PATH_NAIVE}[path]
-    return CopyOptions(path, tile_records, threads, wg_per_cu, 0)
+    return CopyOptions(path, tile_records, threads, wg_per_cu, flags)
 
 
 def copy(src: Mapping, src_blobs, dst: Mapping, dst_blobs, stream=None, path=PATH_AUTO, tile_records=0,
-         threads=0, wg_per_cu=0):
+         threads=0, wg_per_cu=0, flags=0):
     """llama_copy / llama_copy_ex: enqueues the copy on `stream`."""
     sb, db = _blobs(src_blobs), _blobs(dst_blobs)
-    if path == PATH_AUTO and not tile_records and not threads and not wg_per_cu:
+    if path == PATH_AUTO and not tile_records and not threads and not wg_per_cu and not flags:
         check(lib().llama_copy(ctypes.byref(src.desc), sb, ctypes.byref(dst.desc), db, _stream(stream)))
     else:
-        o = _options(path, tile_records, threads, wg_per_cu)
+        o = _options(path, tile_records, threads, wg_per_cu, flags)
         check(lib().llama_copy_ex(ctypes.byref(src.desc), sb, ctypes.byref(dst.desc), db, ctypes.byref(o),
                                   _stream(stream)))
 
@@ -311,10 +314,10 @@ def copy_naive(src: Mapping, src_blobs, dst: Mapping, dst_blobs, stream=None):
                                  _blobs(dst_blobs), _stream(stream)))
 
 
-def plan(src: Mapping, dst: Mapping, path=PATH_AUTO, tile_records=0, threads=0, wg_per_cu=0) -> dict:
+def plan(src: Mapping, dst: Mapping, path=PATH_AUTO, tile_records=0, threads=0, wg_per_cu=0, flags=0) -> dict:
     """llama_plan: what a copy of this pair would launch."""
     info = PlanInfo()
-    o = _options(path, tile_records, threads, wg_per_cu)
+    o = _options(path, tile_records, threads, wg_per_cu, flags)
     check(lib().llama_plan(ctypes.byref(src.desc), ctypes.byref(dst.desc), ctypes.byref(o), ctypes.byref(info)))
     return {"path": PATH_NAMES.get(info.path, "?"), "tile_records": info.tile_records, "threads": info.threads,
             "lds_bytes": info.lds_bytes, "workgroups": info.workgroups, "runs": info.runs,
@@ -382,10 +385,10 @@ class Batch:
     kernel (captured into a hipGraph on its first launch on a stream).
     `items` is a list of (src_mapping, src_blobs, dst_mapping, dst_blobs)."""
 
-    def __init__(self, items, tile_records=0, threads=0, wg_per_cu=0):
+    def __init__(self, items, tile_records=0, threads=0, wg_per_cu=0, flags=0):
         self._items = _Items(items)
         self._h = ctypes.c_void_p()
-        o = _options(PATH_AUTO, tile_records, threads, wg_per_cu)
+        o = _options(PATH_AUTO, tile_records, threads, wg_per_cu, flags)
         check(lib().llama_batch_create(self._items.n, self._items.arr, ctypes.byref(o), ctypes.byref(self._h)))
 
     def launch(self, stream=None):

@@ -1,0 +1,150 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (default plans; the batch with the benchmark's thread counts).
+
+  * particle record, 2^26 records, every ordered layout pair: the source is
+    random bytes with NaN payloads, -0, subnormals and infinities planted;
+    2^20 sampled (record, leaf) values are checked one by one by the oracle,
+    and every destination byte must be written (two runs over destinations filled with 0x00 and 0xFF
+    agree byte for byte);
+  * lattice-Boltzmann cells, 128^3, aligned AoS <-> multi-blob SoA <-> AoSoA32:
+    the whole destination against the oracle's full copy;
+  * the 1,000-array batch: every destination byte written (two fills), and
+    sampled values of 40 items checked by the oracle.
+"""
+import random
+
+import numpy as np
+import pytest
+
+from paper_2106_04284_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+PAIRS = [(a, b) for a in W.LAYOUTS for b in W.LAYOUTS if a != b]
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_04284_amd import llama
+    llama.lib()
+    return llama
+
+
+def _name(layout):
+    kind, lanes = layout
+    return f"{kind}{lanes}" if kind == "aosoa" else kind
+
+
+def _random_blob(nbytes, seed, plant=True):
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    t = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda", generator=g)
+    if plant and nbytes >= 4 * 4096:
+        # special 32-bit patterns at fixed word offsets (the particle's values
+        # are 4-byte words in every layout)
+        words = t[: nbytes // 4 * 4].view(torch.int32)
+        special = torch.from_numpy(W.SPECIAL_U32.view(np.int32).copy()).cuda()
+        for k in range(len(special)):
+            idx = torch.arange(k, words.numel(), 1009 * (k + 1), device="cuda")
+            words[idx] = special[k]
+    return t
+
+
+def _samples(n, nleaves, count, seed):
+    g = np.random.default_rng(seed)
+    idx = g.integers(0, n, size=count, dtype=np.uint64)
+    idx[:16] = np.arange(16, dtype=np.uint64)  # the first and last records
+    idx[16:32] = np.arange(n - 16, n, dtype=np.uint64)
+    leaf = g.integers(0, nleaves, size=count, dtype=np.int32)
+    return idx, leaf
+
+
+@pytest.mark.parametrize("pair", PAIRS, ids=[f"{_name(a)}-{_name(b)}" for a, b in PAIRS])
+def test_particle_2e26_sampled(L, orc, pair):
+    n = 1 << 26
+    a, b = pair
+    ro, rg = orc.Record(W.PARTICLE), L.Record(W.PARTICLE)
+    ms_o, md_o = orc.Mapping(ro, a[0], [n], a[1]), orc.Mapping(ro, b[0], [n], b[1])
+    ms, md = L.Mapping(rg, a[0], [n], a[1]), L.Mapping(rg, b[0], [n], b[1])
+    assert ms.blob_sizes() == ms_o.blob_sizes() and md.blob_sizes() == md_o.blob_sizes()
+    src = [_random_blob(s, 1000 + k) for k, s in enumerate(ms.blob_sizes())]
+    d0 = md.alloc(fill=0x00)
+    d1 = md.alloc(fill=0xFF)
+    L.copy(ms, src, md, d0)
+    L.copy(ms, src, md, d1)
+    torch.cuda.synchronize()
+    for x, y in zip(d0, d1):  # a byte left unwritten would differ
+        assert torch.equal(x, y)
+    src_h = [t.cpu().numpy() for t in src]
+    dst_h = [t.cpu().numpy() for t in d0]
+    idx, leaf = _samples(n, 7, 1 << 20, 7)
+    bad, first = orc.check_samples(ms_o, src_h, md_o, dst_h, idx, leaf)
+    assert bad == 0, f"{bad} sampled values differ, first sample {first}"
+    # (the particle layouts have no padding at 2^26 records: R = S and 2^26 is
+    # a multiple of every lane count; padding is checked in full below)
+
+
+LBM_LAYOUTS = [("aos_aligned", 0), ("soa_multi", 0), ("aosoa", 32)]
+LBM_PAIRS = [(a, b) for a in LBM_LAYOUTS for b in LBM_LAYOUTS if a != b]
+
+
+@pytest.mark.parametrize("pair", LBM_PAIRS, ids=[f"{_name(a)}-{_name(b)}" for a, b in LBM_PAIRS])
+def test_lbm_128cubed_full(L, orc, pair):
+    ext = [128, 128, 128]
+    a, b = pair
+    ro, rg = orc.Record(W.LBM), L.Record(W.LBM)
+    ms_o, md_o = orc.Mapping(ro, a[0], ext, a[1]), orc.Mapping(ro, b[0], ext, b[1])
+    ms, md = L.Mapping(rg, a[0], ext, a[1]), L.Mapping(rg, b[0], ext, b[1])
+    vals = W.lbm_values(128 ** 3, W.BASE_SEED + 3)
+    mb = orc.Mapping(ro, "soa_multi", ext)
+    src_h = orc.copy(mb, [np.ascontiguousarray(v).view(np.uint8).reshape(-1) for v in vals], ms_o)
+    # the source's own padding holds random bytes, not zeros
+    for blob, pad in zip(src_h, orc.padding_masks(ms_o)):
+        blob[pad] = np.random.default_rng(5).integers(0, 256, int(pad.sum()), dtype=np.uint8)
+    want = orc.copy(ms_o, src_h, md_o)
+    src = [torch.from_numpy(x).cuda() for x in src_h]
+    dst = md.alloc(fill=0xCD)
+    L.copy(ms, src, md, dst)
+    torch.cuda.synchronize()
+    for t, w in zip(dst, want):
+        assert np.array_equal(t.cpu().numpy(), w)
+
+
+@pytest.mark.parametrize("threads", [128, 256])
+def test_batch_1000_arrays(L, orc, threads):
+    items_spec = W.batch_items()
+    cache, items = {}, []
+    for k, it in enumerate(items_spec):
+        rg = cache.setdefault(it["record"], L.Record(W.RECORDS[it["record"]]))
+        ms = L.Mapping(rg, it["src"][0], [it["n"]], it["src"][1])
+        md = L.Mapping(rg, it["dst"][0], [it["n"]], it["dst"][1])
+        sb = [_random_blob(s, 5000 + 3 * k + j, plant=False) for j, s in enumerate(ms.blob_sizes())]
+        items.append((ms, sb, md, md.alloc(fill=0x00)))
+    b = L.Batch(items, threads=threads)
+    stream = torch.cuda.Stream()
+    b.launch(stream)  # captured into a hipGraph and launched
+    torch.cuda.synchronize()
+    first = [[t.clone() for t in it[3]] for it in items]
+    for it in items:
+        for t in it[3]:
+            t.fill_(0xFF)
+    b.launch(stream)  # graph replay
+    torch.cuda.synchronize()
+    for f, it in zip(first, items):
+        for x, y in zip(f, it[3]):
+            assert torch.equal(x, y)
+    del first
+    g = random.Random(3)
+    for k in g.sample(range(len(items)), 40):
+        it, spec = items[k], items_spec[k]
+        ro = orc.Record(W.RECORDS[spec["record"]])
+        ms_o = orc.Mapping(ro, spec["src"][0], [spec["n"]], spec["src"][1])
+        md_o = orc.Mapping(ro, spec["dst"][0], [spec["n"]], spec["dst"][1])
+        idx, leaf = _samples(spec["n"], ro.nleaves, 20000, k)
+        bad, first_bad = orc.check_samples(ms_o, [t.cpu().numpy() for t in it[1]], md_o,
+                                           [t.cpu().numpy() for t in it[3]], idx, leaf)
+        assert bad == 0, f"item {k}: {bad} sampled values differ"

@@ -141,8 +141,9 @@ def test_oversized_destination_blobs_keep_their_tail(L, orc):
     run_case(L, orc, W.LBM, ("soa_multi", 0), ("aosoa", 32), [100], seed=5, extra_dst=37)
 
 
-@pytest.mark.parametrize("opts", [dict(path="tile", tile_records=t, threads=th, wg_per_cu=w)
-                                  for t in (16, 64, 256, 1024) for th in (64, 192, 1024) for w in (0, 1, 3)]
+@pytest.mark.parametrize("opts", [dict(path="tile", tile_records=t, threads=th, wg_per_cu=w, flags=fl)
+                                  for t in (16, 64, 256, 1024) for th in (64, 192, 1024) for w in (0, 1, 3)
+                                  for fl in (0, 1)]
                          + [dict(path="naive"), dict(path="naive", threads=64)])
 @pytest.mark.parametrize("pair", [(("aos_packed", 0), ("soa_single", 0)), (("aosoa", 32), ("soa_multi", 0)),
                                   (("aos_aligned", 0), ("aosoa", 8)), (("soa_multi", 0), ("soa_single", 0))])
