@@ -193,6 +193,11 @@ typedef struct {
  * tile and stored from registers). */
 #define LLAMA_COPY_NO_DIRECT 1u
 
+/* TILE: move a misaligned value byte by byte (by default a 2-, 4- or 8-byte
+ * value of a packed record of odd size is read whole from the words that hold
+ * it and written in pieces of the destination's alignment). */
+#define LLAMA_COPY_NO_SPLIT 2u
+
 /* llama_copy with explicit kernel parameters.  The result does not depend on
  * the options; only the speed does. */
 int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
@@ -221,8 +226,9 @@ int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, con
 /* ------------------------------------------------------------------------ */
 
 /* Measures kernel parameters for this copy on its own blobs: TILE with tile
- * sizes 16 .. 4096 records and 64/128/256 threads, and STREAM where the pair
- * has long runs.  Each candidate first runs on a destination filled with a
+ * sizes 16 .. 4096 records and 64/128/256 threads (each also with
+ * LLAMA_COPY_NO_DIRECT where the plan would use a direct mode), and STREAM
+ * where the pair has long runs.  Each candidate first runs on a destination filled with a
  * pattern and must produce the same bytes (compared by a 64-bit hash of the
  * destination blobs) as the default plan; then it is timed (best of `reps`
  * launches, 0: 3).  The fastest goes to the process-wide tuning cache, keyed
@@ -241,7 +247,10 @@ int llama_tune_lookup(const llama_mapping_desc* src, const llama_mapping_desc* d
 
 int llama_tune_clear(void);
 
-/* The tuning cache as a text file (one line per class). */
+/* The tuning cache as a text file: one line per class, 12 fields separated
+ * by blanks (leaf hash in hex, source kind, source lanes, destination kind,
+ * destination lanes, size bucket, path, tile records, threads, wg_per_cu,
+ * flags, measured GB/s); lines starting with '#' are comments. */
 int llama_tune_save(const char* path);
 
 /* Adds the classes of a file written by llama_tune_save; *entries (may be
@@ -343,7 +352,9 @@ typedef struct {
  * device, and one reusable work table per stream; it never allocates blobs.
  *
  * Requests keep their blobs on the device (the caller's, valid until the
- * request completes).  The engine admits queued requests in arrival order
+ * request completes).  The server's streams do not wait for the caller's
+ * streams: a request's source must be complete, and nothing else may touch
+ * its blobs, from submit until it completes.  The engine admits queued requests in arrival order
  * while the bytes in flight stay within budget_bytes and no destination range
  * meets a range of a request in flight; each admitted group is one launch on
  * the next free stream.  Requests that arrive while launches run join the

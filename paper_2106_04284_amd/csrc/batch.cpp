@@ -165,7 +165,7 @@ Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_opt
     reap_retired();
     if (n > 0 && !items)
         fail(LLAMA_E_INVALID_ARG, "batch item array is NULL");
-    if (opt && (opt->path != LLAMA_PATH_AUTO || (opt->flags & ~LLAMA_COPY_NO_DIRECT) != 0))
+    if (opt && (opt->path != LLAMA_PATH_AUTO || (opt->flags & ~kCopyFlags) != 0))
         fail(LLAMA_E_INVALID_ARG, "batch options take tile_records, threads, wg_per_cu and LLAMA_COPY_NO_DIRECT");
     const uint32_t threads = (opt && opt->threads) ? opt->threads : kDefaultThreads;
     if (threads % 64 != 0 || threads == 0 || threads > 1024)

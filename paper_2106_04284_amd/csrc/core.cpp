@@ -456,6 +456,10 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
                         ? a.dst.lds_base + uint32_t(rq.dst_ptr[0] & 15) + uint32_t(rq.dst.base[f])
                         : a.dst.lds_base + dst_lds[f] + uint32_t(e.dst_addr & 15);
         e.move = log2_move(uint64_t(e.src_pos) | e.dst_pos | e.size | src_rm_bits | dst_rm_bits);
+        const uint32_t rd = log2_move(uint64_t(e.src_pos) | e.size | src_rm_bits);
+        const uint32_t wr = log2_move(uint64_t(e.dst_pos) | e.size | dst_rm_bits);
+        if ((e.size == 2 || e.size == 4 || e.size == 8) && (e.move & 7u) < 2 && !(p.flags_in & kPlanNoSplit))
+            e.move |= kMoveSplit | (rd << 20) | (wr << 24);
     }
     size_t k = F;
     for (const auto& g : rq.dst.gaps) { // only record-major (aligned AoS) destinations have gaps
@@ -480,6 +484,36 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
         a.flags |= kTileDirectStore;
         a.dst.lds_bytes = 0;
         a.lds_bytes = sb;
+    }
+    // direct load: a field-major source whose leaf spans start 16-byte
+    // aligned, leaf sizes 4, 8 or 16, destination positions aligned
+    // to the leaf size, and at most kDirectLoadSlots granule slots per thread
+    bool dload = !direct && a.src.mode == kFieldMajor && !(p.flags_in & kPlanNoDirect);
+    uint32_t slots = 0;
+    std::vector<uint32_t> first(F, 0);
+    for (size_t f = 0; f < F && dload; f++) {
+        const TileEntry& e = ta.e[f];
+        const uint32_t sz = e.size;
+        const uint64_t dst_bits = uint64_t(e.dst_pos) | (a.dst.mode == kRecordMajor ? rq.dst.block : 0);
+        dload = (sz == 4 || sz == 8 || sz == 16) && (e.src_addr & 15) == 0 && (lowbit(dst_bits | 16) >= sz);
+        first[f] = slots;
+        const uint32_t granules = uint32_t((uint64_t(T) * sz) / 16);
+        slots += (granules + 63) / 64 * 64;
+    }
+    if (dload && slots <= kDirectLoadSlots * p.threads && p.threads % 64 == 0) {
+        a.flags |= kTileDirectLoad;
+        a.slots = slots;
+        for (size_t f = 0; f < k; f++) {
+            TileEntry& e = ta.e[f];
+            e.dst_pos -= sb; // the destination region moves to the start of LDS
+            if (f < F) {
+                e.src_pos = first[f];
+                e.move = log2_exact(e.size) | (e.move & ~(7u | kMoveSplit));
+            }
+        }
+        a.src.lds_bytes = 0;
+        a.dst.lds_base = 0;
+        a.lds_bytes = db;
     }
     // field-major spans are short: rotate the first loading wave and the
     // first storing thread from leaf to leaf so that every wave takes a share
@@ -597,7 +631,7 @@ Plan make_plan_raw(const Request& rq, const llama_copy_options* opt)
     p.read_bytes = total_bytes(rq.src.blob_size);
     p.write_bytes = total_bytes(rq.dst.blob_size);
     uint32_t want = opt ? opt->path : uint32_t(LLAMA_PATH_AUTO);
-    if (opt && (opt->flags & ~LLAMA_COPY_NO_DIRECT) != 0)
+    if (opt && (opt->flags & ~kCopyFlags) != 0)
         fail(LLAMA_E_INVALID_ARG, "unknown bits in llama_copy_options.flags");
     p.flags_in = opt ? opt->flags : 0;
     if (want > LLAMA_PATH_NAIVE)
@@ -632,6 +666,21 @@ Plan make_plan_raw(const Request& rq, const llama_copy_options* opt)
             t /= 2;
             p.threads = threads ? threads : nthreads(t);
             ok = fill_tile(rq, t, kMaxLdsBytes, p);
+        }
+        if (ok && !threads && p.tile.h.src.mode == kFieldMajor &&
+            !(p.tile.h.flags & (kTileDirectLoad | kTileDirectStore))) {
+            // a field-major source loads directly when every thread holds at
+            // most kDirectLoadSlots granules: try enough threads for that
+            uint32_t slots = 0;
+            for (const Leaf& l : rq.record.leaves)
+                slots += uint32_t((uint64_t(t) * l.size / 16 + 63) / 64 * 64);
+            uint32_t want = (slots + kDirectLoadSlots * 64 - 1) / (kDirectLoadSlots * 64) * 64;
+            if (want > p.threads && want <= 1024) {
+                Plan q = p;
+                q.threads = want;
+                if (fill_tile(rq, t, kMaxLdsBytes, q) && (q.tile.h.flags & kTileDirectLoad))
+                    p = q;
+            }
         }
         if (ok) {
             tile_grid(p, wg_per_cu);

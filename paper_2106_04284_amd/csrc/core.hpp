@@ -98,6 +98,8 @@ struct Plan {
 Plan make_plan(const Request& rq, const llama_copy_options* opt);
 
 constexpr uint32_t kPlanNoDirect = LLAMA_COPY_NO_DIRECT;
+constexpr uint32_t kPlanNoSplit = LLAMA_COPY_NO_SPLIT;
+constexpr uint32_t kCopyFlags = LLAMA_COPY_NO_DIRECT | LLAMA_COPY_NO_SPLIT; // every defined bit
 
 // kernels.hip
 void launch(const Plan& p, void* stream);

@@ -40,13 +40,23 @@ struct TileSide {
 struct TileEntry {
     uint64_t src_addr; // field-major source: device address of the leaf's values (blob + base); 0 for a gap
     uint64_t dst_addr; // field-major destination: device address of the leaf's values
-    uint32_t src_pos;  // LDS byte of record 0 in the source region (region offset and 16-byte phase included)
+    uint32_t src_pos;  // LDS byte of record 0 in the source region (region offset and 16-byte phase
+                       // included); with kTileDirectLoad, the leaf's first granule slot
     uint32_t dst_pos;  // LDS byte of record 0 in the destination region
     uint32_t size;     // bytes per record
-    uint32_t move;     // bits 0-2: log2 of the move width (1 .. 16 bytes); bits 4-7: first loading
-                       // wave of this leaf's source span; bits 8-19: first storing thread of this
-                       // leaf's destination span; bit 31: gap (write zeros)
+    uint32_t move;     // bits 0-2: log2 of the move width (1 .. 16 bytes); bit 3: split move
+                       // (kMoveSplit); bits 4-7: first loading wave of this leaf's source span;
+                       // bits 8-19: first storing thread of this leaf's destination span;
+                       // bits 20-22: log2 of the read alignment; bits 24-26: log2 of the write
+                       // alignment; bit 31: gap (write zeros)
 };
+
+// A leaf of 2, 4 or 8 bytes whose source or destination positions are aligned
+// to less than 4 bytes (a packed record of odd size): each value is read
+// whole (from the 4-byte words that hold it, when the source is misaligned)
+// and written in pieces of the destination's alignment, instead of moving
+// every byte on its own.
+constexpr uint32_t kMoveSplit = 1u << 3;
 
 struct TileHeader {
     uint64_t n;         // records with values
@@ -56,8 +66,8 @@ struct TileHeader {
     uint32_t num_leaves;
     uint32_t num_entries; // leaves, then gaps
     uint32_t lds_bytes;
-    uint32_t flags;       // kTileDirectStore
-    uint32_t pad;
+    uint32_t flags;       // kTileDirectStore, kTileDirectLoad
+    uint32_t slots;       // kTileDirectLoad: granule slots of a tile (a multiple of 64)
     TileSide src, dst;
 };
 
@@ -66,6 +76,16 @@ struct TileHeader {
 // values of one leaf, gathered straight from the source region into registers
 // and stored; the tile needs no destination region in LDS.
 constexpr uint32_t kTileDirectStore = 1;
+
+// Source field-major with 16-byte aligned leaf spans and leaf sizes of 4, 8
+// or 16 bytes: every thread loads its granules of the source spans into
+// registers (all loads of the tile in flight at once) and writes the values to
+// their destination positions in LDS; the tile needs no source region.  Leaf f
+// owns slots [src_pos, src_pos + 64 * ceil(G_f / 64)) of the tile's granule
+// slots (G_f granules of 16 bytes), so each wave's slot lies in one leaf;
+// thread t takes slots t + j * threads, j < kDirectLoadSlots.
+constexpr uint32_t kTileDirectLoad = 2;
+constexpr uint32_t kDirectLoadSlots = 8;
 
 struct TileArgs {
     TileHeader h;

@@ -142,6 +142,75 @@ __device__ __forceinline__ void move4(uint8_t* lds, uint32_t sp, uint32_t dp, co
     }
 }
 
+// A value of T (2, 4 or 8 bytes) at LDS byte p aligned to 2^rd bytes: read
+// whole when rd allows, else assembled from the aligned 4-byte words that hold
+// it (funnel shifts).  The words may reach up to 4 bytes past the value; in a
+// staged tile the destination region follows the source region, so the read
+// stays inside the workgroup's LDS, and the extra bytes are shifted out.
+template <typename T>
+__device__ __forceinline__ T read_split(const uint8_t* lds, uint32_t p, uint32_t rd)
+{
+    if ((1u << rd) >= sizeof(T))
+        return *(const T*)(lds + p);
+    const uint32_t* w = (const uint32_t*)(lds + (p & ~3u));
+    const uint32_t sh = (p & 3u) * 8u;
+    const uint32_t w0 = w[0], w1 = w[1];
+    const uint32_t lo = uint32_t(((uint64_t(w1) << 32) | w0) >> sh);
+    if constexpr (sizeof(T) == 8) {
+        const uint32_t w2 = w[2];
+        const uint32_t hi = uint32_t(((uint64_t(w2) << 32) | w1) >> sh);
+        return T((uint64_t(hi) << 32) | lo);
+    } else {
+        return T(lo);
+    }
+}
+
+// Writes a value of T at LDS byte p aligned to 2^wr bytes, in pieces of that
+// alignment (at most sizeof(T)).
+template <typename T>
+__device__ __forceinline__ void write_split(uint8_t* lds, uint32_t p, T v, uint32_t wr)
+{
+    const uint64_t x = uint64_t(v);
+    if ((1u << wr) >= sizeof(T)) {
+        *(T*)(lds + p) = v;
+    } else if (wr == 2) {
+        *(uint32_t*)(lds + p) = uint32_t(x);
+        *(uint32_t*)(lds + p + 4) = uint32_t(x >> 32);
+    } else if (wr == 1) {
+#pragma unroll
+        for (uint32_t k = 0; k < sizeof(T); k += 2)
+            *(uint16_t*)(lds + p + k) = uint16_t(x >> (8 * k));
+    } else {
+#pragma unroll
+        for (uint32_t k = 0; k < sizeof(T); k++)
+            lds[p + k] = uint8_t(x >> (8 * k));
+    }
+}
+
+// move4 for a split entry (kMoveSplit): the values are sizeof(T) bytes, read
+// at alignment 2^rd and written at alignment 2^wr.
+template <typename T>
+__device__ __forceinline__ void move4_split(uint8_t* lds, uint32_t sp, uint32_t dp, const TileSide& s,
+                                            const TileSide& d, uint32_t r0, uint32_t step, uint32_t nv, uint32_t nd,
+                                            uint32_t rd, uint32_t wr)
+{
+    constexpr uint32_t size = sizeof(T);
+    T v[4];
+#pragma unroll
+    for (uint32_t j = 0; j < 4; j++) {
+        const uint32_t r = r0 + j * step;
+        v[j] = T{};
+        if (r < nv)
+            v[j] = read_split<T>(lds, sp + (r >> s.pos_lg) * s.pos_k + (r & s.pos_m) * size, rd);
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < 4; j++) {
+        const uint32_t r = r0 + j * step;
+        if (r < nd)
+            write_split<T>(lds, dp + (r >> d.pos_lg) * d.pos_k + (r & d.pos_m) * size, v[j], wr);
+    }
+}
+
 // Reads value r of an entry from the source region (ld = log2 of its size).
 template <typename T>
 __device__ __forceinline__ T src_value(const uint8_t* lds, uint32_t sp, const TileSide& s, uint32_t r, uint32_t size)
@@ -171,8 +240,83 @@ __device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t s
         if (r0 + per <= nd) {
             *(GLOBAL u32x4*)(gdst + uint64_t(g) * 16u) = u.v;
         } else {
-            for (uint32_t j = 0; r0 + j < nd; j++)
-                *(GLOBAL T*)(gdst + uint64_t(g) * 16u + j * sizeof(T)) = u.t[j];
+#pragma unroll
+            for (uint32_t j = 0; j < per; j++)
+                if (r0 + j < nd)
+                    *(GLOBAL T*)(gdst + uint64_t(g) * 16u + j * sizeof(T)) = u.t[j];
+        }
+    }
+}
+
+// Direct load of a tile from a field-major source (leaf sizes 4, 8 or 16
+// bytes): every thread loads its slots' granules into registers (all loads in
+// flight together), then writes the values to the destination region.
+// Records in [nv, nd) (AoSoA lanes past the last record) and gap entries are
+// zero-filled.
+template <typename Entries>
+__device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries ent, uint64_t i0, uint32_t nv,
+                                                 uint32_t nd, uint8_t* lds)
+{
+    const uint32_t tid = threadIdx.x, nthr = blockDim.x, wave = wave_id(), lane = tid & 63u;
+    u32x4 v[kDirectLoadSlots];
+    // slot of (wave, j): q = wave * 64 + j * nthr + lane; its leaf is uniform
+#pragma unroll
+    for (uint32_t j = 0; j < kDirectLoadSlots; j++) {
+        const uint32_t q0 = uniform(wave * 64u + j * nthr);
+        if (q0 >= h.slots)
+            break;
+        uint32_t f = 0;
+        while (f + 1 < h.num_leaves && ent(f + 1).src_pos <= q0)
+            f++;
+        const auto& e = ent(f);
+        const uint32_t g = q0 + lane - e.src_pos; // granule within the leaf's span
+        if (g * 16u < nv * e.size)
+            v[j] = *(const GLOBAL u32x4*)(field_span_start(e.src_addr, h.src, i0, e.size) + uint64_t(g) * 16u);
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kDirectLoadSlots; j++) {
+        const uint32_t q0 = uniform(wave * 64u + j * nthr);
+        if (q0 >= h.slots)
+            break;
+        uint32_t f = 0;
+        while (f + 1 < h.num_leaves && ent(f + 1).src_pos <= q0)
+            f++;
+        const auto& e = ent(f);
+        const uint32_t g = q0 + lane - e.src_pos;
+        const uint32_t size = e.size; // 4, 8 or 16
+        const uint32_t per = 16u / size;
+        const uint32_t r0 = g * per;
+        if (g * 16u >= nv * size)
+            continue;
+        const uint32_t d0 = e.dst_pos + (r0 >> h.dst.pos_lg) * h.dst.pos_k + (r0 & h.dst.pos_m) * size;
+        if (size == 16) {
+            *(u32x4*)(lds + d0) = v[j];
+        } else if (size == 8) {
+            *(uint2*)(lds + d0) = uint2{v[j].x, v[j].y};
+            if (r0 + 1 < nv) {
+                const uint32_t r = r0 + 1;
+                *(uint2*)(lds + e.dst_pos + (r >> h.dst.pos_lg) * h.dst.pos_k + (r & h.dst.pos_m) * 8u) =
+                    uint2{v[j].z, v[j].w};
+            }
+        } else {
+            const uint32_t w[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
+#pragma unroll
+            for (uint32_t k = 0; k < 4; k++) {
+                const uint32_t r = r0 + k;
+                if (r < nv)
+                    *(uint32_t*)(lds + e.dst_pos + (r >> h.dst.pos_lg) * h.dst.pos_k + (r & h.dst.pos_m) * 4u) = w[k];
+            }
+        }
+    }
+    // zeros: every gap entry, and every leaf for records in [nv, nd)
+    for (uint32_t k = 0; k < h.num_entries; k++) {
+        const auto& e = ent(k);
+        const bool gap = (e.move >> 31) != 0;
+        const uint32_t first = gap ? 0u : nv;
+        for (uint32_t r = first + tid; r < nd; r += nthr) {
+            const uint32_t dp = e.dst_pos + (r >> h.dst.pos_lg) * h.dst.pos_k + (r & h.dst.pos_m) * e.size;
+            for (uint32_t b = 0; b < e.size; b++)
+                lds[dp + b] = 0;
         }
     }
 }
@@ -181,9 +325,16 @@ __device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t s
 // LDS, then all threads move the values to their destination positions
 // inside LDS, then all threads store the destination span(s).  `ent(k)`
 // returns entry k (kernel arguments for one copy, the work table for a batch).
-template <typename Entries>
+// Kernel variants: kModeAny dispatches on the plan's flags at run time (the
+// batch kernel); the single-copy kernel is compiled once per mode so that each
+// mode gets its own register allocation.
+enum : uint32_t { kModeAny = 0, kModeStaged = 1, kModeDirectStore = 2, kModeDirectLoad = 3 };
+
+template <uint32_t Mode, typename Entries>
 __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint64_t t, uint8_t* lds)
 {
+    const bool dload = Mode == kModeDirectLoad || (Mode == kModeAny && (h.flags & kTileDirectLoad));
+    const bool dstore = Mode == kModeDirectStore || (Mode == kModeAny && (h.flags & kTileDirectStore));
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
     const uint32_t lane = tid & 63u, wave = wave_id(), nwaves = nthr >> 6;
     const uint32_t lds_base = uint32_t(uintptr_t((lds_void_t*)lds));
@@ -193,7 +344,9 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     const uint32_t nd = uint32_t(min<uint64_t>(T, h.npad - i0));              // records the destination spans
 
     // ---- 1. source span(s) -> LDS
-    if (nv > 0) {
+    if (dload) {
+        direct_load_tile(h, ent, i0, nv, nd, lds);
+    } else if (nv > 0) {
         if (h.src.mode == kRecordMajor) {
             const uint32_t len = uint32_t(((uint64_t(nv) + h.src.lanes - 1) >> h.src.log2_lanes) * h.src.block);
             load_span(h.src.span_base + t * h.src.tile_bytes, len, h.src.lds_base, wave, nwaves, 0, lane, lds_base);
@@ -208,7 +361,22 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
-    if (h.flags & kTileDirectStore) {
+    if (dload) {
+        // ---- 2''. the destination region is complete: store it
+        if (h.dst.mode == kRecordMajor) {
+            const uint32_t len = uint32_t(((uint64_t(nd) + h.dst.lanes - 1) >> h.dst.log2_lanes) * h.dst.block);
+            store_span(h.dst.span_base + t * h.dst.tile_bytes, len, h.dst.lds_base, tid, nthr, 0, lds);
+        } else {
+            for (uint32_t f = 0; f < h.num_leaves; f++) {
+                const auto& e = ent(f);
+                store_span(field_span_start(e.dst_addr, h.dst, i0, e.size), nd * e.size, e.dst_pos & ~15u, tid,
+                           nthr, (e.move >> 8) & 4095u, lds);
+            }
+        }
+        return;
+    }
+
+    if (dstore) {
         // ---- 2'. gather each destination granule from the source region and
         //          store it; no destination region, no second barrier
         for (uint32_t f = 0; f < h.num_leaves; f++) {
@@ -231,6 +399,17 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     for (uint32_t k = 0; k < h.num_entries; k++) {
         const auto& e = ent(k);
         const bool gap = (e.move >> 31) != 0;
+        if (e.move & kMoveSplit) {
+            const uint32_t rd = (e.move >> 20) & 7u, wr = (e.move >> 24) & 7u;
+            for (uint32_t r0 = tid; r0 < nd; r0 += 4u * nthr) {
+                switch (e.size) {
+                case 2: move4_split<uint16_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, r0, nthr, nv, nd, rd, wr); break;
+                case 4: move4_split<uint32_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, r0, nthr, nv, nd, rd, wr); break;
+                default: move4_split<uint64_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, r0, nthr, nv, nd, rd, wr); break;
+                }
+            }
+            continue;
+        }
         for (uint32_t r0 = tid; r0 < nd; r0 += 4u * nthr) {
             switch (e.move & 7u) {
             case 4: move4<u32x4>(lds, e.src_pos, e.dst_pos, h.src, h.dst, e.size, r0, nthr, nv, nd, gap); break;
@@ -256,12 +435,13 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     }
 }
 
+template <uint32_t Mode>
 __global__ void __launch_bounds__(1024) tile_kernel(const TileArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     auto ent = [&](uint32_t k) -> const TileEntry& { return a.e[k]; };
     for (uint64_t t = blockIdx.x; t < a.h.num_tiles; t += gridDim.x) {
-        tile_body(a.h, ent, t, lds);
+        tile_body<Mode>(a.h, ent, t, lds);
         if (t + gridDim.x < a.h.num_tiles)
             __syncthreads();
     }
@@ -352,43 +532,56 @@ __global__ void __launch_bounds__(1024) stream_kernel(const StreamArgs a)
 // ---------------------------------------------------------------------------
 
 // Persistent kernel over the work units of many copies.  Each workgroup takes
-// the next unit from an atomic counter until the counter passes the total;
-// the last workgroup to finish puts both counters back to zero, so the next
-// launch (a graph replay included) starts from zero without a memset.
+// a block of consecutive units from an atomic counter (an eighth of the
+// remaining units per workgroup, between 1 and 64, so that blocks shrink
+// towards the end) until the counter passes the total; the last workgroup to
+// finish puts both counters back to zero, so the next launch (a graph replay
+// included) starts from zero without a memset.
 __global__ void __launch_bounds__(1024) batch_kernel(const BatchArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    __shared__ unsigned long long next_unit;
+    __shared__ unsigned long long block_first, block_count;
+    const CONSTANT uint64_t* begin = (const CONSTANT uint64_t*)a.unit_begin;
+    uint64_t seen = 0; // thread 0: the counter after its last block
     for (;;) {
-        if (threadIdx.x == 0)
-            next_unit = atomicAdd(&a.counters[0], 1ull);
+        if (threadIdx.x == 0) {
+            const uint64_t remaining = a.total_units > seen ? a.total_units - seen : 0;
+            const uint64_t want = min<uint64_t>(max<uint64_t>(remaining / (8ull * gridDim.x), 1ull), 64ull);
+            block_first = atomicAdd(&a.counters[0], (unsigned long long)want);
+            block_count = want;
+            seen = block_first + want;
+        }
         __syncthreads();
-        const uint64_t g = __builtin_amdgcn_readfirstlane(uint32_t(next_unit)) |
-                           (uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(next_unit >> 32))) << 32);
+        const uint64_t g0 = __builtin_amdgcn_readfirstlane(uint32_t(block_first)) |
+                            (uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(block_first >> 32))) << 32);
+        const uint64_t g1 = min<uint64_t>(g0 + __builtin_amdgcn_readfirstlane(uint32_t(block_count)), a.total_units);
         __syncthreads();
-        if (g >= a.total_units)
+        if (g0 >= a.total_units)
             break;
-        // item j: unit_begin[j] <= g < unit_begin[j + 1]
-        const CONSTANT uint64_t* begin = (const CONSTANT uint64_t*)a.unit_begin;
+        // item j: begin[j] <= g < begin[j + 1]
         uint32_t lo = 0, hi = a.num_items;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (begin[mid] <= g)
+            if (begin[mid] <= g0)
                 lo = mid;
             else
                 hi = mid;
         }
-        const CONSTANT BatchItem* it = (const CONSTANT BatchItem*)a.items + lo;
-        const uint64_t u = g - begin[lo];
-        if (it->kind == kItemTile) {
-            const TileHeader h = load_const(&it->h);
-            const CONSTANT TileEntry* entries = (const CONSTANT TileEntry*)a.entries + it->first;
-            tile_body(h, [&](uint32_t k) -> const CONSTANT TileEntry& { return entries[k]; }, u, lds);
-        } else {
-            const CONSTANT StreamRun* runs = (const CONSTANT StreamRun*)a.runs + it->first;
-            stream_unit([&](uint32_t k) -> const CONSTANT StreamRun& { return runs[k]; }, it->count, u);
+        for (uint64_t g = g0; g < g1; g++) {
+            while (begin[lo + 1] <= g)
+                lo++;
+            const CONSTANT BatchItem* it = (const CONSTANT BatchItem*)a.items + lo;
+            const uint64_t u = g - begin[lo];
+            if (it->kind == kItemTile) {
+                const TileHeader h = load_const(&it->h);
+                const CONSTANT TileEntry* entries = (const CONSTANT TileEntry*)a.entries + it->first;
+                tile_body<kModeAny>(h, [&](uint32_t k) -> const CONSTANT TileEntry& { return entries[k]; }, u, lds);
+            } else {
+                const CONSTANT StreamRun* runs = (const CONSTANT StreamRun*)a.runs + it->first;
+                stream_unit([&](uint32_t k) -> const CONSTANT StreamRun& { return runs[k]; }, it->count, u);
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -486,9 +679,10 @@ void set_attributes()
 {
     if (g_attr_set)
         return;
-    check_hip(hipFuncSetAttribute((const void*)tile_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  int(kHardLdsBytes)),
-              "hipFuncSetAttribute(tile_kernel)");
+    for (const void* k : {(const void*)tile_kernel<kModeStaged>, (const void*)tile_kernel<kModeDirectStore>,
+                          (const void*)tile_kernel<kModeDirectLoad>})
+        check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes)),
+                  "hipFuncSetAttribute(tile_kernel)");
     check_hip(hipFuncSetAttribute((const void*)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   int(kHardLdsBytes - 64)),
               "hipFuncSetAttribute(batch_kernel)");
@@ -529,7 +723,15 @@ void launch(const Plan& p, void* stream_ptr)
     switch (p.path) {
     case LLAMA_PATH_TILE:
         set_attributes();
-        hipLaunchKernelGGL(tile_kernel, dim3(grid), dim3(p.threads), p.tile.h.lds_bytes, stream, p.tile);
+        if (p.tile.h.flags & kTileDirectLoad)
+            hipLaunchKernelGGL(tile_kernel<kModeDirectLoad>, dim3(grid), dim3(p.threads), p.tile.h.lds_bytes, stream,
+                               p.tile);
+        else if (p.tile.h.flags & kTileDirectStore)
+            hipLaunchKernelGGL(tile_kernel<kModeDirectStore>, dim3(grid), dim3(p.threads), p.tile.h.lds_bytes,
+                               stream, p.tile);
+        else
+            hipLaunchKernelGGL(tile_kernel<kModeStaged>, dim3(grid), dim3(p.threads), p.tile.h.lds_bytes, stream,
+                               p.tile);
         break;
     case LLAMA_PATH_STREAM:
         hipLaunchKernelGGL(stream_kernel, dim3(grid), dim3(p.threads), 0, stream, p.stream);

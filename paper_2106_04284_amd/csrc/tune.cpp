@@ -187,13 +187,21 @@ void autotune(const Request& rq, void* stream_ptr, int reps, llama_copy_options&
     for (uint32_t T = 16; T <= 4096; T *= 2)
         for (uint32_t th : {64u, 128u, 256u})
             if (T / 4 <= 4 * th && T >= th / 4)
-                cands.push_back({LLAMA_PATH_TILE, T, th, 0, 0});
+                for (uint32_t flags : {0u, LLAMA_COPY_NO_DIRECT})
+                    cands.push_back({LLAMA_PATH_TILE, T, th, 0, flags});
     for (const llama_copy_options& c : cands) {
         Plan p;
         try {
             p = make_plan(rq, &c);
         } catch (const Error&) {
             continue; // candidate does not apply (no long runs, too large for LDS)
+        }
+        // the staged variant of a plan that uses no direct mode is the same plan
+        if ((c.flags & LLAMA_COPY_NO_DIRECT) && p.path == LLAMA_PATH_TILE) {
+            llama_copy_options d = c;
+            d.flags = 0;
+            if (!(make_plan(rq, &d).tile.h.flags & (kTileDirectStore | kTileDirectLoad)))
+                continue;
         }
         if (run_and_hash(rq, p, stream, 0x5A) != want)
             fail(LLAMA_E_HIP, "autotune: a candidate plan wrote different bytes than the default plan");
@@ -221,13 +229,13 @@ void tune_save(const char* path)
     if (!f)
         fail(LLAMA_E_INVALID_ARG, std::string("cannot write ") + path);
     f << "# llama_mi355x tuning cache: leaves src_kind src_lanes dst_kind dst_lanes bucket path tile threads "
-         "wg_per_cu gbs\n";
+         "wg_per_cu flags gbs\n";
     for (const auto& kv : g_tune) {
         const TuneKey& k = kv.first;
         const TuneValue& v = kv.second;
         f << std::hex << k.leaves << std::dec << ' ' << k.src_kind << ' ' << k.src_lanes << ' ' << k.dst_kind << ' '
           << k.dst_lanes << ' ' << k.bucket << ' ' << v.opt.path << ' ' << v.opt.tile_records << ' ' << v.opt.threads
-          << ' ' << v.opt.wg_per_cu << ' ' << v.gbs << '\n';
+          << ' ' << v.opt.wg_per_cu << ' ' << v.opt.flags << ' ' << v.gbs << '\n';
     }
     if (!f)
         fail(LLAMA_E_INVALID_ARG, std::string("cannot write ") + path);
@@ -243,14 +251,23 @@ uint32_t tune_load(const char* path)
     while (std::getline(f, line)) {
         if (line.empty() || line[0] == '#')
             continue;
+        {
+            std::istringstream count(line);
+            std::string tok;
+            int fields = 0;
+            while (count >> tok)
+                fields++;
+            if (fields != 12)
+                fail(LLAMA_E_INVALID_ARG, std::string("tuning cache line needs 12 fields in ") + path + ": " + line);
+        }
         std::istringstream in(line);
         TuneKey k{};
         TuneValue v{};
         in >> std::hex >> k.leaves >> std::dec >> k.src_kind >> k.src_lanes >> k.dst_kind >> k.dst_lanes >> k.bucket >>
-            v.opt.path >> v.opt.tile_records >> v.opt.threads >> v.opt.wg_per_cu >> v.gbs;
+            v.opt.path >> v.opt.tile_records >> v.opt.threads >> v.opt.wg_per_cu >> v.opt.flags >> v.gbs;
         if (!in)
             fail(LLAMA_E_INVALID_ARG, std::string("malformed tuning cache line in ") + path + ": " + line);
-        if (v.opt.path > LLAMA_PATH_NAIVE || v.opt.threads % 64 || v.opt.threads > 1024 || v.opt.wg_per_cu > 16 ||
+        if (v.opt.path > LLAMA_PATH_NAIVE || (v.opt.flags & ~kCopyFlags) || v.opt.threads % 64 || v.opt.threads > 1024 || v.opt.wg_per_cu > 16 ||
             (v.opt.tile_records && (v.opt.tile_records < 16 || v.opt.tile_records > 4096 ||
                                     (v.opt.tile_records & (v.opt.tile_records - 1)))))
             fail(LLAMA_E_INVALID_ARG, std::string("invalid parameters in tuning cache line: ") + line);

@@ -288,6 +288,7 @@ def _stream(stream):
 
 
 COPY_NO_DIRECT = 1
+COPY_NO_SPLIT = 2
 
 
 def _options(path=PATH_AUTO, tile_records=0, threads=0, wg_per_cu=0, flags=0):

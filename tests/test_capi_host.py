@@ -217,14 +217,15 @@ def test_tuning_cache_file_round_trip(tmp_path):
     L.tune_save(str(path))
     assert [ln for ln in path.read_text().splitlines() if not ln.startswith("#")] == []
     probe = tmp_path / "probe.txt"
-    probe.write_text("0 0 0 3 0 20 2 64 192 0 1.0\n")
+    probe.write_text("0 0 0 3 0 20 2 64 192 0 1 1.0\n")
     assert L.tune_load(str(probe)) == 1
     L.tune_save(str(path))
-    assert "0 0 0 3 0 20 2 64 192 0 1" in path.read_text()
+    assert "0 0 0 3 0 20 2 64 192 0 1 1" in path.read_text()
     assert L.plan(a, b) == default and L.tune_lookup(a, b) is None
     L.tune_clear()
-    for bad in ("garbage\n", "0 0 0 3 0 20 2 63 192 0 1.0\n", "0 0 0 3 0 20 2 64 100 0 1.0\n",
-                "0 0 0 3 0 20 9 64 192 0 1.0\n"):
+    for bad in ("garbage\n", "0 0 0 3 0 20 2 63 192 0 0 1.0\n", "0 0 0 3 0 20 2 64 100 0 0 1.0\n",
+                "0 0 0 3 0 20 9 64 192 0 0 1.0\n", "0 0 0 3 0 20 2 64 192 0 4 1.0\n",
+                "0 0 0 3 0 20 2 64 192 0 1.0\n"):
         probe.write_text(bad)
         with pytest.raises(L.LlamaError):
             L.tune_load(str(probe))

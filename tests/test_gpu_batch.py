@@ -97,6 +97,7 @@ def test_batch_equals_lone_copies(L, orc):
 def test_batch_options(L, orc, opts):
     items, want = make_items(L, orc, 5, count=20, nmax=8000)
     b = L.Batch(items, **opts)
+    torch.cuda.synchronize()  # inputs were written on the default stream
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         b.launch()

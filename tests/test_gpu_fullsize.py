@@ -132,11 +132,18 @@ def test_batch_1000_arrays(L, orc, threads):
     for it in items:
         for t in it[3]:
             t.fill_(0xFF)
+    torch.cuda.synchronize()  # the fills run on the default stream, the batch on `stream`
     b.launch(stream)  # graph replay
     torch.cuda.synchronize()
-    for f, it in zip(first, items):
-        for x, y in zip(f, it[3]):
-            assert torch.equal(x, y)
+    bad_items = []
+    for k, (f, it) in enumerate(zip(first, items)):
+        for j, (x, y) in enumerate(zip(f, it[3])):
+            if not torch.equal(x, y):
+                diff = torch.nonzero(x != y).flatten()
+                bad_items.append(f"item {k} {items_spec[k]} blob {j}: {diff.numel()} of {x.numel()} bytes differ "
+                                 f"between the runs, first at {int(diff[0])} (run 1 {int(x[diff[0]])}, run 2 "
+                                 f"{int(y[diff[0]])}); plan {L.plan(it[0], it[2], threads=threads)}")
+    assert not bad_items, "\n".join(bad_items[:10])
     del first
     g = random.Random(3)
     for k in g.sample(range(len(items)), 40):

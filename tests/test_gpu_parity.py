@@ -146,7 +146,8 @@ def test_oversized_destination_blobs_keep_their_tail(L, orc):
                                   for fl in (0, 1)]
                          + [dict(path="naive"), dict(path="naive", threads=64)])
 @pytest.mark.parametrize("pair", [(("aos_packed", 0), ("soa_single", 0)), (("aosoa", 32), ("soa_multi", 0)),
-                                  (("aos_aligned", 0), ("aosoa", 8)), (("soa_multi", 0), ("soa_single", 0))])
+                                  (("aos_aligned", 0), ("aosoa", 8)), (("soa_multi", 0), ("soa_single", 0)),
+                                  (("soa_multi", 0), ("aos_aligned", 0)), (("soa_single", 0), ("aosoa", 64))])
 def test_kernel_options(L, orc, opts, pair):
     """The result is the same whatever tile, workgroup size or path is used."""
     for name, n in (("particle", 3001), ("mixed", 1500), ("lbm", 300)):
@@ -157,6 +158,23 @@ def test_kernel_options(L, orc, opts, pair):
             assert e.status == L.E_UNSUPPORTED and opts.get("tile_records", 0) >= 512
             continue
         run_case(L, orc, W.RECORDS[name], pair[0], pair[1], [n], seed=n, **opts)
+
+
+SPLIT_PAIRS = [(("aos_packed", 0), b) for b in LAYOUTS if b[0] != "aos_packed"] + \
+              [(a, ("aos_packed", 0)) for a in LAYOUTS if a[0] != "aos_packed"]
+
+
+@pytest.mark.parametrize("pair", SPLIT_PAIRS, ids=[f"{_name(a)}-{_name(b)}" for a, b in SPLIT_PAIRS])
+@pytest.mark.parametrize("offsets", [(0, 0), (1, 2), (3, 1), (2, 3)])
+@pytest.mark.parametrize("flags", [0, 1, 2])
+@pytest.mark.parametrize("name", ["mixed", "listing1"])
+def test_odd_record_sizes(L, orc, pair, offsets, flags, name):
+    """Packed records of odd size (49 and 21 bytes) put 2-, 4- and 8-byte
+    values at every alignment: the split move (reads assembled from aligned
+    words, writes in pieces), the byte-wise move (flags 2) and the staged path
+    (flags 1) give the oracle's bytes at every blob offset."""
+    run_case(L, orc, W.RECORDS[name], pair[0], pair[1], [1031], seed=17, src_off=offsets[0],
+             dst_off=offsets[1], flags=flags)
 
 
 @pytest.mark.parametrize("seed", range(24))

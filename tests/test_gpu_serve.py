@@ -115,6 +115,7 @@ def test_budget_and_dependencies(L, orc):
     x = torch.randint(0, 255, (n * 28,), dtype=torch.uint8, device="cuda")
     y = b.alloc(fill=0)
     z = c.alloc(fill=0)
+    torch.cuda.synchronize()  # the server's streams do not wait for the default stream
     srv = L.Server(4 * n * 28)
     with pytest.raises(L.LlamaError) as e:
         L.Server(100).submit(a, [x], b, y)
