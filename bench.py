@@ -207,13 +207,16 @@ def _tune_classes(L, torch, classes, stream):
             continue
         sb = [torch.empty(s, dtype=torch.uint8, device="cuda").random_(0, 255) for s in ms.blob_sizes()]
         db = md.alloc()
+        torch.cuda.synchronize()  # the fills ran on torch's stream
         L.autotune(ms, sb, md, db, stream=stream, reps=2)
         tuned += 1
         del sb, db
     return tuned
 
 
-def bench_batch(L, torch, args, dev, stream):
+def _batch_items(L, torch, stream):
+    """The 1,000 arrays of the batching workload, sources filled with random
+    bytes, and the autotuned record/pair classes."""
     items_spec = W.batch_items()
     log(f"batch: allocating {len(items_spec)} arrays")
     cache, items = {}, []
@@ -227,19 +230,30 @@ def bench_batch(L, torch, args, dev, stream):
     torch.cuda.synchronize()
     log(f"batch: {total / 1e9:.1f} GB read+written per pass; autotuning the record/pair classes")
     tuned = _tune_classes(L, torch, {(it["record"], it["src"], it["dst"]) for it in items_spec}, stream)
+    return items, total, tuned
+
+
+def _timed(torch, stream, fn, reps):
+    """Median and minimum milliseconds of `fn` over `reps` runs after one
+    warm-up, with HIP events on `stream`."""
+    fn()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    return statistics.median(ms), min(ms)
+
+
+def bench_batch(L, torch, args, dev, stream):
+    items, total, tuned = _batch_items(L, torch, stream)
 
     def timed(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        ms = []
-        for _ in range(reps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            fn()
-            e1.record(stream)
-            e1.synchronize()
-            ms.append(e0.elapsed_time(e1))
-        return statistics.median(ms), min(ms)
+        return _timed(torch, stream, fn, reps)
 
     best = None
     for th in (128, 256):
@@ -260,7 +274,7 @@ def bench_batch(L, torch, args, dev, stream):
             "vs_baseline": None, "dtype": "u32", "data": "synthetic",
             "config": {"workload": "batching: 1,000 arrays, record counts log-uniform 1e3..1e7, particle or mixed "
                                    "{f64[3],f32[4],i32[2],u8} record, random ordered layout pair of 42; one "
-                                   "persistent hipGraph-captured launch",
+                                   "hipGraph-captured launch",
                        "bytes_per_step": total, "arrays": len(items), "threads": th, "work_units": info["work_units"],
                        "workgroups": info["workgroups"], "tuned_classes": tuned},
             "hbm_peak_frac": round(gbs / HBM_PEAK_GBS, 4),
@@ -272,14 +286,10 @@ def bench_batch(L, torch, args, dev, stream):
             "device": dev.name}
 
 
-def bench_serve(L, torch, args, dev):
-    """Poisson requests replayed against the server with three policies:
-    continuous batching, one naive kernel per request, one llama_copy per
-    request.  Arrival rate: rho times the batched throughput measured on a
-    calibration trace."""
-    import time as _t
+def _serve_setup(L, torch, count, warm=200):
+    """The serving trace: warm + count requests whose blobs lie in one device
+    arena used as a ring (132 GB), and the autotuned record/pair classes."""
     budget = 64 * 10**9
-    warm, count = 200, args.requests
     trace = W.poisson_trace(W.BASE_SEED + 5, 1000.0, warm + count)
     S = {"particle": 28, "mixed": 49}
     arena_bytes = 2 * budget + 4 * 10**9
@@ -304,58 +314,93 @@ def bench_serve(L, torch, args, dev):
     log(f"serve: {len(reqs)} requests, {sum(r['bytes'] for r in reqs) / 1e9:.0f} GB in total")
     _tune_classes(L, torch, {(r["record"], r["src"], r["dst"]) for r in trace}, torch.cuda.current_stream())
 
-    def run(policy, rate):
-        srv = L.Server(budget, policy=policy)
-        tickets, done = [], {}
-        t0 = _t.perf_counter()
-        base = trace[0]["t"]
-        # arena regions in allocation order: the ring reuses the oldest first;
-        # a region of the previous lap is retired when the new one overlaps
-        # it, anything older at once
-        users = collections.deque()
-        for k, r in enumerate(reqs):
-            due = t0 + (trace[k]["t"] - base) * (1000.0 / rate)
-            while _t.perf_counter() < due:
-                pass
-            while users and (users[0][3] < r["lap"] - 1 or (users[0][1] < r["hi"] and r["lo"] < users[0][2])):
-                j = users.popleft()[0]
-                if j not in done:
-                    done[j] = srv.wait(tickets[j])
-            tickets.append(srv.submit(r["ms"], r["sb"], r["md"], r["db"]))
-            users.append((k, r["lo"], r["hi"], r["lap"]))
-            if k == warm - 1:
-                t_meas = _t.perf_counter()
-        for j, t in enumerate(tickets):
-            if j not in done:
-                done[j] = srv.wait(t)
-        t_end = _t.perf_counter()
-        st = srv.stats()
-        srv.close()
-        lat = sorted(done[j][1] for j in range(warm, len(reqs)))
-        measured = sum(reqs[j]["bytes"] for j in range(warm, len(reqs)))
-        return {"gbs": round(measured / (t_end - t_meas) / 1e9, 1),
-                "p50_ms": round(1e3 * lat[len(lat) // 2], 3),
-                "p99_ms": round(1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))], 3),
-                "launches": st["launches"], "mean_batch": round(st["mean_batch"], 2),
-                "max_inflight_gb": round(st["max_inflight_bytes"] / 1e9, 2),
-                "failed": st["failed"]}
+    return {"reqs": reqs, "trace": trace, "warm": warm, "budget": budget, "arena": arena}
 
-    # calibration: everything submitted at once measures the batched throughput
-    calib = run(0, 1e9)
+
+def _serve_run(L, setup, policy, rate, **server_options):
+    """Replays the trace against a new server at `rate` requests per second."""
+    import time as _t
+    reqs, trace, warm, budget = setup["reqs"], setup["trace"], setup["warm"], setup["budget"]
+    srv = L.Server(budget, policy=policy, **server_options)
+    tickets, done = [], {}
+    t0 = _t.perf_counter()
+    base = trace[0]["t"]
+    # arena regions in allocation order: the ring reuses the oldest first;
+    # a region of the previous lap is retired when the new one overlaps
+    # it, anything older at once
+    users = collections.deque()
+    for k, r in enumerate(reqs):
+        due = t0 + (trace[k]["t"] - base) * (1000.0 / rate)
+        while _t.perf_counter() < due:
+            pass
+        while users and (users[0][3] < r["lap"] - 1 or (users[0][1] < r["hi"] and r["lo"] < users[0][2])):
+            j = users.popleft()[0]
+            if j not in done:
+                done[j] = srv.wait(tickets[j])
+        tickets.append(srv.submit(r["ms"], r["sb"], r["md"], r["db"]))
+        users.append((k, r["lo"], r["hi"], r["lap"]))
+        if k == warm - 1:
+            t_meas = _t.perf_counter()
+    for j, t in enumerate(tickets):
+        if j not in done:
+            done[j] = srv.wait(t)
+    t_end = _t.perf_counter()
+    st = srv.stats()
+    srv.close()
+    lat = sorted(done[j][1] for j in range(warm, len(reqs)))
+    measured = sum(reqs[j]["bytes"] for j in range(warm, len(reqs)))
+    return {"gbs": round(measured / (t_end - t_meas) / 1e9, 1),
+            "p50_ms": round(1e3 * lat[len(lat) // 2], 3),
+            "p99_ms": round(1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))], 3),
+            "launches": st["launches"], "mean_batch": round(st["mean_batch"], 2),
+            "max_inflight_gb": round(st["max_inflight_bytes"] / 1e9, 2),
+            "failed": st["failed"]}
+
+
+def bench_serve(L, torch, args, dev):
+    """Poisson requests replayed against the server with three policies:
+    continuous batching, one naive kernel per request, one llama_copy per
+    request.  Arrival rate: rho (0.5 and 0.8) times the GB/s of the batching
+    workload's single launch, measured first in the same process."""
+    import time as _t
+    stream = torch.cuda.current_stream()
+    items, total, _ = _batch_items(L, torch, stream)
+    b = L.Batch(items)
+    med, _ = _timed(torch, stream, lambda: b.launch(stream), 3)
+    batch_gbs = total / (med * 1e-3) / 1e9
+    b.close()
+    del items, b
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log(f"serve: batching workload runs at {batch_gbs:.1f} GB/s; it sets the arrival rates")
+    setup = _serve_setup(L, torch, args.requests)
+    reqs, warm, count = setup["reqs"], setup["warm"], args.requests
+
+    def run(policy, rate):
+        return _serve_run(L, setup, policy, rate)
+
+    # saturation: everything submitted at once measures the server's capacity
+    capacity = run(0, 1e9)
     total_bytes = sum(r["bytes"] for r in reqs[warm:])
     mean_bytes = total_bytes / count
-    rate = args.rho * calib["gbs"] * 1e9 / mean_bytes
-    log(f"serve: batched capacity {calib['gbs']} GB/s; offered load rho={args.rho} -> {rate:.0f} requests/s")
-    out = {name: run(pol, rate) for name, pol in (("batched", 0), ("naive", 1), ("per_request", 2))}
+    log(f"serve: batched server at saturation {capacity['gbs']} GB/s")
+    by_rho = {}
+    for rho in sorted({0.5, args.rho}):
+        rate = rho * batch_gbs * 1e9 / mean_bytes
+        log(f"serve: offered load rho={rho} -> {rate:.0f} requests/s")
+        by_rho[rho] = {"rate_per_s": round(rate, 1), "offered_gbs": round(rho * batch_gbs, 1),
+                       **{name: run(pol, rate) for name, pol in (("batched", 0), ("naive", 1), ("per_request", 2))}}
+    out = by_rho[args.rho]
     return {"metric": METRIC, "value": out["batched"]["gbs"], "unit": "GB/s", "n_gpus": 1, "steps": count,
             "warmup": warm, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "u32", "data": "synthetic",
             "config": {"workload": "serving: Poisson arrivals, payload log-uniform 64 KB..1 GB, particle or mixed "
                                    "record, random ordered layout pair of 42, HBM admission budget 64 GB",
-                       "rho": args.rho, "rate_per_s": round(rate, 1), "requests": count, "warmup_requests": warm,
-                       "mean_request_bytes": round(mean_bytes)},
+                       "rho": args.rho, "rate_per_s": out["rate_per_s"], "requests": count, "warmup_requests": warm,
+                       "mean_request_bytes": round(mean_bytes), "batching_workload_gbs": round(batch_gbs, 1)},
             "p50_ms": out["batched"]["p50_ms"], "p99_ms": out["batched"]["p99_ms"],
-            "extras": {"capacity_gbs": calib["gbs"], **{k: v for k, v in out.items()}},
+            "extras": {"server_saturation_gbs": capacity["gbs"],
+                       **{f"rho_{rho}": v for rho, v in by_rho.items()}},
             "device": dev.name}
 
 

@@ -270,10 +270,11 @@ typedef struct {
 } llama_copy_item;
 
 /* A prepared batch: the items' plans in one device work table, run by one
- * persistent kernel whose workgroups take tiles (and 4 KiB chunks of long
- * runs) from an atomic counter.  The launch is captured into a hipGraph on
- * the first llama_batch_launch on a non-null stream and replayed afterwards.
- * The result equals n separate llama_copy calls.
+ * persistent kernel whose workgroups take blocks of work units (the tiles of
+ * tiled items and the 4 KiB chunks of long-run items) from an atomic counter
+ * in the table.  The launch is captured into a hipGraph on the first
+ * llama_batch_launch on a non-null stream and replayed afterwards.  The
+ * result equals n separate llama_copy calls.
  *  - Validation: every item as in llama_copy; no destination range may
  *    overlap another destination range or any source range of the batch
  *    (items run in no fixed order).
@@ -281,7 +282,12 @@ typedef struct {
  *    blobs stay the caller's and must stay valid while launches are pending.
  *  - Options (may be NULL): tile_records (a fixed tile size for every TILE
  *    item, 0: each item's own), threads (per workgroup, for every item),
- *    wg_per_cu (resident workgroups per compute unit); path and flags must be 0.
+ *    wg_per_cu (workgroups per compute unit, 1 .. 16; 0: as many as LDS and
+ *    wave slots allow, at most 8); path must be 0, flags takes
+ *    LLAMA_COPY_NO_DIRECT and LLAMA_COPY_NO_SPLIT.  Every workgroup reserves
+ *    the largest item's LDS, so without a fixed tile size each tiled item
+ *    takes the largest tile whose plan fits 32 KB of LDS (the tuning cache,
+ *    which is measured on standalone launches, is not used).
  *  - Items whose record does not fit the tiled kernel are refused with
  *    LLAMA_E_UNSUPPORTED.
  *  - A batch belongs to the device that was current at creation.
@@ -297,7 +303,7 @@ typedef struct {
     uint64_t read_bytes;   /* source blob bytes of all items */
     uint64_t write_bytes;  /* destination blob bytes of all items */
     uint32_t threads;      /* threads per workgroup */
-    uint32_t wg_per_cu;    /* resident workgroups per compute unit */
+    uint32_t wg_per_cu;    /* workgroups per compute unit */
     uint32_t workgroups;   /* persistent grid size */
     uint32_t lds_bytes;    /* LDS per workgroup */
 } llama_batch_info;
@@ -323,19 +329,28 @@ int llama_copy_batch(size_t n, const llama_copy_item* items, void* stream);
 
 /* How a server runs admitted requests. */
 typedef enum {
-    LLAMA_SERVE_BATCHED = 0,    /* every admitted group is one launch of the persistent batch kernel */
+    LLAMA_SERVE_BATCHED = 0,    /* every admitted group is one launch of the batch kernel (a group
+                                   of one request is launched as that request's own copy) */
     LLAMA_SERVE_NAIVE = 1,      /* one element-wise (naive) kernel per request, one stream */
     LLAMA_SERVE_PER_REQUEST = 2 /* one llama_copy per request, streams round robin */
 } llama_serve_policy;
 
 typedef struct {
     uint64_t budget_bytes;   /* admission budget: source plus destination blob bytes in flight (> 0) */
+    uint64_t group_bytes;    /* BATCHED: a request of this many bytes or more runs alone (its own
+                                copy with its tuned plan); smaller requests queued together share
+                                one launch of the batch kernel, which takes no further request once
+                                its bytes reach this (0: 8 MiB) */
+    uint64_t stream_bytes;   /* BATCHED: no launch joins a stream that already has this many bytes in
+                                flight, and arrivals gather into larger launches meanwhile
+                                (0: no limit) */
     uint32_t streams;        /* HIP streams whose launches overlap (0: 2; NAIVE: 1); at most 16 */
+    uint32_t depth;          /* launches in flight per stream (0: BATCHED 64, PER_REQUEST 128,
+                                NAIVE 256); at most 1024 */
     uint32_t max_batch;      /* requests per launch at most (0: 1024) */
     uint32_t queue_capacity; /* queued requests at most before submit says LLAMA_E_BUSY (0: 2^20) */
     uint32_t threads;        /* threads per workgroup (0: 256) */
     uint32_t policy;         /* llama_serve_policy */
-    uint32_t reserved;
 } llama_server_config;
 
 typedef struct {

@@ -4,7 +4,9 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "batch.hpp"
@@ -74,12 +76,52 @@ void reap_retired()
     (void)hipGetLastError();
 }
 
+// the largest tile that fitted kBatchLdsBytes, per class of copies (leaf
+// hash, source kind and lanes, destination kind and lanes, threads, flags)
+std::mutex g_tile_memo_mutex;
+std::map<std::tuple<uint64_t, uint32_t, uint64_t, uint32_t, uint64_t, uint32_t, uint32_t>, uint32_t> g_tile_memo;
+
 } // namespace
 
 void BatchTable::add(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags)
 {
     llama_copy_options o{LLAMA_PATH_AUTO, tile_records, threads, 0, flags};
-    Plan p = make_plan(rq, &o);
+    Plan p;
+    if (tile_records) {
+        p = make_plan(rq, &o);
+    } else {
+        // Every workgroup of the launch reserves the same LDS and about five
+        // fit a compute unit, so the bytes in flight per compute unit grow
+        // with the bytes per tile: take the largest tile whose plan fits
+        // kBatchLdsBytes (a standalone launch's tuned tile may be small
+        // because many of its workgroups fit a compute unit at once).
+        // the tile found for a class of copies is remembered, so that a
+        // repeated class costs one plan instead of a search
+        TuneKey k = tune_key(rq);
+        k.bucket = 0;
+        const auto key = std::make_tuple(k.leaves, k.src_kind, k.src_lanes, k.dst_kind, k.dst_lanes, threads, flags);
+        uint32_t start = 4096;
+        {
+            std::lock_guard<std::mutex> lock(g_tile_memo_mutex);
+            auto it = g_tile_memo.find(key);
+            if (it != g_tile_memo.end())
+                start = it->second;
+        }
+        bool found = false;
+        uint32_t T = start;
+        for (; T >= 16 && !found; T /= 2) {
+            o.tile_records = T;
+            p = make_plan(rq, &o);
+            found = p.path == LLAMA_PATH_STREAM || p.path == LLAMA_PATH_EMPTY ||
+                    (p.path == LLAMA_PATH_TILE && p.tile.h.lds_bytes <= kBatchLdsBytes);
+        }
+        if (!found)
+            fail(LLAMA_E_UNSUPPORTED, "its record does not fit the tiled kernel; copy it with llama_copy");
+        if (T * 2 != start) {
+            std::lock_guard<std::mutex> lock(g_tile_memo_mutex);
+            g_tile_memo[key] = T * 2;
+        }
+    }
     read_bytes += p.read_bytes;
     write_bytes += p.write_bytes;
     if (p.path == LLAMA_PATH_EMPTY)
@@ -156,8 +198,15 @@ void BatchTable::serialise(uint8_t* host, uint64_t device, BatchArgs& args) cons
 uint32_t batch_wg_per_cu(uint32_t lds_bytes, uint32_t threads)
 {
     const uint32_t waves = threads / 64;
-    uint32_t fit = std::min<uint32_t>(lds_bytes ? (kHardLdsBytes - 64) / lds_bytes : 16, kMaxWavesPerCu / waves);
+    // 64 bytes of static LDS (the block counters) per workgroup besides the tile
+    const uint32_t fit = std::min<uint32_t>(lds_bytes ? kHardLdsBytes / (lds_bytes + 64) : 16, kMaxWavesPerCu / waves);
     return std::max<uint32_t>(1, std::min<uint32_t>(fit, 8));
+}
+
+uint32_t batch_grid(uint64_t units, uint32_t lds_bytes, uint32_t threads, uint32_t wg_per_cu)
+{
+    const uint32_t w = wg_per_cu ? wg_per_cu : batch_wg_per_cu(lds_bytes, threads);
+    return uint32_t(std::min<uint64_t>(std::max<uint64_t>(units, 1), uint64_t(device_cu_count()) * w));
 }
 
 Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_options* opt)
@@ -166,7 +215,7 @@ Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_opt
     if (n > 0 && !items)
         fail(LLAMA_E_INVALID_ARG, "batch item array is NULL");
     if (opt && (opt->path != LLAMA_PATH_AUTO || (opt->flags & ~kCopyFlags) != 0))
-        fail(LLAMA_E_INVALID_ARG, "batch options take tile_records, threads, wg_per_cu and LLAMA_COPY_NO_DIRECT");
+        fail(LLAMA_E_INVALID_ARG, "batch options take tile_records, threads, wg_per_cu and the LLAMA_COPY_NO_* flags");
     const uint32_t threads = (opt && opt->threads) ? opt->threads : kDefaultThreads;
     if (threads % 64 != 0 || threads == 0 || threads > 1024)
         fail(LLAMA_E_INVALID_ARG, "threads must be a multiple of 64 in 64..1024");
@@ -207,7 +256,7 @@ Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_opt
     b->write_bytes = t.write_bytes;
     check_hip(hipGetDevice(&b->device), "hipGetDevice");
     b->wg_per_cu = (opt && opt->wg_per_cu) ? opt->wg_per_cu : batch_wg_per_cu(t.lds_bytes, threads);
-    b->grid = uint32_t(std::min<uint64_t>(std::max<uint64_t>(t.units, 1), uint64_t(device_cu_count()) * b->wg_per_cu));
+    b->grid = batch_grid(t.units, t.lds_bytes, threads, b->wg_per_cu);
 
     const size_t total = t.bytes();
     std::vector<uint8_t> host(total);

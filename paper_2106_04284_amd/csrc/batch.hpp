@@ -44,8 +44,16 @@ struct BatchTable {
     void serialise(uint8_t* host, uint64_t device, BatchArgs& args) const;
 };
 
-// resident workgroups per compute unit for a table run with `threads`
+// LDS per workgroup that a batch item may use unless the caller fixes the
+// tile size: five workgroups fit one compute unit
+constexpr uint32_t kBatchLdsBytes = kHardLdsBytes / 5 - 64;
+
+// resident workgroups per compute unit for a table run with `threads`: as
+// many as LDS and wave slots allow, at most 8
 uint32_t batch_wg_per_cu(uint32_t lds_bytes, uint32_t threads);
+// the persistent grid: wg_per_cu (0: batch_wg_per_cu) workgroups per compute
+// unit, and no more than there are units
+uint32_t batch_grid(uint64_t units, uint32_t lds_bytes, uint32_t threads, uint32_t wg_per_cu);
 
 Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_options* opt);
 void launch_batch(Batch* b, void* stream);

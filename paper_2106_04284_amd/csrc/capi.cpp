@@ -324,8 +324,6 @@ int llama_server_create(const llama_server_config* config, llama_server** server
     return guarded([&] {
         need(server, "server");
         *server = nullptr;
-        if (config && config->reserved != 0)
-            fail(LLAMA_E_INVALID_ARG, "llama_server_config.reserved must be 0");
         *server = new llama_server{create_server(config)};
     });
 }

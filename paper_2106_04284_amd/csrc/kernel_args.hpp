@@ -146,9 +146,11 @@ struct NaiveArgs {
 static_assert(sizeof(NaiveArgs) <= 4096, "kernel arguments are limited to 4 KiB");
 
 // ---------------------------------------------------------------------------
-// BATCH: many copies in one persistent launch.  The work table lives in device
-// memory; work unit g (a tile of a TILE item, a 4 KiB chunk of a STREAM item)
-// belongs to the item j with unit_begin[j] <= g < unit_begin[j + 1].
+// BATCH: many copies in one persistent launch whose workgroups take blocks of
+// work units from counters[0] until none is left.  The work table lives in
+// device memory;
+// work unit g (a tile of a TILE item, a 4 KiB chunk of a STREAM item) belongs
+// to the item j with unit_begin[j] <= g < unit_begin[j + 1].
 // ---------------------------------------------------------------------------
 
 enum : uint32_t { kItemTile = 0, kItemStream = 1 };

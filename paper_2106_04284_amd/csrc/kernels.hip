@@ -537,6 +537,36 @@ __global__ void __launch_bounds__(1024) stream_kernel(const StreamArgs a)
 // towards the end) until the counter passes the total; the last workgroup to
 // finish puts both counters back to zero, so the next launch (a graph replay
 // included) starts from zero without a memset.
+// Runs work unit g of item j (begin[j] <= g < begin[j + 1]).
+__device__ __forceinline__ void batch_unit(const BatchArgs& a, const CONSTANT uint64_t* begin, uint32_t j,
+                                           uint64_t g, uint8_t* lds)
+{
+    const CONSTANT BatchItem* it = (const CONSTANT BatchItem*)a.items + j;
+    const uint64_t u = g - begin[j];
+    if (it->kind == kItemTile) {
+        const TileHeader h = load_const(&it->h);
+        const CONSTANT TileEntry* entries = (const CONSTANT TileEntry*)a.entries + it->first;
+        tile_body<kModeAny>(h, [&](uint32_t k) -> const CONSTANT TileEntry& { return entries[k]; }, u, lds);
+    } else {
+        const CONSTANT StreamRun* runs = (const CONSTANT StreamRun*)a.runs + it->first;
+        stream_unit([&](uint32_t k) -> const CONSTANT StreamRun& { return runs[k]; }, it->count, u);
+    }
+}
+
+// The item holding unit g: the last j with begin[j] <= g.
+__device__ __forceinline__ uint32_t batch_item_of(const CONSTANT uint64_t* begin, uint32_t num_items, uint64_t g)
+{
+    uint32_t lo = 0, hi = num_items;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (begin[mid] <= g)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 __global__ void __launch_bounds__(1024) batch_kernel(const BatchArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
@@ -558,28 +588,11 @@ __global__ void __launch_bounds__(1024) batch_kernel(const BatchArgs a)
         __syncthreads();
         if (g0 >= a.total_units)
             break;
-        // item j: begin[j] <= g < begin[j + 1]
-        uint32_t lo = 0, hi = a.num_items;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (begin[mid] <= g0)
-                lo = mid;
-            else
-                hi = mid;
-        }
+        uint32_t lo = batch_item_of(begin, a.num_items, g0);
         for (uint64_t g = g0; g < g1; g++) {
             while (begin[lo + 1] <= g)
                 lo++;
-            const CONSTANT BatchItem* it = (const CONSTANT BatchItem*)a.items + lo;
-            const uint64_t u = g - begin[lo];
-            if (it->kind == kItemTile) {
-                const TileHeader h = load_const(&it->h);
-                const CONSTANT TileEntry* entries = (const CONSTANT TileEntry*)a.entries + it->first;
-                tile_body<kModeAny>(h, [&](uint32_t k) -> const CONSTANT TileEntry& { return entries[k]; }, u, lds);
-            } else {
-                const CONSTANT StreamRun* runs = (const CONSTANT StreamRun*)a.runs + it->first;
-                stream_unit([&](uint32_t k) -> const CONSTANT StreamRun& { return runs[k]; }, it->count, u);
-            }
+            batch_unit(a, begin, lo, g, lds);
             __syncthreads();
         }
     }

@@ -4,13 +4,21 @@
 // Submitted requests are validated and queued.  An engine thread repeats:
 //  1. finished launches (an event per launch) complete their requests and
 //     return their bytes to the budget;
-//  2. while a stream slot is free, queued requests are admitted in arrival
+//  2. while a launch slot is free, queued requests are admitted in arrival
 //     order as long as the bytes in flight (source plus destination blobs)
 //     stay within the budget and no admitted range conflicts with a range in
-//     flight; the admitted requests form one work table, uploaded from pinned
-//     memory and run by the persistent batch kernel on that slot's stream.
-// Requests that arrive while launches run join the next launch as soon as a
-// slot and budget free up, and launches on different streams overlap.
+//     flight; a group closes once its bytes reach group_bytes; the admitted
+//     requests form one work table, uploaded from pinned memory and run by
+//     the persistent batch kernel on that slot's stream (a group of one
+//     request is launched as that request's own copy).
+// Each stream holds up to `depth` launches, so the next launches wait on the
+// device while one runs, and launches on different streams overlap.  Batched:
+// requests never wait to be batched.  A request of group_bytes or more runs
+// alone (as its own copy, with its tuned plan); smaller requests queued at
+// the same time share one launch of the batch kernel, up to group_bytes, so
+// that many small requests do not pay one launch each.  With stream_bytes
+// set, no launch joins a stream holding that many bytes, and arrivals gather
+// in the queue meanwhile (fewer, larger launches at the cost of latency).
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -61,11 +69,13 @@ struct Pending {
 // One launch in flight: its event, and (batched policy) its work table.
 struct Slot {
     hipStream_t stream = nullptr; // one of the server's streams
+    uint32_t stream_index = 0;
     hipEvent_t done = nullptr;
     void* dev = nullptr;
     size_t dev_cap = 0;
     void* host = nullptr; // pinned
     size_t host_cap = 0;
+    bool own_dev = false, own_host = false; // false: a piece of the server's preallocated tables
     bool busy = false;
     std::vector<uint64_t> tickets;
     std::vector<Clock::time_point> arrivals;
@@ -86,6 +96,13 @@ struct Server {
     int device = 0;
     std::vector<hipStream_t> streams;
     std::vector<Slot> slots;
+    // per stream: busy slots in launch order (they finish in that order),
+    // free slots, and the bytes of the launches in flight
+    void* table_dev = nullptr;  // BATCHED: kSlotTableBytes of device memory per slot
+    void* table_host = nullptr; // and as much pinned host memory
+    std::vector<std::deque<uint32_t>> order;
+    std::vector<std::vector<uint32_t>> free_slots;
+    std::vector<uint64_t> stream_bytes;
     std::mutex mu;
     std::condition_variable work_cv;  // engine waits for submissions
     std::condition_variable done_cv;  // waiters wait for completions
@@ -111,23 +128,30 @@ struct Server {
 
 namespace {
 
+// Work-table memory preallocated per slot of a batched server, so that
+// launches allocate nothing (a table of about 400 items fits); a larger
+// table gets memory of its own, kept by the slot.
+constexpr size_t kSlotTableBytes = size_t(256) << 10;
+
 void ensure_capacity(Slot& s, size_t bytes)
 {
     if (bytes > s.dev_cap) {
-        if (s.dev)
+        if (s.dev && s.own_dev)
             check_hip(hipFree(s.dev), "hipFree");
         s.dev = nullptr;
-        size_t cap = std::max<size_t>(bytes, 1 << 16);
-        check_hip(hipMalloc(&s.dev, cap), "hipMalloc(server table)");
-        s.dev_cap = cap;
+        s.dev_cap = 0;
+        s.own_dev = true;
+        check_hip(hipMalloc(&s.dev, bytes), "hipMalloc(server table)");
+        s.dev_cap = bytes;
     }
     if (bytes > s.host_cap) {
-        if (s.host)
+        if (s.host && s.own_host)
             check_hip(hipHostFree(s.host), "hipHostFree");
         s.host = nullptr;
-        size_t cap = std::max<size_t>(bytes, 1 << 16);
-        check_hip(hipHostMalloc(&s.host, cap, hipHostMallocDefault), "hipHostMalloc(server table)");
-        s.host_cap = cap;
+        s.host_cap = 0;
+        s.own_host = true;
+        check_hip(hipHostMalloc(&s.host, bytes, hipHostMallocDefault), "hipHostMalloc(server table)");
+        s.host_cap = bytes;
     }
 }
 
@@ -136,7 +160,11 @@ void ensure_capacity(Slot& s, size_t bytes)
 // Launches `group` on slot `s` according to the policy.
 void Server::launch_slot(Slot& s, std::vector<Pending>& group)
 {
-    if (cfg.policy == LLAMA_SERVE_BATCHED) {
+    if (cfg.policy == LLAMA_SERVE_BATCHED && group.size() == 1) {
+        // a group of one is the request's own launch (its tuned plan, no
+        // work table to upload)
+        launch(make_plan(group[0].rq, nullptr), s.stream);
+    } else if (cfg.policy == LLAMA_SERVE_BATCHED) {
         BatchTable t;
         for (Pending& p : group)
             t.add(p.rq, cfg.threads, 0);
@@ -146,10 +174,8 @@ void Server::launch_slot(Slot& s, std::vector<Pending>& group)
             BatchArgs args{};
             t.serialise((uint8_t*)s.host, uint64_t(uintptr_t(s.dev)), args);
             check_hip(hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice, s.stream), "hipMemcpyAsync(table)");
-            const uint32_t wg = batch_wg_per_cu(t.lds_bytes, cfg.threads);
-            const uint32_t grid =
-                uint32_t(std::min<uint64_t>(std::max<uint64_t>(t.units, 1), uint64_t(device_cu_count()) * wg));
-            launch_batch_args(args, grid, cfg.threads, t.lds_bytes, s.stream);
+            launch_batch_args(args, batch_grid(t.units, t.lds_bytes, cfg.threads, 0), cfg.threads, t.lds_bytes,
+                              s.stream);
         }
     } else {
         llama_copy_options o{cfg.policy == LLAMA_SERVE_NAIVE ? uint32_t(LLAMA_PATH_NAIVE) : uint32_t(LLAMA_PATH_AUTO),
@@ -164,36 +190,41 @@ bool Server::complete_finished(std::unique_lock<std::mutex>& lock)
 {
     (void)lock;
     bool any = false;
-    for (Slot& s : slots) {
-        if (!s.busy)
-            continue;
-        hipError_t q = hipEventQuery(s.done);
-        if (q == hipErrorNotReady)
-            continue;
-        const Clock::time_point now = Clock::now();
-        const int status = q == hipSuccess ? LLAMA_OK : LLAMA_E_HIP;
-        for (size_t k = 0; k < s.tickets.size(); k++) {
-            Outcome& o = outcomes[s.tickets[k]];
-            o.done = true;
-            o.status = status;
-            o.latency = std::chrono::duration<double>(now - s.arrivals[k]).count();
-            if (status == LLAMA_OK) {
-                completed++;
-                latencies.push_back(o.latency);
-            } else {
-                failed++;
+    for (size_t st = 0; st < streams.size(); st++) {
+        while (!order[st].empty()) {
+            const uint32_t idx = order[st].front();
+            Slot& s = slots[idx];
+            hipError_t q = hipEventQuery(s.done);
+            if (q == hipErrorNotReady)
+                break; // later launches of this stream are not done either
+            const Clock::time_point now = Clock::now();
+            const int status = q == hipSuccess ? LLAMA_OK : LLAMA_E_HIP;
+            for (size_t k = 0; k < s.tickets.size(); k++) {
+                Outcome& o = outcomes[s.tickets[k]];
+                o.done = true;
+                o.status = status;
+                o.latency = std::chrono::duration<double>(now - s.arrivals[k]).count();
+                if (status == LLAMA_OK) {
+                    completed++;
+                    latencies.push_back(o.latency);
+                } else {
+                    failed++;
+                }
             }
+            if (status == LLAMA_OK)
+                bytes_done += s.bytes;
+            last_completion = now;
+            inflight_bytes -= s.bytes;
+            stream_bytes[st] -= s.bytes;
+            s.tickets.clear();
+            s.arrivals.clear();
+            s.ranges.clear();
+            s.bytes = 0;
+            s.busy = false;
+            order[st].pop_front();
+            free_slots[st].push_back(idx);
+            any = true;
         }
-        if (status == LLAMA_OK)
-            bytes_done += s.bytes;
-        last_completion = now;
-        inflight_bytes -= s.bytes;
-        s.tickets.clear();
-        s.arrivals.clear();
-        s.ranges.clear();
-        s.bytes = 0;
-        s.busy = false;
-        any = true;
     }
     if (any)
         done_cv.notify_all();
@@ -203,20 +234,35 @@ bool Server::complete_finished(std::unique_lock<std::mutex>& lock)
 bool Server::admit(std::unique_lock<std::mutex>& lock)
 {
     bool any = false;
-    for (Slot& s : slots) {
-        if (s.busy || queue.empty())
-            continue;
+    while (!queue.empty()) {
+        // the stream with the fewest bytes in flight among those with a free slot
+        size_t st = streams.size();
+        for (size_t k = 0; k < streams.size(); k++)
+            if (!free_slots[k].empty() && (st == streams.size() || stream_bytes[k] < stream_bytes[st]))
+                st = k;
+        if (st == streams.size())
+            break;
+        // batched: while every stream holds enough work, requests gather in
+        // the queue and leave later as one launch
+        if (cfg.policy == LLAMA_SERVE_BATCHED && stream_bytes[st] >= cfg.stream_bytes)
+            break;
         std::vector<Pending> group;
         std::vector<Range> ranges;
         uint64_t bytes = 0;
         const uint32_t max_group = cfg.policy == LLAMA_SERVE_BATCHED ? cfg.max_batch : 1;
-        while (!queue.empty() && group.size() < max_group) {
+        while (!queue.empty() && group.size() < max_group && bytes < cfg.group_bytes) {
             Pending& p = queue.front();
+            if (!group.empty() && p.bytes >= cfg.group_bytes)
+                break; // a large request runs alone, in the next launch
             if (inflight_bytes + bytes + p.bytes > cfg.budget_bytes)
                 break; // the budget is full: later requests wait (arrival order is kept)
             bool clash = conflicts(p.ranges, ranges);
-            for (const Slot& o : slots)
-                clash = clash || (o.busy && conflicts(p.ranges, o.ranges));
+            for (size_t k = 0; k < streams.size() && !clash; k++)
+                for (uint32_t b : order[k])
+                    if (conflicts(p.ranges, slots[b].ranges)) {
+                        clash = true;
+                        break;
+                    }
             if (clash)
                 break;
             bytes += p.bytes;
@@ -226,6 +272,9 @@ bool Server::admit(std::unique_lock<std::mutex>& lock)
         }
         if (group.empty())
             break;
+        const uint32_t idx = free_slots[st].back();
+        free_slots[st].pop_back();
+        Slot& s = slots[idx];
         s.busy = true;
         s.bytes = bytes;
         s.ranges = std::move(ranges);
@@ -233,11 +282,14 @@ bool Server::admit(std::unique_lock<std::mutex>& lock)
             s.tickets.push_back(p.ticket);
             s.arrivals.push_back(p.arrival);
         }
+        order[st].push_back(idx);
+        stream_bytes[st] += bytes;
         inflight_bytes += bytes;
         max_inflight_bytes = std::max(max_inflight_bytes, inflight_bytes);
         launches++;
         admitted_total += group.size();
-        // the launch itself runs without the lock (planning, upload)
+        // the launch itself runs without the lock (planning, upload); only
+        // this thread changes the slots, so `idx` is still last in order[st]
         lock.unlock();
         int status = LLAMA_OK;
         try {
@@ -253,11 +305,14 @@ bool Server::admit(std::unique_lock<std::mutex>& lock)
                 failed++;
             }
             inflight_bytes -= s.bytes;
+            stream_bytes[st] -= s.bytes;
             s.tickets.clear();
             s.arrivals.clear();
             s.ranges.clear();
             s.bytes = 0;
             s.busy = false;
+            order[st].pop_back();
+            free_slots[st].push_back(idx);
             done_cv.notify_all();
         }
         any = true;
@@ -273,8 +328,8 @@ void Server::run()
         bool progress = complete_finished(lock);
         progress = admit(lock) || progress;
         bool busy = false;
-        for (const Slot& s : slots)
-            busy = busy || s.busy;
+        for (const auto& o : order)
+            busy = busy || !o.empty();
         if (stop && queue.empty() && !busy)
             break;
         if (!progress) {
@@ -302,6 +357,14 @@ Server* create_server(const llama_server_config* cfg)
         c.streams = c.policy == LLAMA_SERVE_NAIVE ? 1 : 2;
     if (c.streams > 16)
         fail(LLAMA_E_INVALID_ARG, "at most 16 streams");
+    if (c.depth == 0)
+        c.depth = c.policy == LLAMA_SERVE_BATCHED ? 64 : c.policy == LLAMA_SERVE_PER_REQUEST ? 128 : 256;
+    if (c.depth > 1024)
+        fail(LLAMA_E_INVALID_ARG, "at most 1024 launches in flight per stream");
+    if (c.group_bytes == 0)
+        c.group_bytes = uint64_t(8) << 20;
+    if (c.stream_bytes == 0)
+        c.stream_bytes = ~uint64_t(0);
     if (c.max_batch == 0)
         c.max_batch = 1024;
     if (c.queue_capacity == 0)
@@ -312,22 +375,42 @@ Server* create_server(const llama_server_config* cfg)
         fail(LLAMA_E_INVALID_ARG, "threads must be a multiple of 64 in 64..1024");
     s->cfg = c;
     check_hip(hipGetDevice(&s->device), "hipGetDevice");
-    // batched: one launch per stream in flight, so that requests arriving
-    // meanwhile gather into the next launch; one request per launch
-    // otherwise, up to 256 launches queued back to back
+    // `depth` launches in flight per stream, slots taking the streams in turn
     s->streams.assign(c.streams, nullptr);
-    s->slots.resize(c.policy == LLAMA_SERVE_BATCHED ? c.streams : 256);
+    s->slots.resize(size_t(c.streams) * c.depth);
     try {
         for (hipStream_t& st : s->streams)
             check_hip(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+        s->order.resize(c.streams);
+        s->free_slots.resize(c.streams);
+        s->stream_bytes.assign(c.streams, 0);
         for (size_t k = 0; k < s->slots.size(); k++) {
-            s->slots[k].stream = s->streams[k % s->streams.size()];
+            const uint32_t st = uint32_t(k % s->streams.size());
+            s->slots[k].stream = s->streams[st];
+            s->slots[k].stream_index = st;
             check_hip(hipEventCreateWithFlags(&s->slots[k].done, hipEventDisableTiming), "hipEventCreate");
+        }
+        for (size_t k = s->slots.size(); k-- > 0;)
+            s->free_slots[s->slots[k].stream_index].push_back(uint32_t(k));
+        if (c.policy == LLAMA_SERVE_BATCHED) {
+            const size_t n = s->slots.size();
+            check_hip(hipMalloc(&s->table_dev, n * kSlotTableBytes), "hipMalloc(server tables)");
+            check_hip(hipHostMalloc(&s->table_host, n * kSlotTableBytes, hipHostMallocDefault),
+                      "hipHostMalloc(server tables)");
+            for (size_t k = 0; k < n; k++) {
+                s->slots[k].dev = (uint8_t*)s->table_dev + k * kSlotTableBytes;
+                s->slots[k].host = (uint8_t*)s->table_host + k * kSlotTableBytes;
+                s->slots[k].dev_cap = s->slots[k].host_cap = kSlotTableBytes;
+            }
         }
     } catch (...) {
         for (Slot& sl : s->slots)
             if (sl.done)
                 hipEventDestroy(sl.done);
+        if (s->table_dev)
+            hipFree(s->table_dev);
+        if (s->table_host)
+            hipHostFree(s->table_host);
         for (hipStream_t st : s->streams)
             if (st)
                 hipStreamDestroy(st);
@@ -451,12 +534,16 @@ void destroy_server(Server* s)
     for (hipStream_t st : s->streams)
         (void)hipStreamSynchronize(st);
     for (Slot& sl : s->slots) {
-        if (sl.dev)
+        if (sl.dev && sl.own_dev)
             (void)hipFree(sl.dev);
-        if (sl.host)
+        if (sl.host && sl.own_host)
             (void)hipHostFree(sl.host);
         (void)hipEventDestroy(sl.done);
     }
+    if (s->table_dev)
+        (void)hipFree(s->table_dev);
+    if (s->table_host)
+        (void)hipHostFree(s->table_host);
     for (hipStream_t st : s->streams)
         (void)hipStreamDestroy(st);
     (void)hipGetLastError();

@@ -426,9 +426,10 @@ SERVE_BATCHED, SERVE_NAIVE, SERVE_PER_REQUEST = 0, 1, 2
 
 
 class ServerConfig(ctypes.Structure):
-    _fields_ = [("budget_bytes", ctypes.c_uint64), ("streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
-                ("queue_capacity", ctypes.c_uint32), ("threads", ctypes.c_uint32), ("policy", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("group_bytes", ctypes.c_uint64),
+                ("stream_bytes", ctypes.c_uint64), ("streams", ctypes.c_uint32),
+                ("depth", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("queue_capacity", ctypes.c_uint32),
+                ("threads", ctypes.c_uint32), ("policy", ctypes.c_uint32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -444,8 +445,10 @@ class Server:
     continuous batching.  submit() keeps the request's mappings and blobs
     alive until its ticket has been waited for or polled done."""
 
-    def __init__(self, budget_bytes, streams=0, max_batch=0, queue_capacity=0, threads=0, policy=SERVE_BATCHED):
-        cfg = ServerConfig(int(budget_bytes), streams, max_batch, queue_capacity, threads, policy, 0)
+    def __init__(self, budget_bytes, streams=0, max_batch=0, queue_capacity=0, threads=0, policy=SERVE_BATCHED,
+                 group_bytes=0, depth=0, stream_bytes=0):
+        cfg = ServerConfig(int(budget_bytes), int(group_bytes), int(stream_bytes), streams, depth, max_batch,
+                           queue_capacity, threads, policy)
         self._h = ctypes.c_void_p()
         check(lib().llama_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
         self._keep = {}

@@ -97,6 +97,16 @@ def test_batch_equals_lone_copies(L, orc):
 def test_batch_options(L, orc, opts):
     items, want = make_items(L, orc, 5, count=20, nmax=8000)
     b = L.Batch(items, **opts)
+    info = b.info()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    if opts.get("wg_per_cu"):
+        assert info["wg_per_cu"] == opts["wg_per_cu"]
+    else:  # as many as fit a compute unit's LDS and wave slots
+        w = min(160 * 1024 // (info["lds_bytes"] + 64), 32 // (info["threads"] // 64), 8)
+        assert info["wg_per_cu"] == max(1, w)
+    assert info["workgroups"] == min(info["work_units"], cus * info["wg_per_cu"])
+    if not opts.get("tile_records"):
+        assert info["lds_bytes"] <= 160 * 1024 // 5 - 64
     torch.cuda.synchronize()  # inputs were written on the default stream
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):

@@ -77,6 +77,28 @@ def test_mix_equals_alone(L, orc, policy):
             assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("group_bytes,depth,stream_bytes", [(1, 1, 0), (1, 3, 0), (1 << 20, 2, 0), (1 << 40, 1, 0),
+                                                          (1 << 40, 4, 1), (1 << 21, 8, 1 << 22)])
+def test_group_bytes_and_depth(L, orc, group_bytes, depth, stream_bytes):
+    """A launch closes once its bytes reach group_bytes (one request per launch
+    when that is 1 byte); any depth of launches per stream, and holding
+    requests back while a stream has stream_bytes in flight, give the same
+    bytes."""
+    reqs = requests(L, orc, 21, count=40, nmax=20000)
+    srv = L.Server(1 << 34, group_bytes=group_bytes, depth=depth, stream_bytes=stream_bytes)
+    torch.cuda.synchronize()
+    tickets = [srv.submit(r["src"], r["sd"], r["dst"], r["dd"]) for r in reqs]
+    for t in tickets:
+        assert srv.wait(t)[0] == L.OK
+    st = srv.stats()
+    assert st["completed"] == len(reqs)
+    if group_bytes == 1:
+        assert st["launches"] == len(reqs)
+    srv.close()
+    for r in reqs:
+        check(r)
+
+
 def test_concurrent_submitters_and_bad_requests(L, orc):
     reqs = requests(L, orc, 11, count=48, nmax=20000)
     srv = L.Server(1 << 34)
