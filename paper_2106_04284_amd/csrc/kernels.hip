@@ -117,6 +117,33 @@ __device__ __forceinline__ uint64_t field_span_start(uint64_t addr, const TileSi
     return addr + (i0 >> s.log2_lanes) * s.block + (i0 & (s.lanes - 1)) * size;
 }
 
+// Device address of 16-byte granule g of a leaf's values in a tile, from the
+// leaf's tile base; `lg` is log2 of the leaf size.  A field-major side holds
+// the values as one span; an AoSoA side as lane runs of 2^(log2 L + lg - 4)
+// granules, one per block (the planner ensures a run is whole granules).
+template <bool kRecordMajorSide>
+__device__ __forceinline__ uint64_t leaf_granule_addr(uint64_t base, const TileSide& s, uint32_t g, uint32_t lg)
+{
+    if constexpr (!kRecordMajorSide) {
+        return base + uint64_t(g) * 16u;
+    } else {
+        const uint32_t run = s.log2_lanes + lg - 4u;
+        return base + uint64_t(g >> run) * s.block + uint64_t(g & ((1u << run) - 1u)) * 16u;
+    }
+}
+
+// Device address of a leaf's first value in tile t (records i0 ..): a
+// record-major side advances by whole tiles, a field-major side by values.
+template <bool kRecordMajorSide>
+__device__ __forceinline__ uint64_t leaf_tile_base(uint64_t addr, const TileSide& s, uint64_t t, uint64_t i0,
+                                                   uint32_t size)
+{
+    if constexpr (kRecordMajorSide)
+        return addr + t * s.tile_bytes;
+    else
+        return field_span_start(addr, s, i0, size);
+}
+
 // Moves one entry of records r0, r0 + step, r0 + 2 step, r0 + 3 step inside
 // LDS in words of type T; records >= nv, and gap entries, receive zeros.  The
 // four loads are issued before the four stores.
@@ -218,13 +245,15 @@ __device__ __forceinline__ T src_value(const uint8_t* lds, uint32_t sp, const Ti
     return *(const T*)(lds + sp + (r >> s.pos_lg) * s.pos_k + (r & s.pos_m) * size);
 }
 
-// Direct store of one leaf: every 16-byte granule of the destination span
-// gathers 16 / size consecutive records from the source region; records >= nv
-// (AoSoA lanes past the last record) are zero; a granule that passes record nd
-// is stored value by value.
-template <typename T>
-__device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t sp, const TileSide& s, uint64_t gdst,
-                                                  uint32_t nv, uint32_t nd, uint32_t tid, uint32_t nthr, uint32_t rot)
+// Direct store of one leaf: every 16-byte granule of the leaf's destination
+// values (a field-major span, or the lane runs of an AoSoA block) gathers
+// 16 / size consecutive records from the source region; records >= nv (AoSoA
+// lanes past the last record) are zero; a granule that passes record nd is
+// stored value by value.  `gdst` is the leaf's tile base on side d.
+template <typename T, bool kDstRecordMajor>
+__device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t sp, const TileSide& s,
+                                                  const TileSide& d, uint64_t gdst, uint32_t nv, uint32_t nd,
+                                                  uint32_t tid, uint32_t nthr, uint32_t rot)
 {
     constexpr uint32_t per = 16 / sizeof(T);
     const uint32_t G = (nd + per - 1) / per;
@@ -237,13 +266,36 @@ __device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t s
 #pragma unroll
         for (uint32_t j = 0; j < per; j++)
             u.t[j] = r0 + j < nv ? src_value<T>(lds, sp, s, r0 + j, sizeof(T)) : T{};
+        constexpr uint32_t lg = sizeof(T) == 16 ? 4 : sizeof(T) == 8 ? 3 : sizeof(T) == 4 ? 2 : sizeof(T) == 2 ? 1 : 0;
+        const uint64_t a = leaf_granule_addr<kDstRecordMajor>(gdst, d, g, lg);
         if (r0 + per <= nd) {
-            *(GLOBAL u32x4*)(gdst + uint64_t(g) * 16u) = u.v;
+            *(GLOBAL u32x4*)a = u.v;
         } else {
 #pragma unroll
             for (uint32_t j = 0; j < per; j++)
                 if (r0 + j < nd)
-                    *(GLOBAL T*)(gdst + uint64_t(g) * 16u + j * sizeof(T)) = u.t[j];
+                    *(GLOBAL T*)(a + j * sizeof(T)) = u.t[j];
+        }
+    }
+}
+
+// Direct store of a tile: every leaf in turn, at the width of its values.
+template <bool kDstRecordMajor, typename Entries>
+__device__ __forceinline__ void direct_store_tile(const TileHeader& h, Entries ent, uint64_t t, uint64_t i0,
+                                                  uint32_t nv, uint32_t nd, uint32_t tid, uint32_t nthr,
+                                                  const uint8_t* lds)
+{
+    for (uint32_t f = 0; f < h.num_leaves; f++) {
+        const auto& e = ent(f);
+        const uint64_t gdst = leaf_tile_base<kDstRecordMajor>(e.dst_addr, h.dst, t, i0, e.size);
+        const uint32_t rot = (e.move >> 8) & 4095u;
+        const uint32_t sp = e.src_pos;
+        switch (e.move & 7u) {
+        case 4: direct_store_leaf<u32x4, kDstRecordMajor>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
+        case 3: direct_store_leaf<uint64_t, kDstRecordMajor>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
+        case 2: direct_store_leaf<uint32_t, kDstRecordMajor>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
+        case 1: direct_store_leaf<uint16_t, kDstRecordMajor>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
+        default: direct_store_leaf<uint8_t, kDstRecordMajor>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
         }
     }
 }
@@ -253,9 +305,9 @@ __device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t s
 // flight together), then writes the values to the destination region.
 // Records in [nv, nd) (AoSoA lanes past the last record) and gap entries are
 // zero-filled.
-template <typename Entries>
-__device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries ent, uint64_t i0, uint32_t nv,
-                                                 uint32_t nd, uint8_t* lds)
+template <bool kSrcRecordMajor, typename Entries>
+__device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries ent, uint64_t t, uint64_t i0,
+                                                 uint32_t nv, uint32_t nd, uint8_t* lds)
 {
     const uint32_t tid = threadIdx.x, nthr = blockDim.x, wave = wave_id(), lane = tid & 63u;
     u32x4 v[kDirectLoadSlots];
@@ -269,9 +321,10 @@ __device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries en
         while (f + 1 < h.num_leaves && ent(f + 1).src_pos <= q0)
             f++;
         const auto& e = ent(f);
-        const uint32_t g = q0 + lane - e.src_pos; // granule within the leaf's span
+        const uint32_t g = q0 + lane - e.src_pos; // granule within the leaf's values of the tile
         if (g * 16u < nv * e.size)
-            v[j] = *(const GLOBAL u32x4*)(field_span_start(e.src_addr, h.src, i0, e.size) + uint64_t(g) * 16u);
+            v[j] = *(const GLOBAL u32x4*)leaf_granule_addr<kSrcRecordMajor>(
+                leaf_tile_base<kSrcRecordMajor>(e.src_addr, h.src, t, i0, e.size), h.src, g, e.move & 7u);
     }
 #pragma unroll
     for (uint32_t j = 0; j < kDirectLoadSlots; j++) {
@@ -345,7 +398,10 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
 
     // ---- 1. source span(s) -> LDS
     if (dload) {
-        direct_load_tile(h, ent, i0, nv, nd, lds);
+        if (h.src.mode == kRecordMajor)
+            direct_load_tile<true>(h, ent, t, i0, nv, nd, lds);
+        else
+            direct_load_tile<false>(h, ent, t, i0, nv, nd, lds);
     } else if (nv > 0) {
         if (h.src.mode == kRecordMajor) {
             const uint32_t len = uint32_t(((uint64_t(nv) + h.src.lanes - 1) >> h.src.log2_lanes) * h.src.block);
@@ -379,18 +435,10 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     if (dstore) {
         // ---- 2'. gather each destination granule from the source region and
         //          store it; no destination region, no second barrier
-        for (uint32_t f = 0; f < h.num_leaves; f++) {
-            const auto& e = ent(f);
-            const uint64_t gdst = field_span_start(e.dst_addr, h.dst, i0, e.size);
-            const uint32_t rot = (e.move >> 8) & 4095u;
-            switch (e.move & 7u) {
-            case 4: direct_store_leaf<u32x4>(lds, e.src_pos, h.src, gdst, nv, nd, tid, nthr, rot); break;
-            case 3: direct_store_leaf<uint64_t>(lds, e.src_pos, h.src, gdst, nv, nd, tid, nthr, rot); break;
-            case 2: direct_store_leaf<uint32_t>(lds, e.src_pos, h.src, gdst, nv, nd, tid, nthr, rot); break;
-            case 1: direct_store_leaf<uint16_t>(lds, e.src_pos, h.src, gdst, nv, nd, tid, nthr, rot); break;
-            default: direct_store_leaf<uint8_t>(lds, e.src_pos, h.src, gdst, nv, nd, tid, nthr, rot); break;
-            }
-        }
+        if (h.dst.mode == kRecordMajor)
+            direct_store_tile<true>(h, ent, t, i0, nv, nd, tid, nthr, lds);
+        else
+            direct_store_tile<false>(h, ent, t, i0, nv, nd, tid, nthr, lds);
         return;
     }
 
