@@ -13,8 +13,16 @@ written, 1 GB = 1e9 B), the roofline of the dominant kernel (the TILE kernel,
 timed per launch with HIP events on the launch stream), and the CPU oracle
 timed on a bounded sample of the same workload.
 
-Other workloads (--workload): lbm (128^3 cells of 19 f64 + u32, aligned AoS
-<-> SoA multi-blob <-> AoSoA32).
+Other workloads (--workload):
+  lbm    128^3 cells of 19 f64 + u32, aligned AoS <-> SoA multi-blob <->
+         AoSoA32, each copy started cold (1 GiB read before it);
+  batch  1,000 arrays of log-uniform size and mixed record types as one
+         hipGraph-captured launch, against 1,000 naive and 1,000 llama_copy
+         launches;
+  serve  a Poisson trace of copy requests against the request server at
+         offered loads of 0.5 and 0.8 of the batch's GB/s (p50/p99 latency);
+  pic    4,096 particle-in-cell frames of 256 records, SoA <-> AoSoA32, as
+         one batch launch per direction against per-frame launches.
 """
 from __future__ import annotations
 
@@ -113,7 +121,11 @@ def setup_layouts(L, torch, record, extents, layouts, values):
     return maps, blobs
 
 
-def time_pairs(L, torch, maps, blobs, pairs, steps, warmup, stream):
+def time_pairs(L, torch, maps, blobs, pairs, steps, warmup, stream, flush=None):
+    """Times every pair `steps` times with HIP events around each copy.  With
+    `flush` (a device buffer larger than the 256 MB Infinity Cache), the
+    buffer is read before each copy, outside its events, so that every copy
+    starts cold."""
     plans = {p: L.plan(maps[p[0]], maps[p[1]]) for p in pairs}
     for _ in range(warmup):
         for a, b in pairs:
@@ -124,10 +136,13 @@ def time_pairs(L, torch, maps, blobs, pairs, steps, warmup, stream):
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     start.record(stream)
-    for _ in range(steps):
+    for k in range(steps):
         for a, b in pairs:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
+            if flush is not None:
+                with torch.cuda.stream(stream):
+                    flush.sum(dtype=torch.int64)  # reads it: evicts without leaving dirty lines
             e0.record(stream)
             L.copy(maps[a], blobs[a], maps[b], blobs[b], stream=stream)
             e1.record(stream)
@@ -143,7 +158,8 @@ def time_pairs(L, torch, maps, blobs, pairs, steps, warmup, stream):
         per_pair[p] = {"path": plans[p]["path"], "bytes": nb, "ms_median": statistics.median(ms),
                        "ms_min": min(ms), "ms_mean": statistics.mean(ms),
                        "gbs_median": nb / (statistics.median(ms) * 1e-3) / 1e9}
-    return wall, total_ms, per_pair, plans
+    copies_ms = sum(sum(e0.elapsed_time(e1) for e0, e1 in lst) for lst in ev.values())
+    return wall, (copies_ms if flush is not None else total_ms), per_pair, plans
 
 
 def naive_reference(L, torch, maps, blobs, pairs, stream, reps=3):
@@ -286,6 +302,44 @@ def bench_batch(L, torch, args, dev, stream):
             "device": dev.name}
 
 
+def bench_pic(L, torch, args, dev, stream):
+    """Particle-in-cell-shaped batch: 4,096 frames of 256 particle records,
+    single-blob SoA -> AoSoA32 and back, each direction as one batch launch,
+    against one naive launch and one llama_copy per frame."""
+    frames, per = 4096, 256
+    r = L.Record(W.PARTICLE)
+    soa, aosoa = L.Mapping(r, "soa_single", [per]), L.Mapping(r, "aosoa", [per], 32)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(W.BASE_SEED + 6)
+    a = [torch.randint(0, 256, (soa.blob_size(0),), dtype=torch.uint8, device="cuda", generator=g)
+         for _ in range(frames)]
+    b = [aosoa.alloc()[0] for _ in range(frames)]
+    fwd = [(soa, [x], aosoa, [y]) for x, y in zip(a, b)]
+    back = [(aosoa, [y], soa, [x]) for x, y in zip(a, b)]
+    total = frames * (soa.blob_size(0) + aosoa.blob_size(0))
+    torch.cuda.synchronize()
+    res = {}
+    for name, items in (("soa_to_aosoa32", fwd), ("aosoa32_to_soa", back)):
+        bt = L.Batch(items)
+        med, mn = _timed(torch, stream, lambda: bt.launch(stream), args.steps)
+        naive, _ = _timed(torch, stream, lambda: [L.copy_naive(*it, stream=stream) for it in items], 3)
+        lone, _ = _timed(torch, stream, lambda: [L.copy(*it, stream=stream) for it in items], 3)
+        res[name] = {"batched_ms": round(med, 4), "batched_gbs": round(total / (med * 1e-3) / 1e9, 1),
+                     "naive_per_frame_gbs": round(total / (naive * 1e-3) / 1e9, 1),
+                     "llama_copy_per_frame_gbs": round(total / (lone * 1e-3) / 1e9, 1),
+                     "batched_vs_naive": round(naive / med, 2), "batched_vs_per_frame_copy": round(lone / med, 2)}
+        bt.close()
+    gbs = res["soa_to_aosoa32"]["batched_gbs"]
+    return {"metric": METRIC, "value": gbs, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+            "ms_per_step": res["soa_to_aosoa32"]["batched_ms"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "particle-in-cell frames: 4,096 frames of 256 particle records (7xf32), "
+                                   "single-blob SoA <-> AoSoA32, one hipGraph-captured batch launch per direction",
+                       "bytes_per_step": total, "frames": frames, "records_per_frame": per,
+                       "cache": "58.7 MB per launch: mostly resident in the 256 MB Infinity Cache"},
+            "hbm_peak_frac": round(gbs / HBM_PEAK_GBS, 4), "extras": res, "device": dev.name}
+
+
 def _serve_setup(L, torch, count, warm=200):
     """The serving trace: warm + count requests whose blobs lie in one device
     arena used as a ring (132 GB), and the autotuned record/pair classes."""
@@ -409,7 +463,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="particle", choices=["particle", "lbm", "batch", "serve"])
+    ap.add_argument("--workload", default="particle", choices=["particle", "lbm", "batch", "serve", "pic"])
     ap.add_argument("--requests", type=int, default=2000, help="serve: measured requests (after 200 warm-up)")
     ap.add_argument("--rho", type=float, default=0.8, help="serve: offered load as a fraction of batched GB/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -437,6 +491,9 @@ def main():
     if args.workload == "serve":
         print(json.dumps(bench_serve(L, torch, args, dev)), flush=True)
         return
+    if args.workload == "pic":
+        print(json.dumps(bench_pic(L, torch, args, dev, stream)), flush=True)
+        return
 
     if args.workload == "particle":
         n = 1 << 26
@@ -457,12 +514,18 @@ def main():
                    "6 ordered pairs of aligned AoS, SoA multi-blob, AoSoA32"
         dtype = "u64"
         cpu_n = 1 << 17
+    # the 128^3 lattice (663 MB per copy) would partly stay in the 256 MB
+    # Infinity Cache between copies: read 1 GiB before each timed copy
+    cold = args.workload == "lbm"
 
     log(f"inputs generated ({args.workload}); filling {len(layouts)} layouts on {dev.name}")
     maps, blobs = setup_layouts(L, torch, record, extents, layouts, values)
     del values
     log(f"timing {args.steps} steps of {len(pairs)} copies after {args.warmup} warm-up steps")
-    wall, total_ms, per_pair, plans = time_pairs(L, torch, maps, blobs, pairs, args.steps, args.warmup, stream)
+    flush = torch.ones(1 << 27, dtype=torch.int64, device="cuda") if cold else None
+    wall, total_ms, per_pair, plans = time_pairs(L, torch, maps, blobs, pairs, args.steps, args.warmup, stream,
+                                                 flush=flush)
+    del flush
     log(f"timed: {total_ms / args.steps:.2f} ms per step")
     step_bytes = sum(v["bytes"] for v in per_pair.values())
     value = step_bytes * args.steps / (total_ms * 1e-3) / 1e9
@@ -472,11 +535,16 @@ def main():
     tile_bytes = statistics.mean(per_pair[p]["bytes"] for p in tile)
     achieved = tile_bytes / (tile_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic() if args.workload == "particle" else None,
                 "kernel": "tile_kernel", "bytes_per_launch": int(tile_bytes),
                 "launch_ms_mean": round(tile_ms, 4), "launches": len(tile) * args.steps}
 
     extras = {}
+    # payload: 2 N S per copy (values only, no padding)
+    rec_bytes = L.Record(record).info()[1]
+    payload = 2 * int(np.prod(extents)) * rec_bytes * len(pairs) * args.steps
+    extras["payload_gbs"] = round(payload / (total_ms * 1e-3) / 1e9, 1)
     nbytes_layout = sum(maps[layouts[0]].blob_sizes())
     d2d = d2d_reference(torch, nbytes_layout, stream)
     extras["d2d_memcpy_gbs"] = round(d2d, 1) if d2d else None
@@ -503,7 +571,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(total_ms / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": {"workload": workload, "records": int(np.prod(extents)), "pairs": len(pairs),
-                   "bytes_per_step": step_bytes, "parallelism": "single GPU"},
+                   "bytes_per_step": step_bytes, "parallelism": "single GPU",
+                   "cache": "cold: 1 GiB read before each timed copy" if cold else "no flush (layouts exceed "
+                            "the 256 MB Infinity Cache)"},
         "roofline": roofline, "cpu_baseline": cpu,
         "hbm_peak_frac": round(value / HBM_PEAK_GBS, 4), "extras": extras,
         "device": dev.name, "wall_s": round(wall, 3),

@@ -558,13 +558,25 @@ void tile_grid(Plan& p, uint32_t wg_per_cu)
     p.workgroups = wg_per_cu ? std::min<uint64_t>(p.tiles, uint64_t(device_cu_count()) * wg_per_cu) : p.tiles;
 }
 
+// The default tile: the largest power of two with T * S <= 16 KiB, but at
+// least 128 records while T * S stays within 32 KiB, so that a large record
+// (the 156-byte lattice-Boltzmann cell) still gets 1 KiB per f64 leaf span.
 uint32_t default_tile(const Request& rq)
 {
     uint64_t rec = std::max<uint64_t>(rq.record.packed_size, 1);
     uint64_t T = 16;
-    while (T * 2 * rec <= kDefaultTileBytes && T < 4096)
+    while ((T * 2 * rec <= kDefaultTileBytes || (T < 128 && T * 2 * rec <= 2 * kDefaultTileBytes)) && T < 4096)
         T *= 2;
     return uint32_t(T);
+}
+
+// Default threads of a tile: about 112 source bytes per thread (128 threads
+// for a 14 KiB particle tile), a multiple of 64 in 64 .. 256.
+uint32_t default_threads(const Request& rq, uint32_t T)
+{
+    const uint64_t bytes = uint64_t(T) * std::max<uint64_t>(rq.record.packed_size, 1);
+    const uint64_t th = (bytes / 112 + 63) / 64 * 64;
+    return uint32_t(std::min<uint64_t>(std::max<uint64_t>(th, 64), kDefaultThreads));
 }
 
 void fill_naive(const Request& rq, Plan& p)
@@ -673,7 +685,7 @@ Plan make_plan_raw(const Request& rq, const llama_copy_options* opt)
     }
     if (want == LLAMA_PATH_AUTO || want == LLAMA_PATH_TILE) {
         // four records per thread in the LDS remap
-        auto nthreads = [&](uint32_t t) { return std::min<uint32_t>(std::max<uint32_t>(t / 4, 64), kDefaultThreads); };
+        auto nthreads = [&](uint32_t t) { return default_threads(rq, t); };
         uint32_t t = T ? T : default_tile(rq);
         p.threads = threads ? threads : nthreads(t);
         bool ok = fill_tile(rq, t, T ? kHardLdsBytes : kMaxLdsBytes, p);

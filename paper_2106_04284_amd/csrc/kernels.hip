@@ -311,13 +311,14 @@ __device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries en
 {
     const uint32_t tid = threadIdx.x, nthr = blockDim.x, wave = wave_id(), lane = tid & 63u;
     u32x4 v[kDirectLoadSlots];
-    // slot of (wave, j): q = wave * 64 + j * nthr + lane; its leaf is uniform
+    // slot of (wave, j): q = wave * 64 + j * nthr + lane; its leaf is uniform,
+    // and the slots grow with j, so each leaf search resumes from the last
+    uint32_t f = 0;
 #pragma unroll
     for (uint32_t j = 0; j < kDirectLoadSlots; j++) {
         const uint32_t q0 = uniform(wave * 64u + j * nthr);
         if (q0 >= h.slots)
             break;
-        uint32_t f = 0;
         while (f + 1 < h.num_leaves && ent(f + 1).src_pos <= q0)
             f++;
         const auto& e = ent(f);
@@ -326,12 +327,12 @@ __device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries en
             v[j] = *(const GLOBAL u32x4*)leaf_granule_addr<kSrcRecordMajor>(
                 leaf_tile_base<kSrcRecordMajor>(e.src_addr, h.src, t, i0, e.size), h.src, g, e.move & 7u);
     }
+    f = 0;
 #pragma unroll
     for (uint32_t j = 0; j < kDirectLoadSlots; j++) {
         const uint32_t q0 = uniform(wave * 64u + j * nthr);
         if (q0 >= h.slots)
             break;
-        uint32_t f = 0;
         while (f + 1 < h.num_leaves && ent(f + 1).src_pos <= q0)
             f++;
         const auto& e = ent(f);
