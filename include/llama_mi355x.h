@@ -364,7 +364,8 @@ typedef struct {
 } llama_server_stats;
 
 /* A server owns an engine thread, `streams` HIP streams on the current
- * device, and one reusable work table per stream; it never allocates blobs.
+ * device, and one preallocated work table per launch slot (streams x depth);
+ * it never allocates blobs.
  *
  * Requests keep their blobs on the device (the caller's, valid until the
  * request completes).  The server's streams do not wait for the caller's
@@ -398,6 +399,35 @@ int llama_server_reset_stats(llama_server* server);
 
 /* Finishes every queued and running request, then frees the server. */
 int llama_server_destroy(llama_server* server);
+
+/* An executor runs a server's launches on an engine of the caller's instead
+ * of the library's HIP streams (another device runtime, a simulator, or a
+ * host reference used to test the engine without a GPU).  The server keeps
+ * everything else: validation, admission within the budget, range conflicts,
+ * arrival order, grouping, completion and latency accounting.
+ *  - start(context, launch, n, items): begin launch number `launch` (unique,
+ *    increasing) copying items[0 .. n); return LLAMA_OK, or an error status
+ *    that fails the launch's requests.  `items` is valid during the call;
+ *    the descriptors and blob arrays it points to stay valid until poll has
+ *    reported the launch finished.
+ *  - poll(context, launch): 1 when the launch has finished, 0 while it runs,
+ *    a negative status when it failed (its requests fail with that status).
+ * Both are called from the server's engine thread only, one call at a time;
+ * poll is called with the server's lock held, so neither may call any
+ * llama_server_* function. */
+typedef struct {
+    void* context;
+    int (*start)(void* context, uint64_t launch, size_t n, const llama_copy_item* items);
+    int (*poll)(void* context, uint64_t launch);
+} llama_executor;
+
+/* llama_server_create on an executor (NULL: the HIP engine).  With an
+ * executor the server touches no GPU: `policy` only chooses the grouping
+ * (BATCHED: small requests share a launch as above; otherwise one request per
+ * launch), `streams` x `depth` bounds the launches in flight, and `threads`
+ * and the record's fit in the tiled kernel are not checked. */
+int llama_server_create_ex(const llama_server_config* config, const llama_executor* executor,
+                           llama_server** server);
 
 #ifdef __cplusplus
 }

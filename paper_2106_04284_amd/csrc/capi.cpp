@@ -328,6 +328,15 @@ int llama_server_create(const llama_server_config* config, llama_server** server
     });
 }
 
+int llama_server_create_ex(const llama_server_config* config, const llama_executor* executor, llama_server** server)
+{
+    return guarded([&] {
+        need(server, "server");
+        *server = nullptr;
+        *server = new llama_server{create_server(config, executor)};
+    });
+}
+
 int llama_server_submit(llama_server* server, const llama_copy_item* item, uint64_t* ticket)
 {
     return guarded([&] {

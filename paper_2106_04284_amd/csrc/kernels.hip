@@ -338,8 +338,7 @@ __device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries en
         const auto& e = ent(f);
         const uint32_t g = q0 + lane - e.src_pos;
         const uint32_t size = e.size; // 4, 8 or 16
-        const uint32_t per = 16u / size;
-        const uint32_t r0 = g * per;
+        const uint32_t r0 = g << (4u - (e.move & 7u)); // first record of the granule
         if (g * 16u >= nv * size)
             continue;
         const uint32_t d0 = e.dst_pos + (r0 >> h.dst.pos_lg) * h.dst.pos_k + (r0 & h.dst.pos_m) * size;

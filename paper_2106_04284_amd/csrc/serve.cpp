@@ -26,6 +26,7 @@
 #include <condition_variable>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 
@@ -58,12 +59,40 @@ bool conflicts(const std::vector<Range>& a, const std::vector<Range>& b)
     return false;
 }
 
+// A request's descriptors and blob arrays copied at submit, for an executor
+// (the caller's own are borrowed only for the duration of the call).
+struct OwnedItem {
+    std::vector<llama_field> src_nodes, dst_nodes;
+    llama_record_desc src_record{}, dst_record{};
+    llama_mapping_desc src{}, dst{};
+    std::vector<llama_blob> src_blobs, dst_blobs;
+    llama_copy_item item{};
+};
+
+std::unique_ptr<OwnedItem> own_item(const llama_copy_item* it, const Request& rq)
+{
+    std::unique_ptr<OwnedItem> o(new OwnedItem());
+    o->src_nodes.assign(it->src->record->nodes, it->src->record->nodes + it->src->record->num_nodes);
+    o->dst_nodes.assign(it->dst->record->nodes, it->dst->record->nodes + it->dst->record->num_nodes);
+    o->src_record = llama_record_desc{uint32_t(o->src_nodes.size()), o->src_nodes.data()};
+    o->dst_record = llama_record_desc{uint32_t(o->dst_nodes.size()), o->dst_nodes.data()};
+    o->src = *it->src;
+    o->dst = *it->dst;
+    o->src.record = &o->src_record;
+    o->dst.record = &o->dst_record;
+    o->src_blobs.assign(it->src_blobs, it->src_blobs + rq.src_ptr.size());
+    o->dst_blobs.assign(it->dst_blobs, it->dst_blobs + rq.dst_ptr.size());
+    o->item = llama_copy_item{&o->src, o->src_blobs.data(), &o->dst, o->dst_blobs.data()};
+    return o;
+}
+
 struct Pending {
     uint64_t ticket;
     Request rq;
     uint64_t bytes;
     std::vector<Range> ranges;
     Clock::time_point arrival;
+    std::unique_ptr<OwnedItem> owned; // with an executor only
 };
 
 // One launch in flight: its event, and (batched policy) its work table.
@@ -77,6 +106,8 @@ struct Slot {
     size_t host_cap = 0;
     bool own_dev = false, own_host = false; // false: a piece of the server's preallocated tables
     bool busy = false;
+    uint64_t launch_id = 0;                      // with an executor
+    std::vector<std::unique_ptr<OwnedItem>> owned; // with an executor: the launch's items
     std::vector<uint64_t> tickets;
     std::vector<Clock::time_point> arrivals;
     std::vector<Range> ranges;
@@ -94,6 +125,9 @@ struct Outcome {
 struct Server {
     llama_server_config cfg{};
     int device = 0;
+    bool has_exec = false; // runs on `exec` instead of HIP
+    llama_executor exec{};
+    uint64_t launch_counter = 0;
     std::vector<hipStream_t> streams;
     std::vector<Slot> slots;
     // per stream: busy slots in launch order (they finish in that order),
@@ -160,6 +194,18 @@ void ensure_capacity(Slot& s, size_t bytes)
 // Launches `group` on slot `s` according to the policy.
 void Server::launch_slot(Slot& s, std::vector<Pending>& group)
 {
+    if (has_exec) {
+        std::vector<llama_copy_item> items;
+        for (const Pending& p : group)
+            items.push_back(p.owned->item);
+        s.launch_id = ++launch_counter;
+        const int st = exec.start(exec.context, s.launch_id, items.size(), items.data());
+        if (st != LLAMA_OK)
+            fail(st < 0 ? st : LLAMA_E_INVALID_ARG, "the executor did not start launch " + std::to_string(s.launch_id));
+        for (Pending& p : group)
+            s.owned.push_back(std::move(p.owned));
+        return;
+    }
     if (cfg.policy == LLAMA_SERVE_BATCHED && group.size() == 1) {
         // a group of one is the request's own launch (its tuned plan, no
         // work table to upload)
@@ -191,14 +237,25 @@ bool Server::complete_finished(std::unique_lock<std::mutex>& lock)
     (void)lock;
     bool any = false;
     for (size_t st = 0; st < streams.size(); st++) {
-        while (!order[st].empty()) {
-            const uint32_t idx = order[st].front();
+        for (size_t pos = 0; pos < order[st].size();) {
+            const uint32_t idx = order[st][pos];
             Slot& s = slots[idx];
-            hipError_t q = hipEventQuery(s.done);
-            if (q == hipErrorNotReady)
-                break; // later launches of this stream are not done either
+            int status = LLAMA_OK;
+            if (has_exec) {
+                // an executor may finish launches in any order
+                const int q = exec.poll(exec.context, s.launch_id);
+                if (q == 0) {
+                    pos++;
+                    continue;
+                }
+                status = q > 0 ? LLAMA_OK : q;
+            } else {
+                const hipError_t q = hipEventQuery(s.done);
+                if (q == hipErrorNotReady)
+                    break; // later launches of this stream are not done either
+                status = q == hipSuccess ? LLAMA_OK : LLAMA_E_HIP;
+            }
             const Clock::time_point now = Clock::now();
-            const int status = q == hipSuccess ? LLAMA_OK : LLAMA_E_HIP;
             for (size_t k = 0; k < s.tickets.size(); k++) {
                 Outcome& o = outcomes[s.tickets[k]];
                 o.done = true;
@@ -219,9 +276,10 @@ bool Server::complete_finished(std::unique_lock<std::mutex>& lock)
             s.tickets.clear();
             s.arrivals.clear();
             s.ranges.clear();
+            s.owned.clear();
             s.bytes = 0;
             s.busy = false;
-            order[st].pop_front();
+            order[st].erase(order[st].begin() + pos);
             free_slots[st].push_back(idx);
             any = true;
         }
@@ -309,6 +367,7 @@ bool Server::admit(std::unique_lock<std::mutex>& lock)
             s.tickets.clear();
             s.arrivals.clear();
             s.ranges.clear();
+            s.owned.clear();
             s.bytes = 0;
             s.busy = false;
             order[st].pop_back();
@@ -322,7 +381,8 @@ bool Server::admit(std::unique_lock<std::mutex>& lock)
 
 void Server::run()
 {
-    (void)hipSetDevice(device);
+    if (!has_exec)
+        (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lock(mu);
     for (;;) {
         bool progress = complete_finished(lock);
@@ -343,9 +403,15 @@ void Server::run()
     }
 }
 
-Server* create_server(const llama_server_config* cfg)
+Server* create_server(const llama_server_config* cfg, const llama_executor* exec)
 {
     std::unique_ptr<Server> s(new Server());
+    if (exec) {
+        if (!exec->start || !exec->poll)
+            fail(LLAMA_E_INVALID_ARG, "the executor needs both start and poll");
+        s->has_exec = true;
+        s->exec = *exec;
+    }
     llama_server_config c{};
     if (cfg)
         c = *cfg;
@@ -374,24 +440,29 @@ Server* create_server(const llama_server_config* cfg)
     if (c.threads % 64 != 0 || c.threads > 1024)
         fail(LLAMA_E_INVALID_ARG, "threads must be a multiple of 64 in 64..1024");
     s->cfg = c;
-    check_hip(hipGetDevice(&s->device), "hipGetDevice");
     // `depth` launches in flight per stream, slots taking the streams in turn
     s->streams.assign(c.streams, nullptr);
     s->slots.resize(size_t(c.streams) * c.depth);
+    s->order.resize(c.streams);
+    s->free_slots.resize(c.streams);
+    s->stream_bytes.assign(c.streams, 0);
+    for (size_t k = 0; k < s->slots.size(); k++)
+        s->slots[k].stream_index = uint32_t(k % s->streams.size());
+    for (size_t k = s->slots.size(); k-- > 0;)
+        s->free_slots[s->slots[k].stream_index].push_back(uint32_t(k));
+    if (s->has_exec) {
+        s->device = -1; // no GPU: the executor runs the launches
+        s->engine = std::thread([srv = s.get()] { srv->run(); });
+        return s.release();
+    }
+    check_hip(hipGetDevice(&s->device), "hipGetDevice");
     try {
         for (hipStream_t& st : s->streams)
             check_hip(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
-        s->order.resize(c.streams);
-        s->free_slots.resize(c.streams);
-        s->stream_bytes.assign(c.streams, 0);
-        for (size_t k = 0; k < s->slots.size(); k++) {
-            const uint32_t st = uint32_t(k % s->streams.size());
-            s->slots[k].stream = s->streams[st];
-            s->slots[k].stream_index = st;
-            check_hip(hipEventCreateWithFlags(&s->slots[k].done, hipEventDisableTiming), "hipEventCreate");
+        for (Slot& sl : s->slots) {
+            sl.stream = s->streams[sl.stream_index];
+            check_hip(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming), "hipEventCreate");
         }
-        for (size_t k = s->slots.size(); k-- > 0;)
-            s->free_slots[s->slots[k].stream_index].push_back(uint32_t(k));
         if (c.policy == LLAMA_SERVE_BATCHED) {
             const size_t n = s->slots.size();
             check_hip(hipMalloc(&s->table_dev, n * kSlotTableBytes), "hipMalloc(server tables)");
@@ -426,12 +497,16 @@ uint64_t server_submit(Server* s, const llama_copy_item* item)
         fail(LLAMA_E_INVALID_ARG, "item is NULL");
     Pending p;
     p.rq = make_request(item->src, item->src_blobs, item->dst, item->dst_blobs, true);
-    int dev = 0;
-    check_hip(hipGetDevice(&dev), "hipGetDevice");
-    if (dev != s->device)
-        fail(LLAMA_E_INVALID_ARG, "request submitted from device " + std::to_string(dev) + " to a server on device " +
-                                      std::to_string(s->device));
-    if (s->cfg.policy != LLAMA_SERVE_NAIVE) {
+    if (s->has_exec) {
+        p.owned = own_item(item, p.rq);
+    } else {
+        int dev = 0;
+        check_hip(hipGetDevice(&dev), "hipGetDevice");
+        if (dev != s->device)
+            fail(LLAMA_E_INVALID_ARG, "request submitted from device " + std::to_string(dev) +
+                                          " to a server on device " + std::to_string(s->device));
+    }
+    if (!s->has_exec && s->cfg.policy != LLAMA_SERVE_NAIVE) {
         llama_copy_options o{LLAMA_PATH_AUTO, 0, s->cfg.threads, 0, 0};
         if (s->cfg.policy == LLAMA_SERVE_BATCHED && make_plan(p.rq, &o).path == LLAMA_PATH_NAIVE)
             fail(LLAMA_E_UNSUPPORTED, "the record does not fit the tiled kernel; copy it with llama_copy");
@@ -530,6 +605,10 @@ void destroy_server(Server* s)
     s->work_cv.notify_all();
     if (s->engine.joinable())
         s->engine.join();
+    if (s->has_exec) { // the engine has drained every launch
+        delete s;
+        return;
+    }
     (void)hipSetDevice(s->device);
     for (hipStream_t st : s->streams)
         (void)hipStreamSynchronize(st);

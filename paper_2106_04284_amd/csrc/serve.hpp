@@ -7,7 +7,7 @@ namespace llama {
 
 struct Server;
 
-Server* create_server(const llama_server_config* cfg);
+Server* create_server(const llama_server_config* cfg, const llama_executor* exec = nullptr);
 uint64_t server_submit(Server* s, const llama_copy_item* item);
 // true when the request has finished (status and latency filled in); with
 // `wait`, blocks until it has

@@ -127,6 +127,7 @@ _SIGNATURES = {
     "llama_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "llama_server_reset_stats": (ctypes.c_int, [ctypes.c_void_p]),
     "llama_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "llama_server_create_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "llama_batch_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.POINTER(CopyItem), ctypes.POINTER(CopyOptions),
                                           ctypes.POINTER(ctypes.c_void_p)]),
     "llama_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -432,6 +433,14 @@ class ServerConfig(ctypes.Structure):
                 ("threads", ctypes.c_uint32), ("policy", ctypes.c_uint32)]
 
 
+EXEC_START = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_size_t, ctypes.POINTER(CopyItem))
+EXEC_POLL = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64)
+
+
+class Executor(ctypes.Structure):
+    _fields_ = [("context", ctypes.c_void_p), ("start", EXEC_START), ("poll", EXEC_POLL)]
+
+
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
                 ("queued", ctypes.c_uint64), ("launches", ctypes.c_uint64), ("bytes_done", ctypes.c_uint64),
@@ -446,12 +455,38 @@ class Server:
     alive until its ticket has been waited for or polled done."""
 
     def __init__(self, budget_bytes, streams=0, max_batch=0, queue_capacity=0, threads=0, policy=SERVE_BATCHED,
-                 group_bytes=0, depth=0, stream_bytes=0):
+                 group_bytes=0, depth=0, stream_bytes=0, executor=None):
+        """`executor` (llama_server_create_ex): an object with start(launch,
+        items) and poll(launch) methods returning the C statuses; `items` is a
+        list of CopyItem structures.  It runs on the server's engine thread
+        and must not call the server."""
         cfg = ServerConfig(int(budget_bytes), int(group_bytes), int(stream_bytes), streams, depth, max_batch,
                            queue_capacity, threads, policy)
         self._h = ctypes.c_void_p()
-        check(lib().llama_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
         self._keep = {}
+        self._exec = None
+        if executor is None:
+            check(lib().llama_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+            return
+
+        def start(_ctx, launch, n, items):
+            try:
+                return int(executor.start(int(launch), [items[k] for k in range(n)]))
+            except Exception:  # an exception cannot cross the C boundary: fail the launch
+                import traceback
+                traceback.print_exc()
+                return E_INVALID_ARG
+
+        def poll(_ctx, launch):
+            try:
+                return int(executor.poll(int(launch)))
+            except Exception:
+                import traceback
+                traceback.print_exc()
+                return E_INVALID_ARG
+
+        self._exec = Executor(None, EXEC_START(start), EXEC_POLL(poll))  # kept alive with the server
+        check(lib().llama_server_create_ex(ctypes.byref(cfg), ctypes.byref(self._exec), ctypes.byref(self._h)))
 
     def submit(self, src: Mapping, src_blobs, dst: Mapping, dst_blobs) -> int:
         it = _Items([(src, src_blobs, dst, dst_blobs)])
