@@ -198,6 +198,15 @@ typedef struct {
  * it and written in pieces of the destination's alignment). */
 #define LLAMA_COPY_NO_SPLIT 2u
 
+/* Keep the destination's padding bytes (aligned-AoS gaps and record tails,
+ * AoSoA lanes past the last record) as they were, instead of writing zeros
+ * there.  Field-major destinations are written value by value as before; the
+ * tiles of a record-major destination with padding are read, their values
+ * replaced, and written back whole, so such a copy also reads the
+ * destination, and nothing else may write the destination's padding while it
+ * runs.  Without padding in the destination the flag changes nothing. */
+#define LLAMA_COPY_PRESERVE_PADDING 4u
+
 /* llama_copy with explicit kernel parameters.  The result does not depend on
  * the options; only the speed does. */
 int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
@@ -283,8 +292,8 @@ typedef struct {
  *  - Options (may be NULL): tile_records (a fixed tile size for every TILE
  *    item, 0: each item's own), threads (per workgroup, for every item),
  *    wg_per_cu (workgroups per compute unit, 1 .. 16; 0: as many as LDS and
- *    wave slots allow, at most 8); path must be 0, flags takes
- *    LLAMA_COPY_NO_DIRECT and LLAMA_COPY_NO_SPLIT.  Every workgroup reserves
+ *    wave slots allow, at most 8); path must be 0, flags takes the
+ *    LLAMA_COPY_* bits.  Every workgroup reserves
  *    the largest item's LDS, so without a fixed tile size each tiled item
  *    takes the largest tile whose plan fits 32 KB of LDS (the tuning cache,
  *    which is measured on standalone launches, is not used).

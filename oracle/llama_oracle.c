@@ -432,6 +432,28 @@ int orc_copy(const orc_record* r, const orc_mapping* src, uint8_t* const* src_bl
     return ORC_OK;
 }
 
+/* The same copy with the other padding reading, which the library offers as
+ * an option: destination bytes that no value maps to keep whatever they held
+ * before the copy (nothing is zeroed). */
+int orc_copy_keep(const orc_record* r, const orc_mapping* src, uint8_t* const* src_blobs,
+                  const orc_mapping* dst, uint8_t* const* dst_blobs)
+{
+    if (!valid_mapping(src) || !valid_mapping(dst) || !same_extents(src, dst))
+        return ORC_E_ARG;
+    if (orc_record_count(src) == 0)
+        return ORC_OK;
+    uint64_t coord[ORC_MAX_RANK] = {0};
+    do {
+        for (int f = 0; f < r->nleaves; f++) {
+            uint64_t bs, os, bd, od;
+            orc_blob_nr_and_offset(src, r, coord, f, &bs, &os);
+            orc_blob_nr_and_offset(dst, r, coord, f, &bd, &od);
+            memcpy(dst_blobs[bd] + od, src_blobs[bs] + os, (size_t)r->size[f]);
+        }
+    } while (next_coord(src, coord));
+    return ORC_OK;
+}
+
 /* Adds one to counts[b][o] for every byte o of blob b that a (coordinate, leaf)
  * value maps to.  Used to check that a mapping is injective and which of its
  * bytes are padding. */

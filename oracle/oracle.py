@@ -92,6 +92,8 @@ def lib():
         L.orc_blob_nr_and_offset.restype = ctypes.c_int
         L.orc_copy.argtypes = [RP, MP, PP, MP, PP]
         L.orc_copy.restype = ctypes.c_int
+        L.orc_copy_keep.argtypes = [RP, MP, PP, MP, PP]
+        L.orc_copy_keep.restype = ctypes.c_int
         L.orc_write_counts.argtypes = [RP, MP, PP]
         L.orc_write_counts.restype = ctypes.c_int
         L.orc_check_samples.argtypes = [RP, MP, PP, MP, PP, ctypes.POINTER(u64), ctypes.POINTER(i32),
@@ -218,8 +220,12 @@ def _ptrs(blobs):
     return arr
 
 
-def copy(src: Mapping, src_blobs, dst: Mapping, dst_blobs=None):
-    """The naive field-wise copy; returns the destination blobs."""
+def copy(src: Mapping, src_blobs, dst: Mapping, dst_blobs=None, keep_padding=False):
+    """The naive field-wise copy; returns the destination blobs.  By default
+    the destination's padding becomes zero; with keep_padding, `dst_blobs`
+    (required) are updated in place and their padding keeps its bytes."""
+    if keep_padding and dst_blobs is None:
+        raise ValueError("keep_padding needs the destination blobs")
     if dst_blobs is None:
         dst_blobs = dst.alloc()
     for b, s in zip(src_blobs, src.blob_sizes()):
@@ -228,8 +234,9 @@ def copy(src: Mapping, src_blobs, dst: Mapping, dst_blobs=None):
     for b, s in zip(dst_blobs, dst.blob_sizes()):
         if b.size < s:
             raise ValueError("destination blob too small")
-    rc = lib().orc_copy(ctypes.byref(src.record.c), ctypes.byref(src.c), _ptrs(src_blobs),
-                        ctypes.byref(dst.c), _ptrs(dst_blobs))
+    fn = lib().orc_copy_keep if keep_padding else lib().orc_copy
+    rc = fn(ctypes.byref(src.record.c), ctypes.byref(src.c), _ptrs(src_blobs), ctypes.byref(dst.c),
+            _ptrs(dst_blobs))
     if rc != 0:
         raise ValueError(f"oracle copy failed ({rc})")
     return dst_blobs

@@ -215,7 +215,7 @@ Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_opt
     if (n > 0 && !items)
         fail(LLAMA_E_INVALID_ARG, "batch item array is NULL");
     if (opt && (opt->path != LLAMA_PATH_AUTO || (opt->flags & ~kCopyFlags) != 0))
-        fail(LLAMA_E_INVALID_ARG, "batch options take tile_records, threads, wg_per_cu and the LLAMA_COPY_NO_* flags");
+        fail(LLAMA_E_INVALID_ARG, "batch options take tile_records, threads, wg_per_cu and LLAMA_COPY_* flags");
     const uint32_t threads = (opt && opt->threads) ? opt->threads : kDefaultThreads;
     if (threads % 64 != 0 || threads == 0 || threads > 1024)
         fail(LLAMA_E_INVALID_ARG, "threads must be a multiple of 64 in 64..1024");

@@ -308,7 +308,9 @@ struct RunList {
 // Contiguous-chunk analysis (the run-time analysis of sec. 3.9, done on the
 // affine form): returns false when the copy does not reduce to a few long
 // runs.
-bool stream_runs(const Request& rq, RunList& out)
+// Contiguous runs of a pair; zero runs (src 0) fill AoSoA tail lanes unless
+// `preserve` keeps the destination's padding.
+bool stream_runs(const Request& rq, RunList& out, bool preserve)
 {
     const Side &s = rq.src, &d = rq.dst;
     const Record& r = rq.record;
@@ -330,7 +332,8 @@ bool stream_runs(const Request& rq, RunList& out)
         for (size_t f = 0; f < F; f++) {
             uint64_t off = full * d.block + d.base[f];
             out.add(rq.src_ptr[0] + off, rq.dst_ptr[0] + off, tail * r.leaves[f].size);
-            out.add(0, rq.dst_ptr[0] + off + tail * r.leaves[f].size, (L - tail) * r.leaves[f].size);
+            if (!preserve)
+                out.add(0, rq.dst_ptr[0] + off + tail * r.leaves[f].size, (L - tail) * r.leaves[f].size);
         }
         return true;
     }
@@ -342,9 +345,16 @@ bool stream_runs(const Request& rq, RunList& out)
         uint64_t sa = rq.src_ptr[s.blob[f]] + s.base[f];
         uint64_t da = rq.dst_ptr[d.blob[f]] + d.base[f];
         out.add(sa, da, s.n * sz);
-        out.add(0, da + d.n * sz, (d.npad - d.n) * sz);
+        if (!preserve)
+            out.add(0, da + d.n * sz, (d.npad - d.n) * sz);
     }
     return true;
+}
+
+// LLAMA_COPY_PRESERVE_PADDING, where the destination has padding to keep
+bool preserve_padding(const Request& rq, const Plan& p)
+{
+    return (p.flags_in & kPlanPreserve) && rq.dst.has_padding();
 }
 
 uint64_t total_bytes(const std::vector<uint64_t>& v)
@@ -358,7 +368,7 @@ uint64_t total_bytes(const std::vector<uint64_t>& v)
 bool fill_stream(const Request& rq, Plan& p)
 {
     RunList rl;
-    if (!stream_runs(rq, rl))
+    if (!stream_runs(rq, rl, preserve_padding(rq, p)))
         return false;
     if (rl.runs.size() > size_t(kStreamMaxRuns))
         return false;
@@ -502,7 +512,11 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
     // starting 16-byte aligned, leaf sizes 4, 8 or 16, destination positions
     // aligned to the leaf size, and at most kDirectLoadSlots granule slots
     // per thread
-    bool dload = !direct && !(p.flags_in & kPlanNoDirect);
+    // (a kept destination padding needs the destination region loaded first)
+    const bool preserve = preserve_padding(rq, p);
+    if (preserve)
+        a.flags |= kTilePreserve;
+    bool dload = !direct && !preserve && !(p.flags_in & kPlanNoDirect);
     uint32_t slots = 0;
     std::vector<uint32_t> first(F, 0);
     for (size_t f = 0; f < F && dload; f++) {
@@ -617,6 +631,7 @@ void fill_naive(const Request& rq, Plan& p)
         e.width = width(e.dst_addr, e.size, rq.dst);
     }
     a.num_entries = uint32_t(k);
+    a.preserve = preserve_padding(rq, p) ? 1u : 0u;
     p.path = LLAMA_PATH_NAIVE;
     p.workgroups = (a.npad + p.threads - 1) / p.threads;
 }
@@ -639,7 +654,7 @@ Plan make_plan(const Request& rq, const llama_copy_options* opt)
                 tuned.threads = opt->threads;
             if (opt && opt->wg_per_cu)
                 tuned.wg_per_cu = opt->wg_per_cu;
-            tuned.flags = opt ? opt->flags : 0;
+            tuned.flags = (tuned.flags & kTuneFlags) | (opt ? opt->flags : 0u);
             try {
                 return make_plan_raw(rq, &tuned);
             } catch (const Error&) {

@@ -99,7 +99,10 @@ Plan make_plan(const Request& rq, const llama_copy_options* opt);
 
 constexpr uint32_t kPlanNoDirect = LLAMA_COPY_NO_DIRECT;
 constexpr uint32_t kPlanNoSplit = LLAMA_COPY_NO_SPLIT;
-constexpr uint32_t kCopyFlags = LLAMA_COPY_NO_DIRECT | LLAMA_COPY_NO_SPLIT; // every defined bit
+constexpr uint32_t kPlanPreserve = LLAMA_COPY_PRESERVE_PADDING;
+constexpr uint32_t kCopyFlags = LLAMA_COPY_NO_DIRECT | LLAMA_COPY_NO_SPLIT | LLAMA_COPY_PRESERVE_PADDING; // every bit
+// the flags that change only speed, which the tuner may choose and cache
+constexpr uint32_t kTuneFlags = LLAMA_COPY_NO_DIRECT | LLAMA_COPY_NO_SPLIT;
 
 // kernels.hip
 void launch(const Plan& p, void* stream);

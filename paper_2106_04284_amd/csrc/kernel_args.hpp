@@ -66,7 +66,7 @@ struct TileHeader {
     uint32_t num_leaves;
     uint32_t num_entries; // leaves, then gaps
     uint32_t lds_bytes;
-    uint32_t flags;       // kTileDirectStore, kTileDirectLoad
+    uint32_t flags;       // kTileDirectStore, kTileDirectLoad, kTilePreserve
     uint32_t slots;       // kTileDirectLoad: granule slots of a tile (a multiple of 64)
     TileSide src, dst;
 };
@@ -86,6 +86,12 @@ constexpr uint32_t kTileDirectStore = 1;
 // thread t takes slots t + j * threads, j < kDirectLoadSlots.
 constexpr uint32_t kTileDirectLoad = 2;
 constexpr uint32_t kDirectLoadSlots = 8;
+
+// Destination padding keeps its bytes: no zeros are written; a record-major
+// destination region is loaded from the destination before the values move
+// in (never combined with kTileDirectLoad), and field-major spans are stored
+// only for records with values.
+constexpr uint32_t kTilePreserve = 4;
 
 struct TileArgs {
     TileHeader h;
@@ -140,6 +146,8 @@ struct NaiveArgs {
     uint64_t npad;
     uint32_t num_leaves;
     uint32_t num_entries;
+    uint32_t preserve; // 1: padding keeps its bytes (gap entries and records >= n are skipped)
+    uint32_t pad;
     NaiveSide src, dst;
     NaiveEntry e[kNaiveMaxEntries];
 };

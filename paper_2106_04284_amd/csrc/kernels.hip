@@ -395,6 +395,10 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     const uint64_t i0 = t << h.log2_tile;
     const uint32_t nv = i0 < h.n ? uint32_t(min<uint64_t>(T, h.n - i0)) : 0u; // records with values
     const uint32_t nd = uint32_t(min<uint64_t>(T, h.npad - i0));              // records the destination spans
+    // kept padding: only records with values are written (a record-major
+    // destination region is loaded first and stored back whole)
+    const bool preserve = (h.flags & kTilePreserve) != 0;
+    const uint32_t ns = preserve ? nv : nd;
 
     // ---- 1. source span(s) -> LDS
     if (dload) {
@@ -413,6 +417,10 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
                           nwaves, (e.move >> 4) & 15u, lane, lds_base);
             }
         }
+    }
+    if (preserve && !dstore && h.dst.mode == kRecordMajor) {
+        const uint32_t len = uint32_t(((uint64_t(nd) + h.dst.lanes - 1) >> h.dst.log2_lanes) * h.dst.block);
+        load_span(h.dst.span_base + t * h.dst.tile_bytes, len, h.dst.lds_base, wave, nwaves, 0, lane, lds_base);
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -436,35 +444,37 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
         // ---- 2'. gather each destination granule from the source region and
         //          store it; no destination region, no second barrier
         if (h.dst.mode == kRecordMajor)
-            direct_store_tile<true>(h, ent, t, i0, nv, nd, tid, nthr, lds);
+            direct_store_tile<true>(h, ent, t, i0, nv, ns, tid, nthr, lds);
         else
-            direct_store_tile<false>(h, ent, t, i0, nv, nd, tid, nthr, lds);
+            direct_store_tile<false>(h, ent, t, i0, nv, ns, tid, nthr, lds);
         return;
     }
 
     // ---- 2. every value from its source to its destination position;
-    //         destination padding becomes zero
+    //         destination padding becomes zero (or, kept, is left as loaded)
     for (uint32_t k = 0; k < h.num_entries; k++) {
         const auto& e = ent(k);
         const bool gap = (e.move >> 31) != 0;
+        if (gap && preserve)
+            continue;
         if (e.move & kMoveSplit) {
             const uint32_t rd = (e.move >> 20) & 7u, wr = (e.move >> 24) & 7u;
-            for (uint32_t r0 = tid; r0 < nd; r0 += 4u * nthr) {
+            for (uint32_t r0 = tid; r0 < ns; r0 += 4u * nthr) {
                 switch (e.size) {
-                case 2: move4_split<uint16_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, r0, nthr, nv, nd, rd, wr); break;
-                case 4: move4_split<uint32_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, r0, nthr, nv, nd, rd, wr); break;
-                default: move4_split<uint64_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, r0, nthr, nv, nd, rd, wr); break;
+                case 2: move4_split<uint16_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, r0, nthr, nv, ns, rd, wr); break;
+                case 4: move4_split<uint32_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, r0, nthr, nv, ns, rd, wr); break;
+                default: move4_split<uint64_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, r0, nthr, nv, ns, rd, wr); break;
                 }
             }
             continue;
         }
-        for (uint32_t r0 = tid; r0 < nd; r0 += 4u * nthr) {
+        for (uint32_t r0 = tid; r0 < ns; r0 += 4u * nthr) {
             switch (e.move & 7u) {
-            case 4: move4<u32x4>(lds, e.src_pos, e.dst_pos, h.src, h.dst, e.size, r0, nthr, nv, nd, gap); break;
-            case 3: move4<uint64_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, e.size, r0, nthr, nv, nd, gap); break;
-            case 2: move4<uint32_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, e.size, r0, nthr, nv, nd, gap); break;
-            case 1: move4<uint16_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, e.size, r0, nthr, nv, nd, gap); break;
-            default: move4<uint8_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, e.size, r0, nthr, nv, nd, gap); break;
+            case 4: move4<u32x4>(lds, e.src_pos, e.dst_pos, h.src, h.dst, e.size, r0, nthr, nv, ns, gap); break;
+            case 3: move4<uint64_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, e.size, r0, nthr, nv, ns, gap); break;
+            case 2: move4<uint32_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, e.size, r0, nthr, nv, ns, gap); break;
+            case 1: move4<uint16_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, e.size, r0, nthr, nv, ns, gap); break;
+            default: move4<uint8_t>(lds, e.src_pos, e.dst_pos, h.src, h.dst, e.size, r0, nthr, nv, ns, gap); break;
             }
         }
     }
@@ -477,7 +487,7 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     } else {
         for (uint32_t f = 0; f < h.num_leaves; f++) {
             const auto& e = ent(f);
-            store_span(field_span_start(e.dst_addr, h.dst, i0, e.size), nd * e.size, e.dst_pos & ~15u, tid, nthr,
+            store_span(field_span_start(e.dst_addr, h.dst, i0, e.size), ns * e.size, e.dst_pos & ~15u, tid, nthr,
                        (e.move >> 8) & 4095u, lds);
         }
     }
@@ -672,6 +682,8 @@ __global__ void __launch_bounds__(1024) naive_kernel(const NaiveArgs a)
         for (uint32_t k = 0; k < a.num_entries; k++) {
             const NaiveEntry& e = a.e[k];
             const bool zero = e.src_addr == 0 || i >= a.n;
+            if (zero && a.preserve)
+                continue; // padding keeps its bytes
             const uint64_t doff = a.dst.lanes ? (i / a.dst.lanes) * a.dst.block + (i % a.dst.lanes) * e.size
                                               : i * e.size;
             uint64_t soff = 0;

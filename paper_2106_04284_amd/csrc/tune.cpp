@@ -267,7 +267,8 @@ uint32_t tune_load(const char* path)
             v.opt.path >> v.opt.tile_records >> v.opt.threads >> v.opt.wg_per_cu >> v.opt.flags >> v.gbs;
         if (!in)
             fail(LLAMA_E_INVALID_ARG, std::string("malformed tuning cache line in ") + path + ": " + line);
-        if (v.opt.path > LLAMA_PATH_NAIVE || (v.opt.flags & ~kCopyFlags) || v.opt.threads % 64 || v.opt.threads > 1024 || v.opt.wg_per_cu > 16 ||
+        if (v.opt.path > LLAMA_PATH_NAIVE || (v.opt.flags & ~kTuneFlags) || v.opt.threads % 64 ||
+            v.opt.threads > 1024 || v.opt.wg_per_cu > 16 ||
             (v.opt.tile_records && (v.opt.tile_records < 16 || v.opt.tile_records > 4096 ||
                                     (v.opt.tile_records & (v.opt.tile_records - 1)))))
             fail(LLAMA_E_INVALID_ARG, std::string("invalid parameters in tuning cache line: ") + line);

@@ -22,9 +22,10 @@ def L():
     return llama
 
 
-def make_items(L, orc, seed, count, nmax, records=("particle", "mixed"), layouts=None):
+def make_items(L, orc, seed, count, nmax, records=("particle", "mixed"), layouts=None, keep=False):
     """Random batch items: record, size, layout pair; source bytes random, the
-    oracle's expected destination computed on the host."""
+    oracle's expected destination computed on the host (keep: padding keeps
+    the destination's 0xCD canary)."""
     g = random.Random(seed)
     layouts = layouts or (W.LAYOUTS + [("aosoa", 16)])
     items, want = [], []
@@ -36,7 +37,11 @@ def make_items(L, orc, seed, count, nmax, records=("particle", "mixed"), layouts
         ro, rg = orc.Record(rec), L.Record(rec)
         ms_o, md_o = orc.Mapping(ro, a[0], [n], a[1]), orc.Mapping(ro, b[0], [n], b[1])
         src = [W.random_bytes(s, seed * 7919 + k * 31 + j) for j, s in enumerate(ms_o.blob_sizes())]
-        want.append(orc.copy(ms_o, src, md_o))
+        if keep:
+            want.append(orc.copy(ms_o, src, md_o, [np.full(x, 0xCD, np.uint8) for x in md_o.blob_sizes()],
+                                 keep_padding=True))
+        else:
+            want.append(orc.copy(ms_o, src, md_o))
         ms, md = L.Mapping(rg, a[0], [n], a[1]), L.Mapping(rg, b[0], [n], b[1])
         sd = [torch.from_numpy(x).cuda() for x in src]
         dd = md.alloc(fill=0xCD)
@@ -124,6 +129,17 @@ def test_one_shot_batch_and_null_stream(L, orc):
     refill(items, 0x5A)
     b = L.Batch(items)
     b.launch(stream=0)  # the null stream is not captured; the kernel is launched directly
+    torch.cuda.synchronize()
+    check(items, want)
+
+
+def test_batch_preserve_padding(L, orc):
+    """LLAMA_COPY_PRESERVE_PADDING in a batch: padding keeps its canary in
+    tiled items and in long-run items (AoSoA tail lanes)."""
+    items, want = make_items(L, orc, 17, count=30, nmax=5000, records=("particle", "mixed", "lbm"), keep=True)
+    b = L.Batch(items, flags=L.COPY_PRESERVE_PADDING)
+    torch.cuda.synchronize()
+    b.launch()
     torch.cuda.synchronize()
     check(items, want)
 

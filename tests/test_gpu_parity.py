@@ -18,6 +18,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 GUARD = 64
+L_NO_DIRECT = 1  # LLAMA_COPY_NO_DIRECT
 LAYOUTS = W.LAYOUTS
 PAIRS = [(a, b) for a in LAYOUTS for b in LAYOUTS]
 
@@ -50,7 +51,9 @@ def _device_blobs(blobs, offset=0, fill=None, sizes=None):
 
 
 def run_case(L, orc, rec, src_layout, dst_layout, extents, seed, src_off=0, dst_off=0, fill=0xCD,
-             extra_dst=0, **opts):
+             extra_dst=0, keep=False, **opts):
+    """keep: LLAMA_COPY_PRESERVE_PADDING; the destination's padding must keep
+    the canary `fill` (the oracle's keep-padding copy over canary blobs)."""
     ro, rg = orc.Record(rec), L.Record(rec)
     ms_o = orc.Mapping(ro, src_layout[0], extents, src_layout[1])
     md_o = orc.Mapping(ro, dst_layout[0], extents, dst_layout[1])
@@ -58,7 +61,12 @@ def run_case(L, orc, rec, src_layout, dst_layout, extents, seed, src_off=0, dst_
     md = L.Mapping(rg, dst_layout[0], extents, dst_layout[1])
     assert ms.blob_sizes() == ms_o.blob_sizes() and md.blob_sizes() == md_o.blob_sizes()
     src = [W.random_bytes(s, seed * 131 + k) for k, s in enumerate(ms_o.blob_sizes())]
-    want = orc.copy(ms_o, src, md_o)
+    if keep:
+        opts["flags"] = opts.get("flags", 0) | L.COPY_PRESERVE_PADDING
+        want = orc.copy(ms_o, src, md_o, [np.full(s, fill, np.uint8) for s in md_o.blob_sizes()],
+                        keep_padding=True)
+    else:
+        want = orc.copy(ms_o, src, md_o)
     s_views, _ = _device_blobs(src, src_off)
     dsizes = [s + extra_dst for s in md_o.blob_sizes()]
     d_views, d_bufs = _device_blobs(None, dst_off, fill=fill, sizes=dsizes)
@@ -158,6 +166,25 @@ def test_kernel_options(L, orc, opts, pair):
             assert e.status == L.E_UNSUPPORTED and opts.get("tile_records", 0) >= 512
             continue
         run_case(L, orc, W.RECORDS[name], pair[0], pair[1], [n], seed=n, **opts)
+
+
+@pytest.mark.parametrize("pair", PAIRS, ids=[f"{_name(a)}-{_name(b)}" for a, b in PAIRS])
+@pytest.mark.parametrize("name", ["mixed", "lbm", "listing1"])
+def test_preserve_padding(L, orc, pair, name):
+    """LLAMA_COPY_PRESERVE_PADDING: aligned-AoS gaps and AoSoA tail lanes keep
+    the destination's canary bytes, every value lands as in the default copy
+    (1,031 records: a partial AoSoA block and several tiles)."""
+    run_case(L, orc, W.RECORDS[name], pair[0], pair[1], [1031], seed=29, keep=True)
+
+
+@pytest.mark.parametrize("opts", [dict(flags=L_NO_DIRECT), dict(path="naive"), dict(path="tile", tile_records=16),
+                                  dict(path="tile", tile_records=256, threads=64, wg_per_cu=2)])
+@pytest.mark.parametrize("pair", [(("soa_multi", 0), ("aos_aligned", 0)), (("aosoa", 8), ("aosoa", 64)),
+                                  (("aos_packed", 0), ("aosoa", 32)), (("aosoa", 64), ("soa_single", 0)),
+                                  (("aos_aligned", 0), ("aos_aligned", 0))])
+def test_preserve_padding_options(L, orc, opts, pair):
+    for name, n in (("mixed", 1031), ("lbm", 333), ("listing1", 77)):
+        run_case(L, orc, W.RECORDS[name], pair[0], pair[1], [n], seed=n, keep=True, dst_off=3, **opts)
 
 
 SPLIT_PAIRS = [(("aos_packed", 0), b) for b in LAYOUTS if b[0] != "aos_packed"] + \

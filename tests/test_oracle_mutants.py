@@ -29,6 +29,10 @@ MUTANTS = {
                             "uint64_t block = i % L;\n        uint64_t lane = i / L;"),
     "aosoa_blob_size_no_tail": ("return blocks * m->lanes * orc_packed_size(r);", "return n * orc_packed_size(r);"),
     "padding_not_zeroed": ("memset(dst_blobs[b], 0, (size_t)orc_blob_size(dst, r, b));", "(void)0;"),
+    "keep_mode_zeroes_padding": ("                  const orc_mapping* dst, uint8_t* const* dst_blobs)\n{\n",
+                                 "                  const orc_mapping* dst, uint8_t* const* dst_blobs)\n{\n"
+                                 "    for (int b = 0; b < orc_blob_count(dst, r); b++)\n"
+                                 "        memset(dst_blobs[b], 0, (size_t)orc_blob_size(dst, r, b));\n"),
     "static_array_one_short": ("for (uint64_t c = 1; c < count; c++)", "for (uint64_t c = 2; c < count; c++)"),
     "aos_aligned_uses_packed_stride": ("*offset = i * orc_aligned_size(r) + orc_aligned_offset(r, f);",
                                        "*offset = i * orc_packed_size(r) + orc_aligned_offset(r, f);"),

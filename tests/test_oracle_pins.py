@@ -369,6 +369,33 @@ def test_padding_is_zero_and_round_trip(orc, name):
                 assert not x[pad].any()
 
 
+@pytest.mark.parametrize("name", ["particle", "mixed", "listing1", "lbm"])
+@pytest.mark.parametrize("n", [1, 5, 67])
+def test_keep_padding_copy_against_serialiser(orc, name, n):
+    """The other padding reading (the library's opt-in): the destination's
+    padding keeps its old bytes and every value is written.  Value bytes equal
+    the serialiser's layout; the padding is where the serialiser leaves zeros
+    even when every value byte is 0xFF, and there the old bytes remain."""
+    rec = W.RECORDS[name]
+    types = W.leaf_types(rec)
+    vals = _unique_leaf_values(types, n, 300 + n)
+    ones = [np.full(n * np.dtype(W.NP_DTYPES[t]).itemsize, 0xFF, np.uint8).view(W.NP_DTYPES[t]) for t in types]
+    r = orc.Record(rec)
+    lay = _layouts(lanes=(1, 8, 32))
+    for ka, la in lay:
+        src = _build(orc, rec, ka, [n], la, vals)
+        a = orc.Mapping(r, ka, [n], la)
+        for kb, lb in lay:
+            b = orc.Mapping(r, kb, [n], lb)
+            want = [np.frombuffer(x, np.uint8) for x in _serialise(types, vals, kb, n, lb)]
+            pad = [np.frombuffer(x, np.uint8) == 0 for x in _serialise(types, ones, kb, n, lb)]
+            init = [W.random_bytes(s, 7 + k) for k, s in enumerate(b.blob_sizes())]
+            got = orc.copy(a, src, b, [x.copy() for x in init], keep_padding=True)
+            for g, w, p, i in zip(got, want, pad, init):
+                assert np.array_equal(g[~p], w[~p]), (ka, la, kb, lb)
+                assert np.array_equal(g[p], i[p]), (ka, la, kb, lb)
+
+
 def test_composition(orc):
     """A -> B -> C equals A -> C for every triple of layouts."""
     r = orc.Record(W.MIXED)
