@@ -227,6 +227,9 @@ typedef struct {
     uint64_t write_bytes;   /* bytes of destination blobs the copy writes */
 } llama_plan_info;
 
+/* What a copy of this pair with these options would launch, without blobs:
+ * the plan assumes distinct blobs aligned to 256 bytes (a real copy plans for
+ * its actual blob addresses, which can change alignment-dependent choices). */
 int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, const llama_copy_options* options,
                llama_plan_info* info);
 

@@ -259,8 +259,12 @@ Request make_request(const llama_mapping_desc* src, const llama_blob* src_blobs,
                                               " overlap");
         }
     } else {
-        rq.src_ptr.assign(rq.src.blob_size.size(), 0);
-        rq.dst_ptr.assign(rq.dst.blob_size.size(), 0);
+        // a plan without blobs assumes distinct, 256-byte aligned blobs (1 TiB
+        // apart), so that runs of different blobs never look contiguous
+        for (size_t b = 0; b < rq.src.blob_size.size(); b++)
+            rq.src_ptr.push_back((uint64_t(b) + 1) << 40);
+        for (size_t b = 0; b < rq.dst.blob_size.size(); b++)
+            rq.dst_ptr.push_back((uint64_t(b) + 1 + 4096) << 40);
     }
     return rq;
 }

@@ -98,6 +98,55 @@ def test_planner_paths_for_particle_pairs():
             assert path == "tile", (a, b)
 
 
+SOA_KINDS = {"soa_single", "soa_multi"}
+
+
+@pytest.mark.parametrize("name", ["particle", "mixed", "lbm", "listing1"])
+@pytest.mark.parametrize("n", [1000, 1024])
+def test_planner_classification_all_pairs(orc, name, n):
+    """All 49 ordered pairs (identity included): a long-run copy only where
+    every byte moves in whole runs (identical placement without destination
+    gaps, or SoA <-> SoA, one run per leaf); the tiled transpose otherwise.
+    A different mapping never becomes a whole-blob memcpy (sec. 3.9)."""
+    r = L.Record(W.RECORDS[name])
+    ro = orc.Record(W.RECORDS[name])
+    gaps = ro.aligned_size != ro.packed_size
+    for a in W.LAYOUTS:
+        for b in W.LAYOUTS:
+            ma, mb = L.Mapping(r, a[0], [n], a[1]), L.Mapping(r, b[0], [n], b[1])
+            p = L.plan(ma, mb)
+            same_bytes = a == b or (not gaps and {a[0], b[0]} == {"aos_packed", "aos_aligned"})
+            if same_bytes and not (b[0] == "aos_aligned" and gaps):
+                assert p["path"] == "stream", (a, b)
+                # a partial last AoSoA block: whole blocks, then per leaf its
+                # values and its zero lanes (leaf 0's values continue the
+                # whole blocks: one run)
+                tail = b[0] == "aosoa" and n % b[1] != 0
+                assert p["runs"] == (mb.blob_count if not tail else 2 * ro.nleaves), (a, b)
+            elif a[0] in SOA_KINDS and b[0] in SOA_KINDS:
+                assert p["path"] == "stream" and p["runs"] == ro.nleaves, (a, b)
+            else:
+                assert p["path"] == "tile", (a, b)
+
+
+@pytest.mark.parametrize("name", ["particle", "mixed", "lbm", "listing1"])
+def test_byte_accounting(orc, name):
+    """The bytes a plan reports (and the benchmark counts) are the blob bytes
+    the mappings span, padding included, each read or written once; the
+    payload 2 N S is at most that, and equal without padding."""
+    r, ro = L.Record(W.RECORDS[name]), orc.Record(W.RECORDS[name])
+    n = 1031
+    for a in W.LAYOUTS:
+        for b in W.LAYOUTS:
+            ma, mb = L.Mapping(r, a[0], [n], a[1]), L.Mapping(r, b[0], [n], b[1])
+            oa, ob = orc.Mapping(ro, a[0], [n], a[1]), orc.Mapping(ro, b[0], [n], b[1])
+            p = L.plan(ma, mb)
+            assert p["read_bytes"] == sum(oa.blob_sizes()) and p["write_bytes"] == sum(ob.blob_sizes())
+            payload = 2 * n * ro.packed_size
+            pad = sum(int(m.sum()) for m in orc.padding_masks(oa)) + sum(int(m.sum()) for m in orc.padding_masks(ob))
+            assert p["read_bytes"] + p["write_bytes"] == payload + pad
+
+
 def test_planner_identity_and_padding():
     r = L.Record(W.MIXED)
     # identical aligned AoS with gaps: padding must be rewritten as zeros, so
