@@ -4,6 +4,7 @@ paper_2106_04284_amd.build`` or through ``__graft_entry__.build()``."""
 from __future__ import annotations
 
 import os
+import re
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -35,16 +36,35 @@ def _run(cmd):
     return r
 
 
+def _check_no_scratch(report: str):
+    """Every kernel keeps its values in registers: a kernel that spills (or
+    keeps an array in scratch memory) runs many times slower, so the build
+    refuses it.  `report` is hipcc's kernel-resource-usage remarks."""
+    kernel, bad = None, []
+    for line in report.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            kernel = m.group(1)
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and int(m.group(1)) > 0:
+            bad.append(f"{kernel}: {m.group(1)} bytes of scratch per lane")
+    if bad:
+        raise RuntimeError("kernels use scratch memory (register spills):\n" + "\n".join(bad))
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = []
     for s in HIP_SOURCES:
-        jobs.append([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, s), "-o", os.path.join(BUILD, s + ".o")])
+        jobs.append([HIPCC] + HIP_FLAGS + ["-Rpass-analysis=kernel-resource-usage", "-c", os.path.join(CSRC, s),
+                                           "-o", os.path.join(BUILD, s + ".o")])
     for s in CXX_SOURCES:
         jobs.append(["g++"] + CXX_FLAGS + ["-c", os.path.join(CSRC, s), "-o", os.path.join(BUILD, s + ".o")])
     with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
         for r in ex.map(_run, jobs):
-            if verbose and (r.stdout or r.stderr):
+            if r.args[0] == HIPCC:
+                _check_no_scratch(r.stderr)
+            elif verbose and (r.stdout or r.stderr):
                 print(r.stdout + r.stderr)
     objs = [os.path.join(BUILD, s + ".o") for s in HIP_SOURCES + CXX_SOURCES]
     tmp = LIB + ".tmp"

@@ -498,9 +498,23 @@ __global__ void __launch_bounds__(1024) tile_kernel(const TileArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     auto ent = [&](uint32_t k) -> const TileEntry& { return a.e[k]; };
-    for (uint64_t t = blockIdx.x; t < a.h.num_tiles; t += gridDim.x) {
+    const uint64_t nt = a.h.num_tiles;
+    uint64_t t = blockIdx.x, stride = gridDim.x;
+    if (Mode != kModeStaged && gridDim.x == nt) {
+        // one workgroup per tile: workgroups are dispatched to the 8 XCDs in
+        // turn, so block b goes to XCD b mod 8; give each XCD one contiguous
+        // eighth of the tiles (a bijection for any tile count).  Measured
+        // +4-7% for the direct modes, -2.5% for the staged one, which keeps
+        // the plain order.  One call site of tile_body: a second inlined
+        // copy changed how the compiler unrolled the direct-load registers
+        // and moved them to scratch.
+        const uint64_t b = blockIdx.x, x = b & 7u, k = b >> 3, q = nt >> 3, rem = nt & 7u;
+        t = x * q + min(x, rem) + k;
+        stride = nt;
+    }
+    for (; t < nt; t += stride) {
         tile_body<Mode>(a.h, ent, t, lds);
-        if (t + gridDim.x < a.h.num_tiles)
+        if (t + stride < nt)
             __syncthreads();
     }
 }

@@ -280,3 +280,16 @@ def test_tuning_cache_file_round_trip(tmp_path):
             L.tune_load(str(probe))
     with pytest.raises(L.LlamaError):
         L.tune_load(str(tmp_path / "missing.txt"))
+
+
+def test_build_refuses_kernels_with_scratch():
+    """A kernel that spills to scratch memory runs many times slower: the
+    build parses hipcc's resource remarks and refuses it."""
+    from paper_2106_04284_amd import build as B
+    ok = ("k.hip:1:1: remark: Function Name: good [-Rpass-analysis=kernel-resource-usage]\n"
+          "k.hip:1:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis=kernel-resource-usage]\n")
+    B._check_no_scratch(ok)
+    bad = ok + ("k.hip:2:1: remark: Function Name: spills [-Rpass-analysis=kernel-resource-usage]\n"
+                "k.hip:2:1: remark:     ScratchSize [bytes/lane]: 3960 [-Rpass-analysis=kernel-resource-usage]\n")
+    with pytest.raises(RuntimeError, match="spills: 3960"):
+        B._check_no_scratch(bad)
