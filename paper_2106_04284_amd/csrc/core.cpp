@@ -728,6 +728,25 @@ Plan make_plan_raw(const Request& rq, const llama_copy_options* opt)
                     p = q;
             }
         }
+        if (ok && !T && !threads && (p.tile.h.flags & kTileDirectStore) && p.tile.h.src.mode == kRecordMajor) {
+            // direct store of a small record (at most 32 bytes) from a
+            // record-major source runs fastest with tiles of about 4 KiB and
+            // one wave per workgroup (+2-5% on the particle pairs; a
+            // field-major source loses as much, its leaf spans being short),
+            // as long as every leaf span keeps 256 bytes
+            uint64_t t2 = t;
+            while (t2 > 128 && t2 * std::max<uint64_t>(rq.record.packed_size, 1) > 4096)
+                t2 /= 2;
+            uint32_t smin = ~0u;
+            for (const Leaf& l : rq.record.leaves)
+                smin = std::min(smin, l.size);
+            if (t2 < t && t2 * std::max<uint64_t>(rq.record.packed_size, 1) <= 4096 && t2 * smin >= 256) {
+                Plan q = p;
+                q.threads = 64;
+                if (fill_tile(rq, uint32_t(t2), kMaxLdsBytes, q) && (q.tile.h.flags & kTileDirectStore))
+                    p = q;
+            }
+        }
         if (ok) {
             tile_grid(p, wg_per_cu);
             return p;
