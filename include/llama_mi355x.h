@@ -188,9 +188,10 @@ typedef struct {
     uint32_t flags;        /* LLAMA_COPY_* bits */
 } llama_copy_options;
 
-/* TILE: always stage the destination through LDS (by default a field-major
- * destination with 16-byte aligned leaf spans is gathered from the source
- * tile and stored from registers). */
+/* TILE: always stage the destination through LDS (LLAMA_TILE_STAGED).  By
+ * default the planner takes, where the layouts allow it, a mode that skips
+ * one of the two LDS regions: LLAMA_TILE_DIRECT_STORE, LLAMA_TILE_GATHER_STORE
+ * or LLAMA_TILE_DIRECT_LOAD. */
 #define LLAMA_COPY_NO_DIRECT 1u
 
 /* TILE: move a misaligned value byte by byte (by default a 2-, 4- or 8-byte
@@ -212,6 +213,17 @@ typedef struct {
 int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
                   const llama_blob* dst_blobs, const llama_copy_options* options, void* stream);
 
+/* How a TILE copy moves one tile (llama_plan_info.tile_mode). */
+typedef enum {
+    LLAMA_TILE_STAGED = 1,       /* source span(s) -> LDS -> destination region in LDS -> destination span(s) */
+    LLAMA_TILE_DIRECT_STORE = 2, /* field-major (or long-run AoSoA) destination: 16-byte granules of one
+                                    leaf gathered from the staged source and stored from registers */
+    LLAMA_TILE_DIRECT_LOAD = 3,  /* field-major (or long-run AoSoA) source: granules loaded into registers
+                                    and written to the destination region in LDS */
+    LLAMA_TILE_GATHER_STORE = 4  /* record-major destination of whole 4-byte words: every 16-byte granule
+                                    of the destination span assembled word by word from the staged source */
+} llama_tile_mode;
+
 /* What llama_copy_ex would do for this pair with these options (NULL: the
  * defaults), without touching any blob. */
 typedef struct {
@@ -225,6 +237,8 @@ typedef struct {
     uint64_t tiles;         /* TILE: tiles of tile_records records */
     uint64_t read_bytes;    /* bytes of source blobs the copy reads */
     uint64_t write_bytes;   /* bytes of destination blobs the copy writes */
+    uint32_t tile_mode;     /* TILE: llama_tile_mode; 0 for the other paths */
+    uint32_t reserved;      /* 0 */
 } llama_plan_info;
 
 /* What a copy of this pair with these options would launch, without blobs:

@@ -88,7 +88,7 @@ void BatchTable::add(const Request& rq, uint32_t threads, uint32_t tile_records,
     llama_copy_options o{LLAMA_PATH_AUTO, tile_records, threads, 0, flags};
     Plan p;
     if (tile_records) {
-        p = make_plan(rq, &o);
+        p = make_plan(rq, &o, false);
     } else {
         // Every workgroup of the launch reserves the same LDS and about five
         // fit a compute unit, so the bytes in flight per compute unit grow
@@ -111,7 +111,7 @@ void BatchTable::add(const Request& rq, uint32_t threads, uint32_t tile_records,
         uint32_t T = start;
         for (; T >= 16 && !found; T /= 2) {
             o.tile_records = T;
-            p = make_plan(rq, &o);
+            p = make_plan(rq, &o, false);
             found = p.path == LLAMA_PATH_STREAM || p.path == LLAMA_PATH_EMPTY ||
                     (p.path == LLAMA_PATH_TILE && p.tile.h.lds_bytes <= kBatchLdsBytes);
         }

@@ -168,6 +168,15 @@ int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, con
         info->tiles = p.tiles;
         info->read_bytes = p.read_bytes;
         info->write_bytes = p.write_bytes;
+        info->tile_mode = 0;
+        info->reserved = 0;
+        if (p.path == LLAMA_PATH_TILE) {
+            const uint32_t f = p.tile.h.flags;
+            info->tile_mode = (f & kTileDirectStore)   ? LLAMA_TILE_DIRECT_STORE
+                              : (f & kTileDirectLoad)  ? LLAMA_TILE_DIRECT_LOAD
+                              : (f & kTileGatherStore) ? LLAMA_TILE_GATHER_STORE
+                                                       : LLAMA_TILE_STAGED;
+        }
     });
 }
 

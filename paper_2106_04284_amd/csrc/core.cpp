@@ -512,15 +512,56 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
         a.dst.lds_bytes = 0;
         a.lds_bytes = sb;
     }
+    const bool preserve = preserve_padding(rq, p);
+    // gather store: a record-major destination whose blocks are whole 4-byte
+    // words of values or padding, every tile span 16-byte aligned; a source
+    // with more lanes per block than the destination needs leaf sizes that
+    // are powers of two (the lane runs of a block then advance by shifts)
+    const uint64_t gwords = rq.dst.block / 4;
+    bool gather = !direct && !preserve && p.gather_ok && !(p.flags_in & kPlanNoDirect) &&
+                  a.dst.mode == kRecordMajor && rq.dst.lanes <= kGatherMaxLanes && rq.dst.block % 4 == 0 &&
+                  gwords >= 2 && gwords <= kGatherMaxWords && rq.dst_ptr[0] % 16 == 0 && a.dst.tile_bytes % 16 == 0 &&
+                  (a.dst.tile_bytes / 4) * gwords < (uint64_t(1) << 32) &&
+                  (a.src.mode == kFieldMajor || rq.src.block % 4 == 0);
+    const bool more_lanes = a.src.mode == kFieldMajor || rq.src.lanes > rq.dst.lanes;
+    for (size_t f = 0; f < F && gather; f++) {
+        const TileEntry& e = ta.e[f];
+        gather = e.size % 4 == 0 && rq.dst.base[f] % 4 == 0 && e.src_pos % 4 == 0 && (!more_lanes || is_pow2(e.size));
+    }
+    const uint32_t table_bytes = uint32_t((gwords * 4 + 15) / 16 * 16);
+    if (gather && uint64_t(sb) + table_bytes <= std::min<uint64_t>(lds_limit, kHardLdsBytes)) {
+        a.flags |= kTileGatherStore;
+        a.dst.lds_base = sb;
+        a.dst.lds_bytes = table_bytes;
+        a.lds_bytes = sb + table_bytes;
+        TileGather& g = ta.gather;
+        g.words = uint32_t(gwords);
+        g.magic = uint32_t(((uint64_t(1) << 32) + gwords - 1) / gwords);
+        const uint32_t lgd = a.dst.log2_lanes;
+        if (!more_lanes) { // at most L_d source lanes: block b starts L_d / L_s source blocks further
+            g.q = 0;
+            g.mq = 0;
+            g.kq = uint32_t((rq.dst.lanes >> a.src.log2_lanes) * rq.src.block);
+        } else if (a.src.mode == kFieldMajor) { // block b starts b * L_d values further in each leaf span
+            g.q = 31;
+            g.mq = 0x7FFFFFFFu;
+            g.kq = 0;
+        } else {
+            g.q = a.src.log2_lanes - lgd;
+            g.mq = (1u << g.q) - 1u;
+            g.kq = uint32_t(rq.src.block);
+        }
+        for (size_t f = 0; f < F; f++)
+            ta.e[f].dst_pos = uint32_t(rq.dst.base[f]); // the value of lane 0 in a destination block
+    }
     // direct load: source leaf values in 16-byte granules of one leaf,
     // starting 16-byte aligned, leaf sizes 4, 8 or 16, destination positions
     // aligned to the leaf size, and at most kDirectLoadSlots granule slots
     // per thread
     // (a kept destination padding needs the destination region loaded first)
-    const bool preserve = preserve_padding(rq, p);
     if (preserve)
         a.flags |= kTilePreserve;
-    bool dload = !direct && !preserve && !(p.flags_in & kPlanNoDirect);
+    bool dload = !direct && !(a.flags & kTileGatherStore) && !preserve && !(p.flags_in & kPlanNoDirect);
     uint32_t slots = 0;
     std::vector<uint32_t> first(F, 0);
     for (size_t f = 0; f < F && dload; f++) {
@@ -643,13 +684,13 @@ void fill_naive(const Request& rq, Plan& p)
 } // namespace
 
 namespace {
-Plan make_plan_raw(const Request& rq, const llama_copy_options* opt);
+Plan make_plan_raw(const Request& rq, const llama_copy_options* opt, bool gather_ok);
 }
 
 // The plan for `opt`; when the caller leaves the path and tile size to the
 // library, a tuning-cache entry for this class of copies supplies them (the
 // caller's threads and wg_per_cu still win).
-Plan make_plan(const Request& rq, const llama_copy_options* opt)
+Plan make_plan(const Request& rq, const llama_copy_options* opt, bool gather_ok)
 {
     if (!opt || (opt->path == LLAMA_PATH_AUTO && opt->tile_records == 0)) {
         llama_copy_options tuned;
@@ -660,20 +701,21 @@ Plan make_plan(const Request& rq, const llama_copy_options* opt)
                 tuned.wg_per_cu = opt->wg_per_cu;
             tuned.flags = (tuned.flags & kTuneFlags) | (opt ? opt->flags : 0u);
             try {
-                return make_plan_raw(rq, &tuned);
+                return make_plan_raw(rq, &tuned, gather_ok);
             } catch (const Error&) {
                 // the cached parameters do not apply here; plan from scratch
             }
         }
     }
-    return make_plan_raw(rq, opt);
+    return make_plan_raw(rq, opt, gather_ok);
 }
 
 namespace {
 
-Plan make_plan_raw(const Request& rq, const llama_copy_options* opt)
+Plan make_plan_raw(const Request& rq, const llama_copy_options* opt, bool gather_ok)
 {
     Plan p;
+    p.gather_ok = gather_ok;
     p.read_bytes = total_bytes(rq.src.blob_size);
     p.write_bytes = total_bytes(rq.dst.blob_size);
     uint32_t want = opt ? opt->path : uint32_t(LLAMA_PATH_AUTO);

@@ -58,6 +58,22 @@ struct TileEntry {
 // every byte on its own.
 constexpr uint32_t kMoveSplit = 1u << 3;
 
+// kTileGatherStore: where word w of a destination block finds its source.
+// The word table (in LDS, at dst.lds_base) holds, for every 4-byte word w of
+// destination block 0, the LDS byte p0 of its source word (bits 0-17), log2
+// of the destination's lane-run bytes L_d * size of its leaf (bits 18-22),
+// its record j < L_d inside the block (bits 23-30), or bit 31 for padding.
+// Word w of block b then reads LDS byte
+//   p0 + (b >> q) * kq + ((b & mq) << run)
+// (a source with at most L_d lanes per block: q = 0, mq = 0 and kq the source
+// bytes of L_d records; a source with more: q = log2 of the lane ratio,
+// mq = 2^q - 1, kq the source block).
+struct TileGather {
+    uint32_t words; // 4-byte words per destination block
+    uint32_t magic; // ceil(2^32 / words): u / words == mulhi(u, magic) for u * words < 2^32
+    uint32_t q, mq, kq, pad;
+};
+
 struct TileHeader {
     uint64_t n;         // records with values
     uint64_t npad;      // records the destination spans (>= n)
@@ -66,7 +82,7 @@ struct TileHeader {
     uint32_t num_leaves;
     uint32_t num_entries; // leaves, then gaps
     uint32_t lds_bytes;
-    uint32_t flags;       // kTileDirectStore, kTileDirectLoad, kTilePreserve
+    uint32_t flags;       // kTileDirectStore, kTileDirectLoad, kTilePreserve, kTileGatherStore
     uint32_t slots;       // kTileDirectLoad: granule slots of a tile (a multiple of 64)
     TileSide src, dst;
 };
@@ -93,9 +109,26 @@ constexpr uint32_t kDirectLoadSlots = 8;
 // only for records with values.
 constexpr uint32_t kTilePreserve = 4;
 
+// Destination record-major (AoS, or AoSoA with L_d <= 256 lanes), 16-byte
+// aligned tile spans, and every 4-byte word of a destination block either one
+// word of a value (leaf sizes and offsets multiples of 4) or padding: the
+// source is staged in LDS as usual, then every thread assembles whole 16-byte
+// granules of the destination span word by word from the source region (the
+// word table maps each word to its source) and stores them; the tile needs no
+// destination region and no second barrier.  A source with more lanes per
+// block than the destination (field-major included) needs leaf sizes that are
+// powers of two.
+constexpr uint32_t kTileGatherStore = 8;
+constexpr uint32_t kGatherMaxWords = 4096; // word table entries (16 KiB of LDS)
+constexpr uint32_t kGatherMaxLanes = 256;
+
+// The gather geometry follows the entries, so that the header and entries
+// keep their offsets in the argument block (entries 16-byte aligned; a
+// header grown by 24 bytes measured 3-5% slower for the other modes).
 struct TileArgs {
     TileHeader h;
     TileEntry e[kTileMaxEntries];
+    TileGather gather; // kTileGatherStore
 };
 static_assert(sizeof(TileArgs) <= 4096, "kernel arguments are limited to 4 KiB");
 

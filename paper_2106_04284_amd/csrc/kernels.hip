@@ -8,6 +8,11 @@
 //                 are moved inside LDS from source to destination positions
 //                 (one leaf per step, lanes over records), and the destination
 //                 span(s) are written back with 16-byte coalesced stores.
+//                 Three modes keep one side out of LDS: direct store and
+//                 gather store build 16-byte destination granules in
+//                 registers from the staged source (by leaf, or word by word
+//                 through a table); direct load loads source granules into
+//                 registers and writes them to the destination region.
 //  stream_kernel  long contiguous runs (SoA <-> SoA, identical layouts),
 //                 16-byte loads and stores, no LDS.
 //  naive_kernel   the element-wise baseline: one thread per record, each leaf
@@ -374,6 +379,69 @@ __device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries en
     }
 }
 
+// Gather store: builds the word table of a record-major destination block
+// (kTileGatherStore) in LDS; entry w names the source of 4-byte word w of
+// destination block 0, or padding.  Leaf f's values in a destination block
+// are L_d consecutive values from byte e.dst_pos.  Runs once per workgroup;
+// the first tile's barrier publishes it.
+template <typename Entries>
+__device__ __forceinline__ void gather_table(const TileHeader& h, const TileGather& gg, Entries ent, uint8_t* lds)
+{
+    uint32_t* tab = (uint32_t*)(lds + h.dst.lds_base);
+    const uint32_t L = 1u << h.dst.log2_lanes;
+    for (uint32_t w = threadIdx.x; w < gg.words; w += blockDim.x) {
+        const uint32_t b = w * 4u;
+        uint32_t x = 1u << 31;
+        for (uint32_t f = 0; f < h.num_leaves; f++) {
+            const auto& e = ent(f);
+            const uint32_t off = b - e.dst_pos; // wraps above L * size when b precedes the leaf
+            if (off < L * e.size) {
+                const uint32_t j = off / e.size, k = off - j * e.size;
+                const uint32_t p0 = e.src_pos + (j >> h.src.pos_lg) * h.src.pos_k + (j & h.src.pos_m) * e.size + k;
+                x = p0 | (uint32_t(__builtin_ctz(L * e.size)) << 18) | (j << 23);
+            }
+        }
+        tab[w] = x;
+    }
+}
+
+// Gather store of one tile: every thread assembles 16-byte granules of the
+// destination span word by word from the source region and stores them;
+// padding words and records >= nv are zero.
+__device__ __forceinline__ void gather_store_tile(const TileHeader& h, const TileGather& gg, uint64_t t, uint32_t nv,
+                                                  uint32_t nd, uint32_t tid, uint32_t nthr, const uint8_t* lds)
+{
+    const uint32_t* tab = (const uint32_t*)(lds + h.dst.lds_base);
+    const uint32_t lgd = h.dst.log2_lanes;
+    const uint32_t words = uint32_t(((uint64_t(nd) + h.dst.lanes - 1) >> lgd) * h.dst.block) >> 2;
+    const uint64_t gbase = h.dst.span_base + t * h.dst.tile_bytes;
+    for (uint32_t u = tid * 4u; u < words; u += nthr * 4u) {
+        uint32_t blk = __umulhi(u, gg.magic);
+        uint32_t w = u - blk * gg.words;
+        uint32_t v[4];
+#pragma unroll
+        for (uint32_t c = 0; c < 4; c++) {
+            const uint32_t e = tab[w];
+            const uint32_t r = (blk << lgd) + ((e >> 23) & 255u);
+            const uint32_t pos = (e & 0x3FFFFu) + (blk >> gg.q) * gg.kq + ((blk & gg.mq) << ((e >> 18) & 31u));
+            v[c] = (e >> 31) == 0 && r < nv ? *(const uint32_t*)(lds + pos) : 0u;
+            if (++w == gg.words) {
+                w = 0;
+                blk++;
+            }
+        }
+        const uint64_t a = gbase + uint64_t(u) * 4u;
+        if (u + 4u <= words) {
+            *(GLOBAL u32x4*)a = u32x4{v[0], v[1], v[2], v[3]};
+        } else {
+#pragma unroll
+            for (uint32_t c = 0; c < 4; c++)
+                if (u + c < words)
+                    *(GLOBAL uint32_t*)(a + 4u * c) = v[c];
+        }
+    }
+}
+
 // One tile: every wave issues its share of the source loads straight into
 // LDS, then all threads move the values to their destination positions
 // inside LDS, then all threads store the destination span(s).  `ent(k)`
@@ -381,10 +449,11 @@ __device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries en
 // Kernel variants: kModeAny dispatches on the plan's flags at run time (the
 // batch kernel); the single-copy kernel is compiled once per mode so that each
 // mode gets its own register allocation.
-enum : uint32_t { kModeAny = 0, kModeStaged = 1, kModeDirectStore = 2, kModeDirectLoad = 3 };
+enum : uint32_t { kModeAny = 0, kModeStaged = 1, kModeDirectStore = 2, kModeDirectLoad = 3, kModeGatherStore = 4 };
 
 template <uint32_t Mode, typename Entries>
-__device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint64_t t, uint8_t* lds)
+__device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint64_t t, uint8_t* lds,
+                                          const TileGather* gg = nullptr)
 {
     const bool dload = Mode == kModeDirectLoad || (Mode == kModeAny && (h.flags & kTileDirectLoad));
     const bool dstore = Mode == kModeDirectStore || (Mode == kModeAny && (h.flags & kTileDirectStore));
@@ -437,6 +506,13 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
                            nthr, (e.move >> 8) & 4095u, lds);
             }
         }
+        return;
+    }
+
+    if (Mode == kModeGatherStore) {
+        // ---- 2'''. assemble every destination granule word by word from
+        //           the source region and store it; no destination region
+        gather_store_tile(h, *gg, t, nv, nd, tid, nthr, lds);
         return;
     }
 
@@ -512,8 +588,10 @@ __global__ void __launch_bounds__(1024) tile_kernel(const TileArgs a)
         t = x * q + min(x, rem) + k;
         stride = nt;
     }
+    if (Mode == kModeGatherStore)
+        gather_table(a.h, a.gather, ent, lds);
     for (; t < nt; t += stride) {
-        tile_body<Mode>(a.h, ent, t, lds);
+        tile_body<Mode>(a.h, ent, t, lds, &a.gather);
         if (t + stride < nt)
             __syncthreads();
     }
@@ -767,7 +845,7 @@ void set_attributes()
     if (g_attr_set)
         return;
     for (const void* k : {(const void*)tile_kernel<kModeStaged>, (const void*)tile_kernel<kModeDirectStore>,
-                          (const void*)tile_kernel<kModeDirectLoad>})
+                          (const void*)tile_kernel<kModeDirectLoad>, (const void*)tile_kernel<kModeGatherStore>})
         check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes)),
                   "hipFuncSetAttribute(tile_kernel)");
     check_hip(hipFuncSetAttribute((const void*)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -815,6 +893,9 @@ void launch(const Plan& p, void* stream_ptr)
                                p.tile);
         else if (p.tile.h.flags & kTileDirectStore)
             hipLaunchKernelGGL(tile_kernel<kModeDirectStore>, dim3(grid), dim3(p.threads), p.tile.h.lds_bytes,
+                               stream, p.tile);
+        else if (p.tile.h.flags & kTileGatherStore)
+            hipLaunchKernelGGL(tile_kernel<kModeGatherStore>, dim3(grid), dim3(p.threads), p.tile.h.lds_bytes,
                                stream, p.tile);
         else
             hipLaunchKernelGGL(tile_kernel<kModeStaged>, dim3(grid), dim3(p.threads), p.tile.h.lds_bytes, stream,

@@ -200,7 +200,7 @@ void autotune(const Request& rq, void* stream_ptr, int reps, llama_copy_options&
         if ((c.flags & LLAMA_COPY_NO_DIRECT) && p.path == LLAMA_PATH_TILE) {
             llama_copy_options d = c;
             d.flags = 0;
-            if (!(make_plan(rq, &d).tile.h.flags & (kTileDirectStore | kTileDirectLoad)))
+            if (!(make_plan(rq, &d).tile.h.flags & (kTileDirectStore | kTileDirectLoad | kTileGatherStore)))
                 continue;
         }
         if (run_and_hash(rq, p, stream, 0x5A) != want)

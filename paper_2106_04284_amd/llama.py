@@ -25,6 +25,7 @@ KINDS = {"aos_packed": AOS_PACKED, "aos_aligned": AOS_ALIGNED, "soa_single": SOA
 
 PATH_AUTO, PATH_STREAM, PATH_TILE, PATH_NAIVE, PATH_EMPTY = 0, 1, 2, 3, 4
 PATH_NAMES = {PATH_STREAM: "stream", PATH_TILE: "tile", PATH_NAIVE: "naive", PATH_EMPTY: "empty"}
+TILE_MODE_NAMES = {1: "staged", 2: "direct_store", 3: "direct_load", 4: "gather_store"}
 
 OK = 0
 E_INVALID_ARG, E_RECORD_MISMATCH, E_EXTENT_MISMATCH, E_BLOB_TOO_SMALL = -1, -2, -3, -4
@@ -70,7 +71,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("path", ctypes.c_uint32), ("tile_records", ctypes.c_uint32), ("threads", ctypes.c_uint32),
                 ("lds_bytes", ctypes.c_uint32), ("workgroups", ctypes.c_uint64), ("runs", ctypes.c_uint32),
                 ("wg_per_cu", ctypes.c_uint32), ("tiles", ctypes.c_uint64), ("read_bytes", ctypes.c_uint64),
-                ("write_bytes", ctypes.c_uint64)]
+                ("write_bytes", ctypes.c_uint64), ("tile_mode", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class CopyItem(ctypes.Structure):
@@ -325,7 +326,8 @@ def plan(src: Mapping, dst: Mapping, path=PATH_AUTO, tile_records=0, threads=0, 
     return {"path": PATH_NAMES.get(info.path, "?"), "tile_records": info.tile_records, "threads": info.threads,
             "lds_bytes": info.lds_bytes, "workgroups": info.workgroups, "runs": info.runs,
             "wg_per_cu": info.wg_per_cu, "tiles": info.tiles,
-            "read_bytes": info.read_bytes, "write_bytes": info.write_bytes}
+            "read_bytes": info.read_bytes, "write_bytes": info.write_bytes,
+            "tile_mode": TILE_MODE_NAMES.get(info.tile_mode)}
 
 
 # --------------------------------------------------------------------------

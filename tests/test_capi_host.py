@@ -129,6 +129,50 @@ def test_planner_classification_all_pairs(orc, name, n):
                 assert p["path"] == "tile", (a, b)
 
 
+def test_tile_modes():
+    """The tile mode the planner takes: a destination in 16-byte granules of
+    one leaf stores from registers; a record-major destination made of whole
+    4-byte words gathers word by word from the staged source; a source in
+    granules of one leaf loads into registers; anything else stages both
+    sides.  LLAMA_COPY_NO_DIRECT stages every tile, and a destination whose
+    padding is kept never gathers."""
+    def plan(name, a, b, n=1 << 20, **kw):
+        r = L.Record(W.RECORDS[name])
+        return L.plan(L.Mapping(r, a[0], [n], a[1]), L.Mapping(r, b[0], [n], b[1]), **kw)
+
+    def mode(*args, **kw):
+        return plan(*args, **kw)["tile_mode"]
+    A, AA, S, M = ("aos_packed", 0), ("aos_aligned", 0), ("soa_single", 0), ("soa_multi", 0)
+    Q8, Q32 = ("aosoa", 8), ("aosoa", 32)
+    # particle, 4-byte leaves: AoSoA32 lane runs are 128 bytes (one cache
+    # line), AoSoA8 runs 32 bytes
+    assert mode("particle", A, S) == "direct_store"
+    assert mode("particle", A, Q32) == "direct_store"
+    assert mode("particle", A, Q8) == "gather_store"
+    assert mode("particle", Q8, AA) == "gather_store"
+    assert mode("particle", S, A) == "gather_store"
+    # lbm: 8-byte leaves and a 4-byte flag word in a 160-byte aligned cell
+    assert mode("lbm", M, AA) == "gather_store"
+    assert mode("lbm", Q32, AA) == "gather_store"
+    assert mode("lbm", AA, M) == "direct_store"
+    # a u8 leaf (mixed) or u16 / bool leaves (listing1) share words with
+    # other leaves or padding: no gather
+    assert mode("mixed", M, AA) == "staged"
+    assert mode("listing1", M, AA) == "staged"
+    assert mode("particle", A, Q8, flags=L.COPY_NO_DIRECT) == "staged"
+    assert mode("lbm", M, AA, flags=L.COPY_PRESERVE_PADDING) == "staged"
+    assert mode("particle", A, Q8, n=1031, flags=L.COPY_PRESERVE_PADDING) == "staged"  # 1031 = 128 * 8 + 7
+    assert mode("particle", A, Q8, flags=L.COPY_PRESERVE_PADDING) == "gather_store"  # no padding to keep
+    assert plan("particle", A, S)["tile_mode"] == "direct_store"
+    assert plan("particle", A, A)["tile_mode"] is None  # identical layouts: no tiles
+    # LDS of a gathering tile: the source region (512 records of 28 bytes and
+    # room for the 16-byte phase) plus the word table of one destination
+    # block (8 records of 28 bytes: 56 words), and no destination region
+    p = plan("particle", A, Q8)
+    assert p["tile_records"] == 512
+    assert p["lds_bytes"] == (512 * 28 + 30) // 16 * 16 + 8 * 28
+
+
 @pytest.mark.parametrize("name", ["particle", "mixed", "lbm", "listing1"])
 def test_byte_accounting(orc, name):
     """The bytes a plan reports (and the benchmark counts) are the blob bytes

@@ -204,6 +204,33 @@ def test_odd_record_sizes(L, orc, pair, offsets, flags, name):
              dst_off=offsets[1], flags=flags)
 
 
+# record-major destinations made of whole 4-byte words: the gather-store tile
+# mode, over tile sizes, thread counts, a persistent grid (several tiles per
+# workgroup, one word table), ragged record counts and source blobs at every
+# 4-byte phase; destinations 16-byte aligned (dst offset 16), and at offset 4,
+# where the planner falls back to the staged mode
+GATHER_CASES = [("particle", ("aos_packed", 0), ("aosoa", 8)), ("particle", ("aosoa", 8), ("aos_aligned", 0)),
+                ("particle", ("soa_multi", 0), ("aos_packed", 0)), ("particle", ("aosoa", 64), ("aosoa", 8)),
+                ("lbm", ("soa_multi", 0), ("aos_aligned", 0)), ("lbm", ("aosoa", 32), ("aos_aligned", 0)),
+                ("lbm", ("aos_aligned", 0), ("aosoa", 8)), ("lbm", ("aosoa", 64), ("aosoa", 8))]
+GATHER_RUNS = [(77, {}), (1031, {}), (4099, {"tile_records": 16}), (5000, {"tile_records": 64, "threads": 64}),
+               (20000, {"tile_records": 256, "threads": 1024}), (30011, {"tile_records": 16, "wg_per_cu": 1})]
+
+
+@pytest.mark.parametrize("case", GATHER_CASES, ids=[f"{c[0]}-{_name(c[1])}-{_name(c[2])}" for c in GATHER_CASES])
+@pytest.mark.parametrize("run", GATHER_RUNS, ids=[f"n{n}-{'-'.join(f'{k}{v}' for k, v in o.items())}"
+                                                  for n, o in GATHER_RUNS])
+@pytest.mark.parametrize("offsets", [(0, 0), (4, 16), (8, 0), (12, 4)])
+def test_gather_store(L, orc, case, run, offsets):
+    name, a, b = case
+    n, opts = run
+    r = L.Record(W.RECORDS[name])
+    assert L.plan(L.Mapping(r, a[0], [n], a[1]), L.Mapping(r, b[0], [n], b[1]), **opts)["tile_mode"] == \
+        "gather_store"
+    run_case(L, orc, W.RECORDS[name], a, b, [n], seed=n + offsets[0], src_off=offsets[0], dst_off=offsets[1],
+             **opts)
+
+
 @pytest.mark.parametrize("seed", range(24))
 def test_random_records(L, orc, seed):
     g = random.Random(seed)
