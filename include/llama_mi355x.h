@@ -238,7 +238,9 @@ typedef struct {
     uint64_t read_bytes;    /* bytes of source blobs the copy reads */
     uint64_t write_bytes;   /* bytes of destination blobs the copy writes */
     uint32_t tile_mode;     /* TILE: llama_tile_mode; 0 for the other paths */
-    uint32_t reserved;      /* 0 */
+    uint32_t stream_stores; /* TILE: 1 when the destination's 16-byte stores carry the nontemporal
+                               hint (destinations of 1 GiB or more, several times the 256 MB
+                               Infinity Cache); 0 otherwise */
 } llama_plan_info;
 
 /* What a copy of this pair with these options would launch, without blobs:

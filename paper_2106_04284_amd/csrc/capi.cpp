@@ -169,13 +169,14 @@ int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, con
         info->read_bytes = p.read_bytes;
         info->write_bytes = p.write_bytes;
         info->tile_mode = 0;
-        info->reserved = 0;
+        info->stream_stores = 0;
         if (p.path == LLAMA_PATH_TILE) {
             const uint32_t f = p.tile.h.flags;
             info->tile_mode = (f & kTileDirectStore)   ? LLAMA_TILE_DIRECT_STORE
                               : (f & kTileDirectLoad)  ? LLAMA_TILE_DIRECT_LOAD
                               : (f & kTileGatherStore) ? LLAMA_TILE_GATHER_STORE
                                                        : LLAMA_TILE_STAGED;
+            info->stream_stores = (f & kTileStreamStores) ? 1u : 0u;
         }
     });
 }

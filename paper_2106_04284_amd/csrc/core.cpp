@@ -602,6 +602,8 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
         first_wave = uint32_t((first_wave + (granules + 63) / 64) % nwaves);
         first_thread = uint32_t((first_thread + granules) % p.threads);
     }
+    if (total_bytes(rq.dst.blob_size) >= kStreamStoreBytes)
+        a.flags |= kTileStreamStores;
     p.path = LLAMA_PATH_TILE;
     p.lds_bytes = a.lds_bytes;
     p.tiles = a.num_tiles;

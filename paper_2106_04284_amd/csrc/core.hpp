@@ -135,5 +135,8 @@ constexpr uint32_t kDefaultTileBytes = 16384;  // TILE: target source bytes per 
 constexpr uint32_t kMaxLdsBytes = 65536;       // TILE: LDS budget per workgroup for the default plan
 constexpr uint32_t kHardLdsBytes = 160 * 1024; // LDS of one gfx950 compute unit
 constexpr uint32_t kMaxWavesPerCu = 32;
+// TILE: destinations of at least this many bytes get nontemporal stores
+// (4x the 256 MB Infinity Cache, which then holds at most a quarter of them)
+constexpr uint64_t kStreamStoreBytes = uint64_t(1) << 30;
 
 } // namespace llama

@@ -82,7 +82,7 @@ struct TileHeader {
     uint32_t num_leaves;
     uint32_t num_entries; // leaves, then gaps
     uint32_t lds_bytes;
-    uint32_t flags;       // kTileDirectStore, kTileDirectLoad, kTilePreserve, kTileGatherStore
+    uint32_t flags;       // kTileDirectStore, kTileDirectLoad, kTilePreserve, kTileGatherStore, kTileStreamStores
     uint32_t slots;       // kTileDirectLoad: granule slots of a tile (a multiple of 64)
     TileSide src, dst;
 };
@@ -120,6 +120,10 @@ constexpr uint32_t kTilePreserve = 4;
 // powers of two.
 constexpr uint32_t kTileGatherStore = 8;
 constexpr uint32_t kGatherMaxWords = 4096; // word table entries (16 KiB of LDS)
+
+// The tile's 16-byte destination stores carry the nontemporal hint: set for
+// destinations several times larger than the 256 MB Infinity Cache.
+constexpr uint32_t kTileStreamStores = 16;
 constexpr uint32_t kGatherMaxLanes = 256;
 
 // The gather geometry follows the entries, so that the header and entries

@@ -55,6 +55,33 @@ __device__ __forceinline__ T load_const(const CONSTANT T* p)
     return v;
 }
 
+// 16-byte loads of source bytes, which a copy reads exactly once: the
+// nontemporal hint streams them past the caches (a plain copy measured
+// 6.19 -> 6.52 TB/s with it, reads alone 6.79 -> 7.09 TB/s).
+__device__ __forceinline__ u32x4 load_once(const GLOBAL u32x4* p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
+// The same at a 4-byte-aligned address.
+__device__ __forceinline__ u32x4 load_once_a4(const GLOBAL u32x4_a4* p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
+// A 16-byte store of destination bytes; kStream marks it nontemporal, for
+// destinations far larger than the 256 MB Infinity Cache (tile copies of
+// 1.9 GB measured +3-5% with it; copies of a few hundred MB lose up to 9%,
+// because plain stores can leave part of the writes in that cache).
+template <bool kStream>
+__device__ __forceinline__ void store16(GLOBAL u32x4* p, u32x4 v)
+{
+    if constexpr (kStream)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 // One 16-byte global load per active lane, written by the memory system
 // straight into LDS at m0 + 16 * lane (global_load_lds_dwordx4).  Issued as
 // inline assembly so that the compiler does not wait for these loads at every
@@ -64,7 +91,7 @@ __device__ __forceinline__ T load_const(const CONSTANT T* p)
 #pragma clang diagnostic ignored "-Winline-asm" // m0 is written here and used by nothing else in these kernels
 __device__ __forceinline__ void lds_dma16(uint64_t gaddr, uint32_t lds_addr)
 {
-    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(gaddr), "s"(lds_addr) : "memory", "m0");
+    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off nt" : : "v"(gaddr), "s"(lds_addr) : "memory", "m0");
 }
 #pragma clang diagnostic pop
 
@@ -92,6 +119,7 @@ __device__ __forceinline__ void load_span(uint64_t gstart, uint32_t len, uint32_
 // whole granules with 16-byte stores, the partial first and last granule byte
 // by byte so that no byte outside the span is written.  Granule gi goes to
 // thread (gi + rot) mod nthr, so that short spans spread over the waves.
+template <bool kStream>
 __device__ __forceinline__ void store_span(uint64_t gstart, uint32_t len, uint32_t lds_region, uint32_t tid,
                                            uint32_t nthr, uint32_t rot, const uint8_t* lds)
 {
@@ -104,7 +132,7 @@ __device__ __forceinline__ void store_span(uint64_t gstart, uint32_t len, uint32
         const uint32_t hi = min(16u, end - gi * 16u);
         const uint8_t* lp = lds + lds_region + gi * 16u;
         if (lo == 0 && hi == 16) {
-            *(GLOBAL u32x4*)(g0 + uint64_t(gi) * 16u) = *(const u32x4*)lp;
+            store16<kStream>((GLOBAL u32x4*)(g0 + uint64_t(gi) * 16u), *(const u32x4*)lp);
         } else {
             GLOBAL uint8_t* gp = (GLOBAL uint8_t*)(g0 + uint64_t(gi) * 16u);
             for (uint32_t b = lo; b < hi; b++)
@@ -255,7 +283,7 @@ __device__ __forceinline__ T src_value(const uint8_t* lds, uint32_t sp, const Ti
 // 16 / size consecutive records from the source region; records >= nv (AoSoA
 // lanes past the last record) are zero; a granule that passes record nd is
 // stored value by value.  `gdst` is the leaf's tile base on side d.
-template <typename T, bool kDstRecordMajor>
+template <typename T, bool kDstRecordMajor, bool kStream>
 __device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t sp, const TileSide& s,
                                                   const TileSide& d, uint64_t gdst, uint32_t nv, uint32_t nd,
                                                   uint32_t tid, uint32_t nthr, uint32_t rot)
@@ -274,7 +302,7 @@ __device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t s
         constexpr uint32_t lg = sizeof(T) == 16 ? 4 : sizeof(T) == 8 ? 3 : sizeof(T) == 4 ? 2 : sizeof(T) == 2 ? 1 : 0;
         const uint64_t a = leaf_granule_addr<kDstRecordMajor>(gdst, d, g, lg);
         if (r0 + per <= nd) {
-            *(GLOBAL u32x4*)a = u.v;
+            store16<kStream>((GLOBAL u32x4*)a, u.v);
         } else {
 #pragma unroll
             for (uint32_t j = 0; j < per; j++)
@@ -285,7 +313,7 @@ __device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t s
 }
 
 // Direct store of a tile: every leaf in turn, at the width of its values.
-template <bool kDstRecordMajor, typename Entries>
+template <bool kDstRecordMajor, bool kStream, typename Entries>
 __device__ __forceinline__ void direct_store_tile(const TileHeader& h, Entries ent, uint64_t t, uint64_t i0,
                                                   uint32_t nv, uint32_t nd, uint32_t tid, uint32_t nthr,
                                                   const uint8_t* lds)
@@ -296,11 +324,11 @@ __device__ __forceinline__ void direct_store_tile(const TileHeader& h, Entries e
         const uint32_t rot = (e.move >> 8) & 4095u;
         const uint32_t sp = e.src_pos;
         switch (e.move & 7u) {
-        case 4: direct_store_leaf<u32x4, kDstRecordMajor>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
-        case 3: direct_store_leaf<uint64_t, kDstRecordMajor>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
-        case 2: direct_store_leaf<uint32_t, kDstRecordMajor>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
-        case 1: direct_store_leaf<uint16_t, kDstRecordMajor>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
-        default: direct_store_leaf<uint8_t, kDstRecordMajor>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
+        case 4: direct_store_leaf<u32x4, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
+        case 3: direct_store_leaf<uint64_t, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
+        case 2: direct_store_leaf<uint32_t, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
+        case 1: direct_store_leaf<uint16_t, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
+        default: direct_store_leaf<uint8_t, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
         }
     }
 }
@@ -329,8 +357,8 @@ __device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries en
         const auto& e = ent(f);
         const uint32_t g = q0 + lane - e.src_pos; // granule within the leaf's values of the tile
         if (g * 16u < nv * e.size)
-            v[j] = *(const GLOBAL u32x4*)leaf_granule_addr<kSrcRecordMajor>(
-                leaf_tile_base<kSrcRecordMajor>(e.src_addr, h.src, t, i0, e.size), h.src, g, e.move & 7u);
+            v[j] = load_once((const GLOBAL u32x4*)leaf_granule_addr<kSrcRecordMajor>(
+                leaf_tile_base<kSrcRecordMajor>(e.src_addr, h.src, t, i0, e.size), h.src, g, e.move & 7u));
     }
     f = 0;
 #pragma unroll
@@ -408,6 +436,7 @@ __device__ __forceinline__ void gather_table(const TileHeader& h, const TileGath
 // Gather store of one tile: every thread assembles 16-byte granules of the
 // destination span word by word from the source region and stores them;
 // padding words and records >= nv are zero.
+template <bool kStream>
 __device__ __forceinline__ void gather_store_tile(const TileHeader& h, const TileGather& gg, uint64_t t, uint32_t nv,
                                                   uint32_t nd, uint32_t tid, uint32_t nthr, const uint8_t* lds)
 {
@@ -432,7 +461,7 @@ __device__ __forceinline__ void gather_store_tile(const TileHeader& h, const Til
         }
         const uint64_t a = gbase + uint64_t(u) * 4u;
         if (u + 4u <= words) {
-            *(GLOBAL u32x4*)a = u32x4{v[0], v[1], v[2], v[3]};
+            store16<kStream>((GLOBAL u32x4*)a, u32x4{v[0], v[1], v[2], v[3]});
         } else {
 #pragma unroll
             for (uint32_t c = 0; c < 4; c++)
@@ -450,11 +479,15 @@ __device__ __forceinline__ void gather_store_tile(const TileHeader& h, const Til
 // batch kernel); the single-copy kernel is compiled once per mode so that each
 // mode gets its own register allocation.
 enum : uint32_t { kModeAny = 0, kModeStaged = 1, kModeDirectStore = 2, kModeDirectLoad = 3, kModeGatherStore = 4 };
+// added to a mode: the tile's 16-byte destination stores are nontemporal
+constexpr uint32_t kModeStreamStores = 8;
 
-template <uint32_t Mode, typename Entries>
+template <uint32_t ModeBits, typename Entries>
 __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint64_t t, uint8_t* lds,
                                           const TileGather* gg = nullptr)
 {
+    constexpr uint32_t Mode = ModeBits & 7u;
+    constexpr bool kStream = (ModeBits & kModeStreamStores) != 0;
     const bool dload = Mode == kModeDirectLoad || (Mode == kModeAny && (h.flags & kTileDirectLoad));
     const bool dstore = Mode == kModeDirectStore || (Mode == kModeAny && (h.flags & kTileDirectStore));
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
@@ -498,11 +531,11 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
         // ---- 2''. the destination region is complete: store it
         if (h.dst.mode == kRecordMajor) {
             const uint32_t len = uint32_t(((uint64_t(nd) + h.dst.lanes - 1) >> h.dst.log2_lanes) * h.dst.block);
-            store_span(h.dst.span_base + t * h.dst.tile_bytes, len, h.dst.lds_base, tid, nthr, 0, lds);
+            store_span<kStream>(h.dst.span_base + t * h.dst.tile_bytes, len, h.dst.lds_base, tid, nthr, 0, lds);
         } else {
             for (uint32_t f = 0; f < h.num_leaves; f++) {
                 const auto& e = ent(f);
-                store_span(field_span_start(e.dst_addr, h.dst, i0, e.size), nd * e.size, e.dst_pos & ~15u, tid,
+                store_span<kStream>(field_span_start(e.dst_addr, h.dst, i0, e.size), nd * e.size, e.dst_pos & ~15u, tid,
                            nthr, (e.move >> 8) & 4095u, lds);
             }
         }
@@ -512,7 +545,7 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     if (Mode == kModeGatherStore) {
         // ---- 2'''. assemble every destination granule word by word from
         //           the source region and store it; no destination region
-        gather_store_tile(h, *gg, t, nv, nd, tid, nthr, lds);
+        gather_store_tile<kStream>(h, *gg, t, nv, nd, tid, nthr, lds);
         return;
     }
 
@@ -520,9 +553,9 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
         // ---- 2'. gather each destination granule from the source region and
         //          store it; no destination region, no second barrier
         if (h.dst.mode == kRecordMajor)
-            direct_store_tile<true>(h, ent, t, i0, nv, ns, tid, nthr, lds);
+            direct_store_tile<true, kStream>(h, ent, t, i0, nv, ns, tid, nthr, lds);
         else
-            direct_store_tile<false>(h, ent, t, i0, nv, ns, tid, nthr, lds);
+            direct_store_tile<false, kStream>(h, ent, t, i0, nv, ns, tid, nthr, lds);
         return;
     }
 
@@ -559,19 +592,20 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     // ---- 3. LDS -> destination span(s)
     if (h.dst.mode == kRecordMajor) {
         const uint32_t len = uint32_t(((uint64_t(nd) + h.dst.lanes - 1) >> h.dst.log2_lanes) * h.dst.block);
-        store_span(h.dst.span_base + t * h.dst.tile_bytes, len, h.dst.lds_base, tid, nthr, 0, lds);
+        store_span<kStream>(h.dst.span_base + t * h.dst.tile_bytes, len, h.dst.lds_base, tid, nthr, 0, lds);
     } else {
         for (uint32_t f = 0; f < h.num_leaves; f++) {
             const auto& e = ent(f);
-            store_span(field_span_start(e.dst_addr, h.dst, i0, e.size), ns * e.size, e.dst_pos & ~15u, tid, nthr,
+            store_span<kStream>(field_span_start(e.dst_addr, h.dst, i0, e.size), ns * e.size, e.dst_pos & ~15u, tid, nthr,
                        (e.move >> 8) & 4095u, lds);
         }
     }
 }
 
-template <uint32_t Mode>
+template <uint32_t ModeBits>
 __global__ void __launch_bounds__(1024) tile_kernel(const TileArgs a)
 {
+    constexpr uint32_t Mode = ModeBits & 7u;
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     auto ent = [&](uint32_t k) -> const TileEntry& { return a.e[k]; };
     const uint64_t nt = a.h.num_tiles;
@@ -591,7 +625,7 @@ __global__ void __launch_bounds__(1024) tile_kernel(const TileArgs a)
     if (Mode == kModeGatherStore)
         gather_table(a.h, a.gather, ent, lds);
     for (; t < nt; t += stride) {
-        tile_body<Mode>(a.h, ent, t, lds, &a.gather);
+        tile_body<ModeBits>(a.h, ent, t, lds, &a.gather);
         if (t + stride < nt)
             __syncthreads();
     }
@@ -628,26 +662,28 @@ __device__ __forceinline__ void copy_run_chunk(uint64_t dst, uint64_t src, uint6
         const GLOBAL u32x4* s = (const GLOBAL u32x4*)(src + head);
         uint64_t g = tid;
         for (; g + 3u * nthr < ng; g += 4u * nthr) {
-            u32x4 v0 = s[g], v1 = s[g + nthr], v2 = s[g + 2u * nthr], v3 = s[g + 3u * nthr];
+            u32x4 v0 = load_once(s + g), v1 = load_once(s + g + nthr), v2 = load_once(s + g + 2u * nthr),
+                  v3 = load_once(s + g + 3u * nthr);
             d[g] = v0;
             d[g + nthr] = v1;
             d[g + 2u * nthr] = v2;
             d[g + 3u * nthr] = v3;
         }
         for (; g < ng; g += nthr)
-            d[g] = s[g];
+            d[g] = load_once(s + g);
     } else {
         const GLOBAL u32x4_a4* s = (const GLOBAL u32x4_a4*)(src + head);
         uint64_t g = tid;
         for (; g + 3u * nthr < ng; g += 4u * nthr) {
-            const u32x4 v0 = s[g], v1 = s[g + nthr], v2 = s[g + 2u * nthr], v3 = s[g + 3u * nthr];
+            const u32x4 v0 = load_once_a4(s + g), v1 = load_once_a4(s + g + nthr),
+                        v2 = load_once_a4(s + g + 2u * nthr), v3 = load_once_a4(s + g + 3u * nthr);
             d[g] = v0;
             d[g + nthr] = v1;
             d[g + 2u * nthr] = v2;
             d[g + 3u * nthr] = v3;
         }
         for (; g < ng; g += nthr)
-            d[g] = s[g];
+            d[g] = load_once_a4(s + g);
     }
 }
 
@@ -838,14 +874,23 @@ void check_hip(hipError_t e, const char* what)
         fail(LLAMA_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// tile_kernel variants by mode (kModeStaged .. kModeGatherStore), plain
+// stores first, then streaming stores
+const void* const kTileKernels[8] = {
+    (const void*)tile_kernel<kModeStaged>, (const void*)tile_kernel<kModeDirectStore>,
+    (const void*)tile_kernel<kModeDirectLoad>, (const void*)tile_kernel<kModeGatherStore>,
+    (const void*)tile_kernel<kModeStaged | kModeStreamStores>,
+    (const void*)tile_kernel<kModeDirectStore | kModeStreamStores>,
+    (const void*)tile_kernel<kModeDirectLoad | kModeStreamStores>,
+    (const void*)tile_kernel<kModeGatherStore | kModeStreamStores>};
+
 bool g_attr_set = false;
 
 void set_attributes()
 {
     if (g_attr_set)
         return;
-    for (const void* k : {(const void*)tile_kernel<kModeStaged>, (const void*)tile_kernel<kModeDirectStore>,
-                          (const void*)tile_kernel<kModeDirectLoad>, (const void*)tile_kernel<kModeGatherStore>})
+    for (const void* k : kTileKernels)
         check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes)),
                   "hipFuncSetAttribute(tile_kernel)");
     check_hip(hipFuncSetAttribute((const void*)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -886,21 +931,19 @@ void launch(const Plan& p, void* stream_ptr)
         return;
     const uint32_t grid = uint32_t(std::min<uint64_t>(p.workgroups, kMaxGrid));
     switch (p.path) {
-    case LLAMA_PATH_TILE:
+    case LLAMA_PATH_TILE: {
         set_attributes();
-        if (p.tile.h.flags & kTileDirectLoad)
-            hipLaunchKernelGGL(tile_kernel<kModeDirectLoad>, dim3(grid), dim3(p.threads), p.tile.h.lds_bytes, stream,
-                               p.tile);
-        else if (p.tile.h.flags & kTileDirectStore)
-            hipLaunchKernelGGL(tile_kernel<kModeDirectStore>, dim3(grid), dim3(p.threads), p.tile.h.lds_bytes,
-                               stream, p.tile);
-        else if (p.tile.h.flags & kTileGatherStore)
-            hipLaunchKernelGGL(tile_kernel<kModeGatherStore>, dim3(grid), dim3(p.threads), p.tile.h.lds_bytes,
-                               stream, p.tile);
-        else
-            hipLaunchKernelGGL(tile_kernel<kModeStaged>, dim3(grid), dim3(p.threads), p.tile.h.lds_bytes, stream,
-                               p.tile);
+        const uint32_t f = p.tile.h.flags;
+        const uint32_t mode = (f & kTileDirectLoad)    ? kModeDirectLoad
+                              : (f & kTileDirectStore) ? kModeDirectStore
+                              : (f & kTileGatherStore) ? kModeGatherStore
+                                                       : kModeStaged;
+        const void* k = kTileKernels[(mode - 1) + ((f & kTileStreamStores) ? 4 : 0)];
+        void* args[] = {(void*)&p.tile};
+        check_hip(hipLaunchKernel(k, dim3(grid), dim3(p.threads), args, p.tile.h.lds_bytes, stream),
+                  "hipLaunchKernel(tile_kernel)");
         break;
+    }
     case LLAMA_PATH_STREAM:
         hipLaunchKernelGGL(stream_kernel, dim3(grid), dim3(p.threads), 0, stream, p.stream);
         break;

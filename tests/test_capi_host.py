@@ -165,6 +165,15 @@ def test_tile_modes():
     assert mode("particle", A, Q8, flags=L.COPY_PRESERVE_PADDING) == "gather_store"  # no padding to keep
     assert plan("particle", A, S)["tile_mode"] == "direct_store"
     assert plan("particle", A, A)["tile_mode"] is None  # identical layouts: no tiles
+    # nontemporal destination stores from 1 GiB of destination up: the
+    # particle at 2^26 records (1.88 GB per layout), not the 128^3
+    # lattice-Boltzmann grid (336 MB aligned)
+    assert plan("particle", A, Q8, n=1 << 26)["stream_stores"]
+    assert plan("particle", A, S, n=1 << 26)["stream_stores"]
+    assert not plan("particle", A, Q8, n=(1 << 30) // 28 - 1000)["stream_stores"]
+    assert plan("particle", A, Q8, n=(1 << 30) // 28 + 1000)["stream_stores"]
+    assert not plan("lbm", M, AA, n=128 ** 3)["stream_stores"]
+    assert not plan("particle", A, A, n=1 << 26)["stream_stores"]  # STREAM path: plain stores
     # LDS of a gathering tile: the source region (512 records of 28 bytes and
     # room for the 16-byte phase) plus the word table of one destination
     # block (8 records of 28 bytes: 56 words), and no destination region
