@@ -514,27 +514,19 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
     }
     const bool preserve = preserve_padding(rq, p);
     // gather store: a record-major destination whose blocks are whole 4-byte
-    // words of values or padding, every tile span 16-byte aligned; a source
-    // with more lanes per block than the destination needs leaf sizes that
-    // are powers of two (the lane runs of a block then advance by shifts)
+    // words, every tile span 16-byte aligned; a source with more lanes per
+    // block than the destination needs leaf sizes that are powers of two (the
+    // lane runs of a block then advance by shifts)
     const uint64_t gwords = rq.dst.block / 4;
-    bool gather = !direct && !preserve && p.gather_ok && !(p.flags_in & kPlanNoDirect) &&
+    const bool more_lanes = a.src.mode == kFieldMajor || rq.src.lanes > rq.dst.lanes;
+    bool gather = !direct && !preserve && !(p.flags_in & kPlanNoDirect) &&
                   a.dst.mode == kRecordMajor && rq.dst.lanes <= kGatherMaxLanes && rq.dst.block % 4 == 0 &&
                   gwords >= 2 && gwords <= kGatherMaxWords && rq.dst_ptr[0] % 16 == 0 && a.dst.tile_bytes % 16 == 0 &&
-                  (a.dst.tile_bytes / 4) * gwords < (uint64_t(1) << 32) &&
-                  (a.src.mode == kFieldMajor || rq.src.block % 4 == 0);
-    const bool more_lanes = a.src.mode == kFieldMajor || rq.src.lanes > rq.dst.lanes;
-    for (size_t f = 0; f < F && gather; f++) {
-        const TileEntry& e = ta.e[f];
-        gather = e.size % 4 == 0 && rq.dst.base[f] % 4 == 0 && e.src_pos % 4 == 0 && (!more_lanes || is_pow2(e.size));
-    }
-    const uint32_t table_bytes = uint32_t((gwords * 4 + 15) / 16 * 16);
-    if (gather && uint64_t(sb) + table_bytes <= std::min<uint64_t>(lds_limit, kHardLdsBytes)) {
-        a.flags |= kTileGatherStore;
-        a.dst.lds_base = sb;
-        a.dst.lds_bytes = table_bytes;
-        a.lds_bytes = sb + table_bytes;
-        TileGather& g = ta.gather;
+                  (a.dst.tile_bytes / 4) * gwords < (uint64_t(1) << 32);
+    for (size_t f = 0; f < F && gather; f++)
+        gather = !more_lanes || is_pow2(r.leaves[f].size);
+    if (gather) {
+        TileGather g{};
         g.words = uint32_t(gwords);
         g.magic = uint32_t(((uint64_t(1) << 32) + gwords - 1) / gwords);
         const uint32_t lgd = a.dst.log2_lanes;
@@ -551,8 +543,56 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
             g.mq = (1u << g.q) - 1u;
             g.kq = uint32_t(rq.src.block);
         }
-        for (size_t f = 0; f < F; f++)
-            ta.e[f].dst_pos = uint32_t(rq.dst.base[f]); // the value of lane 0 in a destination block
+        // the kernel's word classification: the source of every byte of
+        // destination block 0 (LDS byte for block 0, log2 lane run, record),
+        // then whole, padding or composite per word
+        const uint32_t L = uint32_t(rq.dst.lanes);
+        std::vector<uint32_t> src_of(gwords * 4, 1u << 31);
+        for (size_t f = 0; f < F; f++) {
+            const TileEntry& e = ta.e[f];
+            const uint32_t run = log2_exact(uint64_t(L) * e.size);
+            for (uint32_t jj = 0; jj < L; jj++)
+                for (uint32_t k = 0; k < e.size; k++) {
+                    const uint32_t p0 = e.src_pos + (jj >> a.src.pos_lg) * a.src.pos_k + (jj & a.src.pos_m) * e.size + k;
+                    src_of[rq.dst.base[f] + uint64_t(jj) * e.size + k] = p0 | (run << 18) | (jj << 23);
+                }
+        }
+        std::vector<uint32_t> table(gwords), bytes;
+        for (uint64_t w = 0; w < gwords; w++) {
+            const uint32_t* x = &src_of[4 * w];
+            const bool aligned = (x[0] & 3u) == 0 && (g.kq & 3u) == 0 && (g.mq == 0 || ((x[0] >> 18) & 31u) >= 2);
+            if ((x[0] >> 31) == 0 && x[1] == x[0] + 1 && x[2] == x[0] + 2 && x[3] == x[0] + 3 && aligned) {
+                table[w] = x[0];
+            } else if (((x[0] & x[1] & x[2] & x[3]) >> 31) != 0) {
+                table[w] = 1u << 31;
+            } else {
+                table[w] = (3u << 30) | uint32_t(bytes.size() / 4);
+                bytes.insert(bytes.end(), x, x + 4);
+            }
+        }
+        table.insert(table.end(), bytes.begin(), bytes.end());
+        const uint64_t composite = bytes.size() / 4;
+        g.table = uint32_t(table.size());
+        // composite words read 4 bytes each: into AoS the gather still beats
+        // the staged mode with a quarter of the words composite (listing 1's
+        // aligned record: +75%), into AoSoA it loses beyond about 1/16 (the
+        // u16 and bool lanes of listing 1: -15 to -35%; the mixed record's u8
+        // lanes, 2% of the words: within a few percent either way); the table
+        // travels after the entries in the argument block
+        const uint64_t share = rq.dst.lanes == 1 ? 4 : 16;
+        const uint64_t table_bytes = (table.size() * 4 + 15) / 16 * 16;
+        const uint64_t room = uint64_t(kTileMaxEntries - a.num_entries) * (sizeof(TileEntry) / 4);
+        if (composite * share <= gwords && table.size() <= room &&
+            uint64_t(sb) + table_bytes <= std::min<uint64_t>(lds_limit, kHardLdsBytes)) {
+            a.flags |= kTileGatherStore;
+            a.dst.lds_base = sb;
+            a.dst.lds_bytes = uint32_t(table_bytes);
+            a.lds_bytes = uint32_t(sb + table_bytes);
+            ta.gather = g;
+            std::memcpy(&ta.e[a.num_entries], table.data(), table.size() * 4);
+            for (size_t f = 0; f < F; f++)
+                ta.e[f].dst_pos = uint32_t(rq.dst.base[f]); // the value of lane 0 in a destination block
+        }
     }
     // direct load: source leaf values in 16-byte granules of one leaf,
     // starting 16-byte aligned, leaf sizes 4, 8 or 16, destination positions
@@ -686,13 +726,13 @@ void fill_naive(const Request& rq, Plan& p)
 } // namespace
 
 namespace {
-Plan make_plan_raw(const Request& rq, const llama_copy_options* opt, bool gather_ok);
+Plan make_plan_raw(const Request& rq, const llama_copy_options* opt);
 }
 
 // The plan for `opt`; when the caller leaves the path and tile size to the
 // library, a tuning-cache entry for this class of copies supplies them (the
 // caller's threads and wg_per_cu still win).
-Plan make_plan(const Request& rq, const llama_copy_options* opt, bool gather_ok)
+Plan make_plan(const Request& rq, const llama_copy_options* opt)
 {
     if (!opt || (opt->path == LLAMA_PATH_AUTO && opt->tile_records == 0)) {
         llama_copy_options tuned;
@@ -703,21 +743,20 @@ Plan make_plan(const Request& rq, const llama_copy_options* opt, bool gather_ok)
                 tuned.wg_per_cu = opt->wg_per_cu;
             tuned.flags = (tuned.flags & kTuneFlags) | (opt ? opt->flags : 0u);
             try {
-                return make_plan_raw(rq, &tuned, gather_ok);
+                return make_plan_raw(rq, &tuned);
             } catch (const Error&) {
                 // the cached parameters do not apply here; plan from scratch
             }
         }
     }
-    return make_plan_raw(rq, opt, gather_ok);
+    return make_plan_raw(rq, opt);
 }
 
 namespace {
 
-Plan make_plan_raw(const Request& rq, const llama_copy_options* opt, bool gather_ok)
+Plan make_plan_raw(const Request& rq, const llama_copy_options* opt)
 {
     Plan p;
-    p.gather_ok = gather_ok;
     p.read_bytes = total_bytes(rq.src.blob_size);
     p.write_bytes = total_bytes(rq.dst.blob_size);
     uint32_t want = opt ? opt->path : uint32_t(LLAMA_PATH_AUTO);

@@ -89,14 +89,13 @@ struct Plan {
     uint32_t wg_per_cu = 0;
     uint64_t tiles = 0;
     uint32_t flags_in = 0; // llama_copy_options.flags of the request
-    bool gather_ok = true; // kTileGatherStore allowed (the batch kernel runs the other modes only)
     uint64_t read_bytes = 0, write_bytes = 0;
     TileArgs tile{};     // path == TILE
     StreamArgs stream{}; // path == STREAM
     NaiveArgs naive{};   // path == NAIVE
 };
 
-Plan make_plan(const Request& rq, const llama_copy_options* opt, bool gather_ok = true);
+Plan make_plan(const Request& rq, const llama_copy_options* opt);
 
 constexpr uint32_t kPlanNoDirect = LLAMA_COPY_NO_DIRECT;
 constexpr uint32_t kPlanNoSplit = LLAMA_COPY_NO_SPLIT;

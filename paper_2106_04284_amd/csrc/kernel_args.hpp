@@ -58,12 +58,21 @@ struct TileEntry {
 // every byte on its own.
 constexpr uint32_t kMoveSplit = 1u << 3;
 
-// kTileGatherStore: where word w of a destination block finds its source.
-// The word table (in LDS, at dst.lds_base) holds, for every 4-byte word w of
-// destination block 0, the LDS byte p0 of its source word (bits 0-17), log2
-// of the destination's lane-run bytes L_d * size of its leaf (bits 18-22),
-// its record j < L_d inside the block (bits 23-30), or bit 31 for padding.
-// Word w of block b then reads LDS byte
+// kTileGatherStore: where the words of a destination block find their
+// sources.  The planner's word table describes every 4-byte word w of
+// destination block 0:
+//   bit 31 clear:     a whole word of one value, read as one 4-byte word: the
+//                     LDS byte p0 of its source for block 0 (bits 0-17), log2
+//                     of its leaf's lane run L_d * size (bits 18-22) and its
+//                     record j < L_d in the block (bits 23-29);
+//   bits 31-30 = 10:  padding (zero);
+//   bits 31-30 = 11:  a composite word (its bytes come from different values
+//                     or padding): bits 0-15 index c, and entries words + 4c
+//                     .. words + 4c + 3 of the table give its 4 bytes' sources
+//                     in the same form (bit 31: a zero byte).
+// The table follows the entries: in the argument block at entry num_entries
+// (reinterpreted as 32-bit words), in a batch after the item's entries.  A
+// source of block b lies at LDS byte
 //   p0 + (b >> q) * kq + ((b & mq) << run)
 // (a source with at most L_d lanes per block: q = 0, mq = 0 and kq the source
 // bytes of L_d records; a source with more: q = log2 of the lane ratio,
@@ -71,7 +80,8 @@ constexpr uint32_t kMoveSplit = 1u << 3;
 struct TileGather {
     uint32_t words; // 4-byte words per destination block
     uint32_t magic; // ceil(2^32 / words): u / words == mulhi(u, magic) for u * words < 2^32
-    uint32_t q, mq, kq, pad;
+    uint32_t q, mq, kq;
+    uint32_t table; // 32-bit words of the table: words + 4 per composite word
 };
 
 struct TileHeader {
@@ -109,22 +119,21 @@ constexpr uint32_t kDirectLoadSlots = 8;
 // only for records with values.
 constexpr uint32_t kTilePreserve = 4;
 
-// Destination record-major (AoS, or AoSoA with L_d <= 256 lanes), 16-byte
-// aligned tile spans, and every 4-byte word of a destination block either one
-// word of a value (leaf sizes and offsets multiples of 4) or padding: the
-// source is staged in LDS as usual, then every thread assembles whole 16-byte
-// granules of the destination span word by word from the source region (the
-// word table maps each word to its source) and stores them; the tile needs no
-// destination region and no second barrier.  A source with more lanes per
-// block than the destination (field-major included) needs leaf sizes that are
-// powers of two.
+// Destination record-major (AoS, or AoSoA with L_d <= 128 lanes) with blocks
+// of whole 4-byte words and 16-byte aligned tile spans: the source is staged
+// in LDS as usual, then every thread assembles whole 16-byte granules of the
+// destination span word by word from the source region (the word table maps
+// each word to its source, or to the sources of its 4 bytes) and stores
+// them; the tile needs no destination region and no second barrier.  A
+// source with more lanes per block than the destination (field-major
+// included) needs leaf sizes that are powers of two.
 constexpr uint32_t kTileGatherStore = 8;
-constexpr uint32_t kGatherMaxWords = 4096; // word table entries (16 KiB of LDS)
+constexpr uint32_t kGatherMaxWords = 4096; // word table entries (16 KiB of LDS without composite words)
+constexpr uint32_t kGatherMaxLanes = 128;
 
 // The tile's 16-byte destination stores carry the nontemporal hint: set for
 // destinations several times larger than the 256 MB Infinity Cache.
 constexpr uint32_t kTileStreamStores = 16;
-constexpr uint32_t kGatherMaxLanes = 256;
 
 // The gather geometry follows the entries, so that the header and entries
 // keep their offsets in the argument block (entries 16-byte aligned; a
@@ -202,9 +211,11 @@ enum : uint32_t { kItemTile = 0, kItemStream = 1 };
 
 struct BatchItem {
     uint32_t kind;  // kItemTile / kItemStream
-    uint32_t count; // entries (TILE) or runs (STREAM)
+    uint32_t count; // entries (TILE; the gather word table after them included) or runs (STREAM)
     uint64_t first; // index of the item's first entry or run
     TileHeader h;   // TILE: the tile geometry; STREAM: h.num_tiles = chunks
+    TileGather gather; // TILE with kTileGatherStore
+    uint32_t pad[2];
 };
 
 struct BatchArgs {

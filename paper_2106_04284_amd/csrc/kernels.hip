@@ -407,40 +407,32 @@ __device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries en
     }
 }
 
-// Gather store: builds the word table of a record-major destination block
-// (kTileGatherStore) in LDS; entry w names the source of 4-byte word w of
-// destination block 0, or padding.  Leaf f's values in a destination block
-// are L_d consecutive values from byte e.dst_pos.  Runs once per workgroup;
-// the first tile's barrier publishes it.
-template <typename Entries>
-__device__ __forceinline__ void gather_table(const TileHeader& h, const TileGather& gg, Entries ent, uint8_t* lds)
+// Gather store (kTileGatherStore): copies the planner's word table into LDS
+// (at dst.lds_base) once per workgroup; the first tile's barrier publishes it.
+__device__ __forceinline__ void gather_table(const TileHeader& h, const TileGather& gg, const uint32_t* table,
+                                             uint8_t* lds)
 {
     uint32_t* tab = (uint32_t*)(lds + h.dst.lds_base);
-    const uint32_t L = 1u << h.dst.log2_lanes;
-    for (uint32_t w = threadIdx.x; w < gg.words; w += blockDim.x) {
-        const uint32_t b = w * 4u;
-        uint32_t x = 1u << 31;
-        for (uint32_t f = 0; f < h.num_leaves; f++) {
-            const auto& e = ent(f);
-            const uint32_t off = b - e.dst_pos; // wraps above L * size when b precedes the leaf
-            if (off < L * e.size) {
-                const uint32_t j = off / e.size, k = off - j * e.size;
-                const uint32_t p0 = e.src_pos + (j >> h.src.pos_lg) * h.src.pos_k + (j & h.src.pos_m) * e.size + k;
-                x = p0 | (uint32_t(__builtin_ctz(L * e.size)) << 18) | (j << 23);
-            }
-        }
-        tab[w] = x;
-    }
+    for (uint32_t k = threadIdx.x; k < gg.table; k += blockDim.x)
+        tab[k] = table[k];
+}
+
+// LDS byte of a gather source (a word-table entry of a whole word, or a byte
+// entry of a composite word) in destination block blk.
+__device__ __forceinline__ uint32_t gather_pos(uint32_t x, uint32_t blk, const TileGather& gg)
+{
+    return (x & 0x3FFFFu) + (blk >> gg.q) * gg.kq + ((blk & gg.mq) << ((x >> 18) & 31u));
 }
 
 // Gather store of one tile: every thread assembles 16-byte granules of the
 // destination span word by word from the source region and stores them;
-// padding words and records >= nv are zero.
+// padding and records >= nv are zero.
 template <bool kStream>
 __device__ __forceinline__ void gather_store_tile(const TileHeader& h, const TileGather& gg, uint64_t t, uint32_t nv,
                                                   uint32_t nd, uint32_t tid, uint32_t nthr, const uint8_t* lds)
 {
     const uint32_t* tab = (const uint32_t*)(lds + h.dst.lds_base);
+    const uint32_t* btab = tab + gg.words; // the byte sources of composite words
     const uint32_t lgd = h.dst.log2_lanes;
     const uint32_t words = uint32_t(((uint64_t(nd) + h.dst.lanes - 1) >> lgd) * h.dst.block) >> 2;
     const uint64_t gbase = h.dst.span_base + t * h.dst.tile_bytes;
@@ -451,9 +443,19 @@ __device__ __forceinline__ void gather_store_tile(const TileHeader& h, const Til
 #pragma unroll
         for (uint32_t c = 0; c < 4; c++) {
             const uint32_t e = tab[w];
-            const uint32_t r = (blk << lgd) + ((e >> 23) & 255u);
-            const uint32_t pos = (e & 0x3FFFFu) + (blk >> gg.q) * gg.kq + ((blk & gg.mq) << ((e >> 18) & 31u));
-            v[c] = (e >> 31) == 0 && r < nv ? *(const uint32_t*)(lds + pos) : 0u;
+            uint32_t x = 0;
+            if ((e >> 31) == 0) {
+                if ((blk << lgd) + ((e >> 23) & 127u) < nv)
+                    x = *(const uint32_t*)(lds + gather_pos(e, blk, gg));
+            } else if ((e >> 30) == 3u) {
+#pragma unroll
+                for (uint32_t k = 0; k < 4; k++) {
+                    const uint32_t be = btab[4u * (e & 0xFFFFu) + k];
+                    if ((be >> 31) == 0 && (blk << lgd) + ((be >> 23) & 127u) < nv)
+                        x |= uint32_t(lds[gather_pos(be, blk, gg)]) << (8u * k);
+                }
+            }
+            v[c] = x;
             if (++w == gg.words) {
                 w = 0;
                 blk++;
@@ -490,6 +492,7 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     constexpr bool kStream = (ModeBits & kModeStreamStores) != 0;
     const bool dload = Mode == kModeDirectLoad || (Mode == kModeAny && (h.flags & kTileDirectLoad));
     const bool dstore = Mode == kModeDirectStore || (Mode == kModeAny && (h.flags & kTileDirectStore));
+    const bool gstore = Mode == kModeGatherStore || (Mode == kModeAny && (h.flags & kTileGatherStore));
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
     const uint32_t lane = tid & 63u, wave = wave_id(), nwaves = nthr >> 6;
     const uint32_t lds_base = uint32_t(uintptr_t((lds_void_t*)lds));
@@ -542,7 +545,7 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
         return;
     }
 
-    if (Mode == kModeGatherStore) {
+    if (gstore) {
         // ---- 2'''. assemble every destination granule word by word from
         //           the source region and store it; no destination region
         gather_store_tile<kStream>(h, *gg, t, nv, nd, tid, nthr, lds);
@@ -622,8 +625,8 @@ __global__ void __launch_bounds__(1024) tile_kernel(const TileArgs a)
         t = x * q + min(x, rem) + k;
         stride = nt;
     }
-    if (Mode == kModeGatherStore)
-        gather_table(a.h, a.gather, ent, lds);
+    if (Mode == kModeGatherStore) // the word table follows the entries in the argument block
+        gather_table(a.h, a.gather, reinterpret_cast<const uint32_t*>(a.e + a.h.num_entries), lds);
     for (; t < nt; t += stride) {
         tile_body<ModeBits>(a.h, ent, t, lds, &a.gather);
         if (t + stride < nt)
@@ -724,15 +727,29 @@ __global__ void __launch_bounds__(1024) stream_kernel(const StreamArgs a)
 // finish puts both counters back to zero, so the next launch (a graph replay
 // included) starts from zero without a memset.
 // Runs work unit g of item j (begin[j] <= g < begin[j + 1]).
+// `table_item`: the item whose gather word table the workgroup's LDS holds
+// (the table is copied when a unit of another gathering item comes).
 __device__ __forceinline__ void batch_unit(const BatchArgs& a, const CONSTANT uint64_t* begin, uint32_t j,
-                                           uint64_t g, uint8_t* lds)
+                                           uint64_t g, uint8_t* lds, uint32_t& table_item)
 {
     const CONSTANT BatchItem* it = (const CONSTANT BatchItem*)a.items + j;
     const uint64_t u = g - begin[j];
     if (it->kind == kItemTile) {
         const TileHeader h = load_const(&it->h);
         const CONSTANT TileEntry* entries = (const CONSTANT TileEntry*)a.entries + it->first;
-        tile_body<kModeAny>(h, [&](uint32_t k) -> const CONSTANT TileEntry& { return entries[k]; }, u, lds);
+        TileGather gg{};
+        if (h.flags & kTileGatherStore) {
+            gg = load_const(&it->gather);
+            if (table_item != j) {
+                // the previous unit's barrier has ended every read of the
+                // region; this unit's first barrier publishes the table
+                gather_table(h, gg, (const uint32_t*)(entries + h.num_entries), lds);
+                table_item = j;
+            }
+        } else if (h.lds_bytes > 0) {
+            table_item = ~0u; // this unit's regions may cover the table
+        }
+        tile_body<kModeAny>(h, [&](uint32_t k) -> const CONSTANT TileEntry& { return entries[k]; }, u, lds, &gg);
     } else {
         const CONSTANT StreamRun* runs = (const CONSTANT StreamRun*)a.runs + it->first;
         stream_unit([&](uint32_t k) -> const CONSTANT StreamRun& { return runs[k]; }, it->count, u);
@@ -759,6 +776,7 @@ __global__ void __launch_bounds__(1024) batch_kernel(const BatchArgs a)
     __shared__ unsigned long long block_first, block_count;
     const CONSTANT uint64_t* begin = (const CONSTANT uint64_t*)a.unit_begin;
     uint64_t seen = 0; // thread 0: the counter after its last block
+    uint32_t table_item = ~0u;
     for (;;) {
         if (threadIdx.x == 0) {
             const uint64_t remaining = a.total_units > seen ? a.total_units - seen : 0;
@@ -778,7 +796,7 @@ __global__ void __launch_bounds__(1024) batch_kernel(const BatchArgs a)
         for (uint64_t g = g0; g < g1; g++) {
             while (begin[lo + 1] <= g)
                 lo++;
-            batch_unit(a, begin, lo, g, lds);
+            batch_unit(a, begin, lo, g, lds, table_item);
             __syncthreads();
         }
     }

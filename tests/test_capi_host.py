@@ -131,10 +131,10 @@ def test_planner_classification_all_pairs(orc, name, n):
 
 def test_tile_modes():
     """The tile mode the planner takes: a destination in 16-byte granules of
-    one leaf stores from registers; a record-major destination made of whole
-    4-byte words gathers word by word from the staged source; a source in
-    granules of one leaf loads into registers; anything else stages both
-    sides.  LLAMA_COPY_NO_DIRECT stages every tile, and a destination whose
+    one leaf stores from registers; a record-major destination in 4-byte
+    words gathers word by word from the staged source (at most a quarter of
+    the words composite, read byte by byte); a source in granules of one leaf
+    loads into registers; anything else stages both sides.  LLAMA_COPY_NO_DIRECT stages every tile, and a destination whose
     padding is kept never gathers."""
     def plan(name, a, b, n=1 << 20, **kw):
         r = L.Record(W.RECORDS[name])
@@ -156,9 +156,26 @@ def test_tile_modes():
     assert mode("lbm", Q32, AA) == "gather_store"
     assert mode("lbm", AA, M) == "direct_store"
     # a u8 leaf (mixed) or u16 / bool leaves (listing1) share words with
-    # other leaves or padding: no gather
-    assert mode("mixed", M, AA) == "staged"
-    assert mode("listing1", M, AA) == "staged"
+    # other leaves or padding: those words are composite, read byte by byte
+    assert mode("mixed", M, AA) == "gather_store"
+    assert mode("mixed", AA, Q8) == "gather_store"
+    assert mode("listing1", M, AA) == "gather_store"
+    # the 49-byte packed mixed record: as a destination its blocks are not
+    # whole words; as a source most of its values sit at odd positions, so
+    # that most destination words would be composite
+    assert mode("mixed", AA, A) == "staged"
+    assert mode("mixed", A, Q8) == "staged"
+    # into AoSoA, listing 1's u16 and bool lanes make a quarter of the words
+    # composite: staged; the mixed record's u8 lanes are 2% of the words
+    assert mode("listing1", M, Q8) == "staged"
+    assert mode("listing1", AA, Q32) == "staged"
+    assert mode("mixed", M, Q32) == "gather_store"
+    # LDS with composite words: the source region (leaf spans of 256 records)
+    # plus the word table of a 56-byte aligned record (14 words: 12 whole, the
+    # u8 word composite with its 4 byte sources, one padding word)
+    p = plan("mixed", M, AA)
+    spans = 3 * ((256 * 8 + 30) // 16 * 16) + 6 * ((256 * 4 + 30) // 16 * 16) + (256 + 30) // 16 * 16
+    assert p["tile_records"] == 256 and p["lds_bytes"] == spans + ((14 + 4) * 4 + 15) // 16 * 16
     assert mode("particle", A, Q8, flags=L.COPY_NO_DIRECT) == "staged"
     assert mode("lbm", M, AA, flags=L.COPY_PRESERVE_PADDING) == "staged"
     assert mode("particle", A, Q8, n=1031, flags=L.COPY_PRESERVE_PADDING) == "staged"  # 1031 = 128 * 8 + 7

@@ -90,25 +90,27 @@ def test_particle_2e26_sampled(L, orc, pair):
 
 # destinations of 1 GiB or more take nontemporal stores; the particle pairs
 # above run them in the direct-store and gather-store modes, these cases in
-# the staged mode (the mixed record's u8 leaf shares words with padding) and
-# the direct-load mode (a destination 4 bytes past 16-byte alignment cannot
-# gather: a field-major source then loads into registers)
-STREAM_STORE_CASES = [("mixed", 1 << 25, ("aos_aligned", 0), ("aosoa", 8), 0),
-                      ("mixed", 1 << 25, ("aosoa", 8), ("aos_aligned", 0), 0),
-                      ("particle", 1 << 26, ("soa_multi", 0), ("aos_packed", 0), 4)]
+# the staged mode (the packed 49-byte mixed record puts most values at odd
+# positions), the gather-store mode with composite words (the mixed record's
+# u8 leaf shares words with other lanes or padding) and the direct-load mode
+# (a destination 4 bytes past 16-byte alignment cannot gather: a field-major
+# source then loads into registers; the plan without blobs, which assumes
+# aligned blobs, gathers)
+STREAM_STORE_CASES = [("mixed", 1 << 25, ("aos_packed", 0), ("aosoa", 8), 0, "staged"),
+                      ("mixed", 1 << 25, ("aosoa", 8), ("aos_aligned", 0), 0, "gather_store"),
+                      ("mixed", 1 << 25, ("soa_multi", 0), ("aosoa", 32), 0, "gather_store"),
+                      ("particle", 1 << 26, ("soa_multi", 0), ("aos_packed", 0), 4, "gather_store")]
 
 
 @pytest.mark.parametrize("case", STREAM_STORE_CASES,
                          ids=[f"{c[0]}-{_name(c[2])}-{_name(c[3])}-off{c[4]}" for c in STREAM_STORE_CASES])
 def test_stream_store_modes_sampled(L, orc, case):
-    name, n, a, b, off = case
+    name, n, a, b, off, mode = case
     ro, rg = orc.Record(W.RECORDS[name]), L.Record(W.RECORDS[name])
     ms_o, md_o = orc.Mapping(ro, a[0], [n], a[1]), orc.Mapping(ro, b[0], [n], b[1])
     ms, md = L.Mapping(rg, a[0], [n], a[1]), L.Mapping(rg, b[0], [n], b[1])
     p = L.plan(ms, md)
-    assert p["path"] == "tile" and p["stream_stores"]
-    if off == 0:
-        assert p["tile_mode"] == "staged"
+    assert p["path"] == "tile" and p["stream_stores"] and p["tile_mode"] == mode
     src = [_random_blob(sz, 2000 + k, plant=False) for k, sz in enumerate(ms.blob_sizes())]
     outs = []
     for fill in (0x00, 0xFF):

@@ -204,15 +204,19 @@ def test_odd_record_sizes(L, orc, pair, offsets, flags, name):
              dst_off=offsets[1], flags=flags)
 
 
-# record-major destinations made of whole 4-byte words: the gather-store tile
-# mode, over tile sizes, thread counts, a persistent grid (several tiles per
-# workgroup, one word table), ragged record counts and source blobs at every
-# 4-byte phase; destinations 16-byte aligned (dst offset 16), and at offset 4,
-# where the planner falls back to the staged mode
+# record-major destinations in 4-byte words: the gather-store tile mode, over
+# tile sizes, thread counts, a persistent grid (several tiles per workgroup,
+# one word table), ragged record counts and source blobs at every 4-byte
+# phase; destinations 16-byte aligned (dst offset 16), and at offset 4, where
+# the planner falls back to the staged mode
 GATHER_CASES = [("particle", ("aos_packed", 0), ("aosoa", 8)), ("particle", ("aosoa", 8), ("aos_aligned", 0)),
                 ("particle", ("soa_multi", 0), ("aos_packed", 0)), ("particle", ("aosoa", 64), ("aosoa", 8)),
                 ("lbm", ("soa_multi", 0), ("aos_aligned", 0)), ("lbm", ("aosoa", 32), ("aos_aligned", 0)),
-                ("lbm", ("aos_aligned", 0), ("aosoa", 8)), ("lbm", ("aosoa", 64), ("aosoa", 8))]
+                ("lbm", ("aos_aligned", 0), ("aosoa", 8)), ("lbm", ("aosoa", 64), ("aosoa", 8)),
+                # 1- and 2-byte leaves: composite words assembled byte by byte
+                ("mixed", ("aos_aligned", 0), ("aosoa", 8)), ("mixed", ("soa_multi", 0), ("aos_aligned", 0)),
+                ("mixed", ("aosoa", 32), ("aos_aligned", 0)), ("mixed", ("soa_single", 0), ("aosoa", 8)),
+                ("listing1", ("aosoa", 64), ("aos_aligned", 0)), ("listing1", ("soa_multi", 0), ("aos_aligned", 0))]
 GATHER_RUNS = [(77, {}), (1031, {}), (4099, {"tile_records": 16}), (5000, {"tile_records": 64, "threads": 64}),
                (20000, {"tile_records": 256, "threads": 1024}), (30011, {"tile_records": 16, "wg_per_cu": 1})]
 
