@@ -238,10 +238,15 @@ typedef struct {
     uint64_t read_bytes;    /* bytes of source blobs the copy reads */
     uint64_t write_bytes;   /* bytes of destination blobs the copy writes */
     uint32_t tile_mode;     /* TILE: llama_tile_mode; 0 for the other paths */
-    uint32_t stream_stores; /* TILE: 1 when the destination's 16-byte stores carry the nontemporal
-                               hint (destinations of 1 GiB or more, several times the 256 MB
-                               Infinity Cache); 0 otherwise */
+    uint32_t cache_hints;   /* TILE and STREAM: bit 0 (LLAMA_HINT_STREAM_LOADS) when the source
+                               loads carry the nontemporal hint (sources of 256 MiB or more, the
+                               size of the Infinity Cache); bit 1 (LLAMA_HINT_STREAM_STORES) when
+                               the destination's 16-byte stores do (TILE, destinations of 1 GiB or
+                               more) */
 } llama_plan_info;
+
+#define LLAMA_HINT_STREAM_LOADS 1u
+#define LLAMA_HINT_STREAM_STORES 2u
 
 /* What a copy of this pair with these options would launch, without blobs:
  * the plan assumes distinct blobs aligned to 256 bytes (a real copy plans for

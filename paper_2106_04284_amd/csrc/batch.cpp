@@ -203,7 +203,7 @@ void BatchTable::serialise(uint8_t* host, uint64_t device, BatchArgs& args) cons
     args.runs = (const StreamRun*)(device + l.runs);
     args.total_units = units;
     args.num_items = uint32_t(items.size());
-    args.pad = 0;
+    args.flags = read_bytes >= kStreamLoadBytes ? kBatchLoadsOnce : 0u;
 }
 
 uint32_t batch_wg_per_cu(uint32_t lds_bytes, uint32_t threads)

@@ -169,14 +169,17 @@ int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, con
         info->read_bytes = p.read_bytes;
         info->write_bytes = p.write_bytes;
         info->tile_mode = 0;
-        info->stream_stores = 0;
+        info->cache_hints = 0;
         if (p.path == LLAMA_PATH_TILE) {
             const uint32_t f = p.tile.h.flags;
             info->tile_mode = (f & kTileDirectStore)   ? LLAMA_TILE_DIRECT_STORE
                               : (f & kTileDirectLoad)  ? LLAMA_TILE_DIRECT_LOAD
                               : (f & kTileGatherStore) ? LLAMA_TILE_GATHER_STORE
                                                        : LLAMA_TILE_STAGED;
-            info->stream_stores = (f & kTileStreamStores) ? 1u : 0u;
+            info->cache_hints = ((f & kTileStreamLoads) ? LLAMA_HINT_STREAM_LOADS : 0u) |
+                                ((f & kTileStreamStores) ? LLAMA_HINT_STREAM_STORES : 0u);
+        } else if (p.path == LLAMA_PATH_STREAM) {
+            info->cache_hints = (p.stream.flags & kStreamLoadsOnce) ? LLAMA_HINT_STREAM_LOADS : 0u;
         }
     });
 }

@@ -386,6 +386,7 @@ bool fill_stream(const Request& rq, Plan& p)
     p.path = LLAMA_PATH_STREAM;
     std::memset(&p.stream, 0, sizeof(p.stream));
     p.stream.num_runs = uint32_t(rl.runs.size());
+    p.stream.flags = total_bytes(rq.src.blob_size) >= kStreamLoadBytes ? kStreamLoadsOnce : 0u;
     p.stream.num_chunks = chunks;
     for (size_t k = 0; k < rl.runs.size(); k++)
         p.stream.r[k] = rl.runs[k];
@@ -644,6 +645,8 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
     }
     if (total_bytes(rq.dst.blob_size) >= kStreamStoreBytes)
         a.flags |= kTileStreamStores;
+    if (total_bytes(rq.src.blob_size) >= kStreamLoadBytes)
+        a.flags |= kTileStreamLoads;
     p.path = LLAMA_PATH_TILE;
     p.lds_bytes = a.lds_bytes;
     p.tiles = a.num_tiles;

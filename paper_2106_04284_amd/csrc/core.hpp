@@ -137,5 +137,8 @@ constexpr uint32_t kMaxWavesPerCu = 32;
 // TILE: destinations of at least this many bytes get nontemporal stores
 // (4x the 256 MB Infinity Cache, which then holds at most a quarter of them)
 constexpr uint64_t kStreamStoreBytes = uint64_t(1) << 30;
+// sources of at least this many bytes (the Infinity Cache) get nontemporal
+// loads: smaller ones may still sit in that cache
+constexpr uint64_t kStreamLoadBytes = uint64_t(256) << 20;
 
 } // namespace llama

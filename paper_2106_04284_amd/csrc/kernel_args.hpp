@@ -92,7 +92,8 @@ struct TileHeader {
     uint32_t num_leaves;
     uint32_t num_entries; // leaves, then gaps
     uint32_t lds_bytes;
-    uint32_t flags;       // kTileDirectStore, kTileDirectLoad, kTilePreserve, kTileGatherStore, kTileStreamStores
+    uint32_t flags;       // kTileDirectStore, kTileDirectLoad, kTilePreserve, kTileGatherStore,
+                          // kTileStreamStores, kTileStreamLoads
     uint32_t slots;       // kTileDirectLoad: granule slots of a tile (a multiple of 64)
     TileSide src, dst;
 };
@@ -134,6 +135,9 @@ constexpr uint32_t kGatherMaxLanes = 128;
 // The tile's 16-byte destination stores carry the nontemporal hint: set for
 // destinations several times larger than the 256 MB Infinity Cache.
 constexpr uint32_t kTileStreamStores = 16;
+// The tile's source loads carry the nontemporal hint: set for sources at
+// least as large as the Infinity Cache.
+constexpr uint32_t kTileStreamLoads = 32;
 
 // The gather geometry follows the entries, so that the header and entries
 // keep their offsets in the argument block (entries 16-byte aligned; a
@@ -161,9 +165,12 @@ struct StreamRun {
     uint64_t first_chunk; // exclusive prefix sum of chunk counts
 };
 
+// StreamArgs.flags: the source loads carry the nontemporal hint
+constexpr uint32_t kStreamLoadsOnce = 1;
+
 struct StreamArgs {
     uint32_t num_runs;
-    uint32_t pad;
+    uint32_t flags; // kStreamLoadsOnce
     uint64_t num_chunks;
     StreamRun r[kStreamMaxRuns];
 };
@@ -226,7 +233,10 @@ struct BatchArgs {
     unsigned long long* counters; // [0]: next work unit, [1]: workgroups finished
     uint64_t total_units;
     uint32_t num_items;
-    uint32_t pad;
+    uint32_t flags; // kBatchLoadsOnce
 };
+
+// BatchArgs.flags: the source loads carry the nontemporal hint
+constexpr uint32_t kBatchLoadsOnce = 1;
 
 } // namespace llama

@@ -55,18 +55,28 @@ __device__ __forceinline__ T load_const(const CONSTANT T* p)
     return v;
 }
 
-// 16-byte loads of source bytes, which a copy reads exactly once: the
-// nontemporal hint streams them past the caches (a plain copy measured
-// 6.19 -> 6.52 TB/s with it, reads alone 6.79 -> 7.09 TB/s).
-__device__ __forceinline__ u32x4 load_once(const GLOBAL u32x4* p)
+// 16-byte loads of source bytes.  A copy reads every source byte once;
+// kOnce adds the nontemporal hint, for sources larger than the 256 MB
+// Infinity Cache, which streams them past the caches (a plain copy from HBM
+// measured 6.19 -> 6.52 TB/s with it, reads alone 6.79 -> 7.09 TB/s; a
+// 58 MB batch of frames that the cache holds lost 8% with it).
+template <bool kOnce>
+__device__ __forceinline__ u32x4 load_src(const GLOBAL u32x4* p)
 {
-    return __builtin_nontemporal_load(p);
+    if constexpr (kOnce)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
 }
 
 // The same at a 4-byte-aligned address.
-__device__ __forceinline__ u32x4 load_once_a4(const GLOBAL u32x4_a4* p)
+template <bool kOnce>
+__device__ __forceinline__ u32x4 load_src_a4(const GLOBAL u32x4_a4* p)
 {
-    return __builtin_nontemporal_load(p);
+    if constexpr (kOnce)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
 }
 
 // A 16-byte store of destination bytes; kStream marks it nontemporal, for
@@ -89,9 +99,16 @@ __device__ __forceinline__ void store16(GLOBAL u32x4* p, u32x4 v)
 // the barrier that publishes the buffer.
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Winline-asm" // m0 is written here and used by nothing else in these kernels
+// kOnce: with the nontemporal hint (see load_src).
+template <bool kOnce>
 __device__ __forceinline__ void lds_dma16(uint64_t gaddr, uint32_t lds_addr)
 {
-    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off nt" : : "v"(gaddr), "s"(lds_addr) : "memory", "m0");
+    if constexpr (kOnce)
+        asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off nt" : : "v"(gaddr), "s"(lds_addr)
+                     : "memory", "m0");
+    else
+        asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(gaddr), "s"(lds_addr)
+                     : "memory", "m0");
 }
 #pragma clang diagnostic pop
 
@@ -101,6 +118,7 @@ __device__ __forceinline__ void lds_dma16(uint64_t gaddr, uint32_t lds_addr)
 // nwaves.  A granule that holds a byte of the span lies in the same page as
 // that byte, so the rounding never reaches an unmapped page; the extra bytes
 // are never used.
+template <bool kOnce>
 __device__ __forceinline__ void load_span(uint64_t gstart, uint32_t len, uint32_t lds_region, uint32_t wave,
                                           uint32_t nwaves, uint32_t first_wave, uint32_t lane, uint32_t lds_base)
 {
@@ -111,7 +129,7 @@ __device__ __forceinline__ void load_span(uint64_t gstart, uint32_t len, uint32_
     for (uint32_t c = c0; c * 64u < G; c += nwaves) {
         const uint32_t gi = c * 64u + lane;
         if (gi < G)
-            lds_dma16(g0 + uint64_t(gi) * 16u, uniform(lds_base + lds_region + c * 1024u));
+            lds_dma16<kOnce>(g0 + uint64_t(gi) * 16u, uniform(lds_base + lds_region + c * 1024u));
     }
 }
 
@@ -338,7 +356,7 @@ __device__ __forceinline__ void direct_store_tile(const TileHeader& h, Entries e
 // flight together), then writes the values to the destination region.
 // Records in [nv, nd) (AoSoA lanes past the last record) and gap entries are
 // zero-filled.
-template <bool kSrcRecordMajor, typename Entries>
+template <bool kSrcRecordMajor, bool kOnce, typename Entries>
 __device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries ent, uint64_t t, uint64_t i0,
                                                  uint32_t nv, uint32_t nd, uint8_t* lds)
 {
@@ -357,7 +375,7 @@ __device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries en
         const auto& e = ent(f);
         const uint32_t g = q0 + lane - e.src_pos; // granule within the leaf's values of the tile
         if (g * 16u < nv * e.size)
-            v[j] = load_once((const GLOBAL u32x4*)leaf_granule_addr<kSrcRecordMajor>(
+            v[j] = load_src<kOnce>((const GLOBAL u32x4*)leaf_granule_addr<kSrcRecordMajor>(
                 leaf_tile_base<kSrcRecordMajor>(e.src_addr, h.src, t, i0, e.size), h.src, g, e.move & 7u));
     }
     f = 0;
@@ -483,6 +501,8 @@ __device__ __forceinline__ void gather_store_tile(const TileHeader& h, const Til
 enum : uint32_t { kModeAny = 0, kModeStaged = 1, kModeDirectStore = 2, kModeDirectLoad = 3, kModeGatherStore = 4 };
 // added to a mode: the tile's 16-byte destination stores are nontemporal
 constexpr uint32_t kModeStreamStores = 8;
+// added to a mode: the tile's source loads are nontemporal
+constexpr uint32_t kModeStreamLoads = 16;
 
 template <uint32_t ModeBits, typename Entries>
 __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint64_t t, uint8_t* lds,
@@ -490,6 +510,7 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
 {
     constexpr uint32_t Mode = ModeBits & 7u;
     constexpr bool kStream = (ModeBits & kModeStreamStores) != 0;
+    constexpr bool kOnce = (ModeBits & kModeStreamLoads) != 0;
     const bool dload = Mode == kModeDirectLoad || (Mode == kModeAny && (h.flags & kTileDirectLoad));
     const bool dstore = Mode == kModeDirectStore || (Mode == kModeAny && (h.flags & kTileDirectStore));
     const bool gstore = Mode == kModeGatherStore || (Mode == kModeAny && (h.flags & kTileGatherStore));
@@ -508,24 +529,24 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     // ---- 1. source span(s) -> LDS
     if (dload) {
         if (h.src.mode == kRecordMajor)
-            direct_load_tile<true>(h, ent, t, i0, nv, nd, lds);
+            direct_load_tile<true, kOnce>(h, ent, t, i0, nv, nd, lds);
         else
-            direct_load_tile<false>(h, ent, t, i0, nv, nd, lds);
+            direct_load_tile<false, kOnce>(h, ent, t, i0, nv, nd, lds);
     } else if (nv > 0) {
         if (h.src.mode == kRecordMajor) {
             const uint32_t len = uint32_t(((uint64_t(nv) + h.src.lanes - 1) >> h.src.log2_lanes) * h.src.block);
-            load_span(h.src.span_base + t * h.src.tile_bytes, len, h.src.lds_base, wave, nwaves, 0, lane, lds_base);
+            load_span<kOnce>(h.src.span_base + t * h.src.tile_bytes, len, h.src.lds_base, wave, nwaves, 0, lane, lds_base);
         } else {
             for (uint32_t f = 0; f < h.num_leaves; f++) {
                 const auto& e = ent(f);
-                load_span(field_span_start(e.src_addr, h.src, i0, e.size), nv * e.size, e.src_pos & ~15u, wave,
+                load_span<kOnce>(field_span_start(e.src_addr, h.src, i0, e.size), nv * e.size, e.src_pos & ~15u, wave,
                           nwaves, (e.move >> 4) & 15u, lane, lds_base);
             }
         }
     }
     if (preserve && !dstore && h.dst.mode == kRecordMajor) {
         const uint32_t len = uint32_t(((uint64_t(nd) + h.dst.lanes - 1) >> h.dst.log2_lanes) * h.dst.block);
-        load_span(h.dst.span_base + t * h.dst.tile_bytes, len, h.dst.lds_base, wave, nwaves, 0, lane, lds_base);
+        load_span<false>(h.dst.span_base + t * h.dst.tile_bytes, len, h.dst.lds_base, wave, nwaves, 0, lane, lds_base);
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -640,6 +661,7 @@ __global__ void __launch_bounds__(1024) tile_kernel(const TileArgs a)
 
 // Copies [src, src + len) to [dst, dst + len) (src == 0: writes zeros);
 // src and dst are congruent modulo 4.
+template <bool kOnce>
 __device__ __forceinline__ void copy_run_chunk(uint64_t dst, uint64_t src, uint64_t len, uint32_t tid, uint32_t nthr)
 {
     const uint32_t head = uint32_t(min<uint64_t>(len, (16u - (uint32_t(dst) & 15u)) & 15u));
@@ -665,34 +687,34 @@ __device__ __forceinline__ void copy_run_chunk(uint64_t dst, uint64_t src, uint6
         const GLOBAL u32x4* s = (const GLOBAL u32x4*)(src + head);
         uint64_t g = tid;
         for (; g + 3u * nthr < ng; g += 4u * nthr) {
-            u32x4 v0 = load_once(s + g), v1 = load_once(s + g + nthr), v2 = load_once(s + g + 2u * nthr),
-                  v3 = load_once(s + g + 3u * nthr);
+            u32x4 v0 = load_src<kOnce>(s + g), v1 = load_src<kOnce>(s + g + nthr), v2 = load_src<kOnce>(s + g + 2u * nthr),
+                  v3 = load_src<kOnce>(s + g + 3u * nthr);
             d[g] = v0;
             d[g + nthr] = v1;
             d[g + 2u * nthr] = v2;
             d[g + 3u * nthr] = v3;
         }
         for (; g < ng; g += nthr)
-            d[g] = load_once(s + g);
+            d[g] = load_src<kOnce>(s + g);
     } else {
         const GLOBAL u32x4_a4* s = (const GLOBAL u32x4_a4*)(src + head);
         uint64_t g = tid;
         for (; g + 3u * nthr < ng; g += 4u * nthr) {
-            const u32x4 v0 = load_once_a4(s + g), v1 = load_once_a4(s + g + nthr),
-                        v2 = load_once_a4(s + g + 2u * nthr), v3 = load_once_a4(s + g + 3u * nthr);
+            const u32x4 v0 = load_src_a4<kOnce>(s + g), v1 = load_src_a4<kOnce>(s + g + nthr),
+                        v2 = load_src_a4<kOnce>(s + g + 2u * nthr), v3 = load_src_a4<kOnce>(s + g + 3u * nthr);
             d[g] = v0;
             d[g + nthr] = v1;
             d[g + 2u * nthr] = v2;
             d[g + 3u * nthr] = v3;
         }
         for (; g < ng; g += nthr)
-            d[g] = load_once_a4(s + g);
+            d[g] = load_src_a4<kOnce>(s + g);
     }
 }
 
 // Work unit c of a run list: the run holding chunk c is the last run whose
 // first chunk is <= c.  `run(k)` returns run k.
-template <typename Runs>
+template <bool kOnce, typename Runs>
 __device__ __forceinline__ void stream_unit(Runs run, uint32_t num_runs, uint64_t c)
 {
     uint32_t lo = 0, hi = num_runs;
@@ -706,14 +728,16 @@ __device__ __forceinline__ void stream_unit(Runs run, uint32_t num_runs, uint64_
     const auto& r = run(lo);
     const uint64_t off = (c - r.first_chunk) << kStreamChunkLog2;
     const uint64_t len = min<uint64_t>(r.bytes - off, uint64_t(1) << kStreamChunkLog2);
-    copy_run_chunk(r.dst + off, r.src ? r.src + off : 0, len, threadIdx.x, blockDim.x);
+    copy_run_chunk<kOnce>(r.dst + off, r.src ? r.src + off : 0, len, threadIdx.x, blockDim.x);
 }
 
+// kOnce: nontemporal source loads (StreamArgs.flags & kStreamLoadsOnce).
+template <bool kOnce>
 __global__ void __launch_bounds__(1024) stream_kernel(const StreamArgs a)
 {
     auto run = [&](uint32_t k) -> const StreamRun& { return a.r[k]; };
     for (uint64_t c = blockIdx.x; c < a.num_chunks; c += gridDim.x)
-        stream_unit(run, a.num_runs, c);
+        stream_unit<kOnce>(run, a.num_runs, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -729,6 +753,7 @@ __global__ void __launch_bounds__(1024) stream_kernel(const StreamArgs a)
 // Runs work unit g of item j (begin[j] <= g < begin[j + 1]).
 // `table_item`: the item whose gather word table the workgroup's LDS holds
 // (the table is copied when a unit of another gathering item comes).
+template <bool kOnce>
 __device__ __forceinline__ void batch_unit(const BatchArgs& a, const CONSTANT uint64_t* begin, uint32_t j,
                                            uint64_t g, uint8_t* lds, uint32_t& table_item)
 {
@@ -749,10 +774,11 @@ __device__ __forceinline__ void batch_unit(const BatchArgs& a, const CONSTANT ui
         } else if (h.lds_bytes > 0) {
             table_item = ~0u; // this unit's regions may cover the table
         }
-        tile_body<kModeAny>(h, [&](uint32_t k) -> const CONSTANT TileEntry& { return entries[k]; }, u, lds, &gg);
+        tile_body<kModeAny | (kOnce ? kModeStreamLoads : 0u)>(
+            h, [&](uint32_t k) -> const CONSTANT TileEntry& { return entries[k]; }, u, lds, &gg);
     } else {
         const CONSTANT StreamRun* runs = (const CONSTANT StreamRun*)a.runs + it->first;
-        stream_unit([&](uint32_t k) -> const CONSTANT StreamRun& { return runs[k]; }, it->count, u);
+        stream_unit<kOnce>([&](uint32_t k) -> const CONSTANT StreamRun& { return runs[k]; }, it->count, u);
     }
 }
 
@@ -770,6 +796,8 @@ __device__ __forceinline__ uint32_t batch_item_of(const CONSTANT uint64_t* begin
     return lo;
 }
 
+// kOnce: nontemporal source loads (BatchArgs.flags & kBatchLoadsOnce).
+template <bool kOnce>
 __global__ void __launch_bounds__(1024) batch_kernel(const BatchArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
@@ -796,7 +824,7 @@ __global__ void __launch_bounds__(1024) batch_kernel(const BatchArgs a)
         for (uint64_t g = g0; g < g1; g++) {
             while (begin[lo + 1] <= g)
                 lo++;
-            batch_unit(a, begin, lo, g, lds, table_item);
+            batch_unit<kOnce>(a, begin, lo, g, lds, table_item);
             __syncthreads();
         }
     }
@@ -892,15 +920,16 @@ void check_hip(hipError_t e, const char* what)
         fail(LLAMA_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// tile_kernel variants by mode (kModeStaged .. kModeGatherStore), plain
-// stores first, then streaming stores
-const void* const kTileKernels[8] = {
+// tile_kernel variants by mode (kModeStaged .. kModeGatherStore): plain
+// loads and stores, then nontemporal loads, then nontemporal loads and stores
+constexpr uint32_t kLd = kModeStreamLoads, kLdSt = kModeStreamLoads | kModeStreamStores;
+const void* const kTileKernels[12] = {
     (const void*)tile_kernel<kModeStaged>, (const void*)tile_kernel<kModeDirectStore>,
     (const void*)tile_kernel<kModeDirectLoad>, (const void*)tile_kernel<kModeGatherStore>,
-    (const void*)tile_kernel<kModeStaged | kModeStreamStores>,
-    (const void*)tile_kernel<kModeDirectStore | kModeStreamStores>,
-    (const void*)tile_kernel<kModeDirectLoad | kModeStreamStores>,
-    (const void*)tile_kernel<kModeGatherStore | kModeStreamStores>};
+    (const void*)tile_kernel<kModeStaged | kLd>, (const void*)tile_kernel<kModeDirectStore | kLd>,
+    (const void*)tile_kernel<kModeDirectLoad | kLd>, (const void*)tile_kernel<kModeGatherStore | kLd>,
+    (const void*)tile_kernel<kModeStaged | kLdSt>, (const void*)tile_kernel<kModeDirectStore | kLdSt>,
+    (const void*)tile_kernel<kModeDirectLoad | kLdSt>, (const void*)tile_kernel<kModeGatherStore | kLdSt>};
 
 bool g_attr_set = false;
 
@@ -911,9 +940,9 @@ void set_attributes()
     for (const void* k : kTileKernels)
         check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes)),
                   "hipFuncSetAttribute(tile_kernel)");
-    check_hip(hipFuncSetAttribute((const void*)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  int(kHardLdsBytes - 64)),
-              "hipFuncSetAttribute(batch_kernel)");
+    for (const void* k : {(const void*)batch_kernel<false>, (const void*)batch_kernel<true>})
+        check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes - 64)),
+                  "hipFuncSetAttribute(batch_kernel)");
     g_attr_set = true;
 }
 
@@ -956,14 +985,20 @@ void launch(const Plan& p, void* stream_ptr)
                               : (f & kTileDirectStore) ? kModeDirectStore
                               : (f & kTileGatherStore) ? kModeGatherStore
                                                        : kModeStaged;
-        const void* k = kTileKernels[(mode - 1) + ((f & kTileStreamStores) ? 4 : 0)];
+        // streaming stores come with streaming loads (a destination of 1 GiB
+        // or more has a source of far more than 256 MB in every layout pair)
+        const uint32_t variant = (f & kTileStreamStores) ? 2 : (f & kTileStreamLoads) ? 1 : 0;
+        const void* k = kTileKernels[(mode - 1) + 4 * variant];
         void* args[] = {(void*)&p.tile};
         check_hip(hipLaunchKernel(k, dim3(grid), dim3(p.threads), args, p.tile.h.lds_bytes, stream),
                   "hipLaunchKernel(tile_kernel)");
         break;
     }
     case LLAMA_PATH_STREAM:
-        hipLaunchKernelGGL(stream_kernel, dim3(grid), dim3(p.threads), 0, stream, p.stream);
+        if (p.stream.flags & kStreamLoadsOnce)
+            hipLaunchKernelGGL(stream_kernel<true>, dim3(grid), dim3(p.threads), 0, stream, p.stream);
+        else
+            hipLaunchKernelGGL(stream_kernel<false>, dim3(grid), dim3(p.threads), 0, stream, p.stream);
         break;
     case LLAMA_PATH_NAIVE:
         hipLaunchKernelGGL(naive_kernel, dim3(grid), dim3(p.threads), 0, stream, p.naive);
@@ -987,7 +1022,10 @@ void launch_hash(const void* p, uint64_t len, unsigned long long* acc, void* str
 void launch_batch_args(const BatchArgs& args, uint32_t grid, uint32_t threads, uint32_t lds_bytes, void* stream)
 {
     set_attributes();
-    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(threads), lds_bytes, (hipStream_t)stream, args);
+    if (args.flags & kBatchLoadsOnce)
+        hipLaunchKernelGGL(batch_kernel<true>, dim3(grid), dim3(threads), lds_bytes, (hipStream_t)stream, args);
+    else
+        hipLaunchKernelGGL(batch_kernel<false>, dim3(grid), dim3(threads), lds_bytes, (hipStream_t)stream, args);
     check_hip(hipGetLastError(), "batch kernel launch");
 }
 

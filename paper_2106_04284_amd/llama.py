@@ -71,7 +71,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("path", ctypes.c_uint32), ("tile_records", ctypes.c_uint32), ("threads", ctypes.c_uint32),
                 ("lds_bytes", ctypes.c_uint32), ("workgroups", ctypes.c_uint64), ("runs", ctypes.c_uint32),
                 ("wg_per_cu", ctypes.c_uint32), ("tiles", ctypes.c_uint64), ("read_bytes", ctypes.c_uint64),
-                ("write_bytes", ctypes.c_uint64), ("tile_mode", ctypes.c_uint32), ("stream_stores", ctypes.c_uint32)]
+                ("write_bytes", ctypes.c_uint64), ("tile_mode", ctypes.c_uint32), ("cache_hints", ctypes.c_uint32)]
 
 
 class CopyItem(ctypes.Structure):
@@ -327,7 +327,8 @@ def plan(src: Mapping, dst: Mapping, path=PATH_AUTO, tile_records=0, threads=0, 
             "lds_bytes": info.lds_bytes, "workgroups": info.workgroups, "runs": info.runs,
             "wg_per_cu": info.wg_per_cu, "tiles": info.tiles,
             "read_bytes": info.read_bytes, "write_bytes": info.write_bytes,
-            "tile_mode": TILE_MODE_NAMES.get(info.tile_mode), "stream_stores": bool(info.stream_stores)}
+            "tile_mode": TILE_MODE_NAMES.get(info.tile_mode), "stream_loads": bool(info.cache_hints & 1),
+            "stream_stores": bool(info.cache_hints & 2)}
 
 
 # --------------------------------------------------------------------------

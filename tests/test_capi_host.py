@@ -191,6 +191,13 @@ def test_tile_modes():
     assert plan("particle", A, Q8, n=(1 << 30) // 28 + 1000)["stream_stores"]
     assert not plan("lbm", M, AA, n=128 ** 3)["stream_stores"]
     assert not plan("particle", A, A, n=1 << 26)["stream_stores"]  # STREAM path: plain stores
+    # nontemporal loads from 256 MiB of source up (the Infinity Cache): the
+    # 128^3 lattice-Boltzmann grid (336 MB), not a 58 MB batch of frames
+    assert plan("lbm", M, AA, n=128 ** 3)["stream_loads"]
+    assert plan("particle", A, A, n=1 << 26)["stream_loads"]  # STREAM path too
+    assert not plan("particle", S, Q32, n=4096 * 256)["stream_loads"]
+    assert not plan("particle", A, Q8, n=(256 << 20) // 28 - 1000)["stream_loads"]
+    assert plan("particle", A, Q8, n=(256 << 20) // 28 + 1000)["stream_loads"]
     # LDS of a gathering tile: the source region (512 records of 28 bytes and
     # room for the 16-byte phase) plus the word table of one destination
     # block (8 records of 28 bytes: 56 words), and no destination region
