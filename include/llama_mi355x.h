@@ -291,7 +291,7 @@ int llama_tune_save(const char* path);
 int llama_tune_load(const char* path, uint32_t* entries);
 
 /* ------------------------------------------------------------------------ */
-/* Batches: many independent copies in one persistent launch                */
+/* Batches: many independent copies in one launch                           */
 /* ------------------------------------------------------------------------ */
 
 /* One copy of a batch; the same contract as llama_copy's arguments. */
@@ -303,11 +303,14 @@ typedef struct {
 } llama_copy_item;
 
 /* A prepared batch: the items' plans in one device work table, run by one
- * persistent kernel whose workgroups take blocks of work units (the tiles of
- * tiled items and the 4 KiB chunks of long-run items) from an atomic counter
- * in the table.  The launch is captured into a hipGraph on the first
- * llama_batch_launch on a non-null stream and replayed afterwards.  The
- * result equals n separate llama_copy calls.
+ * kernel launch over the work units (the tiles of tiled items and the 4 KiB
+ * chunks of long-run items).  Items that all fall in one LDS class (long
+ * runs, or tiles of up to 1, 2, 4, ... KiB of LDS) run one workgroup per work
+ * unit; a batch of several classes runs a persistent grid whose workgroups
+ * take blocks of units from an atomic counter in the table.  The launch is
+ * captured into a hipGraph on the first llama_batch_launch on a non-null
+ * stream and replayed afterwards.  The result equals n separate llama_copy
+ * calls.
  *  - Validation: every item as in llama_copy; no destination range may
  *    overlap another destination range or any source range of the batch
  *    (items run in no fixed order).
@@ -315,7 +318,8 @@ typedef struct {
  *    blobs stay the caller's and must stay valid while launches are pending.
  *  - Options (may be NULL): tile_records (a fixed tile size for every TILE
  *    item, 0: each item's own), threads (per workgroup, for every item),
- *    wg_per_cu (workgroups per compute unit, 1 .. 16; 0: as many as LDS and
+ *    wg_per_cu (1 .. 16: a persistent grid of that many workgroups per compute
+ *    unit; 0: the choice above, a persistent grid taking as many as LDS and
  *    wave slots allow, at most 8); path must be 0, flags takes the
  *    LLAMA_COPY_* bits.  Every workgroup reserves
  *    the largest item's LDS, so without a fixed tile size each tiled item
@@ -336,8 +340,8 @@ typedef struct {
     uint64_t read_bytes;   /* source blob bytes of all items */
     uint64_t write_bytes;  /* destination blob bytes of all items */
     uint32_t threads;      /* threads per workgroup */
-    uint32_t wg_per_cu;    /* workgroups per compute unit */
-    uint32_t workgroups;   /* persistent grid size */
+    uint32_t wg_per_cu;    /* persistent grid: workgroups per compute unit; 0: one workgroup per work unit */
+    uint32_t workgroups;   /* grid size */
     uint32_t lds_bytes;    /* LDS per workgroup */
 } llama_batch_info;
 

@@ -83,7 +83,7 @@ std::map<std::tuple<uint64_t, uint32_t, uint64_t, uint32_t, uint64_t, uint32_t, 
 
 } // namespace
 
-void BatchTable::add(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags)
+Plan batch_plan(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags)
 {
     llama_copy_options o{LLAMA_PATH_AUTO, tile_records, threads, 0, flags};
     Plan p;
@@ -129,10 +129,27 @@ void BatchTable::add(const Request& rq, uint32_t threads, uint32_t tile_records,
             g_tile_memo[key] = T * 2;
         }
     }
+    if (p.path != LLAMA_PATH_EMPTY && p.path != LLAMA_PATH_TILE && p.path != LLAMA_PATH_STREAM)
+        fail(LLAMA_E_UNSUPPORTED, "its record does not fit the tiled kernel; copy it with llama_copy");
+    return p;
+}
+
+void BatchTable::add(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags)
+{
+    add_plan(batch_plan(rq, threads, tile_records, flags));
+}
+
+void BatchTable::add_plan(const Plan& p)
+{
     read_bytes += p.read_bytes;
     write_bytes += p.write_bytes;
     if (p.path == LLAMA_PATH_EMPTY)
         return;
+    uint32_t cls = 0;
+    if (p.path == LLAMA_PATH_TILE)
+        for (cls = 1; (uint64_t(1024) << (cls - 1)) < p.tile.h.lds_bytes && cls < 31; cls++) {
+        }
+    classes |= 1u << cls;
     BatchItem it{};
     if (p.path == LLAMA_PATH_TILE) {
         it.kind = kItemTile;
@@ -164,14 +181,16 @@ void BatchTable::add(const Request& rq, uint32_t threads, uint32_t tile_records,
 namespace {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct TableLayout {
-    size_t counters, begin, items, entries, runs, total;
+    size_t counters, begin, hint, items, entries, runs, total;
 };
+size_t hint_count(uint64_t units) { return size_t((units >> kBatchHintLog2) + 2); }
 TableLayout table_layout(const BatchTable& t)
 {
     TableLayout l;
     l.counters = 0;
     l.begin = align256(2 * sizeof(unsigned long long));
-    l.items = align256(l.begin + (t.unit_begin.size() + 1) * sizeof(uint64_t));
+    l.hint = align256(l.begin + (t.unit_begin.size() + 1) * sizeof(uint64_t));
+    l.items = align256(l.hint + hint_count(t.units) * sizeof(uint32_t));
     l.entries = align256(l.items + std::max<size_t>(t.items.size(), 1) * sizeof(BatchItem));
     l.runs = align256(l.entries + std::max<size_t>(t.entries.size(), 1) * sizeof(TileEntry));
     l.total = align256(l.runs + std::max<size_t>(t.runs.size(), 1) * sizeof(StreamRun));
@@ -190,6 +209,15 @@ void BatchTable::serialise(uint8_t* host, uint64_t device, BatchArgs& args) cons
     std::memset(host, 0, l.total);
     std::memcpy(host + l.begin, unit_begin.data(), unit_begin.size() * sizeof(uint64_t));
     std::memcpy(host + l.begin + unit_begin.size() * sizeof(uint64_t), &units, sizeof(uint64_t));
+    // the item of every 2^kBatchHintLog2-th unit (the last item past the end)
+    uint32_t* hint = (uint32_t*)(host + l.hint);
+    size_t j = 0;
+    for (size_t c = 0; c < hint_count(units); c++) {
+        const uint64_t g = uint64_t(c) << kBatchHintLog2;
+        while (j + 1 < unit_begin.size() && unit_begin[j + 1] <= g)
+            j++;
+        hint[c] = uint32_t(j);
+    }
     if (!items.empty())
         std::memcpy(host + l.items, items.data(), items.size() * sizeof(BatchItem));
     if (!entries.empty())
@@ -198,12 +226,26 @@ void BatchTable::serialise(uint8_t* host, uint64_t device, BatchArgs& args) cons
         std::memcpy(host + l.runs, runs.data(), runs.size() * sizeof(StreamRun));
     args.counters = (unsigned long long*)(device + l.counters);
     args.unit_begin = (const uint64_t*)(device + l.begin);
+    args.hint = (const uint32_t*)(device + l.hint);
     args.items = (const BatchItem*)(device + l.items);
     args.entries = (const TileEntry*)(device + l.entries);
     args.runs = (const StreamRun*)(device + l.runs);
     args.total_units = units;
     args.num_items = uint32_t(items.size());
     args.flags = read_bytes >= kStreamLoadBytes ? kBatchLoadsOnce : 0u;
+}
+
+// A batch whose items share one LDS class runs one workgroup per work unit:
+// the dispatcher keeps every workgroup's footprint small and starts them as
+// residency allows (4,096 particle frames of one class: 2.7x faster than a
+// persistent grid).  A batch spanning several classes runs a persistent grid
+// over one table instead: every workgroup of a launch reserves the largest
+// class's LDS, and the persistent workgroups overlap items of different
+// kinds (the 1,000-array batch: +5% over one workgroup per unit, with or
+// without one launch per class).
+bool batch_per_unit(const BatchTable& t)
+{
+    return (t.classes & (t.classes - 1)) == 0;
 }
 
 uint32_t batch_wg_per_cu(uint32_t lds_bytes, uint32_t threads)
@@ -214,10 +256,12 @@ uint32_t batch_wg_per_cu(uint32_t lds_bytes, uint32_t threads)
     return std::max<uint32_t>(1, std::min<uint32_t>(fit, 8));
 }
 
-uint32_t batch_grid(uint64_t units, uint32_t lds_bytes, uint32_t threads, uint32_t wg_per_cu)
+uint32_t batch_grid(uint64_t units, uint32_t wg_per_cu)
 {
-    const uint32_t w = wg_per_cu ? wg_per_cu : batch_wg_per_cu(lds_bytes, threads);
-    return uint32_t(std::min<uint64_t>(std::max<uint64_t>(units, 1), uint64_t(device_cu_count()) * w));
+    const uint64_t u = std::max<uint64_t>(units, 1);
+    if (wg_per_cu == 0)
+        return uint32_t(std::min<uint64_t>(u, kBatchMaxGrid));
+    return uint32_t(std::min<uint64_t>(u, uint64_t(device_cu_count()) * wg_per_cu));
 }
 
 Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_options* opt)
@@ -266,8 +310,9 @@ Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_opt
     b->read_bytes = t.read_bytes;
     b->write_bytes = t.write_bytes;
     check_hip(hipGetDevice(&b->device), "hipGetDevice");
-    b->wg_per_cu = (opt && opt->wg_per_cu) ? opt->wg_per_cu : batch_wg_per_cu(t.lds_bytes, threads);
-    b->grid = batch_grid(t.units, t.lds_bytes, threads, b->wg_per_cu);
+    const uint32_t w = opt ? opt->wg_per_cu : 0;
+    b->wg_per_cu = w ? w : batch_per_unit(t) ? 0 : batch_wg_per_cu(t.lds_bytes, threads);
+    b->grid = batch_grid(t.units, b->wg_per_cu);
 
     const size_t total = t.bytes();
     std::vector<uint8_t> host(total);

@@ -11,13 +11,13 @@ namespace llama {
 struct Batch {
     int device = 0;
     uint32_t threads = 0;
-    uint32_t wg_per_cu = 0;
+    uint32_t wg_per_cu = 0; // persistent: workgroups per compute unit; 0: one workgroup per work unit
     uint32_t grid = 0;
     uint32_t lds_bytes = 0; // largest TILE item
     uint64_t total_units = 0;
     uint64_t items = 0, tile_items = 0, stream_items = 0;
     uint64_t read_bytes = 0, write_bytes = 0;
-    void* table = nullptr; // device work table (counters, prefix, items, entries, runs)
+    void* table = nullptr; // device work table (counters, prefix, hints, items, entries, runs)
     size_t table_bytes = 0;
     void* graph_exec = nullptr; // hipGraphExec_t of the captured launch
     BatchArgs args{};
@@ -33,10 +33,15 @@ struct BatchTable {
     uint32_t lds_bytes = 0;
     uint64_t tile_items = 0, stream_items = 0;
     uint64_t read_bytes = 0, write_bytes = 0;
+    // LDS classes of the items: bit 0 long runs, bit c >= 1 tiles of at
+    // most 2^(c + 9) bytes of LDS
+    uint32_t classes = 0;
 
     // plans `rq` with `threads` per workgroup and adds it; fails with
     // LLAMA_E_UNSUPPORTED for a record the tiled kernel cannot hold
     void add(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags = 0);
+    // adds an item planned by batch_plan
+    void add_plan(const Plan& p);
     // bytes of the serialised table
     size_t bytes() const;
     // writes the table to `host` (bytes() long) as it must lie at device
@@ -48,12 +53,21 @@ struct BatchTable {
 // tile size: five workgroups fit one compute unit
 constexpr uint32_t kBatchLdsBytes = kHardLdsBytes / 5 - 64;
 
-// resident workgroups per compute unit for a table run with `threads`: as
-// many as LDS and wave slots allow, at most 8
+// How a table runs: one workgroup per work unit when its items share one LDS
+// class, else a persistent grid (see create_batch).
+bool batch_per_unit(const BatchTable& t);
+// resident workgroups per compute unit of a persistent grid: as many as LDS
+// and wave slots allow, at most 8
 uint32_t batch_wg_per_cu(uint32_t lds_bytes, uint32_t threads);
-// the persistent grid: wg_per_cu (0: batch_wg_per_cu) workgroups per compute
-// unit, and no more than there are units
-uint32_t batch_grid(uint64_t units, uint32_t lds_bytes, uint32_t threads, uint32_t wg_per_cu);
+// The grid of a batch launch: wg_per_cu 0 launches one workgroup per work
+// unit (at most kBatchMaxGrid workgroups, which then loop over the units);
+// 1 .. 16 a persistent grid of that many workgroups per compute unit, no
+// more than there are units.
+constexpr uint64_t kBatchMaxGrid = uint64_t(1) << 24;
+uint32_t batch_grid(uint64_t units, uint32_t wg_per_cu);
+
+// the plan of a batch item (see BatchTable::add)
+Plan batch_plan(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags);
 
 Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_options* opt);
 void launch_batch(Batch* b, void* stream);

@@ -225,8 +225,13 @@ struct BatchItem {
     uint32_t pad[2];
 };
 
+// hint[c] = the item of work unit c << kBatchHintLog2 (the one-workgroup-
+// per-unit launch searches only the items between two hints)
+constexpr uint32_t kBatchHintLog2 = 10;
+
 struct BatchArgs {
     const uint64_t* unit_begin; // num_items + 1 prefix sums of work units
+    const uint32_t* hint;       // ceil(total_units / 2^kBatchHintLog2) + 1 item indices
     const BatchItem* items;
     const TileEntry* entries;
     const StreamRun* runs;

@@ -796,6 +796,42 @@ __device__ __forceinline__ uint32_t batch_item_of(const CONSTANT uint64_t* begin
     return lo;
 }
 
+// One workgroup per work unit, the default batch launch: the dispatcher
+// starts workgroups as residency allows, as for single copies, which
+// measured faster than any persistent grid; unit g's item is found by binary
+// search over the unit prefix sums, between the hints of g's block of units.  With as many workgroups as units, each
+// XCD takes one contiguous eighth of the units (as tile_kernel does).
+template <bool kOnce>
+__global__ void __launch_bounds__(1024) batch_unit_kernel(const BatchArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    const CONSTANT uint64_t* begin = (const CONSTANT uint64_t*)a.unit_begin;
+    const uint64_t nt = a.total_units;
+    uint64_t g = blockIdx.x, stride = gridDim.x;
+    if (gridDim.x == nt) {
+        const uint64_t b = blockIdx.x, x = b & 7u, k = b >> 3, q = nt >> 3, rem = nt & 7u;
+        g = x * q + min(x, rem) + k;
+        stride = nt;
+    }
+    const CONSTANT uint32_t* hint = (const CONSTANT uint32_t*)a.hint;
+    uint32_t table_item = ~0u;
+    for (; g < nt; g += stride) {
+        // the item lies between the hints of g's block of units
+        const uint64_t c = g >> kBatchHintLog2;
+        uint32_t lo = hint[c], hi = min(hint[c + 1] + 1u, a.num_items);
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (begin[mid] <= g)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        batch_unit<kOnce>(a, begin, lo, g, lds, table_item);
+        if (g + stride < nt)
+            __syncthreads();
+    }
+}
+
 // kOnce: nontemporal source loads (BatchArgs.flags & kBatchLoadsOnce).
 template <bool kOnce>
 __global__ void __launch_bounds__(1024) batch_kernel(const BatchArgs a)
@@ -940,7 +976,8 @@ void set_attributes()
     for (const void* k : kTileKernels)
         check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes)),
                   "hipFuncSetAttribute(tile_kernel)");
-    for (const void* k : {(const void*)batch_kernel<false>, (const void*)batch_kernel<true>})
+    for (const void* k : {(const void*)batch_kernel<false>, (const void*)batch_kernel<true>,
+                          (const void*)batch_unit_kernel<false>, (const void*)batch_unit_kernel<true>})
         check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes - 64)),
                   "hipFuncSetAttribute(batch_kernel)");
     g_attr_set = true;
@@ -1019,19 +1056,22 @@ void launch_hash(const void* p, uint64_t len, unsigned long long* acc, void* str
     check_hip(hipGetLastError(), "hash kernel launch");
 }
 
-void launch_batch_args(const BatchArgs& args, uint32_t grid, uint32_t threads, uint32_t lds_bytes, void* stream)
+void launch_batch_args(const BatchArgs& args, uint32_t grid, uint32_t threads, uint32_t lds_bytes, bool persistent,
+                       void* stream)
 {
     set_attributes();
-    if (args.flags & kBatchLoadsOnce)
-        hipLaunchKernelGGL(batch_kernel<true>, dim3(grid), dim3(threads), lds_bytes, (hipStream_t)stream, args);
-    else
-        hipLaunchKernelGGL(batch_kernel<false>, dim3(grid), dim3(threads), lds_bytes, (hipStream_t)stream, args);
+    const bool once = (args.flags & kBatchLoadsOnce) != 0;
+    const void* k = persistent ? (once ? (const void*)batch_kernel<true> : (const void*)batch_kernel<false>)
+                               : (once ? (const void*)batch_unit_kernel<true> : (const void*)batch_unit_kernel<false>);
+    void* kargs[] = {(void*)&args};
+    check_hip(hipLaunchKernel(k, dim3(grid), dim3(threads), kargs, lds_bytes, (hipStream_t)stream),
+              "hipLaunchKernel(batch)");
     check_hip(hipGetLastError(), "batch kernel launch");
 }
 
 void launch_batch_kernel(const Batch& b, void* stream)
 {
-    launch_batch_args(b.args, b.grid, b.threads, b.lds_bytes, stream);
+    launch_batch_args(b.args, b.grid, b.threads, b.lds_bytes, b.wg_per_cu != 0, stream);
 }
 
 } // namespace llama

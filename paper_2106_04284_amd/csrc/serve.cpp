@@ -220,8 +220,8 @@ void Server::launch_slot(Slot& s, std::vector<Pending>& group)
             BatchArgs args{};
             t.serialise((uint8_t*)s.host, uint64_t(uintptr_t(s.dev)), args);
             check_hip(hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice, s.stream), "hipMemcpyAsync(table)");
-            launch_batch_args(args, batch_grid(t.units, t.lds_bytes, cfg.threads, 0), cfg.threads, t.lds_bytes,
-                              s.stream);
+            const uint32_t w = batch_per_unit(t) ? 0 : batch_wg_per_cu(t.lds_bytes, cfg.threads);
+            launch_batch_args(args, batch_grid(t.units, w), cfg.threads, t.lds_bytes, w != 0, s.stream);
         }
     } else {
         llama_copy_options o{cfg.policy == LLAMA_SERVE_NAIVE ? uint32_t(LLAMA_PATH_NAIVE) : uint32_t(LLAMA_PATH_AUTO),

@@ -17,6 +17,7 @@ void server_reset_stats(Server* s);
 void destroy_server(Server* s);
 
 // kernels.hip: one launch of the batch kernel over a serialised work table
-void launch_batch_args(const BatchArgs& args, uint32_t grid, uint32_t threads, uint32_t lds_bytes, void* stream);
+void launch_batch_args(const BatchArgs& args, uint32_t grid, uint32_t threads, uint32_t lds_bytes, bool persistent,
+                       void* stream);
 
 } // namespace llama

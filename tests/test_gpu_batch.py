@@ -97,19 +97,23 @@ def test_batch_equals_lone_copies(L, orc):
     check(items, want)
 
 
-@pytest.mark.parametrize("opts", [dict(threads=64), dict(threads=512), dict(wg_per_cu=1), dict(wg_per_cu=16),
+@pytest.mark.parametrize("opts", [dict(threads=64), dict(threads=512), dict(wg_per_cu=1), dict(wg_per_cu=5),
+                                  dict(wg_per_cu=16), dict(wg_per_cu=2, tile_records=16),
                                   dict(tile_records=64, threads=128), dict(tile_records=16)])
 def test_batch_options(L, orc, opts):
     items, want = make_items(L, orc, 5, count=20, nmax=8000)
     b = L.Batch(items, **opts)
     info = b.info()
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    if opts.get("wg_per_cu"):
+    if opts.get("wg_per_cu"):  # a persistent grid of that many workgroups per compute unit
         assert info["wg_per_cu"] == opts["wg_per_cu"]
-    else:  # as many as fit a compute unit's LDS and wave slots
+    elif info["wg_per_cu"]:  # items of several LDS classes: as many as fit LDS and wave slots
         w = min(160 * 1024 // (info["lds_bytes"] + 64), 32 // (info["threads"] // 64), 8)
         assert info["wg_per_cu"] == max(1, w)
-    assert info["workgroups"] == min(info["work_units"], cus * info["wg_per_cu"])
+    if info["wg_per_cu"]:
+        assert info["workgroups"] == min(info["work_units"], cus * info["wg_per_cu"])
+    else:  # one workgroup per work unit
+        assert info["workgroups"] == info["work_units"]
     if not opts.get("tile_records"):
         assert info["lds_bytes"] <= 160 * 1024 // 5 - 64
     torch.cuda.synchronize()  # inputs were written on the default stream
@@ -119,6 +123,56 @@ def test_batch_options(L, orc, opts):
         b.launch()  # a second run over the same destinations gives the same bytes
     stream.synchronize()
     check(items, want)
+
+
+ONE_CLASS = [("particle", ("soa_single", 0), ("aosoa", 32)), ("particle", ("aos_packed", 0), ("aosoa", 8)),
+             ("particle", ("soa_multi", 0), ("soa_single", 0)), ("mixed", ("aos_aligned", 0), ("aosoa", 64))]
+
+
+@pytest.mark.parametrize("case", ONE_CLASS, ids=[f"{c[0]}-{c[1][0]}{c[1][1] or ''}-{c[2][0]}{c[2][1] or ''}"
+                                                 for c in ONE_CLASS])
+def test_one_class_batch_runs_one_workgroup_per_unit(L, orc, case):
+    """Items that share one LDS class (frames of one layout pair) run one
+    workgroup per work unit; a batch with items of several classes runs a
+    persistent grid.  Both leave the oracle's bytes, over two graph replays."""
+    name, a, b = case
+    items, want = make_items_pair(L, orc, 41, 30, 5000, name, a, b)
+    bt = L.Batch(items)
+    info = bt.info()
+    assert info["wg_per_cu"] == 0 and info["workgroups"] == info["work_units"]
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        bt.launch()
+        bt.launch()
+    stream.synchronize()
+    check(items, want)
+    # adding items of another class makes the batch persistent
+    more, more_want = make_items(L, orc, 43, count=12, nmax=5000)
+    mixed_batch = L.Batch(items + more)
+    assert mixed_batch.info()["wg_per_cu"] > 0
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        mixed_batch.launch()
+    stream.synchronize()
+    check(items + more, want + more_want)
+
+
+def make_items_pair(L, orc, seed, count, nmax, name, a, b):
+    """Items of one record and one layout pair, random sizes (at least 100
+    records, so that every item is tiled the same way)."""
+    g = random.Random(seed)
+    rec = W.RECORDS[name]
+    items, want = [], []
+    for k in range(count):
+        n = g.randint(100, nmax)
+        ro, rg = orc.Record(rec), L.Record(rec)
+        ms_o, md_o = orc.Mapping(ro, a[0], [n], a[1]), orc.Mapping(ro, b[0], [n], b[1])
+        src = [W.random_bytes(s, seed * 7919 + k * 31 + j) for j, s in enumerate(ms_o.blob_sizes())]
+        want.append(orc.copy(ms_o, src, md_o))
+        ms, md = L.Mapping(rg, a[0], [n], a[1]), L.Mapping(rg, b[0], [n], b[1])
+        items.append((ms, [torch.from_numpy(x).cuda() for x in src], md, md.alloc(fill=0xCD)))
+    return items, want
 
 
 def test_one_shot_batch_and_null_stream(L, orc):
