@@ -164,11 +164,19 @@ void BatchTable::add_plan(const Plan& p)
         lds_bytes = std::max(lds_bytes, p.tile.h.lds_bytes);
         tile_items++;
     } else if (p.path == LLAMA_PATH_STREAM) {
+        // a batch moves a run in 16 KiB units (four 16-byte loads per thread
+        // in flight): 4 KiB units starved the persistent grid's workgroups
         it.kind = kItemStream;
         it.count = p.stream.num_runs;
         it.first = runs.size();
-        it.h.num_tiles = p.stream.num_chunks;
-        runs.insert(runs.end(), p.stream.r, p.stream.r + p.stream.num_runs);
+        uint64_t chunks = 0;
+        for (uint32_t r = 0; r < p.stream.num_runs; r++) {
+            StreamRun run = p.stream.r[r];
+            run.first_chunk = chunks;
+            chunks += (run.bytes + (uint64_t(1) << kBatchStreamChunkLog2) - 1) >> kBatchStreamChunkLog2;
+            runs.push_back(run);
+        }
+        it.h.num_tiles = chunks;
         stream_items++;
     } else {
         fail(LLAMA_E_UNSUPPORTED, "its record does not fit the tiled kernel; copy it with llama_copy");

@@ -156,7 +156,8 @@ static_assert(sizeof(TileArgs) <= 4096, "kernel arguments are limited to 4 KiB")
 // ---------------------------------------------------------------------------
 
 constexpr int kStreamMaxRuns = 120;
-constexpr uint32_t kStreamChunkLog2 = 12; // 4 KiB per workgroup
+constexpr uint32_t kStreamChunkLog2 = 12;      // 4 KiB per workgroup (a single copy)
+constexpr uint32_t kBatchStreamChunkLog2 = 14; // 16 KiB per work unit of a batch
 
 struct StreamRun {
     uint64_t src;

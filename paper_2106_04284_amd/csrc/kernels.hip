@@ -714,8 +714,9 @@ __device__ __forceinline__ void copy_run_chunk(uint64_t dst, uint64_t src, uint6
 
 // Work unit c of a run list: the run holding chunk c is the last run whose
 // first chunk is <= c.  `run(k)` returns run k.
+// Chunks are 2^chunk_log2 bytes.
 template <bool kOnce, typename Runs>
-__device__ __forceinline__ void stream_unit(Runs run, uint32_t num_runs, uint64_t c)
+__device__ __forceinline__ void stream_unit(Runs run, uint32_t num_runs, uint64_t c, uint32_t chunk_log2)
 {
     uint32_t lo = 0, hi = num_runs;
     while (hi - lo > 1) {
@@ -726,8 +727,8 @@ __device__ __forceinline__ void stream_unit(Runs run, uint32_t num_runs, uint64_
             hi = mid;
     }
     const auto& r = run(lo);
-    const uint64_t off = (c - r.first_chunk) << kStreamChunkLog2;
-    const uint64_t len = min<uint64_t>(r.bytes - off, uint64_t(1) << kStreamChunkLog2);
+    const uint64_t off = (c - r.first_chunk) << chunk_log2;
+    const uint64_t len = min<uint64_t>(r.bytes - off, uint64_t(1) << chunk_log2);
     copy_run_chunk<kOnce>(r.dst + off, r.src ? r.src + off : 0, len, threadIdx.x, blockDim.x);
 }
 
@@ -737,7 +738,7 @@ __global__ void __launch_bounds__(1024) stream_kernel(const StreamArgs a)
 {
     auto run = [&](uint32_t k) -> const StreamRun& { return a.r[k]; };
     for (uint64_t c = blockIdx.x; c < a.num_chunks; c += gridDim.x)
-        stream_unit<kOnce>(run, a.num_runs, c);
+        stream_unit<kOnce>(run, a.num_runs, c, kStreamChunkLog2);
 }
 
 // ---------------------------------------------------------------------------
@@ -778,7 +779,8 @@ __device__ __forceinline__ void batch_unit(const BatchArgs& a, const CONSTANT ui
             h, [&](uint32_t k) -> const CONSTANT TileEntry& { return entries[k]; }, u, lds, &gg);
     } else {
         const CONSTANT StreamRun* runs = (const CONSTANT StreamRun*)a.runs + it->first;
-        stream_unit<kOnce>([&](uint32_t k) -> const CONSTANT StreamRun& { return runs[k]; }, it->count, u);
+        stream_unit<kOnce>([&](uint32_t k) -> const CONSTANT StreamRun& { return runs[k]; }, it->count, u,
+                           kBatchStreamChunkLog2);
     }
 }
 
