@@ -499,19 +499,28 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
                                             (side.lanes * sz) % 16 == 0);
     };
     // direct store: destination leaf values in 16-byte granules of one leaf,
-    // starting 16-byte aligned, with leaf sizes 1..16 (powers of two) read at
-    // their own width
+    // with leaf sizes 1..16 (powers of two) read at their own width; an AoSoA
+    // destination's lane runs start 16-byte aligned, a field-major leaf span
+    // may start at any multiple of its size (its phase in the granule grid:
+    // the partial first and last granules are written value by value)
     bool direct = rq.dst.gaps.empty() && !(p.flags_in & kPlanNoDirect);
     for (size_t f = 0; f < F && direct; f++) {
         const TileEntry& e = ta.e[f];
         const uint32_t sz = e.size;
-        direct = sz <= 16 && (sz & (sz - 1)) == 0 && granule_runs(a.dst, sz) && (e.dst_addr & 15) == 0 &&
-                 (1u << (e.move & 7u)) == sz;
+        const uint64_t src_bits = uint64_t(e.src_pos) | sz | src_rm_bits;
+        direct = sz <= 16 && (sz & (sz - 1)) == 0 && granule_runs(a.dst, sz) &&
+                 (a.dst.mode == kFieldMajor ? e.dst_addr % sz == 0 : (e.dst_addr & 15) == 0) &&
+                 lowbit(src_bits | 16) >= sz;
     }
     if (direct) {
         a.flags |= kTileDirectStore;
         a.dst.lds_bytes = 0;
         a.lds_bytes = sb;
+        for (size_t f = 0; f < F; f++) { // the width is the leaf size; the phase replaces the split bits
+            TileEntry& e = ta.e[f];
+            const uint32_t phase = a.dst.mode == kFieldMajor ? uint32_t((e.dst_addr & 15) / e.size) : 0u;
+            e.move = (e.move & ~(7u | kMoveSplit | (0xFFu << 20))) | log2_exact(e.size) | (phase << 20);
+        }
     }
     const bool preserve = preserve_padding(rq, p);
     // gather store: a record-major destination whose blocks are whole 4-byte

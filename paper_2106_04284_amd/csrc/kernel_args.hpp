@@ -48,7 +48,9 @@ struct TileEntry {
                        // (kMoveSplit); bits 4-7: first loading wave of this leaf's source span;
                        // bits 8-19: first storing thread of this leaf's destination span;
                        // bits 20-22: log2 of the read alignment; bits 24-26: log2 of the write
-                       // alignment; bit 31: gap (write zeros)
+                       // alignment (split moves); with kTileDirectStore, bits 20-23: the
+                       // destination span's phase in values, (dst_addr mod 16) / size;
+                       // bit 31: gap (write zeros)
 };
 
 // A leaf of 2, 4 or 8 bytes whose source or destination positions are aligned

@@ -299,33 +299,40 @@ __device__ __forceinline__ T src_value(const uint8_t* lds, uint32_t sp, const Ti
 // Direct store of one leaf: every 16-byte granule of the leaf's destination
 // values (a field-major span, or the lane runs of an AoSoA block) gathers
 // 16 / size consecutive records from the source region; records >= nv (AoSoA
-// lanes past the last record) are zero; a granule that passes record nd is
-// stored value by value.  `gdst` is the leaf's tile base on side d.
+// lanes past the last record) are zero.  A field-major span that starts `ph`
+// values past the 16-byte grid (the granules stay on the grid) and a granule
+// that passes record nd are stored value by value, only for records 0 .. nd
+// - 1 of the tile.  `gdst` is the leaf's tile base on side d.
 template <typename T, bool kDstRecordMajor, bool kStream>
 __device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t sp, const TileSide& s,
                                                   const TileSide& d, uint64_t gdst, uint32_t nv, uint32_t nd,
-                                                  uint32_t tid, uint32_t nthr, uint32_t rot)
+                                                  uint32_t tid, uint32_t nthr, uint32_t rot, uint32_t ph)
 {
     constexpr uint32_t per = 16 / sizeof(T);
-    const uint32_t G = (nd + per - 1) / per;
+    const uint32_t G = (nd + ph + per - 1) / per;
+    const uint64_t gbase = gdst - uint64_t(ph) * sizeof(T); // 16-byte aligned
     for (uint32_t g = tid >= rot ? tid - rot : tid + nthr - rot; g < G; g += nthr) {
-        const uint32_t r0 = g * per;
+        const int32_t r0 = int32_t(g * per) - int32_t(ph); // record of the granule's first value
         union {
             u32x4 v;
             T t[per];
         } u;
 #pragma unroll
-        for (uint32_t j = 0; j < per; j++)
-            u.t[j] = r0 + j < nv ? src_value<T>(lds, sp, s, r0 + j, sizeof(T)) : T{};
+        for (uint32_t j = 0; j < per; j++) {
+            const int32_t r = r0 + int32_t(j);
+            u.t[j] = r >= 0 && uint32_t(r) < nv ? src_value<T>(lds, sp, s, uint32_t(r), sizeof(T)) : T{};
+        }
         constexpr uint32_t lg = sizeof(T) == 16 ? 4 : sizeof(T) == 8 ? 3 : sizeof(T) == 4 ? 2 : sizeof(T) == 2 ? 1 : 0;
-        const uint64_t a = leaf_granule_addr<kDstRecordMajor>(gdst, d, g, lg);
-        if (r0 + per <= nd) {
+        const uint64_t a = leaf_granule_addr<kDstRecordMajor>(gbase, d, g, lg);
+        if (r0 >= 0 && uint32_t(r0) + per <= nd) {
             store16<kStream>((GLOBAL u32x4*)a, u.v);
         } else {
 #pragma unroll
-            for (uint32_t j = 0; j < per; j++)
-                if (r0 + j < nd)
+            for (uint32_t j = 0; j < per; j++) {
+                const int32_t r = r0 + int32_t(j);
+                if (r >= 0 && uint32_t(r) < nd)
                     *(GLOBAL T*)(a + j * sizeof(T)) = u.t[j];
+            }
         }
     }
 }
@@ -340,13 +347,14 @@ __device__ __forceinline__ void direct_store_tile(const TileHeader& h, Entries e
         const auto& e = ent(f);
         const uint64_t gdst = leaf_tile_base<kDstRecordMajor>(e.dst_addr, h.dst, t, i0, e.size);
         const uint32_t rot = (e.move >> 8) & 4095u;
+        const uint32_t ph = (e.move >> 20) & 15u;
         const uint32_t sp = e.src_pos;
         switch (e.move & 7u) {
-        case 4: direct_store_leaf<u32x4, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
-        case 3: direct_store_leaf<uint64_t, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
-        case 2: direct_store_leaf<uint32_t, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
-        case 1: direct_store_leaf<uint16_t, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
-        default: direct_store_leaf<uint8_t, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot); break;
+        case 4: direct_store_leaf<u32x4, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
+        case 3: direct_store_leaf<uint64_t, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
+        case 2: direct_store_leaf<uint32_t, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
+        case 1: direct_store_leaf<uint16_t, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
+        default: direct_store_leaf<uint8_t, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
         }
     }
 }

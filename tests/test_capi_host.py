@@ -155,6 +155,11 @@ def test_tile_modes():
     assert mode("lbm", M, AA) == "gather_store"
     assert mode("lbm", Q32, AA) == "gather_store"
     assert mode("lbm", AA, M) == "direct_store"
+    # an odd record count puts single-blob SoA leaf spans off the 16-byte
+    # grid (4 N f bytes in): still stored directly, the partial granules at
+    # the span ends value by value
+    assert mode("particle", A, S, n=1000003) == "direct_store"
+    assert mode("mixed", AA, S, n=1000003) == "direct_store"
     # a u8 leaf (mixed) or u16 / bool leaves (listing1) share words with
     # other leaves or padding: those words are composite, read byte by byte
     assert mode("mixed", M, AA) == "gather_store"

@@ -235,6 +235,22 @@ def test_gather_store(L, orc, case, run, offsets):
              **opts)
 
 
+# field-major destinations whose leaf spans start off the 16-byte grid (an
+# odd record count in a single-blob SoA, or a blob 4, 8 or 12 bytes in): the
+# direct store writes the partial first and last granules of every span value
+# by value, and must touch no byte outside the spans
+PHASE_PAIRS = [(("aos_packed", 0), ("soa_single", 0)), (("aosoa", 8), ("soa_single", 0)),
+               (("aos_aligned", 0), ("soa_multi", 0)), (("aosoa", 32), ("soa_multi", 0))]
+
+
+@pytest.mark.parametrize("pair", PHASE_PAIRS, ids=[f"{_name(a)}-{_name(b)}" for a, b in PHASE_PAIRS])
+@pytest.mark.parametrize("name", ["particle", "mixed", "lbm"])
+@pytest.mark.parametrize("n", [1, 3, 17, 777, 4099])
+@pytest.mark.parametrize("dst_off", [0, 4, 8, 12])
+def test_direct_store_off_grid(L, orc, pair, name, n, dst_off):
+    run_case(L, orc, W.RECORDS[name], pair[0], pair[1], [n], seed=n + dst_off, dst_off=dst_off)
+
+
 @pytest.mark.parametrize("seed", range(24))
 def test_random_records(L, orc, seed):
     g = random.Random(seed)
