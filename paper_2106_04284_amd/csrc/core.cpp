@@ -523,15 +523,28 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
         }
     }
     const bool preserve = preserve_padding(rq, p);
-    // gather store: a record-major destination whose blocks are whole 4-byte
-    // words, every tile span 16-byte aligned; a source with more lanes per
-    // block than the destination needs leaf sizes that are powers of two (the
-    // lane runs of a block then advance by shifts)
-    const uint64_t gwords = rq.dst.block / 4;
-    const bool more_lanes = a.src.mode == kFieldMajor || rq.src.lanes > rq.dst.lanes;
-    bool gather = !direct && !preserve && !(p.flags_in & kPlanNoDirect) &&
-                  a.dst.mode == kRecordMajor && rq.dst.lanes <= kGatherMaxLanes && rq.dst.block % 4 == 0 &&
-                  gwords >= 2 && gwords <= kGatherMaxWords && rq.dst_ptr[0] % 16 == 0 && a.dst.tile_bytes % 16 == 0 &&
+    // gather store: a record-major destination, every tile span 16-byte
+    // aligned, planned over a super-block of gb = 1, 2 or 4 destination
+    // blocks: the fewest whose bytes, and the source bytes that its records
+    // advance by, are whole 4-byte words (4 records of a 49-byte packed
+    // record); a source with more lanes per block than the super-block has
+    // records needs leaf sizes that are powers of two (its lane runs then
+    // advance by shifts)
+    const uint64_t Ld = rq.dst.lanes;
+    auto src_advance = [&](uint64_t recs) -> uint64_t { // source bytes per super-block, 0: by shifts
+        if (a.src.mode == kFieldMajor || rq.src.lanes > recs)
+            return 0;
+        return (recs >> a.src.log2_lanes) * rq.src.block;
+    };
+    uint64_t gb = 1;
+    while (gb < 4 && ((gb * rq.dst.block) % 4 != 0 || src_advance(gb * Ld) % 4 != 0))
+        gb *= 2;
+    const uint64_t recs = gb * Ld; // records per super-block
+    const uint64_t gwords = gb * rq.dst.block / 4;
+    const bool more_lanes = src_advance(recs) == 0;
+    bool gather = !direct && !preserve && !(p.flags_in & kPlanNoDirect) && a.dst.mode == kRecordMajor &&
+                  recs <= kGatherMaxLanes && recs <= T && (gb * rq.dst.block) % 4 == 0 && gwords >= 2 &&
+                  gwords <= kGatherMaxWords && rq.dst_ptr[0] % 16 == 0 && a.dst.tile_bytes % 16 == 0 &&
                   (a.dst.tile_bytes / 4) * gwords < (uint64_t(1) << 32);
     for (size_t f = 0; f < F && gather; f++)
         gather = !more_lanes || is_pow2(r.leaves[f].size);
@@ -539,40 +552,38 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
         TileGather g{};
         g.words = uint32_t(gwords);
         g.magic = uint32_t(((uint64_t(1) << 32) + gwords - 1) / gwords);
-        const uint32_t lgd = a.dst.log2_lanes;
-        if (!more_lanes) { // at most L_d source lanes: block b starts L_d / L_s source blocks further
+        g.lg = log2_exact(recs);
+        if (!more_lanes) { // super-block b starts recs / L_s source blocks further
             g.q = 0;
-            g.mq = 0;
-            g.kq = uint32_t((rq.dst.lanes >> a.src.log2_lanes) * rq.src.block);
-        } else if (a.src.mode == kFieldMajor) { // block b starts b * L_d values further in each leaf span
+            g.kq = uint32_t(src_advance(recs));
+        } else if (a.src.mode == kFieldMajor) { // super-block b starts b * recs values further in each leaf span
             g.q = 31;
-            g.mq = 0x7FFFFFFFu;
             g.kq = 0;
         } else {
-            g.q = a.src.log2_lanes - lgd;
-            g.mq = (1u << g.q) - 1u;
+            g.q = a.src.log2_lanes - g.lg;
             g.kq = uint32_t(rq.src.block);
         }
         // the kernel's word classification: the source of every byte of
-        // destination block 0 (LDS byte for block 0, log2 lane run, record),
-        // then whole, padding or composite per word
-        const uint32_t L = uint32_t(rq.dst.lanes);
+        // destination super-block 0 (LDS byte for super-block 0, log2 of the
+        // bytes of recs values, record), then a kind per word
         std::vector<uint32_t> src_of(gwords * 4, 1u << 31);
         for (size_t f = 0; f < F; f++) {
             const TileEntry& e = ta.e[f];
-            const uint32_t run = log2_exact(uint64_t(L) * e.size);
-            for (uint32_t jj = 0; jj < L; jj++)
+            const uint32_t run = log2_exact(recs * e.size);
+            for (uint32_t jj = 0; jj < recs; jj++)
                 for (uint32_t k = 0; k < e.size; k++) {
                     const uint32_t p0 = e.src_pos + (jj >> a.src.pos_lg) * a.src.pos_k + (jj & a.src.pos_m) * e.size + k;
-                    src_of[rq.dst.base[f] + uint64_t(jj) * e.size + k] = p0 | (run << 18) | (jj << 23);
+                    const uint64_t b = (jj / Ld) * rq.dst.block + rq.dst.base[f] + (jj % Ld) * e.size + k;
+                    src_of[b] = p0 | (run << 18) | (jj << 23);
                 }
         }
         std::vector<uint32_t> table(gwords), bytes;
         for (uint64_t w = 0; w < gwords; w++) {
             const uint32_t* x = &src_of[4 * w];
-            const bool aligned = (x[0] & 3u) == 0 && (g.kq & 3u) == 0 && (g.mq == 0 || ((x[0] >> 18) & 31u) >= 2);
-            if ((x[0] >> 31) == 0 && x[1] == x[0] + 1 && x[2] == x[0] + 2 && x[3] == x[0] + 3 && aligned) {
-                table[w] = x[0];
+            // the word's position modulo 4 is the same in every super-block
+            const bool steady = (g.kq & 3u) == 0 && (g.q == 0 || ((x[0] >> 18) & 31u) >= 2);
+            if ((x[0] >> 31) == 0 && x[1] == x[0] + 1 && x[2] == x[0] + 2 && x[3] == x[0] + 3 && steady) {
+                table[w] = x[0] | ((x[0] & 3u) ? 1u << 30 : 0u); // bit 30: read funnel-shifted
             } else if (((x[0] & x[1] & x[2] & x[3]) >> 31) != 0) {
                 table[w] = 1u << 31;
             } else {
@@ -592,9 +603,19 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
         const uint64_t share = rq.dst.lanes == 1 ? 4 : 16;
         const uint64_t table_bytes = (table.size() * 4 + 15) / 16 * 16;
         const uint64_t room = uint64_t(kTileMaxEntries - a.num_entries) * (sizeof(TileEntry) / 4);
-        if (composite * share <= gwords && table.size() <= room &&
+        // words at odd positions (read funnel-shifted) pay off into AoS and
+        // into AoSoA with long lane runs: from the packed 49-byte record +60%
+        // into aligned AoS, +7% and +21% into AoSoA32 and AoSoA64, but -9%
+        // into AoSoA8
+        bool shifted = false;
+        for (uint64_t w = 0; w < gwords && !shifted; w++)
+            shifted = (table[w] >> 30) == 1u;
+        const bool odd_ok = !shifted || rq.dst.lanes == 1 || rq.dst.lanes >= 32;
+        if (composite * share <= gwords && table.size() <= room && odd_ok &&
             uint64_t(sb) + table_bytes <= std::min<uint64_t>(lds_limit, kHardLdsBytes)) {
             a.flags |= kTileGatherStore;
+            if (shifted || rq.dst.block % 4 != 0)
+                a.flags |= kTileGatherOdd;
             a.dst.lds_base = sb;
             a.dst.lds_bytes = uint32_t(table_bytes);
             a.lds_bytes = uint32_t(sb + table_bytes);

@@ -60,29 +60,38 @@ struct TileEntry {
 // every byte on its own.
 constexpr uint32_t kMoveSplit = 1u << 3;
 
-// kTileGatherStore: where the words of a destination block find their
-// sources.  The planner's word table describes every 4-byte word w of
-// destination block 0:
-//   bit 31 clear:     a whole word of one value, read as one 4-byte word: the
-//                     LDS byte p0 of its source for block 0 (bits 0-17), log2
-//                     of its leaf's lane run L_d * size (bits 18-22) and its
-//                     record j < L_d in the block (bits 23-29);
+// kTileGatherStore: where the words of the destination find their sources.
+// The word table covers a super-block: 1, 2 or 4 destination blocks (2^lg
+// records), enough that its bytes, and the source bytes that its records
+// advance by, are whole 4-byte words.  Entry w describes 4-byte word w of
+// super-block 0:
+//   bit 31 clear:     a whole word of one value: the LDS byte p0 of its
+//                     source for super-block 0 (bits 0-17), log2 of the bytes
+//                     of 2^lg values of its leaf (bits 18-22), its record
+//                     j < 2^lg in the super-block (bits 23-29), and bit 30
+//                     when p0 is not a multiple of 4 (the word is then read as
+//                     the two aligned words that hold it, funnel-shifted);
 //   bits 31-30 = 10:  padding (zero);
 //   bits 31-30 = 11:  a composite word (its bytes come from different values
 //                     or padding): bits 0-15 index c, and entries words + 4c
 //                     .. words + 4c + 3 of the table give its 4 bytes' sources
 //                     in the same form (bit 31: a zero byte).
-// The table follows the entries: in the argument block at entry num_entries
-// (reinterpreted as 32-bit words), in a batch after the item's entries.  A
-// source of block b lies at LDS byte
-//   p0 + (b >> q) * kq + ((b & mq) << run)
-// (a source with at most L_d lanes per block: q = 0, mq = 0 and kq the source
-// bytes of L_d records; a source with more: q = log2 of the lane ratio,
-// mq = 2^q - 1, kq the source block).
+// A word is whole when its 4 bytes are consecutive bytes of one value whose
+// position modulo 4 is the same in every super-block.  The table follows the
+// entries: in the argument block at entry num_entries (reinterpreted as
+// 32-bit words), in a batch after the item's entries.  A source of
+// super-block b lies at LDS byte
+//   p0 + (b >> q) * kq + ((b & (2^q - 1)) << run)
+// (a source with at most 2^lg lanes per block: q = 0 and kq the source bytes
+// of 2^lg records; a source with more: q = log2 of its lanes over 2^lg (31
+// for a field-major source) and kq the source block).  Six words, so that the
+// argument block keeps its size (the hidden arguments behind it moving by 8
+// bytes measured 4-13% slower on some direct-store pairs).
 struct TileGather {
-    uint32_t words; // 4-byte words per destination block
+    uint32_t words; // 4-byte words per destination super-block
     uint32_t magic; // ceil(2^32 / words): u / words == mulhi(u, magic) for u * words < 2^32
-    uint32_t q, mq, kq;
+    uint32_t q, lg; // lg: log2 of the records of a super-block
+    uint32_t kq;
     uint32_t table; // 32-bit words of the table: words + 4 per composite word
 };
 
@@ -140,6 +149,11 @@ constexpr uint32_t kTileStreamStores = 16;
 // The tile's source loads carry the nontemporal hint: set for sources at
 // least as large as the Infinity Cache.
 constexpr uint32_t kTileStreamLoads = 32;
+// A gathering tile whose table has whole words at odd positions (read
+// funnel-shifted) or whose destination blocks are not whole words (a span
+// can end inside a word): the gather runs in its own kernel variant, so that
+// the common case keeps its registers.
+constexpr uint32_t kTileGatherOdd = 64;
 
 // The gather geometry follows the entries, so that the header and entries
 // keep their offsets in the argument block (entries 16-byte aligned; a

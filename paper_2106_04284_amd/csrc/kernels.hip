@@ -447,20 +447,22 @@ __device__ __forceinline__ void gather_table(const TileHeader& h, const TileGath
 // entry of a composite word) in destination block blk.
 __device__ __forceinline__ uint32_t gather_pos(uint32_t x, uint32_t blk, const TileGather& gg)
 {
-    return (x & 0x3FFFFu) + (blk >> gg.q) * gg.kq + ((blk & gg.mq) << ((x >> 18) & 31u));
+    return (x & 0x3FFFFu) + (blk >> gg.q) * gg.kq + ((blk & ((1u << gg.q) - 1u)) << ((x >> 18) & 31u));
 }
 
 // Gather store of one tile: every thread assembles 16-byte granules of the
 // destination span word by word from the source region and stores them;
 // padding and records >= nv are zero.
-template <bool kStream>
+template <bool kStream, bool kOdd>
 __device__ __forceinline__ void gather_store_tile(const TileHeader& h, const TileGather& gg, uint64_t t, uint32_t nv,
                                                   uint32_t nd, uint32_t tid, uint32_t nthr, const uint8_t* lds)
 {
     const uint32_t* tab = (const uint32_t*)(lds + h.dst.lds_base);
     const uint32_t* btab = tab + gg.words; // the byte sources of composite words
-    const uint32_t lgd = h.dst.log2_lanes;
-    const uint32_t words = uint32_t(((uint64_t(nd) + h.dst.lanes - 1) >> lgd) * h.dst.block) >> 2;
+    const uint32_t lgd = gg.lg;            // records per super-block, log2
+    // the span's bytes; a block of odd size can end it inside a word
+    const uint32_t span = uint32_t(((uint64_t(nd) + h.dst.lanes - 1) >> h.dst.log2_lanes) * h.dst.block);
+    const uint32_t words = (span + 3u) >> 2;
     const uint64_t gbase = h.dst.span_base + t * h.dst.tile_bytes;
     for (uint32_t u = tid * 4u; u < words; u += nthr * 4u) {
         uint32_t blk = __umulhi(u, gg.magic);
@@ -471,8 +473,15 @@ __device__ __forceinline__ void gather_store_tile(const TileHeader& h, const Til
             const uint32_t e = tab[w];
             uint32_t x = 0;
             if ((e >> 31) == 0) {
-                if ((blk << lgd) + ((e >> 23) & 127u) < nv)
-                    x = *(const uint32_t*)(lds + gather_pos(e, blk, gg));
+                if ((blk << lgd) + ((e >> 23) & 127u) < nv) {
+                    const uint32_t p = gather_pos(e, blk, gg);
+                    if (kOdd && (e & (1u << 30))) { // at p mod 4 = 1..3: the two aligned words that hold it
+                        const uint32_t* wp = (const uint32_t*)(lds + (p & ~3u));
+                        x = uint32_t(((uint64_t(wp[1]) << 32) | wp[0]) >> ((p & 3u) * 8u));
+                    } else {
+                        x = *(const uint32_t*)(lds + p);
+                    }
+                }
             } else if ((e >> 30) == 3u) {
 #pragma unroll
                 for (uint32_t k = 0; k < 4; k++) {
@@ -488,13 +497,23 @@ __device__ __forceinline__ void gather_store_tile(const TileHeader& h, const Til
             }
         }
         const uint64_t a = gbase + uint64_t(u) * 4u;
-        if (u + 4u <= words) {
+        if ((u + 4u) * 4u <= span) {
             store16<kStream>((GLOBAL u32x4*)a, u32x4{v[0], v[1], v[2], v[3]});
-        } else {
+        } else if (!kOdd) { // the span's last granule: whole words (blocks of whole words)
 #pragma unroll
             for (uint32_t c = 0; c < 4; c++)
                 if (u + c < words)
                     *(GLOBAL uint32_t*)(a + 4u * c) = v[c];
+        } else { // the span's last granule: whole words, then the bytes of a partial word
+#pragma unroll
+            for (uint32_t c = 0; c < 4; c++) {
+                const uint32_t b = (u + c) * 4u;
+                if (b + 4u <= span)
+                    *(GLOBAL uint32_t*)(a + 4u * c) = v[c];
+                else
+                    for (uint32_t k = 0; b + k < span; k++)
+                        *(GLOBAL uint8_t*)(a + 4u * c + k) = uint8_t(v[c] >> (8u * k));
+            }
         }
     }
 }
@@ -506,7 +525,14 @@ __device__ __forceinline__ void gather_store_tile(const TileHeader& h, const Til
 // Kernel variants: kModeAny dispatches on the plan's flags at run time (the
 // batch kernel); the single-copy kernel is compiled once per mode so that each
 // mode gets its own register allocation.
-enum : uint32_t { kModeAny = 0, kModeStaged = 1, kModeDirectStore = 2, kModeDirectLoad = 3, kModeGatherStore = 4 };
+enum : uint32_t {
+    kModeAny = 0,
+    kModeStaged = 1,
+    kModeDirectStore = 2,
+    kModeDirectLoad = 3,
+    kModeGatherStore = 4,
+    kModeGatherOdd = 5 // gather store with kTileGatherOdd
+};
 // added to a mode: the tile's 16-byte destination stores are nontemporal
 constexpr uint32_t kModeStreamStores = 8;
 // added to a mode: the tile's source loads are nontemporal
@@ -521,7 +547,8 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     constexpr bool kOnce = (ModeBits & kModeStreamLoads) != 0;
     const bool dload = Mode == kModeDirectLoad || (Mode == kModeAny && (h.flags & kTileDirectLoad));
     const bool dstore = Mode == kModeDirectStore || (Mode == kModeAny && (h.flags & kTileDirectStore));
-    const bool gstore = Mode == kModeGatherStore || (Mode == kModeAny && (h.flags & kTileGatherStore));
+    const bool gstore = Mode == kModeGatherStore || Mode == kModeGatherOdd ||
+                        (Mode == kModeAny && (h.flags & kTileGatherStore));
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
     const uint32_t lane = tid & 63u, wave = wave_id(), nwaves = nthr >> 6;
     const uint32_t lds_base = uint32_t(uintptr_t((lds_void_t*)lds));
@@ -577,7 +604,10 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     if (gstore) {
         // ---- 2'''. assemble every destination granule word by word from
         //           the source region and store it; no destination region
-        gather_store_tile<kStream>(h, *gg, t, nv, nd, tid, nthr, lds);
+        if (Mode == kModeGatherOdd || (Mode == kModeAny && (h.flags & kTileGatherOdd)))
+            gather_store_tile<kStream, true>(h, *gg, t, nv, nd, tid, nthr, lds);
+        else
+            gather_store_tile<kStream, false>(h, *gg, t, nv, nd, tid, nthr, lds);
         return;
     }
 
@@ -654,7 +684,7 @@ __global__ void __launch_bounds__(1024) tile_kernel(const TileArgs a)
         t = x * q + min(x, rem) + k;
         stride = nt;
     }
-    if (Mode == kModeGatherStore) // the word table follows the entries in the argument block
+    if (Mode == kModeGatherStore || Mode == kModeGatherOdd) // the word table follows the entries
         gather_table(a.h, a.gather, reinterpret_cast<const uint32_t*>(a.e + a.h.num_entries), lds);
     for (; t < nt; t += stride) {
         tile_body<ModeBits>(a.h, ent, t, lds, &a.gather);
@@ -966,16 +996,20 @@ void check_hip(hipError_t e, const char* what)
         fail(LLAMA_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// tile_kernel variants by mode (kModeStaged .. kModeGatherStore): plain
-// loads and stores, then nontemporal loads, then nontemporal loads and stores
+// tile_kernel variants by mode (kModeStaged .. kModeGatherOdd): plain loads
+// and stores, then nontemporal loads, then nontemporal loads and stores
 constexpr uint32_t kLd = kModeStreamLoads, kLdSt = kModeStreamLoads | kModeStreamStores;
-const void* const kTileKernels[12] = {
+constexpr uint32_t kTileModes = 5;
+const void* const kTileKernels[3 * kTileModes] = {
     (const void*)tile_kernel<kModeStaged>, (const void*)tile_kernel<kModeDirectStore>,
     (const void*)tile_kernel<kModeDirectLoad>, (const void*)tile_kernel<kModeGatherStore>,
+    (const void*)tile_kernel<kModeGatherOdd>,
     (const void*)tile_kernel<kModeStaged | kLd>, (const void*)tile_kernel<kModeDirectStore | kLd>,
     (const void*)tile_kernel<kModeDirectLoad | kLd>, (const void*)tile_kernel<kModeGatherStore | kLd>,
+    (const void*)tile_kernel<kModeGatherOdd | kLd>,
     (const void*)tile_kernel<kModeStaged | kLdSt>, (const void*)tile_kernel<kModeDirectStore | kLdSt>,
-    (const void*)tile_kernel<kModeDirectLoad | kLdSt>, (const void*)tile_kernel<kModeGatherStore | kLdSt>};
+    (const void*)tile_kernel<kModeDirectLoad | kLdSt>, (const void*)tile_kernel<kModeGatherStore | kLdSt>,
+    (const void*)tile_kernel<kModeGatherOdd | kLdSt>};
 
 bool g_attr_set = false;
 
@@ -1030,12 +1064,12 @@ void launch(const Plan& p, void* stream_ptr)
         const uint32_t f = p.tile.h.flags;
         const uint32_t mode = (f & kTileDirectLoad)    ? kModeDirectLoad
                               : (f & kTileDirectStore) ? kModeDirectStore
-                              : (f & kTileGatherStore) ? kModeGatherStore
+                              : (f & kTileGatherStore) ? ((f & kTileGatherOdd) ? kModeGatherOdd : kModeGatherStore)
                                                        : kModeStaged;
         // streaming stores come with streaming loads (a destination of 1 GiB
         // or more has a source of far more than 256 MB in every layout pair)
         const uint32_t variant = (f & kTileStreamStores) ? 2 : (f & kTileStreamLoads) ? 1 : 0;
-        const void* k = kTileKernels[(mode - 1) + 4 * variant];
+        const void* k = kTileKernels[(mode - 1) + kTileModes * variant];
         void* args[] = {(void*)&p.tile};
         check_hip(hipLaunchKernel(k, dim3(grid), dim3(p.threads), args, p.tile.h.lds_bytes, stream),
                   "hipLaunchKernel(tile_kernel)");

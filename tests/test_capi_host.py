@@ -165,11 +165,16 @@ def test_tile_modes():
     assert mode("mixed", M, AA) == "gather_store"
     assert mode("mixed", AA, Q8) == "gather_store"
     assert mode("listing1", M, AA) == "gather_store"
-    # the 49-byte packed mixed record: as a destination its blocks are not
-    # whole words; as a source most of its values sit at odd positions, so
-    # that most destination words would be composite
-    assert mode("mixed", AA, A) == "staged"
+    # the 49-byte packed mixed record: 4 records are whole words, and its
+    # values at odd positions keep their position modulo 4 from one group of
+    # 4 records to the next, so both directions gather (read funnel-shifted)
+    # into AoS and into AoSoA with long lane runs; from SoA into it the words
+    # that straddle two values are too many
+    assert mode("mixed", AA, A) == "gather_store"
+    assert mode("mixed", A, AA) == "gather_store"
+    assert mode("mixed", A, Q32) == "gather_store"
     assert mode("mixed", A, Q8) == "staged"
+    assert mode("mixed", M, A) == "staged"
     # into AoSoA, listing 1's u16 and bool lanes make a quarter of the words
     # composite: staged; the mixed record's u8 lanes are 2% of the words
     assert mode("listing1", M, Q8) == "staged"

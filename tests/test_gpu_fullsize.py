@@ -90,13 +90,15 @@ def test_particle_2e26_sampled(L, orc, pair):
 
 # destinations of 1 GiB or more take nontemporal stores; the particle pairs
 # above run them in the direct-store and gather-store modes, these cases in
-# the staged mode (the packed 49-byte mixed record puts most values at odd
-# positions), the gather-store mode with composite words (the mixed record's
+# the staged mode (from SoA into the packed 49-byte mixed record, most words
+# straddle two values), the gather-store mode from that packed record (whole
+# words at odd positions read funnel-shifted), with composite words (the mixed record's
 # u8 leaf shares words with other lanes or padding) and the direct-load mode
 # (a destination 4 bytes past 16-byte alignment cannot gather: a field-major
 # source then loads into registers; the plan without blobs, which assumes
 # aligned blobs, gathers)
-STREAM_STORE_CASES = [("mixed", 1 << 25, ("aos_packed", 0), ("aosoa", 8), 0, "staged"),
+STREAM_STORE_CASES = [("mixed", 1 << 25, ("soa_multi", 0), ("aos_packed", 0), 0, "staged"),
+                      ("mixed", 1 << 25, ("aos_packed", 0), ("aosoa", 64), 0, "gather_store"),
                       ("mixed", 1 << 25, ("aosoa", 8), ("aos_aligned", 0), 0, "gather_store"),
                       ("mixed", 1 << 25, ("soa_multi", 0), ("aosoa", 32), 0, "gather_store"),
                       ("particle", 1 << 26, ("soa_multi", 0), ("aos_packed", 0), 4, "gather_store")]

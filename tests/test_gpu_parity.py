@@ -216,7 +216,12 @@ GATHER_CASES = [("particle", ("aos_packed", 0), ("aosoa", 8)), ("particle", ("ao
                 # 1- and 2-byte leaves: composite words assembled byte by byte
                 ("mixed", ("aos_aligned", 0), ("aosoa", 8)), ("mixed", ("soa_multi", 0), ("aos_aligned", 0)),
                 ("mixed", ("aosoa", 32), ("aos_aligned", 0)), ("mixed", ("soa_single", 0), ("aosoa", 8)),
-                ("listing1", ("aosoa", 64), ("aos_aligned", 0)), ("listing1", ("soa_multi", 0), ("aos_aligned", 0))]
+                ("listing1", ("aosoa", 64), ("aos_aligned", 0)), ("listing1", ("soa_multi", 0), ("aos_aligned", 0)),
+                # packed records of odd size: super-blocks of 4 records, whole
+                # words at odd positions read funnel-shifted, a span that ends
+                # inside a word
+                ("mixed", ("aos_packed", 0), ("aos_aligned", 0)), ("mixed", ("aos_aligned", 0), ("aos_packed", 0)),
+                ("listing1", ("aos_packed", 0), ("aos_aligned", 0))]
 GATHER_RUNS = [(77, {}), (1031, {}), (4099, {"tile_records": 16}), (5000, {"tile_records": 64, "threads": 64}),
                (20000, {"tile_records": 256, "threads": 1024}), (30011, {"tile_records": 16, "wg_per_cu": 1})]
 
