@@ -844,9 +844,13 @@ Plan make_plan_raw(const Request& rq, const llama_copy_options* opt)
                     p = q;
             }
         }
-        if (ok && !threads && (p.tile.h.flags & kTileGatherStore) && p.threads < 256) {
+        if (ok && !threads && (p.tile.h.flags & kTileGatherStore) && p.threads < 256 &&
+            (p.threads < 192 || p.tile.h.src.mode == kRecordMajor)) {
             // a gathering tile assembles every destination word on its own:
-            // at least 256 threads (particle pairs: -2% over 128)
+            // 256 threads (particle pairs: -2% over 128), except that a
+            // field-major source the default gives 192 keeps them (the
+            // lattice-Boltzmann cell from SoA multi-blob: 7% faster than
+            // 256; from AoSoA32, 4% slower)
             Plan q = p;
             q.threads = 256;
             if (fill_tile(rq, t, T ? kHardLdsBytes : kMaxLdsBytes, q) && (q.tile.h.flags & kTileGatherStore))
@@ -868,6 +872,24 @@ Plan make_plan_raw(const Request& rq, const llama_copy_options* opt)
                 Plan q = p;
                 q.threads = 64;
                 if (fill_tile(rq, uint32_t(t2), kMaxLdsBytes, q) && (q.tile.h.flags & kTileDirectStore))
+                    p = q;
+            }
+        }
+        if (ok && !T && !threads && (p.tile.h.flags & kTileDirectStore) && p.tile.h.src.mode == kFieldMajor) {
+            // direct store from a field-major source reads one span per leaf:
+            // where the widest leaf's span is under 2 KiB (the 156-byte
+            // lattice-Boltzmann cell at 128 records), twice the records
+            // (SoA multi-blob to AoSoA32 at 128^3: -14%)
+            uint32_t smax = 0;
+            for (const Leaf& l : rq.record.leaves)
+                smax = std::max(smax, l.size);
+            if (uint64_t(t) * smax < 2048 && t < 4096) {
+                Plan q = p;
+                q.threads = nthreads(2 * t);
+                // the staged twin of the doubled tile may exceed the default
+                // LDS budget; the direct store itself must not
+                if (fill_tile(rq, 2 * t, kHardLdsBytes, q) && (q.tile.h.flags & kTileDirectStore) &&
+                    q.lds_bytes <= kMaxLdsBytes)
                     p = q;
             }
         }

@@ -129,6 +129,36 @@ def test_planner_classification_all_pairs(orc, name, n):
                 assert p["path"] == "tile", (a, b)
 
 
+def test_default_tile_sizes():
+    """Default tile records and threads: about 16 KiB of source per tile and
+    112 source bytes per thread; at least 256 threads for a gathering tile
+    unless a field-major source gets 192; a small record stored directly
+    from a record-major source in tiles of 4 KiB and one wave; a direct
+    store from a field-major source whose widest leaf span is under 2 KiB
+    at twice the records."""
+    def plan(name, a, b, n):
+        r = L.Record(W.RECORDS[name])
+        p = L.plan(L.Mapping(r, a[0], [n], a[1]), L.Mapping(r, b[0], [n], b[1]))
+        return p["tile_mode"], p["tile_records"], p["threads"]
+
+    AA, M, S, Q32 = ("aos_aligned", 0), ("soa_multi", 0), ("soa_single", 0), ("aosoa", 32)
+    A, Q8 = ("aos_packed", 0), ("aosoa", 8)
+    n = 128 ** 3
+    # lattice-Boltzmann cell, 156 bytes packed: 128-record tiles, 192 threads
+    assert plan("lbm", AA, M, n) == ("direct_store", 128, 192)
+    assert plan("lbm", Q32, M, n) == ("direct_store", 128, 192)
+    assert plan("lbm", M, AA, n) == ("gather_store", 128, 192)
+    assert plan("lbm", Q32, AA, n) == ("gather_store", 128, 256)
+    assert plan("lbm", M, Q32, n) == ("direct_store", 256, 256)
+    # particle, 28 bytes: 512-record tiles; 4 KiB and one wave from a
+    # record-major source; the 2 KiB leaf spans from SoA are not doubled
+    n = 1 << 26
+    assert plan("particle", S, A, n) == ("gather_store", 512, 256)
+    assert plan("particle", A, Q8, n) == ("gather_store", 512, 256)
+    assert plan("particle", A, M, n) == ("direct_store", 128, 64)
+    assert plan("particle", M, Q32, n) == ("direct_store", 512, 128)
+
+
 def test_tile_modes():
     """The tile mode the planner takes: a destination in 16-byte granules of
     one leaf stores from registers; a record-major destination in 4-byte
