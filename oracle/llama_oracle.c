@@ -30,6 +30,11 @@
  *      AoSoA L  like AoS but each field repeated L times before the next
  *               field; the linear index i splits as (i / L, i mod L)
  *               (sec. 4.1).
+ *      Split    a selected part of the record dimension mapped by one of the
+ *               mappings above, the remaining leaves by another; each part
+ *               is that mapping of its own sub-record (the selected leaves,
+ *               or the others in their order) and owns its blobs, the
+ *               selected part's first.
  *
  *  - Copy (sec. 3.9 "Copying between views", sec. 4.2 "Layout changing
  *    copying"): the naive copy, nested loops over the array dimensions (outer)
@@ -46,6 +51,9 @@
  *     of f), a block is L * (packed record size) bytes, the blob holds
  *     ceil(N / L) blocks;
  *   - multi-blob SoA has one blob per leaf, in leaf order;
+ *   - Split selects a contiguous range of leaves (a record coordinate
+ *     selects a subtree, whose leaves are contiguous in depth-first order),
+ *     the two parts keep separate blobs, and neither part is itself a Split;
  *   - destination bytes that no (coordinate, leaf) pair maps to (alignment gaps
  *     of aligned AoS, unused lanes of the last AoSoA block) are set to zero.
  *
@@ -64,6 +72,10 @@
 #define ORC_SOA_SINGLE 2
 #define ORC_SOA_MULTI 3
 #define ORC_AOSOA 4
+#define ORC_SPLIT 5
+
+/* most leaves a record mapped by Split may have */
+#define ORC_SPLIT_MAX_LEAVES 1024
 
 /* error codes */
 #define ORC_OK 0
@@ -82,6 +94,12 @@ typedef struct {
     int32_t rank;
     uint64_t extents[ORC_MAX_RANK];
     uint64_t lanes; /* AoSoA only */
+    /* Split only: leaves [first, first + count) form the selected part,
+     * mapped by part_kind[0] (lanes part_lanes[0]); the other leaves by
+     * part_kind[1] (lanes part_lanes[1]) */
+    int32_t first, count;
+    int32_t part_kind[2];
+    uint64_t part_lanes[2];
 } orc_mapping;
 
 /* ---------------------------------------------------------------------------
@@ -315,8 +333,53 @@ static int next_coord(const orc_mapping* m, uint64_t* coord)
  * Mappings (sec. 3.7): blob count, blob sizes, blobNrAndOffset.
  * ------------------------------------------------------------------------- */
 
+/* one part of a Split: its plain mapping and its sub-record */
+typedef struct {
+    orc_mapping m;
+    orc_record r;
+    uint64_t size[ORC_SPLIT_MAX_LEAVES];
+    uint64_t align[ORC_SPLIT_MAX_LEAVES];
+} orc_part;
+
+static int in_selection(const orc_mapping* m, int f) { return f >= m->first && f < m->first + m->count; }
+
+/* part 0 holds the selected leaves, part 1 the others, each in leaf order */
+static void split_part(const orc_mapping* m, const orc_record* r, int part, orc_part* out)
+{
+    out->m = *m;
+    out->m.kind = m->part_kind[part];
+    out->m.lanes = m->part_lanes[part];
+    int n = 0;
+    for (int f = 0; f < r->nleaves && n < ORC_SPLIT_MAX_LEAVES; f++)
+        if (in_selection(m, f) == (part == 0)) {
+            out->size[n] = r->size[f];
+            out->align[n] = r->align[f];
+            n++;
+        }
+    out->r.nleaves = n;
+    out->r.size = out->size;
+    out->r.align = out->align;
+}
+
+/* which part leaf f is in, and its index inside that part's sub-record */
+static int split_leaf(const orc_mapping* m, int f, int* part)
+{
+    if (in_selection(m, f)) {
+        *part = 0;
+        return f - m->first;
+    }
+    *part = 1;
+    return f < m->first ? f : f - m->count;
+}
+
 int orc_blob_count(const orc_mapping* m, const orc_record* r)
 {
+    if (m->kind == ORC_SPLIT) {
+        orc_part p0, p1;
+        split_part(m, r, 0, &p0);
+        split_part(m, r, 1, &p1);
+        return orc_blob_count(&p0.m, &p0.r) + orc_blob_count(&p1.m, &p1.r);
+    }
     if (m->kind == ORC_SOA_MULTI)
         return r->nleaves;
     return 1;
@@ -325,6 +388,16 @@ int orc_blob_count(const orc_mapping* m, const orc_record* r)
 uint64_t orc_blob_size(const orc_mapping* m, const orc_record* r, int blob)
 {
     uint64_t n = orc_record_count(m);
+    if (m->kind == ORC_SPLIT) {
+        orc_part p;
+        split_part(m, r, 0, &p);
+        int b0 = orc_blob_count(&p.m, &p.r);
+        if (blob >= b0) {
+            split_part(m, r, 1, &p);
+            blob -= b0;
+        }
+        return orc_blob_size(&p.m, &p.r, blob);
+    }
     switch (m->kind) {
     case ORC_AOS_PACKED:
         return n * orc_packed_size(r);
@@ -348,6 +421,20 @@ int orc_blob_nr_and_offset(const orc_mapping* m, const orc_record* r, const uint
 {
     if (f < 0 || f >= r->nleaves)
         return ORC_E_ARG;
+    if (m->kind == ORC_SPLIT) { /* the part's own mapping of its sub-record */
+        orc_part p;
+        int part;
+        int g = split_leaf(m, f, &part);
+        uint64_t first_blob = 0;
+        if (part == 1) {
+            split_part(m, r, 0, &p);
+            first_blob = (uint64_t)orc_blob_count(&p.m, &p.r);
+        }
+        split_part(m, r, part, &p);
+        int rc = orc_blob_nr_and_offset(&p.m, &p.r, coord, g, blob, offset);
+        *blob += first_blob;
+        return rc;
+    }
     uint64_t n = orc_record_count(m);
     uint64_t i = orc_linearize(m, coord);
     switch (m->kind) {
@@ -383,15 +470,22 @@ int orc_blob_nr_and_offset(const orc_mapping* m, const orc_record* r, const uint
  * Validation shared by the entry points below.
  * ------------------------------------------------------------------------- */
 
-static int valid_mapping(const orc_mapping* m)
+static int valid_plain(int32_t kind, uint64_t lanes)
+{
+    if (kind < ORC_AOS_PACKED || kind > ORC_AOSOA)
+        return 0;
+    return kind != ORC_AOSOA || lanes != 0;
+}
+
+static int valid_mapping(const orc_mapping* m, const orc_record* r)
 {
     if (m->rank < 1 || m->rank > ORC_MAX_RANK)
         return 0;
-    if (m->kind < ORC_AOS_PACKED || m->kind > ORC_AOSOA)
-        return 0;
-    if (m->kind == ORC_AOSOA && m->lanes == 0)
-        return 0;
-    return 1;
+    if (m->kind == ORC_SPLIT)
+        return r->nleaves <= ORC_SPLIT_MAX_LEAVES && m->first >= 0 && m->count >= 1 &&
+               m->count < r->nleaves && m->first + m->count <= r->nleaves &&
+               valid_plain(m->part_kind[0], m->part_lanes[0]) && valid_plain(m->part_kind[1], m->part_lanes[1]);
+    return valid_plain(m->kind, m->lanes);
 }
 
 static int same_extents(const orc_mapping* a, const orc_mapping* b)
@@ -413,7 +507,7 @@ static int same_extents(const orc_mapping* a, const orc_mapping* b)
 int orc_copy(const orc_record* r, const orc_mapping* src, uint8_t* const* src_blobs,
              const orc_mapping* dst, uint8_t* const* dst_blobs)
 {
-    if (!valid_mapping(src) || !valid_mapping(dst) || !same_extents(src, dst))
+    if (!valid_mapping(src, r) || !valid_mapping(dst, r) || !same_extents(src, dst))
         return ORC_E_ARG;
     /* padding policy: the whole destination starts at zero */
     for (int b = 0; b < orc_blob_count(dst, r); b++)
@@ -438,7 +532,7 @@ int orc_copy(const orc_record* r, const orc_mapping* src, uint8_t* const* src_bl
 int orc_copy_keep(const orc_record* r, const orc_mapping* src, uint8_t* const* src_blobs,
                   const orc_mapping* dst, uint8_t* const* dst_blobs)
 {
-    if (!valid_mapping(src) || !valid_mapping(dst) || !same_extents(src, dst))
+    if (!valid_mapping(src, r) || !valid_mapping(dst, r) || !same_extents(src, dst))
         return ORC_E_ARG;
     if (orc_record_count(src) == 0)
         return ORC_OK;
@@ -459,7 +553,7 @@ int orc_copy_keep(const orc_record* r, const orc_mapping* src, uint8_t* const* s
  * bytes are padding. */
 int orc_write_counts(const orc_record* r, const orc_mapping* m, uint32_t* const* counts)
 {
-    if (!valid_mapping(m))
+    if (!valid_mapping(m, r))
         return ORC_E_ARG;
     if (orc_record_count(m) == 0)
         return ORC_OK;

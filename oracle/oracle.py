@@ -13,7 +13,10 @@ Records are given in the neutral nested form used by the workload definitions:
 a record is a list of members; a member is an elemental type name, a nested
 list (a nested record), or a ``(member, count)`` pair for a static array.
 Mappings are ``(kind, extents, lanes)`` with kind one of ``aos_packed``,
-``aos_aligned``, ``soa_single``, ``soa_multi``, ``aosoa``.
+``aos_aligned``, ``soa_single``, ``soa_multi``, ``aosoa``, or ``split`` with
+``split=(first, count, (kind, lanes), (kind, lanes))``: leaves
+``[first, first + count)`` mapped by the first plain mapping, the others by the
+second (sec. 3.7 Split).
 """
 from __future__ import annotations
 
@@ -30,7 +33,7 @@ _LIB = os.path.join(_HERE, "liborc.so")
 MAX_RANK = 8
 MAX_LEAVES = 4096
 
-KINDS = {"aos_packed": 0, "aos_aligned": 1, "soa_single": 2, "soa_multi": 3, "aosoa": 4}
+KINDS = {"aos_packed": 0, "aos_aligned": 1, "soa_single": 2, "soa_multi": 3, "aosoa": 4, "split": 5}
 
 
 class _Record(ctypes.Structure):
@@ -41,7 +44,9 @@ class _Record(ctypes.Structure):
 
 class _Mapping(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("rank", ctypes.c_int32),
-                ("extents", ctypes.c_uint64 * MAX_RANK), ("lanes", ctypes.c_uint64)]
+                ("extents", ctypes.c_uint64 * MAX_RANK), ("lanes", ctypes.c_uint64),
+                ("first", ctypes.c_int32), ("count", ctypes.c_int32),
+                ("part_kind", ctypes.c_int32 * 2), ("part_lanes", ctypes.c_uint64 * 2)]
 
 
 def build(force: bool = False) -> str:
@@ -159,7 +164,7 @@ class Record:
 # mappings
 # --------------------------------------------------------------------------
 
-def _mapping(kind: str, extents, lanes: int = 0) -> _Mapping:
+def _mapping(kind: str, extents, lanes: int = 0, split=None) -> _Mapping:
     ext = [int(e) for e in (extents if isinstance(extents, (list, tuple)) else [extents])]
     if not 1 <= len(ext) <= MAX_RANK:
         raise ValueError("rank must be 1..8")
@@ -169,16 +174,28 @@ def _mapping(kind: str, extents, lanes: int = 0) -> _Mapping:
     for d, e in enumerate(ext):
         m.extents[d] = e
     m.lanes = int(lanes)
+    if kind == "split":
+        first, count, (k0, l0), (k1, l1) = split
+        if "split" in (k0, k1):
+            raise ValueError("a part of a split mapping is a plain mapping")
+        m.first, m.count = int(first), int(count)
+        m.part_kind[0], m.part_kind[1] = KINDS[k0], KINDS[k1]
+        m.part_lanes[0], m.part_lanes[1] = int(l0), int(l1)
     return m
 
 
 class Mapping:
-    def __init__(self, record: Record, kind: str, extents, lanes: int = 0):
+    def __init__(self, record: Record, kind: str, extents, lanes: int = 0, split=None):
         self.record = record
         self.kind = kind
         self.extents = [int(e) for e in (extents if isinstance(extents, (list, tuple)) else [extents])]
         self.lanes = int(lanes)
-        self.c = _mapping(kind, self.extents, lanes)
+        self.split = split
+        if kind == "split":
+            first, count = int(split[0]), int(split[1])
+            if not (first >= 0 and count >= 1 and first + count <= record.nleaves and count < record.nleaves):
+                raise ValueError("split: the selected leaves must be a proper, non-empty range")
+        self.c = _mapping(kind, self.extents, lanes, split)
 
     @property
     def count(self) -> int:

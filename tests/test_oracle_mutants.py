@@ -33,6 +33,10 @@ MUTANTS = {
                                  "                  const orc_mapping* dst, uint8_t* const* dst_blobs)\n{\n"
                                  "    for (int b = 0; b < orc_blob_count(dst, r); b++)\n"
                                  "        memset(dst_blobs[b], 0, (size_t)orc_blob_size(dst, r, b));\n"),
+    "split_rest_index_off": ("return f < m->first ? f : f - m->count;", "return f < m->first ? f : f - m->first;"),
+    "split_rest_blobs_overlap": ("first_blob = (uint64_t)orc_blob_count(&p.m, &p.r);", "first_blob = 0;"),
+    "split_selection_one_long": ("return f >= m->first && f < m->first + m->count;",
+                                 "return f >= m->first && f <= m->first + m->count;"),
     "static_array_one_short": ("for (uint64_t c = 1; c < count; c++)", "for (uint64_t c = 2; c < count; c++)"),
     "aos_aligned_uses_packed_stride": ("*offset = i * orc_aligned_size(r) + orc_aligned_offset(r, f);",
                                        "*offset = i * orc_packed_size(r) + orc_aligned_offset(r, f);"),

@@ -464,3 +464,79 @@ def test_random_records_against_serialiser(orc, rec, n, lanes, kind, seed):
     got = _build(orc, rec, kind, [n], lanes if kind == "aosoa" else 0, vals)
     want = _serialise(types, vals, kind, n, lanes)
     assert [bytes(b) for b in got] == want
+
+
+# --------------------------------------------------------------------------
+# Split (sec. 3.7): the selected leaves through one mapping, the others through
+# another, each part over its own sub-record and in its own blobs
+# --------------------------------------------------------------------------
+
+def _split_ranges(F):
+    out = {(0, 1), (0, F - 1), (1, F - 1), (F // 2, 1), (1, max(F - 2, 1))}
+    return sorted((a, c) for a, c in out if c >= 1 and c < F and a + c <= F)
+
+
+@pytest.mark.parametrize("name", ["particle", "mixed", "lbm", "listing1"])
+@pytest.mark.parametrize("n", [0, 1, 5, 67])
+def test_split_equals_serialised_parts(orc, name, n):
+    """A Split layout is the prose serialiser's layout of the selected leaves
+    (as a record of their own) followed by its layout of the other leaves."""
+    rec = W.RECORDS[name]
+    types = W.leaf_types(rec)
+    F = len(types)
+    vals = _unique_leaf_values(types, n, 40 + n)
+    r = orc.Record(rec)
+    src = orc.Mapping(r, "soa_multi", [n])
+    rng = random.Random(F * 100 + n)
+    parts = _layouts(lanes=(1, 4, 32))
+    for first, count in _split_ranges(F):
+        sel = list(range(first, first + count))
+        rest = [f for f in range(F) if f not in sel]
+        for p0 in parts:
+            p1 = rng.choice(parts)
+            m = orc.Mapping(r, "split", [n], split=(first, count, p0, p1))
+            got = orc.copy(src, _soa_multi_blobs(vals), m)
+            want = (_serialise([types[f] for f in sel], [vals[f] for f in sel], p0[0], n, p0[1]) +
+                    _serialise([types[f] for f in rest], [vals[f] for f in rest], p1[0], n, p1[1]))
+            assert [bytes(b) for b in got] == want, (first, count, p0, p1)
+
+
+def test_split_of_multi_blob_soa_permutes_its_blobs(orc):
+    """Splitting multi-blob SoA into two multi-blob SoA parts only reorders the
+    blobs: the selected leaves' blobs first, then the others in leaf order."""
+    types = W.leaf_types(W.MIXED)
+    F, n = len(types), 333
+    vals = _unique_leaf_values(types, n, 12)
+    r = orc.Record(W.MIXED)
+    mb = orc.Mapping(r, "soa_multi", [n])
+    whole = _soa_multi_blobs(vals)
+    for first, count in _split_ranges(F):
+        m = orc.Mapping(r, "split", [n], split=(first, count, ("soa_multi", 0), ("soa_multi", 0)))
+        got = orc.copy(mb, whole, m)
+        order = list(range(first, first + count)) + [f for f in range(F) if not first <= f < first + count]
+        assert len(got) == F
+        for b, f in enumerate(order):
+            assert np.array_equal(got[b], whole[f]), (first, count, b)
+
+
+@pytest.mark.parametrize("name", ["particle", "mixed"])
+def test_split_exactly_once_and_round_trip(orc, name):
+    """Every value byte of a Split layout is written exactly once, its only
+    unwritten bytes are its parts' padding, and AoS -> Split -> AoS is the
+    identity."""
+    rec = W.RECORDS[name]
+    types = W.leaf_types(rec)
+    F, n = len(types), 45
+    r = orc.Record(rec)
+    S = sum(SIZES[t] for t in types)
+    for first, count in _split_ranges(F):
+        for p0, p1 in ((("aos_aligned", 0), ("aosoa", 8)), (("aosoa", 4), ("soa_single", 0)),
+                       (("soa_multi", 0), ("aos_packed", 0))):
+            m = orc.Mapping(r, "split", [n], split=(first, count, p0, p1))
+            counts = orc.write_counts(m)
+            assert all(int(c.max(initial=0)) <= 1 for c in counts)
+            assert sum(int(c.sum()) for c in counts) == n * S
+            aos = orc.Mapping(r, "aos_aligned", [n])
+            start = _build(orc, rec, "aos_aligned", [n], 0, _unique_leaf_values(types, n, first + count))
+            back = orc.copy(m, orc.copy(aos, start, m), aos)
+            assert np.array_equal(back[0], start[0])
