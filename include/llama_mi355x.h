@@ -108,10 +108,28 @@ typedef enum {
     LLAMA_AOS_ALIGNED = 1, /* records one after another, leaves aligned: 1 blob of N*R */
     LLAMA_SOA_SINGLE = 2,  /* per leaf f, N values contiguous at N*(packed offset of f): 1 blob of N*S */
     LLAMA_SOA_MULTI = 3,   /* per leaf f, N values contiguous in blob f: F blobs of N*s_f */
-    LLAMA_AOSOA = 4        /* blocks of `lanes` records; inside a block leaf f's values are
+    LLAMA_AOSOA = 4,       /* blocks of `lanes` records; inside a block leaf f's values are
                               contiguous at lanes*(packed offset of f): 1 blob of
                               ceil(N/lanes)*lanes*S */
+    LLAMA_SPLIT = 5        /* two of the kinds above over two parts of the record (sec. 3.7
+                              Split); see llama_split_desc */
 } llama_mapping_kind;
+
+/* A Split mapping (sec. 3.7): the leaves [first_leaf, first_leaf + leaf_count)
+ * of the flattened record form the selected part, mapped by kind[0] (lanes[0]);
+ * the other leaves, in leaf order, form the rest, mapped by kind[1] (lanes[1]).
+ * Each part is that mapping of its own sub-record (its leaves with their sizes
+ * and alignments, offsets recomputed) over the same array dimensions.  The
+ * parts keep separate blobs: the selected part's blobs first, then the rest's.
+ * A record coordinate selects a subtree, whose leaves are such a contiguous
+ * range in depth-first order.  Both parts must be non-empty and neither may be
+ * LLAMA_SPLIT.  The descriptor is read during each call only. */
+typedef struct {
+    uint32_t first_leaf;
+    uint32_t leaf_count;
+    uint32_t kind[2];  /* llama_mapping_kind of the selected part and of the rest */
+    uint32_t lanes[2]; /* LLAMA_AOSOA parts: lanes per block, a power of two */
+} llama_split_desc;
 
 #define LLAMA_MAX_RANK 8
 
@@ -124,6 +142,7 @@ typedef struct {
     uint64_t extents[LLAMA_MAX_RANK]; /* extents[0 .. rank-1]; zero extents allowed */
     uint32_t lanes;                   /* LLAMA_AOSOA: lanes per block, a power of two; else ignored */
     uint32_t reserved;                /* must be 0 */
+    const llama_split_desc* split;    /* LLAMA_SPLIT: the split (required); else ignored */
 } llama_mapping_desc;
 
 /* Number of blobs the mapping needs (the paper's compile-time blobCount). */
@@ -158,7 +177,13 @@ typedef struct {
  *    written exactly once: leaf values from the source, and zero for the
  *    destination's padding (alignment gaps of aligned AoS, lanes past the last
  *    record in the last AoSoA block).
- *  - A data space with zero records enqueues nothing and returns LLAMA_OK. */
+ *  - A data space with zero records enqueues nothing and returns LLAMA_OK.
+ *  - A Split on either side runs as one copy per pair of parts that share
+ *    leaves, in order on `stream`, each writing only its own leaves and the
+ *    padding of its destination part.  A pair that writes part of the records
+ *    of a record-major destination part (AoS, AoSoA) takes the element-wise
+ *    path; every other pair is planned like a plain copy.  Batches, servers,
+ *    plans and autotuning take plain mappings only (LLAMA_E_UNSUPPORTED). */
 int llama_copy(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
                const llama_blob* dst_blobs, void* stream);
 

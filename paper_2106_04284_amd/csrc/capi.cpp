@@ -188,9 +188,27 @@ int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, co
                   const llama_blob* dst_blobs, const llama_copy_options* options, void* stream)
 {
     return guarded([&] {
-        Request rq = make_request(src, src_blobs, dst, dst_blobs, true);
-        Plan p = make_plan(rq, options);
-        launch(p, stream);
+        Request rq = make_request(src, src_blobs, dst, dst_blobs, true, true);
+        if (src->kind != LLAMA_SPLIT && dst->kind != LLAMA_SPLIT) {
+            Plan p = make_plan(rq, options);
+            launch(p, stream);
+            return;
+        }
+        // a Split side: one copy per pair of parts sharing leaves, in order
+        // on the stream; every plan is made before the first launch
+        std::vector<Plan> plans;
+        for (const SubCopy& c : split_copies(src, dst, rq)) {
+            if (c.naive) {
+                llama_copy_options o = options ? *options : llama_copy_options{0, 0, 0, 0, 0};
+                o.path = LLAMA_PATH_NAIVE;
+                o.tile_records = 0;
+                plans.push_back(make_plan(c.rq, &o));
+            } else {
+                plans.push_back(make_plan(c.rq, options));
+            }
+        }
+        for (const Plan& p : plans)
+            launch(p, stream);
     });
 }
 

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <iterator>
 
 namespace llama {
 
@@ -86,16 +87,12 @@ uint32_t parse_node(const llama_record_desc* d, uint32_t idx, uint32_t depth, st
 
 } // namespace
 
-Record flatten(const llama_record_desc* d)
+namespace {
+
+// packed and aligned offsets and the record sizes from the leaf sizes
+void lay_out(Record& r)
 {
-    if (!d)
-        fail(LLAMA_E_INVALID_ARG, "record descriptor is NULL");
-    if (d->num_nodes == 0 || !d->nodes)
-        fail(LLAMA_E_INVALID_ARG, "record has no nodes");
-    Record r;
-    uint32_t idx = 0;
-    while (idx < d->num_nodes)
-        idx = parse_node(d, idx, 0, r.leaves);
+    r.max_align = 1;
     uint64_t packed = 0, aligned = 0;
     for (Leaf& l : r.leaves) {
         l.packed_offset = packed;
@@ -107,9 +104,33 @@ Record flatten(const llama_record_desc* d)
     }
     r.packed_size = packed;
     r.aligned_size = round_up(aligned, r.max_align);
+}
+
+} // namespace
+
+Record flatten(const llama_record_desc* d)
+{
+    if (!d)
+        fail(LLAMA_E_INVALID_ARG, "record descriptor is NULL");
+    if (d->num_nodes == 0 || !d->nodes)
+        fail(LLAMA_E_INVALID_ARG, "record has no nodes");
+    Record r;
+    uint32_t idx = 0;
+    while (idx < d->num_nodes)
+        idx = parse_node(d, idx, 0, r.leaves);
+    lay_out(r);
     if (r.aligned_size > (uint64_t(1) << 32))
         fail(LLAMA_E_INVALID_ARG, "record larger than 4 GiB");
     return r;
+}
+
+Record sub_record(const Record& r, const std::vector<uint32_t>& pick)
+{
+    Record s;
+    for (uint32_t f : pick)
+        s.leaves.push_back(r.leaves[f]);
+    lay_out(s);
+    return s;
 }
 
 bool same_leaves(const Record& a, const Record& b)
@@ -122,16 +143,107 @@ bool same_leaves(const Record& a, const Record& b)
     return true;
 }
 
+namespace {
+
+// One part of a mapping: a plain mapping of the sub-record of `leaves`, whose
+// blobs start at blob `first_blob` of the whole mapping.
+struct Part {
+    std::vector<uint32_t> leaves;
+    Record sub;
+    Side side;
+    uint32_t first_blob = 0;
+};
+
+// The parts of a mapping: a Split's two (sec. 3.7: the selected leaf range,
+// then the other leaves), a plain mapping's one.
+std::vector<Part> parts_of(const llama_mapping_desc* m, const Record& r)
+{
+    const size_t F = r.leaves.size();
+    std::vector<Part> parts;
+    if (m->kind != LLAMA_SPLIT) {
+        Part p;
+        for (size_t f = 0; f < F; f++)
+            p.leaves.push_back(uint32_t(f));
+        p.sub = r;
+        p.side = make_side(m, r);
+        parts.push_back(std::move(p));
+        return parts;
+    }
+    const llama_split_desc* sd = m->split;
+    if (!sd)
+        fail(LLAMA_E_INVALID_ARG, "LLAMA_SPLIT mapping without a split descriptor");
+    if (sd->leaf_count == 0 || sd->leaf_count >= F || sd->first_leaf > F - sd->leaf_count)
+        fail(LLAMA_E_INVALID_ARG, "split: the selected leaves [" + std::to_string(sd->first_leaf) + ", +" +
+                                      std::to_string(sd->leaf_count) + ") must be a non-empty proper range of the " +
+                                      std::to_string(F) + " leaves");
+    uint32_t first_blob = 0;
+    for (int k = 0; k < 2; k++) {
+        if (sd->kind[k] >= LLAMA_SPLIT)
+            fail(LLAMA_E_INVALID_ARG, "split: part " + std::to_string(k) + " must be a plain mapping kind");
+        Part p;
+        for (size_t f = 0; f < F; f++) {
+            const bool sel = f >= sd->first_leaf && f < size_t(sd->first_leaf) + sd->leaf_count;
+            if (sel == (k == 0))
+                p.leaves.push_back(uint32_t(f));
+        }
+        p.sub = sub_record(r, p.leaves);
+        llama_mapping_desc inner = *m;
+        inner.kind = sd->kind[k];
+        inner.lanes = sd->lanes[k];
+        inner.reserved = 0;
+        inner.split = nullptr;
+        p.side = make_side(&inner, p.sub);
+        p.first_blob = first_blob;
+        first_blob += uint32_t(p.side.blob_size.size());
+        parts.push_back(std::move(p));
+    }
+    return parts;
+}
+
+// A Split side: every leaf at its part's place, with its part's L and K; the
+// blobs of the selected part, then those of the rest.
+Side split_side(const llama_mapping_desc* m, const Record& r)
+{
+    const std::vector<Part> parts = parts_of(m, r);
+    const size_t F = r.leaves.size();
+    Side s = parts[0].side;
+    s.kind = LLAMA_SPLIT;
+    s.lanes = 0;
+    s.block = 0;
+    s.npad = s.n;
+    s.gaps.clear();
+    s.blob.assign(F, 0);
+    s.base.assign(F, 0);
+    s.leaf_lanes.assign(F, 0);
+    s.leaf_block.assign(F, 0);
+    s.blob_size.clear();
+    for (const Part& p : parts) {
+        for (size_t k = 0; k < p.leaves.size(); k++) {
+            const uint32_t f = p.leaves[k];
+            s.blob[f] = p.first_blob + p.side.blob[k];
+            s.base[f] = p.side.base[k];
+            s.leaf_lanes[f] = p.side.lanes;
+            s.leaf_block[f] = p.side.block;
+        }
+        s.blob_size.insert(s.blob_size.end(), p.side.blob_size.begin(), p.side.blob_size.end());
+    }
+    return s;
+}
+
+} // namespace
+
 Side make_side(const llama_mapping_desc* m, const Record& r)
 {
     if (!m)
         fail(LLAMA_E_INVALID_ARG, "mapping descriptor is NULL");
-    if (m->kind > LLAMA_AOSOA)
+    if (m->kind > LLAMA_SPLIT)
         fail(LLAMA_E_INVALID_ARG, "mapping kind " + std::to_string(m->kind) + " is not a llama_mapping_kind");
     if (m->rank < 1 || m->rank > LLAMA_MAX_RANK)
         fail(LLAMA_E_INVALID_ARG, "mapping rank must be 1..8");
     if (m->reserved != 0)
         fail(LLAMA_E_INVALID_ARG, "mapping reserved field must be 0");
+    if (m->kind == LLAMA_SPLIT)
+        return split_side(m, r);
     Side s;
     s.kind = m->kind;
     s.rank = m->rank;
@@ -227,7 +339,7 @@ bool overlaps(uint64_t a, uint64_t an, uint64_t b, uint64_t bn)
 } // namespace
 
 Request make_request(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
-                     const llama_blob* dst_blobs, bool need_blobs)
+                     const llama_blob* dst_blobs, bool need_blobs, bool allow_split)
 {
     if (!src || !dst)
         fail(LLAMA_E_INVALID_ARG, "mapping descriptor is NULL");
@@ -240,6 +352,8 @@ Request make_request(const llama_mapping_desc* src, const llama_blob* src_blobs,
     }
     rq.src = make_side(src, rq.record);
     rq.dst = make_side(dst, rq.record);
+    if (!allow_split && (src->kind == LLAMA_SPLIT || dst->kind == LLAMA_SPLIT))
+        fail(LLAMA_E_UNSUPPORTED, "Split mappings are copied by llama_copy, llama_copy_ex and llama_copy_naive only");
     if (src->rank != dst->rank)
         fail(LLAMA_E_EXTENT_MISMATCH, "source and destination ranks differ");
     for (uint32_t d = 0; d < src->rank; d++)
@@ -269,6 +383,61 @@ Request make_request(const llama_mapping_desc* src, const llama_blob* src_blobs,
     return rq;
 }
 
+namespace {
+
+// the side of part `p` that holds only leaves `pick` (a subset of p.leaves,
+// both in leaf order)
+Side restrict_side(const Part& p, const std::vector<uint32_t>& pick)
+{
+    Side s = p.side;
+    s.blob.clear();
+    s.base.clear();
+    size_t k = 0;
+    for (uint32_t f : pick) {
+        while (p.leaves[k] != f)
+            k++;
+        s.blob.push_back(p.side.blob[k]);
+        s.base.push_back(p.side.base[k]);
+    }
+    s.partial = pick.size() != p.leaves.size();
+    return s;
+}
+
+} // namespace
+
+std::vector<SubCopy> split_copies(const llama_mapping_desc* src, const llama_mapping_desc* dst, const Request& whole)
+{
+    const std::vector<Part> sp = parts_of(src, whole.record);
+    const std::vector<Part> dp = parts_of(dst, whole.record);
+    std::vector<SubCopy> out;
+    for (const Part& P : dp) {
+        bool padding_written = false;
+        for (const Part& Q : sp) {
+            std::vector<uint32_t> both;
+            std::set_intersection(P.leaves.begin(), P.leaves.end(), Q.leaves.begin(), Q.leaves.end(),
+                                  std::back_inserter(both));
+            if (both.empty())
+                continue;
+            SubCopy c;
+            c.rq.record = sub_record(whole.record, both);
+            c.rq.src = restrict_side(Q, both);
+            c.rq.dst = restrict_side(P, both);
+            if (padding_written) {
+                // the alignment gaps of this destination part are written once
+                c.rq.dst.gaps.clear();
+            }
+            padding_written = true;
+            c.naive = c.rq.dst.partial && P.side.lanes >= 1;
+            c.rq.src_ptr.assign(whole.src_ptr.begin() + Q.first_blob,
+                                whole.src_ptr.begin() + Q.first_blob + Q.side.blob_size.size());
+            c.rq.dst_ptr.assign(whole.dst_ptr.begin() + P.first_blob,
+                                whole.dst_ptr.begin() + P.first_blob + P.side.blob_size.size());
+            out.push_back(std::move(c));
+        }
+    }
+    return out;
+}
+
 // ---------------------------------------------------------------------------
 // Planning
 // ---------------------------------------------------------------------------
@@ -284,6 +453,8 @@ uint64_t effective_lanes(const Side& s)
 
 bool same_placement(const Side& a, const Side& b)
 {
+    if (a.partial || b.partial)
+        return false;
     if (effective_lanes(a) != effective_lanes(b) || a.blob_size != b.blob_size || a.blob != b.blob ||
         a.base != b.base || a.npad != b.npad || a.gaps != b.gaps)
         return false;

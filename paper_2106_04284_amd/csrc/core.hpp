@@ -37,6 +37,8 @@ struct Record {
 
 Record flatten(const llama_record_desc* desc);
 bool same_leaves(const Record& a, const Record& b);
+// the record of leaves `pick` of `r` (in that order), offsets recomputed
+Record sub_record(const Record& r, const std::vector<uint32_t>& pick);
 
 // The affine form of a mapping (sec. 3.7 blobNrAndOffset): leaf f of the
 // record with row-major linear index i lives in blob `blob[f]` at
@@ -58,12 +60,20 @@ struct Side {
     // byte ranges inside one record that no leaf covers (aligned AoS only):
     // (offset, length) pairs
     std::vector<std::pair<uint64_t, uint64_t>> gaps;
+    // LLAMA_SPLIT (sec. 3.7): each leaf keeps its part's L and K; a Split side
+    // describes offsets only and is copied part by part (split_copies)
+    std::vector<uint64_t> leaf_lanes, leaf_block;
+    // a side of one part-to-part copy whose leaves leave other bytes of its
+    // records to other copies: never treated as one whole-blob copy
+    bool partial = false;
     bool has_padding() const { return !gaps.empty() || npad != n; }
     uint64_t offset(uint64_t i, uint32_t f, const Record& r) const
     {
-        if (lanes == 0)
+        const uint64_t L = leaf_lanes.empty() ? lanes : leaf_lanes[f];
+        const uint64_t K = leaf_block.empty() ? block : leaf_block[f];
+        if (L == 0)
             return base[f] + i * r.leaves[f].size;
-        return base[f] + (i / lanes) * block + (i % lanes) * r.leaves[f].size;
+        return base[f] + (i / L) * K + (i % L) * r.leaves[f].size;
     }
 };
 
@@ -76,9 +86,23 @@ struct Request {
     std::vector<uint64_t> src_ptr, dst_ptr; // device addresses of the blobs
 };
 
-// Validates descriptors (and blobs when given) and builds the request.
+// Validates descriptors (and blobs when given) and builds the request.  A
+// Split side fails with LLAMA_E_UNSUPPORTED unless `allow_split`.
 Request make_request(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
-                     const llama_blob* dst_blobs, bool need_blobs);
+                     const llama_blob* dst_blobs, bool need_blobs, bool allow_split = false);
+
+// One part-to-part copy of a copy with a Split side: the leaves both parts
+// hold, from the source part to the destination part.  `naive`: it writes part
+// of the records of a record-major destination part, so only the element-wise
+// path writes nothing but its own leaves.
+struct SubCopy {
+    Request rq;
+    bool naive = false;
+};
+// The part-to-part copies of `whole` (made with allow_split), destination part
+// by destination part; a plain side is one part holding every leaf.  The
+// padding of a destination part is written by the first copy into it.
+std::vector<SubCopy> split_copies(const llama_mapping_desc* src, const llama_mapping_desc* dst, const Request& whole);
 
 // A complete launch plan for one copy.
 struct Plan {

@@ -19,9 +19,9 @@ LIB_PATH = os.path.join(PKG, "libllama_mi355x.so")
 
 MAX_RANK = 8
 
-AOS_PACKED, AOS_ALIGNED, SOA_SINGLE, SOA_MULTI, AOSOA = 0, 1, 2, 3, 4
+AOS_PACKED, AOS_ALIGNED, SOA_SINGLE, SOA_MULTI, AOSOA, SPLIT = 0, 1, 2, 3, 4, 5
 KINDS = {"aos_packed": AOS_PACKED, "aos_aligned": AOS_ALIGNED, "soa_single": SOA_SINGLE,
-         "soa_multi": SOA_MULTI, "aosoa": AOSOA}
+         "soa_multi": SOA_MULTI, "aosoa": AOSOA, "split": SPLIT}
 
 PATH_AUTO, PATH_STREAM, PATH_TILE, PATH_NAIVE, PATH_EMPTY = 0, 1, 2, 3, 4
 PATH_NAMES = {PATH_STREAM: "stream", PATH_TILE: "tile", PATH_NAIVE: "naive", PATH_EMPTY: "empty"}
@@ -52,10 +52,15 @@ class RecordDesc(ctypes.Structure):
     _fields_ = [("num_nodes", ctypes.c_uint32), ("nodes", ctypes.POINTER(Field))]
 
 
+class SplitDesc(ctypes.Structure):
+    _fields_ = [("first_leaf", ctypes.c_uint32), ("leaf_count", ctypes.c_uint32),
+                ("kind", ctypes.c_uint32 * 2), ("lanes", ctypes.c_uint32 * 2)]
+
+
 class MappingDesc(ctypes.Structure):
     _fields_ = [("record", ctypes.POINTER(RecordDesc)), ("kind", ctypes.c_uint32), ("rank", ctypes.c_uint32),
                 ("extents", ctypes.c_uint64 * MAX_RANK), ("lanes", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("reserved", ctypes.c_uint32), ("split", ctypes.POINTER(SplitDesc))]
 
 
 class Blob(ctypes.Structure):
@@ -219,12 +224,19 @@ class Record:
 
 
 class Mapping:
-    def __init__(self, record: Record, kind: str, extents, lanes: int = 0):
+    """A mapping of `record` over `extents`.  kind "split" takes
+    split=(first_leaf, leaf_count, (kind, lanes), (kind, lanes)): the selected
+    leaf range through the first plain mapping, the other leaves through the
+    second (sec. 3.7 Split)."""
+
+    def __init__(self, record: Record, kind: str, extents, lanes: int = 0, split=None):
         ext = [int(e) for e in (extents if isinstance(extents, (list, tuple)) else [extents])]
         self.record = record
         self.kind = kind
         self.extents = ext
         self.lanes = int(lanes)
+        self.split = split
+        self._split = None
         self.desc = MappingDesc()
         self.desc.record = ctypes.pointer(record.desc)
         self.desc.kind = KINDS[kind] if isinstance(kind, str) else int(kind)
@@ -233,6 +245,15 @@ class Mapping:
             self.desc.extents[d] = e
         self.desc.lanes = self.lanes
         self.desc.reserved = 0
+        if split is not None:
+            first, count, (k0, l0), (k1, l1) = split
+            sd = SplitDesc()
+            sd.first_leaf, sd.leaf_count = int(first), int(count)
+            sd.kind[0] = KINDS[k0] if isinstance(k0, str) else int(k0)
+            sd.kind[1] = KINDS[k1] if isinstance(k1, str) else int(k1)
+            sd.lanes[0], sd.lanes[1] = int(l0), int(l1)
+            self._split = sd  # kept alive with the descriptor that points at it
+            self.desc.split = ctypes.pointer(sd)
 
     @property
     def blob_count(self) -> int:

@@ -7,6 +7,7 @@ import os
 import random
 import re
 
+import numpy as np
 import pytest
 
 from paper_2106_04284_amd import llama as L
@@ -410,3 +411,45 @@ def test_build_refuses_kernels_with_scratch():
                 "k.hip:2:1: remark:     ScratchSize [bytes/lane]: 3960 [-Rpass-analysis=kernel-resource-usage]\n")
     with pytest.raises(RuntimeError, match="spills: 3960"):
         B._check_no_scratch(bad)
+
+
+def test_split_mapping_host(orc):
+    """Split mappings (sec. 3.7) through the C ABI: blob counts, sizes and
+    every offset equal the oracle's; malformed splits are rejected; plans,
+    batches and tuning take plain mappings only."""
+    import random
+    rng = random.Random(5)
+    plain = [("aos_packed", 0), ("aos_aligned", 0), ("soa_single", 0), ("soa_multi", 0), ("aosoa", 4), ("aosoa", 32)]
+    for name in ("particle", "mixed", "listing1", "lbm"):
+        rec = W.RECORDS[name]
+        rg, ro = L.Record(rec), orc.Record(rec)
+        F = ro.nleaves
+        for first, count in [(0, 1), (0, F - 1), (1, F - 1), (F // 2, 1)]:
+            for _ in range(3):
+                sp = (first, count, rng.choice(plain), rng.choice(plain))
+                for ext in ([1], [45], [3, 5]):
+                    m = L.Mapping(rg, "split", ext, split=sp)
+                    o = orc.Mapping(ro, "split", ext, split=sp)
+                    assert m.blob_sizes() == o.blob_sizes(), (name, sp, ext)
+                    n = int(np.prod(ext))
+                    for i in sorted({0, n // 2, n - 1}):
+                        coord = list(np.unravel_index(i, ext))
+                        for f in range(F):
+                            assert m.offset(coord, f) == o.blob_nr_and_offset(coord, f), (name, sp, ext, i, f)
+    rg = L.Record(W.PARTICLE)
+    ok = ("soa_multi", 0), ("aos_packed", 0)
+    for bad in [(0, 7, *ok), (5, 3, *ok), (0, 0, *ok), (1, 2, ("split", 0), ok[1]), (1, 2, ("aosoa", 3), ok[1])]:
+        with pytest.raises(L.LlamaError) as e:
+            L.Mapping(rg, "split", [10], split=bad).blob_sizes()
+        assert e.value.status == L.E_INVALID_ARG
+    s = L.Mapping(rg, "split", [10], split=(0, 3, *ok))
+    a = L.Mapping(rg, "aos_packed", [10])
+    for call in (lambda: L.plan(s, a), lambda: L.plan(a, s)):
+        with pytest.raises(L.LlamaError) as e:
+            call()
+        assert e.value.status == L.E_UNSUPPORTED
+    desc = L.MappingDesc()
+    ctypes.memmove(ctypes.byref(desc), ctypes.byref(s.desc), ctypes.sizeof(desc))
+    desc.split = None
+    cnt = ctypes.c_uint32()
+    assert L.lib().llama_mapping_blob_count(ctypes.byref(desc), ctypes.byref(cnt)) == L.E_INVALID_ARG

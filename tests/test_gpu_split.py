@@ -1,0 +1,137 @@
+"""GPU parity of copies with a Split mapping (sec. 3.7) on either side: the
+HIP copy through the C ABI against the CPU oracle, byte for byte, with the
+destination's padding and the bytes around every destination blob checked.
+A Split copy runs as one copy per pair of parts sharing leaves."""
+import random
+
+import numpy as np
+import pytest
+
+from paper_2106_04284_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GUARD = 64
+PLAIN = [("aos_packed", 0), ("aos_aligned", 0), ("soa_single", 0), ("soa_multi", 0), ("aosoa", 4),
+         ("aosoa", 8), ("aosoa", 32), ("aosoa", 64)]
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_04284_amd import llama
+    llama.lib()
+    return llama
+
+
+def _maps(L, orc, rec, layout, extents):
+    kind, arg = layout
+    ro, rg = orc.Record(rec), L.Record(rec)
+    if kind == "split":
+        return orc.Mapping(ro, "split", extents, split=arg), L.Mapping(rg, "split", extents, split=arg)
+    return orc.Mapping(ro, kind, extents, arg), L.Mapping(rg, kind, extents, arg)
+
+
+def _cases():
+    rng = random.Random(2106)
+    out = []
+    for name in ("particle", "mixed", "listing1", "lbm"):
+        F = len(W.leaf_types(W.RECORDS[name]))
+        ranges = sorted({(0, 1), (0, F - 1), (1, F - 1), (F // 2, 1), (1, max(1, F // 2)), (F - 1, 1)})
+
+        def split():
+            first, count = rng.choice(ranges)
+            return ("split", (first, count, rng.choice(PLAIN), rng.choice(PLAIN)))
+
+        for _ in range(10):
+            n = rng.choice([1, 63, 777, 4099, 20011])
+            ext = [n] if rng.random() < 0.8 else [13, 17]
+            s = split()
+            kind = rng.randrange(4)
+            if kind == 0:
+                pair = (rng.choice(PLAIN), s)
+            elif kind == 1:
+                pair = (s, rng.choice(PLAIN))
+            elif kind == 2:  # the same selection on both sides, other inner mappings
+                f, c = s[1][0], s[1][1]
+                pair = (s, ("split", (f, c, rng.choice(PLAIN), rng.choice(PLAIN))))
+            else:
+                pair = (s, split())
+            out.append((name, pair[0], pair[1], ext))
+    return out
+
+
+CASES = _cases()
+
+
+def _id(c):
+    def lay(x):
+        if x[0] == "split":
+            f, n, a, b = x[1]
+            return f"split{f}+{n}[{a[0]}{a[1] or ''},{b[0]}{b[1] or ''}]"
+        return f"{x[0]}{x[1] or ''}"
+    return f"{c[0]}-{lay(c[1])}-{lay(c[2])}-{'x'.join(map(str, c[3]))}"
+
+
+def _run(L, orc, rec, src_l, dst_l, extents, seed, fill=0xCD, keep=False, **opts):
+    ms_o, ms = _maps(L, orc, rec, src_l, extents)
+    md_o, md = _maps(L, orc, rec, dst_l, extents)
+    assert ms.blob_sizes() == ms_o.blob_sizes() and md.blob_sizes() == md_o.blob_sizes()
+    src = [W.random_bytes(s, seed * 131 + k) for k, s in enumerate(ms_o.blob_sizes())]
+    if keep:
+        opts["flags"] = opts.get("flags", 0) | L.COPY_PRESERVE_PADDING
+        want = orc.copy(ms_o, src, md_o, [np.full(s, fill, np.uint8) for s in md_o.blob_sizes()], keep_padding=True)
+    else:
+        want = orc.copy(ms_o, src, md_o)
+    s_dev = [torch.from_numpy(b).cuda() for b in src]
+    bufs = []
+    for s in md_o.blob_sizes():
+        buf = torch.full((s + 2 * GUARD,), fill, dtype=torch.uint8, device="cuda")
+        bufs.append(buf)
+    L.copy(ms, s_dev, md, [b[GUARD:b.numel() - GUARD] for b in bufs], **opts)
+    torch.cuda.synchronize()
+    for k, (buf, w) in enumerate(zip(bufs, want)):
+        host = buf.cpu().numpy()
+        got = host[GUARD:GUARD + w.size]
+        if not np.array_equal(got, w):
+            bad = np.flatnonzero(got != w)
+            raise AssertionError(f"blob {k}: {bad.size} bytes differ, first at {bad[0]} "
+                                 f"(got {got[bad[0]]:#x}, want {w[bad[0]]:#x})")
+        assert (host[:GUARD] == fill).all() and (host[GUARD + w.size:] == fill).all(), \
+            f"blob {k}: bytes outside the blob changed"
+
+
+@pytest.mark.parametrize("case", CASES, ids=_id)
+def test_split_copy(L, orc, case):
+    name, src_l, dst_l, ext = case
+    print(f"split case {_id(case)}", flush=True)
+    _run(L, orc, W.RECORDS[name], src_l, dst_l, ext, seed=len(_id(case)))
+
+
+@pytest.mark.parametrize("opts", [dict(flags=1), dict(path="naive"), dict(keep=True), dict(threads=64),
+                                  dict(tile_records=16)], ids=["no_direct", "naive", "keep", "t64", "T16"])
+def test_split_copy_options(L, orc, opts):
+    """Options reach every part-to-part copy; the element-wise path and kept
+    padding give the oracle's bytes too."""
+    opts = dict(opts)
+    keep = opts.pop("keep", False)
+    if opts.get("path") == "naive":
+        opts["path"] = L.PATH_NAIVE
+    rec = W.MIXED
+    a = ("split", (2, 5, ("aos_aligned", 0), ("aosoa", 8)))
+    b = ("split", (0, 4, ("aosoa", 32), ("aos_aligned", 0)))
+    for k, (s, d) in enumerate([(a, b), (("aos_aligned", 0), a), (b, ("aosoa", 64))]):
+        print(f"split options {opts} keep={keep} pair {k}", flush=True)
+        _run(L, orc, rec, s, d, [3001], seed=70 + k, keep=keep, **opts)
+
+
+def test_split_copy_zero_records(L, orc):
+    rg = L.Record(W.PARTICLE)
+    s = L.Mapping(rg, "split", [0], split=(0, 3, ("soa_multi", 0), ("aos_aligned", 0)))
+    d = L.Mapping(rg, "aosoa", [0], 8)
+    L.copy(s, [torch.empty(0, dtype=torch.uint8, device="cuda")] * 5, d,
+           [torch.empty(0, dtype=torch.uint8, device="cuda")])
+    torch.cuda.synchronize()
