@@ -52,6 +52,9 @@ def log(msg):
 
 
 def _name(layout):
+    if layout[0] == "split":
+        f, c, a, b = layout[1]
+        return f"split[{f},{f + c})({_name(a)},{_name(b)})"
     kind, lanes = layout
     return f"{kind}{lanes}" if kind == "aosoa" else kind
 
@@ -81,10 +84,18 @@ def measured_traffic():
 # CPU baseline: the oracle on a bounded sample of the same workload
 # --------------------------------------------------------------------------
 
+def make_mapping(mod, rec, layout, extents):
+    """A mapping of `mod` (the library binding or the oracle): layout is
+    (kind, lanes), or ("split", (first, count, (kind, lanes), (kind, lanes)))."""
+    if layout[0] == "split":
+        return mod.Mapping(rec, "split", extents, split=layout[1])
+    return mod.Mapping(rec, layout[0], extents, layout[1])
+
+
 def cpu_baseline(record, layouts, pairs, n_sample, budget_s=20.0):
     from oracle import oracle as orc
     ro = orc.Record(record)
-    maps = {l: orc.Mapping(ro, l[0], [n_sample], l[1]) for l in layouts}
+    maps = {l: make_mapping(orc, ro, l, [n_sample]) for l in layouts}
     srcs = {l: [W.random_bytes(s, 99 + k) for k, s in enumerate(maps[l].blob_sizes())] for l in layouts}
     dsts = {l: maps[l].alloc() for l in layouts}
     nbytes, elapsed, done = 0, 0.0, 0
@@ -109,7 +120,7 @@ def setup_layouts(L, torch, record, extents, layouts, values):
     """Uploads the per-leaf values as multi-blob SoA and fills every other
     layout from it on the GPU (untimed)."""
     rg = L.Record(record)
-    maps = {l: L.Mapping(rg, l[0], extents, l[1]) for l in layouts}
+    maps = {l: make_mapping(L, rg, l, extents) for l in layouts}
     mb_layout = ("soa_multi", 0)
     blobs = {mb_layout: [torch.from_numpy(np.ascontiguousarray(v).view(np.uint8).reshape(-1)).cuda()
                          for v in values]}
@@ -126,7 +137,8 @@ def time_pairs(L, torch, maps, blobs, pairs, steps, warmup, stream, flush=None):
     `flush` (a device buffer larger than the 256 MB Infinity Cache), the
     buffer is read before each copy, outside its events, so that every copy
     starts cold."""
-    plans = {p: L.plan(maps[p[0]], maps[p[1]]) for p in pairs}
+    plans = {p: (L.plan(maps[p[0]], maps[p[1]]) if "split" not in (p[0][0], p[1][0]) else {"path": "split"})
+             for p in pairs}
     for _ in range(warmup):
         for a, b in pairs:
             L.copy(maps[a], blobs[a], maps[b], blobs[b], stream=stream)
@@ -154,7 +166,7 @@ def time_pairs(L, torch, maps, blobs, pairs, steps, warmup, stream, flush=None):
     per_pair = {}
     for p, lst in ev.items():
         ms = [e0.elapsed_time(e1) for e0, e1 in lst]
-        nb = plans[p]["read_bytes"] + plans[p]["write_bytes"]
+        nb = sum(maps[p[0]].blob_sizes()) + sum(maps[p[1]].blob_sizes())
         per_pair[p] = {"path": plans[p]["path"], "bytes": nb, "ms_median": statistics.median(ms),
                        "ms_min": min(ms), "ms_mean": statistics.mean(ms),
                        "gbs_median": nb / (statistics.median(ms) * 1e-3) / 1e9}
@@ -463,7 +475,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="particle", choices=["particle", "lbm", "batch", "serve", "pic"])
+    ap.add_argument("--workload", default="particle", choices=["particle", "lbm", "split", "batch", "serve", "pic"])
     ap.add_argument("--requests", type=int, default=2000, help="serve: measured requests (after 200 warm-up)")
     ap.add_argument("--rho", type=float, default=0.8, help="serve: offered load as a fraction of batched GB/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -505,6 +517,23 @@ def main():
                    "42 ordered pairs of packed AoS, aligned AoS, SoA single-blob, SoA multi-blob, AoSoA8/32/64"
         dtype = "u32"
         cpu_n = 1 << 19
+    elif args.workload == "split":
+        # Split mappings (sec. 3.7) of the particle: positions as AoSoA32 with
+        # velocities and mass as multi-blob SoA; velocities as multi-blob SoA
+        # with positions and mass as aligned AoS
+        n = 1 << 26
+        record, extents = W.PARTICLE, [n]
+        A, M, Q32 = ("aos_packed", 0), ("soa_multi", 0), ("aosoa", 32)
+        S1 = ("split", (0, 3, Q32, M))
+        S2 = ("split", (3, 3, M, ("aos_aligned", 0)))
+        layouts = [A, M, Q32, S1, S2]
+        pairs = [(A, S1), (S1, A), (M, S2), (S2, Q32), (S1, S2), (S2, S1)]
+        values = W.raw_u32_values(7, n, W.BASE_SEED + 4)
+        workload = "n-body particle 7xf32, 2^26 records, 6 ordered pairs with a Split side: " \
+                   "split[pos](AoSoA32, SoA multi-blob) and split[vel](SoA multi-blob, aligned AoS) against " \
+                   "packed AoS, SoA multi-blob, AoSoA32 and each other"
+        dtype = "u32"
+        cpu_n = 1 << 19
     else:
         record, extents = W.LBM, [128, 128, 128]
         layouts = [("aos_aligned", 0), ("soa_multi", 0), ("aosoa", 32)]
@@ -530,14 +559,15 @@ def main():
     step_bytes = sum(v["bytes"] for v in per_pair.values())
     value = step_bytes * args.steps / (total_ms * 1e-3) / 1e9
 
-    tile = [p for p in pairs if per_pair[p]["path"] == "tile"]
+    tile = [p for p in pairs if per_pair[p]["path"] == "tile"] or pairs
+    kernel = "tile_kernel" if per_pair[tile[0]]["path"] == "tile" else "part copies (tile, stream, naive kernels)"
     tile_ms = statistics.mean(per_pair[p]["ms_mean"] for p in tile)
     tile_bytes = statistics.mean(per_pair[p]["bytes"] for p in tile)
     achieved = tile_bytes / (tile_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic() if args.workload == "particle" else None,
-                "kernel": "tile_kernel", "bytes_per_launch": int(tile_bytes),
+                "kernel": kernel, "bytes_per_launch": int(tile_bytes),
                 "launch_ms_mean": round(tile_ms, 4), "launches": len(tile) * args.steps}
 
     extras = {}

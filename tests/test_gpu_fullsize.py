@@ -140,6 +140,46 @@ def test_stream_store_modes_sampled(L, orc, case):
             assert not blob.reshape(-1, sz)[:, pad].any()
 
 
+# the Split pairs the benchmark times (particle, 2^26 records): positions as
+# AoSoA32 with velocities and mass as multi-blob SoA, and velocities as
+# multi-blob SoA with positions and mass as aligned AoS
+_S1 = ("split", (0, 3, ("aosoa", 32), ("soa_multi", 0)))
+_S2 = ("split", (3, 3, ("soa_multi", 0), ("aos_aligned", 0)))
+SPLIT_PAIRS = [(("aos_packed", 0), _S1), (_S1, ("aos_packed", 0)), (("soa_multi", 0), _S2), (_S2, ("aosoa", 32)),
+               (_S1, _S2), (_S2, _S1)]
+
+
+def _mk(mod, rec, layout, ext):
+    if layout[0] == "split":
+        return mod.Mapping(rec, "split", ext, split=layout[1])
+    return mod.Mapping(rec, layout[0], ext, layout[1])
+
+
+@pytest.mark.parametrize("pair", SPLIT_PAIRS, ids=["A-S1", "S1-A", "M-S2", "S2-Q32", "S1-S2", "S2-S1"])
+def test_split_2e26_sampled(L, orc, pair):
+    """Every destination byte written (two fills agree) and 2^20 sampled
+    values equal the oracle's, at the benchmark's size."""
+    n = 1 << 26
+    a, b = pair
+    ro, rg = orc.Record(W.PARTICLE), L.Record(W.PARTICLE)
+    ms_o, md_o = _mk(orc, ro, a, [n]), _mk(orc, ro, b, [n])
+    ms, md = _mk(L, rg, a, [n]), _mk(L, rg, b, [n])
+    assert ms.blob_sizes() == ms_o.blob_sizes() and md.blob_sizes() == md_o.blob_sizes()
+    src = [_random_blob(s, 2000 + k) for k, s in enumerate(ms.blob_sizes())]
+    d0 = md.alloc(fill=0x00)
+    d1 = md.alloc(fill=0xFF)
+    L.copy(ms, src, md, d0)
+    L.copy(ms, src, md, d1)
+    torch.cuda.synchronize()
+    for x, y in zip(d0, d1):
+        assert torch.equal(x, y)
+    src_h = [t.cpu().numpy() for t in src]
+    dst_h = [t.cpu().numpy() for t in d0]
+    idx, leaf = _samples(n, 7, 1 << 20, 9)
+    bad, first = orc.check_samples(ms_o, src_h, md_o, dst_h, idx, leaf)
+    assert bad == 0, f"{bad} sampled values differ, first sample {first}"
+
+
 LBM_LAYOUTS = [("aos_aligned", 0), ("soa_multi", 0), ("aosoa", 32)]
 LBM_PAIRS = [(a, b) for a in LBM_LAYOUTS for b in LBM_LAYOUTS if a != b]
 
