@@ -411,13 +411,35 @@ std::vector<SubCopy> split_copies(const llama_mapping_desc* src, const llama_map
     const std::vector<Part> dp = parts_of(dst, whole.record);
     std::vector<SubCopy> out;
     for (const Part& P : dp) {
-        bool padding_written = false;
+        // the source parts that share leaves with P, with those leaves
+        std::vector<std::pair<const Part*, std::vector<uint32_t>>> from;
         for (const Part& Q : sp) {
             std::vector<uint32_t> both;
             std::set_intersection(P.leaves.begin(), P.leaves.end(), Q.leaves.begin(), Q.leaves.end(),
                                   std::back_inserter(both));
-            if (both.empty())
-                continue;
+            if (!both.empty())
+                from.emplace_back(&Q, std::move(both));
+        }
+        // An AoS part fed by several source parts: the copy with the most
+        // bytes goes first and writes whole records, taking every byte its
+        // leaves do not cover as padding (zero, or kept); the others then
+        // write only their own leaves over it.
+        const bool whole_first = from.size() > 1 && P.side.lanes == 1 &&
+                                 P.leaves.size() + P.side.gaps.size() + 1 <= size_t(kTileMaxEntries);
+        if (whole_first) {
+            auto bytes = [&](const std::vector<uint32_t>& g) {
+                uint64_t b = 0;
+                for (uint32_t f : g)
+                    b += whole.record.leaves[f].size;
+                return b;
+            };
+            std::stable_sort(from.begin(), from.end(),
+                             [&](const auto& x, const auto& y) { return bytes(x.second) > bytes(y.second); });
+        }
+        bool padding_written = false;
+        for (const auto& fq : from) {
+            const Part& Q = *fq.first;
+            const std::vector<uint32_t>& both = fq.second;
             SubCopy c;
             c.rq.record = sub_record(whole.record, both);
             c.rq.src = restrict_side(Q, both);
@@ -425,9 +447,26 @@ std::vector<SubCopy> split_copies(const llama_mapping_desc* src, const llama_map
             if (padding_written) {
                 // the alignment gaps of this destination part are written once
                 c.rq.dst.gaps.clear();
+            } else if (whole_first) {
+                // every byte of the record outside these leaves becomes a gap
+                std::vector<std::pair<uint64_t, uint64_t>> cover;
+                for (size_t k = 0; k < both.size(); k++)
+                    cover.push_back({c.rq.dst.base[k], whole.record.leaves[both[k]].size});
+                std::sort(cover.begin(), cover.end());
+                c.rq.dst.gaps.clear();
+                uint64_t cur = 0;
+                for (const auto& cv : cover) {
+                    if (cv.first > cur)
+                        c.rq.dst.gaps.push_back({cur, cv.first - cur});
+                    cur = std::max(cur, cv.first + cv.second);
+                }
+                if (P.side.block > cur)
+                    c.rq.dst.gaps.push_back({cur, P.side.block - cur});
+                c.rq.dst.partial = false;
             }
+            const bool wrote_whole = whole_first && !padding_written;
             padding_written = true;
-            c.naive = c.rq.dst.partial && P.side.lanes >= 1;
+            c.naive = c.rq.dst.partial && P.side.lanes >= 1 && !wrote_whole;
             c.rq.src_ptr.assign(whole.src_ptr.begin() + Q.first_blob,
                                 whole.src_ptr.begin() + Q.first_blob + Q.side.blob_size.size());
             c.rq.dst_ptr.assign(whole.dst_ptr.begin() + P.first_blob,

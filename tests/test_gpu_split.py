@@ -135,3 +135,22 @@ def test_split_copy_zero_records(L, orc):
     L.copy(s, [torch.empty(0, dtype=torch.uint8, device="cuda")] * 5, d,
            [torch.empty(0, dtype=torch.uint8, device="cuda")])
     torch.cuda.synchronize()
+
+
+AOS_FED_BY_TWO = [(name, first, count, part, dst, keep)
+                  for name in ("particle", "mixed", "listing1", "lbm")
+                  for first, count in ((0, 1), (1, 2))
+                  for part in (("aosoa", 8), ("soa_single", 0))
+                  for dst in (("aos_packed", 0), ("aos_aligned", 0), ("aosoa", 1))
+                  for keep in (False, True)]
+
+
+@pytest.mark.parametrize("case", AOS_FED_BY_TWO, ids=lambda c: "-".join(map(str, c)))
+def test_split_into_aos_from_two_parts(L, orc, case):
+    """An AoS destination fed by two source parts: the larger part copy writes
+    whole records (every other byte as padding), the smaller one then writes
+    its own leaves over it."""
+    name, first, count, part, dst, keep = case
+    src = ("split", (first, count, part, ("soa_multi", 0)))
+    print(f"split into aos {case}", flush=True)
+    _run(L, orc, W.RECORDS[name], src, dst, [1031], seed=first * 7 + count, keep=keep)
