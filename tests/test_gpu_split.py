@@ -76,7 +76,7 @@ def _id(c):
     return f"{c[0]}-{lay(c[1])}-{lay(c[2])}-{'x'.join(map(str, c[3]))}"
 
 
-def _run(L, orc, rec, src_l, dst_l, extents, seed, fill=0xCD, keep=False, **opts):
+def _run(L, orc, rec, src_l, dst_l, extents, seed, fill=0xCD, keep=False, src_off=0, dst_off=0, **opts):
     ms_o, ms = _maps(L, orc, rec, src_l, extents)
     md_o, md = _maps(L, orc, rec, dst_l, extents)
     assert ms.blob_sizes() == ms_o.blob_sizes() and md.blob_sizes() == md_o.blob_sizes()
@@ -86,21 +86,26 @@ def _run(L, orc, rec, src_l, dst_l, extents, seed, fill=0xCD, keep=False, **opts
         want = orc.copy(ms_o, src, md_o, [np.full(s, fill, np.uint8) for s in md_o.blob_sizes()], keep_padding=True)
     else:
         want = orc.copy(ms_o, src, md_o)
-    s_dev = [torch.from_numpy(b).cuda() for b in src]
+    s_dev = []
+    for b in src:  # each source blob at byte `src_off` of its own buffer
+        sbuf = torch.empty(b.size + src_off, dtype=torch.uint8, device="cuda")
+        sbuf[src_off:].copy_(torch.from_numpy(b))
+        s_dev.append(sbuf[src_off:])
     bufs = []
     for s in md_o.blob_sizes():
-        buf = torch.full((s + 2 * GUARD,), fill, dtype=torch.uint8, device="cuda")
+        buf = torch.full((s + 2 * GUARD + dst_off,), fill, dtype=torch.uint8, device="cuda")
         bufs.append(buf)
-    L.copy(ms, s_dev, md, [b[GUARD:b.numel() - GUARD] for b in bufs], **opts)
+    lo = GUARD + dst_off
+    L.copy(ms, s_dev, md, [b[lo:b.numel() - GUARD] for b in bufs], **opts)
     torch.cuda.synchronize()
     for k, (buf, w) in enumerate(zip(bufs, want)):
         host = buf.cpu().numpy()
-        got = host[GUARD:GUARD + w.size]
+        got = host[lo:lo + w.size]
         if not np.array_equal(got, w):
             bad = np.flatnonzero(got != w)
             raise AssertionError(f"blob {k}: {bad.size} bytes differ, first at {bad[0]} "
                                  f"(got {got[bad[0]]:#x}, want {w[bad[0]]:#x})")
-        assert (host[:GUARD] == fill).all() and (host[GUARD + w.size:] == fill).all(), \
+        assert (host[:lo] == fill).all() and (host[lo + w.size:] == fill).all(), \
             f"blob {k}: bytes outside the blob changed"
 
 
@@ -154,3 +159,15 @@ def test_split_into_aos_from_two_parts(L, orc, case):
     src = ("split", (first, count, part, ("soa_multi", 0)))
     print(f"split into aos {case}", flush=True)
     _run(L, orc, W.RECORDS[name], src, dst, [1031], seed=first * 7 + count, keep=keep)
+
+
+@pytest.mark.parametrize("offs", [(1, 0), (0, 3), (4, 8), (7, 13)], ids=lambda o: f"src{o[0]}-dst{o[1]}")
+def test_split_copy_misaligned_blobs(L, orc, offs):
+    """Blobs at any byte offset: every part copy plans for the addresses its
+    part's blobs really have."""
+    src_off, dst_off = offs
+    a = ("split", (0, 3, ("aosoa", 32), ("soa_multi", 0)))
+    b = ("split", (3, 3, ("soa_multi", 0), ("aos_aligned", 0)))
+    for k, (s, d) in enumerate([(("aos_packed", 0), a), (a, ("aos_packed", 0)), (a, b), (b, ("aosoa", 8))]):
+        print(f"split misaligned {offs} pair {k}", flush=True)
+        _run(L, orc, W.PARTICLE, s, d, [5003], seed=90 + k, src_off=src_off, dst_off=dst_off)
