@@ -182,8 +182,11 @@ typedef struct {
  *    leaves, in order on `stream`, each writing only its own leaves and the
  *    padding of its destination part.  A pair that writes part of the records
  *    of a record-major destination part (AoS, AoSoA) takes the element-wise
- *    path; every other pair is planned like a plain copy.  Batches, servers,
- *    plans and autotuning take plain mappings only (LLAMA_E_UNSUPPORTED). */
+ *    path; every other pair is planned like a plain copy.  Batches take a
+ *    Split item as its pairs, side by side, unless one of them writes part of
+ *    the records of a record-major destination part (LLAMA_E_UNSUPPORTED);
+ *    servers, plans and autotuning take plain mappings only
+ *    (LLAMA_E_UNSUPPORTED). */
 int llama_copy(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
                const llama_blob* dst_blobs, void* stream);
 
@@ -358,7 +361,7 @@ typedef struct {
 typedef struct llama_batch llama_batch;
 
 typedef struct {
-    uint64_t items;        /* non-empty items */
+    uint64_t items;        /* non-empty items; an item with a Split side counts its part copies */
     uint64_t tile_items;   /* items copied by the tiled kernel */
     uint64_t stream_items; /* items copied as long runs */
     uint64_t work_units;   /* tiles plus run chunks */

@@ -292,17 +292,31 @@ Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_opt
     rqs.reserve(n);
     for (size_t k = 0; k < n; k++) {
         try {
-            rqs.push_back(make_request(items[k].src, items[k].src_blobs, items[k].dst, items[k].dst_blobs, true));
+            rqs.push_back(make_request(items[k].src, items[k].src_blobs, items[k].dst, items[k].dst_blobs, true, true));
         } catch (const Error& e) {
             fail(e.status, "batch item " + std::to_string(k) + ": " + e.message);
         }
     }
     check_batch_overlap(rqs);
 
+    // An item with a Split side becomes its part copies, which write disjoint
+    // bytes and so may run side by side; one that would write part of the
+    // records of a record-major destination part needs its part copies in
+    // order and is refused.
     BatchTable t;
     for (size_t k = 0; k < n; k++) {
         try {
-            t.add(rqs[k], threads, T, opt ? opt->flags : 0u);
+            if (items[k].src->kind != LLAMA_SPLIT && items[k].dst->kind != LLAMA_SPLIT) {
+                t.add(rqs[k], threads, T, opt ? opt->flags : 0u);
+                continue;
+            }
+            std::vector<SubCopy> parts = split_copies(items[k].src, items[k].dst, rqs[k]);
+            for (const SubCopy& c : parts)
+                if (c.naive) // then the copies into that part depend on their order
+                    fail(LLAMA_E_UNSUPPORTED, "its part copies write parts of the records of a record-major "
+                                              "destination part in turn; copy it with llama_copy");
+            for (const SubCopy& c : parts)
+                t.add(c.rq, threads, T, opt ? opt->flags : 0u);
         } catch (const Error& e) {
             fail(e.status, "batch item " + std::to_string(k) + ": " + e.message);
         }

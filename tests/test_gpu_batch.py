@@ -240,3 +240,48 @@ def test_autotune_caches_a_bit_exact_plan(L, orc, tmp_path):
     assert L.tune_lookup(a, b) is None
     assert L.tune_load(path) == 1 and L.tune_lookup(a, b) == best
     L.tune_clear()
+
+
+def _split_map(mod, rec, layout, n):
+    if layout[0] == "split":
+        return mod.Mapping(rec, "split", [n], split=layout[1])
+    return mod.Mapping(rec, layout[0], [n], layout[1])
+
+
+def test_batch_with_split_items(L, orc):
+    """Items with a Split side (sec. 3.7) run as their part copies, side by
+    side with plain items, over two graph replays; an item whose part copies
+    would write parts of the records of a record-major destination part in
+    turn is refused."""
+    g = random.Random(44)
+    s1 = ("split", (0, 3, ("aosoa", 32), ("soa_multi", 0)))
+    s2 = ("split", (3, 3, ("soa_multi", 0), ("aos_aligned", 0)))
+    s3 = ("split", (0, 3, ("aos_packed", 0), ("aosoa", 8)))
+    pairs = [(("aos_packed", 0), s1), (s1, ("soa_multi", 0)), (s2, ("soa_single", 0)), (s1, s3), (s3, s1),
+             (("aosoa", 64), s2), (("aos_aligned", 0), ("aosoa", 16))]
+    ro, rg = orc.Record(W.PARTICLE), L.Record(W.PARTICLE)
+    items, want = [], []
+    for k in range(21):
+        a, b = pairs[k % len(pairs)]
+        n = g.choice([1, 77, 4099, 30011])
+        ms_o, md_o = _split_map(orc, ro, a, n), _split_map(orc, ro, b, n)
+        src = [W.random_bytes(x, 500 + k * 13 + j) for j, x in enumerate(ms_o.blob_sizes())]
+        want.append(orc.copy(ms_o, src, md_o))
+        ms, md = _split_map(L, rg, a, n), _split_map(L, rg, b, n)
+        items.append((ms, [torch.from_numpy(x).cuda() for x in src], md, md.alloc(fill=0xCD)))
+    print("split batch: 21 items", flush=True)
+    b = L.Batch(items)
+    for rep in range(2):
+        refill(items, 0xCD if rep == 0 else 0x00)
+        torch.cuda.synchronize()
+        b.launch()
+        torch.cuda.synchronize()
+        check(items, want)
+    b.close()
+    # into packed AoS from both parts of s1: the part copies depend on their order
+    n = 100
+    ms, md = _split_map(L, rg, s1, n), L.Mapping(rg, "aos_packed", [n])
+    bad = [(ms, [t.cuda() for t in (torch.zeros(x, dtype=torch.uint8) for x in ms.blob_sizes())], md, md.alloc())]
+    with pytest.raises(L.LlamaError) as e:
+        L.Batch(bad)
+    assert e.value.status == L.E_UNSUPPORTED
