@@ -199,6 +199,18 @@ int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, co
         std::vector<Plan> plans;
         for (const SubCopy& c : split_copies(src, dst, rq)) {
             if (c.naive) {
+                // a tile plan that stores 16-byte granules of its own leaves
+                // straight from the staged source (direct store, no padding
+                // gaps) writes no other byte of the part's blocks either
+                try {
+                    Plan t = make_plan(c.rq, options);
+                    if (t.path == LLAMA_PATH_TILE && (t.tile.h.flags & kTileDirectStore) && c.rq.dst.gaps.empty()) {
+                        plans.push_back(t);
+                        continue;
+                    }
+                } catch (const Error&) {
+                    // the caller's path or tile size does not fit this part copy
+                }
                 llama_copy_options o = options ? *options : llama_copy_options{0, 0, 0, 0, 0};
                 o.path = LLAMA_PATH_NAIVE;
                 o.tile_records = 0;
