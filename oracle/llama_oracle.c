@@ -30,6 +30,8 @@
  *      AoSoA L  like AoS but each field repeated L times before the next
  *               field; the linear index i splits as (i / L, i mod L)
  *               (sec. 4.1).
+ *      One      every coordinate maps to the same single record, packed:
+ *               the array dimensions collapse to one element.
  *      Split    a selected part of the record dimension mapped by one of the
  *               mappings above, the remaining leaves by another; each part
  *               is that mapping of its own sub-record (the selected leaves,
@@ -73,6 +75,7 @@
 #define ORC_SOA_MULTI 3
 #define ORC_AOSOA 4
 #define ORC_SPLIT 5
+#define ORC_ONE 6
 
 /* most leaves a record mapped by Split may have */
 #define ORC_SPLIT_MAX_LEAVES 1024
@@ -382,7 +385,7 @@ int orc_blob_count(const orc_mapping* m, const orc_record* r)
     }
     if (m->kind == ORC_SOA_MULTI)
         return r->nleaves;
-    return 1;
+    return 1; /* AoS, SoA single-blob, AoSoA, One */
 }
 
 uint64_t orc_blob_size(const orc_mapping* m, const orc_record* r, int blob)
@@ -411,6 +414,8 @@ uint64_t orc_blob_size(const orc_mapping* m, const orc_record* r, int blob)
         uint64_t blocks = (n + m->lanes - 1) / m->lanes;
         return blocks * m->lanes * orc_packed_size(r);
     }
+    case ORC_ONE: /* a single packed record, whatever the extents */
+        return orc_packed_size(r);
     }
     return 0;
 }
@@ -462,6 +467,11 @@ int orc_blob_nr_and_offset(const orc_mapping* m, const orc_record* r, const uint
         *offset = block * (L * orc_packed_size(r)) + L * orc_packed_offset(r, f) + lane * r->size[f];
         return ORC_OK;
     }
+    case ORC_ONE: /* the one record, whatever the coordinate */
+        (void)i;
+        *blob = 0;
+        *offset = orc_packed_offset(r, f);
+        return ORC_OK;
     }
     return ORC_E_ARG;
 }
@@ -472,6 +482,8 @@ int orc_blob_nr_and_offset(const orc_mapping* m, const orc_record* r, const uint
 
 static int valid_plain(int32_t kind, uint64_t lanes)
 {
+    if (kind == ORC_ONE)
+        return 1;
     if (kind < ORC_AOS_PACKED || kind > ORC_AOSOA)
         return 0;
     return kind != ORC_AOSOA || lanes != 0;

@@ -13,7 +13,8 @@ Records are given in the neutral nested form used by the workload definitions:
 a record is a list of members; a member is an elemental type name, a nested
 list (a nested record), or a ``(member, count)`` pair for a static array.
 Mappings are ``(kind, extents, lanes)`` with kind one of ``aos_packed``,
-``aos_aligned``, ``soa_single``, ``soa_multi``, ``aosoa``, or ``split`` with
+``aos_aligned``, ``soa_single``, ``soa_multi``, ``aosoa``, ``one`` (every
+coordinate at the same single packed record), or ``split`` with
 ``split=(first, count, (kind, lanes), (kind, lanes))``: leaves
 ``[first, first + count)`` mapped by the first plain mapping, the others by the
 second (sec. 3.7 Split).
@@ -33,7 +34,7 @@ _LIB = os.path.join(_HERE, "liborc.so")
 MAX_RANK = 8
 MAX_LEAVES = 4096
 
-KINDS = {"aos_packed": 0, "aos_aligned": 1, "soa_single": 2, "soa_multi": 3, "aosoa": 4, "split": 5}
+KINDS = {"aos_packed": 0, "aos_aligned": 1, "soa_single": 2, "soa_multi": 3, "aosoa": 4, "split": 5, "one": 6}
 
 
 class _Record(ctypes.Structure):

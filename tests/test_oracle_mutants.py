@@ -37,6 +37,8 @@ MUTANTS = {
     "split_rest_blobs_overlap": ("first_blob = (uint64_t)orc_blob_count(&p.m, &p.r);", "first_blob = 0;"),
     "split_selection_one_long": ("return f >= m->first && f < m->first + m->count;",
                                  "return f >= m->first && f <= m->first + m->count;"),
+    "one_offset_uses_index": ("        (void)i;\n        *blob = 0;\n        *offset = orc_packed_offset(r, f);",
+                              "        *blob = 0;\n        *offset = i * orc_packed_size(r) + orc_packed_offset(r, f);"),
     "static_array_one_short": ("for (uint64_t c = 1; c < count; c++)", "for (uint64_t c = 2; c < count; c++)"),
     "aos_aligned_uses_packed_stride": ("*offset = i * orc_aligned_size(r) + orc_aligned_offset(r, f);",
                                        "*offset = i * orc_packed_size(r) + orc_aligned_offset(r, f);"),

@@ -540,3 +540,42 @@ def test_split_exactly_once_and_round_trip(orc, name):
             start = _build(orc, rec, "aos_aligned", [n], 0, _unique_leaf_values(types, n, first + count))
             back = orc.copy(m, orc.copy(aos, start, m), aos)
             assert np.array_equal(back[0], start[0])
+
+
+# --------------------------------------------------------------------------
+# One (sec. 3.7): the array dimensions collapse to a single record
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["particle", "mixed", "lbm", "listing1"])
+@pytest.mark.parametrize("ext", [[1], [37], [4, 9]])
+def test_one_broadcasts_a_single_packed_record(orc, name, ext):
+    """One holds one packed record whatever the extents; copied into packed
+    AoS it is that record repeated (numpy tile), and every value byte of it
+    is read by every coordinate."""
+    rec = W.RECORDS[name]
+    types = W.leaf_types(rec)
+    r = orc.Record(rec)
+    one = orc.Mapping(r, "one", ext)
+    S = sum(SIZES[t] for t in types)
+    n = int(np.prod(ext))
+    assert one.blob_sizes() == [S]
+    blob = [np.frombuffer(bytes(random.Random(n).randrange(256) for _ in range(S)), np.uint8).copy()]
+    aos = orc.copy(one, blob, orc.Mapping(r, "aos_packed", ext))
+    assert np.array_equal(aos[0], np.tile(blob[0], n))
+    assert [int(c.min()) for c in orc.write_counts(one)] == [n]
+
+
+def test_split_with_one_part_reads_a_shared_value(orc):
+    """Split of the particle with mass through One (the nesting of sec. 3.7's
+    listing, one level deep): into multi-blob SoA, every record gets the same
+    mass and its own position and velocity."""
+    n = 50
+    r = orc.Record(W.PARTICLE)
+    m = orc.Mapping(r, "split", [n], split=(6, 1, ("one", 0), ("soa_multi", 0)))
+    assert m.blob_sizes() == [4] + [4 * n] * 6
+    rng = np.random.default_rng(3)
+    src = [rng.integers(0, 256, s, dtype=np.uint8) for s in m.blob_sizes()]
+    out = orc.copy(m, src, orc.Mapping(r, "soa_multi", [n]))
+    for f in range(6):
+        assert np.array_equal(out[f], src[1 + f])
+    assert np.array_equal(out[6], np.tile(src[0], n))
