@@ -111,8 +111,11 @@ typedef enum {
     LLAMA_AOSOA = 4,       /* blocks of `lanes` records; inside a block leaf f's values are
                               contiguous at lanes*(packed offset of f): 1 blob of
                               ceil(N/lanes)*lanes*S */
-    LLAMA_SPLIT = 5        /* two of the kinds above over two parts of the record (sec. 3.7
+    LLAMA_SPLIT = 5,       /* two of the other kinds over two parts of the record (sec. 3.7
                               Split); see llama_split_desc */
+    LLAMA_ONE = 6          /* every array coordinate at the same single record, packed: 1 blob
+                              of S (sec. 3.7 One).  A copy reads it as a broadcast, element-wise;
+                              it is never a copy's destination (LLAMA_E_UNSUPPORTED) */
 } llama_mapping_kind;
 
 /* A Split mapping (sec. 3.7): the leaves [first_leaf, first_leaf + leaf_count)
@@ -127,7 +130,7 @@ typedef enum {
 typedef struct {
     uint32_t first_leaf;
     uint32_t leaf_count;
-    uint32_t kind[2];  /* llama_mapping_kind of the selected part and of the rest */
+    uint32_t kind[2];  /* llama_mapping_kind of the selected part and of the rest (not LLAMA_SPLIT) */
     uint32_t lanes[2]; /* LLAMA_AOSOA parts: lanes per block, a power of two */
 } llama_split_desc;
 

@@ -85,6 +85,8 @@ std::map<std::tuple<uint64_t, uint32_t, uint64_t, uint32_t, uint64_t, uint32_t, 
 
 Plan batch_plan(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags)
 {
+    if (rq.src.kind == LLAMA_ONE)
+        fail(LLAMA_E_UNSUPPORTED, "a One source is copied element-wise; copy it with llama_copy");
     llama_copy_options o{LLAMA_PATH_AUTO, tile_records, threads, 0, flags};
     Plan p;
     if (tile_records) {

@@ -178,7 +178,7 @@ std::vector<Part> parts_of(const llama_mapping_desc* m, const Record& r)
                                       std::to_string(F) + " leaves");
     uint32_t first_blob = 0;
     for (int k = 0; k < 2; k++) {
-        if (sd->kind[k] >= LLAMA_SPLIT)
+        if (sd->kind[k] == LLAMA_SPLIT || sd->kind[k] > LLAMA_ONE)
             fail(LLAMA_E_INVALID_ARG, "split: part " + std::to_string(k) + " must be a plain mapping kind");
         Part p;
         for (size_t f = 0; f < F; f++) {
@@ -236,7 +236,7 @@ Side make_side(const llama_mapping_desc* m, const Record& r)
 {
     if (!m)
         fail(LLAMA_E_INVALID_ARG, "mapping descriptor is NULL");
-    if (m->kind > LLAMA_SPLIT)
+    if (m->kind > LLAMA_ONE)
         fail(LLAMA_E_INVALID_ARG, "mapping kind " + std::to_string(m->kind) + " is not a llama_mapping_kind");
     if (m->rank < 1 || m->rank > LLAMA_MAX_RANK)
         fail(LLAMA_E_INVALID_ARG, "mapping rank must be 1..8");
@@ -293,6 +293,14 @@ Side make_side(const llama_mapping_desc* m, const Record& r)
             s.blob[f] = uint32_t(f);
             s.blob_size.push_back(mul(n, r.leaves[f].size, "blob size"));
         }
+        break;
+    case LLAMA_ONE:
+        // blocked with L = 1 and K = 0: every record at the one packed record
+        s.lanes = 1;
+        s.block = 0;
+        for (size_t f = 0; f < F; f++)
+            s.base[f] = r.leaves[f].packed_offset;
+        s.blob_size = {S};
         break;
     case LLAMA_AOSOA: {
         if (!is_pow2(m->lanes))
@@ -354,6 +362,8 @@ Request make_request(const llama_mapping_desc* src, const llama_blob* src_blobs,
     rq.dst = make_side(dst, rq.record);
     if (!allow_split && (src->kind == LLAMA_SPLIT || dst->kind == LLAMA_SPLIT))
         fail(LLAMA_E_UNSUPPORTED, "Split mappings are copied by llama_copy, llama_copy_ex and llama_copy_naive only");
+    if (dst->kind == LLAMA_ONE)
+        fail(LLAMA_E_UNSUPPORTED, "a One mapping holds a single record and cannot receive a copy of many");
     if (src->rank != dst->rank)
         fail(LLAMA_E_EXTENT_MISMATCH, "source and destination ranks differ");
     for (uint32_t d = 0; d < src->rank; d++)
@@ -411,6 +421,8 @@ std::vector<SubCopy> split_copies(const llama_mapping_desc* src, const llama_map
     const std::vector<Part> dp = parts_of(dst, whole.record);
     std::vector<SubCopy> out;
     for (const Part& P : dp) {
+        if (P.side.kind == LLAMA_ONE)
+            fail(LLAMA_E_UNSUPPORTED, "a One part holds a single record and cannot receive a copy of many");
         // the source parts that share leaves with P, with those leaves
         std::vector<std::pair<const Part*, std::vector<uint32_t>>> from;
         for (const Part& Q : sp) {
@@ -1022,6 +1034,14 @@ Plan make_plan_raw(const Request& rq, const llama_copy_options* opt)
         return p;
     }
     p.threads = threads ? threads : kDefaultThreads;
+    if (rq.src.kind == LLAMA_ONE) {
+        // a broadcast: every record reads the same bytes, which only the
+        // element-wise kernel's per-record arithmetic expresses (K = 0)
+        if (want != LLAMA_PATH_AUTO && want != LLAMA_PATH_NAIVE)
+            fail(LLAMA_E_UNSUPPORTED, "a One source is copied element-wise only");
+        fill_naive(rq, p);
+        return p;
+    }
     if (want == LLAMA_PATH_AUTO || want == LLAMA_PATH_STREAM) {
         if (fill_stream(rq, p))
             return p;

@@ -19,9 +19,9 @@ LIB_PATH = os.path.join(PKG, "libllama_mi355x.so")
 
 MAX_RANK = 8
 
-AOS_PACKED, AOS_ALIGNED, SOA_SINGLE, SOA_MULTI, AOSOA, SPLIT = 0, 1, 2, 3, 4, 5
+AOS_PACKED, AOS_ALIGNED, SOA_SINGLE, SOA_MULTI, AOSOA, SPLIT, ONE = 0, 1, 2, 3, 4, 5, 6
 KINDS = {"aos_packed": AOS_PACKED, "aos_aligned": AOS_ALIGNED, "soa_single": SOA_SINGLE,
-         "soa_multi": SOA_MULTI, "aosoa": AOSOA, "split": SPLIT}
+         "soa_multi": SOA_MULTI, "aosoa": AOSOA, "split": SPLIT, "one": ONE}
 
 PATH_AUTO, PATH_STREAM, PATH_TILE, PATH_NAIVE, PATH_EMPTY = 0, 1, 2, 3, 4
 PATH_NAMES = {PATH_STREAM: "stream", PATH_TILE: "tile", PATH_NAIVE: "naive", PATH_EMPTY: "empty"}

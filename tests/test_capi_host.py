@@ -453,3 +453,43 @@ def test_split_mapping_host(orc):
     desc.split = None
     cnt = ctypes.c_uint32()
     assert L.lib().llama_mapping_blob_count(ctypes.byref(desc), ctypes.byref(cnt)) == L.E_INVALID_ARG
+
+
+def test_one_mapping_host(orc):
+    """One (sec. 3.7): one packed record whatever the extents, offsets equal the
+    oracle's, alone and as a Split part; never a copy's destination, and a
+    One source is planned element-wise."""
+    for name in ("particle", "mixed"):
+        rec = W.RECORDS[name]
+        rg, ro = L.Record(rec), orc.Record(rec)
+        F = ro.nleaves
+        for ext in ([1], [33], [2, 7]):
+            m, o = L.Mapping(rg, "one", ext), orc.Mapping(ro, "one", ext)
+            assert m.blob_sizes() == o.blob_sizes() == [rg.info()[1]]
+            sp = (F - 1, 1, ("one", 0), ("aosoa", 8))
+            ms, os_ = L.Mapping(rg, "split", ext, split=sp), orc.Mapping(ro, "split", ext, split=sp)
+            assert ms.blob_sizes() == os_.blob_sizes()
+            n = int(np.prod(ext))
+            for i in (0, n - 1):
+                coord = list(np.unravel_index(i, ext))
+                for f in range(F):
+                    assert m.offset(coord, f) == o.blob_nr_and_offset(coord, f)
+                    assert ms.offset(coord, f) == os_.blob_nr_and_offset(coord, f)
+    rg = L.Record(W.PARTICLE)
+    one, aos = L.Mapping(rg, "one", [10]), L.Mapping(rg, "aos_packed", [10])
+    assert L.plan(one, aos)["path"] == "naive"
+    with pytest.raises(L.LlamaError) as e:
+        L.plan(one, aos, path="tile")
+    assert e.value.status == L.E_UNSUPPORTED
+    with pytest.raises(L.LlamaError) as e:
+        L.plan(aos, one)
+    assert e.value.status == L.E_UNSUPPORTED
+    # into a One part of a Split: refused before anything is enqueued
+    bufs = [ctypes.create_string_buffer(s) for s in (28 * 10, 28)]
+    blob = lambda b: L.Blob(ctypes.cast(b, ctypes.c_void_p), len(b))  # noqa: E731
+    dst = L.Mapping(rg, "split", [10], split=(0, 6, ("aos_packed", 0), ("one", 0)))
+    src_b = (L.Blob * 1)(blob(bufs[0]))
+    dst_bufs = [ctypes.create_string_buffer(s) for s in dst.blob_sizes()]
+    dst_b = (L.Blob * 2)(*[blob(b) for b in dst_bufs])
+    rc = L.lib().llama_copy(ctypes.byref(aos.desc), src_b, ctypes.byref(dst.desc), dst_b, None)
+    assert rc == L.E_UNSUPPORTED

@@ -171,3 +171,27 @@ def test_split_copy_misaligned_blobs(L, orc, offs):
     for k, (s, d) in enumerate([(("aos_packed", 0), a), (a, ("aos_packed", 0)), (a, b), (b, ("aosoa", 8))]):
         print(f"split misaligned {offs} pair {k}", flush=True)
         _run(L, orc, W.PARTICLE, s, d, [5003], seed=90 + k, src_off=src_off, dst_off=dst_off)
+
+
+ONE_CASES = [(name, dst, n) for name in ("particle", "mixed", "lbm", "listing1")
+             for dst in PLAIN for n in (1, 3001)]
+
+
+@pytest.mark.parametrize("case", ONE_CASES, ids=lambda c: f"{c[0]}-{c[1][0]}{c[1][1] or ''}-{c[2]}")
+def test_one_broadcast_copy(L, orc, case):
+    """A One source (sec. 3.7) broadcast into every plain layout."""
+    name, dst, n = case
+    print(f"one case {case}", flush=True)
+    _run(L, orc, W.RECORDS[name], ("one", 0), dst, [n], seed=n + len(name))
+
+
+@pytest.mark.parametrize("dst", [("aos_aligned", 0), ("soa_multi", 0), ("aosoa", 32),
+                                 ("split", (3, 3, ("soa_multi", 0), ("aos_aligned", 0)))],
+                         ids=["aos_aligned", "soa_multi", "aosoa32", "split"])
+def test_split_with_one_part(L, orc, dst):
+    """The particle with its mass through One and the rest as multi-blob SoA
+    (a one-level form of the nested mapping in sec. 3.7's listing)."""
+    src = ("split", (6, 1, ("one", 0), ("soa_multi", 0)))
+    for n, ext in ((1, [1]), (4099, [4099]), (391, [17, 23])):
+        print(f"split with one -> {dst} n={n}", flush=True)
+        _run(L, orc, W.PARTICLE, src, dst, ext, seed=n)
