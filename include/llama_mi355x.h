@@ -125,13 +125,16 @@ typedef enum {
  * and alignments, offsets recomputed) over the same array dimensions.  The
  * parts keep separate blobs: the selected part's blobs first, then the rest's.
  * A record coordinate selects a subtree, whose leaves are such a contiguous
- * range in depth-first order.  Both parts must be non-empty and neither may be
- * LLAMA_SPLIT.  The descriptor is read during each call only. */
-typedef struct {
+ * range in depth-first order.  Both parts must be non-empty.  A part of kind
+ * LLAMA_SPLIT is split again by split[k], whose leaf range counts the part's
+ * own leaves (the nesting of sec. 3.7's mapping listing), at most 8 levels
+ * deep.  The descriptors are read during each call only. */
+typedef struct llama_split_desc {
     uint32_t first_leaf;
     uint32_t leaf_count;
-    uint32_t kind[2];  /* llama_mapping_kind of the selected part and of the rest (not LLAMA_SPLIT) */
+    uint32_t kind[2];  /* llama_mapping_kind of the selected part and of the rest */
     uint32_t lanes[2]; /* LLAMA_AOSOA parts: lanes per block, a power of two */
+    const struct llama_split_desc* split[2]; /* LLAMA_SPLIT parts: their split; else ignored */
 } llama_split_desc;
 
 #define LLAMA_MAX_RANK 8

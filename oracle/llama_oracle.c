@@ -55,7 +55,8 @@
  *   - multi-blob SoA has one blob per leaf, in leaf order;
  *   - Split selects a contiguous range of leaves (a record coordinate
  *     selects a subtree, whose leaves are contiguous in depth-first order),
- *     the two parts keep separate blobs, and neither part is itself a Split;
+ *     the two parts keep separate blobs, and a part may itself be a Split
+ *     over its own leaves (the nesting of sec. 3.7's mapping listing);
  *   - destination bytes that no (coordinate, leaf) pair maps to (alignment gaps
  *     of aligned AoS, unused lanes of the last AoSoA block) are set to zero.
  *
@@ -92,17 +93,19 @@ typedef struct {
     const uint64_t* align; /* alignment of each leaf */
 } orc_record;
 
-typedef struct {
+typedef struct orc_mapping_s {
     int32_t kind;
     int32_t rank;
     uint64_t extents[ORC_MAX_RANK];
     uint64_t lanes; /* AoSoA only */
     /* Split only: leaves [first, first + count) form the selected part,
      * mapped by part_kind[0] (lanes part_lanes[0]); the other leaves by
-     * part_kind[1] (lanes part_lanes[1]) */
+     * part_kind[1] (lanes part_lanes[1]); a part of kind Split takes its
+     * split from part_split[k] (over the part's own leaves) */
     int32_t first, count;
     int32_t part_kind[2];
     uint64_t part_lanes[2];
+    const struct orc_mapping_s* part_split[2];
 } orc_mapping;
 
 /* ---------------------------------------------------------------------------
@@ -349,9 +352,16 @@ static int in_selection(const orc_mapping* m, int f) { return f >= m->first && f
 /* part 0 holds the selected leaves, part 1 the others, each in leaf order */
 static void split_part(const orc_mapping* m, const orc_record* r, int part, orc_part* out)
 {
-    out->m = *m;
-    out->m.kind = m->part_kind[part];
-    out->m.lanes = m->part_lanes[part];
+    if (m->part_kind[part] == ORC_SPLIT && m->part_split[part]) {
+        out->m = *m->part_split[part]; /* a nested split over the part's leaves */
+        out->m.rank = m->rank;
+        for (int d = 0; d < ORC_MAX_RANK; d++)
+            out->m.extents[d] = m->extents[d];
+    } else {
+        out->m = *m;
+        out->m.kind = m->part_kind[part];
+        out->m.lanes = m->part_lanes[part];
+    }
     int n = 0;
     for (int f = 0; f < r->nleaves && n < ORC_SPLIT_MAX_LEAVES; f++)
         if (in_selection(m, f) == (part == 0)) {
@@ -480,6 +490,8 @@ int orc_blob_nr_and_offset(const orc_mapping* m, const orc_record* r, const uint
  * Validation shared by the entry points below.
  * ------------------------------------------------------------------------- */
 
+static int valid_mapping(const orc_mapping* m, const orc_record* r);
+
 static int valid_plain(int32_t kind, uint64_t lanes)
 {
     if (kind == ORC_ONE)
@@ -493,10 +505,24 @@ static int valid_mapping(const orc_mapping* m, const orc_record* r)
 {
     if (m->rank < 1 || m->rank > ORC_MAX_RANK)
         return 0;
-    if (m->kind == ORC_SPLIT)
-        return r->nleaves <= ORC_SPLIT_MAX_LEAVES && m->first >= 0 && m->count >= 1 &&
-               m->count < r->nleaves && m->first + m->count <= r->nleaves &&
-               valid_plain(m->part_kind[0], m->part_lanes[0]) && valid_plain(m->part_kind[1], m->part_lanes[1]);
+    if (m->kind == ORC_SPLIT) {
+        if (!(r->nleaves <= ORC_SPLIT_MAX_LEAVES && m->first >= 0 && m->count >= 1 && m->count < r->nleaves &&
+              m->first + m->count <= r->nleaves))
+            return 0;
+        for (int k = 0; k < 2; k++) {
+            if (m->part_kind[k] == ORC_SPLIT) {
+                orc_part p;
+                if (!m->part_split[k] || m->part_split[k]->kind != ORC_SPLIT)
+                    return 0;
+                split_part(m, r, k, &p);
+                if (!valid_mapping(&p.m, &p.r))
+                    return 0;
+            } else if (!valid_plain(m->part_kind[k], m->part_lanes[k])) {
+                return 0;
+            }
+        }
+        return 1;
+    }
     return valid_plain(m->kind, m->lanes);
 }
 

@@ -47,7 +47,8 @@ class _Mapping(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("rank", ctypes.c_int32),
                 ("extents", ctypes.c_uint64 * MAX_RANK), ("lanes", ctypes.c_uint64),
                 ("first", ctypes.c_int32), ("count", ctypes.c_int32),
-                ("part_kind", ctypes.c_int32 * 2), ("part_lanes", ctypes.c_uint64 * 2)]
+                ("part_kind", ctypes.c_int32 * 2), ("part_lanes", ctypes.c_uint64 * 2),
+                ("part_split", ctypes.c_void_p * 2)]
 
 
 def build(force: bool = False) -> str:
@@ -176,12 +177,17 @@ def _mapping(kind: str, extents, lanes: int = 0, split=None) -> _Mapping:
         m.extents[d] = e
     m.lanes = int(lanes)
     if kind == "split":
-        first, count, (k0, l0), (k1, l1) = split
-        if "split" in (k0, k1):
-            raise ValueError("a part of a split mapping is a plain mapping")
+        first, count, p0, p1 = split
         m.first, m.count = int(first), int(count)
-        m.part_kind[0], m.part_kind[1] = KINDS[k0], KINDS[k1]
-        m.part_lanes[0], m.part_lanes[1] = int(l0), int(l1)
+        m._nested = []  # keeps nested splits alive while m is
+        for k, (pk, pa) in enumerate((p0, p1)):
+            m.part_kind[k] = KINDS[pk]
+            if pk == "split":  # pa is the nested split over the part's leaves
+                inner = _mapping("split", ext, 0, pa)
+                m._nested.append(inner)
+                m.part_split[k] = ctypes.addressof(inner)
+            else:
+                m.part_lanes[k] = int(pa)
     return m
 
 

@@ -154,9 +154,10 @@ struct Part {
     uint32_t first_blob = 0;
 };
 
-// The parts of a mapping: a Split's two (sec. 3.7: the selected leaf range,
-// then the other leaves), a plain mapping's one.
-std::vector<Part> parts_of(const llama_mapping_desc* m, const Record& r)
+// The parts of a mapping: a Split's (sec. 3.7: the selected leaf range, then
+// the other leaves; a part that is a Split again gives its own parts, in
+// order), a plain mapping's one.
+std::vector<Part> parts_of(const llama_mapping_desc* m, const Record& r, int depth = 0)
 {
     const size_t F = r.leaves.size();
     std::vector<Part> parts;
@@ -172,26 +173,42 @@ std::vector<Part> parts_of(const llama_mapping_desc* m, const Record& r)
     const llama_split_desc* sd = m->split;
     if (!sd)
         fail(LLAMA_E_INVALID_ARG, "LLAMA_SPLIT mapping without a split descriptor");
+    if (depth >= 8)
+        fail(LLAMA_E_INVALID_ARG, "split: nested more than 8 levels deep");
     if (sd->leaf_count == 0 || sd->leaf_count >= F || sd->first_leaf > F - sd->leaf_count)
         fail(LLAMA_E_INVALID_ARG, "split: the selected leaves [" + std::to_string(sd->first_leaf) + ", +" +
                                       std::to_string(sd->leaf_count) + ") must be a non-empty proper range of the " +
                                       std::to_string(F) + " leaves");
     uint32_t first_blob = 0;
     for (int k = 0; k < 2; k++) {
-        if (sd->kind[k] == LLAMA_SPLIT || sd->kind[k] > LLAMA_ONE)
-            fail(LLAMA_E_INVALID_ARG, "split: part " + std::to_string(k) + " must be a plain mapping kind");
-        Part p;
+        if (sd->kind[k] > LLAMA_ONE)
+            fail(LLAMA_E_INVALID_ARG, "split: part " + std::to_string(k) + " has no valid mapping kind");
+        std::vector<uint32_t> leaves;
         for (size_t f = 0; f < F; f++) {
             const bool sel = f >= sd->first_leaf && f < size_t(sd->first_leaf) + sd->leaf_count;
             if (sel == (k == 0))
-                p.leaves.push_back(uint32_t(f));
+                leaves.push_back(uint32_t(f));
         }
-        p.sub = sub_record(r, p.leaves);
+        const Record sub = sub_record(r, leaves);
         llama_mapping_desc inner = *m;
         inner.kind = sd->kind[k];
         inner.lanes = sd->lanes[k];
         inner.reserved = 0;
-        inner.split = nullptr;
+        inner.split = sd->kind[k] == LLAMA_SPLIT ? sd->split[k] : nullptr;
+        if (sd->kind[k] == LLAMA_SPLIT) {
+            // the inner split's parts, their leaves renumbered in this record
+            for (Part& q : parts_of(&inner, sub, depth + 1)) {
+                for (uint32_t& f : q.leaves)
+                    f = leaves[f];
+                q.first_blob += first_blob;
+                parts.push_back(std::move(q));
+            }
+            first_blob = parts.back().first_blob + uint32_t(parts.back().side.blob_size.size());
+            continue;
+        }
+        Part p;
+        p.leaves = leaves;
+        p.sub = sub;
         p.side = make_side(&inner, p.sub);
         p.first_blob = first_blob;
         first_blob += uint32_t(p.side.blob_size.size());

@@ -53,8 +53,28 @@ class RecordDesc(ctypes.Structure):
 
 
 class SplitDesc(ctypes.Structure):
-    _fields_ = [("first_leaf", ctypes.c_uint32), ("leaf_count", ctypes.c_uint32),
-                ("kind", ctypes.c_uint32 * 2), ("lanes", ctypes.c_uint32 * 2)]
+    pass
+
+
+SplitDesc._fields_ = [("first_leaf", ctypes.c_uint32), ("leaf_count", ctypes.c_uint32),
+                      ("kind", ctypes.c_uint32 * 2), ("lanes", ctypes.c_uint32 * 2),
+                      ("split", ctypes.POINTER(SplitDesc) * 2)]
+
+
+def _split_desc(spec, keep):
+    """A SplitDesc for (first, count, part, part); a part is (kind, lanes) or
+    ("split", spec) for a nested split.  Every descriptor made goes to `keep`."""
+    first, count, p0, p1 = spec
+    sd = SplitDesc()
+    sd.first_leaf, sd.leaf_count = int(first), int(count)
+    for k, (kind, arg) in enumerate((p0, p1)):
+        sd.kind[k] = KINDS[kind] if isinstance(kind, str) else int(kind)
+        if sd.kind[k] == SPLIT:
+            sd.split[k] = ctypes.pointer(_split_desc(arg, keep))
+        else:
+            sd.lanes[k] = int(arg)
+    keep.append(sd)
+    return sd
 
 
 class MappingDesc(ctypes.Structure):
@@ -225,9 +245,10 @@ class Record:
 
 class Mapping:
     """A mapping of `record` over `extents`.  kind "split" takes
-    split=(first_leaf, leaf_count, (kind, lanes), (kind, lanes)): the selected
-    leaf range through the first plain mapping, the other leaves through the
-    second (sec. 3.7 Split)."""
+    split=(first_leaf, leaf_count, part, part): the selected leaf range through
+    the first part's mapping, the other leaves through the second's (sec. 3.7
+    Split); a part is (kind, lanes), or ("split", (first, count, part, part))
+    to split that part's leaves again."""
 
     def __init__(self, record: Record, kind: str, extents, lanes: int = 0, split=None):
         ext = [int(e) for e in (extents if isinstance(extents, (list, tuple)) else [extents])]
@@ -246,14 +267,8 @@ class Mapping:
         self.desc.lanes = self.lanes
         self.desc.reserved = 0
         if split is not None:
-            first, count, (k0, l0), (k1, l1) = split
-            sd = SplitDesc()
-            sd.first_leaf, sd.leaf_count = int(first), int(count)
-            sd.kind[0] = KINDS[k0] if isinstance(k0, str) else int(k0)
-            sd.kind[1] = KINDS[k1] if isinstance(k1, str) else int(k1)
-            sd.lanes[0], sd.lanes[1] = int(l0), int(l1)
-            self._split = sd  # kept alive with the descriptor that points at it
-            self.desc.split = ctypes.pointer(sd)
+            self._split = []  # the descriptors, kept alive with the one that points at them
+            self.desc.split = ctypes.pointer(_split_desc(split, self._split))
 
     @property
     def blob_count(self) -> int:

@@ -438,7 +438,8 @@ def test_split_mapping_host(orc):
                             assert m.offset(coord, f) == o.blob_nr_and_offset(coord, f), (name, sp, ext, i, f)
     rg = L.Record(W.PARTICLE)
     ok = ("soa_multi", 0), ("aos_packed", 0)
-    for bad in [(0, 7, *ok), (5, 3, *ok), (0, 0, *ok), (1, 2, ("split", 0), ok[1]), (1, 2, ("aosoa", 3), ok[1])]:
+    for bad in [(0, 7, *ok), (5, 3, *ok), (0, 0, *ok), (1, 2, (7, 0), ok[1]), (1, 2, ("aosoa", 3), ok[1]),
+                (1, 2, ("split", (0, 2, *ok)), ok[1])]:
         with pytest.raises(L.LlamaError) as e:
             L.Mapping(rg, "split", [10], split=bad).blob_sizes()
         assert e.value.status == L.E_INVALID_ARG
@@ -493,3 +494,35 @@ def test_one_mapping_host(orc):
     dst_b = (L.Blob * 2)(*[blob(b) for b in dst_bufs])
     rc = L.lib().llama_copy(ctypes.byref(aos.desc), src_b, ctypes.byref(dst.desc), dst_b, None)
     assert rc == L.E_UNSUPPORTED
+
+
+def test_nested_split_descriptors(orc):
+    """Nested splits (sec. 3.7's mapping listing): offsets and blob sizes equal
+    the oracle's; a Split part without its descriptor and a descriptor that
+    contains itself are rejected."""
+    rg, ro = L.Record(W.PARTICLE), orc.Record(W.PARTICLE)
+    specs = [(3, 3, ("soa_multi", 0), ("split", (3, 1, ("one", 0), ("aos_aligned", 0)))),
+             (0, 3, ("split", (1, 1, ("aosoa", 8), ("soa_single", 0))), ("split", (0, 2, ("aos_packed", 0), ("aosoa", 4)))),
+             (6, 1, ("aos_packed", 0), ("split", (2, 3, ("soa_multi", 0),
+                                                  ("split", (0, 1, ("aosoa", 32), ("aos_aligned", 0))))))]
+    for sp in specs:
+        for ext in ([1], [45], [3, 5]):
+            m, o = L.Mapping(rg, "split", ext, split=sp), orc.Mapping(ro, "split", ext, split=sp)
+            assert m.blob_sizes() == o.blob_sizes()
+            n = int(np.prod(ext))
+            for i in (0, n - 1):
+                coord = list(np.unravel_index(i, ext))
+                for f in range(7):
+                    assert m.offset(coord, f) == o.blob_nr_and_offset(coord, f), (sp, ext, i, f)
+    m = L.Mapping(rg, "split", [10], split=(0, 3, ("soa_multi", 0), ("split", (0, 2, ("aos_packed", 0), ("one", 0)))))
+    inner = ctypes.cast(m.desc.split.contents.split[1], ctypes.c_void_p).value  # the address, not a view of the slot
+    m.desc.split.contents.split[1] = ctypes.POINTER(L.SplitDesc)()  # a Split part with no descriptor
+    with pytest.raises(L.LlamaError) as e:
+        m.blob_sizes()
+    assert e.value.status == L.E_INVALID_ARG
+    m.desc.split.contents.split[1] = m.desc.split  # contains itself
+    with pytest.raises(L.LlamaError) as e:
+        m.blob_sizes()
+    assert e.value.status == L.E_INVALID_ARG
+    m.desc.split.contents.split[1] = ctypes.cast(inner, ctypes.POINTER(L.SplitDesc))
+    assert m.blob_sizes() == [40, 40, 40, 80, 8]  # pos as SoA; vel.x, vel.y packed; vel.z, mass in One

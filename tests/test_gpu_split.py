@@ -195,3 +195,23 @@ def test_split_with_one_part(L, orc, dst):
     for n, ext in ((1, [1]), (4099, [4099]), (391, [17, 23])):
         print(f"split with one -> {dst} n={n}", flush=True)
         _run(L, orc, W.PARTICLE, src, dst, ext, seed=n)
+
+
+# the nesting of sec. 3.7's mapping listing: velocities as multi-blob SoA, the
+# rest split again into mass through One and positions as aligned AoS
+LISTING_C = ("split", (3, 3, ("soa_multi", 0), ("split", (3, 1, ("one", 0), ("aos_aligned", 0)))))
+NESTED_A = ("split", (0, 3, ("split", (1, 1, ("aosoa", 8), ("soa_single", 0))),
+                      ("split", (0, 2, ("aos_packed", 0), ("aosoa", 4)))))
+NESTED_B = ("split", (6, 1, ("aos_packed", 0), ("split", (2, 3, ("soa_multi", 0),
+                                                         ("split", (0, 1, ("aosoa", 32), ("aos_aligned", 0)))))))
+NESTED_PAIRS = [(LISTING_C, ("aos_packed", 0)), (LISTING_C, ("soa_multi", 0)), (LISTING_C, ("aosoa", 32)),
+                (LISTING_C, NESTED_A), (("aos_aligned", 0), NESTED_A), (NESTED_A, NESTED_B), (NESTED_B, NESTED_A),
+                (NESTED_B, ("aosoa", 8)), (("soa_single", 0), NESTED_B)]
+
+
+@pytest.mark.parametrize("k", range(len(NESTED_PAIRS)))
+def test_nested_split_copy(L, orc, k):
+    src, dst = NESTED_PAIRS[k]
+    for ext in ([1], [2053], [9, 31]):
+        print(f"nested split pair {k} ext {ext}", flush=True)
+        _run(L, orc, W.PARTICLE, src, dst, ext, seed=k * 10 + len(ext))

@@ -579,3 +579,28 @@ def test_split_with_one_part_reads_a_shared_value(orc):
     for f in range(6):
         assert np.array_equal(out[f], src[1 + f])
     assert np.array_equal(out[6], np.tile(src[0], n))
+
+
+@pytest.mark.parametrize("n", [1, 9, 70])
+def test_nested_split_equals_serialised_parts(orc, n):
+    """A Split whose rest is itself a Split (the nesting in sec. 3.7's mapping
+    listing): the blobs are the prose serialiser's layouts of the three parts,
+    in order: the selected leaves, then the inner split's selected leaves,
+    then the remaining ones."""
+    types = W.leaf_types(W.PARTICLE)
+    vals = _unique_leaf_values(types, n, 77 + n)
+    r = orc.Record(W.PARTICLE)
+    for inner0, inner1 in ((("aosoa", 4), ("aos_aligned", 0)), (("soa_single", 0), ("aos_packed", 0))):
+        m = orc.Mapping(r, "split", [n], split=(3, 3, ("soa_multi", 0), ("split", (3, 1, inner0, inner1))))
+        got = orc.copy(orc.Mapping(r, "soa_multi", [n]), _soa_multi_blobs(vals), m)
+        want = (_serialise(types[3:6], vals[3:6], "soa_multi", n, 0) +
+                _serialise(types[6:7], vals[6:7], inner0[0], n, inner0[1]) +
+                _serialise(types[0:3], vals[0:3], inner1[0], n, inner1[1]))
+        assert [bytes(b) for b in got] == want, (inner0, inner1)
+    # the listing's own shape: velocities as SoA, mass through One, positions as aligned AoS
+    c = orc.Mapping(r, "split", [n], split=(3, 3, ("soa_multi", 0), ("split", (3, 1, ("one", 0), ("aos_aligned", 0)))))
+    assert c.blob_sizes() == [4 * n] * 3 + [4, 12 * n]
+    src = [np.random.default_rng(n).integers(0, 256, s, dtype=np.uint8) for s in c.blob_sizes()]
+    aos = orc.copy(c, src, orc.Mapping(r, "aos_packed", [n]))[0].reshape(n, 28)
+    assert (aos[:, 24:28] == src[3]).all()
+    assert np.array_equal(aos[:, 0:12].reshape(-1), src[4])
