@@ -6,6 +6,7 @@ import ctypes
 import os
 import random
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -526,3 +527,24 @@ def test_nested_split_descriptors(orc):
     assert e.value.status == L.E_INVALID_ARG
     m.desc.split.contents.split[1] = ctypes.cast(inner, ctypes.POINTER(L.SplitDesc))
     assert m.blob_sizes() == [40, 40, 40, 80, 8]  # pos as SoA; vel.x, vel.y packed; vel.z, mass in One
+
+
+def test_header_is_c99_and_matches_the_binding(tmp_path):
+    """The header compiles as C99, and the binding's structures have the C
+    layout: sizes and the offsets of the fields added for Split."""
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    src = tmp_path / "abi.c"
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "llama_mi355x.h"\n'
+        "int main(void) {\n"
+        '  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(llama_mapping_desc), offsetof(llama_mapping_desc, split),\n'
+        "         sizeof(llama_split_desc), offsetof(llama_split_desc, split), sizeof(llama_copy_options),\n"
+        "         sizeof(llama_plan_info), sizeof(llama_copy_item));\n"
+        "  return 0;\n}\n")
+    exe = tmp_path / "abi"
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-I", inc, str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(L.MappingDesc), L.MappingDesc.split.offset, ctypes.sizeof(L.SplitDesc),
+            L.SplitDesc.split.offset, ctypes.sizeof(L.CopyOptions), ctypes.sizeof(L.PlanInfo),
+            ctypes.sizeof(L.CopyItem)]
+    assert got == want
