@@ -188,11 +188,12 @@ typedef struct {
  *    leaves, in order on `stream`, each writing only its own leaves and the
  *    padding of its destination part.  A pair that writes part of the records
  *    of a record-major destination part (AoS, AoSoA) takes the element-wise
- *    path; every other pair is planned like a plain copy.  Batches take a
- *    Split item as its pairs, side by side, unless one of them writes part of
- *    the records of a record-major destination part (LLAMA_E_UNSUPPORTED);
- *    servers, plans and autotuning take plain mappings only
- *    (LLAMA_E_UNSUPPORTED). */
+ *    path; every other pair is planned like a plain copy.  Batches and the
+ *    batched server policy take a Split item as its pairs, side by side,
+ *    unless one of them writes part of the records of a record-major
+ *    destination part or reads a One part (LLAMA_E_UNSUPPORTED); the other
+ *    server policies run its pairs in order.  Plans, autotuning and servers
+ *    with an executor take plain mappings only (LLAMA_E_UNSUPPORTED). */
 int llama_copy(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
                const llama_blob* dst_blobs, void* stream);
 

@@ -89,6 +89,7 @@ std::unique_ptr<OwnedItem> own_item(const llama_copy_item* it, const Request& rq
 struct Pending {
     uint64_t ticket;
     Request rq;
+    std::vector<SubCopy> parts; // a request with a Split side: its part copies, else empty
     uint64_t bytes;
     std::vector<Range> ranges;
     Clock::time_point arrival;
@@ -208,12 +209,19 @@ void Server::launch_slot(Slot& s, std::vector<Pending>& group)
     }
     if (cfg.policy == LLAMA_SERVE_BATCHED && group.size() == 1) {
         // a group of one is the request's own launch (its tuned plan, no
-        // work table to upload)
-        launch(make_plan(group[0].rq, nullptr), s.stream);
+        // work table to upload); a Split request's part copies in order
+        if (group[0].parts.empty())
+            launch(make_plan(group[0].rq, nullptr), s.stream);
+        for (const SubCopy& c : group[0].parts)
+            launch(make_plan(c.rq, nullptr), s.stream);
     } else if (cfg.policy == LLAMA_SERVE_BATCHED) {
         BatchTable t;
-        for (Pending& p : group)
-            t.add(p.rq, cfg.threads, 0);
+        for (Pending& p : group) {
+            if (p.parts.empty())
+                t.add(p.rq, cfg.threads, 0);
+            for (const SubCopy& c : p.parts) // disjoint bytes: side by side
+                t.add(c.rq, cfg.threads, 0);
+        }
         if (t.units > 0) {
             const size_t bytes = t.bytes();
             ensure_capacity(s, bytes);
@@ -226,8 +234,13 @@ void Server::launch_slot(Slot& s, std::vector<Pending>& group)
     } else {
         llama_copy_options o{cfg.policy == LLAMA_SERVE_NAIVE ? uint32_t(LLAMA_PATH_NAIVE) : uint32_t(LLAMA_PATH_AUTO),
                              0, 0, 0, 0};
-        for (Pending& p : group)
-            launch(make_plan(p.rq, &o), s.stream);
+        llama_copy_options naive{uint32_t(LLAMA_PATH_NAIVE), 0, 0, 0, 0};
+        for (Pending& p : group) {
+            if (p.parts.empty())
+                launch(make_plan(p.rq, &o), s.stream);
+            for (const SubCopy& c : p.parts)
+                launch(make_plan(c.rq, c.naive ? &naive : &o), s.stream);
+        }
     }
     check_hip(hipEventRecord(s.done, s.stream), "hipEventRecord");
 }
@@ -496,7 +509,13 @@ uint64_t server_submit(Server* s, const llama_copy_item* item)
     if (!item)
         fail(LLAMA_E_INVALID_ARG, "item is NULL");
     Pending p;
-    p.rq = make_request(item->src, item->src_blobs, item->dst, item->dst_blobs, true);
+    p.rq = make_request(item->src, item->src_blobs, item->dst, item->dst_blobs, true, true);
+    const bool split = item->src->kind == LLAMA_SPLIT || item->dst->kind == LLAMA_SPLIT;
+    if (split) {
+        if (s->has_exec)
+            fail(LLAMA_E_UNSUPPORTED, "a server with an executor takes plain mappings only");
+        p.parts = split_copies(item->src, item->dst, p.rq);
+    }
     if (s->has_exec) {
         p.owned = own_item(item, p.rq);
     } else {
@@ -508,8 +527,11 @@ uint64_t server_submit(Server* s, const llama_copy_item* item)
     }
     if (!s->has_exec && s->cfg.policy != LLAMA_SERVE_NAIVE) {
         llama_copy_options o{LLAMA_PATH_AUTO, 0, s->cfg.threads, 0, 0};
-        if (s->cfg.policy == LLAMA_SERVE_BATCHED && make_plan(p.rq, &o).path == LLAMA_PATH_NAIVE)
+        if (s->cfg.policy == LLAMA_SERVE_BATCHED && !split && make_plan(p.rq, &o).path == LLAMA_PATH_NAIVE)
             fail(LLAMA_E_UNSUPPORTED, "the record does not fit the tiled kernel; copy it with llama_copy");
+        for (const SubCopy& c : p.parts)
+            if (s->cfg.policy == LLAMA_SERVE_BATCHED && (c.naive || make_plan(c.rq, &o).path == LLAMA_PATH_NAIVE))
+                fail(LLAMA_E_UNSUPPORTED, "a part copy of this Split request runs element-wise; copy it with llama_copy");
     }
     p.bytes = 0;
     for (size_t b = 0; b < p.rq.src_ptr.size(); b++) {

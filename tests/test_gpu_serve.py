@@ -151,3 +151,51 @@ def test_budget_and_dependencies(L, orc):
     torch.cuda.synchronize()
     assert torch.equal(z[0], want[0])
     srv.close()
+
+
+def _smap(mod, rec, layout, n):
+    if layout[0] == "split":
+        return mod.Mapping(rec, "split", [n], split=layout[1])
+    return mod.Mapping(rec, layout[0], [n], layout[1])
+
+
+@pytest.mark.parametrize("policy", [0, 1, 2])
+def test_split_requests(L, orc, policy):
+    """Requests with a Split side (sec. 3.7) among plain ones: their part
+    copies go into the group's launch side by side (batched), or run in order
+    (per request, element-wise); all equal the oracle.  The batched server
+    refuses a request whose part copies must run in order."""
+    s1 = ("split", (0, 3, ("aosoa", 32), ("soa_multi", 0)))
+    s2 = ("split", (3, 3, ("soa_multi", 0), ("aos_aligned", 0)))
+    s3 = ("split", (0, 3, ("aos_packed", 0), ("aosoa", 8)))
+    pairs = [(("aos_packed", 0), s1), (s1, ("soa_multi", 0)), (s1, s3), (s3, s1), (("aosoa", 64), s2),
+             (("aos_aligned", 0), ("soa_single", 0))]
+    if policy != 0:  # part copies in order: into AoS from two parts, and a One source
+        pairs += [(s1, ("aos_packed", 0)), (s2, ("aosoa", 32)),
+                  (("split", (6, 1, ("one", 0), ("soa_multi", 0))), ("aos_aligned", 0))]
+    g = random.Random(60 + policy)
+    ro, rg = orc.Record(W.PARTICLE), L.Record(W.PARTICLE)
+    reqs = []
+    for k in range(3 * len(pairs)):
+        a, b = pairs[k % len(pairs)]
+        n = g.choice([1, 500, 20011])
+        ms_o, md_o = _smap(orc, ro, a, n), _smap(orc, ro, b, n)
+        src = [W.random_bytes(x, 900 + k * 7 + j) for j, x in enumerate(ms_o.blob_sizes())]
+        ms, md = _smap(L, rg, a, n), _smap(L, rg, b, n)
+        reqs.append({"src": ms, "sd": [torch.from_numpy(x).cuda() for x in src], "dst": md,
+                     "dd": md.alloc(fill=0xCD), "want": orc.copy(ms_o, src, md_o)})
+    srv = L.Server(1 << 33, policy=policy)
+    torch.cuda.synchronize()
+    print(f"split requests, policy {policy}: {len(reqs)}", flush=True)
+    tickets = [srv.submit(r["src"], r["sd"], r["dst"], r["dd"]) for r in reqs]
+    for t in tickets:
+        assert srv.wait(t)[0] == L.OK
+    if policy == 0:
+        n = 100
+        ms, md = _smap(L, rg, s1, n), L.Mapping(rg, "aos_packed", [n])
+        with pytest.raises(L.LlamaError) as e:
+            srv.submit(ms, ms.alloc(), md, md.alloc())
+        assert e.value.status == L.E_UNSUPPORTED
+    srv.close()
+    for r in reqs:
+        check(r)
