@@ -65,6 +65,7 @@
  */
 #include <stdint.h>
 #include <stddef.h>
+#include <stdlib.h>
 #include <string.h>
 
 #define ORC_MAX_RANK 8
@@ -583,6 +584,73 @@ int orc_copy_keep(const orc_record* r, const orc_mapping* src, uint8_t* const* s
             memcpy(dst_blobs[bd] + od, src_blobs[bs] + os, (size_t)r->size[f]);
         }
     } while (next_coord(src, coord));
+    return ORC_OK;
+}
+
+/* The copy between views whose records differ (sec. 3.9: a field missing on
+ * one side).  Destination leaf k takes source leaf from[k], whose size must be
+ * the same; a leaf with from[k] < 0 keeps all its bytes, unused AoSoA lanes
+ * included.  The destination's padding (alignment gaps, and the unused AoSoA
+ * lanes of the leaves that take a value) becomes zero, or keeps its bytes
+ * with `keep`.  Both mappings are plain (not Split); the source may be One. */
+int orc_copy_leaves(const orc_record* rs, const orc_mapping* src, uint8_t* const* src_blobs, const orc_record* rd,
+                    const orc_mapping* dst, uint8_t* const* dst_blobs, const int32_t* from, int keep)
+{
+    if (!valid_mapping(src, rs) || !valid_mapping(dst, rd) || !same_extents(src, dst) || src->kind == ORC_SPLIT ||
+        dst->kind == ORC_SPLIT || dst->kind == ORC_ONE)
+        return ORC_E_ARG;
+    for (int k = 0; k < rd->nleaves; k++)
+        if (from[k] >= rs->nleaves || (from[k] >= 0 && rs->size[from[k]] != rd->size[k]))
+            return ORC_E_ARG;
+    uint64_t n = orc_record_count(dst);
+    if (!keep) {
+        /* mark every byte a leaf owns: values of all records, and for the
+         * leaves that keep their bytes, their unused AoSoA lanes too */
+        int nb = orc_blob_count(dst, rd);
+        uint8_t* owned[ORC_SPLIT_MAX_LEAVES];
+        if (nb > ORC_SPLIT_MAX_LEAVES)
+            return ORC_E_ARG;
+        for (int b = 0; b < nb; b++)
+            owned[b] = (uint8_t*)calloc((size_t)orc_blob_size(dst, rd, b) + 1, 1);
+        uint64_t coord[ORC_MAX_RANK] = {0};
+        if (n > 0)
+            do {
+                for (int k = 0; k < rd->nleaves; k++) {
+                    uint64_t b, o;
+                    orc_blob_nr_and_offset(dst, rd, coord, k, &b, &o);
+                    memset(owned[b] + o, 1, (size_t)rd->size[k]);
+                }
+            } while (next_coord(dst, coord));
+        if (dst->kind == ORC_AOSOA) {
+            uint64_t L = dst->lanes;
+            for (uint64_t i = n; i < (n + L - 1) / L * L; i++)
+                for (int k = 0; k < rd->nleaves; k++)
+                    if (from[k] < 0)
+                        memset(owned[0] + (i / L) * (L * orc_packed_size(rd)) + L * orc_packed_offset(rd, k) +
+                                   (i % L) * rd->size[k],
+                               1, (size_t)rd->size[k]);
+        }
+        for (int b = 0; b < nb; b++) {
+            uint64_t sz = orc_blob_size(dst, rd, b);
+            for (uint64_t o = 0; o < sz; o++)
+                if (!owned[b][o])
+                    dst_blobs[b][o] = 0;
+            free(owned[b]);
+        }
+    }
+    if (n == 0)
+        return ORC_OK;
+    uint64_t coord[ORC_MAX_RANK] = {0};
+    do {
+        for (int k = 0; k < rd->nleaves; k++) {
+            if (from[k] < 0)
+                continue;
+            uint64_t bs, os, bd, od;
+            orc_blob_nr_and_offset(src, rs, coord, from[k], &bs, &os);
+            orc_blob_nr_and_offset(dst, rd, coord, k, &bd, &od);
+            memcpy(dst_blobs[bd] + od, src_blobs[bs] + os, (size_t)rd->size[k]);
+        }
+    } while (next_coord(dst, coord));
     return ORC_OK;
 }
 

@@ -266,6 +266,19 @@ def copy(src: Mapping, src_blobs, dst: Mapping, dst_blobs=None, keep_padding=Fal
     return dst_blobs
 
 
+def copy_leaves(src: Mapping, src_blobs, dst: Mapping, dst_blobs, source_leaf, keep_padding=False):
+    """The copy between differing records: destination leaf k takes source
+    leaf source_leaf[k] (None: the leaf keeps its bytes).  Updates and returns
+    `dst_blobs`."""
+    frm = (ctypes.c_int32 * max(dst.record.nleaves, 1))(*[-1 if x is None else int(x) for x in source_leaf])
+    rc = lib().orc_copy_leaves(ctypes.byref(src.record.c), ctypes.byref(src.c), _ptrs(src_blobs),
+                               ctypes.byref(dst.record.c), ctypes.byref(dst.c), _ptrs(dst_blobs), frm,
+                               1 if keep_padding else 0)
+    if rc != 0:
+        raise ValueError(f"oracle copy_leaves failed ({rc})")
+    return dst_blobs
+
+
 def write_counts(m: Mapping):
     """Per-byte count of how many (coordinate, leaf) values map to each byte."""
     counts = [np.zeros(s, dtype=np.uint32) for s in m.blob_sizes()]

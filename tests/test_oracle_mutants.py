@@ -39,6 +39,10 @@ MUTANTS = {
                                  "return f >= m->first && f <= m->first + m->count;"),
     "one_offset_uses_index": ("        (void)i;\n        *blob = 0;\n        *offset = orc_packed_offset(r, f);",
                               "        *blob = 0;\n        *offset = i * orc_packed_size(r) + orc_packed_offset(r, f);"),
+    "copy_leaves_zeroes_kept_lanes": ("                    if (from[k] < 0)\n                        memset(owned[0]",
+                                      "                    if (from[k] < -1)\n                        memset(owned[0]"),
+    "copy_leaves_reads_own_index": ("orc_blob_nr_and_offset(src, rs, coord, from[k], &bs, &os);",
+                                    "orc_blob_nr_and_offset(src, rs, coord, k, &bs, &os);"),
     "static_array_one_short": ("for (uint64_t c = 1; c < count; c++)", "for (uint64_t c = 2; c < count; c++)"),
     "aos_aligned_uses_packed_stride": ("*offset = i * orc_aligned_size(r) + orc_aligned_offset(r, f);",
                                        "*offset = i * orc_packed_size(r) + orc_aligned_offset(r, f);"),

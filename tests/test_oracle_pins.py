@@ -604,3 +604,64 @@ def test_nested_split_equals_serialised_parts(orc, n):
     aos = orc.copy(c, src, orc.Mapping(r, "aos_packed", [n]))[0].reshape(n, 28)
     assert (aos[:, 24:28] == src[3]).all()
     assert np.array_equal(aos[:, 0:12].reshape(-1), src[4])
+
+
+# --------------------------------------------------------------------------
+# copies between differing records (sec. 3.9: a field missing on one side)
+# --------------------------------------------------------------------------
+
+PARTICLE_NO_MASS = [["f32", "f32", "f32"], ["f32", "f32", "f32"]]
+
+
+@pytest.mark.parametrize("kind", _layouts(lanes=(4, 32)))
+@pytest.mark.parametrize("n", [1, 45])
+def test_copy_leaves_field_missing_on_either_side(orc, kind, n):
+    """Into a record without mass: the serialiser's layout of the six common
+    leaves.  Into a record with mass from one without: the mass keeps its
+    bytes (unused AoSoA lanes included), everything else as the serialiser."""
+    types7, types6 = W.leaf_types(W.PARTICLE), W.leaf_types(PARTICLE_NO_MASS)
+    vals = _unique_leaf_values(types7, n, 5 + n)
+    r7, r6 = orc.Record(W.PARTICLE), orc.Record(PARTICLE_NO_MASS)
+    src7 = orc.copy(orc.Mapping(r7, "soa_multi", [n]), _soa_multi_blobs(vals), orc.Mapping(r7, "aos_packed", [n]))
+    m6 = orc.Mapping(r6, kind[0], [n], kind[1])
+    got = orc.copy_leaves(orc.Mapping(r7, "aos_packed", [n]), src7, m6, m6.alloc(fill=0xEE), list(range(6)))
+    assert [bytes(b) for b in got] == _serialise(types6, vals[:6], kind[0], n, kind[1])
+    # the other way: mass has no source and keeps its canary, lanes past N included
+    src6 = orc.copy(orc.Mapping(r6, "soa_multi", [n]), _soa_multi_blobs(vals[:6]), orc.Mapping(r6, "aos_packed", [n]))
+    m7 = orc.Mapping(r7, kind[0], [n], kind[1])
+    got = orc.copy_leaves(orc.Mapping(r6, "aos_packed", [n]), src6, m7, m7.alloc(fill=0xEE),
+                          list(range(6)) + [None])
+    canary = [np.frombuffer(bytes([0xEE]) * 4 * n, np.float32)]
+    full = _serialise(types7, vals[:6] + canary, kind[0], n, kind[1])
+    if kind[0] == "aosoa":  # unused lanes of the mass chunk keep the canary too
+        L_, S = kind[1], 28
+        blocks = -(-n // L_)
+        want = bytearray(full[0])
+        for i in range(n, blocks * L_):
+            o = (i // L_) * L_ * S + L_ * 24 + (i % L_) * 4
+            want[o:o + 4] = b"\xee" * 4
+        full = [bytes(want)]
+    assert [bytes(b) for b in got] == full
+
+
+def test_copy_leaves_identity_and_permutation(orc):
+    """The identity leaf map is the plain copy; a map that swaps two
+    equal-size leaves equals the copy of the swapped values."""
+    types = W.leaf_types(W.MIXED)
+    n = 77
+    vals = _unique_leaf_values(types, n, 8)
+    r = orc.Record(W.MIXED)
+    mb = orc.Mapping(r, "soa_multi", [n])
+    for kind in _layouts(lanes=(8,)):
+        m = orc.Mapping(r, kind[0], [n], kind[1])
+        plain = orc.copy(mb, _soa_multi_blobs(vals), m)
+        got = orc.copy_leaves(mb, _soa_multi_blobs(vals), m, m.alloc(fill=0x5A), list(range(len(types))))
+        assert all(np.array_equal(a, b) for a, b in zip(plain, got)), kind
+        # leaves 3 and 4 are both f32: swap them
+        perm = list(range(len(types)))
+        perm[3], perm[4] = 4, 3
+        sw = list(vals)
+        sw[3], sw[4] = vals[4], vals[3]
+        got = orc.copy_leaves(mb, _soa_multi_blobs(vals), m, m.alloc(fill=0x5A), perm)
+        want = orc.copy(mb, _soa_multi_blobs(sw), m)
+        assert all(np.array_equal(a, b) for a, b in zip(want, got)), kind
