@@ -248,6 +248,28 @@ typedef struct {
 int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
                   const llama_blob* dst_blobs, const llama_copy_options* options, void* stream);
 
+/* Marks a destination leaf that takes no source leaf (llama_copy_leaves). */
+#define LLAMA_NO_LEAF 0xFFFFFFFFu
+
+/* Copies between views whose records differ (sec. 3.9: a field missing on one
+ * side).  Destination leaf k takes source leaf src_leaf[k] (src_leaf holds one
+ * entry per flattened destination leaf), which must have the same size; a
+ * destination leaf with LLAMA_NO_LEAF keeps all its bytes, unused AoSoA lanes
+ * included.  The destination's padding (alignment gaps, and the unused AoSoA
+ * lanes of the leaves that take a value) becomes zero, or keeps its bytes with
+ * LLAMA_COPY_PRESERVE_PADDING.  A source leaf may feed several destination
+ * leaves.  Mappings: not Split; the source may be One, the destination not
+ * (LLAMA_E_UNSUPPORTED).  Errors: LLAMA_E_INVALID_ARG for a leaf index out of
+ * range or no destination leaf with a source, LLAMA_E_RECORD_MISMATCH for
+ * leaves of different sizes, and llama_copy's others.  When some destination
+ * leaves keep their bytes, a record-major destination is written by a
+ * direct-store tile plan if one applies, else element-wise; options as for
+ * llama_copy_ex. */
+int llama_copy_leaves(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                      const llama_blob* dst_blobs, const uint32_t* src_leaf, const llama_copy_options* options,
+                      void* stream);
+
+
 /* How a TILE copy moves one tile (llama_plan_info.tile_mode). */
 typedef enum {
     LLAMA_TILE_STAGED = 1,       /* source span(s) -> LDS -> destination region in LDS -> destination span(s) */

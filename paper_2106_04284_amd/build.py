@@ -26,7 +26,7 @@ CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-I" + INCLUDE, "
              "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__"]
 
 HIP_SOURCES = ["kernels.hip"]
-CXX_SOURCES = ["core.cpp", "capi.cpp", "batch.cpp", "tune.cpp", "serve.cpp"]
+CXX_SOURCES = ["core.cpp", "capi.cpp", "batch.cpp", "tune.cpp", "serve.cpp", "leaves.cpp"]
 
 
 def _run(cmd):

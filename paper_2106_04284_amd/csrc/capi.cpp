@@ -224,6 +224,13 @@ int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, co
     });
 }
 
+int llama_copy_leaves(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                      const llama_blob* dst_blobs, const uint32_t* src_leaf, const llama_copy_options* options,
+                      void* stream)
+{
+    return guarded([&] { copy_leaves(src, src_blobs, dst, dst_blobs, src_leaf, options, stream); });
+}
+
 int llama_copy(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
                const llama_blob* dst_blobs, void* stream)
 {

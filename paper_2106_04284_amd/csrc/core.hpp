@@ -104,6 +104,12 @@ struct SubCopy {
 // padding of a destination part is written by the first copy into it.
 std::vector<SubCopy> split_copies(const llama_mapping_desc* src, const llama_mapping_desc* dst, const Request& whole);
 
+// llama_copy_leaves (leaves.cpp): validates, plans and enqueues the copy
+// between differing records.
+void copy_leaves(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                 const llama_blob* dst_blobs, const uint32_t* src_leaf, const llama_copy_options* options,
+                 void* stream);
+
 // A complete launch plan for one copy.
 struct Plan {
     uint32_t path = LLAMA_PATH_EMPTY;

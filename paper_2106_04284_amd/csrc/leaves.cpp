@@ -1,0 +1,127 @@
+// Copies between views whose records differ (sec. 3.9: a field missing on one
+// side): each destination leaf takes a chosen source leaf of the same size, or
+// keeps its bytes.
+#include "core.hpp"
+
+namespace llama {
+
+namespace {
+
+void blob_ptrs(const char* which, const Side& s, const llama_blob* blobs, std::vector<uint64_t>& ptrs)
+{
+    if (!blobs)
+        fail(LLAMA_E_INVALID_ARG, std::string(which) + " blob array is NULL");
+    ptrs.resize(s.blob_size.size());
+    for (size_t b = 0; b < s.blob_size.size(); b++) {
+        if (blobs[b].size < s.blob_size[b])
+            fail(LLAMA_E_BLOB_TOO_SMALL, std::string(which) + " blob " + std::to_string(b) + " holds " +
+                                             std::to_string(blobs[b].size) + " bytes, the mapping needs " +
+                                             std::to_string(s.blob_size[b]));
+        if (!blobs[b].ptr && s.blob_size[b] != 0)
+            fail(LLAMA_E_INVALID_ARG, std::string(which) + " blob " + std::to_string(b) + " is NULL");
+        ptrs[b] = uint64_t(uintptr_t(blobs[b].ptr));
+    }
+}
+
+bool overlap(uint64_t a, uint64_t an, uint64_t b, uint64_t bn)
+{
+    return an != 0 && bn != 0 && a < b + bn && b < a + an;
+}
+
+} // namespace
+
+void copy_leaves(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                 const llama_blob* dst_blobs, const uint32_t* src_leaf, const llama_copy_options* options,
+                 void* stream)
+{
+    if (!src || !dst)
+        fail(LLAMA_E_INVALID_ARG, "mapping descriptor is NULL");
+    if (!src_leaf)
+        fail(LLAMA_E_INVALID_ARG, "src_leaf is NULL");
+    if (src->kind == LLAMA_SPLIT || dst->kind == LLAMA_SPLIT)
+        fail(LLAMA_E_UNSUPPORTED, "llama_copy_leaves takes mappings that are not Split");
+    if (dst->kind == LLAMA_ONE)
+        fail(LLAMA_E_UNSUPPORTED, "a One mapping holds a single record and cannot receive a copy of many");
+    const Record rs = flatten(src->record), rd = flatten(dst->record);
+    const Side ss = make_side(src, rs), sd = make_side(dst, rd);
+    if (src->rank != dst->rank)
+        fail(LLAMA_E_EXTENT_MISMATCH, "source and destination ranks differ");
+    for (uint32_t d = 0; d < src->rank; d++)
+        if (src->extents[d] != dst->extents[d])
+            fail(LLAMA_E_EXTENT_MISMATCH, "source and destination extents differ in dimension " + std::to_string(d));
+    // the destination leaves that take a value, and their source leaves
+    std::vector<uint32_t> to, from;
+    for (size_t k = 0; k < rd.leaves.size(); k++) {
+        const uint32_t f = src_leaf[k];
+        if (f == LLAMA_NO_LEAF)
+            continue;
+        if (f >= rs.leaves.size())
+            fail(LLAMA_E_INVALID_ARG, "src_leaf[" + std::to_string(k) + "] = " + std::to_string(f) +
+                                          " is not a source leaf");
+        if (rs.leaves[f].size != rd.leaves[k].size)
+            fail(LLAMA_E_RECORD_MISMATCH, "destination leaf " + std::to_string(k) + " has " +
+                                              std::to_string(rd.leaves[k].size) + " bytes, source leaf " +
+                                              std::to_string(f) + " has " + std::to_string(rs.leaves[f].size));
+        to.push_back(uint32_t(k));
+        from.push_back(f);
+    }
+    if (to.empty())
+        fail(LLAMA_E_INVALID_ARG, "no destination leaf takes a source leaf");
+
+    Request rq;
+    rq.record = sub_record(rd, to);
+    rq.src = ss;
+    rq.src.blob.clear();
+    rq.src.base.clear();
+    for (uint32_t f : from) {
+        rq.src.blob.push_back(ss.blob[f]);
+        rq.src.base.push_back(ss.base[f]);
+    }
+    bool identity = from.size() == rs.leaves.size();
+    for (size_t j = 0; identity && j < from.size(); j++)
+        identity = from[j] == j;
+    rq.src.partial = !identity;
+    rq.dst = sd;
+    rq.dst.blob.clear();
+    rq.dst.base.clear();
+    for (uint32_t k : to) {
+        rq.dst.blob.push_back(sd.blob[k]);
+        rq.dst.base.push_back(sd.base[k]);
+    }
+    rq.dst.partial = to.size() != rd.leaves.size();
+    blob_ptrs("source", ss, src_blobs, rq.src_ptr);
+    blob_ptrs("destination", sd, dst_blobs, rq.dst_ptr);
+    for (size_t a = 0; a < rq.dst_ptr.size(); a++) {
+        for (size_t b = 0; b < rq.src_ptr.size(); b++)
+            if (overlap(rq.dst_ptr[a], sd.blob_size[a], rq.src_ptr[b], ss.blob_size[b]))
+                fail(LLAMA_E_OVERLAP, "destination blob " + std::to_string(a) + " overlaps source blob " +
+                                          std::to_string(b));
+        for (size_t b = a + 1; b < rq.dst_ptr.size(); b++)
+            if (overlap(rq.dst_ptr[a], sd.blob_size[a], rq.dst_ptr[b], sd.blob_size[b]))
+                fail(LLAMA_E_OVERLAP, "destination blobs " + std::to_string(a) + " and " + std::to_string(b) +
+                                          " overlap");
+    }
+
+    if (rq.dst.partial && sd.lanes >= 1) {
+        // a record-major destination written in part: only a direct store
+        // (granules of its own leaves, no padding gaps) or the element-wise
+        // kernel leaves the other leaves' bytes alone
+        try {
+            Plan t = make_plan(rq, options);
+            if (t.path == LLAMA_PATH_TILE && (t.tile.h.flags & kTileDirectStore) && rq.dst.gaps.empty()) {
+                launch(t, stream);
+                return;
+            }
+        } catch (const Error&) {
+            // the caller's path or tile size does not fit; go element-wise
+        }
+        llama_copy_options o = options ? *options : llama_copy_options{0, 0, 0, 0, 0};
+        o.path = LLAMA_PATH_NAIVE;
+        o.tile_records = 0;
+        launch(make_plan(rq, &o), stream);
+        return;
+    }
+    launch(make_plan(rq, options), stream);
+}
+
+} // namespace llama

@@ -136,6 +136,9 @@ _SIGNATURES = {
                                         ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob), ctypes.c_void_p]),
     "llama_copy_ex": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob), ctypes.POINTER(MappingDesc),
                                      ctypes.POINTER(Blob), ctypes.POINTER(CopyOptions), ctypes.c_void_p]),
+    "llama_copy_leaves": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob), ctypes.POINTER(MappingDesc),
+                                         ctypes.POINTER(Blob), ctypes.POINTER(ctypes.c_uint32),
+                                         ctypes.POINTER(CopyOptions), ctypes.c_void_p]),
     "llama_autotune": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob), ctypes.POINTER(MappingDesc),
                                       ctypes.POINTER(Blob), ctypes.c_void_p, ctypes.c_uint32,
                                       ctypes.POINTER(CopyOptions), ctypes.POINTER(ctypes.c_double)]),
@@ -346,6 +349,19 @@ def copy(src: Mapping, src_blobs, dst: Mapping, dst_blobs, stream=None, path=PAT
         o = _options(path, tile_records, threads, wg_per_cu, flags)
         check(lib().llama_copy_ex(ctypes.byref(src.desc), sb, ctypes.byref(dst.desc), db, ctypes.byref(o),
                                   _stream(stream)))
+
+
+NO_LEAF = 0xFFFFFFFF
+
+
+def copy_leaves(src: Mapping, src_blobs, dst: Mapping, dst_blobs, source_leaf, stream=None, path=PATH_AUTO,
+                tile_records=0, threads=0, wg_per_cu=0, flags=0):
+    """llama_copy_leaves: destination leaf k takes source leaf source_leaf[k]
+    (None: the leaf keeps its bytes); the records may differ."""
+    arr = (ctypes.c_uint32 * max(len(source_leaf), 1))(*[NO_LEAF if x is None else int(x) for x in source_leaf])
+    o = _options(path, tile_records, threads, wg_per_cu, flags)
+    check(lib().llama_copy_leaves(ctypes.byref(src.desc), _blobs(src_blobs), ctypes.byref(dst.desc),
+                                  _blobs(dst_blobs), arr, ctypes.byref(o), _stream(stream)))
 
 
 def copy_naive(src: Mapping, src_blobs, dst: Mapping, dst_blobs, stream=None):

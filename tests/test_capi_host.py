@@ -548,3 +548,33 @@ def test_header_is_c99_and_matches_the_binding(tmp_path):
             L.SplitDesc.split.offset, ctypes.sizeof(L.CopyOptions), ctypes.sizeof(L.PlanInfo),
             ctypes.sizeof(L.CopyItem)]
     assert got == want
+
+
+def test_copy_leaves_validation():
+    """llama_copy_leaves rejects bad leaf maps before anything is enqueued."""
+    r7, r6 = L.Record(W.PARTICLE), L.Record([["f32", "f32", "f32"], ["f32", "f32", "f32"]])
+    a, b = L.Mapping(r7, "aos_packed", [10]), L.Mapping(r6, "soa_multi", [10])
+    bufs = [ctypes.create_string_buffer(x) for x in a.blob_sizes() + b.blob_sizes()]
+    blob = lambda x: L.Blob(ctypes.cast(x, ctypes.c_void_p), len(x))  # noqa: E731
+    sb = (L.Blob * 1)(blob(bufs[0]))
+    db = (L.Blob * 6)(*[blob(x) for x in bufs[1:]])
+
+    def rc(m_src, s_b, m_dst, d_b, leaves):
+        arr = (ctypes.c_uint32 * len(leaves))(*leaves)
+        return L.lib().llama_copy_leaves(ctypes.byref(m_src.desc), s_b, ctypes.byref(m_dst.desc), d_b, arr, None, None)
+
+    assert rc(a, sb, b, db, [0, 1, 2, 3, 4, 7]) == L.E_INVALID_ARG           # no source leaf 7
+    assert rc(a, sb, b, db, [L.NO_LEAF] * 6) == L.E_INVALID_ARG             # nothing to copy
+    rm = L.Record([["f32", "f32", "f32"], ["f32", "f32", "f64"]])
+    c = L.Mapping(rm, "soa_multi", [10])
+    cb = [ctypes.create_string_buffer(x) for x in c.blob_sizes()]
+    cbb = (L.Blob * 6)(*[blob(x) for x in cb])
+    assert rc(a, sb, c, cbb, [0, 1, 2, 3, 4, 5]) == L.E_RECORD_MISMATCH     # 4 bytes into 8
+    one = L.Mapping(r6, "one", [10])
+    ob = (L.Blob * 1)(blob(ctypes.create_string_buffer(24)))
+    assert rc(a, sb, one, ob, list(range(6))) == L.E_UNSUPPORTED            # into One
+    s = L.Mapping(r6, "split", [10], split=(0, 3, ("soa_multi", 0), ("aos_packed", 0)))
+    assert rc(a, sb, s, db, list(range(6))) == L.E_UNSUPPORTED              # Split
+    small = (L.Blob * 6)(*[L.Blob(ctypes.cast(x, ctypes.c_void_p), 4) for x in bufs[1:]])
+    assert rc(a, sb, b, small, list(range(6))) == L.E_BLOB_TOO_SMALL
+    assert rc(a, sb, b, (L.Blob * 6)(*([blob(bufs[0])] * 6)), list(range(6))) == L.E_OVERLAP
