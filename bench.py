@@ -352,6 +352,66 @@ def bench_pic(L, torch, args, dev, stream):
             "hbm_peak_frac": round(gbs / HBM_PEAK_GBS, 4), "extras": res, "device": dev.name}
 
 
+def bench_leaves(L, torch, args, dev, stream):
+    """Copies between records that differ (sec. 3.9): the particle with and
+    without its mass, 2^26 records, three layout pairs each way.  Into the
+    record without mass the mass is dropped; into the record with mass the
+    mass keeps its bytes.  Bytes are the values moved (read + written)."""
+    n = 1 << 26
+    no_mass = [["f32", "f32", "f32"], ["f32", "f32", "f32"]]
+    r7, r6 = L.Record(W.PARTICLE), L.Record(no_mass)
+    lay = [("aos_packed", 0), ("soa_multi", 0), ("aosoa", 32)]
+    m7 = {l: L.Mapping(r7, l[0], [n], l[1]) for l in lay}
+    m6 = {l: L.Mapping(r6, l[0], [n], l[1]) for l in lay}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(W.BASE_SEED + 7)
+    b7 = {l: [torch.randint(0, 256, (s,), dtype=torch.uint8, device="cuda", generator=g) for s in m.blob_sizes()]
+          for l, m in m7.items()}
+    b6 = {l: [torch.randint(0, 256, (s,), dtype=torch.uint8, device="cuda", generator=g) for s in m.blob_sizes()]
+          for l, m in m6.items()}
+    drop, keep = list(range(6)), list(range(6)) + [None]
+    cases = [(f"{_name(a)}->{_name(b)}-without-mass", m7[a], b7[a], m6[b], b6[b], drop)
+             for a, b in ((lay[0], lay[1]), (lay[1], lay[2]), (lay[2], lay[0]))]
+    cases += [(f"{_name(a)}-without-mass->{_name(b)}", m6[a], b6[a], m7[b], b7[b], keep)
+              for a, b in ((lay[1], lay[0]), (lay[0], lay[2]), (lay[2], lay[1]))]
+    moved = 2 * n * 24  # six 4-byte leaves read and written per record
+    torch.cuda.synchronize()
+    per, total_ms = {}, 0.0
+    for name, ms, sb, md, db, lv in cases:
+        med, mn = _timed(torch, stream, lambda: L.copy_leaves(ms, sb, md, db, lv, stream=stream), args.steps)
+        per[name] = {"ms_median": round(med, 4), "gbs": round(moved / (med * 1e-3) / 1e9, 1)}
+        total_ms += med
+    value = round(moved * len(cases) / (total_ms * 1e-3) / 1e9, 1)
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as orc
+        ns = 1 << 19
+        o7, o6 = orc.Record(W.PARTICLE), orc.Record(no_mass)
+        t = 0.0
+        for k, (a, b, lv, rs, rd) in enumerate([(lay[0], lay[1], drop, o7, o6), (lay[1], lay[0], keep, o6, o7)]):
+            ms = orc.Mapping(rs, a[0], [ns], a[1])
+            md = orc.Mapping(rd, b[0], [ns], b[1])
+            src = [W.random_bytes(x, 70 + k + j) for j, x in enumerate(ms.blob_sizes())]
+            dst = md.alloc()
+            t0 = time.perf_counter()
+            orc.copy_leaves(ms, src, md, dst, lv)
+            t += time.perf_counter() - t0
+        cpu = {"value": 2 * 2 * ns * 24 / t / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"2 of the 6 pairs (one each way) at {ns} records ({t:.1f} s, single thread)"}
+    return {"metric": METRIC, "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+            "ms_per_step": round(total_ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "particle 7xf32 and the particle without mass (6xf32), 2^26 records, "
+                                   "copies between the two records over packed AoS, SoA multi-blob and AoSoA32, "
+                                   "3 pairs each way", "records": n, "pairs": len(cases),
+                       "bytes_per_step": moved * len(cases), "parallelism": "single GPU"},
+            "roofline": {"bound": "hbm", "achieved": value, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(value / HBM_PEAK_GBS, 4), "traffic": None,
+                         "kernel": "llama_copy_leaves (tile, stream or naive kernel)"},
+            "cpu_baseline": cpu, "hbm_peak_frac": round(value / HBM_PEAK_GBS, 4), "extras": per,
+            "device": dev.name}
+
+
 def _serve_setup(L, torch, count, warm=200):
     """The serving trace: warm + count requests whose blobs lie in one device
     arena used as a ring (132 GB), and the autotuned record/pair classes."""
@@ -475,7 +535,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="particle", choices=["particle", "lbm", "split", "batch", "serve", "pic"])
+    ap.add_argument("--workload", default="particle", choices=["particle", "lbm", "split", "leaves", "batch", "serve", "pic"])
     ap.add_argument("--requests", type=int, default=2000, help="serve: measured requests (after 200 warm-up)")
     ap.add_argument("--rho", type=float, default=0.8, help="serve: offered load as a fraction of batched GB/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -505,6 +565,9 @@ def main():
         return
     if args.workload == "pic":
         print(json.dumps(bench_pic(L, torch, args, dev, stream)), flush=True)
+        return
+    if args.workload == "leaves":
+        print(json.dumps(bench_leaves(L, torch, args, dev, stream)), flush=True)
         return
 
     if args.workload == "particle":
