@@ -3,6 +3,8 @@
 // keeps its bytes.
 #include "core.hpp"
 
+#include <algorithm>
+
 namespace llama {
 
 namespace {
@@ -102,18 +104,54 @@ void copy_leaves(const llama_mapping_desc* src, const llama_blob* src_blobs, con
                                           " overlap");
     }
 
+    if (rq.dst.partial && sd.lanes == 1 && sd.gaps.empty() && sd.npad == sd.n) {
+        // records without padding written in part (packed AoS): the bytes of
+        // the leaves without a source are gaps whose bytes the tile keeps, by
+        // loading each destination region and storing it back whole
+        Request kept = rq;
+        std::vector<std::pair<uint64_t, uint64_t>> cover;
+        for (size_t j = 0; j < to.size(); j++)
+            cover.push_back({kept.dst.base[j], rd.leaves[to[j]].size});
+        std::sort(cover.begin(), cover.end());
+        uint64_t cur = 0;
+        for (const auto& c : cover) {
+            if (c.first > cur)
+                kept.dst.gaps.push_back({cur, c.first - cur});
+            cur = std::max(cur, c.first + c.second);
+        }
+        if (sd.block > cur)
+            kept.dst.gaps.push_back({cur, sd.block - cur});
+        kept.dst.partial = false;
+        llama_copy_options o = options ? *options : llama_copy_options{0, 0, 0, 0, 0};
+        o.flags |= LLAMA_COPY_PRESERVE_PADDING;
+        Plan t;
+        bool planned = false;
+        try {
+            t = make_plan(kept, &o);
+            planned = true;
+        } catch (const Error&) {
+            // too many gap entries for this build's kernels: go on below
+        }
+        if (planned) {
+            launch(t, stream);
+            return;
+        }
+    }
     if (rq.dst.partial && sd.lanes >= 1) {
         // a record-major destination written in part: only a direct store
         // (granules of its own leaves, no padding gaps) or the element-wise
         // kernel leaves the other leaves' bytes alone
+        Plan t;
+        bool direct = false;
         try {
-            Plan t = make_plan(rq, options);
-            if (t.path == LLAMA_PATH_TILE && (t.tile.h.flags & kTileDirectStore) && rq.dst.gaps.empty()) {
-                launch(t, stream);
-                return;
-            }
+            t = make_plan(rq, options);
+            direct = t.path == LLAMA_PATH_TILE && (t.tile.h.flags & kTileDirectStore) && rq.dst.gaps.empty();
         } catch (const Error&) {
             // the caller's path or tile size does not fit; go element-wise
+        }
+        if (direct) {
+            launch(t, stream);
+            return;
         }
         llama_copy_options o = options ? *options : llama_copy_options{0, 0, 0, 0, 0};
         o.path = LLAMA_PATH_NAIVE;

@@ -82,3 +82,30 @@ def test_copy_leaves(L, orc, case):
             raise AssertionError(f"blob {k}: {bad.size} bytes differ, first at {bad[0]} "
                                  f"(got {got[bad[0]]:#x}, want {w[bad[0]]:#x})")
         assert (host[:GUARD] == fill).all() and (host[GUARD + w.size:] == fill).all()
+
+
+@pytest.mark.parametrize("case", [("mixed", ("soa_multi", 0), [0, None, 2, 3, None, 5, 6, 7, None, 9], False),
+                                  ("mixed", ("aosoa", 8), [None, 1, 2, None, 4, 5, 6, None, 8, 9], True),
+                                  ("listing1", ("soa_single", 0), [0, 1, 2, None, 4, 5, None], False),
+                                  ("particle", ("aosoa", 32), [6, 5, 4, 3, 2, 1, None], False)],
+                         ids=["mixed-soa_multi", "mixed-aosoa8-keep", "listing1-soa_single", "particle-reversed"])
+def test_copy_leaves_into_packed_aos_in_part(L, orc, case):
+    """Packed AoS written in part: the leaves without a source keep their
+    bytes through a tile that stores whole regions back."""
+    name, a, leaves, keep = case
+    rec = W.RECORDS[name]
+    for n in (1, 1000, 20011):
+        print(f"copy_leaves into packed aos {case} n={n}", flush=True)
+        ro, rg = orc.Record(rec), L.Record(rec)
+        ms_o, md_o = orc.Mapping(ro, a[0], [n], a[1]), orc.Mapping(ro, "aos_packed", [n])
+        ms, md = L.Mapping(rg, a[0], [n], a[1]), L.Mapping(rg, "aos_packed", [n])
+        src = [W.random_bytes(x, n + j) for j, x in enumerate(ms_o.blob_sizes())]
+        want = orc.copy_leaves(ms_o, src, md_o, [np.full(x, 0xCD, np.uint8) for x in md_o.blob_sizes()], leaves,
+                               keep_padding=keep)
+        buf = torch.full((md_o.blob_size(0) + 2 * GUARD,), 0xCD, dtype=torch.uint8, device="cuda")
+        L.copy_leaves(ms, [torch.from_numpy(x).cuda() for x in src], md, [buf[GUARD:buf.numel() - GUARD]], leaves,
+                      flags=L.COPY_PRESERVE_PADDING if keep else 0)
+        torch.cuda.synchronize()
+        host = buf.cpu().numpy()
+        assert np.array_equal(host[GUARD:GUARD + want[0].size], want[0])
+        assert (host[:GUARD] == 0xCD).all() and (host[GUARD + want[0].size:] == 0xCD).all()
