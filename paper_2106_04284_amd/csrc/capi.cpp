@@ -1,4 +1,5 @@
 // extern "C" entry points declared in include/llama_mi355x.h.
+#include <algorithm>
 #include <cstring>
 #include <memory>
 #include <exception>
@@ -198,6 +199,36 @@ int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, co
         // on the stream; every plan is made before the first launch
         std::vector<Plan> plans;
         for (const SubCopy& c : split_copies(src, dst, rq)) {
+            if (c.naive && c.rq.dst.lanes == 1 && c.rq.dst.gaps.empty() && c.rq.dst.npad == c.rq.dst.n) {
+                // into AoS records another part copy has already written
+                // whole: a staged tile that keeps every byte outside these
+                // leaves (taken as gaps) by storing each loaded region back
+                Request kept = c.rq;
+                std::vector<std::pair<uint64_t, uint64_t>> cover;
+                for (size_t k = 0; k < kept.record.leaves.size(); k++)
+                    cover.push_back({kept.dst.base[k], kept.record.leaves[k].size});
+                std::sort(cover.begin(), cover.end());
+                uint64_t cur = 0;
+                for (const auto& cv : cover) {
+                    if (cv.first > cur)
+                        kept.dst.gaps.push_back({cur, cv.first - cur});
+                    cur = std::max(cur, cv.first + cv.second);
+                }
+                if (kept.dst.block > cur)
+                    kept.dst.gaps.push_back({cur, kept.dst.block - cur});
+                kept.dst.partial = false;
+                llama_copy_options o = options ? *options : llama_copy_options{0, 0, 0, 0, 0};
+                o.flags |= LLAMA_COPY_PRESERVE_PADDING;
+                bool planned = false;
+                try {
+                    plans.push_back(make_plan(kept, &o));
+                    planned = true;
+                } catch (const Error&) {
+                    // too many gap entries: element-wise below
+                }
+                if (planned)
+                    continue;
+            }
             if (c.naive) {
                 // a tile plan that stores 16-byte granules of its own leaves
                 // straight from the staged source (direct store, no padding
