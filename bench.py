@@ -39,6 +39,12 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# CPUs this process may run on, read before any OpenMP runtime pins the thread
+AFFINITY_CPUS = len(os.sched_getaffinity(0))
+# the threaded CPU oracle runs one thread per core, each pinned (sec. 4 setup);
+# OpenMP reads these when it starts
+os.environ.setdefault("OMP_PROC_BIND", "close")
+os.environ.setdefault("OMP_PLACES", "cores")
 
 from paper_2106_04284_amd import workloads as W  # noqa: E402
 
@@ -92,24 +98,70 @@ def make_mapping(mod, rec, layout, extents):
     return mod.Mapping(rec, layout[0], extents, layout[1])
 
 
-def cpu_baseline(record, layouts, pairs, n_sample, budget_s=20.0):
+def host_info():
+    """The host's CPU model and core counts, for the CPU baseline."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": AFFINITY_CPUS,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_baseline(record, layouts, pairs, n_single, n_full, budget_single_s=6.0, budget_all_s=12.0):
+    """The oracle on the host: one thread over the pairs at n_single records,
+    then the threaded oracle on every core it may use (pinned, one thread per
+    core) over pairs at the full n_full records, and host memcpy of one full
+    layout at 1 and at all threads (the reference line of sec. 4.2)."""
     from oracle import oracle as orc
     ro = orc.Record(record)
-    maps = {l: make_mapping(orc, ro, l, [n_sample]) for l in layouts}
-    srcs = {l: [W.random_bytes(s, 99 + k) for k, s in enumerate(maps[l].blob_sizes())] for l in layouts}
-    dsts = {l: maps[l].alloc() for l in layouts}
-    nbytes, elapsed, done = 0, 0.0, 0
-    for a, b in pairs:
+    threads = orc.max_threads()
+
+    def run(n, todo, nthreads, budget):
+        maps = {l: make_mapping(orc, ro, l, [n]) for l in layouts}
+        size = max(sum(m.blob_sizes()) for m in maps.values())
+        pool = W.random_bytes(size, 99)
+        out = np.zeros(size, dtype=np.uint8)  # pages touched before timing
+
+        def views(buf, m):
+            offs = np.cumsum([0] + m.blob_sizes())
+            return [buf[offs[k]:offs[k + 1]] for k in range(m.blob_count)]
+
+        nbytes, elapsed, done = 0, 0.0, 0
+        for a, b in todo:
+            src, dst = views(pool, maps[a]), views(out, maps[b])
+            t0 = time.perf_counter()
+            orc.copy_threads(maps[a], src, maps[b], dst, threads=nthreads)
+            elapsed += time.perf_counter() - t0
+            nbytes += sum(maps[a].blob_sizes()) + sum(maps[b].blob_sizes())
+            done += 1
+            if elapsed > budget:
+                break
+        return nbytes, elapsed, done, pool, out
+
+    nb1, t1, done1, _, _ = run(n_single, pairs, 1, budget_single_s)
+    spread = pairs[::7] + [p for k, p in enumerate(pairs) if k % 7]
+    nba, ta, donea, pool, out = run(n_full, spread, threads, budget_all_s)
+    mem = {}
+    for nt in (1, threads):
+        orc.memcpy_threads(out, pool, nt)
         t0 = time.perf_counter()
-        orc.copy(maps[a], srcs[a], maps[b], dsts[b])
-        elapsed += time.perf_counter() - t0
-        nbytes += sum(maps[a].blob_sizes()) + sum(maps[b].blob_sizes())
-        done += 1
-        if elapsed > budget_s:
-            break
-    return {"value": nbytes / elapsed / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} of the {len(pairs)} layout pairs at {n_sample} records each "
-                      f"({nbytes / 1e9:.3f} GB read+written, {elapsed:.1f} s, single thread)"}
+        used = orc.memcpy_threads(out, pool, nt)
+        mem[used] = 2 * pool.nbytes / (time.perf_counter() - t0) / 1e9
+    del pool, out
+    host = host_info()
+    return {"value": round(nba / ta / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"threaded oracle, {threads} threads pinned one per core, {donea} of the {len(pairs)} layout "
+                      f"pairs at the full {n_full} records ({nba / 1e9:.2f} GB read+written in {ta:.1f} s); "
+                      f"one thread: {done1} pairs at {n_single} records ({nb1 / 1e9:.2f} GB in {t1:.1f} s)",
+            "single_thread_gbs": round(nb1 / t1 / 1e9, 3),
+            "host_memcpy_gbs": {str(k): round(v, 1) for k, v in mem.items()},
+            "host": host}
 
 
 # --------------------------------------------------------------------------
@@ -580,6 +632,7 @@ def main():
                    "42 ordered pairs of packed AoS, aligned AoS, SoA single-blob, SoA multi-blob, AoSoA8/32/64"
         dtype = "u32"
         cpu_n = 1 << 19
+        cpu_full = n
     elif args.workload == "split":
         # Split mappings (sec. 3.7) of the particle: positions as AoSoA32 with
         # velocities and mass as multi-blob SoA; velocities as multi-blob SoA
@@ -597,6 +650,7 @@ def main():
                    "packed AoS, SoA multi-blob, AoSoA32 and each other"
         dtype = "u32"
         cpu_n = 1 << 19
+        cpu_full = n
     else:
         record, extents = W.LBM, [128, 128, 128]
         layouts = [("aos_aligned", 0), ("soa_multi", 0), ("aosoa", 32)]
@@ -606,6 +660,7 @@ def main():
                    "6 ordered pairs of aligned AoS, SoA multi-blob, AoSoA32"
         dtype = "u64"
         cpu_n = 1 << 17
+        cpu_full = 128 ** 3
     # the 128^3 lattice (663 MB per copy) would partly stay in the 256 MB
     # Infinity Cache between copies: read 1 GiB before each timed copy
     cold = args.workload == "lbm"
@@ -657,7 +712,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(record, layouts, pairs, cpu_n)
+        cpu = cpu_baseline(record, layouts, pairs, cpu_n, cpu_full)
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,

@@ -61,12 +61,18 @@
  *     of aligned AoS, unused lanes of the last AoSoA block) are set to zero.
  *
  * Arithmetic: plain unsigned 64-bit integers, plain '/' and '%'.  No shifts,
- * masks, tiling, blocking or reordering.
+ * masks, tiling, blocking or reordering.  The one exception is
+ * orc_copy_threads, which runs the same loop over contiguous pieces of the
+ * coordinate order on several host threads, to time the oracle on all cores;
+ * its result is the serial copy's byte for byte.
  */
 #include <stdint.h>
 #include <stddef.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_MAX_RANK 8
 
@@ -704,4 +710,136 @@ int64_t orc_check_samples(const orc_record* r, const orc_mapping* src, uint8_t* 
         }
     }
     return bad;
+}
+
+/* ---------------------------------------------------------------------------
+ * The same copy on several host threads (the paper times its copies with one
+ * thread per physical core, sec. 4).  The coordinate range is cut into
+ * contiguous pieces of the row-major order; each thread runs the loop of
+ * orc_copy over its piece, starting from the coordinate of its first linear
+ * index.  Values of different coordinates occupy different destination bytes
+ * (a mapping that is a valid destination maps distinct values to distinct
+ * bytes), so the result does not depend on the number of threads.  A
+ * destination holding a One part (every coordinate at the same bytes) is copied
+ * on one thread, so that the last coordinate's value wins as in orc_copy.
+ * ------------------------------------------------------------------------- */
+
+static int has_one(const orc_mapping* m)
+{
+    if (m->kind == ORC_ONE)
+        return 1;
+    if (m->kind != ORC_SPLIT)
+        return 0;
+    for (int k = 0; k < 2; k++) {
+        if (m->part_kind[k] == ORC_ONE)
+            return 1;
+        if (m->part_kind[k] == ORC_SPLIT && m->part_split[k] && has_one(m->part_split[k]))
+            return 1;
+    }
+    return 0;
+}
+
+/* the row-major coordinate of linear index i */
+static void delinearize(const orc_mapping* m, uint64_t i, uint64_t* coord)
+{
+    for (int d = m->rank - 1; d >= 0; d--) {
+        coord[d] = i % m->extents[d];
+        i /= m->extents[d];
+    }
+}
+
+/* orc_copy (keep == 0) or orc_copy_keep (keep != 0) on `threads` threads
+ * (<= 0: the OpenMP default).  Built without OpenMP it runs on one thread. */
+int orc_copy_threads(const orc_record* r, const orc_mapping* src, uint8_t* const* src_blobs,
+                     const orc_mapping* dst, uint8_t* const* dst_blobs, int keep, int threads)
+{
+    if (!valid_mapping(src, r) || !valid_mapping(dst, r) || !same_extents(src, dst))
+        return ORC_E_ARG;
+    if (has_one(dst))
+        return keep ? orc_copy_keep(r, src, src_blobs, dst, dst_blobs) : orc_copy(r, src, src_blobs, dst, dst_blobs);
+#ifdef _OPENMP
+    if (threads <= 0)
+        threads = omp_get_max_threads();
+#else
+    threads = 1;
+#endif
+    int64_t pieces = (int64_t)threads * 16;
+    if (!keep) {
+        /* padding policy: the whole destination starts at zero */
+        for (int b = 0; b < orc_blob_count(dst, r); b++) {
+            uint64_t size = orc_blob_size(dst, r, b);
+            uint8_t* base = dst_blobs[b];
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(threads) schedule(static)
+#endif
+            for (int64_t k = 0; k < pieces; k++) {
+                uint64_t lo = size / (uint64_t)pieces * (uint64_t)k;
+                uint64_t hi = k + 1 == pieces ? size : size / (uint64_t)pieces * (uint64_t)(k + 1);
+                memset(base + lo, 0, (size_t)(hi - lo));
+            }
+        }
+    }
+    uint64_t n = orc_record_count(src);
+    if (n == 0)
+        return ORC_OK;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 1)
+#endif
+    for (int64_t k = 0; k < pieces; k++) {
+        uint64_t lo = n / (uint64_t)pieces * (uint64_t)k;
+        uint64_t hi = k + 1 == pieces ? n : n / (uint64_t)pieces * (uint64_t)(k + 1);
+        if (lo == hi)
+            continue;
+        uint64_t coord[ORC_MAX_RANK] = {0};
+        delinearize(src, lo, coord);
+        for (uint64_t i = lo; i < hi; i++) {
+            for (int f = 0; f < r->nleaves; f++) {
+                uint64_t bs, os, bd, od;
+                orc_blob_nr_and_offset(src, r, coord, f, &bs, &os);
+                orc_blob_nr_and_offset(dst, r, coord, f, &bd, &od);
+                memcpy(dst_blobs[bd] + od, src_blobs[bs] + os, (size_t)r->size[f]);
+            }
+            next_coord(src, coord);
+        }
+    }
+    return ORC_OK;
+}
+
+/* Host memcpy of `bytes` bytes on `threads` threads, each taking one
+ * contiguous piece: the reference the paper sets beside its copies
+ * (sec. 4.2).  Returns the number of threads used. */
+int orc_memcpy_threads(uint8_t* dst, const uint8_t* src, uint64_t bytes, int threads)
+{
+#ifdef _OPENMP
+    if (threads <= 0)
+        threads = omp_get_max_threads();
+#else
+    threads = 1;
+#endif
+    int used = 1;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(threads)
+    {
+        int t = omp_get_thread_num(), nt = omp_get_num_threads();
+        uint64_t lo = bytes / (uint64_t)nt * (uint64_t)t;
+        uint64_t hi = t + 1 == nt ? bytes : bytes / (uint64_t)nt * (uint64_t)(t + 1);
+        memcpy(dst + lo, src + lo, (size_t)(hi - lo));
+        if (t == 0)
+            used = nt;
+    }
+#else
+    memcpy(dst, src, (size_t)bytes);
+#endif
+    return used;
+}
+
+/* Threads an OpenMP region of this library gets by default (1 without
+ * OpenMP). */
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -52,7 +52,8 @@ class _Mapping(ctypes.Structure):
 
 
 def build(force: bool = False) -> str:
-    """Compiles llama_oracle.c into liborc.so with gcc -O2.
+    """Compiles llama_oracle.c into liborc.so with gcc -O2 -fopenmp (OpenMP
+    serves only the threaded copy used to time the oracle on all cores).
 
     LLAMA_ORACLE_LIB names another build of the oracle to load instead; the
     test suite uses it to run the pins against deliberately broken copies of
@@ -62,7 +63,7 @@ def build(force: bool = False) -> str:
         return override
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-Wall", "-Wextra", "-shared", "-fPIC",
                                _SRC, "-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB
@@ -101,6 +102,12 @@ def lib():
         L.orc_copy.restype = ctypes.c_int
         L.orc_copy_keep.argtypes = [RP, MP, PP, MP, PP]
         L.orc_copy_keep.restype = ctypes.c_int
+        L.orc_copy_threads.argtypes = [RP, MP, PP, MP, PP, ctypes.c_int, ctypes.c_int]
+        L.orc_copy_threads.restype = ctypes.c_int
+        L.orc_memcpy_threads.argtypes = [ctypes.c_void_p, ctypes.c_void_p, u64, ctypes.c_int]
+        L.orc_memcpy_threads.restype = ctypes.c_int
+        L.orc_max_threads.argtypes = []
+        L.orc_max_threads.restype = ctypes.c_int
         L.orc_write_counts.argtypes = [RP, MP, PP]
         L.orc_write_counts.restype = ctypes.c_int
         L.orc_check_samples.argtypes = [RP, MP, PP, MP, PP, ctypes.POINTER(u64), ctypes.POINTER(i32),
@@ -264,6 +271,38 @@ def copy(src: Mapping, src_blobs, dst: Mapping, dst_blobs=None, keep_padding=Fal
     if rc != 0:
         raise ValueError(f"oracle copy failed ({rc})")
     return dst_blobs
+
+
+def copy_threads(src: Mapping, src_blobs, dst: Mapping, dst_blobs=None, keep_padding=False, threads=0):
+    """copy() run on `threads` host threads (0: the OpenMP default), each over
+    a contiguous piece of the coordinate order; the same bytes as copy()."""
+    if keep_padding and dst_blobs is None:
+        raise ValueError("keep_padding needs the destination blobs")
+    if dst_blobs is None:
+        dst_blobs = [np.empty(s, dtype=np.uint8) for s in dst.blob_sizes()]
+    for b, s in zip(src_blobs, src.blob_sizes()):
+        if b.size < s:
+            raise ValueError("source blob too small")
+    for b, s in zip(dst_blobs, dst.blob_sizes()):
+        if b.size < s:
+            raise ValueError("destination blob too small")
+    rc = lib().orc_copy_threads(ctypes.byref(src.record.c), ctypes.byref(src.c), _ptrs(src_blobs),
+                                ctypes.byref(dst.c), _ptrs(dst_blobs), 1 if keep_padding else 0, int(threads))
+    if rc != 0:
+        raise ValueError(f"oracle copy failed ({rc})")
+    return dst_blobs
+
+
+def memcpy_threads(dst: np.ndarray, src: np.ndarray, threads=0) -> int:
+    """Host memcpy of src into dst on `threads` threads (0: the OpenMP
+    default); returns the threads used."""
+    if dst.nbytes < src.nbytes:
+        raise ValueError("destination too small")
+    return int(lib().orc_memcpy_threads(dst.ctypes.data, src.ctypes.data, src.nbytes, int(threads)))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def copy_leaves(src: Mapping, src_blobs, dst: Mapping, dst_blobs, source_leaf, keep_padding=False):

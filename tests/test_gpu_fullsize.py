@@ -1,17 +1,16 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
 times (default plans; the batch with the benchmark's thread counts).
 
-  * particle record, 2^26 records, every ordered layout pair: the source is
-    random bytes with NaN payloads, -0, subnormals and infinities planted;
-    2^20 sampled (record, leaf) values are checked one by one by the oracle,
-    and every destination byte must be written (two runs over destinations filled with 0x00 and 0xFF
-    agree byte for byte);
+  * particle record, 2^26 records, every ordered layout pair: the oracle builds
+    all seven layouts from the benchmark's raw 32-bit values (NaN payloads,
+    -0, subnormals and infinities planted); each is uploaded and copied into
+    every other layout, whose every byte must equal the oracle's layout;
   * lattice-Boltzmann cells, 128^3, aligned AoS <-> multi-blob SoA <-> AoSoA32:
     the whole destination against the oracle's full copy;
-  * the 1,000-array batch: every destination byte written (two fills), and
-    sampled values of 40 items checked by the oracle.
+  * the 1,000-array batch: the two launches (graph capture, replay) agree
+    byte for byte, and every item's destination equals the oracle's copy in
+    full.
 """
-import random
 
 import numpy as np
 import pytest
@@ -63,29 +62,51 @@ def _samples(n, nleaves, count, seed):
     return idx, leaf
 
 
-@pytest.mark.parametrize("pair", PAIRS, ids=[f"{_name(a)}-{_name(b)}" for a, b in PAIRS])
-def test_particle_2e26_sampled(L, orc, pair):
+@pytest.fixture(scope="module")
+def particle_2e26_layouts(L, orc):
+    """The seven particle layouts at 2^26 records, each built by the oracle
+    from the benchmark's raw 32-bit values (NaN payloads, -0, subnormals and
+    infinities planted), then uploaded: the expected bytes of every copy."""
     n = 1 << 26
-    a, b = pair
-    ro, rg = orc.Record(W.PARTICLE), L.Record(W.PARTICLE)
-    ms_o, md_o = orc.Mapping(ro, a[0], [n], a[1]), orc.Mapping(ro, b[0], [n], b[1])
-    ms, md = L.Mapping(rg, a[0], [n], a[1]), L.Mapping(rg, b[0], [n], b[1])
-    assert ms.blob_sizes() == ms_o.blob_sizes() and md.blob_sizes() == md_o.blob_sizes()
-    src = [_random_blob(s, 1000 + k) for k, s in enumerate(ms.blob_sizes())]
-    d0 = md.alloc(fill=0x00)
-    d1 = md.alloc(fill=0xFF)
-    L.copy(ms, src, md, d0)
-    L.copy(ms, src, md, d1)
+    ro = orc.Record(W.PARTICLE)
+    values = W.raw_u32_values(7, n, W.BASE_SEED + 2)
+    mb = orc.Mapping(ro, "soa_multi", [n])
+    mb_blobs = [v.view(np.uint8).reshape(-1) for v in values]
+    out = {}
+    for lay in W.LAYOUTS:
+        if lay == ("soa_multi", 0):
+            host = mb_blobs
+        else:
+            host = orc.copy_threads(mb, mb_blobs, orc.Mapping(ro, lay[0], [n], lay[1]))
+        out[lay] = [torch.from_numpy(h).cuda() for h in host]
+        del host
+    del values, mb_blobs
     torch.cuda.synchronize()
-    for x, y in zip(d0, d1):  # a byte left unwritten would differ
-        assert torch.equal(x, y)
-    src_h = [t.cpu().numpy() for t in src]
-    dst_h = [t.cpu().numpy() for t in d0]
-    idx, leaf = _samples(n, 7, 1 << 20, 7)
-    bad, first = orc.check_samples(ms_o, src_h, md_o, dst_h, idx, leaf)
-    assert bad == 0, f"{bad} sampled values differ, first sample {first}"
-    # (the particle layouts have no padding at 2^26 records: R = S and 2^26 is
-    # a multiple of every lane count; padding is checked in full below)
+    return n, out
+
+
+@pytest.mark.parametrize("src", W.LAYOUTS, ids=[_name(a) for a in W.LAYOUTS])
+def test_particle_2e26_full(L, particle_2e26_layouts, src):
+    """Every destination byte of the six copies out of `src` at 2^26 records
+    equals the oracle's layout (the benchmark's pairs, default plans)."""
+    n, want = particle_2e26_layouts
+    rg = L.Record(W.PARTICLE)
+    ms = L.Mapping(rg, src[0], [n], src[1])
+    bad = []
+    for dst in W.LAYOUTS:
+        if dst == src:
+            continue
+        md = L.Mapping(rg, dst[0], [n], dst[1])
+        out = md.alloc(fill=0xA5)
+        L.copy(ms, want[src], md, out)
+        torch.cuda.synchronize()
+        for k, (x, y) in enumerate(zip(out, want[dst])):
+            if not torch.equal(x, y):
+                diff = torch.nonzero(x != y).flatten()
+                bad.append(f"{_name(src)} -> {_name(dst)} blob {k}: {diff.numel()} bytes differ, first at "
+                           f"{int(diff[0])}; plan {L.plan(ms, md)}")
+        del out
+    assert not bad, "\n".join(bad)
 
 
 # destinations of 1 GiB or more take nontemporal stores; the particle pairs
@@ -237,13 +258,43 @@ def test_batch_1000_arrays(L, orc, threads):
                                  f"{int(y[diff[0]])}); plan {L.plan(it[0], it[2], threads=threads)}")
     assert not bad_items, "\n".join(bad_items[:10])
     del first
-    g = random.Random(3)
-    for k in g.sample(range(len(items)), 40):
-        it, spec = items[k], items_spec[k]
+    # every item in full against the oracle's copy of its source
+    mismatched = []
+    for k, (it, spec) in enumerate(zip(items, items_spec)):
         ro = orc.Record(W.RECORDS[spec["record"]])
         ms_o = orc.Mapping(ro, spec["src"][0], [spec["n"]], spec["src"][1])
         md_o = orc.Mapping(ro, spec["dst"][0], [spec["n"]], spec["dst"][1])
-        idx, leaf = _samples(spec["n"], ro.nleaves, 20000, k)
-        bad, first_bad = orc.check_samples(ms_o, [t.cpu().numpy() for t in it[1]], md_o,
-                                           [t.cpu().numpy() for t in it[3]], idx, leaf)
-        assert bad == 0, f"item {k}: {bad} sampled values differ"
+        want = orc.copy_threads(ms_o, [t.cpu().numpy() for t in it[1]], md_o)
+        for j, (t, w) in enumerate(zip(it[3], want)):
+            got = t.cpu().numpy()
+            if not np.array_equal(got, w):
+                mismatched.append(f"item {k} {spec} blob {j}: {int((got != w).sum())} bytes differ")
+    assert not mismatched, "\n".join(mismatched[:10])
+
+
+BIG_PAIRS = [(("aos_packed", 0), ("soa_single", 0)), (("aosoa", 32), ("aos_aligned", 0)),
+             (("soa_single", 0), ("soa_multi", 0))]
+
+
+@pytest.mark.parametrize("pair", BIG_PAIRS, ids=[f"{_name(a)}-{_name(b)}" for a, b in BIG_PAIRS])
+def test_particle_2e28_blobs_past_4gib(L, orc, pair):
+    """Blobs of 7.5 GB (2^28 particle records): byte offsets past 2^32 in the
+    tile, direct-store and stream paths; the whole destination equals the
+    oracle's copy."""
+    n = 1 << 28
+    a, b = pair
+    ro, rg = orc.Record(W.PARTICLE), L.Record(W.PARTICLE)
+    ms_o, md_o = orc.Mapping(ro, a[0], [n], a[1]), orc.Mapping(ro, b[0], [n], b[1])
+    ms, md = L.Mapping(rg, a[0], [n], a[1]), L.Mapping(rg, b[0], [n], b[1])
+    assert max(ms.blob_sizes() + md.blob_sizes()) > (1 << 32)
+    src = [_random_blob(s, 3000 + k) for k, s in enumerate(ms.blob_sizes())]
+    out = md.alloc(fill=0xA5)
+    L.copy(ms, src, md, out)
+    torch.cuda.synchronize()
+    src_h = [t.cpu().numpy() for t in src]
+    del src
+    want = orc.copy_threads(ms_o, src_h, md_o)
+    del src_h
+    for k, (t, w) in enumerate(zip(out, want)):
+        got = t.cpu().numpy()
+        assert np.array_equal(got, w), f"blob {k}: {int((got != w).sum())} bytes differ"

@@ -199,3 +199,34 @@ def test_split_requests(L, orc, policy):
     srv.close()
     for r in reqs:
         check(r)
+
+
+@pytest.mark.parametrize("policy", [0, 2])
+def test_bench_size_requests_in_full(L, orc, policy):
+    """Requests of the serving benchmark's sizes (payloads of 256 MB to 1 GB
+    beside small ones) in one mix under its 64 GB budget: every destination
+    byte equals the oracle's copy."""
+    g = random.Random(41 + policy)
+    reqs = []
+    for k in range(10):
+        name = g.choice(["particle", "mixed"])
+        ro, rg = orc.Record(W.RECORDS[name]), L.Record(W.RECORDS[name])
+        payload = g.uniform(256e6, 1e9) if k % 2 == 0 else g.uniform(64e3, 8e6)
+        n = int(payload // ro.packed_size)
+        a, b = g.sample(W.LAYOUTS, 2)
+        ms_o, md_o = orc.Mapping(ro, a[0], [n], a[1]), orc.Mapping(ro, b[0], [n], b[1])
+        src = [W.random_bytes(s, 9000 + k * 13 + j) for j, s in enumerate(ms_o.blob_sizes())]
+        want = orc.copy_threads(ms_o, src, md_o)
+        ms, md = L.Mapping(rg, a[0], [n], a[1]), L.Mapping(rg, b[0], [n], b[1])
+        reqs.append({"src": ms, "sd": [torch.from_numpy(x).cuda() for x in src], "dst": md,
+                     "dd": md.alloc(fill=0xCD), "want": want})
+        del src
+    srv = L.Server(64 << 30, policy=policy)
+    torch.cuda.synchronize()
+    tickets = [srv.submit(r["src"], r["sd"], r["dst"], r["dd"]) for r in reqs]
+    for t in tickets:
+        assert srv.wait(t)[0] == L.OK
+    assert srv.stats()["completed"] == len(reqs)
+    srv.close()
+    for r in reqs:
+        check(r)

@@ -665,3 +665,53 @@ def test_copy_leaves_identity_and_permutation(orc):
         got = orc.copy_leaves(mb, _soa_multi_blobs(vals), m, m.alloc(fill=0x5A), perm)
         want = orc.copy(mb, _soa_multi_blobs(sw), m)
         assert all(np.array_equal(a, b) for a, b in zip(want, got)), kind
+
+
+# --------------------------------------------------------------------------
+# the threaded copy used to time the oracle on all host cores (sec. 4 runs one
+# thread per physical core): the same bytes as the serial copy
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["particle", "mixed", "lbm", "listing1"])
+@pytest.mark.parametrize("ext", [[1], [67], [1000], [3, 5, 7]])
+def test_threaded_copy_equals_serial_copy(orc, name, ext):
+    rec = W.RECORDS[name]
+    r = orc.Record(rec)
+    n = int(np.prod(ext))
+    layouts = _layouts(lanes=(1, 8, 32))
+    g = random.Random(hash((name, n)) & 0xFFFF)
+    for a, b in g.sample([(a, b) for a in layouts for b in layouts], 12) + [(("aos_packed", 0), ("aosoa", 8))]:
+        ms, md = orc.Mapping(r, a[0], ext, a[1]), orc.Mapping(r, b[0], ext, b[1])
+        src = [W.random_bytes(s, 5 + k) for k, s in enumerate(ms.blob_sizes())]
+        want = orc.copy(ms, src, md)
+        for threads in (1, 3, 8):
+            got = orc.copy_threads(ms, src, md, [W.random_bytes(s, 9) for s in md.blob_sizes()], threads=threads)
+            assert all(np.array_equal(x, y) for x, y in zip(got, want)), (a, b, threads)
+            kept = [W.random_bytes(s, 11) for s in md.blob_sizes()]
+            want_k = orc.copy(ms, src, md, [x.copy() for x in kept], keep_padding=True)
+            got_k = orc.copy_threads(ms, src, md, kept, keep_padding=True, threads=threads)
+            assert all(np.array_equal(x, y) for x, y in zip(got_k, want_k)), (a, b, threads, "keep")
+
+
+def test_threaded_copy_splits_and_one(orc):
+    r = orc.Record(W.PARTICLE)
+    n = 777
+    S = ("split", (0, 3, ("aosoa", 8), ("soa_multi", 0)))
+    cases = [(S, ("aos_aligned", 0)), (("aos_packed", 0), S), (("one", 0), ("soa_single", 0)),
+             (("aos_packed", 0), ("split", (3, 4, ("one", 0), ("aos_packed", 0))))]
+    for a, b in cases:
+        ms = orc.Mapping(r, a[0], [n], split=a[1]) if a[0] == "split" else orc.Mapping(r, a[0], [n], a[1])
+        md = orc.Mapping(r, b[0], [n], split=b[1]) if b[0] == "split" else orc.Mapping(r, b[0], [n], b[1])
+        src = [W.random_bytes(s, 21 + k) for k, s in enumerate(ms.blob_sizes())]
+        want = orc.copy(ms, src, md)
+        got = orc.copy_threads(ms, src, md, threads=8)
+        assert all(np.array_equal(x, y) for x, y in zip(got, want)), (a, b)
+
+
+def test_memcpy_threads_copies_every_byte(orc):
+    src = W.random_bytes(1 << 20 | 13, 3)
+    for threads in (1, 5, 8):
+        dst = np.zeros(src.size + 7, dtype=np.uint8)
+        used = orc.memcpy_threads(dst, src, threads)
+        assert 1 <= used <= threads
+        assert np.array_equal(dst[:src.size], src) and not dst[src.size:].any()
