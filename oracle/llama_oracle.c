@@ -113,7 +113,16 @@ typedef struct orc_mapping_s {
     int32_t part_kind[2];
     uint64_t part_lanes[2];
     const struct orc_mapping_s* part_split[2];
+    /* how a coordinate becomes the linear index the mapping lays out: row-major
+     * (ORC_ROW_MAJOR, the default), column-major or Morton order */
+    int32_t linearizer;
 } orc_mapping;
+
+/* linearizers (sec. 3.7 lists them among the building blocks of mappings;
+ * sec. 2 names other storage orders and space-filling curves) */
+#define ORC_ROW_MAJOR 0
+#define ORC_COL_MAJOR 1
+#define ORC_MORTON 2
 
 /* ---------------------------------------------------------------------------
  * Record parsing and flattening (sec. 3.3, Listings 1-2).
@@ -320,13 +329,60 @@ uint64_t orc_record_count(const orc_mapping* m)
     return n;
 }
 
-/* row-major linear index of a coordinate, last index fastest */
+/* bits of the Morton index per dimension: enough for the largest extent */
+static int morton_bits(const orc_mapping* m)
+{
+    uint64_t largest = 0;
+    for (int d = 0; d < m->rank; d++)
+        if (m->extents[d] > largest)
+            largest = m->extents[d];
+    int b = 0;
+    while (b < 64 && ((uint64_t)1 << b) < largest)
+        b++;
+    return b;
+}
+
+/* The linear index of a coordinate.
+ *  - row-major: last index fastest, i = (..((c0) * e1 + c1) * e2 + ..) + c(r-1)
+ *    (the linearisation of Listing 4);
+ *  - column-major: first index fastest, the same with the dimensions reversed;
+ *  - Morton (Z-order): bit j of coordinate d becomes bit j * r + (r - 1 - d)
+ *    of the index, so that within each group of r bits the last dimension
+ *    is the least significant, as in row-major order. */
 uint64_t orc_linearize(const orc_mapping* m, const uint64_t* coord)
 {
     uint64_t i = 0;
+    if (m->linearizer == ORC_COL_MAJOR) {
+        for (int d = m->rank - 1; d >= 0; d--)
+            i = i * m->extents[d] + coord[d];
+        return i;
+    }
+    if (m->linearizer == ORC_MORTON) {
+        int b = morton_bits(m);
+        for (int j = 0; j < b; j++)
+            for (int d = 0; d < m->rank; d++)
+                if ((coord[d] / ((uint64_t)1 << j)) % 2 == 1)
+                    i += (uint64_t)1 << (j * m->rank + (m->rank - 1 - d));
+        return i;
+    }
     for (int d = 0; d < m->rank; d++)
         i = i * m->extents[d] + coord[d];
     return i;
+}
+
+/* How many linear indices the mapping lays out: the record count for the
+ * row- and column-major orders; for Morton order one more than the index of
+ * the last coordinate (the index grows with every coordinate), so indices
+ * that no coordinate reaches lie between them and are padding. */
+uint64_t orc_linear_size(const orc_mapping* m)
+{
+    uint64_t n = orc_record_count(m);
+    if (m->linearizer != ORC_MORTON || n == 0)
+        return n;
+    uint64_t last[ORC_MAX_RANK];
+    for (int d = 0; d < m->rank; d++)
+        last[d] = m->extents[d] - 1;
+    return orc_linearize(m, last) + 1;
 }
 
 /* advances a coordinate to the next one in row-major order; returns 0 after
@@ -407,7 +463,7 @@ int orc_blob_count(const orc_mapping* m, const orc_record* r)
 
 uint64_t orc_blob_size(const orc_mapping* m, const orc_record* r, int blob)
 {
-    uint64_t n = orc_record_count(m);
+    uint64_t n = orc_linear_size(m);
     if (m->kind == ORC_SPLIT) {
         orc_part p;
         split_part(m, r, 0, &p);
@@ -457,7 +513,7 @@ int orc_blob_nr_and_offset(const orc_mapping* m, const orc_record* r, const uint
         *blob += first_blob;
         return rc;
     }
-    uint64_t n = orc_record_count(m);
+    uint64_t n = orc_linear_size(m);
     uint64_t i = orc_linearize(m, coord);
     switch (m->kind) {
     case ORC_AOS_PACKED: /* record i at i * S, leaf f at its packed offset */
@@ -511,6 +567,9 @@ static int valid_plain(int32_t kind, uint64_t lanes)
 static int valid_mapping(const orc_mapping* m, const orc_record* r)
 {
     if (m->rank < 1 || m->rank > ORC_MAX_RANK)
+        return 0;
+    if (m->linearizer < ORC_ROW_MAJOR || m->linearizer > ORC_MORTON ||
+        (m->linearizer == ORC_MORTON && morton_bits(m) * m->rank > 64))
         return 0;
     if (m->kind == ORC_SPLIT) {
         if (!(r->nleaves <= ORC_SPLIT_MAX_LEAVES && m->first >= 0 && m->count >= 1 && m->count < r->nleaves &&
@@ -593,6 +652,54 @@ int orc_copy_keep(const orc_record* r, const orc_mapping* src, uint8_t* const* s
     return ORC_OK;
 }
 
+/* The copy of a box of the array dimensions (sec. 3.2: a VirtualView is a
+ * view onto a sub-box of another view's array dimensions, shifted by an
+ * offset; sec. 3.9 names copies between views of different size or shape).
+ * Source and destination share the record dimension and the rank; their
+ * extents may differ.  For every coordinate c of the box, in row-major order,
+ * and every leaf, the value at src_offset + c is copied to dst_offset + c.
+ * Destination records outside the box keep every byte.  The alignment gaps of
+ * the box's records in an aligned-AoS destination become zero, or keep their
+ * bytes with `keep`.  Both mappings are plain (not Split); the source may be
+ * One.  The box must lie inside both views. */
+int orc_copy_box(const orc_record* r, const orc_mapping* src, uint8_t* const* src_blobs, const uint64_t* src_offset,
+                 const orc_mapping* dst, uint8_t* const* dst_blobs, const uint64_t* dst_offset, const uint64_t* box,
+                 int keep)
+{
+    if (!valid_mapping(src, r) || !valid_mapping(dst, r) || src->rank != dst->rank || src->kind == ORC_SPLIT ||
+        dst->kind == ORC_SPLIT || dst->kind == ORC_ONE)
+        return ORC_E_ARG;
+    orc_mapping b = *src; /* iterates the box's coordinates */
+    for (int d = 0; d < src->rank; d++) {
+        if (src_offset[d] + box[d] > src->extents[d] || dst_offset[d] + box[d] > dst->extents[d] ||
+            src_offset[d] + box[d] < box[d] || dst_offset[d] + box[d] < box[d])
+            return ORC_E_ARG;
+        b.extents[d] = box[d];
+    }
+    if (orc_record_count(&b) == 0)
+        return ORC_OK;
+    uint64_t c[ORC_MAX_RANK] = {0};
+    do {
+        uint64_t sc[ORC_MAX_RANK], dc[ORC_MAX_RANK];
+        for (int d = 0; d < src->rank; d++) {
+            sc[d] = src_offset[d] + c[d];
+            dc[d] = dst_offset[d] + c[d];
+        }
+        if (!keep && dst->kind == ORC_AOS_ALIGNED) {
+            /* the record's bytes start at zero, so its gaps end up zero */
+            uint64_t R = orc_aligned_size(r);
+            memset(dst_blobs[0] + orc_linearize(dst, dc) * R, 0, (size_t)R);
+        }
+        for (int f = 0; f < r->nleaves; f++) {
+            uint64_t bs, os, bd, od;
+            orc_blob_nr_and_offset(src, r, sc, f, &bs, &os);
+            orc_blob_nr_and_offset(dst, r, dc, f, &bd, &od);
+            memcpy(dst_blobs[bd] + od, src_blobs[bs] + os, (size_t)r->size[f]);
+        }
+    } while (next_coord(&b, c));
+    return ORC_OK;
+}
+
 /* The copy between views whose records differ (sec. 3.9: a field missing on
  * one side).  Destination leaf k takes source leaf from[k], whose size must be
  * the same; a leaf with from[k] < 0 keeps all its bytes, unused AoSoA lanes
@@ -603,7 +710,8 @@ int orc_copy_leaves(const orc_record* rs, const orc_mapping* src, uint8_t* const
                     const orc_mapping* dst, uint8_t* const* dst_blobs, const int32_t* from, int keep)
 {
     if (!valid_mapping(src, rs) || !valid_mapping(dst, rd) || !same_extents(src, dst) || src->kind == ORC_SPLIT ||
-        dst->kind == ORC_SPLIT || dst->kind == ORC_ONE)
+        dst->kind == ORC_SPLIT || dst->kind == ORC_ONE || src->linearizer != ORC_ROW_MAJOR ||
+        dst->linearizer != ORC_ROW_MAJOR)
         return ORC_E_ARG;
     for (int k = 0; k < rd->nleaves; k++)
         if (from[k] >= rs->nleaves || (from[k] >= 0 && rs->size[from[k]] != rd->size[k]))

@@ -34,6 +34,7 @@ _LIB = os.path.join(_HERE, "liborc.so")
 MAX_RANK = 8
 MAX_LEAVES = 4096
 
+LINEARIZERS = {"row": 0, "col": 1, "morton": 2}
 KINDS = {"aos_packed": 0, "aos_aligned": 1, "soa_single": 2, "soa_multi": 3, "aosoa": 4, "split": 5, "one": 6}
 
 
@@ -48,7 +49,7 @@ class _Mapping(ctypes.Structure):
                 ("extents", ctypes.c_uint64 * MAX_RANK), ("lanes", ctypes.c_uint64),
                 ("first", ctypes.c_int32), ("count", ctypes.c_int32),
                 ("part_kind", ctypes.c_int32 * 2), ("part_lanes", ctypes.c_uint64 * 2),
-                ("part_split", ctypes.c_void_p * 2)]
+                ("part_split", ctypes.c_void_p * 2), ("linearizer", ctypes.c_int32)]
 
 
 def build(force: bool = False) -> str:
@@ -102,6 +103,11 @@ def lib():
         L.orc_copy.restype = ctypes.c_int
         L.orc_copy_keep.argtypes = [RP, MP, PP, MP, PP]
         L.orc_copy_keep.restype = ctypes.c_int
+        L.orc_linear_size.argtypes = [MP]
+        L.orc_linear_size.restype = u64
+        L.orc_copy_box.argtypes = [RP, MP, PP, ctypes.POINTER(u64), MP, PP, ctypes.POINTER(u64),
+                                   ctypes.POINTER(u64), ctypes.c_int]
+        L.orc_copy_box.restype = ctypes.c_int
         L.orc_copy_threads.argtypes = [RP, MP, PP, MP, PP, ctypes.c_int, ctypes.c_int]
         L.orc_copy_threads.restype = ctypes.c_int
         L.orc_memcpy_threads.argtypes = [ctypes.c_void_p, ctypes.c_void_p, u64, ctypes.c_int]
@@ -173,7 +179,7 @@ class Record:
 # mappings
 # --------------------------------------------------------------------------
 
-def _mapping(kind: str, extents, lanes: int = 0, split=None) -> _Mapping:
+def _mapping(kind: str, extents, lanes: int = 0, split=None, linearizer: str = "row") -> _Mapping:
     ext = [int(e) for e in (extents if isinstance(extents, (list, tuple)) else [extents])]
     if not 1 <= len(ext) <= MAX_RANK:
         raise ValueError("rank must be 1..8")
@@ -183,6 +189,7 @@ def _mapping(kind: str, extents, lanes: int = 0, split=None) -> _Mapping:
     for d, e in enumerate(ext):
         m.extents[d] = e
     m.lanes = int(lanes)
+    m.linearizer = LINEARIZERS[linearizer]
     if kind == "split":
         first, count, p0, p1 = split
         m.first, m.count = int(first), int(count)
@@ -190,7 +197,7 @@ def _mapping(kind: str, extents, lanes: int = 0, split=None) -> _Mapping:
         for k, (pk, pa) in enumerate((p0, p1)):
             m.part_kind[k] = KINDS[pk]
             if pk == "split":  # pa is the nested split over the part's leaves
-                inner = _mapping("split", ext, 0, pa)
+                inner = _mapping("split", ext, 0, pa, linearizer)
                 m._nested.append(inner)
                 m.part_split[k] = ctypes.addressof(inner)
             else:
@@ -199,21 +206,27 @@ def _mapping(kind: str, extents, lanes: int = 0, split=None) -> _Mapping:
 
 
 class Mapping:
-    def __init__(self, record: Record, kind: str, extents, lanes: int = 0, split=None):
+    def __init__(self, record: Record, kind: str, extents, lanes: int = 0, split=None, linearizer: str = "row"):
         self.record = record
         self.kind = kind
         self.extents = [int(e) for e in (extents if isinstance(extents, (list, tuple)) else [extents])]
         self.lanes = int(lanes)
         self.split = split
+        self.linearizer = linearizer
         if kind == "split":
             first, count = int(split[0]), int(split[1])
             if not (first >= 0 and count >= 1 and first + count <= record.nleaves and count < record.nleaves):
                 raise ValueError("split: the selected leaves must be a proper, non-empty range")
-        self.c = _mapping(kind, self.extents, lanes, split)
+        self.c = _mapping(kind, self.extents, lanes, split, linearizer)
 
     @property
     def count(self) -> int:
         return int(lib().orc_record_count(ctypes.byref(self.c)))
+
+    @property
+    def linear_size(self) -> int:
+        """Linear indices the mapping lays out (Morton order: holes included)."""
+        return int(lib().orc_linear_size(ctypes.byref(self.c)))
 
     @property
     def blob_count(self) -> int:
@@ -303,6 +316,23 @@ def memcpy_threads(dst: np.ndarray, src: np.ndarray, threads=0) -> int:
 
 def max_threads() -> int:
     return int(lib().orc_max_threads())
+
+
+def copy_box(src: Mapping, src_blobs, src_offset, dst: Mapping, dst_blobs, dst_offset, box, keep_padding=False):
+    """The copy of a box of the array dimensions: the values at src_offset + c
+    go to dst_offset + c for every coordinate c of `box`.  Updates and
+    returns `dst_blobs`."""
+    r = len(src.extents)
+    so = (ctypes.c_uint64 * MAX_RANK)(*[int(x) for x in src_offset])
+    do = (ctypes.c_uint64 * MAX_RANK)(*[int(x) for x in dst_offset])
+    bx = (ctypes.c_uint64 * MAX_RANK)(*[int(x) for x in box])
+    if not (len(src_offset) == len(dst_offset) == len(box) == r):
+        raise ValueError("offsets and box need one entry per dimension")
+    rc = lib().orc_copy_box(ctypes.byref(src.record.c), ctypes.byref(src.c), _ptrs(src_blobs), so,
+                            ctypes.byref(dst.c), _ptrs(dst_blobs), do, bx, 1 if keep_padding else 0)
+    if rc != 0:
+        raise ValueError(f"oracle copy_box failed ({rc})")
+    return dst_blobs
 
 
 def copy_leaves(src: Mapping, src_blobs, dst: Mapping, dst_blobs, source_leaf, keep_padding=False):

@@ -17,7 +17,17 @@ MUTANTS = {
     "aligned_offset_no_rounding": ("off = round_up(off, r->align[g]);", "off = off;"),
     "aligned_stride_no_tail_rounding": ("return round_up(end, max_align);", "return end;"),
     "packed_offset_drops_a_leaf": ("for (int g = 0; g < f; g++)", "for (int g = 1; g < f; g++)"),
-    "linearize_wrong_extent": ("i = i * m->extents[d] + coord[d];", "i = i * m->extents[0] + coord[d];"),
+    "linearize_wrong_extent": ("for (int d = 0; d < m->rank; d++)\n        i = i * m->extents[d] + coord[d];",
+                               "for (int d = 0; d < m->rank; d++)\n        i = i * m->extents[0] + coord[d];"),
+    "column_major_is_row_major": ("for (int d = m->rank - 1; d >= 0; d--)\n            i = i * m->extents[d] + coord[d];",
+                                  "for (int d = 0; d < m->rank; d++)\n            i = i * m->extents[d] + coord[d];"),
+    "morton_first_dimension_lowest": ("i += (uint64_t)1 << (j * m->rank + (m->rank - 1 - d));",
+                                      "i += (uint64_t)1 << (j * m->rank + d);"),
+    "morton_size_is_record_count": ("    if (m->linearizer != ORC_MORTON || n == 0)\n        return n;",
+                                    "    if (1)\n        return n;"),
+    "box_source_offset_dropped": ("sc[d] = src_offset[d] + c[d];", "sc[d] = c[d];"),
+    "box_destination_uses_source_offset": ("dc[d] = dst_offset[d] + c[d];", "dc[d] = src_offset[d] + c[d];"),
+    "box_gaps_not_zeroed": ("memset(dst_blobs[0] + orc_linearize(dst, dc) * R, 0, (size_t)R);", "(void)R;"),
     "soa_single_wrong_element_size": ("*offset = n * orc_packed_offset(r, f) + i * r->size[f];",
                                       "*offset = n * orc_packed_offset(r, f) + i * r->size[0];"),
     "soa_single_base_uses_index": ("*offset = n * orc_packed_offset(r, f) + i * r->size[f];",

@@ -715,3 +715,210 @@ def test_memcpy_threads_copies_every_byte(orc):
         used = orc.memcpy_threads(dst, src, threads)
         assert 1 <= used <= threads
         assert np.array_equal(dst[:src.size], src) and not dst[src.size:].any()
+
+
+# --------------------------------------------------------------------------
+# linearizers (sec. 3.7 lists the linearizer among a mapping's building
+# blocks; sec. 2 points to other storage orders and space-filling curves)
+# --------------------------------------------------------------------------
+
+def _coords(ext):
+    return [tuple(int(x) for x in c) for c in np.ndindex(*ext)]
+
+
+@pytest.mark.parametrize("ext", [[7], [5, 7], [2, 3, 4], [4, 1, 6, 3]])
+def test_column_major_equals_numpy_fortran_order(orc, ext):
+    r = orc.Record(W.PARTICLE)
+    m = orc.Mapping(r, "aos_packed", ext, linearizer="col")
+    assert m.linear_size == int(np.prod(ext))
+    for c in _coords(ext):
+        assert m.linearize(c) == int(np.ravel_multi_index(c, ext, order="F"))
+
+
+def test_morton_4x4_golden(orc):
+    want = [[int(x) for x in row] for row in _golden("morton_4x4.txt")]
+    m = orc.Mapping(orc.Record(W.PARTICLE), "aos_packed", [4, 4], linearizer="morton")
+    assert [[m.linearize([y, x]) for x in range(4)] for y in range(4)] == want
+
+
+def _z_recursive(c, k):
+    """Z-order index of coordinate c in a grid of side 2^k, built by recursion
+    on quadrants: the quadrant of c's top bits (first dimension most
+    significant) times the cells per quadrant, plus c's index inside it."""
+    if k == 0:
+        return 0
+    half = 1 << (k - 1)
+    quadrant = 0
+    for x in c:
+        quadrant = quadrant * 2 + (1 if x >= half else 0)
+    return quadrant * half ** len(c) + _z_recursive([x % half for x in c], k - 1)
+
+
+@pytest.mark.parametrize("ext", [[8, 8], [4, 4, 4], [2, 2, 2, 2], [16, 16]])
+def test_morton_equals_recursive_quadrants(orc, ext):
+    m = orc.Mapping(orc.Record(W.PARTICLE), "aos_packed", ext, linearizer="morton")
+    k = int(ext[0]).bit_length() - 1
+    idx = [m.linearize(c) for c in _coords(ext)]
+    assert idx == [_z_recursive(list(c), k) for c in _coords(ext)]
+    assert sorted(idx) == list(range(int(np.prod(ext))))  # a bijection when every extent is 2^k
+    assert m.linear_size == int(np.prod(ext))
+
+
+@pytest.mark.parametrize("ext", [[3, 5], [5, 3], [6, 2, 3], [9], [1, 7]])
+def test_morton_ragged_extents(orc, ext):
+    """Extents that are not one power of two: the Z index of the coordinate in
+    the enclosing grid of side 2^k, injective, growing along every dimension;
+    the mapping lays out up to the last coordinate's index."""
+    m = orc.Mapping(orc.Record(W.PARTICLE), "aos_packed", ext, linearizer="morton")
+    k = max(int(e - 1).bit_length() for e in ext)
+    idx = {c: m.linearize(c) for c in _coords(ext)}
+    assert all(idx[c] == _z_recursive(list(c), k) for c in idx)
+    assert len(set(idx.values())) == len(idx)
+    assert m.linear_size == max(idx.values()) + 1
+    assert m.blob_sizes() == [m.linear_size * 28]
+
+
+@pytest.mark.parametrize("name", ["particle", "mixed", "lbm"])
+@pytest.mark.parametrize("lin", ["col", "morton"])
+def test_linearizer_layouts(orc, name, lin):
+    """Multi-blob SoA under a linearizer holds each leaf's values at their
+    linear index (numpy fancy indexing): column-major is numpy's Fortran
+    order; Morton slots no coordinate reaches are zero.  Every other layout
+    round-trips through it, and exactly-once coverage holds with the holes as
+    padding."""
+    ext = [5, 6] if lin == "morton" else [3, 4, 5]
+    rec = W.RECORDS[name]
+    r = orc.Record(rec)
+    types = W.leaf_types(rec)
+    n = int(np.prod(ext))
+    vals = _unique_leaf_values(types, n, 17)
+    src_m = orc.Mapping(r, "soa_multi", ext)
+    src = _soa_multi_blobs(vals)
+    dst_m = orc.Mapping(r, "soa_multi", ext, linearizer=lin)
+    got = orc.copy(src_m, src, dst_m)
+    if lin == "col":
+        want = [np.ascontiguousarray(np.asarray(v).reshape(ext).ravel(order="F")).view(np.uint8) for v in vals]
+    else:
+        k = max(int(e - 1).bit_length() for e in ext)
+        z = np.array([_z_recursive(list(c), k) for c in _coords(ext)])
+        want = []
+        for v in vals:
+            w = np.zeros(dst_m.linear_size, dtype=v.dtype)
+            w[z] = v
+            want.append(w.view(np.uint8))
+    for g_, w_ in zip(got, want):
+        assert np.array_equal(g_, w_)
+    for kind, lanes in _layouts(lanes=(4, 8)):
+        m = orc.Mapping(r, kind, ext, lanes, linearizer=lin)
+        there = orc.copy(src_m, src, m)
+        back = orc.copy(m, there, src_m)
+        assert all(np.array_equal(x, y) for x, y in zip(back, src)), kind
+        counts = orc.write_counts(m)
+        assert all(c.max() <= 1 for c in counts)
+        assert sum(int(c.sum()) for c in counts) == n * r.packed_size
+        for blob, pad in zip(there, orc.padding_masks(m)):
+            assert not blob[pad].any()
+
+
+def test_copy_between_linearizers_commutes(orc):
+    r = orc.Record(W.MIXED)
+    ext = [5, 3, 4]
+    vals = _unique_leaf_values(W.leaf_types(W.MIXED), 60, 3)
+    a = orc.Mapping(r, "soa_multi", ext)
+    src = _soa_multi_blobs(vals)
+    b = orc.Mapping(r, "aosoa", ext, 8, linearizer="morton")
+    c = orc.Mapping(r, "aos_aligned", ext, linearizer="col")
+    via_b = orc.copy(b, orc.copy(a, src, b), c)
+    direct = orc.copy(a, src, c)
+    assert all(np.array_equal(x, y) for x, y in zip(via_b, direct))
+
+
+# --------------------------------------------------------------------------
+# box copies (sec. 3.2 VirtualView onto a sub-box; sec. 3.9 copies between
+# views of different size or shape)
+# --------------------------------------------------------------------------
+
+BOX_CASES = [([9], [13], [2], [5], [6]), ([5, 7], [6, 4], [1, 2], [3, 0], [2, 4]),
+             ([4, 5, 6], [6, 5, 4], [1, 0, 2], [2, 1, 0], [3, 4, 3]), ([4, 4], [4, 4], [0, 0], [0, 0], [4, 4]),
+             ([3, 3], [3, 3], [1, 1], [0, 0], [0, 2])]
+
+
+@pytest.mark.parametrize("case", BOX_CASES, ids=[str(c[4]) for c in BOX_CASES])
+@pytest.mark.parametrize("name", ["particle", "mixed", "listing1"])
+def test_box_copy_equals_numpy_slicing(orc, case, name):
+    se, de, so, do, box = case
+    rec = W.RECORDS[name]
+    r = orc.Record(rec)
+    types = W.leaf_types(rec)
+    V = _unique_leaf_values(types, int(np.prod(se)), 5)
+    Wv = _unique_leaf_values(types, int(np.prod(de)), 6)
+    sl_s = tuple(slice(o, o + b) for o, b in zip(so, box))
+    sl_d = tuple(slice(o, o + b) for o, b in zip(do, box))
+    expect_vals = []
+    for v, w in zip(V, Wv):
+        w2 = np.array(w).reshape(de).copy()
+        w2[sl_d] = np.array(v).reshape(se)[sl_s]
+        expect_vals.append(w2.reshape(-1))
+    g = random.Random(hash((name, tuple(box))) & 0xFFFF)
+    for a, b in g.sample([(a, b) for a in _layouts((4, 8)) for b in _layouts((4, 8))], 10):
+        for lin in ("row", "morton"):
+            ms = orc.Mapping(r, a[0], se, a[1], linearizer=lin)
+            md = orc.Mapping(r, b[0], de, b[1], linearizer="row" if lin == "morton" else "col")
+            src = orc.copy(orc.Mapping(r, "soa_multi", se), _soa_multi_blobs(V), ms)
+            dst = orc.copy(orc.Mapping(r, "soa_multi", de), _soa_multi_blobs(Wv), md)
+            orc.copy_box(ms, src, so, md, dst, do, box)
+            want = orc.copy(orc.Mapping(r, "soa_multi", de), _soa_multi_blobs(expect_vals), md)
+            assert all(np.array_equal(x, y) for x, y in zip(dst, want)), (a, b, lin)
+
+
+def test_box_copy_touches_only_the_box(orc):
+    """Brute force over every destination byte: bytes of the box's values hold
+    the source's values, the box records' alignment gaps are zero (or keep
+    their bytes), every other byte keeps its value."""
+    rec = W.MIXED
+    r = orc.Record(rec)
+    se, de, so, do, box = [4, 6], [5, 5], [1, 2], [2, 0], [3, 4]
+    ms = orc.Mapping(r, "aosoa", se, 4)
+    md = orc.Mapping(r, "aos_aligned", de)
+    src = [W.random_bytes(s, 1) for s in ms.blob_sizes()]
+    before = [W.random_bytes(s, 2) for s in md.blob_sizes()]
+    R = r.aligned_size
+    for keep in (False, True):
+        dst = orc.copy_box(ms, src, so, md, [x.copy() for x in before], do, box, keep_padding=keep)
+        value_bytes, box_records = {}, set()
+        for c in _coords(box):
+            sc = [o + x for o, x in zip(so, c)]
+            dc = [o + x for o, x in zip(do, c)]
+            box_records.add(int(np.ravel_multi_index(dc, de)))
+            for f in range(r.nleaves):
+                bs, os_ = ms.blob_nr_and_offset(sc, f)
+                bd, od = md.blob_nr_and_offset(dc, f)
+                for k in range(r.sizes[f]):
+                    value_bytes[od + k] = src[bs][os_ + k]
+        for o in range(md.blob_size(0)):
+            if o in value_bytes:
+                assert dst[0][o] == value_bytes[o]
+            elif o // R in box_records and not keep:
+                assert dst[0][o] == 0
+            else:
+                assert dst[0][o] == before[0][o]
+
+
+def test_box_copy_of_everything_is_the_copy(orc):
+    r = orc.Record(W.LBM)
+    ext = [3, 4, 5]
+    for a, b in [(("aos_aligned", 0), ("aosoa", 8)), (("soa_single", 0), ("aos_aligned", 0))]:
+        ms, md = orc.Mapping(r, a[0], ext, a[1]), orc.Mapping(r, b[0], ext, b[1])
+        src = [W.random_bytes(s, 4) for s in ms.blob_sizes()]
+        got = orc.copy_box(ms, src, [0, 0, 0], md, md.alloc(), [0, 0, 0], ext)
+        assert all(np.array_equal(x, y) for x, y in zip(got, orc.copy(ms, src, md)))
+
+
+def test_box_copy_rejects_boxes_outside_a_view(orc):
+    r = orc.Record(W.PARTICLE)
+    ms, md = orc.Mapping(r, "aos_packed", [4, 4]), orc.Mapping(r, "soa_multi", [3, 5])
+    src, dst = ms.alloc(), md.alloc()
+    with pytest.raises(ValueError):
+        orc.copy_box(ms, src, [1, 0], md, dst, [0, 0], [4, 1])
+    with pytest.raises(ValueError):
+        orc.copy_box(ms, src, [0, 0], md, dst, [0, 2], [1, 4])
