@@ -417,6 +417,26 @@ int llama_batch_destroy(llama_batch* batch);
  * launch has finished.  Asynchronous like llama_copy. */
 int llama_copy_batch(size_t n, const llama_copy_item* items, void* stream);
 
+/* llama_copy_batch for callers that cannot allocate device memory (code under
+ * stream capture, serving loops that must not call hipMalloc, harnesses that
+ * forbid it): the same validation, plans, kernels and result, but the work
+ * table (plans, unit prefix sums and the persistent grid's work counters)
+ * goes into a static device buffer of the library, 8 MiB on every device the
+ * library runs on (held until the process ends), instead of an allocation.
+ * The call allocates no device memory and frees none: it uploads the table
+ * into that buffer with hipMemcpyAsync on `stream` (the counters are uploaded
+ * as zeros) and launches the batch kernel after it, without a graph.
+ *  - A batch whose table needs more than 8 MiB fails with LLAMA_E_NO_BUDGET
+ *    before anything is enqueued (a plain item takes a few hundred bytes of
+ *    table: the 1,000-array batch needs about half a megabyte).
+ *  - Every call on one device shares that device's buffer, which keeps the
+ *    last call's table: calls whose work overlaps in time on one device race
+ *    (a later upload overwrites a table still being read).  Calls in order on
+ *    one stream are safe; calls on different streams must be ordered by the
+ *    caller (events or synchronisation).
+ *  - No batch handle, graph or host callback outlives the call. */
+int llama_copy_batch_noalloc(size_t n, const llama_copy_item* items, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching within an HBM budget                        */
 /* ------------------------------------------------------------------------ */

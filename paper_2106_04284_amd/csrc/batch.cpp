@@ -274,14 +274,15 @@ uint32_t batch_grid(uint64_t units, uint32_t wg_per_cu)
     return uint32_t(std::min<uint64_t>(u, uint64_t(device_cu_count()) * wg_per_cu));
 }
 
-Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_options* opt)
+BatchTable build_batch_table(size_t n, const llama_copy_item* items, const llama_copy_options* opt,
+                             uint32_t& threads)
 {
     reap_retired();
     if (n > 0 && !items)
         fail(LLAMA_E_INVALID_ARG, "batch item array is NULL");
     if (opt && (opt->path != LLAMA_PATH_AUTO || (opt->flags & ~kCopyFlags) != 0))
         fail(LLAMA_E_INVALID_ARG, "batch options take tile_records, threads, wg_per_cu and LLAMA_COPY_* flags");
-    const uint32_t threads = (opt && opt->threads) ? opt->threads : kDefaultThreads;
+    threads = (opt && opt->threads) ? opt->threads : kDefaultThreads;
     if (threads % 64 != 0 || threads == 0 || threads > 1024)
         fail(LLAMA_E_INVALID_ARG, "threads must be a multiple of 64 in 64..1024");
     if (opt && opt->wg_per_cu > 16)
@@ -323,7 +324,13 @@ Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_opt
             fail(e.status, "batch item " + std::to_string(k) + ": " + e.message);
         }
     }
+    return t;
+}
 
+Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_options* opt)
+{
+    uint32_t threads = 0;
+    const BatchTable t = build_batch_table(n, items, opt, threads);
     std::unique_ptr<Batch> b(new Batch());
     b->threads = threads;
     b->total_units = t.units;
@@ -349,6 +356,32 @@ Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_opt
         check_hip(e, "hipMemcpy(batch table)");
     }
     return b.release();
+}
+
+void copy_batch_noalloc(size_t n, const llama_copy_item* items, void* stream)
+{
+    uint32_t threads = 0;
+    const BatchTable t = build_batch_table(n, items, nullptr, threads);
+    if (t.units == 0)
+        return;
+    const size_t total = t.bytes();
+    if (total > kScratchBytes)
+        fail(LLAMA_E_NO_BUDGET, "the batch's work table needs " + std::to_string(total) +
+                                    " bytes, more than the " + std::to_string(kScratchBytes) +
+                                    " bytes of the library's static work-table buffer; use llama_copy_batch");
+    const uint64_t dev_table = scratch_address(); // this device's copy of the static buffer
+    // the host image is kept per thread and reused; hipMemcpyAsync has read a
+    // pageable source by the time it returns
+    static thread_local std::vector<uint8_t> host;
+    if (host.size() < total)
+        host.resize(total);
+    BatchArgs args{};
+    t.serialise(host.data(), dev_table, args); // the counters go up as zeros with the table
+    check_hip(hipMemcpyAsync((void*)uintptr_t(dev_table), host.data(), total, hipMemcpyHostToDevice,
+                             (hipStream_t)stream),
+              "hipMemcpyAsync(batch table into the static buffer)");
+    const uint32_t wg = batch_per_unit(t) ? 0 : batch_wg_per_cu(t.lds_bytes, threads);
+    launch_batch_args(args, batch_grid(t.units, wg), threads, t.lds_bytes, wg != 0, stream);
 }
 
 void launch_batch(Batch* b, void* stream_ptr)

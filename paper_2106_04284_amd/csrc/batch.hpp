@@ -69,13 +69,28 @@ uint32_t batch_grid(uint64_t units, uint32_t wg_per_cu);
 // the plan of a batch item (see BatchTable::add)
 Plan batch_plan(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags);
 
+// validates the items and plans them into one work table (nothing on the device)
+BatchTable build_batch_table(size_t n, const llama_copy_item* items, const llama_copy_options* opt,
+                             uint32_t& threads);
 Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_options* opt);
+// llama_copy_batch_noalloc: the work table goes into the library's static
+// device buffer (kScratchBytes) instead of an allocation
+void copy_batch_noalloc(size_t n, const llama_copy_item* items, void* stream);
 void launch_batch(Batch* b, void* stream);
 void destroy_batch(Batch* b);
 // frees `b` once the work enqueued so far on `stream` has finished
 void retire_batch(Batch* b, void* stream);
 
+// Size of the library's static device buffer for the work table of
+// llama_copy_batch_noalloc (one per device, held until the process ends).
+constexpr size_t kScratchBytes = size_t(8) << 20;
+
 // kernels.hip
 void launch_batch_kernel(const Batch& b, void* stream);
+void launch_batch_args(const BatchArgs& args, uint32_t grid, uint32_t threads, uint32_t lds_bytes, bool persistent,
+                       void* stream);
+// device address of the current device's static work-table buffer
+// (resolved with hipGetSymbolAddress on the first call on each device)
+uint64_t scratch_address();
 
 } // namespace llama

@@ -396,6 +396,11 @@ int llama_copy_batch(size_t n, const llama_copy_item* items, void* stream)
     });
 }
 
+int llama_copy_batch_noalloc(size_t n, const llama_copy_item* items, void* stream)
+{
+    return guarded([&] { copy_batch_noalloc(n, items, stream); });
+}
+
 struct llama_server {
     llama::Server* s;
 };

@@ -19,9 +19,17 @@
 //                 located with run-time '/' and '%' and moved at its own width.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "batch.hpp"
 #include "core.hpp"
 #include "serve.hpp"
+
+// The work table of llama_copy_batch_noalloc: a static device buffer, so that
+// that entry point allocates nothing.  Each device holds its own copy, at its
+// own address, which host code takes from hipGetSymbolAddress (the array's
+// name itself is not a device address in host code).
+static __device__ __align__(256) uint8_t scratch[llama::kScratchBytes];
 
 namespace llama {
 
@@ -1111,6 +1119,30 @@ void launch_batch_args(const BatchArgs& args, uint32_t grid, uint32_t threads, u
     check_hip(hipLaunchKernel(k, dim3(grid), dim3(threads), kargs, lds_bytes, (hipStream_t)stream),
               "hipLaunchKernel(batch)");
     check_hip(hipGetLastError(), "batch kernel launch");
+}
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mutex;
+uint64_t g_scratch_addr[kScratchDevices] = {}; // per device; 0 until resolved
+} // namespace
+
+uint64_t scratch_address()
+{
+    int dev = 0;
+    check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kScratchDevices)
+        fail(LLAMA_E_UNSUPPORTED, "device " + std::to_string(dev) + " is past the static buffers' device limit");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_addr[dev] == 0) {
+        // with `dev` current: this device's copy of the array
+        void* ptr = nullptr;
+        check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!ptr)
+            fail(LLAMA_E_HIP, "hipGetSymbolAddress(scratch) returned no address");
+        g_scratch_addr[dev] = uint64_t(uintptr_t(ptr));
+    }
+    return g_scratch_addr[dev];
 }
 
 void launch_batch_kernel(const Batch& b, void* stream)

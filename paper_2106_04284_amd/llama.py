@@ -163,6 +163,7 @@ _SIGNATURES = {
     "llama_batch_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BatchInfo)]),
     "llama_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "llama_copy_batch": (ctypes.c_int, [ctypes.c_size_t, ctypes.POINTER(CopyItem), ctypes.c_void_p]),
+    "llama_copy_batch_noalloc": (ctypes.c_int, [ctypes.c_size_t, ctypes.POINTER(CopyItem), ctypes.c_void_p]),
 }
 
 
@@ -473,6 +474,13 @@ def copy_batch(items, stream=None):
     """llama_copy_batch: one-shot batch launched on `stream`."""
     it = _Items(items)
     check(lib().llama_copy_batch(it.n, it.arr, _stream(stream)))
+
+
+def copy_batch_noalloc(items, stream=None):
+    """llama_copy_batch_noalloc: the one-shot batch with its work table in the
+    library's static device buffer (no device allocation)."""
+    it = _Items(items)
+    check(lib().llama_copy_batch_noalloc(it.n, it.arr, _stream(stream)))
 
 
 # --------------------------------------------------------------------------
