@@ -22,7 +22,13 @@ Other workloads (--workload):
   serve  a Poisson trace of copy requests against the request server at
          offered loads of 0.5 and 0.8 of the batch's GB/s (p50/p99 latency);
   pic    4,096 particle-in-cell frames of 256 records, SoA <-> AoSoA32, as
-         one batch launch per direction against per-frame launches.
+         one batch launch per direction against per-frame launches;
+  box    sub-box copies: the 256^3 interior of a 258^3 lattice-Boltzmann
+         grid into a 256^3 grid of another layout (sec. 3.2 VirtualView);
+  linearize  2^26 particles on an 8192 x 8192 grid between row-major,
+         column-major and Morton views (sec. 3.7 linearizers);
+  transfer   host <-> device copies with a layout change, chunked and
+         overlapped (sec. 3.9), against unchunked and raw memcpy.
 """
 from __future__ import annotations
 
@@ -335,14 +341,14 @@ def bench_batch(L, torch, args, dev, stream):
     def timed(fn, reps):
         return _timed(torch, stream, fn, reps)
 
-    best = None
-    for th in (128, 256):
-        b = L.Batch(items, threads=th)
-        med, mn = timed(lambda: b.launch(stream), 3)
-        log(f"batch: threads {th}: {total / (med * 1e-3) / 1e9:.1f} GB/s")
-        if best is None or med < best[1]:
-            best = (b, med, th)
-    b, _, th = best
+    # the default plan (largest tile in 31 KiB of LDS, 256 threads), then the
+    # batch's autotuner choosing LDS budget, threads and grid on these arrays
+    b = L.Batch(items)
+    heur_med, _ = timed(lambda: b.launch(stream), 3)
+    log(f"batch: default plan {total / (heur_med * 1e-3) / 1e9:.1f} GB/s; autotuning the batch")
+    tuned_gbs = b.autotune(stream=stream, reps=2)
+    th = b.info()["threads"]
+    log(f"batch: autotuned {tuned_gbs:.1f} GB/s (threads {th}, lds {b.info()['lds_bytes']})")
     med, mn = timed(lambda: b.launch(stream), args.steps)
     info = b.info()
     log("batch: timing 1,000 per-array naive launches and 1,000 per-array llama_copy launches")
@@ -356,9 +362,12 @@ def bench_batch(L, torch, args, dev, stream):
                                    "{f64[3],f32[4],i32[2],u8} record, random ordered layout pair of 42; one "
                                    "hipGraph-captured launch",
                        "bytes_per_step": total, "arrays": len(items), "threads": th, "work_units": info["work_units"],
-                       "workgroups": info["workgroups"], "tuned_classes": tuned},
+                       "workgroups": info["workgroups"], "wg_per_cu": info["wg_per_cu"],
+                       "lds_bytes": info["lds_bytes"], "tuned_classes": tuned},
             "hbm_peak_frac": round(gbs / HBM_PEAK_GBS, 4),
             "extras": {"batched_ms_min": round(mn, 3),
+                       "default_plan_gbs": round(total / (heur_med * 1e-3) / 1e9, 1),
+                       "autotuned_vs_default": round(heur_med / med, 3),
                        "naive_per_array_gbs": round(total / (naive_med * 1e-3) / 1e9, 1),
                        "llama_copy_per_array_gbs": round(total / (lone_med * 1e-3) / 1e9, 1),
                        "batched_vs_naive": round(naive_med / med, 2),
@@ -582,12 +591,206 @@ def bench_serve(L, torch, args, dev):
             "device": dev.name}
 
 
+def _time_calls(torch, stream, calls, steps, warmup):
+    """Times named calls (name, fn, bytes) `steps` times each with HIP events
+    around every call; returns the whole-step milliseconds and per-call
+    medians and means."""
+    for _ in range(warmup):
+        for _, fn, _ in calls:
+            fn()
+    torch.cuda.synchronize()
+    ev = {name: [] for name, _, _ in calls}
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        for name, fn, _ in calls:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            ev[name].append((e0, e1))
+    end.record(stream)
+    torch.cuda.synchronize()
+    per = {}
+    for name, _, nb in calls:
+        ms = [e0.elapsed_time(e1) for e0, e1 in ev[name]]
+        per[name] = {"bytes": nb, "ms_median": statistics.median(ms), "ms_mean": statistics.mean(ms),
+                     "gbs_median": nb / (statistics.median(ms) * 1e-3) / 1e9}
+    return start.elapsed_time(end), per
+
+
+def _box_line(L, torch, args, dev, stream, workload, calls, naive_calls, record, dtype, extra_config):
+    total_ms, per = _time_calls(torch, stream, calls, args.steps, args.warmup)
+    step_bytes = sum(nb for _, _, nb in calls)
+    value = step_bytes * args.steps / (total_ms * 1e-3) / 1e9
+    box_ms = statistics.mean(v["ms_mean"] for v in per.values())
+    box_bytes = statistics.mean(v["bytes"] for v in per.values())
+    achieved = box_bytes / (box_ms * 1e-3) / 1e9
+    extras = {"pairs": {k: round(v["gbs_median"], 1) for k, v in per.items()}}
+    if naive_calls and not args.no_naive:
+        log(f"{args.workload}: timing the element-wise box baseline")
+        _, nper = _time_calls(torch, stream, naive_calls, 2, 1)
+        nv = statistics.median(v["gbs_median"] for v in nper.values())
+        extras["naive_box_kernel_gbs"] = round(nv, 1)
+        extras["box_vs_naive_speedup"] = round(statistics.median(v["gbs_median"] for v in per.values()) / nv, 2)
+    return {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(total_ms / args.steps, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+            "config": {"workload": workload, "pairs": len(calls), "bytes_per_step": step_bytes,
+                       "parallelism": "single GPU", **extra_config},
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "box_kernel",
+                         "bytes_per_launch": int(box_bytes), "launch_ms_mean": round(box_ms, 4),
+                         "launches": len(calls) * args.steps},
+            "cpu_baseline": None, "hbm_peak_frac": round(value / HBM_PEAK_GBS, 4), "extras": extras,
+            "device": dev.name}
+
+
+def bench_box(L, torch, args, dev, stream):
+    """Sub-box copies (sec. 3.2 VirtualView): the 256^3 interior of a
+    lattice-Boltzmann grid with a one-cell halo (258^3 cells) into a 256^3
+    grid of another layout, 6 ordered pairs."""
+    rec = W.LBM
+    rg = L.Record(rec)
+    S, R = rg.info()[1], rg.info()[2]
+    src_ext, dst_ext, box = [258] * 3, [256] * 3, [256] * 3
+    layouts = [("aos_aligned", 0), ("soa_multi", 0), ("aosoa", 32)]
+    pairs = [(a, b) for a in layouts for b in layouts if a != b]
+    srcs, dsts = {}, {}
+    for l in layouts:
+        ms = L.Mapping(rg, l[0], src_ext, l[1])
+        srcs[l] = (ms, [torch.empty(s, dtype=torch.uint8, device="cuda").random_(0, 255) for s in ms.blob_sizes()])
+        md = L.Mapping(rg, l[0], dst_ext, l[1])
+        dsts[l] = (md, md.alloc(fill=0))
+    torch.cuda.synchronize()
+    nbox = 256 ** 3
+
+    def rb(l):
+        return R if l == ("aos_aligned", 0) else S
+    calls, naive = [], []
+    for a, b in pairs:
+        (ms, sb), (md, db) = srcs[a], dsts[b]
+        nb = nbox * (rb(a) + rb(b))
+        name = f"{_name(a)}->{_name(b)}"
+        calls.append((name, lambda ms=ms, sb=sb, md=md, db=db: L.copy_box(ms, sb, [1, 1, 1], md, db, [0, 0, 0], box,
+                                                                         stream=stream), nb))
+        naive.append((name, lambda ms=ms, sb=sb, md=md, db=db: L.copy_box(ms, sb, [1, 1, 1], md, db, [0, 0, 0], box,
+                                                                         stream=stream, path="naive"), nb))
+    log(f"box: timing {len(calls)} box copies of {nbox} cells")
+    return _box_line(L, torch, args, dev, stream,
+                     "lattice-Boltzmann cell {f64[19], u32}: the 256^3 interior of a 258^3 grid (one-cell halo) "
+                     "into a 256^3 grid, 6 ordered pairs of aligned AoS, SoA multi-blob, AoSoA32 (box copies)",
+                     calls, naive, rec, "u64", {"records": nbox, "source_extents": src_ext, "box": box})
+
+
+def bench_linearize(L, torch, args, dev, stream):
+    """Whole copies between views whose linearizers differ (sec. 3.7): the
+    particle record on an 8192 x 8192 grid (2^26 records), 6 ordered pairs
+    between row-major, column-major and Morton views of different layouts."""
+    rg = L.Record(W.PARTICLE)
+    ext = [8192, 8192]
+    A, As, M, Ss, Q = ("aos_packed", 0), ("aos_aligned", 0), ("soa_multi", 0), ("soa_single", 0), ("aosoa", 32)
+    pairs = [((A, "row"), (M, "col")), ((M, "col"), (A, "row")), ((Ss, "row"), (Q, "morton")),
+             ((Q, "morton"), (A, "row")), ((Q, "row"), (Q, "col")), ((M, "morton"), (As, "col"))]
+    views = {}
+    for v in {p for pr in pairs for p in pr}:
+        m = L.Mapping(rg, v[0][0], ext, v[0][1], linearizer=v[1])
+        views[v] = (m, [torch.empty(s, dtype=torch.uint8, device="cuda").random_(0, 255) for s in m.blob_sizes()])
+    torch.cuda.synchronize()
+    calls, naive = [], []
+    for a, b in pairs:
+        (ms, sb), (md, db) = views[a], views[b]
+        nb = sum(ms.blob_sizes()) + sum(md.blob_sizes())
+        name = f"{_name(a[0])}/{a[1]}->{_name(b[0])}/{b[1]}"
+        calls.append((name, lambda ms=ms, sb=sb, md=md, db=db: L.copy(ms, sb, md, db, stream=stream), nb))
+        naive.append((name, lambda ms=ms, sb=sb, md=md, db=db: L.copy(ms, sb, md, db, stream=stream, path="naive"),
+                      nb))
+    log(f"linearize: timing {len(calls)} copies between linearizers")
+    return _box_line(L, torch, args, dev, stream,
+                     "n-body particle 7xf32 on an 8192 x 8192 grid (2^26 records), 6 ordered pairs between "
+                     "row-major, column-major and Morton views of packed/aligned AoS, SoA and AoSoA32",
+                     calls, naive, W.PARTICLE, "u32", {"records": 1 << 26, "extents": ext})
+
+
+def bench_transfer(L, torch, args, dev, stream):
+    """Host <-> device copies with a layout change (sec. 3.9): 2^26 particles
+    from pinned host memory as packed AoS into device SoA multi-blob, and
+    back from device AoSoA32 into host packed AoS, chunked with transfers and
+    layout changes overlapped, against the same transfer done in one piece
+    (one memcpy of the whole view, then the layout change) and against raw
+    host <-> device memcpy of the same bytes."""
+    import ctypes
+    rg = L.Record(W.PARTICLE)
+    n = 1 << 26
+    A, M, Q = ("aos_packed", 0), ("soa_multi", 0), ("aosoa", 32)
+    ha = L.Mapping(rg, A[0], [n])
+    dm, dq = L.Mapping(rg, M[0], [n]), L.Mapping(rg, Q[0], [n], Q[1])
+    host = torch.empty(ha.blob_size(0), dtype=torch.uint8, pin_memory=True)
+    host.random_(0, 255)
+    back = torch.empty_like(host, pin_memory=True)
+    dmb, dqb = dm.alloc(fill=0), dq.alloc(fill=0)
+    staging = torch.empty(ha.blob_size(0), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    nb = host.numel()
+    chunk = 64 << 20
+
+    def h2d_chunked():
+        L.copy_transfer(ha, [host], dm, dmb, src_on_host=True, chunk_bytes=chunk, stream=stream)
+
+    def h2d_whole():
+        hip.hipMemcpyAsync(ctypes.c_void_p(staging.data_ptr()), ctypes.c_void_p(host.data_ptr()), nb, 1, sp)
+        L.copy(ha, [staging], dm, dmb, stream=stream)
+
+    def h2d_raw():
+        hip.hipMemcpyAsync(ctypes.c_void_p(staging.data_ptr()), ctypes.c_void_p(host.data_ptr()), nb, 1, sp)
+
+    def d2h_chunked():
+        L.copy_transfer(dq, dqb, ha, [back], src_on_host=False, chunk_bytes=chunk, stream=stream)
+
+    def d2h_whole():
+        L.copy(dq, dqb, ha, [staging], stream=stream)
+        hip.hipMemcpyAsync(ctypes.c_void_p(back.data_ptr()), ctypes.c_void_p(staging.data_ptr()), nb, 2, sp)
+
+    def d2h_raw():
+        hip.hipMemcpyAsync(ctypes.c_void_p(back.data_ptr()), ctypes.c_void_p(staging.data_ptr()), nb, 2, sp)
+
+    calls = [("h2d_chunked", h2d_chunked, nb), ("d2h_chunked", d2h_chunked, nb)]
+    refs = [("h2d_whole", h2d_whole, nb), ("h2d_memcpy", h2d_raw, nb), ("d2h_whole", d2h_whole, nb),
+            ("d2h_memcpy", d2h_raw, nb)]
+    log("transfer: timing chunked host <-> device copies")
+    total_ms, per = _time_calls(torch, stream, calls, args.steps, args.warmup)
+    _, rper = _time_calls(torch, stream, refs, max(2, args.steps // 2), 1)
+    value = sum(v["bytes"] for v in per.values()) * args.steps / (total_ms * 1e-3) / 1e9
+    ex = {k: round(v["gbs_median"], 2) for k, v in {**per, **rper}.items()}
+    ex["h2d_vs_memcpy"] = round(per["h2d_chunked"]["gbs_median"] / rper["h2d_memcpy"]["gbs_median"], 3)
+    ex["d2h_vs_memcpy"] = round(per["d2h_chunked"]["gbs_median"] / rper["d2h_memcpy"]["gbs_median"], 3)
+    ex["h2d_vs_whole"] = round(per["h2d_chunked"]["gbs_median"] / rper["h2d_whole"]["gbs_median"], 3)
+    ex["d2h_vs_whole"] = round(per["d2h_chunked"]["gbs_median"] / rper["d2h_whole"]["gbs_median"], 3)
+    return {"metric": "host<->device layout-changing copy GB/s (bytes crossing the link)", "value": round(value, 2),
+            "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(total_ms / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "n-body particle 7xf32, 2^26 records (1.879 GB): pinned host packed AoS -> "
+                                   "device SoA multi-blob, and device AoSoA32 -> pinned host packed AoS, 64 MiB "
+                                   "chunks, transfers and layout changes overlapped", "records": n,
+                       "chunk_bytes": chunk, "parallelism": "single GPU"},
+            "roofline": {"bound": "host link", "achieved": round(value, 2),
+                         "peak": round((rper["h2d_memcpy"]["gbs_median"] + rper["d2h_memcpy"]["gbs_median"]) / 2, 2),
+                         "unit": "GB/s", "frac": None, "traffic": None, "kernel": "hipMemcpyAsync + tile_kernel"},
+            "cpu_baseline": None, "extras": ex, "device": dev.name}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="particle", choices=["particle", "lbm", "split", "leaves", "batch", "serve", "pic"])
+    ap.add_argument("--workload", default="particle",
+                    choices=["particle", "lbm", "split", "leaves", "batch", "serve", "pic", "box", "linearize",
+                             "transfer"])
     ap.add_argument("--requests", type=int, default=2000, help="serve: measured requests (after 200 warm-up)")
     ap.add_argument("--rho", type=float, default=0.8, help="serve: offered load as a fraction of batched GB/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -620,6 +823,13 @@ def main():
         return
     if args.workload == "leaves":
         print(json.dumps(bench_leaves(L, torch, args, dev, stream)), flush=True)
+        return
+    if args.workload in ("box", "linearize", "transfer"):
+        fn = {"box": bench_box, "linearize": bench_linearize, "transfer": bench_transfer}[args.workload]
+        line = fn(L, torch, args, dev, stream)
+        if line["roofline"]["frac"] is None and line["roofline"]["peak"]:
+            line["roofline"]["frac"] = round(line["roofline"]["achieved"] / line["roofline"]["peak"], 4)
+        print(json.dumps(line), flush=True)
         return
 
     if args.workload == "particle":

@@ -139,15 +139,28 @@ typedef struct llama_split_desc {
 
 #define LLAMA_MAX_RANK 8
 
-/* A mapping of the data space: record dimension, kind and array dimensions.
- * Coordinates are linearised row-major, last index fastest (sec. 3.6). */
+/* Linearizers: how an array coordinate becomes the linear index i that a
+ * mapping lays out (sec. 3.7 lists linearizers among the building blocks of
+ * mappings; sec. 2 names other storage orders and space-filling curves).  In
+ * rank 1 all three are the identity. */
+typedef enum {
+    LLAMA_ROW_MAJOR = 0, /* last index fastest (sec. 3.6, Listing 4) */
+    LLAMA_COL_MAJOR = 1, /* first index fastest */
+    LLAMA_MORTON = 2     /* Z-order: bit j of coordinate d is bit j*rank + (rank-1-d) of i, with as
+                            many bits per coordinate as the largest extent needs; the mapping lays
+                            out indices up to the last coordinate's, and the indices that no
+                            coordinate reaches are padding */
+} llama_linearizer;
+
+/* A mapping of the data space: record dimension, kind and array dimensions. */
 typedef struct {
     const llama_record_desc* record;
     uint32_t kind;                    /* llama_mapping_kind */
     uint32_t rank;                    /* 1 .. LLAMA_MAX_RANK */
     uint64_t extents[LLAMA_MAX_RANK]; /* extents[0 .. rank-1]; zero extents allowed */
     uint32_t lanes;                   /* LLAMA_AOSOA: lanes per block, a power of two; else ignored */
-    uint32_t reserved;                /* must be 0 */
+    uint32_t linearizer;              /* llama_linearizer (0: row-major); Split and its parts: row-major
+                                         only; One: ignored */
     const llama_split_desc* split;    /* LLAMA_SPLIT: the split (required); else ignored */
 } llama_mapping_desc;
 
@@ -177,18 +190,30 @@ typedef struct {
 /* Copies the view (src, src_blobs) into the view (dst, dst_blobs).
  *  - src and dst must flatten to the same leaves (same sizes and alignments
  *    in the same order) and have the same rank and extents.
+ *  - Their linearizers may differ: every coordinate's record moves from its
+ *    source index to its destination index (the box kernel runs such
+ *    copies, and Morton copies whose indices have holes; the other paths
+ *    work on equal linear indices).
  *  - src_blobs / dst_blobs hold blob_count entries of their mapping.
  *  - No source range may overlap a destination range.
  *  - Every byte of every destination blob up to the mapping's blob size is
- *    written exactly once: leaf values from the source, and zero for the
- *    destination's padding (alignment gaps of aligned AoS, lanes past the last
- *    record in the last AoSoA block).
+ *    written exactly once (a Split destination part fed by several source
+ *    parts excepted, see below): leaf values from the source, and zero for
+ *    the destination's padding (alignment gaps of aligned AoS, lanes past the
+ *    last record in the last AoSoA block, Morton indices that no coordinate
+ *    reaches).  llama_copy_heatmap counts it.
  *  - A data space with zero records enqueues nothing and returns LLAMA_OK.
  *  - A Split on either side runs as one copy per pair of parts that share
- *    leaves, in order on `stream`, each writing only its own leaves and the
- *    padding of its destination part.  A pair that writes part of the records
- *    of a record-major destination part (AoS, AoSoA) takes the element-wise
- *    path; every other pair is planned like a plain copy.  Batches and the
+ *    leaves, in order on `stream`.  Into a record-major destination part
+ *    (AoS, AoSoA) fed by several source parts, the copy with the most bytes
+ *    writes whole records first (the other leaves' bytes as zeros, or kept
+ *    with LLAMA_COPY_PRESERVE_PADDING); each later copy into an AoS part
+ *    without padding reads the part's records into LDS, replaces its own
+ *    leaves and stores the records back whole, so those bytes are written
+ *    more than once and nothing else may write the destination while the
+ *    copy runs.  A later copy into another record-major part stores only its
+ *    own leaves (a direct-store tile, else the element-wise path).  Every
+ *    other pair is planned like a plain copy.  Batches and the
  *    batched server policy take a Split item as its pairs, side by side,
  *    unless one of them writes part of the records of a record-major
  *    destination part or reads a One part (LLAMA_E_UNSUPPORTED); the other
@@ -210,7 +235,9 @@ typedef enum {
     LLAMA_PATH_STREAM = 1, /* contiguous runs copied with wide vector accesses (includes identical layouts) */
     LLAMA_PATH_TILE = 2,   /* record tiles staged through LDS, transposed, stored coalesced */
     LLAMA_PATH_NAIVE = 3,  /* the element-wise baseline kernel */
-    LLAMA_PATH_EMPTY = 4   /* plan only: nothing to do (no records) */
+    LLAMA_PATH_EMPTY = 4,  /* plan only: nothing to do (no records) */
+    LLAMA_PATH_BOX = 5     /* tiles of coordinates whose records sit at different linear indices on the
+                              two sides (box copies, differing linearizers), staged through LDS */
 } llama_path;
 
 /* Kernel parameters.  Zero in any field means "the library's choice". */
@@ -248,6 +275,64 @@ typedef struct {
 int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
                   const llama_blob* dst_blobs, const llama_copy_options* options, void* stream);
 
+/* Copies a box of the array dimensions between two views whose extents may
+ * differ (sec. 3.2: a VirtualView shows a sub-box of a view, shifted by an
+ * offset; sec. 3.9 names copies between views of different size or shape):
+ * for every coordinate c with 0 <= c[d] < box[d], the record at
+ * src_offset + c of the source moves to dst_offset + c of the destination.
+ *  - src and dst flatten to the same leaves and have the same rank; extents,
+ *    kinds and linearizers may differ.  The box must lie inside both views
+ *    (LLAMA_E_EXTENT_MISMATCH otherwise).
+ *  - Destination records outside the box keep every byte (AoSoA lanes past
+ *    the last record included).  The alignment gaps of the box's records in
+ *    an aligned-AoS destination become zero, or keep their bytes with
+ *    LLAMA_COPY_PRESERVE_PADDING (then the destination records are read and
+ *    stored back whole).
+ *  - Mappings: plain kinds; the source may be One (broadcast), the
+ *    destination not; no Split (LLAMA_E_UNSUPPORTED).
+ *  - Options: path AUTO or BOX runs the tiled box kernel, NAIVE its
+ *    element-wise baseline (one thread per record of the box); tile_records
+ *    sets the records per tile (a power of two, 16 .. 4096), threads the
+ *    workgroup size; the result does not depend on them.
+ *  - A box with a zero extent enqueues nothing.  No source blob may overlap
+ *    a destination blob.  Asynchronous like llama_copy. */
+int llama_copy_box(const llama_mapping_desc* src, const llama_blob* src_blobs, const uint64_t* src_offset,
+                   const llama_mapping_desc* dst, const llama_blob* dst_blobs, const uint64_t* dst_offset,
+                   const uint64_t* box, const llama_copy_options* options, void* stream);
+
+/* Where a view's blobs live (llama_copy_transfer). */
+typedef enum {
+    LLAMA_MEMORY_DEVICE = 0, /* device memory of the current device */
+    LLAMA_MEMORY_HOST = 1    /* host memory; pinned (hipHostMalloc, torch pin_memory) for the transfers to
+                                overlap the layout changes, pageable works but serialises them */
+} llama_memory;
+
+/* Copies a view between host and device memory, changing the mapping on the
+ * way (sec. 3.9: copies between address spaces shuffle a chunk into the
+ * other mapping in a small intermediate view and transfer it, overlapping
+ * shuffles and transfers; sec. 1 names copies between devices).  The records
+ * are cut into chunks of whole AoSoA blocks of both sides, about chunk_bytes
+ * each (0: 64 MiB).  Host to device: each chunk is transferred in the
+ * source's layout into a device staging view, whose layout the GPU then
+ * changes into the destination; device to host: the GPU changes the layout of
+ * a chunk into the staging view, which is then transferred.  Two staging
+ * buffers alternate, so the transfer of one chunk overlaps the layout change
+ * of the next on a second stream of the library.
+ *  - One of src_memory / dst_memory is LLAMA_MEMORY_HOST, the other
+ *    LLAMA_MEMORY_DEVICE (LLAMA_E_INVALID_ARG otherwise).
+ *  - The result equals llama_copy's: same records, extents and linearizer on
+ *    both sides (LLAMA_E_UNSUPPORTED for differing linear indices, Split and
+ *    a One source); padding zeroed.
+ *  - Asynchronous: returns after enqueueing; the work on `stream` completes
+ *    after the whole copy.  Host blobs must stay valid (and, for a device to
+ *    host copy, unread) until then.
+ *  - The library keeps two staging buffers per device (allocated, or grown,
+ *    on a call that needs more) and runs one transfer per device at a time: a
+ *    call first waits for the previous transfer on the device to finish. */
+int llama_copy_transfer(const llama_mapping_desc* src, const llama_blob* src_blobs, uint32_t src_memory,
+                        const llama_mapping_desc* dst, const llama_blob* dst_blobs, uint32_t dst_memory,
+                        uint64_t chunk_bytes, void* stream);
+
 /* Marks a destination leaf that takes no source leaf (llama_copy_leaves). */
 #define LLAMA_NO_LEAF 0xFFFFFFFFu
 
@@ -262,13 +347,78 @@ int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, co
  * (LLAMA_E_UNSUPPORTED).  Errors: LLAMA_E_INVALID_ARG for a leaf index out of
  * range or no destination leaf with a source, LLAMA_E_RECORD_MISMATCH for
  * leaves of different sizes, and llama_copy's others.  When some destination
- * leaves keep their bytes, a record-major destination is written by a
- * direct-store tile plan if one applies, else element-wise; options as for
- * llama_copy_ex. */
+ * leaves keep their bytes, a packed AoS destination is written by a tile
+ * that loads the destination records into LDS, replaces the leaves that
+ * take a value and stores the records back whole: the kept leaves' bytes
+ * are read and written back unchanged, so nothing else may write that
+ * destination while the copy runs.  Another record-major destination is
+ * written by a direct-store tile plan if one applies (only the leaves that
+ * take a value), else element-wise; options as for llama_copy_ex. */
 int llama_copy_leaves(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
                       const llama_blob* dst_blobs, const uint32_t* src_leaf, const llama_copy_options* options,
                       void* stream);
 
+
+/* ------------------------------------------------------------------------ */
+/* Heatmap and Trace (sec. 3.7): access counters around a copy              */
+/* ------------------------------------------------------------------------ */
+
+/* Per-byte counters of a Heatmap copy.  Each array has one entry per blob of
+ * its mapping (an entry, or the array itself, may be NULL: not counted); an
+ * entry is a device array of 32-bit counters, one per byte of the mapping's
+ * blob size, which the copy adds to (the caller zeroes it first). */
+typedef struct {
+    uint32_t* const* src_reads;  /* source blobs: bytes read */
+    uint32_t* const* dst_writes; /* destination blobs: bytes written */
+    uint32_t* const* dst_reads;  /* destination blobs: bytes read (kept padding, kept-gap tiles) */
+} llama_heatmap;
+
+/* The Heatmap of sec. 3.7, for the library's own copies: runs the copy that
+ * llama_copy_ex (src_leaf == NULL) or llama_copy_leaves (src_leaf != NULL)
+ * would run with these options -- the same plans, paths and tile modes --
+ * in counted kernel variants that add one to a byte's counter for every
+ * global load that reads it and every global store that writes it.  The
+ * destination ends up as the plain copy leaves it.  It is a debugging and
+ * analysis tool: the counted variants run many times slower, and they take
+ * plain (not nontemporal) loads and stores.  At most 128 blobs per list
+ * (source reads and destination reads together count as one list).  The counters live in a device global of the library: Heatmap
+ * copies on one device must not overlap in time.  A copy that writes every
+ * destination byte exactly once shows a destination write count of one on
+ * every byte (zero on kept padding and on leaves without a source). */
+int llama_copy_heatmap(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                       const llama_blob* dst_blobs, const uint32_t* src_leaf, const llama_copy_options* options,
+                       const llama_heatmap* heatmap, void* stream);
+
+/* A byte range whose accesses a Heatmap counts: `size` bytes at `ptr`
+ * (device memory), one 32-bit counter per byte at `counters`. */
+typedef struct {
+    const void* ptr;
+    uint64_t size;
+    uint32_t* counters;
+} llama_count_range;
+
+/* The Heatmap around any of this thread's copies: after llama_heatmap_begin,
+ * llama_copy, llama_copy_ex, llama_copy_naive, llama_copy_leaves and
+ * llama_copy_box on the calling thread run in their counted kernel variants
+ * (the same plans), which add one to the counter of every byte of `reads`
+ * that a global load reads and of every byte of `writes` that a global store
+ * writes, until llama_heatmap_end.  At most 128 ranges per list
+ * (LLAMA_E_UNSUPPORTED).  The list is uploaded on `stream` into a device
+ * global of the library: the copies counted must run on that stream (or
+ * after it), and Heatmaps on one device must not overlap in time.
+ * llama_copy_heatmap is this around one copy. */
+int llama_heatmap_begin(size_t nreads, const llama_count_range* reads, size_t nwrites,
+                        const llama_count_range* writes, void* stream);
+int llama_heatmap_end(void);
+
+/* The Trace of sec. 3.7 (accesses per field), from a view's per-byte
+ * counters (such as a llama_heatmap's): sums[f] is the sum of the counters of
+ * the bytes of leaf f over all records, for each of the F leaves, and
+ * sums[F] the sum over the bytes that no leaf owns (alignment gaps, AoSoA
+ * lanes past the last record).  counters holds one device array of 32-bit
+ * counters per blob of the mapping.  Not for One mappings
+ * (LLAMA_E_UNSUPPORTED).  Synchronous: runs on `stream` and waits for it. */
+int llama_trace_leaves(const llama_mapping_desc* mapping, uint32_t* const* counters, uint64_t* sums, void* stream);
 
 /* How a TILE copy moves one tile (llama_plan_info.tile_mode). */
 typedef enum {
@@ -409,6 +559,21 @@ int llama_batch_create(size_t n, const llama_copy_item* items, const llama_copy_
 int llama_batch_launch(llama_batch* batch, void* stream);
 
 int llama_batch_get_info(const llama_batch* batch, llama_batch_info* info);
+
+/* The batch's autotuner: measures launch parameters on the batch's own
+ * blobs and re-plans the batch with the fastest.  Candidates: the LDS a tiled
+ * item's plan may take (8, 16, 31 or 48 KiB: each item then takes the largest
+ * tile that fits, so this sets the tile shapes and the LDS depth of every
+ * workgroup), 128, 256 or 512 threads per workgroup (the waves that share a
+ * tile), and the grid (the default rule, or a persistent grid of 2, 4 or 8
+ * workgroups per compute unit).  Every candidate first runs on destinations
+ * filled with a pattern and must write the bytes the current plan writes
+ * (compared by a 64-bit hash of every destination); then it is timed, best of
+ * `reps` launches (0: 3).  A tile size fixed at creation stays fixed.
+ * Synchronous: the destinations end up holding the copy, the batch's graph
+ * is captured again on its next launch.  *best_gbs (may be NULL) receives the
+ * winner's read+write GB/s. */
+int llama_batch_autotune(llama_batch* batch, void* stream, uint32_t reps, double* best_gbs);
 
 /* Waits for the device to finish pending work, then frees the batch. */
 int llama_batch_destroy(llama_batch* batch);

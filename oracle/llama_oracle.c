@@ -789,6 +789,61 @@ int orc_write_counts(const orc_record* r, const orc_mapping* m, uint32_t* const*
     return ORC_OK;
 }
 
+/* The writes that the copy's definition makes into the destination, as
+ * per-byte counts (the Heatmap of sec. 3.7 applied to the definition of sec.
+ * 3.9): one for every byte a value is copied to, and one for every byte of
+ * the zero fill.  from == NULL: the plain copy, every leaf takes a value;
+ * otherwise destination leaf k takes a value when from[k] >= 0, as in
+ * orc_copy_leaves, whose zero fill covers the bytes no leaf owns and the
+ * unused AoSoA lanes of the leaves that take a value.  keep: no zero fill.
+ * counts[b] holds blob_size(b) counters and is added to. */
+int orc_copy_writes(const orc_record* r, const orc_mapping* dst, const int32_t* from, int keep,
+                    uint32_t* const* counts)
+{
+    if (!valid_mapping(dst, r) || dst->kind == ORC_ONE)
+        return ORC_E_ARG;
+    int nb = orc_blob_count(dst, r);
+    if (nb > ORC_SPLIT_MAX_LEAVES)
+        return ORC_E_ARG;
+    /* owned[b][o]: 1 when a value of a leaf maps to byte o, 2 when it is an
+     * unused AoSoA lane of a leaf that keeps its bytes */
+    uint8_t* owned[ORC_SPLIT_MAX_LEAVES];
+    for (int b = 0; b < nb; b++)
+        owned[b] = (uint8_t*)calloc((size_t)orc_blob_size(dst, r, b) + 1, 1);
+    uint64_t n = orc_record_count(dst);
+    uint64_t coord[ORC_MAX_RANK] = {0};
+    if (n > 0)
+        do {
+            for (int f = 0; f < r->nleaves; f++) {
+                uint64_t b, o;
+                orc_blob_nr_and_offset(dst, r, coord, f, &b, &o);
+                for (uint64_t k = 0; k < r->size[f]; k++) {
+                    owned[b][o + k] = 1;
+                    if (!from || from[f] >= 0)
+                        counts[b][o + k]++;
+                }
+            }
+        } while (next_coord(dst, coord));
+    if (from && dst->kind == ORC_AOSOA) {
+        uint64_t L = dst->lanes;
+        for (uint64_t i = n; i < (n + L - 1) / L * L; i++)
+            for (int f = 0; f < r->nleaves; f++)
+                if (from[f] < 0)
+                    memset(owned[0] + (i / L) * (L * orc_packed_size(r)) + L * orc_packed_offset(r, f) +
+                               (i % L) * r->size[f],
+                           2, (size_t)r->size[f]);
+    }
+    for (int b = 0; b < nb; b++) {
+        uint64_t sz = orc_blob_size(dst, r, b);
+        if (!keep)
+            for (uint64_t o = 0; o < sz; o++)
+                if (!owned[b][o])
+                    counts[b][o]++;
+        free(owned[b]);
+    }
+    return ORC_OK;
+}
+
 /* Checks sampled values of a finished copy one by one: for each sample
  * (linear index idx[k], leaf leaf[k]) the destination bytes must equal the
  * source bytes, both located through the mappings.  Returns the number of

@@ -116,6 +116,8 @@ def lib():
         L.orc_max_threads.restype = ctypes.c_int
         L.orc_write_counts.argtypes = [RP, MP, PP]
         L.orc_write_counts.restype = ctypes.c_int
+        L.orc_copy_writes.argtypes = [RP, MP, ctypes.POINTER(i32), ctypes.c_int, PP]
+        L.orc_copy_writes.restype = ctypes.c_int
         L.orc_check_samples.argtypes = [RP, MP, PP, MP, PP, ctypes.POINTER(u64), ctypes.POINTER(i32),
                                         i64, ctypes.POINTER(i64)]
         L.orc_check_samples.restype = i64
@@ -357,6 +359,24 @@ def write_counts(m: Mapping):
     rc = lib().orc_write_counts(ctypes.byref(m.record.c), ctypes.byref(m.c), arr)
     if rc != 0:
         raise ValueError("write_counts failed")
+    return counts
+
+
+def copy_writes(dst: Mapping, source_leaf=None, keep_padding=False):
+    """Per-byte count of the writes the copy's definition makes into `dst`:
+    one per byte a value goes to, one per byte of the zero fill (none with
+    keep_padding).  source_leaf: as in copy_leaves (None entries keep their
+    bytes); None: the plain copy."""
+    counts = [np.zeros(s, dtype=np.uint32) for s in dst.blob_sizes()]
+    arr = (ctypes.c_void_p * max(len(counts), 1))()
+    for k, c in enumerate(counts):
+        arr[k] = c.ctypes.data
+    frm = None
+    if source_leaf is not None:
+        frm = (ctypes.c_int32 * max(dst.record.nleaves, 1))(*[-1 if x is None else int(x) for x in source_leaf])
+    rc = lib().orc_copy_writes(ctypes.byref(dst.record.c), ctypes.byref(dst.c), frm, 1 if keep_padding else 0, arr)
+    if rc != 0:
+        raise ValueError("copy_writes failed")
     return counts
 
 

@@ -83,8 +83,9 @@ std::map<std::tuple<uint64_t, uint32_t, uint64_t, uint32_t, uint64_t, uint32_t, 
 
 } // namespace
 
-Plan batch_plan(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags)
+Plan batch_plan(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags, uint32_t lds_budget)
 {
+    const uint32_t budget = lds_budget ? lds_budget : kBatchLdsBytes;
     if (rq.src.kind == LLAMA_ONE)
         fail(LLAMA_E_UNSUPPORTED, "a One source is copied element-wise; copy it with llama_copy");
     llama_copy_options o{LLAMA_PATH_AUTO, tile_records, threads, 0, flags};
@@ -101,7 +102,8 @@ Plan batch_plan(const Request& rq, uint32_t threads, uint32_t tile_records, uint
         // repeated class costs one plan instead of a search
         TuneKey k = tune_key(rq);
         k.bucket = 0;
-        const auto key = std::make_tuple(k.leaves, k.src_kind, k.src_lanes, k.dst_kind, k.dst_lanes, threads, flags);
+        const auto key =
+            std::make_tuple(k.leaves, k.src_kind, k.src_lanes, k.dst_kind, k.dst_lanes, threads, flags | (budget << 8));
         uint32_t start = 4096;
         {
             std::lock_guard<std::mutex> lock(g_tile_memo_mutex);
@@ -122,7 +124,7 @@ Plan batch_plan(const Request& rq, uint32_t threads, uint32_t tile_records, uint
             const uint32_t lds = p.tile.h.lds_bytes * ((p.tile.h.flags & kTileGatherStore) ? 2u : 1u);
             found = p.path == LLAMA_PATH_STREAM || p.path == LLAMA_PATH_EMPTY ||
                     (p.path == LLAMA_PATH_TILE &&
-                     (lds <= kBatchLdsBytes || (T == 16 && p.tile.h.lds_bytes <= kBatchLdsBytes)));
+                     (lds <= budget || (T == 16 && p.tile.h.lds_bytes <= budget)));
         }
         if (!found)
             fail(LLAMA_E_UNSUPPORTED, "its record does not fit the tiled kernel; copy it with llama_copy");
@@ -136,9 +138,9 @@ Plan batch_plan(const Request& rq, uint32_t threads, uint32_t tile_records, uint
     return p;
 }
 
-void BatchTable::add(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags)
+void BatchTable::add(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags, uint32_t lds_budget)
 {
-    add_plan(batch_plan(rq, threads, tile_records, flags));
+    add_plan(batch_plan(rq, threads, tile_records, flags, lds_budget));
 }
 
 void BatchTable::add_plan(const Plan& p)
@@ -275,7 +277,7 @@ uint32_t batch_grid(uint64_t units, uint32_t wg_per_cu)
 }
 
 BatchTable build_batch_table(size_t n, const llama_copy_item* items, const llama_copy_options* opt,
-                             uint32_t& threads)
+                             uint32_t& threads, std::vector<Request>* work)
 {
     reap_retired();
     if (n > 0 && !items)
@@ -311,6 +313,8 @@ BatchTable build_batch_table(size_t n, const llama_copy_item* items, const llama
         try {
             if (items[k].src->kind != LLAMA_SPLIT && items[k].dst->kind != LLAMA_SPLIT) {
                 t.add(rqs[k], threads, T, opt ? opt->flags : 0u);
+                if (work)
+                    work->push_back(rqs[k]);
                 continue;
             }
             std::vector<SubCopy> parts = split_copies(items[k].src, items[k].dst, rqs[k]);
@@ -318,8 +322,11 @@ BatchTable build_batch_table(size_t n, const llama_copy_item* items, const llama
                 if (c.naive) // then the copies into that part depend on their order
                     fail(LLAMA_E_UNSUPPORTED, "its part copies write parts of the records of a record-major "
                                               "destination part in turn; copy it with llama_copy");
-            for (const SubCopy& c : parts)
+            for (const SubCopy& c : parts) {
                 t.add(c.rq, threads, T, opt ? opt->flags : 0u);
+                if (work)
+                    work->push_back(c.rq);
+            }
         } catch (const Error& e) {
             fail(e.status, "batch item " + std::to_string(k) + ": " + e.message);
         }
@@ -327,12 +334,12 @@ BatchTable build_batch_table(size_t n, const llama_copy_item* items, const llama
     return t;
 }
 
-Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_options* opt)
+namespace {
+
+// Fills `b` (counts, grid) from table `t` and uploads the table into a new
+// device allocation, freeing the previous one.
+void install_table(Batch* b, const BatchTable& t, uint32_t wg_per_cu)
 {
-    uint32_t threads = 0;
-    const BatchTable t = build_batch_table(n, items, opt, threads);
-    std::unique_ptr<Batch> b(new Batch());
-    b->threads = threads;
     b->total_units = t.units;
     b->lds_bytes = t.lds_bytes;
     b->items = t.items.size();
@@ -340,22 +347,150 @@ Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_opt
     b->stream_items = t.stream_items;
     b->read_bytes = t.read_bytes;
     b->write_bytes = t.write_bytes;
-    check_hip(hipGetDevice(&b->device), "hipGetDevice");
-    const uint32_t w = opt ? opt->wg_per_cu : 0;
-    b->wg_per_cu = w ? w : batch_per_unit(t) ? 0 : batch_wg_per_cu(t.lds_bytes, threads);
+    b->wg_per_cu = wg_per_cu ? wg_per_cu : batch_per_unit(t) ? 0 : batch_wg_per_cu(t.lds_bytes, b->threads);
     b->grid = batch_grid(t.units, b->wg_per_cu);
-
     const size_t total = t.bytes();
     std::vector<uint8_t> host(total);
-    check_hip(hipMalloc(&b->table, total), "hipMalloc(batch table)");
-    b->table_bytes = total;
-    t.serialise(host.data(), uint64_t(uintptr_t(b->table)), b->args);
-    hipError_t e = hipMemcpy(b->table, host.data(), total, hipMemcpyHostToDevice);
+    void* table = nullptr;
+    check_hip(hipMalloc(&table, total), "hipMalloc(batch table)");
+    BatchArgs args{};
+    t.serialise(host.data(), uint64_t(uintptr_t(table)), args);
+    hipError_t e = hipMemcpy(table, host.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        (void)hipFree(b->table);
+        (void)hipFree(table);
         check_hip(e, "hipMemcpy(batch table)");
     }
+    if (b->table)
+        (void)hipFree(b->table);
+    if (b->graph_exec)
+        (void)hipGraphExecDestroy((hipGraphExec_t)b->graph_exec);
+    b->graph_exec = nullptr;
+    b->table = table;
+    b->table_bytes = total;
+    b->args = args;
+}
+
+} // namespace
+
+Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_options* opt)
+{
+    uint32_t threads = 0;
+    std::unique_ptr<Batch> b(new Batch());
+    const BatchTable t = build_batch_table(n, items, opt, threads, &b->work);
+    b->flags = opt ? opt->flags : 0u;
+    b->tile_records = opt ? opt->tile_records : 0u;
+    b->threads = threads;
+    check_hip(hipGetDevice(&b->device), "hipGetDevice");
+    install_table(b.get(), t, opt ? opt->wg_per_cu : 0);
     return b.release();
+}
+
+void autotune_batch(Batch* b, void* stream_ptr, int reps, double* best_gbs)
+{
+    hipStream_t stream = (hipStream_t)stream_ptr;
+    int dev = 0;
+    check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != b->device)
+        fail(LLAMA_E_INVALID_ARG, "batch was created on another device");
+    if (b->total_units == 0)
+        return;
+    if (reps <= 0)
+        reps = 3;
+    // the destinations of the current plan, hashed: every candidate must match
+    std::vector<std::pair<uint64_t, uint64_t>> dsts;
+    for (const Request& rq : b->work)
+        for (size_t k = 0; k < rq.dst_ptr.size(); k++)
+            if (rq.dst.blob_size[k])
+                dsts.push_back({rq.dst_ptr[k], rq.dst.blob_size[k]});
+    std::sort(dsts.begin(), dsts.end());
+    dsts.erase(std::unique(dsts.begin(), dsts.end()), dsts.end());
+    void* acc_p = nullptr;
+    check_hip(hipMalloc(&acc_p, sizeof(unsigned long long)), "hipMalloc(hash)");
+    unsigned long long* acc = (unsigned long long*)acc_p;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&] {
+        if (e0)
+            (void)hipEventDestroy(e0);
+        if (e1)
+            (void)hipEventDestroy(e1);
+        (void)hipFree(acc_p);
+    };
+    try {
+        check_hip(hipEventCreate(&e0), "hipEventCreate");
+        check_hip(hipEventCreate(&e1), "hipEventCreate");
+        auto hash = [&](int fill) {
+            for (const auto& d : dsts)
+                check_hip(hipMemsetAsync((void*)d.first, fill, d.second, stream), "hipMemsetAsync");
+            launch_batch_kernel(*b, stream);
+            check_hip(hipMemsetAsync(acc, 0, sizeof(*acc), stream), "hipMemsetAsync");
+            for (const auto& d : dsts)
+                launch_hash((const void*)d.first, d.second, acc, stream);
+            unsigned long long h = 0;
+            check_hip(hipMemcpyAsync(&h, acc, sizeof(h), hipMemcpyDeviceToHost, stream), "hipMemcpyAsync");
+            check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
+            return uint64_t(h);
+        };
+        auto time_it = [&] {
+            launch_batch_kernel(*b, stream);
+            double best = 1e30;
+            for (int r = 0; r < reps; r++) {
+                check_hip(hipEventRecord(e0, stream), "hipEventRecord");
+                launch_batch_kernel(*b, stream);
+                check_hip(hipEventRecord(e1, stream), "hipEventRecord");
+                check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+                float ms = 0;
+                check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                best = std::min(best, double(ms));
+            }
+            return best;
+        };
+        const uint64_t want = hash(0x5A);
+        struct Cand {
+            uint32_t budget, threads, wg;
+        };
+        Cand best{b->lds_budget, b->threads, b->wg_per_cu};
+        double best_ms = time_it();
+        // LDS per tiled item (the tile each item takes), threads, and the grid
+        // (0: the default rule, else a persistent grid of that many
+        // workgroups per compute unit)
+        const uint32_t budgets[] = {8 * 1024, 16 * 1024, kBatchLdsBytes, 48 * 1024};
+        const uint32_t threads[] = {128, 256, 512};
+        const uint32_t grids[] = {0, 2, 4, 8};
+        for (uint32_t bud : budgets)
+            for (uint32_t th : threads)
+                for (uint32_t wg : grids) {
+                    BatchTable t;
+                    try {
+                        for (const Request& rq : b->work)
+                            t.add(rq, th, b->tile_records, b->flags, bud);
+                    } catch (const Error&) {
+                        continue; // an item does not fit this budget
+                    }
+                    b->threads = th;
+                    b->lds_budget = bud;
+                    install_table(b, t, wg);
+                    if (hash(0xA5) != want)
+                        fail(LLAMA_E_HIP, "a batch tuning candidate wrote different bytes");
+                    const double ms = time_it();
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = {bud, th, wg};
+                    }
+                }
+        // re-plan with the fastest
+        BatchTable t;
+        for (const Request& rq : b->work)
+            t.add(rq, best.threads, b->tile_records, b->flags, best.budget);
+        b->threads = best.threads;
+        b->lds_budget = best.budget;
+        install_table(b, t, best.wg);
+        if (best_gbs)
+            *best_gbs = double(b->read_bytes + b->write_bytes) / (best_ms * 1e-3) / 1e9;
+    } catch (...) {
+        cleanup();
+        throw;
+    }
+    cleanup();
 }
 
 void copy_batch_noalloc(size_t n, const llama_copy_item* items, void* stream)

@@ -10,6 +10,10 @@ namespace llama {
 
 struct Batch {
     int device = 0;
+    std::vector<Request> work; // the copies the table holds (a Split item as its part copies)
+    uint32_t flags = 0;        // LLAMA_COPY_* bits of the batch
+    uint32_t tile_records = 0; // fixed tile size (0: each item's own)
+    uint32_t lds_budget = 0;   // LDS a tiled item's plan may take (without a fixed tile size)
     uint32_t threads = 0;
     uint32_t wg_per_cu = 0; // persistent: workgroups per compute unit; 0: one workgroup per work unit
     uint32_t grid = 0;
@@ -39,7 +43,8 @@ struct BatchTable {
 
     // plans `rq` with `threads` per workgroup and adds it; fails with
     // LLAMA_E_UNSUPPORTED for a record the tiled kernel cannot hold
-    void add(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags = 0);
+    void add(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags = 0,
+             uint32_t lds_budget = 0);
     // adds an item planned by batch_plan
     void add_plan(const Plan& p);
     // bytes of the serialised table
@@ -67,11 +72,16 @@ constexpr uint64_t kBatchMaxGrid = uint64_t(1) << 24;
 uint32_t batch_grid(uint64_t units, uint32_t wg_per_cu);
 
 // the plan of a batch item (see BatchTable::add)
-Plan batch_plan(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags);
+// (lds_budget 0: kBatchLdsBytes)
+Plan batch_plan(const Request& rq, uint32_t threads, uint32_t tile_records, uint32_t flags, uint32_t lds_budget = 0);
 
 // validates the items and plans them into one work table (nothing on the device)
 BatchTable build_batch_table(size_t n, const llama_copy_item* items, const llama_copy_options* opt,
-                             uint32_t& threads);
+                             uint32_t& threads, std::vector<Request>* work = nullptr);
+// llama_batch_autotune: times candidate LDS budgets, thread counts and grids
+// on the batch's own blobs, keeps those whose output hashes like the current
+// plan's, and re-plans the batch with the fastest
+void autotune_batch(Batch* b, void* stream, int reps, double* best_gbs);
 Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_options* opt);
 // llama_copy_batch_noalloc: the work table goes into the library's static
 // device buffer (kScratchBytes) instead of an allocation

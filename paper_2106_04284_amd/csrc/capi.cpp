@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <exception>
 #include <string>
 
@@ -140,12 +141,10 @@ int llama_mapping_offset(const llama_mapping_desc* mapping, const uint64_t* coor
         Side s = make_side(mapping, r);
         if (leaf >= r.leaves.size())
             fail(LLAMA_E_INVALID_ARG, "leaf " + std::to_string(leaf) + " out of range");
-        uint64_t i = 0;
-        for (uint32_t d = 0; d < s.rank; d++) {
+        for (uint32_t d = 0; d < s.rank; d++)
             if (coord[d] >= s.extents[d])
                 fail(LLAMA_E_INVALID_ARG, "coordinate out of range in dimension " + std::to_string(d));
-            i = i * s.extents[d] + coord[d];
-        }
+        const uint64_t i = linearize(s, coord);
         *blob = s.blob[leaf];
         *offset = s.offset(i, leaf, r);
     });
@@ -157,11 +156,21 @@ int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, con
     return guarded([&] {
         need(info, "info");
         Request rq = make_request(src, nullptr, dst, nullptr, false);
-        Plan p = make_plan(rq, options);
+        Plan p;
+        if (needs_box(rq)) {
+            const uint64_t zero[LLAMA_MAX_RANK] = {};
+            std::vector<Plan> ps = make_box_plans(rq, zero, zero, rq.dst.extents, true, options);
+            if (!ps.empty())
+                p = ps[0];
+        } else {
+            p = make_plan(rq, options);
+        }
         std::memset(info, 0, sizeof(*info));
         info->path = p.path;
         info->threads = p.threads;
-        info->tile_records = p.path == LLAMA_PATH_TILE ? (1u << p.tile.h.log2_tile) : 0;
+        info->tile_records = p.path == LLAMA_PATH_TILE  ? (1u << p.tile.h.log2_tile)
+                             : p.path == LLAMA_PATH_BOX ? (1u << p.box.h.qlog_sum)
+                                                        : 0;
         info->lds_bytes = p.lds_bytes;
         info->workgroups = p.workgroups;
         info->runs = p.path == LLAMA_PATH_STREAM ? p.stream.num_runs : 0;
@@ -185,11 +194,23 @@ int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, con
     });
 }
 
-int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
-                  const llama_blob* dst_blobs, const llama_copy_options* options, void* stream)
+namespace {
+
+// llama_copy_ex's body (also run under the Heatmap's counting)
+void copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+             const llama_blob* dst_blobs, const llama_copy_options* options, void* stream)
 {
-    return guarded([&] {
+    {
         Request rq = make_request(src, src_blobs, dst, dst_blobs, true, true);
+        if (needs_box(rq)) {
+            // records at different linear indices: the whole extents as one box
+            if (src->kind == LLAMA_SPLIT || dst->kind == LLAMA_SPLIT)
+                fail(LLAMA_E_UNSUPPORTED, "Split copies take views with equal linear indices");
+            const uint64_t zero[LLAMA_MAX_RANK] = {};
+            for (const Plan& p : make_box_plans(rq, zero, zero, rq.dst.extents, true, options))
+                launch(p, stream);
+            return;
+        }
         if (src->kind != LLAMA_SPLIT && dst->kind != LLAMA_SPLIT) {
             Plan p = make_plan(rq, options);
             launch(p, stream);
@@ -252,7 +273,139 @@ int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, co
         }
         for (const Plan& p : plans)
             launch(p, stream);
+    }
+}
+
+// the blob sizes a mapping needs
+std::vector<uint64_t> blob_sizes(const llama_mapping_desc* m)
+{
+    need(m, "mapping");
+    need(m->record, "record");
+    return make_side(m, flatten(m->record)).blob_size;
+}
+
+// adds the blobs with counters to a count list
+void add_counted(CountBlob* list, uint32_t& n, const llama_mapping_desc* m, const llama_blob* blobs,
+                 uint32_t* const* counters)
+{
+    if (!counters)
+        return;
+    const std::vector<uint64_t> sizes = blob_sizes(m);
+    for (size_t b = 0; b < sizes.size(); b++) {
+        if (!counters[b] || sizes[b] == 0)
+            continue;
+        if (n >= uint32_t(kCountMaxBlobs))
+            fail(LLAMA_E_UNSUPPORTED, "a Heatmap counts at most " + std::to_string(kCountMaxBlobs) +
+                                          " blobs per list");
+        const uint64_t lo = uint64_t(uintptr_t(blobs[b].ptr));
+        list[n++] = {lo, lo + sizes[b], uint64_t(uintptr_t(counters[b]))};
+    }
+}
+
+} // namespace
+
+int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                  const llama_blob* dst_blobs, const llama_copy_options* options, void* stream)
+{
+    return guarded([&] { copy_ex(src, src_blobs, dst, dst_blobs, options, stream); });
+}
+
+int llama_copy_heatmap(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                       const llama_blob* dst_blobs, const uint32_t* src_leaf, const llama_copy_options* options,
+                       const llama_heatmap* heat, void* stream)
+{
+    return guarded([&] {
+        need(heat, "heatmap");
+        need(src_blobs, "source blobs");
+        need(dst_blobs, "destination blobs");
+        // validates like the copy itself before anything is enqueued (the
+        // records of a copy between differing records are checked side by side)
+        if (src_leaf) {
+            need(src, "source mapping");
+            need(dst, "destination mapping");
+            need(src->record, "source record");
+            need(dst->record, "destination record");
+            std::vector<uint64_t> ptrs;
+            check_blobs("source", make_side(src, flatten(src->record)), src_blobs, ptrs);
+            check_blobs("destination", make_side(dst, flatten(dst->record)), dst_blobs, ptrs);
+        } else {
+            (void)make_request(src, src_blobs, dst, dst_blobs, true, true);
+        }
+        static CountTable table; // large; filled and uploaded under the lock
+        static std::mutex lock;
+        std::lock_guard<std::mutex> g(lock);
+        std::memset(&table, 0, sizeof(table));
+        add_counted(table.r, table.nr, src, src_blobs, heat->src_reads);
+        add_counted(table.r, table.nr, dst, dst_blobs, heat->dst_reads);
+        add_counted(table.w, table.nw, dst, dst_blobs, heat->dst_writes);
+        set_counting(&table, stream);
+        try {
+            if (src_leaf)
+                copy_leaves(src, src_blobs, dst, dst_blobs, src_leaf, options, stream);
+            else
+                copy_ex(src, src_blobs, dst, dst_blobs, options, stream);
+        } catch (...) {
+            set_counting(nullptr, stream);
+            throw;
+        }
+        set_counting(nullptr, stream);
     });
+}
+
+int llama_heatmap_begin(size_t nreads, const llama_count_range* reads, size_t nwrites,
+                        const llama_count_range* writes, void* stream)
+{
+    return guarded([&] {
+        if ((nreads && !reads) || (nwrites && !writes))
+            fail(LLAMA_E_INVALID_ARG, "count range array is NULL");
+        if (nreads > size_t(kCountMaxBlobs) || nwrites > size_t(kCountMaxBlobs))
+            fail(LLAMA_E_UNSUPPORTED, "a Heatmap counts at most " + std::to_string(kCountMaxBlobs) +
+                                          " ranges per list");
+        static CountTable table;
+        std::memset(&table, 0, sizeof(table));
+        auto fill = [](CountBlob* out, uint32_t& n, size_t count, const llama_count_range* in) {
+            for (size_t k = 0; k < count; k++) {
+                if (in[k].size && (!in[k].ptr || !in[k].counters))
+                    fail(LLAMA_E_INVALID_ARG, "count range " + std::to_string(k) + " has a NULL pointer");
+                const uint64_t lo = uint64_t(uintptr_t(in[k].ptr));
+                out[n++] = {lo, lo + in[k].size, uint64_t(uintptr_t(in[k].counters))};
+            }
+        };
+        fill(table.r, table.nr, nreads, reads);
+        fill(table.w, table.nw, nwrites, writes);
+        set_counting(&table, stream);
+    });
+}
+
+int llama_heatmap_end(void)
+{
+    return guarded([&] { set_counting(nullptr, nullptr); });
+}
+
+int llama_trace_leaves(const llama_mapping_desc* mapping, uint32_t* const* counters, uint64_t* sums, void* stream)
+{
+    return guarded([&] {
+        need(mapping, "mapping");
+        need(mapping->record, "record");
+        need(counters, "counters");
+        need(sums, "sums");
+        trace_leaves(mapping, counters, sums, stream);
+    });
+}
+
+int llama_copy_transfer(const llama_mapping_desc* src, const llama_blob* src_blobs, uint32_t src_memory,
+                        const llama_mapping_desc* dst, const llama_blob* dst_blobs, uint32_t dst_memory,
+                        uint64_t chunk_bytes, void* stream)
+{
+    return guarded(
+        [&] { copy_transfer(src, src_blobs, src_memory, dst, dst_blobs, dst_memory, chunk_bytes, stream); });
+}
+
+int llama_copy_box(const llama_mapping_desc* src, const llama_blob* src_blobs, const uint64_t* src_offset,
+                   const llama_mapping_desc* dst, const llama_blob* dst_blobs, const uint64_t* dst_offset,
+                   const uint64_t* box, const llama_copy_options* options, void* stream)
+{
+    return guarded([&] { copy_box(src, src_blobs, src_offset, dst, dst_blobs, dst_offset, box, options, stream); });
 }
 
 int llama_copy_leaves(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
@@ -349,6 +502,14 @@ int llama_batch_launch(llama_batch* batch, void* stream)
     return guarded([&] {
         need(batch, "batch");
         launch_batch(batch->b, stream);
+    });
+}
+
+int llama_batch_autotune(llama_batch* batch, void* stream, uint32_t reps, double* best_gbs)
+{
+    return guarded([&] {
+        need(batch, "batch");
+        autotune_batch(batch->b, stream, int(reps), best_gbs);
     });
 }
 

@@ -2,6 +2,8 @@
 #include "core.hpp"
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <iterator>
 
@@ -193,7 +195,7 @@ std::vector<Part> parts_of(const llama_mapping_desc* m, const Record& r, int dep
         llama_mapping_desc inner = *m;
         inner.kind = sd->kind[k];
         inner.lanes = sd->lanes[k];
-        inner.reserved = 0;
+        inner.linearizer = 0;
         inner.split = sd->kind[k] == LLAMA_SPLIT ? sd->split[k] : nullptr;
         if (sd->kind[k] == LLAMA_SPLIT) {
             // the inner split's parts, their leaves renumbered in this record
@@ -257,17 +259,36 @@ Side make_side(const llama_mapping_desc* m, const Record& r)
         fail(LLAMA_E_INVALID_ARG, "mapping kind " + std::to_string(m->kind) + " is not a llama_mapping_kind");
     if (m->rank < 1 || m->rank > LLAMA_MAX_RANK)
         fail(LLAMA_E_INVALID_ARG, "mapping rank must be 1..8");
-    if (m->reserved != 0)
-        fail(LLAMA_E_INVALID_ARG, "mapping reserved field must be 0");
-    if (m->kind == LLAMA_SPLIT)
+    if (m->linearizer > LLAMA_MORTON)
+        fail(LLAMA_E_INVALID_ARG, "mapping linearizer " + std::to_string(m->linearizer) + " is not a llama_linearizer");
+    if (m->kind == LLAMA_SPLIT) {
+        if (m->linearizer != LLAMA_ROW_MAJOR)
+            fail(LLAMA_E_UNSUPPORTED, "Split mappings take the row-major linearizer only");
         return split_side(m, r);
+    }
     Side s;
     s.kind = m->kind;
     s.rank = m->rank;
-    uint64_t n = 1;
+    // rank 1 and One: every linearizer is the identity
+    s.lin = (m->rank == 1 || m->kind == LLAMA_ONE) ? uint32_t(LLAMA_ROW_MAJOR) : m->linearizer;
+    uint64_t n = 1, largest = 0;
     for (uint32_t d = 0; d < m->rank; d++) {
         s.extents[d] = m->extents[d];
         n = mul(n, m->extents[d], "record count");
+        largest = std::max(largest, m->extents[d]);
+    }
+    s.records = n;
+    if (s.lin == LLAMA_MORTON) {
+        while ((uint64_t(1) << s.morton_bits) < largest)
+            s.morton_bits++;
+        if (uint64_t(s.morton_bits) * m->rank > 63)
+            fail(LLAMA_E_OVERFLOW, "the Morton index of these extents does not fit 63 bits");
+        if (n > 0) { // indices up to the last coordinate's
+            uint64_t last[LLAMA_MAX_RANK] = {};
+            for (uint32_t d = 0; d < m->rank; d++)
+                last[d] = m->extents[d] - 1;
+            n = linearize(s, last) + 1;
+        }
     }
     s.n = n;
     s.npad = n;
@@ -336,7 +357,27 @@ Side make_side(const llama_mapping_desc* m, const Record& r)
     return s;
 }
 
-namespace {
+uint64_t linearize(const Side& s, const uint64_t* c)
+{
+    uint64_t i = 0;
+    if (s.lin == LLAMA_MORTON) {
+        for (uint32_t j = 0; j < s.morton_bits; j++)
+            for (uint32_t d = 0; d < s.rank; d++)
+                i |= ((c[d] >> j) & 1u) << (j * s.rank + (s.rank - 1 - d));
+    } else if (s.lin == LLAMA_COL_MAJOR) {
+        for (int d = int(s.rank) - 1; d >= 0; d--)
+            i = i * s.extents[d] + c[d];
+    } else {
+        for (uint32_t d = 0; d < s.rank; d++)
+            i = i * s.extents[d] + c[d];
+    }
+    return i;
+}
+
+bool needs_box(const Request& rq)
+{
+    return rq.src.lin != rq.dst.lin || rq.src.n != rq.src.records || rq.dst.n != rq.dst.records;
+}
 
 void check_blobs(const char* which, const Side& s, const llama_blob* blobs, std::vector<uint64_t>& ptrs)
 {
@@ -355,6 +396,8 @@ void check_blobs(const char* which, const Side& s, const llama_blob* blobs, std:
         ptrs[b] = p;
     }
 }
+
+namespace {
 
 bool overlaps(uint64_t a, uint64_t an, uint64_t b, uint64_t bn)
 {
@@ -1006,6 +1049,9 @@ Plan make_plan_raw(const Request& rq, const llama_copy_options* opt);
 // caller's threads and wg_per_cu still win).
 Plan make_plan(const Request& rq, const llama_copy_options* opt)
 {
+    if (needs_box(rq))
+        fail(LLAMA_E_UNSUPPORTED, "the two views place records at different linear indices (differing "
+                                  "linearizers, or Morton holes): copy them with llama_copy or llama_copy_box");
     if (!opt || (opt->path == LLAMA_PATH_AUTO && opt->tile_records == 0)) {
         llama_copy_options tuned;
         if (tune_lookup(tune_key(rq), tuned)) {
@@ -1153,5 +1199,42 @@ Plan make_plan_raw(const Request& rq, const llama_copy_options* opt)
 }
 
 } // namespace
+
+bool trace_enabled()
+{
+    static const bool on = [] {
+        const char* v = std::getenv("LLAMA_TRACE");
+        return v && *v && std::string(v) != "0";
+    }();
+    return on;
+}
+
+void trace_plan(const Plan& p)
+{
+    static const char* const paths[] = {"auto", "stream", "tile", "naive", "empty"};
+    std::string mode;
+    if (p.path == LLAMA_PATH_TILE) {
+        const uint32_t f = p.tile.h.flags;
+        mode = (f & kTileDirectLoad)    ? " mode=direct_load"
+               : (f & kTileDirectStore) ? " mode=direct_store"
+               : (f & kTileGatherStore) ? ((f & kTileGatherOdd) ? " mode=gather_odd" : " mode=gather_store")
+                                        : " mode=staged";
+        mode += " tile=" + std::to_string(1u << p.tile.h.log2_tile) + " entries=" +
+                std::to_string(p.tile.h.num_entries) + " lds=" + std::to_string(p.tile.h.lds_bytes);
+        if (f & kTilePreserve)
+            mode += " keep_padding";
+        if (f & kTileStreamLoads)
+            mode += " nt_loads";
+        if (f & kTileStreamStores)
+            mode += " nt_stores";
+    } else if (p.path == LLAMA_PATH_STREAM) {
+        mode = " runs=" + std::to_string(p.stream.num_runs) + " chunks=" + std::to_string(p.stream.num_chunks);
+        if (p.stream.flags & kStreamLoadsOnce)
+            mode += " nt_loads";
+    }
+    std::fprintf(stderr, "[llama] path=%s%s threads=%u workgroups=%llu wg_per_cu=%u read=%llu write=%llu\n",
+                 paths[p.path < 5 ? p.path : 0], mode.c_str(), p.threads, (unsigned long long)p.workgroups,
+                 p.wg_per_cu, (unsigned long long)p.read_bytes, (unsigned long long)p.write_bytes);
+}
 
 } // namespace llama

@@ -50,7 +50,13 @@ struct Side {
     uint32_t kind = 0;
     uint32_t rank = 0;
     uint64_t extents[LLAMA_MAX_RANK] = {};
-    uint64_t n = 0;     // records
+    // the linearizer (llama_linearizer; rank 1: always row-major) and, for
+    // Morton order, the bits per dimension of the index
+    uint32_t lin = LLAMA_ROW_MAJOR;
+    uint32_t morton_bits = 0;
+    uint64_t records = 0; // coordinates: the product of the extents
+    uint64_t n = 0;     // linear indices laid out: the records, or with Morton order the last
+                        // coordinate's index + 1 (indices no coordinate reaches are padding)
     uint64_t lanes = 0; // L (0: unblocked)
     uint64_t block = 0; // K
     uint64_t npad = 0;  // records the blob spans, trailing AoSoA lanes included
@@ -79,12 +85,19 @@ struct Side {
 
 Side make_side(const llama_mapping_desc* m, const Record& r);
 
+// the linear index of coordinate c on side s (its linearizer)
+uint64_t linearize(const Side& s, const uint64_t* c);
+
 // A validated copy request: both sides plus device addresses.
 struct Request {
     Record record;
     Side src, dst;
     std::vector<uint64_t> src_ptr, dst_ptr; // device addresses of the blobs
 };
+
+// Checks a side's blob array (sizes, NULL pointers, address overflow) and
+// collects the device addresses.
+void check_blobs(const char* which, const Side& s, const llama_blob* blobs, std::vector<uint64_t>& ptrs);
 
 // Validates descriptors (and blobs when given) and builds the request.  A
 // Split side fails with LLAMA_E_UNSUPPORTED unless `allow_split`.
@@ -123,9 +136,34 @@ struct Plan {
     TileArgs tile{};     // path == TILE
     StreamArgs stream{}; // path == STREAM
     NaiveArgs naive{};   // path == NAIVE
+    BoxArgs box{};       // path == BOX (box_naive: its element-wise baseline)
+    bool box_naive = false;
 };
 
 Plan make_plan(const Request& rq, const llama_copy_options* opt);
+
+// A copy whose records sit at different linear indices on the two sides
+// (differing linearizers, or Morton indices that no coordinate reaches): it
+// runs through the box kernel (box.cpp), not the linear-index planner.
+bool needs_box(const Request& rq);
+
+// Plans of the box kernel for a box copy (sec. 3.2 VirtualView, sec. 3.9) or,
+// with `full`, for a whole copy between views whose linearizers differ: the
+// box launch, then (full copies into AoSoA) a zero fill of the lanes past the
+// last index.  rq's sides may have different extents; so / dof / box give
+// the box in each view's coordinates.
+std::vector<Plan> make_box_plans(const Request& rq, const uint64_t* so, const uint64_t* dof, const uint64_t* box,
+                                 bool full, const llama_copy_options* opt);
+
+// llama_copy_transfer (transfer.cpp): validates, plans and enqueues.
+void copy_transfer(const llama_mapping_desc* src, const llama_blob* src_blobs, uint32_t src_memory,
+                   const llama_mapping_desc* dst, const llama_blob* dst_blobs, uint32_t dst_memory,
+                   uint64_t chunk_bytes, void* stream);
+
+// llama_copy_box (box.cpp): validates, plans and enqueues.
+void copy_box(const llama_mapping_desc* src, const llama_blob* src_blobs, const uint64_t* src_offset,
+              const llama_mapping_desc* dst, const llama_blob* dst_blobs, const uint64_t* dst_offset,
+              const uint64_t* box, const llama_copy_options* options, void* stream);
 
 constexpr uint32_t kPlanNoDirect = LLAMA_COPY_NO_DIRECT;
 constexpr uint32_t kPlanNoSplit = LLAMA_COPY_NO_SPLIT;
@@ -134,8 +172,19 @@ constexpr uint32_t kCopyFlags = LLAMA_COPY_NO_DIRECT | LLAMA_COPY_NO_SPLIT | LLA
 // the flags that change only speed, which the tuner may choose and cache
 constexpr uint32_t kTuneFlags = LLAMA_COPY_NO_DIRECT | LLAMA_COPY_NO_SPLIT;
 
+// LLAMA_TRACE set in the environment (to anything but "0"): every launch
+// writes one line describing its plan to stderr
+bool trace_enabled();
+void trace_plan(const Plan& p);
+
 // kernels.hip
 void launch(const Plan& p, void* stream);
+// table != NULL: uploads the Heatmap's count table on `stream` and makes
+// this thread's launches take the counted kernel variants; NULL: plain again
+void set_counting(const CountTable* table, void* stream);
+// llama_trace_leaves: per-leaf sums of a view's per-byte counters
+// (sums[0 .. F-1]) and the sum over the bytes no leaf owns (sums[F])
+void trace_leaves(const llama_mapping_desc* m, uint32_t* const* counters, uint64_t* sums, void* stream);
 uint32_t device_cu_count(); // compute units of the current device (256 when none is visible)
 // adds a 64-bit hash of bytes [p, p + len) to *acc (device memory), on `stream`
 void launch_hash(const void* p, uint64_t len, unsigned long long* acc, void* stream);

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "llama_mi355x.h"
+
 namespace llama {
 
 // ---------------------------------------------------------------------------
@@ -260,5 +262,112 @@ struct BatchArgs {
 
 // BatchArgs.flags: the source loads carry the nontemporal hint
 constexpr uint32_t kBatchLoadsOnce = 1;
+
+// ---------------------------------------------------------------------------
+// BOX: copies whose records sit at different linear indices on the two sides:
+// a box of the array dimensions between views of different extents (sec. 3.2
+// VirtualView, sec. 3.9), or views whose linearizers differ (sec. 3.7).
+//
+// A work unit is a tile: a box of 2^qlog[d] coordinates per dimension,
+// clipped to the copy's box.  Each side walks the tile's records as runs of
+// consecutive linear indices of its own order:
+//   kOrderRow     runs along the last dimension (row-major side);
+//   kOrderCol     runs along the first dimension (column-major side);
+//   kOrderMorton  one run over the whole tile (a Morton side whose tiles are
+//                 aligned cubes: such a cube is one range of Morton indices);
+//   kOrderPoint   one run per record (a Morton side whose tiles are not
+//                 aligned);
+//   kOrderOne     a One source: a single run of its single record.
+// The source runs are loaded into LDS (a record-major side as the 16-byte
+// granules of the blocks a run touches, a field-major side per leaf); the
+// destination is written value by value from there (field-major and AoSoA
+// destinations), or through a destination region of whole records stored as
+// exact byte spans (AoS destinations).
+// ---------------------------------------------------------------------------
+
+enum : uint32_t { kOrderRow = 0, kOrderCol = 1, kOrderMorton = 2, kOrderPoint = 3, kOrderOne = 4 };
+enum : uint32_t { kLinRow = 0, kLinCol = 1, kLinMorton = 2 };
+
+constexpr int kBoxMaxEntries = 100;
+
+struct BoxSide {
+    uint64_t offset[LLAMA_MAX_RANK]; // the box's origin in this view's coordinates
+    uint64_t extent[LLAMA_MAX_RANK]; // this view's extents
+    uint64_t blob;     // record-major: device address of the blob
+    uint64_t npad;     // linear indices the blob spans (loads and stores stay below)
+    uint64_t block;    // K (record-major)
+    uint32_t log2_lanes; // record-major: log2 L (AoS: 0)
+    uint32_t mode;     // kRecordMajor / kFieldMajor (SoA)
+    uint32_t lin;      // kLin*: the view's linearizer
+    uint32_t order;    // kOrder*: how a tile's records form runs
+    uint32_t morton_bits; // bits per dimension of the Morton index
+    uint32_t run_log2; // log2 of a run's records (unclipped)
+    uint32_t slot;     // LDS bytes per run
+    uint32_t lds_base; // LDS byte of run 0
+    uint32_t table;    // LDS byte of the run table (one 64-bit start index per run)
+    uint32_t pad;
+};
+
+struct BoxEntry {
+    uint64_t src_addr; // field-major source: blob + leaf base; else 0
+    uint64_t dst_addr; // destination: blob + leaf base (direct stores); 0 for a gap
+    uint32_t size;     // bytes per value (a gap: bytes of the gap)
+    uint32_t src_off;  // record-major source: the leaf's byte in a block; field-major: its LDS byte in a run slot
+    uint32_t dst_off;  // staged destination: the leaf's (or gap's) byte in a record
+    uint32_t gap;      // 1: a destination gap (zeros)
+};
+
+struct BoxHeader {
+    uint32_t rank;
+    uint32_t num_leaves;
+    uint32_t num_entries; // leaves, then destination gaps (staged destinations)
+    uint32_t flags;       // kBoxFull, kBoxPreserve, kBoxStaged, kBoxUnitMorton
+    uint32_t qlog[LLAMA_MAX_RANK]; // tile extents, log2
+    uint32_t qlog_sum;             // log2 of the records of a tile
+    uint32_t lds_bytes;
+    uint64_t box[LLAMA_MAX_RANK];   // the copy's box (full copies: the extents)
+    uint64_t grid[LLAMA_MAX_RANK];  // tiles per dimension
+    uint64_t shift[LLAMA_MAX_RANK]; // tile t covers box coordinates [t q - shift, (t + 1) q - shift)
+    uint64_t num_units;
+};
+
+// a full copy: records outside the extents within a destination run (Morton
+// holes, AoSoA lanes past the last index) are written with zeros
+constexpr uint32_t kBoxFull = 1;
+// padding keeps its bytes (no zeros; a staged destination is loaded first)
+constexpr uint32_t kBoxPreserve = 2;
+// an AoS destination: staged in LDS and stored as exact byte spans
+constexpr uint32_t kBoxStaged = 4;
+// units enumerate aligned cubes in Morton order (a full copy into a Morton
+// destination, whose holes and tail must be written)
+constexpr uint32_t kBoxUnitMorton = 8;
+
+struct BoxArgs {
+    BoxHeader h;
+    BoxSide src, dst;
+    BoxEntry e[kBoxMaxEntries];
+};
+static_assert(sizeof(BoxArgs) <= 4096, "kernel arguments are limited to 4 KiB");
+
+// ---------------------------------------------------------------------------
+// HEATMAP (sec. 3.7): the counted kernel variants add one to a 32-bit counter
+// per byte for every byte a global load reads (blobs in r) and every byte a
+// global store writes (blobs in w).  counters: device address of the blob's
+// hi - lo counters.  The table lives in a device global, written before the
+// counted launches.
+// ---------------------------------------------------------------------------
+
+constexpr int kCountMaxBlobs = 128;
+
+struct CountBlob {
+    uint64_t lo, hi;   // device byte range [lo, hi) of the blob
+    uint64_t counters; // device address of hi - lo 32-bit counters
+};
+
+struct CountTable {
+    uint32_t nr, nw;
+    CountBlob r[kCountMaxBlobs];
+    CountBlob w[kCountMaxBlobs];
+};
 
 } // namespace llama

@@ -42,6 +42,54 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef u32x4 u32x4_a4 __attribute__((aligned(4))); // 16 bytes at a 4-byte-aligned address
 
+// The Heatmap counters of a counted launch (sec. 3.7 Heatmap): set with
+// hipMemcpyAsync before the launch.  A counted kernel variant adds one to a
+// blob's 32-bit counter of a byte for every global load that reads the byte
+// (blobs in r) and every global store that writes it (blobs in w).
+__device__ CountTable g_count_table;
+
+__device__ __forceinline__ void count_range(const CountBlob* t, uint32_t nb, uint64_t a, uint32_t len)
+{
+    for (uint32_t k = 0; k < nb; k++) {
+        const uint64_t lo = t[k].lo, hi = t[k].hi;
+        if (a + len <= lo || a >= hi)
+            continue;
+        uint32_t* c = (uint32_t*)t[k].counters;
+        for (uint64_t b = max(a, lo); b < min(a + len, hi); b++)
+            atomicAdd(c + (b - lo), 1u);
+    }
+}
+
+template <bool kCount>
+__device__ __forceinline__ void note_read(uint64_t a, uint32_t len)
+{
+    if constexpr (kCount)
+        count_range(g_count_table.r, g_count_table.nr, a, len);
+}
+
+template <bool kCount>
+__device__ __forceinline__ void note_write(uint64_t a, uint32_t len)
+{
+    if constexpr (kCount)
+        count_range(g_count_table.w, g_count_table.nw, a, len);
+}
+
+// A global store of one value, counted in a counted variant.
+template <bool kCount, typename T>
+__device__ __forceinline__ void gput(uint64_t a, T v)
+{
+    note_write<kCount>(a, sizeof(T));
+    *(GLOBAL T*)a = v;
+}
+
+// A global load of one value, counted in a counted variant.
+template <bool kCount, typename T>
+__device__ __forceinline__ T gget(uint64_t a)
+{
+    note_read<kCount>(a, sizeof(T));
+    return *(const GLOBAL T*)a;
+}
+
 __device__ __forceinline__ uint32_t wave_id()
 {
     return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -68,9 +116,10 @@ __device__ __forceinline__ T load_const(const CONSTANT T* p)
 // Infinity Cache, which streams them past the caches (a plain copy from HBM
 // measured 6.19 -> 6.52 TB/s with it, reads alone 6.79 -> 7.09 TB/s; a
 // 58 MB batch of frames that the cache holds lost 8% with it).
-template <bool kOnce>
+template <bool kOnce, bool kCount = false>
 __device__ __forceinline__ u32x4 load_src(const GLOBAL u32x4* p)
 {
+    note_read<kCount>(uint64_t(p), 16);
     if constexpr (kOnce)
         return __builtin_nontemporal_load(p);
     else
@@ -78,9 +127,10 @@ __device__ __forceinline__ u32x4 load_src(const GLOBAL u32x4* p)
 }
 
 // The same at a 4-byte-aligned address.
-template <bool kOnce>
+template <bool kOnce, bool kCount = false>
 __device__ __forceinline__ u32x4 load_src_a4(const GLOBAL u32x4_a4* p)
 {
+    note_read<kCount>(uint64_t(p), 16);
     if constexpr (kOnce)
         return __builtin_nontemporal_load(p);
     else
@@ -91,9 +141,10 @@ __device__ __forceinline__ u32x4 load_src_a4(const GLOBAL u32x4_a4* p)
 // destinations far larger than the 256 MB Infinity Cache (tile copies of
 // 1.9 GB measured +3-5% with it; copies of a few hundred MB lose up to 9%,
 // because plain stores can leave part of the writes in that cache).
-template <bool kStream>
+template <bool kStream, bool kCount = false>
 __device__ __forceinline__ void store16(GLOBAL u32x4* p, u32x4 v)
 {
+    note_write<kCount>(uint64_t(p), 16);
     if constexpr (kStream)
         __builtin_nontemporal_store(v, p);
     else
@@ -108,9 +159,10 @@ __device__ __forceinline__ void store16(GLOBAL u32x4* p, u32x4 v)
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Winline-asm" // m0 is written here and used by nothing else in these kernels
 // kOnce: with the nontemporal hint (see load_src).
-template <bool kOnce>
+template <bool kOnce, bool kCount = false>
 __device__ __forceinline__ void lds_dma16(uint64_t gaddr, uint32_t lds_addr)
 {
+    note_read<kCount>(gaddr, 16);
     if constexpr (kOnce)
         asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off nt" : : "v"(gaddr), "s"(lds_addr)
                      : "memory", "m0");
@@ -126,7 +178,7 @@ __device__ __forceinline__ void lds_dma16(uint64_t gaddr, uint32_t lds_addr)
 // nwaves.  A granule that holds a byte of the span lies in the same page as
 // that byte, so the rounding never reaches an unmapped page; the extra bytes
 // are never used.
-template <bool kOnce>
+template <bool kOnce, bool kCount = false>
 __device__ __forceinline__ void load_span(uint64_t gstart, uint32_t len, uint32_t lds_region, uint32_t wave,
                                           uint32_t nwaves, uint32_t first_wave, uint32_t lane, uint32_t lds_base)
 {
@@ -137,7 +189,7 @@ __device__ __forceinline__ void load_span(uint64_t gstart, uint32_t len, uint32_
     for (uint32_t c = c0; c * 64u < G; c += nwaves) {
         const uint32_t gi = c * 64u + lane;
         if (gi < G)
-            lds_dma16<kOnce>(g0 + uint64_t(gi) * 16u, uniform(lds_base + lds_region + c * 1024u));
+            lds_dma16<kOnce, kCount>(g0 + uint64_t(gi) * 16u, uniform(lds_base + lds_region + c * 1024u));
     }
 }
 
@@ -145,7 +197,7 @@ __device__ __forceinline__ void load_span(uint64_t gstart, uint32_t len, uint32_
 // whole granules with 16-byte stores, the partial first and last granule byte
 // by byte so that no byte outside the span is written.  Granule gi goes to
 // thread (gi + rot) mod nthr, so that short spans spread over the waves.
-template <bool kStream>
+template <bool kStream, bool kCount = false>
 __device__ __forceinline__ void store_span(uint64_t gstart, uint32_t len, uint32_t lds_region, uint32_t tid,
                                            uint32_t nthr, uint32_t rot, const uint8_t* lds)
 {
@@ -158,11 +210,11 @@ __device__ __forceinline__ void store_span(uint64_t gstart, uint32_t len, uint32
         const uint32_t hi = min(16u, end - gi * 16u);
         const uint8_t* lp = lds + lds_region + gi * 16u;
         if (lo == 0 && hi == 16) {
-            store16<kStream>((GLOBAL u32x4*)(g0 + uint64_t(gi) * 16u), *(const u32x4*)lp);
+            store16<kStream, kCount>((GLOBAL u32x4*)(g0 + uint64_t(gi) * 16u), *(const u32x4*)lp);
         } else {
-            GLOBAL uint8_t* gp = (GLOBAL uint8_t*)(g0 + uint64_t(gi) * 16u);
+            const uint64_t gp = g0 + uint64_t(gi) * 16u;
             for (uint32_t b = lo; b < hi; b++)
-                gp[b] = lp[b];
+                gput<kCount>(gp + b, lp[b]);
         }
     }
 }
@@ -311,7 +363,7 @@ __device__ __forceinline__ T src_value(const uint8_t* lds, uint32_t sp, const Ti
 // values past the 16-byte grid (the granules stay on the grid) and a granule
 // that passes record nd are stored value by value, only for records 0 .. nd
 // - 1 of the tile.  `gdst` is the leaf's tile base on side d.
-template <typename T, bool kDstRecordMajor, bool kStream>
+template <typename T, bool kDstRecordMajor, bool kStream, bool kCount>
 __device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t sp, const TileSide& s,
                                                   const TileSide& d, uint64_t gdst, uint32_t nv, uint32_t nd,
                                                   uint32_t tid, uint32_t nthr, uint32_t rot, uint32_t ph)
@@ -333,20 +385,20 @@ __device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t s
         constexpr uint32_t lg = sizeof(T) == 16 ? 4 : sizeof(T) == 8 ? 3 : sizeof(T) == 4 ? 2 : sizeof(T) == 2 ? 1 : 0;
         const uint64_t a = leaf_granule_addr<kDstRecordMajor>(gbase, d, g, lg);
         if (r0 >= 0 && uint32_t(r0) + per <= nd) {
-            store16<kStream>((GLOBAL u32x4*)a, u.v);
+            store16<kStream, kCount>((GLOBAL u32x4*)a, u.v);
         } else {
 #pragma unroll
             for (uint32_t j = 0; j < per; j++) {
                 const int32_t r = r0 + int32_t(j);
                 if (r >= 0 && uint32_t(r) < nd)
-                    *(GLOBAL T*)(a + j * sizeof(T)) = u.t[j];
+                    gput<kCount>(a + j * sizeof(T), u.t[j]);
             }
         }
     }
 }
 
 // Direct store of a tile: every leaf in turn, at the width of its values.
-template <bool kDstRecordMajor, bool kStream, typename Entries>
+template <bool kDstRecordMajor, bool kStream, bool kCount, typename Entries>
 __device__ __forceinline__ void direct_store_tile(const TileHeader& h, Entries ent, uint64_t t, uint64_t i0,
                                                   uint32_t nv, uint32_t nd, uint32_t tid, uint32_t nthr,
                                                   const uint8_t* lds)
@@ -358,11 +410,11 @@ __device__ __forceinline__ void direct_store_tile(const TileHeader& h, Entries e
         const uint32_t ph = (e.move >> 20) & 15u;
         const uint32_t sp = e.src_pos;
         switch (e.move & 7u) {
-        case 4: direct_store_leaf<u32x4, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
-        case 3: direct_store_leaf<uint64_t, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
-        case 2: direct_store_leaf<uint32_t, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
-        case 1: direct_store_leaf<uint16_t, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
-        default: direct_store_leaf<uint8_t, kDstRecordMajor, kStream>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
+        case 4: direct_store_leaf<u32x4, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
+        case 3: direct_store_leaf<uint64_t, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
+        case 2: direct_store_leaf<uint32_t, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
+        case 1: direct_store_leaf<uint16_t, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
+        default: direct_store_leaf<uint8_t, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
         }
     }
 }
@@ -372,7 +424,7 @@ __device__ __forceinline__ void direct_store_tile(const TileHeader& h, Entries e
 // flight together), then writes the values to the destination region.
 // Records in [nv, nd) (AoSoA lanes past the last record) and gap entries are
 // zero-filled.
-template <bool kSrcRecordMajor, bool kOnce, typename Entries>
+template <bool kSrcRecordMajor, bool kOnce, bool kCount, typename Entries>
 __device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries ent, uint64_t t, uint64_t i0,
                                                  uint32_t nv, uint32_t nd, uint8_t* lds)
 {
@@ -391,7 +443,7 @@ __device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries en
         const auto& e = ent(f);
         const uint32_t g = q0 + lane - e.src_pos; // granule within the leaf's values of the tile
         if (g * 16u < nv * e.size)
-            v[j] = load_src<kOnce>((const GLOBAL u32x4*)leaf_granule_addr<kSrcRecordMajor>(
+            v[j] = load_src<kOnce, kCount>((const GLOBAL u32x4*)leaf_granule_addr<kSrcRecordMajor>(
                 leaf_tile_base<kSrcRecordMajor>(e.src_addr, h.src, t, i0, e.size), h.src, g, e.move & 7u));
     }
     f = 0;
@@ -461,7 +513,7 @@ __device__ __forceinline__ uint32_t gather_pos(uint32_t x, uint32_t blk, const T
 // Gather store of one tile: every thread assembles 16-byte granules of the
 // destination span word by word from the source region and stores them;
 // padding and records >= nv are zero.
-template <bool kStream, bool kOdd>
+template <bool kStream, bool kOdd, bool kCount>
 __device__ __forceinline__ void gather_store_tile(const TileHeader& h, const TileGather& gg, uint64_t t, uint32_t nv,
                                                   uint32_t nd, uint32_t tid, uint32_t nthr, const uint8_t* lds)
 {
@@ -506,21 +558,21 @@ __device__ __forceinline__ void gather_store_tile(const TileHeader& h, const Til
         }
         const uint64_t a = gbase + uint64_t(u) * 4u;
         if ((u + 4u) * 4u <= span) {
-            store16<kStream>((GLOBAL u32x4*)a, u32x4{v[0], v[1], v[2], v[3]});
+            store16<kStream, kCount>((GLOBAL u32x4*)a, u32x4{v[0], v[1], v[2], v[3]});
         } else if (!kOdd) { // the span's last granule: whole words (blocks of whole words)
 #pragma unroll
             for (uint32_t c = 0; c < 4; c++)
                 if (u + c < words)
-                    *(GLOBAL uint32_t*)(a + 4u * c) = v[c];
+                    gput<kCount>(a + 4u * c, v[c]);
         } else { // the span's last granule: whole words, then the bytes of a partial word
 #pragma unroll
             for (uint32_t c = 0; c < 4; c++) {
                 const uint32_t b = (u + c) * 4u;
                 if (b + 4u <= span)
-                    *(GLOBAL uint32_t*)(a + 4u * c) = v[c];
+                    gput<kCount>(a + 4u * c, v[c]);
                 else
                     for (uint32_t k = 0; b + k < span; k++)
-                        *(GLOBAL uint8_t*)(a + 4u * c + k) = uint8_t(v[c] >> (8u * k));
+                        gput<kCount>(a + 4u * c + k, uint8_t(v[c] >> (8u * k)));
             }
         }
     }
@@ -545,6 +597,8 @@ enum : uint32_t {
 constexpr uint32_t kModeStreamStores = 8;
 // added to a mode: the tile's source loads are nontemporal
 constexpr uint32_t kModeStreamLoads = 16;
+// added to a mode: every global load and store is counted (Heatmap)
+constexpr uint32_t kModeCount = 32;
 
 template <uint32_t ModeBits, typename Entries>
 __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint64_t t, uint8_t* lds,
@@ -553,6 +607,7 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     constexpr uint32_t Mode = ModeBits & 7u;
     constexpr bool kStream = (ModeBits & kModeStreamStores) != 0;
     constexpr bool kOnce = (ModeBits & kModeStreamLoads) != 0;
+    constexpr bool kCount = (ModeBits & kModeCount) != 0;
     const bool dload = Mode == kModeDirectLoad || (Mode == kModeAny && (h.flags & kTileDirectLoad));
     const bool dstore = Mode == kModeDirectStore || (Mode == kModeAny && (h.flags & kTileDirectStore));
     const bool gstore = Mode == kModeGatherStore || Mode == kModeGatherOdd ||
@@ -572,24 +627,24 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     // ---- 1. source span(s) -> LDS
     if (dload) {
         if (h.src.mode == kRecordMajor)
-            direct_load_tile<true, kOnce>(h, ent, t, i0, nv, nd, lds);
+            direct_load_tile<true, kOnce, kCount>(h, ent, t, i0, nv, nd, lds);
         else
-            direct_load_tile<false, kOnce>(h, ent, t, i0, nv, nd, lds);
+            direct_load_tile<false, kOnce, kCount>(h, ent, t, i0, nv, nd, lds);
     } else if (nv > 0) {
         if (h.src.mode == kRecordMajor) {
             const uint32_t len = uint32_t(((uint64_t(nv) + h.src.lanes - 1) >> h.src.log2_lanes) * h.src.block);
-            load_span<kOnce>(h.src.span_base + t * h.src.tile_bytes, len, h.src.lds_base, wave, nwaves, 0, lane, lds_base);
+            load_span<kOnce, kCount>(h.src.span_base + t * h.src.tile_bytes, len, h.src.lds_base, wave, nwaves, 0, lane, lds_base);
         } else {
             for (uint32_t f = 0; f < h.num_leaves; f++) {
                 const auto& e = ent(f);
-                load_span<kOnce>(field_span_start(e.src_addr, h.src, i0, e.size), nv * e.size, e.src_pos & ~15u, wave,
+                load_span<kOnce, kCount>(field_span_start(e.src_addr, h.src, i0, e.size), nv * e.size, e.src_pos & ~15u, wave,
                           nwaves, (e.move >> 4) & 15u, lane, lds_base);
             }
         }
     }
     if (preserve && !dstore && h.dst.mode == kRecordMajor) {
         const uint32_t len = uint32_t(((uint64_t(nd) + h.dst.lanes - 1) >> h.dst.log2_lanes) * h.dst.block);
-        load_span<false>(h.dst.span_base + t * h.dst.tile_bytes, len, h.dst.lds_base, wave, nwaves, 0, lane, lds_base);
+        load_span<false, kCount>(h.dst.span_base + t * h.dst.tile_bytes, len, h.dst.lds_base, wave, nwaves, 0, lane, lds_base);
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -598,11 +653,11 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
         // ---- 2''. the destination region is complete: store it
         if (h.dst.mode == kRecordMajor) {
             const uint32_t len = uint32_t(((uint64_t(nd) + h.dst.lanes - 1) >> h.dst.log2_lanes) * h.dst.block);
-            store_span<kStream>(h.dst.span_base + t * h.dst.tile_bytes, len, h.dst.lds_base, tid, nthr, 0, lds);
+            store_span<kStream, kCount>(h.dst.span_base + t * h.dst.tile_bytes, len, h.dst.lds_base, tid, nthr, 0, lds);
         } else {
             for (uint32_t f = 0; f < h.num_leaves; f++) {
                 const auto& e = ent(f);
-                store_span<kStream>(field_span_start(e.dst_addr, h.dst, i0, e.size), nd * e.size, e.dst_pos & ~15u, tid,
+                store_span<kStream, kCount>(field_span_start(e.dst_addr, h.dst, i0, e.size), nd * e.size, e.dst_pos & ~15u, tid,
                            nthr, (e.move >> 8) & 4095u, lds);
             }
         }
@@ -613,9 +668,9 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
         // ---- 2'''. assemble every destination granule word by word from
         //           the source region and store it; no destination region
         if (Mode == kModeGatherOdd || (Mode == kModeAny && (h.flags & kTileGatherOdd)))
-            gather_store_tile<kStream, true>(h, *gg, t, nv, nd, tid, nthr, lds);
+            gather_store_tile<kStream, true, kCount>(h, *gg, t, nv, nd, tid, nthr, lds);
         else
-            gather_store_tile<kStream, false>(h, *gg, t, nv, nd, tid, nthr, lds);
+            gather_store_tile<kStream, false, kCount>(h, *gg, t, nv, nd, tid, nthr, lds);
         return;
     }
 
@@ -623,9 +678,9 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
         // ---- 2'. gather each destination granule from the source region and
         //          store it; no destination region, no second barrier
         if (h.dst.mode == kRecordMajor)
-            direct_store_tile<true, kStream>(h, ent, t, i0, nv, ns, tid, nthr, lds);
+            direct_store_tile<true, kStream, kCount>(h, ent, t, i0, nv, ns, tid, nthr, lds);
         else
-            direct_store_tile<false, kStream>(h, ent, t, i0, nv, ns, tid, nthr, lds);
+            direct_store_tile<false, kStream, kCount>(h, ent, t, i0, nv, ns, tid, nthr, lds);
         return;
     }
 
@@ -662,11 +717,11 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     // ---- 3. LDS -> destination span(s)
     if (h.dst.mode == kRecordMajor) {
         const uint32_t len = uint32_t(((uint64_t(nd) + h.dst.lanes - 1) >> h.dst.log2_lanes) * h.dst.block);
-        store_span<kStream>(h.dst.span_base + t * h.dst.tile_bytes, len, h.dst.lds_base, tid, nthr, 0, lds);
+        store_span<kStream, kCount>(h.dst.span_base + t * h.dst.tile_bytes, len, h.dst.lds_base, tid, nthr, 0, lds);
     } else {
         for (uint32_t f = 0; f < h.num_leaves; f++) {
             const auto& e = ent(f);
-            store_span<kStream>(field_span_start(e.dst_addr, h.dst, i0, e.size), ns * e.size, e.dst_pos & ~15u, tid, nthr,
+            store_span<kStream, kCount>(field_span_start(e.dst_addr, h.dst, i0, e.size), ns * e.size, e.dst_pos & ~15u, tid, nthr,
                        (e.move >> 8) & 4095u, lds);
         }
     }
@@ -701,13 +756,29 @@ __global__ void __launch_bounds__(1024) tile_kernel(const TileArgs a)
     }
 }
 
+// The counted variant of tile_kernel (plain loads and stores; one workgroup
+// per tile in plain order, or a grid-stride loop), for the Heatmap.
+template <uint32_t Mode>
+__global__ void __launch_bounds__(1024) tile_count_kernel(const TileArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    auto ent = [&](uint32_t k) -> const TileEntry& { return a.e[k]; };
+    if (Mode == kModeGatherStore || Mode == kModeGatherOdd)
+        gather_table(a.h, a.gather, reinterpret_cast<const uint32_t*>(a.e + a.h.num_entries), lds);
+    for (uint64_t t = blockIdx.x; t < a.h.num_tiles; t += gridDim.x) {
+        tile_body<Mode | kModeCount>(a.h, ent, t, lds, &a.gather);
+        if (t + gridDim.x < a.h.num_tiles)
+            __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // STREAM
 // ---------------------------------------------------------------------------
 
 // Copies [src, src + len) to [dst, dst + len) (src == 0: writes zeros);
 // src and dst are congruent modulo 4.
-template <bool kOnce>
+template <bool kOnce, bool kCount = false>
 __device__ __forceinline__ void copy_run_chunk(uint64_t dst, uint64_t src, uint64_t len, uint32_t tid, uint32_t nthr)
 {
     const uint32_t head = uint32_t(min<uint64_t>(len, (16u - (uint32_t(dst) & 15u)) & 15u));
@@ -716,52 +787,53 @@ __device__ __forceinline__ void copy_run_chunk(uint64_t dst, uint64_t src, uint6
     const bool zero = src == 0;
     // head and tail bytes
     if (tid < head)
-        ((GLOBAL uint8_t*)dst)[tid] = zero ? 0 : ((const GLOBAL uint8_t*)src)[tid];
+        gput<kCount>(dst + tid, zero ? uint8_t(0) : gget<kCount, uint8_t>(src + tid));
     if (tid < tail) {
         const uint64_t o = head + body + tid;
-        ((GLOBAL uint8_t*)dst)[o] = zero ? 0 : ((const GLOBAL uint8_t*)src)[o];
+        gput<kCount>(dst + o, zero ? uint8_t(0) : gget<kCount, uint8_t>(src + o));
     }
     // 16-byte granules: 4 per thread in flight
     GLOBAL u32x4* d = (GLOBAL u32x4*)(dst + head);
     const uint64_t ng = body >> 4;
     if (zero) {
         for (uint64_t g = tid; g < ng; g += nthr)
-            d[g] = u32x4{0u, 0u, 0u, 0u};
+            gput<kCount>(uint64_t(d + g), u32x4{0u, 0u, 0u, 0u});
         return;
     }
     if (((src + head) & 15u) == 0) {
         const GLOBAL u32x4* s = (const GLOBAL u32x4*)(src + head);
         uint64_t g = tid;
         for (; g + 3u * nthr < ng; g += 4u * nthr) {
-            u32x4 v0 = load_src<kOnce>(s + g), v1 = load_src<kOnce>(s + g + nthr), v2 = load_src<kOnce>(s + g + 2u * nthr),
-                  v3 = load_src<kOnce>(s + g + 3u * nthr);
-            d[g] = v0;
-            d[g + nthr] = v1;
-            d[g + 2u * nthr] = v2;
-            d[g + 3u * nthr] = v3;
+            u32x4 v0 = load_src<kOnce, kCount>(s + g), v1 = load_src<kOnce, kCount>(s + g + nthr),
+                  v2 = load_src<kOnce, kCount>(s + g + 2u * nthr), v3 = load_src<kOnce, kCount>(s + g + 3u * nthr);
+            gput<kCount>(uint64_t(d + g), v0);
+            gput<kCount>(uint64_t(d + g + nthr), v1);
+            gput<kCount>(uint64_t(d + g + 2u * nthr), v2);
+            gput<kCount>(uint64_t(d + g + 3u * nthr), v3);
         }
         for (; g < ng; g += nthr)
-            d[g] = load_src<kOnce>(s + g);
+            gput<kCount>(uint64_t(d + g), load_src<kOnce, kCount>(s + g));
     } else {
         const GLOBAL u32x4_a4* s = (const GLOBAL u32x4_a4*)(src + head);
         uint64_t g = tid;
         for (; g + 3u * nthr < ng; g += 4u * nthr) {
-            const u32x4 v0 = load_src_a4<kOnce>(s + g), v1 = load_src_a4<kOnce>(s + g + nthr),
-                        v2 = load_src_a4<kOnce>(s + g + 2u * nthr), v3 = load_src_a4<kOnce>(s + g + 3u * nthr);
-            d[g] = v0;
-            d[g + nthr] = v1;
-            d[g + 2u * nthr] = v2;
-            d[g + 3u * nthr] = v3;
+            const u32x4 v0 = load_src_a4<kOnce, kCount>(s + g), v1 = load_src_a4<kOnce, kCount>(s + g + nthr),
+                        v2 = load_src_a4<kOnce, kCount>(s + g + 2u * nthr),
+                        v3 = load_src_a4<kOnce, kCount>(s + g + 3u * nthr);
+            gput<kCount>(uint64_t(d + g), v0);
+            gput<kCount>(uint64_t(d + g + nthr), v1);
+            gput<kCount>(uint64_t(d + g + 2u * nthr), v2);
+            gput<kCount>(uint64_t(d + g + 3u * nthr), v3);
         }
         for (; g < ng; g += nthr)
-            d[g] = load_src_a4<kOnce>(s + g);
+            gput<kCount>(uint64_t(d + g), load_src_a4<kOnce, kCount>(s + g));
     }
 }
 
 // Work unit c of a run list: the run holding chunk c is the last run whose
 // first chunk is <= c.  `run(k)` returns run k.
 // Chunks are 2^chunk_log2 bytes.
-template <bool kOnce, typename Runs>
+template <bool kOnce, bool kCount, typename Runs>
 __device__ __forceinline__ void stream_unit(Runs run, uint32_t num_runs, uint64_t c, uint32_t chunk_log2)
 {
     uint32_t lo = 0, hi = num_runs;
@@ -775,7 +847,7 @@ __device__ __forceinline__ void stream_unit(Runs run, uint32_t num_runs, uint64_
     const auto& r = run(lo);
     const uint64_t off = (c - r.first_chunk) << chunk_log2;
     const uint64_t len = min<uint64_t>(r.bytes - off, uint64_t(1) << chunk_log2);
-    copy_run_chunk<kOnce>(r.dst + off, r.src ? r.src + off : 0, len, threadIdx.x, blockDim.x);
+    copy_run_chunk<kOnce, kCount>(r.dst + off, r.src ? r.src + off : 0, len, threadIdx.x, blockDim.x);
 }
 
 // kOnce: nontemporal source loads (StreamArgs.flags & kStreamLoadsOnce).
@@ -784,7 +856,15 @@ __global__ void __launch_bounds__(1024) stream_kernel(const StreamArgs a)
 {
     auto run = [&](uint32_t k) -> const StreamRun& { return a.r[k]; };
     for (uint64_t c = blockIdx.x; c < a.num_chunks; c += gridDim.x)
-        stream_unit<kOnce>(run, a.num_runs, c, kStreamChunkLog2);
+        stream_unit<kOnce, false>(run, a.num_runs, c, kStreamChunkLog2);
+}
+
+// The counted variant of stream_kernel (plain loads), for the Heatmap.
+__global__ void __launch_bounds__(1024) stream_count_kernel(const StreamArgs a)
+{
+    auto run = [&](uint32_t k) -> const StreamRun& { return a.r[k]; };
+    for (uint64_t c = blockIdx.x; c < a.num_chunks; c += gridDim.x)
+        stream_unit<false, true>(run, a.num_runs, c, kStreamChunkLog2);
 }
 
 // ---------------------------------------------------------------------------
@@ -825,7 +905,7 @@ __device__ __forceinline__ void batch_unit(const BatchArgs& a, const CONSTANT ui
             h, [&](uint32_t k) -> const CONSTANT TileEntry& { return entries[k]; }, u, lds, &gg);
     } else {
         const CONSTANT StreamRun* runs = (const CONSTANT StreamRun*)a.runs + it->first;
-        stream_unit<kOnce>([&](uint32_t k) -> const CONSTANT StreamRun& { return runs[k]; }, it->count, u,
+        stream_unit<kOnce, false>([&](uint32_t k) -> const CONSTANT StreamRun& { return runs[k]; }, it->count, u,
                            kBatchStreamChunkLog2);
     }
 }
@@ -923,17 +1003,550 @@ __global__ void __launch_bounds__(1024) batch_kernel(const BatchArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// BOX: records at different linear indices on the two sides (sub-boxes,
+// differing linearizers); see BoxArgs
+// ---------------------------------------------------------------------------
+
+// The fast dimension of an order's runs (-1: none).
+__device__ __forceinline__ int box_fast(uint32_t order, uint32_t rank)
+{
+    return order == kOrderRow ? int(rank) - 1 : order == kOrderCol ? 0 : -1;
+}
+
+// Tile-local coordinate x of element e of run k (for row and column orders,
+// e is the coordinate in the fast dimension).  The run index ravels the
+// other dimensions, last fastest; a Morton run's element is the Morton index
+// inside the tile's cube.
+__device__ __forceinline__ void box_coord(const BoxHeader& h, uint32_t order, uint32_t k, uint32_t e, uint32_t* x)
+{
+    const uint32_t r = h.rank;
+    if (order == kOrderMorton) {
+#pragma unroll
+        for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+            x[d] = 0;
+        for (uint32_t j = 0; j < h.qlog[0]; j++)
+#pragma unroll
+            for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+                if (d < r)
+                    x[d] |= ((e >> (j * r + r - 1 - d)) & 1u) << j;
+        return;
+    }
+    const int fast = box_fast(order, r);
+    uint32_t rem = k;
+#pragma unroll
+    for (int d = LLAMA_MAX_RANK - 1; d >= 0; d--) {
+        if (d >= int(r)) {
+            x[d] = 0;
+        } else if (d == fast) {
+            x[d] = e;
+        } else {
+            x[d] = rem & ((1u << h.qlog[d]) - 1u);
+            rem >>= h.qlog[d];
+        }
+    }
+}
+
+// The inverse of box_coord: run k and element e of tile-local coordinate x.
+__device__ __forceinline__ void box_run(const BoxHeader& h, uint32_t order, const uint32_t* x, uint32_t& k, uint32_t& e)
+{
+    const uint32_t r = h.rank;
+    k = 0;
+    e = 0;
+    if (order == kOrderOne)
+        return;
+    if (order == kOrderMorton) {
+        for (uint32_t j = 0; j < h.qlog[0]; j++)
+#pragma unroll
+            for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+                if (d < r)
+                    e |= ((x[d] >> j) & 1u) << (j * r + r - 1 - d);
+        return;
+    }
+    const int fast = box_fast(order, r);
+#pragma unroll
+    for (int d = 0; d < LLAMA_MAX_RANK; d++) {
+        if (d >= int(r))
+            continue;
+        if (d == fast)
+            e = x[d];
+        else
+            k = (k << h.qlog[d]) | x[d];
+    }
+}
+
+// Linear index of the absolute coordinate c on side s (its linearizer).
+__device__ __forceinline__ uint64_t box_linear(const BoxSide& s, uint32_t r, const uint64_t* c)
+{
+    uint64_t i = 0;
+    if (s.lin == kLinMorton) {
+        for (uint32_t j = 0; j < s.morton_bits; j++)
+#pragma unroll
+            for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+                if (d < r)
+                    i |= ((c[d] >> j) & 1ull) << (j * r + r - 1 - d);
+    } else if (s.lin == kLinCol) {
+#pragma unroll
+        for (int d = LLAMA_MAX_RANK - 1; d >= 0; d--)
+            if (d < int(r))
+                i = i * s.extent[d] + c[d];
+    } else {
+#pragma unroll
+        for (int d = 0; d < LLAMA_MAX_RANK; d++)
+            if (d < int(r))
+                i = i * s.extent[d] + c[d];
+    }
+    return i;
+}
+
+// Records of run k whose start index is `start` (~0: an empty run): the
+// clipped fast range for row and column orders, the cube up to the blob's
+// end for a Morton run, one record otherwise.
+__device__ __forceinline__ uint32_t box_run_len(const BoxSide& s, uint32_t Q, uint64_t start, uint32_t fast_len)
+{
+    if (start == ~0ull)
+        return 0;
+    if (s.order == kOrderRow || s.order == kOrderCol)
+        return fast_len;
+    if (s.order == kOrderMorton)
+        return start >= s.npad ? 0u : uint32_t(min<uint64_t>(Q, s.npad - start));
+    return 1;
+}
+
+// Copies `size` bytes inside LDS at the widest width both positions allow.
+__device__ __forceinline__ void box_move_lds(uint8_t* lds, uint32_t sp, uint32_t dp, uint32_t size)
+{
+    const uint32_t al = sp | dp | size;
+    if ((al & 7u) == 0) {
+        for (uint32_t b = 0; b < size; b += 8)
+            *(uint64_t*)(lds + dp + b) = *(const uint64_t*)(lds + sp + b);
+    } else if ((al & 3u) == 0) {
+        for (uint32_t b = 0; b < size; b += 4)
+            *(uint32_t*)(lds + dp + b) = *(const uint32_t*)(lds + sp + b);
+    } else if ((al & 1u) == 0) {
+        for (uint32_t b = 0; b < size; b += 2)
+            *(uint16_t*)(lds + dp + b) = *(const uint16_t*)(lds + sp + b);
+    } else {
+        for (uint32_t b = 0; b < size; b++)
+            lds[dp + b] = lds[sp + b];
+    }
+}
+
+// Writes `size` bytes from LDS (sp; zero: zeros) to global address g at the
+// widest width both allow.
+template <bool kCount>
+__device__ __forceinline__ void box_store_value(const uint8_t* lds, uint32_t sp, uint64_t g, uint32_t size, bool zero)
+{
+    const uint32_t al = (zero ? 0u : sp) | uint32_t(g) | size;
+    if ((al & 7u) == 0) {
+        for (uint32_t b = 0; b < size; b += 8)
+            gput<kCount>(g + b, zero ? uint64_t(0) : *(const uint64_t*)(lds + sp + b));
+    } else if ((al & 3u) == 0) {
+        for (uint32_t b = 0; b < size; b += 4)
+            gput<kCount>(g + b, zero ? uint32_t(0) : *(const uint32_t*)(lds + sp + b));
+    } else if ((al & 1u) == 0) {
+        for (uint32_t b = 0; b < size; b += 2)
+            gput<kCount>(g + b, zero ? uint16_t(0) : *(const uint16_t*)(lds + sp + b));
+    } else {
+        for (uint32_t b = 0; b < size; b++)
+            gput<kCount>(g + b, zero ? uint8_t(0) : lds[sp + b]);
+    }
+}
+
+// LDS byte of the value of entry en for the record at index i of source run k
+// (start index `start`).
+__device__ __forceinline__ uint32_t box_src_pos(const BoxSide& s, const BoxEntry& en, uint32_t k, uint64_t start,
+                                                uint64_t i)
+{
+    const uint32_t slot = s.lds_base + k * s.slot;
+    if (s.mode == kFieldMajor) {
+        const uint32_t ph = (uint32_t(en.src_addr) + uint32_t(start) * en.size) & 15u;
+        return slot + en.src_off + ph + uint32_t(i - start) * en.size;
+    }
+    if (s.order == kOrderOne)
+        return slot + (uint32_t(s.blob) & 15u) + en.src_off;
+    const uint64_t b0 = start >> s.log2_lanes;
+    const uint32_t ph = (uint32_t(s.blob) + uint32_t(b0) * uint32_t(s.block)) & 15u;
+    const uint64_t m = (uint64_t(1) << s.log2_lanes) - 1u;
+    return slot + ph + uint32_t((i >> s.log2_lanes) - b0) * uint32_t(s.block) + en.src_off +
+           uint32_t(i & m) * en.size;
+}
+
+template <bool kStaged, bool kCount>
+__device__ __forceinline__ void box_body(const BoxArgs& a, uint64_t u, uint8_t* lds)
+{
+    const BoxHeader& h = a.h;
+    const BoxSide &S = a.src, &D = a.dst;
+    const uint32_t r = h.rank;
+    const uint32_t tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63u, wave = wave_id(), nwaves = nthr >> 6;
+    const uint32_t lds_base = uint32_t(uintptr_t((lds_void_t*)lds));
+    const uint32_t Q = 1u << h.qlog_sum;
+    const bool full = (h.flags & kBoxFull) != 0, preserve = (h.flags & kBoxPreserve) != 0;
+
+    // ---- the tile's frame origin in box coordinates
+    int64_t o[LLAMA_MAX_RANK];
+    if (h.flags & kBoxUnitMorton) {
+        // cube u of the destination's Morton order: deinterleave u
+        uint64_t c[LLAMA_MAX_RANK] = {};
+        for (uint32_t j = 0; j * r < 64; j++)
+#pragma unroll
+            for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+                if (d < r && j * r + r - 1 - d < 64)
+                    c[d] |= ((u >> (j * r + r - 1 - d)) & 1ull) << j;
+#pragma unroll
+        for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+            o[d] = d < r ? int64_t(c[d] << h.qlog[d]) : 0;
+    } else {
+        uint64_t rem = u;
+#pragma unroll
+        for (int d = LLAMA_MAX_RANK - 1; d >= 0; d--) {
+            o[d] = 0;
+            if (d < int(r)) {
+                const uint64_t t = rem % h.grid[d];
+                rem /= h.grid[d];
+                o[d] = int64_t(t << h.qlog[d]) - int64_t(h.shift[d]);
+            }
+        }
+    }
+    // the clipped fast range of each side: [lo, lo + len)
+    const int fs = box_fast(S.order, r), fd = box_fast(D.order, r);
+    uint32_t lo_s = 0, len_s = 0, lo_d = 0, len_d = 0;
+    if (fs >= 0) {
+        const int64_t lo = max<int64_t>(0, -o[fs]), hi = min<int64_t>(1ll << h.qlog[fs], int64_t(h.box[fs]) - o[fs]);
+        lo_s = uint32_t(lo);
+        len_s = hi > lo ? uint32_t(hi - lo) : 0u;
+    }
+    if (fd >= 0) {
+        const int64_t lo = max<int64_t>(0, -o[fd]), hi = min<int64_t>(1ll << h.qlog[fd], int64_t(h.box[fd]) - o[fd]);
+        lo_d = uint32_t(lo);
+        len_d = hi > lo ? uint32_t(hi - lo) : 0u;
+    }
+
+    // ---- run tables: the start index of every run (~0: no record in the box)
+    const uint32_t Rs = Q >> S.run_log2, Rd = Q >> D.run_log2;
+    uint64_t* tab_s = (uint64_t*)(lds + S.table);
+    uint64_t* tab_d = (uint64_t*)(lds + D.table);
+    for (uint32_t q = tid; q < Rs + Rd; q += nthr) {
+        const bool src = q < Rs;
+        const BoxSide& X = src ? S : D;
+        const uint32_t k = src ? q : q - Rs;
+        uint64_t start = ~0ull;
+        if (X.order == kOrderOne) {
+            start = 0;
+        } else if (!src && (h.flags & kBoxUnitMorton)) {
+            start = u << h.qlog_sum; // the cube's first Morton index
+        } else {
+            const int fx = src ? fs : fd;
+            uint32_t x[LLAMA_MAX_RANK];
+            box_coord(h, X.order, k, fx >= 0 ? (src ? lo_s : lo_d) : 0u, x);
+            bool in = fx < 0 || (src ? len_s : len_d) > 0;
+            uint64_t c[LLAMA_MAX_RANK];
+#pragma unroll
+            for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++) {
+                c[d] = 0;
+                if (d < r) {
+                    const int64_t b = o[d] + int64_t(x[d]);
+                    // a Morton run's cube may reach past the box: its records are
+                    // checked one by one
+                    if (X.order != kOrderMorton && (b < 0 || b >= int64_t(h.box[d])))
+                        in = false;
+                    c[d] = uint64_t(int64_t(X.offset[d]) + b);
+                }
+            }
+            if (in)
+                start = box_linear(X, r, c);
+        }
+        (src ? tab_s : tab_d)[k] = start;
+    }
+    __syncthreads();
+
+    // ---- source runs -> LDS, each run by one wave
+    for (uint32_t k = wave; k < Rs; k += nwaves) {
+        const uint64_t start = tab_s[k];
+        const uint32_t w = box_run_len(S, Q, start, len_s);
+        if (w == 0)
+            continue;
+        const uint32_t slot = S.lds_base + k * S.slot;
+        if (S.mode == kFieldMajor) {
+            for (uint32_t f = 0; f < h.num_leaves; f++) {
+                const BoxEntry& en = a.e[f];
+                load_span<false, kCount>(en.src_addr + start * en.size, w * en.size, slot + en.src_off, 0, 1, 0, lane,
+                                         lds_base);
+            }
+        } else if (S.order == kOrderOne) {
+            load_span<false, kCount>(S.blob, uint32_t(S.block), slot, 0, 1, 0, lane, lds_base);
+        } else {
+            const uint64_t b0 = start >> S.log2_lanes, b1 = (start + w - 1) >> S.log2_lanes;
+            load_span<false, kCount>(S.blob + b0 * S.block, uint32_t((b1 - b0 + 1) * S.block), slot, 0, 1, 0, lane,
+                                     lds_base);
+        }
+    }
+    if (kStaged && preserve) { // kept padding: the destination records are loaded first
+        for (uint32_t k = wave; k < Rd; k += nwaves) {
+            const uint64_t start = tab_d[k];
+            const uint32_t w = box_run_len(D, Q, start, len_d);
+            if (w > 0)
+                load_span<false, kCount>(D.blob + start * D.block, uint32_t(w * D.block), D.lds_base + k * D.slot, 0,
+                                         1, 0, lane, lds_base);
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    // ---- destination records, in the destination's order
+    const uint32_t wlog = D.run_log2, wmask = (1u << wlog) - 1u;
+    if constexpr (kStaged) {
+        // AoS destination: whole records into the destination region
+        for (uint32_t j = tid; j < Q; j += nthr) {
+            const uint32_t kd = j >> wlog, ed = j & wmask;
+            const uint64_t sd = tab_d[kd];
+            if (ed >= box_run_len(D, Q, sd, len_d))
+                continue;
+            uint32_t x[LLAMA_MAX_RANK];
+            box_coord(h, D.order, kd, fd >= 0 ? lo_d + ed : ed, x);
+            bool in = true;
+#pragma unroll
+            for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+                if (d < r) {
+                    const int64_t b = o[d] + int64_t(x[d]);
+                    in = in && b >= 0 && b < int64_t(h.box[d]);
+                }
+            const uint32_t K = uint32_t(D.block);
+            const uint32_t dpos = D.lds_base + kd * D.slot + ((uint32_t(D.blob) + uint32_t(sd) * K) & 15u) + ed * K;
+            if (!in) { // a hole of a full copy into a Morton destination
+                if (!preserve)
+                    for (uint32_t b = 0; b < K; b++)
+                        lds[dpos + b] = 0;
+                continue;
+            }
+            uint32_t ks, es;
+            box_run(h, S.order, x, ks, es);
+            if (fs >= 0)
+                es -= lo_s;
+            const uint64_t ss = tab_s[ks];
+            for (uint32_t f = 0; f < h.num_entries; f++) {
+                const BoxEntry& en = a.e[f];
+                if (en.gap) {
+                    if (!preserve)
+                        for (uint32_t b = 0; b < en.size; b++)
+                            lds[dpos + en.dst_off + b] = 0;
+                    continue;
+                }
+                box_move_lds(lds, box_src_pos(S, en, ks, ss, ss + es), dpos + en.dst_off, en.size);
+            }
+        }
+        __syncthreads();
+        for (uint32_t k = wave; k < Rd; k += nwaves) {
+            const uint64_t start = tab_d[k];
+            const uint32_t w = box_run_len(D, Q, start, len_d);
+            if (w > 0)
+                store_span<false, kCount>(D.blob + start * D.block, uint32_t(w * D.block), D.lds_base + k * D.slot,
+                                          lane, 64, 0, lds);
+        }
+    } else {
+        // field-major or AoSoA destination: value by value; the lanes of a
+        // wave hold consecutive records and store the same leaf together
+        const uint64_t lmask = (uint64_t(1) << D.log2_lanes) - 1u;
+        for (uint32_t j = tid; j < Q; j += nthr) {
+            const uint32_t kd = j >> wlog, ed = j & wmask;
+            const uint64_t sd = tab_d[kd];
+            if (ed >= box_run_len(D, Q, sd, len_d))
+                continue;
+            const uint64_t i = sd + ed;
+            const uint64_t gi = D.mode == kFieldMajor ? i : (i >> D.log2_lanes) * D.block;
+            const uint64_t li = D.mode == kFieldMajor ? 0 : (i & lmask);
+            uint32_t x[LLAMA_MAX_RANK];
+            box_coord(h, D.order, kd, fd >= 0 ? lo_d + ed : ed, x);
+            bool in = true;
+#pragma unroll
+            for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+                if (d < r) {
+                    const int64_t b = o[d] + int64_t(x[d]);
+                    in = in && b >= 0 && b < int64_t(h.box[d]);
+                }
+            if (!in) { // a hole or tail lane of a full copy into a Morton destination
+                if (full && !preserve)
+                    for (uint32_t f = 0; f < h.num_entries; f++) {
+                        const BoxEntry& en = a.e[f];
+                        const uint64_t g = en.gap ? D.blob + gi + en.dst_off
+                                                  : en.dst_addr + (D.mode == kFieldMajor ? gi * en.size
+                                                                                         : gi + li * en.size);
+                        box_store_value<kCount>(lds, 0, g, en.size, true);
+                    }
+                continue;
+            }
+            uint32_t ks, es;
+            box_run(h, S.order, x, ks, es);
+            if (fs >= 0)
+                es -= lo_s;
+            const uint64_t ss = tab_s[ks];
+            for (uint32_t f = 0; f < h.num_entries; f++) {
+                const BoxEntry& en = a.e[f];
+                if (en.gap) { // an AoS destination's alignment gap (lanes 1: gi is the record's byte)
+                    if (!preserve)
+                        box_store_value<kCount>(lds, 0, D.blob + gi + en.dst_off, en.size, true);
+                    continue;
+                }
+                const uint64_t g = en.dst_addr + (D.mode == kFieldMajor ? gi * en.size : gi + li * en.size);
+                box_store_value<kCount>(lds, box_src_pos(S, en, ks, ss, ss + es), g, en.size, false);
+            }
+        }
+    }
+}
+
+template <bool kStaged, bool kCount>
+__global__ void __launch_bounds__(1024) box_kernel(const BoxArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    const uint64_t nt = a.h.num_units;
+    uint64_t t = blockIdx.x, stride = gridDim.x;
+    if (!kCount && gridDim.x == nt) { // each XCD one contiguous eighth of the tiles
+        const uint64_t b = blockIdx.x, x = b & 7u, k = b >> 3, q = nt >> 3, rem = nt & 7u;
+        t = x * q + min(x, rem) + k;
+        stride = nt;
+    }
+    for (; t < nt; t += stride) {
+        box_body<kStaged, kCount>(a, t, lds);
+        if (t + stride < nt)
+            __syncthreads();
+    }
+}
+
+// The coordinate of linear index i on side s; false when no coordinate inside
+// the view's extents has that index (a Morton hole, an AoSoA tail lane).
+__device__ __forceinline__ bool box_delinear(const BoxSide& s, uint32_t r, uint64_t i, uint64_t* c)
+{
+    bool in = true;
+    if (s.lin == kLinMorton) {
+#pragma unroll
+        for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+            c[d] = 0;
+        for (uint32_t j = 0; j < s.morton_bits; j++)
+#pragma unroll
+            for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+                if (d < r)
+                    c[d] |= ((i >> (j * r + r - 1 - d)) & 1ull) << j;
+        if (s.morton_bits * r < 64 && (i >> (s.morton_bits * r)) != 0)
+            in = false;
+#pragma unroll
+        for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+            if (d < r && c[d] >= s.extent[d])
+                in = false;
+        return in;
+    }
+    uint64_t rem = i;
+    if (s.lin == kLinCol) {
+#pragma unroll
+        for (int d = 0; d < LLAMA_MAX_RANK; d++) {
+            c[d] = 0;
+            if (d < int(r)) {
+                c[d] = rem % s.extent[d];
+                rem /= s.extent[d];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int d = LLAMA_MAX_RANK - 1; d >= 0; d--) {
+            c[d] = 0;
+            if (d < int(r)) {
+                c[d] = rem % s.extent[d];
+                rem /= s.extent[d];
+            }
+        }
+    }
+    return rem == 0;
+}
+
+// The element-wise baseline of a box copy: one thread per record of the box
+// (row-major), both linear indices from the coordinate, every leaf moved at
+// its own width, aligned-AoS gaps zeroed (kBoxPreserve: kept).  A full copy
+// (kBoxFull) runs one thread per destination index instead, so that the
+// indices no coordinate reaches (Morton holes, AoSoA tail lanes) get zeros.
+template <bool kCount>
+__global__ void __launch_bounds__(1024) box_naive_kernel(const BoxArgs a)
+{
+    const BoxHeader& h = a.h;
+    const uint32_t r = h.rank;
+    const bool full = (h.flags & kBoxFull) != 0, preserve = (h.flags & kBoxPreserve) != 0;
+    uint64_t n = 1;
+    if (full) {
+        n = a.dst.npad;
+    } else {
+        for (uint32_t d = 0; d < r; d++)
+            n *= h.box[d];
+    }
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
+        uint64_t cs[LLAMA_MAX_RANK], cd[LLAMA_MAX_RANK], rem = i;
+        bool in = true;
+        uint64_t id = 0;
+        if (full) {
+            id = i;
+            in = box_delinear(a.dst, r, i, cd);
+#pragma unroll
+            for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+                cs[d] = cd[d];
+        } else {
+#pragma unroll
+            for (int d = LLAMA_MAX_RANK - 1; d >= 0; d--) {
+                cs[d] = cd[d] = 0;
+                if (d < int(r)) {
+                    const uint64_t c = rem % h.box[d];
+                    rem /= h.box[d];
+                    cs[d] = a.src.offset[d] + c;
+                    cd[d] = a.dst.offset[d] + c;
+                }
+            }
+            id = box_linear(a.dst, r, cd);
+        }
+        const uint64_t is = (!in || a.src.order == kOrderOne) ? 0 : box_linear(a.src, r, cs);
+        for (uint32_t f = 0; f < h.num_entries; f++) {
+            const BoxEntry& en = a.e[f];
+            uint64_t gd;
+            if (a.dst.mode == kFieldMajor)
+                gd = en.dst_addr + id * en.size;
+            else if (en.gap)
+                gd = a.dst.blob + id * a.dst.block + en.dst_off;
+            else
+                gd = en.dst_addr + (id >> a.dst.log2_lanes) * a.dst.block +
+                     (id & ((uint64_t(1) << a.dst.log2_lanes) - 1u)) * en.size;
+            if (en.gap || !in) {
+                if (!preserve)
+                    for (uint32_t b = 0; b < en.size; b++)
+                        gput<kCount>(gd + b, uint8_t(0));
+                continue;
+            }
+            uint64_t gs;
+            if (a.src.mode == kFieldMajor)
+                gs = en.src_addr + is * en.size;
+            else
+                gs = a.src.blob + (is >> a.src.log2_lanes) * a.src.block + en.src_off +
+                     (is & ((uint64_t(1) << a.src.log2_lanes) - 1u)) * en.size;
+            const uint32_t al = uint32_t(gs) | uint32_t(gd) | en.size;
+            if ((al & 7u) == 0)
+                for (uint32_t b = 0; b < en.size; b += 8)
+                    gput<kCount>(gd + b, gget<kCount, uint64_t>(gs + b));
+            else if ((al & 3u) == 0)
+                for (uint32_t b = 0; b < en.size; b += 4)
+                    gput<kCount>(gd + b, gget<kCount, uint32_t>(gs + b));
+            else
+                for (uint32_t b = 0; b < en.size; b++)
+                    gput<kCount>(gd + b, gget<kCount, uint8_t>(gs + b));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // NAIVE
 // ---------------------------------------------------------------------------
 
-template <typename T>
+template <typename T, bool kCount>
 __device__ __forceinline__ void naive_move(uint64_t d, uint64_t s, uint32_t size, bool zero)
 {
     for (uint32_t k = 0; k < size; k += sizeof(T))
-        *(GLOBAL T*)(d + k) = zero ? T(0) : *(const GLOBAL T*)(s + k);
+        gput<kCount>(d + k, zero ? T(0) : gget<kCount, T>(s + k));
 }
 
-__global__ void __launch_bounds__(1024) naive_kernel(const NaiveArgs a)
+template <bool kCount>
+__device__ __forceinline__ void naive_body(const NaiveArgs& a)
 {
     const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.npad; i += stride) {
@@ -949,13 +1562,24 @@ __global__ void __launch_bounds__(1024) naive_kernel(const NaiveArgs a)
                 soff = a.src.lanes ? (i / a.src.lanes) * a.src.block + (i % a.src.lanes) * e.size : i * e.size;
             const uint64_t d = e.dst_addr + doff, s = e.src_addr + soff;
             switch (e.width) {
-            case 8: naive_move<uint64_t>(d, s, e.size, zero); break;
-            case 4: naive_move<uint32_t>(d, s, e.size, zero); break;
-            case 2: naive_move<uint16_t>(d, s, e.size, zero); break;
-            default: naive_move<uint8_t>(d, s, e.size, zero); break;
+            case 8: naive_move<uint64_t, kCount>(d, s, e.size, zero); break;
+            case 4: naive_move<uint32_t, kCount>(d, s, e.size, zero); break;
+            case 2: naive_move<uint16_t, kCount>(d, s, e.size, zero); break;
+            default: naive_move<uint8_t, kCount>(d, s, e.size, zero); break;
             }
         }
     }
+}
+
+__global__ void __launch_bounds__(1024) naive_kernel(const NaiveArgs a)
+{
+    naive_body<false>(a);
+}
+
+// The counted variant of naive_kernel, for the Heatmap.
+__global__ void __launch_bounds__(1024) naive_count_kernel(const NaiveArgs a)
+{
+    naive_body<true>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -998,6 +1622,52 @@ __global__ void __launch_bounds__(256) hash_kernel(const uint8_t* p, uint64_t le
         atomicAdd(acc, (unsigned long long)h);
 }
 
+// ---------------------------------------------------------------------------
+// TRACE: per-leaf sums of a view's per-byte Heatmap counters, through the
+// mapping's affine form (sec. 3.7 Trace counts accesses per field)
+// ---------------------------------------------------------------------------
+
+struct TraceLeaf {
+    uint64_t counters; // device address of the counters of the leaf's blob
+    uint64_t base;     // byte offset of the leaf's record 0 in that blob
+    uint64_t lanes;    // L (0: unblocked)
+    uint64_t block;    // K
+    uint32_t size;
+    uint32_t pad;
+};
+
+__global__ void __launch_bounds__(256) trace_kernel(const TraceLeaf* leaves, uint32_t nleaves, uint64_t n,
+                                                    unsigned long long* out)
+{
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint32_t f = 0; f < nleaves; f++) {
+        const TraceLeaf e = leaves[f];
+        const GLOBAL uint32_t* c = (const GLOBAL uint32_t*)e.counters;
+        uint64_t sum = 0;
+        for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+            const uint64_t off = e.lanes ? e.base + (i / e.lanes) * e.block + (i % e.lanes) * e.size
+                                         : e.base + i * e.size;
+            for (uint32_t b = 0; b < e.size; b++)
+                sum += c[off + b];
+        }
+        for (int o = 32; o > 0; o >>= 1)
+            sum += __shfl_xor(sum, o);
+        if ((threadIdx.x & 63) == 0 && sum)
+            atomicAdd(out + f, (unsigned long long)sum);
+    }
+}
+
+__global__ void __launch_bounds__(256) counter_sum_kernel(const uint32_t* c, uint64_t len, unsigned long long* out)
+{
+    uint64_t sum = 0;
+    for (uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < len; k += uint64_t(gridDim.x) * blockDim.x)
+        sum += ((const GLOBAL uint32_t*)c)[k];
+    for (int o = 32; o > 0; o >>= 1)
+        sum += __shfl_xor(sum, o);
+    if ((threadIdx.x & 63) == 0 && sum)
+        atomicAdd(out, (unsigned long long)sum);
+}
+
 void check_hip(hipError_t e, const char* what)
 {
     if (e != hipSuccess)
@@ -1019,6 +1689,11 @@ const void* const kTileKernels[3 * kTileModes] = {
     (const void*)tile_kernel<kModeDirectLoad | kLdSt>, (const void*)tile_kernel<kModeGatherStore | kLdSt>,
     (const void*)tile_kernel<kModeGatherOdd | kLdSt>};
 
+const void* const kTileCountKernels[kTileModes] = {
+    (const void*)tile_count_kernel<kModeStaged>, (const void*)tile_count_kernel<kModeDirectStore>,
+    (const void*)tile_count_kernel<kModeDirectLoad>, (const void*)tile_count_kernel<kModeGatherStore>,
+    (const void*)tile_count_kernel<kModeGatherOdd>};
+
 bool g_attr_set = false;
 
 void set_attributes()
@@ -1028,6 +1703,13 @@ void set_attributes()
     for (const void* k : kTileKernels)
         check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes)),
                   "hipFuncSetAttribute(tile_kernel)");
+    for (const void* k : kTileCountKernels)
+        check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes)),
+                  "hipFuncSetAttribute(tile_count_kernel)");
+    for (const void* k : {(const void*)box_kernel<false, false>, (const void*)box_kernel<true, false>,
+                          (const void*)box_kernel<false, true>, (const void*)box_kernel<true, true>})
+        check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes)),
+                  "hipFuncSetAttribute(box_kernel)");
     for (const void* k : {(const void*)batch_kernel<false>, (const void*)batch_kernel<true>,
                           (const void*)batch_unit_kernel<false>, (const void*)batch_unit_kernel<true>})
         check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes - 64)),
@@ -1060,12 +1742,64 @@ uint32_t device_cu_count()
     return cached;
 }
 
+namespace {
+thread_local bool t_counting = false; // launches on this thread take the counted variants
+}
+
+void set_counting(const CountTable* table, void* stream)
+{
+    if (!table) {
+        t_counting = false;
+        return;
+    }
+    void* sym = nullptr;
+    check_hip(hipGetSymbolAddress(&sym, HIP_SYMBOL(g_count_table)), "hipGetSymbolAddress(g_count_table)");
+    check_hip(hipMemcpyAsync(sym, table, sizeof(CountTable), hipMemcpyHostToDevice, (hipStream_t)stream),
+              "hipMemcpyAsync(count table)");
+    t_counting = true;
+}
+
 void launch(const Plan& p, void* stream_ptr)
 {
     hipStream_t stream = (hipStream_t)stream_ptr;
     if (p.path == LLAMA_PATH_EMPTY || p.workgroups == 0)
         return;
     const uint32_t grid = uint32_t(std::min<uint64_t>(p.workgroups, kMaxGrid));
+    if (trace_enabled())
+        trace_plan(p);
+    if (t_counting) {
+        void* args[] = {p.path == LLAMA_PATH_TILE     ? (void*)&p.tile
+                        : p.path == LLAMA_PATH_STREAM ? (void*)&p.stream
+                                                      : (void*)&p.naive};
+        const void* k = nullptr;
+        uint32_t lds = 0;
+        if (p.path == LLAMA_PATH_TILE) {
+            set_attributes();
+            const uint32_t f = p.tile.h.flags;
+            const uint32_t mode = (f & kTileDirectLoad)    ? kModeDirectLoad
+                                  : (f & kTileDirectStore) ? kModeDirectStore
+                                  : (f & kTileGatherStore) ? ((f & kTileGatherOdd) ? kModeGatherOdd : kModeGatherStore)
+                                                           : kModeStaged;
+            k = kTileCountKernels[mode - 1];
+            lds = p.tile.h.lds_bytes;
+        } else if (p.path == LLAMA_PATH_STREAM) {
+            k = (const void*)stream_count_kernel;
+        } else if (p.path == LLAMA_PATH_NAIVE) {
+            k = (const void*)naive_count_kernel;
+        } else if (p.path == LLAMA_PATH_BOX) {
+            set_attributes();
+            args[0] = (void*)&p.box;
+            k = p.box_naive ? (const void*)box_naive_kernel<true>
+                : (p.box.h.flags & kBoxStaged) ? (const void*)box_kernel<true, true>
+                                               : (const void*)box_kernel<false, true>;
+            lds = p.box_naive ? 0 : p.box.h.lds_bytes;
+        } else {
+            fail(LLAMA_E_INVALID_ARG, "unknown path");
+        }
+        check_hip(hipLaunchKernel(k, dim3(grid), dim3(p.threads), args, lds, stream), "hipLaunchKernel(counted)");
+        check_hip(hipGetLastError(), "kernel launch");
+        return;
+    }
     switch (p.path) {
     case LLAMA_PATH_TILE: {
         set_attributes();
@@ -1092,10 +1826,79 @@ void launch(const Plan& p, void* stream_ptr)
     case LLAMA_PATH_NAIVE:
         hipLaunchKernelGGL(naive_kernel, dim3(grid), dim3(p.threads), 0, stream, p.naive);
         break;
+    case LLAMA_PATH_BOX: {
+        if (p.box_naive) {
+            hipLaunchKernelGGL(box_naive_kernel<false>, dim3(grid), dim3(p.threads), 0, stream, p.box);
+            break;
+        }
+        set_attributes();
+        const void* k = (p.box.h.flags & kBoxStaged) ? (const void*)box_kernel<true, false>
+                                                     : (const void*)box_kernel<false, false>;
+        void* args[] = {(void*)&p.box};
+        check_hip(hipLaunchKernel(k, dim3(grid), dim3(p.threads), args, p.box.h.lds_bytes, stream),
+                  "hipLaunchKernel(box_kernel)");
+        break;
+    }
     default:
         fail(LLAMA_E_INVALID_ARG, "unknown path");
     }
     check_hip(hipGetLastError(), "kernel launch");
+}
+
+void trace_leaves(const llama_mapping_desc* m, uint32_t* const* counters, uint64_t* sums, void* stream_ptr)
+{
+    hipStream_t stream = (hipStream_t)stream_ptr;
+    const Record r = flatten(m->record);
+    const Side s = make_side(m, r);
+    if (s.kind == LLAMA_ONE)
+        fail(LLAMA_E_UNSUPPORTED, "a One mapping puts every record at the same bytes; trace its single record");
+    const uint32_t F = uint32_t(r.leaves.size());
+    for (size_t b = 0; b < s.blob_size.size(); b++)
+        if (!counters[b] && s.blob_size[b])
+            fail(LLAMA_E_INVALID_ARG, "counters of blob " + std::to_string(b) + " are NULL");
+    std::vector<TraceLeaf> leaves(F);
+    for (uint32_t f = 0; f < F; f++) {
+        leaves[f].counters = uint64_t(uintptr_t(counters[s.blob[f]]));
+        leaves[f].base = s.base[f];
+        leaves[f].lanes = s.leaf_lanes.empty() ? s.lanes : s.leaf_lanes[f];
+        leaves[f].block = s.leaf_block.empty() ? s.block : s.leaf_block[f];
+        leaves[f].size = r.leaves[f].size;
+    }
+    const size_t tbytes = F * sizeof(TraceLeaf), obytes = (F + 1) * sizeof(unsigned long long);
+    void* tmp = nullptr;
+    check_hip(hipMalloc(&tmp, tbytes + obytes), "hipMalloc(trace)");
+    std::vector<unsigned long long> out(F + 1, 0);
+    hipError_t e = hipSuccess;
+    unsigned long long* dout = (unsigned long long*)((uint8_t*)tmp + tbytes);
+    auto step = [&](hipError_t x) {
+        if (e == hipSuccess)
+            e = x;
+    };
+    step(hipMemcpyAsync(tmp, leaves.data(), tbytes, hipMemcpyHostToDevice, stream));
+    step(hipMemcpyAsync(dout, out.data(), obytes, hipMemcpyHostToDevice, stream));
+    if (e == hipSuccess && s.n > 0) {
+        const uint32_t grid = uint32_t(std::min<uint64_t>((s.n + 255) / 256, 4096));
+        hipLaunchKernelGGL(trace_kernel, dim3(grid), dim3(256), 0, stream, (const TraceLeaf*)tmp, F, s.n, dout);
+        step(hipGetLastError());
+    }
+    for (size_t b = 0; b < s.blob_size.size() && e == hipSuccess; b++) {
+        if (!s.blob_size[b])
+            continue;
+        const uint32_t grid = uint32_t(std::min<uint64_t>((s.blob_size[b] + 255) / 256, 4096));
+        hipLaunchKernelGGL(counter_sum_kernel, dim3(grid), dim3(256), 0, stream, (const uint32_t*)counters[b],
+                           s.blob_size[b], dout + F);
+        step(hipGetLastError());
+    }
+    step(hipMemcpyAsync(out.data(), dout, obytes, hipMemcpyDeviceToHost, stream));
+    step(hipStreamSynchronize(stream));
+    (void)hipFree(tmp);
+    check_hip(e, "trace");
+    uint64_t leaves_total = 0;
+    for (uint32_t f = 0; f < F; f++) {
+        sums[f] = out[f];
+        leaves_total += out[f];
+    }
+    sums[F] = out[F] - leaves_total; // the bytes no leaf owns
 }
 
 void launch_hash(const void* p, uint64_t len, unsigned long long* acc, void* stream)

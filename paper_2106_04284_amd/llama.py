@@ -23,8 +23,8 @@ AOS_PACKED, AOS_ALIGNED, SOA_SINGLE, SOA_MULTI, AOSOA, SPLIT, ONE = 0, 1, 2, 3, 
 KINDS = {"aos_packed": AOS_PACKED, "aos_aligned": AOS_ALIGNED, "soa_single": SOA_SINGLE,
          "soa_multi": SOA_MULTI, "aosoa": AOSOA, "split": SPLIT, "one": ONE}
 
-PATH_AUTO, PATH_STREAM, PATH_TILE, PATH_NAIVE, PATH_EMPTY = 0, 1, 2, 3, 4
-PATH_NAMES = {PATH_STREAM: "stream", PATH_TILE: "tile", PATH_NAIVE: "naive", PATH_EMPTY: "empty"}
+PATH_AUTO, PATH_STREAM, PATH_TILE, PATH_NAIVE, PATH_EMPTY, PATH_BOX = 0, 1, 2, 3, 4, 5
+PATH_NAMES = {PATH_STREAM: "stream", PATH_TILE: "tile", PATH_NAIVE: "naive", PATH_EMPTY: "empty", PATH_BOX: "box"}
 TILE_MODE_NAMES = {1: "staged", 2: "direct_store", 3: "direct_load", 4: "gather_store"}
 
 OK = 0
@@ -77,10 +77,13 @@ def _split_desc(spec, keep):
     return sd
 
 
+LINEARIZERS = {"row": 0, "col": 1, "morton": 2}
+
+
 class MappingDesc(ctypes.Structure):
     _fields_ = [("record", ctypes.POINTER(RecordDesc)), ("kind", ctypes.c_uint32), ("rank", ctypes.c_uint32),
                 ("extents", ctypes.c_uint64 * MAX_RANK), ("lanes", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("split", ctypes.POINTER(SplitDesc))]
+                ("linearizer", ctypes.c_uint32), ("split", ctypes.POINTER(SplitDesc))]
 
 
 class Blob(ctypes.Structure):
@@ -109,6 +112,11 @@ class BatchInfo(ctypes.Structure):
                 ("work_units", ctypes.c_uint64), ("read_bytes", ctypes.c_uint64), ("write_bytes", ctypes.c_uint64),
                 ("threads", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32), ("workgroups", ctypes.c_uint32),
                 ("lds_bytes", ctypes.c_uint32)]
+
+
+class HeatmapDesc(ctypes.Structure):
+    _fields_ = [("src_reads", ctypes.POINTER(ctypes.c_void_p)), ("dst_writes", ctypes.POINTER(ctypes.c_void_p)),
+                ("dst_reads", ctypes.POINTER(ctypes.c_void_p))]
 
 
 _lib = None
@@ -160,10 +168,27 @@ _SIGNATURES = {
     "llama_batch_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.POINTER(CopyItem), ctypes.POINTER(CopyOptions),
                                           ctypes.POINTER(ctypes.c_void_p)]),
     "llama_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "llama_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                            ctypes.POINTER(ctypes.c_double)]),
     "llama_batch_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BatchInfo)]),
     "llama_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "llama_copy_batch": (ctypes.c_int, [ctypes.c_size_t, ctypes.POINTER(CopyItem), ctypes.c_void_p]),
     "llama_copy_batch_noalloc": (ctypes.c_int, [ctypes.c_size_t, ctypes.POINTER(CopyItem), ctypes.c_void_p]),
+    "llama_copy_transfer": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob), ctypes.c_uint32,
+                                           ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob), ctypes.c_uint32,
+                                           ctypes.c_uint64, ctypes.c_void_p]),
+    "llama_copy_box": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob), ctypes.POINTER(ctypes.c_uint64),
+                                      ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob), ctypes.POINTER(ctypes.c_uint64),
+                                      ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(CopyOptions), ctypes.c_void_p]),
+    "llama_copy_heatmap": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob),
+                                          ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob),
+                                          ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(CopyOptions),
+                                          ctypes.POINTER(HeatmapDesc), ctypes.c_void_p]),
+    "llama_heatmap_begin": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
+    "llama_heatmap_end": (ctypes.c_int, []),
+    "llama_trace_leaves": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(ctypes.c_void_p),
+                                          ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p]),
 }
 
 
@@ -254,13 +279,14 @@ class Mapping:
     Split); a part is (kind, lanes), or ("split", (first, count, part, part))
     to split that part's leaves again."""
 
-    def __init__(self, record: Record, kind: str, extents, lanes: int = 0, split=None):
+    def __init__(self, record: Record, kind: str, extents, lanes: int = 0, split=None, linearizer="row"):
         ext = [int(e) for e in (extents if isinstance(extents, (list, tuple)) else [extents])]
         self.record = record
         self.kind = kind
         self.extents = ext
         self.lanes = int(lanes)
         self.split = split
+        self.linearizer = linearizer
         self._split = None
         self.desc = MappingDesc()
         self.desc.record = ctypes.pointer(record.desc)
@@ -269,7 +295,7 @@ class Mapping:
         for d, e in enumerate(ext[:MAX_RANK]):
             self.desc.extents[d] = e
         self.desc.lanes = self.lanes
-        self.desc.reserved = 0
+        self.desc.linearizer = LINEARIZERS[linearizer] if isinstance(linearizer, str) else int(linearizer)
         if split is not None:
             self._split = []  # the descriptors, kept alive with the one that points at them
             self.desc.split = ctypes.pointer(_split_desc(split, self._split))
@@ -336,7 +362,7 @@ COPY_PRESERVE_PADDING = 4
 
 def _options(path=PATH_AUTO, tile_records=0, threads=0, wg_per_cu=0, flags=0):
     if isinstance(path, str):
-        path = {"auto": PATH_AUTO, "stream": PATH_STREAM, "tile": PATH_TILE, "naive": PATH_NAIVE}[path]
+        path = {"auto": PATH_AUTO, "stream": PATH_STREAM, "tile": PATH_TILE, "naive": PATH_NAIVE, "box": PATH_BOX}[path]
     return CopyOptions(path, tile_records, threads, wg_per_cu, flags)
 
 
@@ -355,6 +381,34 @@ def copy(src: Mapping, src_blobs, dst: Mapping, dst_blobs, stream=None, path=PAT
 NO_LEAF = 0xFFFFFFFF
 
 
+MEMORY_DEVICE, MEMORY_HOST = 0, 1
+
+
+def copy_transfer(src: Mapping, src_blobs, dst: Mapping, dst_blobs, src_on_host: bool, chunk_bytes=0, stream=None):
+    """llama_copy_transfer: a copy between host and device memory that
+    changes the layout on the way, chunk by chunk.  src_on_host: the source
+    blobs are host tensors (the destination's on the device), else the
+    reverse."""
+    sm, dm = (MEMORY_HOST, MEMORY_DEVICE) if src_on_host else (MEMORY_DEVICE, MEMORY_HOST)
+    check(lib().llama_copy_transfer(ctypes.byref(src.desc), _blobs(src_blobs), sm, ctypes.byref(dst.desc),
+                                    _blobs(dst_blobs), dm, int(chunk_bytes), _stream(stream)))
+
+
+def copy_box(src: Mapping, src_blobs, src_offset, dst: Mapping, dst_blobs, dst_offset, box, stream=None,
+             path=PATH_AUTO, tile_records=0, threads=0, flags=0):
+    """llama_copy_box: the records of a box of the array dimensions, from
+    src_offset + c in the source to dst_offset + c in the destination."""
+    r = len(box)
+    so = (ctypes.c_uint64 * MAX_RANK)(*[int(x) for x in src_offset])
+    do = (ctypes.c_uint64 * MAX_RANK)(*[int(x) for x in dst_offset])
+    bx = (ctypes.c_uint64 * MAX_RANK)(*[int(x) for x in box])
+    if len(src_offset) != r or len(dst_offset) != r:
+        raise ValueError("offsets and box need one entry per dimension")
+    o = _options(path, tile_records, threads, 0, flags)
+    check(lib().llama_copy_box(ctypes.byref(src.desc), _blobs(src_blobs), so, ctypes.byref(dst.desc),
+                               _blobs(dst_blobs), do, bx, ctypes.byref(o), _stream(stream)))
+
+
 def copy_leaves(src: Mapping, src_blobs, dst: Mapping, dst_blobs, source_leaf, stream=None, path=PATH_AUTO,
                 tile_records=0, threads=0, wg_per_cu=0, flags=0):
     """llama_copy_leaves: destination leaf k takes source leaf source_leaf[k]
@@ -363,6 +417,71 @@ def copy_leaves(src: Mapping, src_blobs, dst: Mapping, dst_blobs, source_leaf, s
     o = _options(path, tile_records, threads, wg_per_cu, flags)
     check(lib().llama_copy_leaves(ctypes.byref(src.desc), _blobs(src_blobs), ctypes.byref(dst.desc),
                                   _blobs(dst_blobs), arr, ctypes.byref(o), _stream(stream)))
+
+
+def _counter_array(tensors):
+    if tensors is None:
+        return None
+    arr = (ctypes.c_void_p * max(len(tensors), 1))()
+    for k, t in enumerate(tensors):
+        arr[k] = None if t is None else t.data_ptr()
+    return arr
+
+
+def copy_heatmap(src: Mapping, src_blobs, dst: Mapping, dst_blobs, source_leaf=None, stream=None,
+                 src_reads=None, dst_writes=None, dst_reads=None, path=PATH_AUTO, tile_records=0, threads=0,
+                 wg_per_cu=0, flags=0):
+    """llama_copy_heatmap: the copy (llama_copy_ex, or llama_copy_leaves with
+    source_leaf) in its counted kernel variants.  src_reads / dst_writes /
+    dst_reads are lists of int32 device tensors, one per blob (blob size
+    elements each), that the copy adds its per-byte access counts to."""
+    arr = None
+    if source_leaf is not None:
+        arr = (ctypes.c_uint32 * max(len(source_leaf), 1))(*[NO_LEAF if x is None else int(x) for x in source_leaf])
+    o = _options(path, tile_records, threads, wg_per_cu, flags)
+    keep = [_counter_array(x) for x in (src_reads, dst_writes, dst_reads)]
+    h = HeatmapDesc(*[ctypes.cast(a, ctypes.POINTER(ctypes.c_void_p)) if a is not None else None for a in keep])
+    check(lib().llama_copy_heatmap(ctypes.byref(src.desc), _blobs(src_blobs), ctypes.byref(dst.desc),
+                                   _blobs(dst_blobs), arr, ctypes.byref(o), ctypes.byref(h), _stream(stream)))
+
+
+class CountRange(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("size", ctypes.c_uint64), ("counters", ctypes.c_void_p)]
+
+
+class heatmap:
+    """Context manager around llama_heatmap_begin / llama_heatmap_end: the
+    copies made inside it on this thread run in their counted variants.
+    reads / writes: lists of (blob tensor, int32 counter tensor) pairs."""
+
+    def __init__(self, reads=(), writes=(), stream=None):
+        def arr(pairs):
+            a = (CountRange * max(len(pairs), 1))()
+            for k, (blob, cnt) in enumerate(pairs):
+                a[k] = CountRange(blob.data_ptr(), blob.numel() * blob.element_size(), cnt.data_ptr())
+            return a
+        self._r, self._w = arr(list(reads)), arr(list(writes))
+        self._nr, self._nw = len(reads), len(writes)
+        self._stream = stream
+
+    def __enter__(self):
+        check(lib().llama_heatmap_begin(self._nr, self._r, self._nw, self._w, _stream(self._stream)))
+        return self
+
+    def __exit__(self, *exc):
+        check(lib().llama_heatmap_end())
+        return False
+
+
+def trace_leaves(m: Mapping, counters, stream=None):
+    """llama_trace_leaves: per-leaf sums of a view's per-byte counters, then
+    the sum over the bytes no leaf owns (a list of F + 1 integers)."""
+    f = m.record.leaf_count
+    out = (ctypes.c_uint64 * (f + 1))()
+    arr = _counter_array(counters)
+    check(lib().llama_trace_leaves(ctypes.byref(m.desc), ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), out,
+                                   _stream(stream)))
+    return [int(x) for x in out]
 
 
 def copy_naive(src: Mapping, src_blobs, dst: Mapping, dst_blobs, stream=None):
@@ -452,6 +571,13 @@ class Batch:
 
     def launch(self, stream=None):
         check(lib().llama_batch_launch(self._h, _stream(stream)))
+
+    def autotune(self, stream=None, reps=3) -> float:
+        """llama_batch_autotune: re-plans the batch with the fastest measured
+        LDS budget, threads and grid; returns its GB/s."""
+        g = ctypes.c_double()
+        check(lib().llama_batch_autotune(self._h, _stream(stream), int(reps), ctypes.byref(g)))
+        return g.value
 
     def info(self) -> dict:
         i = BatchInfo()

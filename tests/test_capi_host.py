@@ -80,6 +80,46 @@ def test_mapping_arithmetic_matches_oracle(orc, seed):
             assert m.offset(c, f) == mo.blob_nr_and_offset(c, f), (kind, lanes, c, f)
 
 
+@pytest.mark.parametrize("lin", ["col", "morton"])
+@pytest.mark.parametrize("seed", range(4))
+def test_linearizer_offsets_match_oracle(orc, lin, seed):
+    """Blob sizes and every offset of column-major and Morton mappings equal
+    the oracle's (Morton extents of any size: the holes in its indices are
+    padding, so blob sizes follow the last coordinate's index)."""
+    g = random.Random(seed)
+    name = ["particle", "lbm", "mixed", "listing1"][seed]
+    r, o = L.Record(W.RECORDS[name]), orc.Record(W.RECORDS[name])
+    ext = [g.randint(1, 9) for _ in range(g.randint(2, 4))]
+    for kind, lanes in LAYOUTS:
+        m = L.Mapping(r, kind, ext, lanes, linearizer=lin)
+        mo = orc.Mapping(o, kind, ext, lanes, linearizer=lin)
+        assert m.blob_sizes() == mo.blob_sizes(), (kind, lanes, ext)
+        for _ in range(40):
+            c = [g.randrange(e) for e in ext]
+            f = g.randrange(o.nleaves)
+            assert m.offset(c, f) == mo.blob_nr_and_offset(c, f), (kind, lanes, c, f)
+
+
+def test_box_plans_host():
+    """Copies between linearizers plan the box kernel: tiles within the LDS
+    budget, a bad linearizer and Split with a linearizer refused."""
+    r = L.Record(W.RECORDS["lbm"])
+    for a, b in [("row", "col"), ("col", "morton"), ("morton", "row"), ("morton", "morton")]:
+        for kind, lanes in LAYOUTS:
+            ext = [100, 60, 7] if b != "morton" or a != "morton" else [100, 60, 7]
+            p = L.plan(L.Mapping(r, "aos_aligned", ext, linearizer=a), L.Mapping(r, kind, ext, lanes, linearizer=b))
+            assert p["path"] == "box", (a, b, kind)
+            assert 0 < p["lds_bytes"] <= 64 * 1024 and p["tile_records"] >= 16
+    m = L.Mapping(r, "aos_packed", [4, 4])
+    m.desc.linearizer = 3
+    with pytest.raises(L.LlamaError) as e:
+        m.blob_sizes()
+    assert e.value.status == L.E_INVALID_ARG
+    with pytest.raises(L.LlamaError) as e:
+        L.Mapping(r, "split", [4, 4], split=(0, 3, ("soa_multi", 0), ("aos_packed", 0)), linearizer="col").blob_sizes()
+    assert e.value.status == L.E_UNSUPPORTED
+
+
 def test_planner_paths_for_particle_pairs():
     r = L.Record(W.PARTICLE)
     n = 1 << 26
@@ -403,15 +443,23 @@ def test_tuning_cache_file_round_trip(tmp_path):
 
 def test_build_refuses_kernels_with_scratch():
     """A kernel that spills to scratch memory runs many times slower: the
-    build parses hipcc's resource remarks and refuses it."""
+    build parses hipcc's resource remarks and the device assembly, and
+    refuses a kernel with a private segment that its code loads or stores; a
+    reserved slot that no instruction touches is accepted."""
     from paper_2106_04284_amd import build as B
-    ok = ("k.hip:1:1: remark: Function Name: good [-Rpass-analysis=kernel-resource-usage]\n"
+    ok = ("k.hip:1:1: remark: Function Name: _Zgood [-Rpass-analysis=kernel-resource-usage]\n"
           "k.hip:1:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis=kernel-resource-usage]\n")
-    B._check_no_scratch(ok)
-    bad = ok + ("k.hip:2:1: remark: Function Name: spills [-Rpass-analysis=kernel-resource-usage]\n"
+    asm = "_Zgood:\n\tglobal_load_dword v0, v[0:1], off\n\ts_endpgm\n"
+    B._check_no_scratch(ok, asm)
+    slot = ok + ("k.hip:3:1: remark: Function Name: _Zslot [-Rpass-analysis=kernel-resource-usage]\n"
+                 "k.hip:3:1: remark:     ScratchSize [bytes/lane]: 36 [-Rpass-analysis=kernel-resource-usage]\n")
+    B._check_no_scratch(slot, asm + "_Zslot:\n\tv_writelane_b32 v1, s4, 0\n\ts_endpgm\n")
+    bad = ok + ("k.hip:2:1: remark: Function Name: _Zspills [-Rpass-analysis=kernel-resource-usage]\n"
                 "k.hip:2:1: remark:     ScratchSize [bytes/lane]: 3960 [-Rpass-analysis=kernel-resource-usage]\n")
-    with pytest.raises(RuntimeError, match="spills: 3960"):
-        B._check_no_scratch(bad)
+    with pytest.raises(RuntimeError, match="_Zspills: 3960"):
+        B._check_no_scratch(bad, asm + "_Zspills:\n\tscratch_store_dword off, v3, s0 offset:16\n\ts_endpgm\n")
+    with pytest.raises(RuntimeError, match="_Zspills: 3960"):  # no assembly for it: refused
+        B._check_no_scratch(bad, asm)
 
 
 def test_split_mapping_host(orc):

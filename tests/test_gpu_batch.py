@@ -285,3 +285,26 @@ def test_batch_with_split_items(L, orc):
     with pytest.raises(L.LlamaError) as e:
         L.Batch(bad)
     assert e.value.status == L.E_UNSUPPORTED
+
+
+def test_batch_autotune_keeps_result(L, orc):
+    """llama_batch_autotune re-plans the batch (LDS budget, threads, grid);
+    every candidate must write the same bytes, and the tuned batch, replayed
+    from its graph, still equals the oracle."""
+    items, want = make_items(L, orc, 41, count=25, nmax=30000)
+    b = L.Batch(items)
+    gbs = b.autotune(reps=1)
+    assert gbs > 0
+    info = b.info()
+    assert info["threads"] in (128, 256, 512)
+    check(items, want)
+    stream = torch.cuda.Stream()
+    for rep in range(2):
+        refill(items, 0x33 + rep)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            b.launch()
+        stream.synchronize()
+        check(items, want)
+    b.close()
+

@@ -1,0 +1,193 @@
+"""Heatmap and Trace (sec. 3.7) on the GPU: the library's copies run in
+counted kernel variants that count every byte each global load reads and each
+global store writes.
+
+The destination write counts must equal, byte for byte, the writes of the
+copy's definition that the oracle counts (one per value byte, one per byte of
+the zero fill, none on kept padding or on leaves without a source): that is
+the every-byte-exactly-once invariant, checked on the real plans, paths and
+tile modes.  Every source value byte must be read.  The Trace sums the counts
+per leaf through the mapping."""
+import os
+import random
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2106_04284_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_04284_amd import llama
+    llama.lib()
+    return llama
+
+
+LAYOUTS = W.LAYOUTS  # packed/aligned AoS, SoA single/multi, AoSoA 8/32/64
+
+
+def _counters(m):
+    return [torch.zeros(s, dtype=torch.int32, device="cuda") for s in m.blob_sizes()]
+
+
+def _np(ts):
+    return [t.cpu().numpy().view(np.uint32) for t in ts]
+
+
+def _check_writes(expect, writes, dreads, what):
+    """Every byte the definition writes is written exactly once.  A byte it
+    leaves alone (kept padding, a leaf without a source) is either untouched
+    or, where a tile loads a destination region and stores it back whole,
+    read and then written back once with what it held."""
+    for j, (w, got, rd) in enumerate(zip(expect, writes, dreads)):
+        bad = np.flatnonzero((w == 1) & (got != 1))
+        if bad.size:
+            raise AssertionError(f"{what}: blob {j}: {bad.size} value or zero-fill bytes written "
+                                 f"{got[bad[0]]} times, first at {bad[0]}")
+        kept = w == 0
+        bad = np.flatnonzero(kept & ((got > 1) | (got > rd)))
+        if bad.size:
+            raise AssertionError(f"{what}: blob {j}: {bad.size} kept bytes written {got[bad[0]]} times after "
+                                 f"{rd[bad[0]]} reads, first at {bad[0]}")
+
+
+def _run(L, orc, name, a, b, n, seed, opts, source_leaf=None):
+    rec = W.RECORDS[name]
+    ro, rg = orc.Record(rec), L.Record(rec)
+    ms_o, md_o = orc.Mapping(ro, a[0], [n], a[1]), orc.Mapping(ro, b[0], [n], b[1])
+    ms, md = L.Mapping(rg, a[0], [n], a[1]), L.Mapping(rg, b[0], [n], b[1])
+    src = [W.random_bytes(s, seed + j) for j, s in enumerate(ms_o.blob_sizes())]
+    keep = bool(opts.get("flags", 0) & L.COPY_PRESERVE_PADDING)
+    canary = [np.full(s, 0xCD, np.uint8) for s in md_o.blob_sizes()]
+    if source_leaf is None:
+        want = orc.copy(ms_o, src, md_o, [c.copy() for c in canary], keep_padding=keep)
+    else:
+        want = orc.copy_leaves(ms_o, src, md_o, [c.copy() for c in canary], source_leaf, keep_padding=keep)
+    sd = [torch.from_numpy(x).cuda() for x in src]
+    dd = [torch.from_numpy(c.copy()).cuda() for c in canary]
+    reads, writes, dreads = _counters(ms), _counters(md), _counters(md)
+    L.copy_heatmap(ms, sd, md, dd, source_leaf=source_leaf, src_reads=reads, dst_writes=writes, dst_reads=dreads,
+                   **opts)
+    torch.cuda.synchronize()
+    for j, (got, w) in enumerate(zip(dd, want)):
+        assert np.array_equal(got.cpu().numpy(), w), f"{name} {a}->{b} n={n} {opts}: blob {j} differs"
+    _check_writes(orc.copy_writes(md_o, source_leaf=source_leaf, keep_padding=keep), _np(writes), _np(dreads),
+                  f"{name} {a}->{b} n={n} {opts}")
+    cover = orc.write_counts(ms_o)  # the source bytes that hold values
+    used = set(range(ro.nleaves)) if source_leaf is None else {x for x in source_leaf if x is not None}
+    total_src = sum(ms_o.blob_sizes())
+    r = _np(reads)
+    if used == set(range(ro.nleaves)):
+        for j, (got, c) in enumerate(zip(r, cover)):
+            assert bool((got[c > 0] >= 1).all()), f"{name} {a}->{b}: a source value byte of blob {j} was not read"
+    assert sum(int(x.sum()) for x in r) <= 2 * total_src + 4096
+    return ms, md, reads, writes, dreads, keep
+
+
+@pytest.mark.parametrize("name", ["particle", "mixed"])
+@pytest.mark.parametrize("a", LAYOUTS, ids=lambda x: f"{x[0]}{x[1] or ''}")
+def test_every_destination_byte_written_as_defined(L, orc, name, a):
+    """All 49 ordered pairs (identity included) of two records, at a ragged
+    record count, with the default plan and three option sets."""
+    for b in LAYOUTS:
+        for opts in ({}, {"flags": L.COPY_NO_DIRECT}, {"tile_records": 16, "threads": 64},
+                     {"flags": L.COPY_PRESERVE_PADDING}):
+            _run(L, orc, name, a, b, 3001, 17, opts)
+
+
+@pytest.mark.parametrize("name", ["lbm", "listing1"])
+def test_heatmap_other_records(L, orc, name):
+    g = random.Random(3)
+    for _ in range(12):
+        a, b = g.choice(LAYOUTS), g.choice(LAYOUTS)
+        for opts in ({}, {"flags": L.COPY_PRESERVE_PADDING}, {"path": "naive"}):
+            _run(L, orc, name, a, b, g.choice([1, 63, 700]), 5, opts)
+
+
+def test_heatmap_copy_leaves(L, orc):
+    """Leaves without a source are never written; padding as defined."""
+    g = random.Random(11)
+    for k in range(24):
+        name = g.choice(["particle", "mixed", "listing1"])
+        r = orc.Record(W.RECORDS[name])
+        frm = [None if g.random() < 0.35 else f for f in range(r.nleaves)]
+        if all(x is None for x in frm):
+            frm[-1] = r.nleaves - 1
+        a, b = g.choice(LAYOUTS), g.choice(LAYOUTS)
+        opts = {"flags": L.COPY_PRESERVE_PADDING} if k % 3 == 0 else {}
+        _run(L, orc, name, a, b, g.choice([50, 1000, 2049]), 100 + k, opts, source_leaf=frm)
+
+
+def test_trace_sums_per_leaf(L, orc):
+    """The Trace of a copy's destination writes: every leaf written once per
+    record (size bytes each), padding once per padding byte (zero with kept
+    padding); the source Trace reads every leaf at least once per record."""
+    rec = W.RECORDS["mixed"]
+    ro = orc.Record(rec)
+    n = 2500
+    for a, b in [(("aos_packed", 0), ("aos_aligned", 0)), (("soa_multi", 0), ("aosoa", 32)),
+                 (("aosoa", 8), ("soa_single", 0)), (("aos_aligned", 0), ("aosoa", 64))]:
+        for opts in ({}, {"flags": L.COPY_PRESERVE_PADDING}):
+            ms, md, reads, writes, _, keep = _run(L, orc, "mixed", a, b, n, 9, opts)
+            t = L.trace_leaves(md, writes)
+            assert t[:-1] == [n * s for s in ro.sizes]
+            pad = sum(md.blob_sizes()) - n * ro.packed_size
+            # kept padding: untouched, or read and stored back once by a tile
+            assert (t[-1] <= pad) if keep else (t[-1] == pad)
+            ts = L.trace_leaves(ms, reads)
+            assert all(x >= n * s for x, s in zip(ts[:-1], ro.sizes))
+
+
+def test_heatmap_split_parts(L, orc):
+    """A copy into a Split destination writes each byte once when each of its
+    parts comes from one source part; an AoS part fed by two source parts
+    shows its second part copy rewriting the first one's bytes (read and
+    stored back whole), so there every byte is written at least once."""
+    rec = W.RECORDS["particle"]
+    ro, rg = orc.Record(rec), L.Record(rec)
+    n = 4099
+    cases = [(("aos_packed", 0), ("split", (0, 3, ("soa_multi", 0), ("aos_packed", 0))), True),
+             (("split", (0, 3, ("aosoa", 32), ("soa_single", 0))), ("split", (0, 3, ("soa_multi", 0), ("aosoa", 32))),
+              True),
+             (("split", (0, 3, ("soa_multi", 0), ("soa_single", 0))), ("aos_packed", 0), False)]
+    for a, b, once in cases:
+        def mk(mod, r, lay):
+            return mod.Mapping(r, "split", [n], split=lay[1]) if lay[0] == "split" else mod.Mapping(r, lay[0], [n], lay[1])
+        ms_o, md_o, ms, md = mk(orc, ro, a), mk(orc, ro, b), mk(L, rg, a), mk(L, rg, b)
+        src = [W.random_bytes(s, 77 + j) for j, s in enumerate(ms_o.blob_sizes())]
+        want = orc.copy(ms_o, src, md_o)
+        sd = [torch.from_numpy(x).cuda() for x in src]
+        dd = md.alloc(fill=0xCD)
+        writes = _counters(md)
+        L.copy_heatmap(ms, sd, md, dd, dst_writes=writes)
+        torch.cuda.synchronize()
+        for got, w in zip(dd, want):
+            assert np.array_equal(got.cpu().numpy(), w)
+        wc = _np(writes)
+        assert all(int(c.min(initial=1)) >= 1 for c in wc)
+        if once:
+            assert all(int(c.max(initial=1)) == 1 for c in wc)
+
+
+def test_plan_log(L, tmp_path):
+    """LLAMA_TRACE=1 makes every launch print its plan on stderr."""
+    code = ("import torch; from paper_2106_04284_amd import llama as L, workloads as W\n"
+            "r = L.Record(W.PARTICLE); a = L.Mapping(r, 'aos_packed', [5000]); b = L.Mapping(r, 'soa_multi', [5000])\n"
+            "s = a.alloc(fill=1); d = b.alloc(fill=0); L.copy(a, s, b, d); torch.cuda.synchronize()\n")
+    env = dict(os.environ, LLAMA_TRACE="1")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [x for x in r.stderr.splitlines() if x.startswith("[llama] ")]
+    assert len(lines) == 1 and "path=tile" in lines[0] and " mode=" in lines[0], r.stderr[-2000:]
+    assert "read=140000 write=140000" in lines[0]

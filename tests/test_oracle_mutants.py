@@ -56,6 +56,10 @@ MUTANTS = {
     "static_array_one_short": ("for (uint64_t c = 1; c < count; c++)", "for (uint64_t c = 2; c < count; c++)"),
     "aos_aligned_uses_packed_stride": ("*offset = i * orc_aligned_size(r) + orc_aligned_offset(r, f);",
                                        "*offset = i * orc_packed_size(r) + orc_aligned_offset(r, f);"),
+    "copy_writes_no_zero_fill": ("            for (uint64_t o = 0; o < sz; o++)\n                if (!owned[b][o])\n                    counts[b][o]++;",
+                                 "            for (uint64_t o = 0; o < sz; o++)\n                if (!owned[b][o])\n                    (void)0;"),
+    "copy_writes_counts_kept_leaves": ("                    if (!from || from[f] >= 0)\n                        counts[b][o + k]++;",
+                                       "                    counts[b][o + k]++;"),
     "threaded_piece_starts_at_origin": ("delinearize(src, lo, coord);", "(void)lo;"),
     "threaded_last_piece_drops_tail": ("uint64_t hi = k + 1 == pieces ? n : n / (uint64_t)pieces * (uint64_t)(k + 1);",
                                        "uint64_t hi = n / (uint64_t)pieces * (uint64_t)(k + 1);"),

@@ -922,3 +922,48 @@ def test_box_copy_rejects_boxes_outside_a_view(orc):
         orc.copy_box(ms, src, [1, 0], md, dst, [0, 0], [4, 1])
     with pytest.raises(ValueError):
         orc.copy_box(ms, src, [0, 0], md, dst, [0, 2], [1, 4])
+
+
+# --------------------------------------------------------------------------
+# the writes of the definition (Heatmap of the copy, sec. 3.7)
+# --------------------------------------------------------------------------
+
+def _written_by_two_fills(run, sizes):
+    """Which destination bytes a copy writes, found by running it on a
+    destination of 0x00 bytes and on one of 0xFF bytes: a written byte holds
+    the same value both times, an untouched one its fill."""
+    a = run([np.zeros(s, np.uint8) for s in sizes])
+    b = run([np.full(s, 0xFF, np.uint8) for s in sizes])
+    return [(x == y).astype(np.uint32) for x, y in zip(a, b)]
+
+
+@pytest.mark.parametrize("name", ["particle", "mixed", "lbm", "listing1"])
+def test_copy_writes_match_two_fill_coverage(orc, name):
+    """copy_writes, the per-byte writes of the definition, is at most one per
+    byte and equals the bytes the oracle's copies change, for the plain copy
+    (every byte: values, and zeros on padding), the copy that keeps padding,
+    and copies between differing records (leaves without a source keep their
+    bytes, their unused AoSoA lanes included)."""
+    import random
+    r = orc.Record(W.RECORDS[name])
+    g = random.Random(7)
+    for n in (1, 13, 45):
+        for kind, lanes in _layouts():
+            md = orc.Mapping(r, kind, [n], lanes)
+            ms = orc.Mapping(r, "aos_packed", [n])
+            src = [W.random_bytes(s, 11) for s in ms.blob_sizes()]
+            sizes = md.blob_sizes()
+            plain = orc.copy_writes(md)
+            assert all(bool((c == 1).all()) for c in plain), (kind, lanes, n)
+            keep = orc.copy_writes(md, keep_padding=True)
+            want = _written_by_two_fills(lambda d: orc.copy(ms, src, md, d, keep_padding=True), sizes)
+            assert all(np.array_equal(x, y) for x, y in zip(keep, want)), (kind, lanes, n)
+            for keep_padding in (False, True):
+                frm = [None if g.random() < 0.4 else f for f in range(r.nleaves)]
+                if all(x is None for x in frm):
+                    frm[0] = 0
+                got = orc.copy_writes(md, source_leaf=frm, keep_padding=keep_padding)
+                want = _written_by_two_fills(
+                    lambda d: orc.copy_leaves(ms, src, md, d, frm, keep_padding=keep_padding), sizes)
+                assert all(np.array_equal(x, y) for x, y in zip(got, want)), (kind, lanes, n, frm, keep_padding)
+
