@@ -346,7 +346,7 @@ def bench_batch(L, torch, args, dev, stream):
     b = L.Batch(items)
     heur_med, _ = timed(lambda: b.launch(stream), 3)
     log(f"batch: default plan {total / (heur_med * 1e-3) / 1e9:.1f} GB/s; autotuning the batch")
-    tuned_gbs = b.autotune(stream=stream, reps=2)
+    tuned_gbs = b.autotune(stream=stream, reps=2) if not args.no_batch_autotune else total / (heur_med * 1e-3) / 1e9
     th = b.info()["threads"]
     log(f"batch: autotuned {tuned_gbs:.1f} GB/s (threads {th}, lds {b.info()['lds_bytes']})")
     med, mn = timed(lambda: b.launch(stream), args.steps)
@@ -571,12 +571,19 @@ def bench_serve(L, torch, args, dev):
     total_bytes = sum(r["bytes"] for r in reqs[warm:])
     mean_bytes = total_bytes / count
     log(f"serve: batched server at saturation {capacity['gbs']} GB/s")
+    capacity_per_request = run(2, 1e9)
+    log(f"serve: per-request llama_copy at saturation {capacity_per_request['gbs']} GB/s")
     by_rho = {}
-    for rho in sorted({0.5, args.rho}):
+    policies = [("batched", 0), ("naive", 1), ("per_request", 2)]
+    for n_rho, rho in enumerate(sorted({0.5, args.rho})):
         rate = rho * batch_gbs * 1e9 / mean_bytes
         log(f"serve: offered load rho={rho} -> {rate:.0f} requests/s")
+        # the policies in rotated order from one load to the next, so that no
+        # policy always runs first (or right after the naive one's backlog)
+        order = policies[n_rho % 3:] + policies[:n_rho % 3]
+        res = {name: run(pol, rate) for name, pol in order}
         by_rho[rho] = {"rate_per_s": round(rate, 1), "offered_gbs": round(rho * batch_gbs, 1),
-                       **{name: run(pol, rate) for name, pol in (("batched", 0), ("naive", 1), ("per_request", 2))}}
+                       "order": [name for name, _ in order], **res}
     out = by_rho[args.rho]
     return {"metric": METRIC, "value": out["batched"]["gbs"], "unit": "GB/s", "n_gpus": 1, "steps": count,
             "warmup": warm, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
@@ -586,7 +593,8 @@ def bench_serve(L, torch, args, dev):
                        "rho": args.rho, "rate_per_s": out["rate_per_s"], "requests": count, "warmup_requests": warm,
                        "mean_request_bytes": round(mean_bytes), "batching_workload_gbs": round(batch_gbs, 1)},
             "p50_ms": out["batched"]["p50_ms"], "p99_ms": out["batched"]["p99_ms"],
-            "extras": {"server_saturation_gbs": capacity["gbs"],
+            "extras": {"server_saturation_gbs": capacity["gbs"], "saturation_batched": capacity,
+                       "saturation_per_request": capacity_per_request,
                        **{f"rho_{rho}": v for rho, v in by_rho.items()}},
             "device": dev.name}
 
@@ -795,6 +803,7 @@ def main():
     ap.add_argument("--rho", type=float, default=0.8, help="serve: offered load as a fraction of batched GB/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-naive", action="store_true")
+    ap.add_argument("--no-batch-autotune", action="store_true", help="batch: keep the default plan")
     ap.add_argument("--details", default=None, help="write per-pair results to this JSON file")
     args = ap.parse_args()
 

@@ -69,9 +69,12 @@ uint32_t run_log2(uint32_t order, uint32_t rank, const uint32_t* qlog, uint32_t 
 
 // Tile extents (log2 per dimension) for about 2^qsum records: a Morton side
 // needs a cube; otherwise each side's fast dimension gets as long runs as the
-// box allows, split evenly when the two fast dimensions differ.
+// box allows.  When the two fast dimensions differ (a transpose), each side
+// first gets runs of about 256 bytes per span (a field-major side's spans are
+// one leaf's values, a record-major side's whole records; unit_s and unit_d
+// are those bytes per record), then the two share the rest.
 void tile_shape(uint32_t rank, const uint64_t* box, const SidePlan& s, const SidePlan& d, uint32_t qsum,
-                uint32_t* qlog)
+                uint32_t unit_s, uint32_t unit_d, uint32_t* qlog)
 {
     for (uint32_t k = 0; k < LLAMA_MAX_RANK; k++)
         qlog[k] = 0;
@@ -80,43 +83,57 @@ void tile_shape(uint32_t rank, const uint64_t* box, const SidePlan& s, const Sid
         return;
     }
     if (s.order == kOrderMorton || d.order == kOrderMorton) {
-        const uint32_t b = std::max<uint32_t>(1, qsum / rank);
+        // a cube of at least 2^qsum records, so that the other side's runs
+        // stay long (the LDS budget shrinks it if needed)
+        const uint32_t b = std::max<uint32_t>(1, (qsum + rank - 1) / rank);
         for (uint32_t k = 0; k < rank; k++)
             qlog[k] = b;
         return;
     }
     auto cap = [&](uint32_t k) { return log2_ceil(std::max<uint64_t>(box[k], 1)); };
-    // dimensions in the order their extent is filled
-    std::vector<uint32_t> dims;
-    auto push = [&](uint32_t k) {
-        if (std::find(dims.begin(), dims.end(), k) == dims.end())
-            dims.push_back(k);
-    };
-    const bool row = s.order == kOrderRow || d.order == kOrderRow;
-    const bool col = s.order == kOrderCol || d.order == kOrderCol;
+    auto fast = [&](const SidePlan& x) { return x.order == kOrderCol ? 0u : rank - 1; };
     uint32_t left = qsum;
-    if (row && col) { // a transpose: both fast dimensions share the tile
-        const uint32_t b = std::min(cap(0), qsum / 2);
-        qlog[rank - 1] = std::min(cap(rank - 1), qsum - b);
-        qlog[0] = std::min(cap(0), qsum - qlog[rank - 1]);
-        left = qsum - qlog[rank - 1] - qlog[0];
-        for (int k = int(rank) - 2; k >= 1; k--) {
+    const bool one_s = s.order == kOrderOne;
+    const uint32_t fa = one_s ? fast(d) : fast(s), fb = fast(d);
+    if (fa != fb) { // a transpose: both fast dimensions share the tile
+        auto want = [&](uint32_t unit) { return log2_ceil((256 + unit - 1) / std::max<uint32_t>(unit, 1)); };
+        qlog[fa] = std::min({cap(fa), want(unit_s), left});
+        left -= qlog[fa];
+        qlog[fb] = std::min({cap(fb), want(unit_d), left});
+        left -= qlog[fb];
+        while (left > 0 && (qlog[fa] < cap(fa) || qlog[fb] < cap(fb))) {
+            // the side whose spans are shorter grows first
+            const bool grow_a = qlog[fa] < cap(fa) &&
+                                (qlog[fb] >= cap(fb) || (uint64_t(unit_s) << qlog[fa]) <= (uint64_t(unit_d) << qlog[fb]));
+            qlog[grow_a ? fa : fb]++;
+            left--;
+        }
+        for (int k = int(rank) - 1; k >= 0; k--) {
+            if (uint32_t(k) == fa || uint32_t(k) == fb)
+                continue;
             qlog[k] = std::min(cap(uint32_t(k)), left);
             left -= qlog[k];
         }
         return;
     }
-    if (col) {
+    // one fast dimension: fill it, then the next slower ones
+    std::vector<uint32_t> dims;
+    if (fa == 0) {
         for (uint32_t k = 0; k < rank; k++)
-            push(k);
+            dims.push_back(k);
     } else {
         for (int k = int(rank) - 1; k >= 0; k--)
-            push(uint32_t(k));
+            dims.push_back(uint32_t(k));
     }
     for (uint32_t k : dims) {
         qlog[k] = std::min(cap(k), left);
         left -= qlog[k];
     }
+}
+
+uint32_t magic_for(uint32_t g)
+{
+    return uint32_t(((uint64_t(1) << 32) + g - 1) / g);
 }
 
 // Fills a BoxSide (everything but the LDS layout).
@@ -159,7 +176,12 @@ bool try_plan(const Request& rq, const uint64_t* so, const uint64_t* dof, const 
     std::memset(&a, 0, sizeof(a));
     BoxHeader& h = a.h;
     h.rank = rank;
-    tile_shape(rank, box, ss, ds, qsum, h.qlog);
+    uint32_t min_leaf = ~0u;
+    for (const Leaf& l : r.leaves)
+        min_leaf = std::min(min_leaf, l.size);
+    const uint32_t unit_s = ss.field_major ? min_leaf : uint32_t(r.packed_size);
+    const uint32_t unit_d = ds.field_major ? min_leaf : uint32_t(r.packed_size);
+    tile_shape(rank, box, ss, ds, qsum, unit_s, unit_d, h.qlog);
     h.qlog_sum = 0;
     for (uint32_t k = 0; k < rank; k++)
         h.qlog_sum += h.qlog[k];
@@ -206,6 +228,8 @@ bool try_plan(const Request& rq, const uint64_t* so, const uint64_t* dof, const 
         for (uint32_t k = 0; k < rank; k++)
             h.num_units *= h.grid[k];
     }
+    if (h.num_units >= (uint64_t(1) << 32))
+        fail(LLAMA_E_UNSUPPORTED, "a box copy of more than 2^32 tiles");
 
     // entries: the leaves, then (AoS destinations) the destination's gaps
     const size_t F = r.leaves.size();
@@ -216,7 +240,9 @@ bool try_plan(const Request& rq, const uint64_t* so, const uint64_t* dof, const 
     h.num_leaves = uint32_t(F);
     h.num_entries = uint32_t(ne);
     const uint64_t Ws = uint64_t(1) << a.src.run_log2, Wd = uint64_t(1) << a.dst.run_log2;
-    uint32_t src_slot = 0;
+    const uint64_t Q = uint64_t(1) << h.qlog_sum;
+    const uint64_t Rs = Q / Ws, Rd = Q / Wd;
+    uint64_t lds = 0; // source runs first
     for (size_t f = 0; f < F; f++) {
         BoxEntry& e = a.e[f];
         const uint32_t sz = r.leaves[f].size;
@@ -224,9 +250,12 @@ bool try_plan(const Request& rq, const uint64_t* so, const uint64_t* dof, const 
         e.dst_addr = rq.dst_ptr[D.blob[f]] + D.base[f];
         e.dst_off = uint32_t(D.base[f]);
         if (ss.field_major) {
+            // leaf f's runs, one slot of `gran` granules each
             e.src_addr = rq.src_ptr[S.blob[f]] + S.base[f];
-            e.src_off = src_slot;
-            src_slot += round16(Ws * sz + 16);
+            e.src_off = uint32_t(std::min<uint64_t>(lds, ~0u));
+            e.gran = round16(Ws * sz + 16) / 16;
+            e.magic = magic_for(e.gran);
+            lds += Rs * e.gran * 16;
         } else {
             e.src_off = uint32_t(S.base[f]);
         }
@@ -238,7 +267,6 @@ bool try_plan(const Request& rq, const uint64_t* so, const uint64_t* dof, const 
             e.dst_off = uint32_t(D.gaps[g].first);
             e.size = uint32_t(D.gaps[g].second);
         }
-    // LDS: source runs, destination runs (staged), then the two run tables
     if (!ss.field_major) {
         uint64_t blocks;
         if (ss.one)
@@ -247,17 +275,49 @@ bool try_plan(const Request& rq, const uint64_t* so, const uint64_t* dof, const 
             blocks = Ws;
         else
             blocks = (Ws - 1) / S.lanes + 2;
-        src_slot = round16(blocks * a.src.block + 16);
+        a.src.gran = round16(blocks * a.src.block + 16) / 16;
+        a.src.magic = magic_for(a.src.gran);
+        lds = Rs * a.src.gran * 16;
     }
-    a.src.slot = src_slot;
-    a.dst.slot = staged ? round16(Wd * D.block + 16) : 0;
-    const uint64_t Q = uint64_t(1) << h.qlog_sum;
-    const uint64_t Rs = Q / Ws, Rd = Q / Wd;
-    uint64_t lds = 0;
     a.src.lds_base = 0;
-    lds += Rs * a.src.slot;
+    // destination runs (staged), the record map, the two run tables
     a.dst.lds_base = uint32_t(std::min<uint64_t>(lds, ~0u));
-    lds += Rd * a.dst.slot;
+    // an AoS destination of whole 4-byte words of whole 4-byte values, read
+    // from 4-byte aligned source positions, gathers its granules word by word
+    // (no destination region); kept padding needs the region (loaded first)
+    bool gather = staged && !preserve && D.block % 4 == 0 && D.block / 4 <= uint64_t(kBoxMaxWords) &&
+                  F < kBoxWordZero;
+    if (gather) {
+        for (size_t f = 0; f < F && gather; f++) {
+            const uint32_t sz = r.leaves[f].size;
+            gather = sz % 4 == 0 && D.base[f] % 4 == 0 &&
+                     (ss.field_major ? (rq.src_ptr[S.blob[f]] + S.base[f]) % 4 == 0
+                                     : S.base[f] % 4 == 0 && a.src.block % 4 == 0 && rq.src_ptr[0] % 4 == 0);
+        }
+        gather = gather && rq.dst_ptr[0] % 4 == 0;
+    }
+    if (staged) {
+        a.dst.gran = round16(Wd * D.block + 16) / 16;
+        a.dst.magic = magic_for(a.dst.gran);
+        if (!gather)
+            lds += Rd * a.dst.gran * 16;
+    }
+    if (gather) {
+        h.flags |= kBoxGather;
+        h.words = uint32_t(D.block / 4);
+        h.kmagic = magic_for(uint32_t(D.block));
+        for (uint32_t w = 0; w < h.words; w++) {
+            uint32_t e = kBoxWordZero;
+            for (size_t f = 0; f < F; f++)
+                if (D.base[f] <= 4 * w && 4 * w < D.base[f] + r.leaves[f].size)
+                    e = uint32_t(f) | (uint32_t(4 * w - D.base[f]) << 8);
+            a.words[w] = e;
+        }
+        h.wtab = uint32_t(std::min<uint64_t>(lds, ~0u));
+        lds += ((h.words * 4 + 15) & ~15u) + F * 16;
+    }
+    h.map = uint32_t(std::min<uint64_t>(lds, ~0u));
+    lds += Q * 16;
     a.src.table = uint32_t(std::min<uint64_t>(lds, ~0u));
     lds += Rs * 8;
     a.dst.table = uint32_t(std::min<uint64_t>(lds, ~0u));
@@ -322,7 +382,7 @@ std::vector<Plan> make_box_plans(const Request& rq, const uint64_t* so, const ui
         return plans;
     }
     // records per tile: about 16 KiB of source values, at least 64
-    uint32_t qsum = T ? log2u(T) : std::min<uint32_t>(12, std::max<uint32_t>(6, log2u(16384 / std::max<uint64_t>(r.packed_size, 1))));
+    uint32_t qsum = T ? log2u(T) : std::min<uint32_t>(12, std::max<uint32_t>(6, log2u(24576 / std::max<uint64_t>(r.packed_size, 1))));
     const uint32_t budget = 64 * 1024;
     while (!try_plan(rq, so, dof, box, full, preserve, qsum, budget, p)) {
         if (qsum <= 1)

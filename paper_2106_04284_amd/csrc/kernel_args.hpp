@@ -288,7 +288,7 @@ constexpr uint32_t kBatchLoadsOnce = 1;
 enum : uint32_t { kOrderRow = 0, kOrderCol = 1, kOrderMorton = 2, kOrderPoint = 3, kOrderOne = 4 };
 enum : uint32_t { kLinRow = 0, kLinCol = 1, kLinMorton = 2 };
 
-constexpr int kBoxMaxEntries = 100;
+constexpr int kBoxMaxEntries = 80;
 
 struct BoxSide {
     uint64_t offset[LLAMA_MAX_RANK]; // the box's origin in this view's coordinates
@@ -302,29 +302,37 @@ struct BoxSide {
     uint32_t order;    // kOrder*: how a tile's records form runs
     uint32_t morton_bits; // bits per dimension of the Morton index
     uint32_t run_log2; // log2 of a run's records (unclipped)
-    uint32_t slot;     // LDS bytes per run
+    uint32_t gran;     // record-major source, staged destination: 16-byte granules of a run's LDS slot
+    uint32_t magic;    // ceil(2^32 / gran): g / gran == mulhi(g, magic) for the granule counts of a tile
     uint32_t lds_base; // LDS byte of run 0
     uint32_t table;    // LDS byte of the run table (one 64-bit start index per run)
-    uint32_t pad;
 };
 
 struct BoxEntry {
     uint64_t src_addr; // field-major source: blob + leaf base; else 0
     uint64_t dst_addr; // destination: blob + leaf base (direct stores); 0 for a gap
     uint32_t size;     // bytes per value (a gap: bytes of the gap)
-    uint32_t src_off;  // record-major source: the leaf's byte in a block; field-major: its LDS byte in a run slot
-    uint32_t dst_off;  // staged destination: the leaf's (or gap's) byte in a record
+    uint32_t src_off;  // record-major source: the leaf's byte in a block; field-major: the LDS byte of its
+                       // runs' slots (leaf by leaf)
+    uint32_t dst_off;  // AoS destination: the leaf's (or gap's) byte in a record
     uint32_t gap;      // 1: a destination gap (zeros)
+    uint32_t gran;     // field-major source: 16-byte granules of one run's slot of this leaf
+    uint32_t magic;    // ceil(2^32 / gran)
 };
 
 struct BoxHeader {
     uint32_t rank;
     uint32_t num_leaves;
-    uint32_t num_entries; // leaves, then destination gaps (staged destinations)
+    uint32_t num_entries; // leaves, then the gaps of an AoS destination
     uint32_t flags;       // kBoxFull, kBoxPreserve, kBoxStaged, kBoxUnitMorton
     uint32_t qlog[LLAMA_MAX_RANK]; // tile extents, log2
     uint32_t qlog_sum;             // log2 of the records of a tile
     uint32_t lds_bytes;
+    uint32_t map;                  // LDS byte of the record map (16 bytes per record of a tile)
+    uint32_t words;                // kBoxGather: 4-byte words of a destination record
+    uint32_t wtab;                 // kBoxGather: LDS byte of the word table, then the leaves' source fields
+    uint32_t kmagic;               // kBoxGather: ceil(2^32 / K) for the destination record stride K
+    uint32_t pad;
     uint64_t box[LLAMA_MAX_RANK];   // the copy's box (full copies: the extents)
     uint64_t grid[LLAMA_MAX_RANK];  // tiles per dimension
     uint64_t shift[LLAMA_MAX_RANK]; // tile t covers box coordinates [t q - shift, (t + 1) q - shift)
@@ -341,11 +349,21 @@ constexpr uint32_t kBoxStaged = 4;
 // units enumerate aligned cubes in Morton order (a full copy into a Morton
 // destination, whose holes and tail must be written)
 constexpr uint32_t kBoxUnitMorton = 8;
+// an AoS destination whose records are whole 4-byte words of whole 4-byte
+// values: every 16-byte granule of a destination run is assembled word by
+// word from the source region (word table `words`) and stored, without a
+// destination region in LDS
+constexpr uint32_t kBoxGather = 16;
+constexpr int kBoxMaxWords = 52;
+// a word-table entry: the leaf (bits 0-7; kBoxWordZero: a gap) and the byte
+// of the leaf's value (bits 8-19)
+constexpr uint32_t kBoxWordZero = 0xFFu;
 
 struct BoxArgs {
     BoxHeader h;
     BoxSide src, dst;
     BoxEntry e[kBoxMaxEntries];
+    uint32_t words[kBoxMaxWords]; // kBoxGather: the destination record's words
 };
 static_assert(sizeof(BoxArgs) <= 4096, "kernel arguments are limited to 4 KiB");
 

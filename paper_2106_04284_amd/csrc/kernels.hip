@@ -1017,16 +1017,17 @@ __device__ __forceinline__ int box_fast(uint32_t order, uint32_t rank)
 // e is the coordinate in the fast dimension).  The run index ravels the
 // other dimensions, last fastest; a Morton run's element is the Morton index
 // inside the tile's cube.
+template <int R>
 __device__ __forceinline__ void box_coord(const BoxHeader& h, uint32_t order, uint32_t k, uint32_t e, uint32_t* x)
 {
     const uint32_t r = h.rank;
     if (order == kOrderMorton) {
 #pragma unroll
-        for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+        for (uint32_t d = 0; d < R; d++)
             x[d] = 0;
         for (uint32_t j = 0; j < h.qlog[0]; j++)
 #pragma unroll
-            for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+            for (uint32_t d = 0; d < R; d++)
                 if (d < r)
                     x[d] |= ((e >> (j * r + r - 1 - d)) & 1u) << j;
         return;
@@ -1034,7 +1035,7 @@ __device__ __forceinline__ void box_coord(const BoxHeader& h, uint32_t order, ui
     const int fast = box_fast(order, r);
     uint32_t rem = k;
 #pragma unroll
-    for (int d = LLAMA_MAX_RANK - 1; d >= 0; d--) {
+    for (int d = R - 1; d >= 0; d--) {
         if (d >= int(r)) {
             x[d] = 0;
         } else if (d == fast) {
@@ -1047,6 +1048,7 @@ __device__ __forceinline__ void box_coord(const BoxHeader& h, uint32_t order, ui
 }
 
 // The inverse of box_coord: run k and element e of tile-local coordinate x.
+template <int R>
 __device__ __forceinline__ void box_run(const BoxHeader& h, uint32_t order, const uint32_t* x, uint32_t& k, uint32_t& e)
 {
     const uint32_t r = h.rank;
@@ -1057,14 +1059,14 @@ __device__ __forceinline__ void box_run(const BoxHeader& h, uint32_t order, cons
     if (order == kOrderMorton) {
         for (uint32_t j = 0; j < h.qlog[0]; j++)
 #pragma unroll
-            for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+            for (uint32_t d = 0; d < R; d++)
                 if (d < r)
                     e |= ((x[d] >> j) & 1u) << (j * r + r - 1 - d);
         return;
     }
     const int fast = box_fast(order, r);
 #pragma unroll
-    for (int d = 0; d < LLAMA_MAX_RANK; d++) {
+    for (int d = 0; d < R; d++) {
         if (d >= int(r))
             continue;
         if (d == fast)
@@ -1075,23 +1077,24 @@ __device__ __forceinline__ void box_run(const BoxHeader& h, uint32_t order, cons
 }
 
 // Linear index of the absolute coordinate c on side s (its linearizer).
+template <int R>
 __device__ __forceinline__ uint64_t box_linear(const BoxSide& s, uint32_t r, const uint64_t* c)
 {
     uint64_t i = 0;
     if (s.lin == kLinMorton) {
         for (uint32_t j = 0; j < s.morton_bits; j++)
 #pragma unroll
-            for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+            for (uint32_t d = 0; d < R; d++)
                 if (d < r)
                     i |= ((c[d] >> j) & 1ull) << (j * r + r - 1 - d);
     } else if (s.lin == kLinCol) {
 #pragma unroll
-        for (int d = LLAMA_MAX_RANK - 1; d >= 0; d--)
+        for (int d = R - 1; d >= 0; d--)
             if (d < int(r))
                 i = i * s.extent[d] + c[d];
     } else {
 #pragma unroll
-        for (int d = 0; d < LLAMA_MAX_RANK; d++)
+        for (int d = 0; d < R; d++)
             if (d < int(r))
                 i = i * s.extent[d] + c[d];
     }
@@ -1152,26 +1155,56 @@ __device__ __forceinline__ void box_store_value(const uint8_t* lds, uint32_t sp,
     }
 }
 
-// LDS byte of the value of entry en for the record at index i of source run k
-// (start index `start`).
-__device__ __forceinline__ uint32_t box_src_pos(const BoxSide& s, const BoxEntry& en, uint32_t k, uint64_t start,
-                                                uint64_t i)
+// The byte range of run k of side X (start index `start`, w records): its
+// first byte and its length.  Record-major sides span whole blocks; a One
+// source is its single record.
+__device__ __forceinline__ void box_span(const BoxSide& X, uint64_t start, uint32_t w, uint64_t& g0, uint32_t& len)
 {
-    const uint32_t slot = s.lds_base + k * s.slot;
-    if (s.mode == kFieldMajor) {
-        const uint32_t ph = (uint32_t(en.src_addr) + uint32_t(start) * en.size) & 15u;
-        return slot + en.src_off + ph + uint32_t(i - start) * en.size;
+    if (X.order == kOrderOne) {
+        g0 = X.blob;
+        len = uint32_t(X.block);
+        return;
     }
-    if (s.order == kOrderOne)
-        return slot + (uint32_t(s.blob) & 15u) + en.src_off;
-    const uint64_t b0 = start >> s.log2_lanes;
-    const uint32_t ph = (uint32_t(s.blob) + uint32_t(b0) * uint32_t(s.block)) & 15u;
-    const uint64_t m = (uint64_t(1) << s.log2_lanes) - 1u;
-    return slot + ph + uint32_t((i >> s.log2_lanes) - b0) * uint32_t(s.block) + en.src_off +
-           uint32_t(i & m) * en.size;
+    const uint64_t b0 = start >> X.log2_lanes, b1 = (start + w - 1) >> X.log2_lanes;
+    g0 = X.blob + b0 * X.block;
+    len = uint32_t((b1 - b0 + 1) * X.block);
 }
 
-template <bool kStaged, bool kCount>
+// Loads the spans of a group into LDS with 16-byte DMA, every lane of every
+// wave on one granule: span k of the group holds `gran` granules at LDS byte
+// `base` + 16 gran k (its first byte at its global address mod 16); lanes
+// past a span's granules load nothing.  `span(k, g0, len)` gives span k's
+// global range (len 0: no span).
+template <bool kCount, typename Span>
+__device__ __forceinline__ void box_load_group(uint32_t base, uint32_t nspans, uint32_t gran, uint32_t magic,
+                                               uint32_t wave, uint32_t nwaves, uint32_t lane, uint32_t lds_base,
+                                               Span span)
+{
+    const uint32_t total = nspans * gran;
+    for (uint32_t c = wave; c * 64u < total; c += nwaves) {
+        const uint32_t g = c * 64u + lane;
+        const uint32_t k = __umulhi(g, magic);
+        const uint32_t gi = g - k * gran;
+        uint64_t g0 = 0;
+        uint32_t len = 0;
+        if (g < total)
+            span(k, g0, len);
+        if (len > 0 && gi < ((uint32_t(g0) & 15u) + len + 15u) >> 4)
+            lds_dma16<false, kCount>((g0 & ~uint64_t(15)) + uint64_t(gi) * 16u, uniform(lds_base + base + c * 1024u));
+    }
+}
+
+// Record map entries (16 bytes per record of a tile, in the destination's
+// order): a = kMapSkip (no record), kMapHole (a hole of a full copy: zeros),
+// or the source position: record-major source: a = LDS byte of the record's
+// block plus its phase, b = its lane; field-major: a = run, b = element, c =
+// the run's start index (low bits).  d: staged destination: LDS byte of the
+// destination record.
+constexpr uint32_t kMapSkip = 0xFFFFFFFFu, kMapHole = 0xFFFFFFFEu;
+
+// R: the largest rank this instantiation handles (loops over dimensions are
+// unrolled to R, which keeps the per-dimension values in registers)
+template <int R, bool kStaged, bool kCount>
 __device__ __forceinline__ void box_body(const BoxArgs& a, uint64_t u, uint8_t* lds)
 {
     const BoxHeader& h = a.h;
@@ -1183,220 +1216,301 @@ __device__ __forceinline__ void box_body(const BoxArgs& a, uint64_t u, uint8_t* 
     const bool full = (h.flags & kBoxFull) != 0, preserve = (h.flags & kBoxPreserve) != 0;
 
     // ---- the tile's frame origin in box coordinates
-    int64_t o[LLAMA_MAX_RANK];
+    int64_t o[R];
     if (h.flags & kBoxUnitMorton) {
         // cube u of the destination's Morton order: deinterleave u
-        uint64_t c[LLAMA_MAX_RANK] = {};
+        uint64_t c[R] = {};
         for (uint32_t j = 0; j * r < 64; j++)
 #pragma unroll
-            for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+            for (uint32_t d = 0; d < R; d++)
                 if (d < r && j * r + r - 1 - d < 64)
                     c[d] |= ((u >> (j * r + r - 1 - d)) & 1ull) << j;
 #pragma unroll
-        for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
+        for (uint32_t d = 0; d < R; d++)
             o[d] = d < r ? int64_t(c[d] << h.qlog[d]) : 0;
     } else {
-        uint64_t rem = u;
+        // the unit count and every grid extent fit 32 bits (checked by the planner)
+        uint32_t rem = uint32_t(u);
 #pragma unroll
-        for (int d = LLAMA_MAX_RANK - 1; d >= 0; d--) {
+        for (int d = R - 1; d >= 0; d--) {
             o[d] = 0;
             if (d < int(r)) {
-                const uint64_t t = rem % h.grid[d];
-                rem /= h.grid[d];
-                o[d] = int64_t(t << h.qlog[d]) - int64_t(h.shift[d]);
+                const uint32_t g = uint32_t(h.grid[d]), q = rem / g, t = rem - q * g;
+                rem = q;
+                o[d] = int64_t(uint64_t(t) << h.qlog[d]) - int64_t(h.shift[d]);
             }
         }
     }
     // the clipped fast range of each side: [lo, lo + len)
     const int fs = box_fast(S.order, r), fd = box_fast(D.order, r);
     uint32_t lo_s = 0, len_s = 0, lo_d = 0, len_d = 0;
-    if (fs >= 0) {
-        const int64_t lo = max<int64_t>(0, -o[fs]), hi = min<int64_t>(1ll << h.qlog[fs], int64_t(h.box[fs]) - o[fs]);
-        lo_s = uint32_t(lo);
-        len_s = hi > lo ? uint32_t(hi - lo) : 0u;
-    }
-    if (fd >= 0) {
-        const int64_t lo = max<int64_t>(0, -o[fd]), hi = min<int64_t>(1ll << h.qlog[fd], int64_t(h.box[fd]) - o[fd]);
-        lo_d = uint32_t(lo);
-        len_d = hi > lo ? uint32_t(hi - lo) : 0u;
+#pragma unroll
+    for (int d = 0; d < R; d++) {
+        if (d >= int(r))
+            continue;
+        const int64_t lo = max<int64_t>(0, -o[d]), hi = min<int64_t>(1ll << h.qlog[d], int64_t(h.box[d]) - o[d]);
+        const uint32_t l = uint32_t(lo), n = hi > lo ? uint32_t(hi - lo) : 0u;
+        if (d == fs) {
+            lo_s = l;
+            len_s = n;
+        }
+        if (d == fd) {
+            lo_d = l;
+            len_d = n;
+        }
     }
 
-    // ---- run tables: the start index of every run (~0: no record in the box)
+    // ---- run tables: the start index of every run (~0: no record in the box);
+    //      one side per loop, so that the side's fields stay uniform
     const uint32_t Rs = Q >> S.run_log2, Rd = Q >> D.run_log2;
     uint64_t* tab_s = (uint64_t*)(lds + S.table);
     uint64_t* tab_d = (uint64_t*)(lds + D.table);
-    for (uint32_t q = tid; q < Rs + Rd; q += nthr) {
-        const bool src = q < Rs;
-        const BoxSide& X = src ? S : D;
-        const uint32_t k = src ? q : q - Rs;
-        uint64_t start = ~0ull;
-        if (X.order == kOrderOne) {
-            start = 0;
-        } else if (!src && (h.flags & kBoxUnitMorton)) {
-            start = u << h.qlog_sum; // the cube's first Morton index
-        } else {
-            const int fx = src ? fs : fd;
-            uint32_t x[LLAMA_MAX_RANK];
-            box_coord(h, X.order, k, fx >= 0 ? (src ? lo_s : lo_d) : 0u, x);
-            bool in = fx < 0 || (src ? len_s : len_d) > 0;
-            uint64_t c[LLAMA_MAX_RANK];
+    auto run_start = [&](const BoxSide& X, int fx, uint32_t lo, uint32_t len, uint32_t k) -> uint64_t {
+        if (X.order == kOrderOne)
+            return 0;
+        uint32_t x[R];
+        box_coord<R>(h, X.order, k, fx >= 0 ? lo : 0u, x);
+        bool in = fx < 0 || len > 0;
+        uint64_t c[R];
 #pragma unroll
-            for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++) {
-                c[d] = 0;
-                if (d < r) {
-                    const int64_t b = o[d] + int64_t(x[d]);
-                    // a Morton run's cube may reach past the box: its records are
-                    // checked one by one
-                    if (X.order != kOrderMorton && (b < 0 || b >= int64_t(h.box[d])))
-                        in = false;
-                    c[d] = uint64_t(int64_t(X.offset[d]) + b);
-                }
+        for (uint32_t d = 0; d < R; d++) {
+            c[d] = 0;
+            if (d < r) {
+                const int64_t b = o[d] + int64_t(x[d]);
+                // a Morton run's cube may reach past the box: its records are
+                // checked one by one
+                if (X.order != kOrderMorton && (b < 0 || b >= int64_t(h.box[d])))
+                    in = false;
+                c[d] = uint64_t(int64_t(X.offset[d]) + b);
             }
-            if (in)
-                start = box_linear(X, r, c);
         }
-        (src ? tab_s : tab_d)[k] = start;
-    }
+        return in ? box_linear<R>(X, r, c) : ~0ull;
+    };
+    for (uint32_t k = tid; k < Rs; k += nthr)
+        tab_s[k] = run_start(S, fs, lo_s, len_s, k);
+    for (uint32_t k = tid; k < Rd; k += nthr)
+        tab_d[k] = (h.flags & kBoxUnitMorton) ? (u << h.qlog_sum) // the cube's first Morton index
+                                              : run_start(D, fd, lo_d, len_d, k);
     __syncthreads();
 
-    // ---- source runs -> LDS, each run by one wave
-    for (uint32_t k = wave; k < Rs; k += nwaves) {
-        const uint64_t start = tab_s[k];
-        const uint32_t w = box_run_len(S, Q, start, len_s);
-        if (w == 0)
-            continue;
-        const uint32_t slot = S.lds_base + k * S.slot;
-        if (S.mode == kFieldMajor) {
-            for (uint32_t f = 0; f < h.num_leaves; f++) {
-                const BoxEntry& en = a.e[f];
-                load_span<false, kCount>(en.src_addr + start * en.size, w * en.size, slot + en.src_off, 0, 1, 0, lane,
-                                         lds_base);
-            }
-        } else if (S.order == kOrderOne) {
-            load_span<false, kCount>(S.blob, uint32_t(S.block), slot, 0, 1, 0, lane, lds_base);
-        } else {
-            const uint64_t b0 = start >> S.log2_lanes, b1 = (start + w - 1) >> S.log2_lanes;
-            load_span<false, kCount>(S.blob + b0 * S.block, uint32_t((b1 - b0 + 1) * S.block), slot, 0, 1, 0, lane,
-                                     lds_base);
+    // ---- source runs -> LDS, granule by granule over all waves
+    if (S.mode == kFieldMajor) {
+        for (uint32_t f = 0; f < h.num_leaves; f++) {
+            const BoxEntry& en = a.e[f];
+            box_load_group<kCount>(S.lds_base + en.src_off, Rs, en.gran, en.magic, wave, nwaves, lane, lds_base,
+                                   [&](uint32_t k, uint64_t& g0, uint32_t& len) {
+                                       const uint64_t st = tab_s[k];
+                                       const uint32_t w = box_run_len(S, Q, st, len_s);
+                                       g0 = en.src_addr + st * en.size;
+                                       len = w * en.size;
+                                   });
         }
+    } else {
+        box_load_group<kCount>(S.lds_base, Rs, S.gran, S.magic, wave, nwaves, lane, lds_base,
+                               [&](uint32_t k, uint64_t& g0, uint32_t& len) {
+                                   const uint64_t st = tab_s[k];
+                                   const uint32_t w = box_run_len(S, Q, st, len_s);
+                                   len = 0;
+                                   if (w > 0)
+                                       box_span(S, st, w, g0, len);
+                               });
     }
-    if (kStaged && preserve) { // kept padding: the destination records are loaded first
-        for (uint32_t k = wave; k < Rd; k += nwaves) {
-            const uint64_t start = tab_d[k];
-            const uint32_t w = box_run_len(D, Q, start, len_d);
-            if (w > 0)
-                load_span<false, kCount>(D.blob + start * D.block, uint32_t(w * D.block), D.lds_base + k * D.slot, 0,
-                                         1, 0, lane, lds_base);
+    if (kStaged && preserve) // kept padding: the destination records are loaded first
+        box_load_group<kCount>(D.lds_base, Rd, D.gran, D.magic, wave, nwaves, lane, lds_base,
+                               [&](uint32_t k, uint64_t& g0, uint32_t& len) {
+                                   const uint64_t st = tab_d[k];
+                                   const uint32_t w = box_run_len(D, Q, st, len_d);
+                                   g0 = D.blob + st * D.block;
+                                   len = w * uint32_t(D.block);
+                               });
+
+    // ---- the record map, in the destination's order (overlaps the loads)
+    const uint32_t wlog = D.run_log2, wmask = (1u << wlog) - 1u;
+    uint4* map = (uint4*)(lds + h.map);
+    for (uint32_t j = tid; j < Q; j += nthr) {
+        const uint32_t kd = j >> wlog, ed = j & wmask;
+        const uint64_t sd = tab_d[kd];
+        uint4 m{kMapSkip, 0u, 0u, 0u};
+        if (ed < box_run_len(D, Q, sd, len_d)) {
+            if (kStaged)
+                m.w = D.lds_base + kd * (D.gran << 4) + ((uint32_t(D.blob) + uint32_t(sd) * uint32_t(D.block)) & 15u) +
+                      ed * uint32_t(D.block);
+            uint32_t x[R];
+            box_coord<R>(h, D.order, kd, fd >= 0 ? lo_d + ed : ed, x);
+            bool in = true;
+#pragma unroll
+            for (uint32_t d = 0; d < R; d++)
+                if (d < r) {
+                    const int64_t b = o[d] + int64_t(x[d]);
+                    in = in && b >= 0 && b < int64_t(h.box[d]);
+                }
+            if (!in) {
+                // a hole or tail lane of a full copy into a Morton destination
+                m.x = full && !preserve ? kMapHole : kMapSkip;
+            } else {
+                uint32_t ks, es;
+                box_run<R>(h, S.order, x, ks, es);
+                if (fs >= 0)
+                    es -= lo_s;
+                const uint64_t ss = tab_s[ks];
+                if (S.mode == kFieldMajor) {
+                    m.x = ks;
+                    m.y = es;
+                    m.z = uint32_t(ss);
+                } else if (S.order == kOrderOne) {
+                    m.x = S.lds_base + (uint32_t(S.blob) & 15u);
+                    m.y = 0;
+                } else {
+                    const uint64_t i = ss + es, b0 = ss >> S.log2_lanes;
+                    m.x = S.lds_base + ks * (S.gran << 4) +
+                          ((uint32_t(S.blob) + uint32_t(b0) * uint32_t(S.block)) & 15u) +
+                          uint32_t((i >> S.log2_lanes) - b0) * uint32_t(S.block);
+                    m.y = uint32_t(i & ((uint64_t(1) << S.log2_lanes) - 1u));
+                }
+            }
         }
+        map[j] = m;
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
-    // ---- destination records, in the destination's order
-    const uint32_t wlog = D.run_log2, wmask = (1u << wlog) - 1u;
-    if constexpr (kStaged) {
-        // AoS destination: whole records into the destination region
-        for (uint32_t j = tid; j < Q; j += nthr) {
-            const uint32_t kd = j >> wlog, ed = j & wmask;
-            const uint64_t sd = tab_d[kd];
-            if (ed >= box_run_len(D, Q, sd, len_d))
+    // ---- every (entry, record) pair; the lanes of a wave hold consecutive
+    //      records of one entry, whose fields then load as scalars
+    const uint32_t E = h.num_entries;
+    const uint64_t lmask = (uint64_t(1) << D.log2_lanes) - 1u;
+    auto move = [&](const BoxEntry& en, uint32_t rec) {
+        const uint4 m = map[rec];
+        if (m.x == kMapSkip)
+            return;
+        const bool zero = en.gap || m.x == kMapHole;
+        if (zero && preserve)
+            return;
+        uint32_t sp = 0;
+        if (!zero)
+            sp = S.mode == kFieldMajor
+                     ? S.lds_base + en.src_off + m.x * (en.gran << 4) +
+                           ((uint32_t(en.src_addr) + m.z * en.size) & 15u) + m.y * en.size
+                     : m.x + en.src_off + m.y * en.size;
+        if constexpr (kStaged) {
+            if (zero) {
+                for (uint32_t b = 0; b < en.size; b++)
+                    lds[m.w + en.dst_off + b] = 0;
+            } else {
+                box_move_lds(lds, sp, m.w + en.dst_off, en.size);
+            }
+        } else {
+            const uint64_t i = tab_d[rec >> wlog] + (rec & wmask);
+            uint64_t g;
+            if (en.gap)
+                g = D.blob + i * D.block + en.dst_off; // an AoS destination (lanes 1)
+            else if (D.mode == kFieldMajor)
+                g = en.dst_addr + i * en.size;
+            else
+                g = en.dst_addr + (i >> D.log2_lanes) * D.block + (i & lmask) * en.size;
+            box_store_value<kCount>(lds, sp, g, en.size, zero);
+        }
+    };
+    if (kStaged && (h.flags & kBoxGather)) {
+        // ---- AoS destination of whole words: every granule of every
+        //      destination run assembled word by word, stored at once
+        const uint32_t* wt = (const uint32_t*)(lds + h.wtab);
+        const uint4* lf = (const uint4*)(lds + h.wtab + ((h.words * 4u + 15u) & ~15u));
+        const uint32_t K = uint32_t(D.block);
+        const uint32_t total = Rd * D.gran;
+        for (uint32_t g = tid; g < total; g += nthr) {
+            const uint32_t k = __umulhi(g, D.magic), gi = g - k * D.gran;
+            const uint64_t st = tab_d[k];
+            const uint32_t w = box_run_len(D, Q, st, len_d);
+            if (w == 0)
                 continue;
-            uint32_t x[LLAMA_MAX_RANK];
-            box_coord(h, D.order, kd, fd >= 0 ? lo_d + ed : ed, x);
-            bool in = true;
+            const uint64_t g0 = D.blob + st * D.block;
+            const uint32_t shift = uint32_t(g0) & 15u, end = shift + w * K;
+            if (gi * 16u >= end)
+                continue;
+            uint32_t v[4];
 #pragma unroll
-            for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
-                if (d < r) {
-                    const int64_t b = o[d] + int64_t(x[d]);
-                    in = in && b >= 0 && b < int64_t(h.box[d]);
-                }
-            const uint32_t K = uint32_t(D.block);
-            const uint32_t dpos = D.lds_base + kd * D.slot + ((uint32_t(D.blob) + uint32_t(sd) * K) & 15u) + ed * K;
-            if (!in) { // a hole of a full copy into a Morton destination
-                if (!preserve)
-                    for (uint32_t b = 0; b < K; b++)
-                        lds[dpos + b] = 0;
-                continue;
-            }
-            uint32_t ks, es;
-            box_run(h, S.order, x, ks, es);
-            if (fs >= 0)
-                es -= lo_s;
-            const uint64_t ss = tab_s[ks];
-            for (uint32_t f = 0; f < h.num_entries; f++) {
-                const BoxEntry& en = a.e[f];
-                if (en.gap) {
-                    if (!preserve)
-                        for (uint32_t b = 0; b < en.size; b++)
-                            lds[dpos + en.dst_off + b] = 0;
+            for (uint32_t c = 0; c < 4; c++) {
+                v[c] = 0;
+                const int32_t b = int32_t(gi * 16u + 4u * c) - int32_t(shift); // byte of the run's span
+                if (b < 0 || uint32_t(b) >= w * K)
                     continue;
-                }
-                box_move_lds(lds, box_src_pos(S, en, ks, ss, ss + es), dpos + en.dst_off, en.size);
+                const uint32_t rr = __umulhi(uint32_t(b), h.kmagic); // record of the run
+                const uint32_t wi = (uint32_t(b) - rr * K) >> 2;
+                const uint4 m = map[(k << wlog) + rr];
+                const uint32_t e = wt[wi];
+                if (m.x >= kMapHole || (e & 0xFFu) == kBoxWordZero)
+                    continue; // a hole of a full copy, or a gap: zero
+                const uint4 L = lf[e & 0xFFu]; // src_off, size, slot bytes, address low bits
+                const uint32_t sp = S.mode == kFieldMajor
+                                        ? S.lds_base + L.x + m.x * L.z + ((L.w + m.z * L.y) & 15u) + m.y * L.y
+                                        : m.x + L.x + m.y * L.y;
+                v[c] = *(const uint32_t*)(lds + sp + (e >> 8));
+            }
+            const uint64_t ga = (g0 & ~uint64_t(15)) + uint64_t(gi) * 16u;
+            const uint32_t lo = gi == 0 ? shift : 0u, hi = min(16u, end - gi * 16u);
+            if (lo == 0 && hi == 16) {
+                store16<false, kCount>((GLOBAL u32x4*)ga, u32x4{v[0], v[1], v[2], v[3]});
+            } else {
+#pragma unroll
+                for (uint32_t c = 0; c < 4; c++)
+                    if (4u * c >= lo && 4u * c + 4u <= hi)
+                        gput<kCount>(ga + 4u * c, v[c]);
             }
         }
-        __syncthreads();
-        for (uint32_t k = wave; k < Rd; k += nwaves) {
-            const uint64_t start = tab_d[k];
-            const uint32_t w = box_run_len(D, Q, start, len_d);
-            if (w > 0)
-                store_span<false, kCount>(D.blob + start * D.block, uint32_t(w * D.block), D.lds_base + k * D.slot,
-                                          lane, 64, 0, lds);
-        }
+        return;
+    }
+    if (h.qlog_sum >= 6) {
+        // a wave's 64 consecutive pairs lie in one entry: all threads busy
+        for (uint32_t j = tid; j < (E << h.qlog_sum); j += nthr)
+            move(a.e[uniform(j >> h.qlog_sum)], j & (Q - 1u));
     } else {
-        // field-major or AoSoA destination: value by value; the lanes of a
-        // wave hold consecutive records and store the same leaf together
-        const uint64_t lmask = (uint64_t(1) << D.log2_lanes) - 1u;
-        for (uint32_t j = tid; j < Q; j += nthr) {
-            const uint32_t kd = j >> wlog, ed = j & wmask;
-            const uint64_t sd = tab_d[kd];
-            if (ed >= box_run_len(D, Q, sd, len_d))
+        for (uint32_t f = 0; f < E; f++)
+            for (uint32_t rec = tid; rec < Q; rec += nthr)
+                move(a.e[f], rec);
+    }
+
+    if constexpr (kStaged) {
+        // ---- destination runs: exact byte spans, granule by granule
+        __syncthreads();
+        const uint32_t total = Rd * D.gran;
+        for (uint32_t g = tid; g < total; g += nthr) {
+            const uint32_t k = __umulhi(g, D.magic), gi = g - k * D.gran;
+            const uint64_t st = tab_d[k];
+            const uint32_t w = box_run_len(D, Q, st, len_d);
+            if (w == 0)
                 continue;
-            const uint64_t i = sd + ed;
-            const uint64_t gi = D.mode == kFieldMajor ? i : (i >> D.log2_lanes) * D.block;
-            const uint64_t li = D.mode == kFieldMajor ? 0 : (i & lmask);
-            uint32_t x[LLAMA_MAX_RANK];
-            box_coord(h, D.order, kd, fd >= 0 ? lo_d + ed : ed, x);
-            bool in = true;
-#pragma unroll
-            for (uint32_t d = 0; d < LLAMA_MAX_RANK; d++)
-                if (d < r) {
-                    const int64_t b = o[d] + int64_t(x[d]);
-                    in = in && b >= 0 && b < int64_t(h.box[d]);
-                }
-            if (!in) { // a hole or tail lane of a full copy into a Morton destination
-                if (full && !preserve)
-                    for (uint32_t f = 0; f < h.num_entries; f++) {
-                        const BoxEntry& en = a.e[f];
-                        const uint64_t g = en.gap ? D.blob + gi + en.dst_off
-                                                  : en.dst_addr + (D.mode == kFieldMajor ? gi * en.size
-                                                                                         : gi + li * en.size);
-                        box_store_value<kCount>(lds, 0, g, en.size, true);
-                    }
+            const uint64_t g0 = D.blob + st * D.block;
+            const uint32_t shift = uint32_t(g0) & 15u, end = shift + w * uint32_t(D.block);
+            if (gi * 16u >= end)
                 continue;
-            }
-            uint32_t ks, es;
-            box_run(h, S.order, x, ks, es);
-            if (fs >= 0)
-                es -= lo_s;
-            const uint64_t ss = tab_s[ks];
-            for (uint32_t f = 0; f < h.num_entries; f++) {
-                const BoxEntry& en = a.e[f];
-                if (en.gap) { // an AoS destination's alignment gap (lanes 1: gi is the record's byte)
-                    if (!preserve)
-                        box_store_value<kCount>(lds, 0, D.blob + gi + en.dst_off, en.size, true);
-                    continue;
-                }
-                const uint64_t g = en.dst_addr + (D.mode == kFieldMajor ? gi * en.size : gi + li * en.size);
-                box_store_value<kCount>(lds, box_src_pos(S, en, ks, ss, ss + es), g, en.size, false);
+            const uint32_t lo = gi == 0 ? shift : 0u, hi = min(16u, end - gi * 16u);
+            const uint8_t* lp = lds + D.lds_base + g * 16u;
+            const uint64_t ga = (g0 & ~uint64_t(15)) + uint64_t(gi) * 16u;
+            if (lo == 0 && hi == 16) {
+                store16<false, kCount>((GLOBAL u32x4*)ga, *(const u32x4*)lp);
+            } else {
+                for (uint32_t b = lo; b < hi; b++)
+                    gput<kCount>(ga + b, lp[b]);
             }
         }
     }
 }
 
-template <bool kStaged, bool kCount>
+template <int R, bool kStaged, bool kCount>
 __global__ void __launch_bounds__(1024) box_kernel(const BoxArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    if (kStaged && (a.h.flags & kBoxGather)) {
+        // the word table, then per leaf its source fields (src_off, size,
+        // slot bytes, address low bits), read by lanes of different leaves;
+        // the first tile's barriers publish them
+        uint32_t* t = (uint32_t*)(lds + a.h.wtab);
+        for (uint32_t k = threadIdx.x; k < a.h.words; k += blockDim.x)
+            t[k] = a.words[k];
+        uint4* l = (uint4*)(lds + a.h.wtab + ((a.h.words * 4u + 15u) & ~15u));
+        for (uint32_t f = threadIdx.x; f < a.h.num_leaves; f += blockDim.x)
+            l[f] = uint4{a.e[f].src_off, a.e[f].size, a.e[f].gran << 4, uint32_t(a.e[f].src_addr)};
+    }
     const uint64_t nt = a.h.num_units;
     uint64_t t = blockIdx.x, stride = gridDim.x;
     if (!kCount && gridDim.x == nt) { // each XCD one contiguous eighth of the tiles
@@ -1405,7 +1519,7 @@ __global__ void __launch_bounds__(1024) box_kernel(const BoxArgs a)
         stride = nt;
     }
     for (; t < nt; t += stride) {
-        box_body<kStaged, kCount>(a, t, lds);
+        box_body<R, kStaged, kCount>(a, t, lds);
         if (t + stride < nt)
             __syncthreads();
     }
@@ -1495,9 +1609,9 @@ __global__ void __launch_bounds__(1024) box_naive_kernel(const BoxArgs a)
                     cd[d] = a.dst.offset[d] + c;
                 }
             }
-            id = box_linear(a.dst, r, cd);
+            id = box_linear<LLAMA_MAX_RANK>(a.dst, r, cd);
         }
-        const uint64_t is = (!in || a.src.order == kOrderOne) ? 0 : box_linear(a.src, r, cs);
+        const uint64_t is = (!in || a.src.order == kOrderOne) ? 0 : box_linear<LLAMA_MAX_RANK>(a.src, r, cs);
         for (uint32_t f = 0; f < h.num_entries; f++) {
             const BoxEntry& en = a.e[f];
             uint64_t gd;
@@ -1694,6 +1808,18 @@ const void* const kTileCountKernels[kTileModes] = {
     (const void*)tile_count_kernel<kModeDirectLoad>, (const void*)tile_count_kernel<kModeGatherStore>,
     (const void*)tile_count_kernel<kModeGatherOdd>};
 
+// box_kernel<R, staged, counted>: index (R == 8) * 4 + staged * 2 + counted
+const void* const kBoxKernels[8] = {
+    (const void*)box_kernel<4, false, false>, (const void*)box_kernel<4, false, true>,
+    (const void*)box_kernel<4, true, false>,  (const void*)box_kernel<4, true, true>,
+    (const void*)box_kernel<8, false, false>, (const void*)box_kernel<8, false, true>,
+    (const void*)box_kernel<8, true, false>,  (const void*)box_kernel<8, true, true>};
+
+const void* box_kernel_for(const BoxArgs& b, bool counted)
+{
+    return kBoxKernels[(b.h.rank > 4 ? 4 : 0) + ((b.h.flags & kBoxStaged) ? 2 : 0) + (counted ? 1 : 0)];
+}
+
 bool g_attr_set = false;
 
 void set_attributes()
@@ -1706,8 +1832,7 @@ void set_attributes()
     for (const void* k : kTileCountKernels)
         check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes)),
                   "hipFuncSetAttribute(tile_count_kernel)");
-    for (const void* k : {(const void*)box_kernel<false, false>, (const void*)box_kernel<true, false>,
-                          (const void*)box_kernel<false, true>, (const void*)box_kernel<true, true>})
+    for (const void* k : kBoxKernels)
         check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes)),
                   "hipFuncSetAttribute(box_kernel)");
     for (const void* k : {(const void*)batch_kernel<false>, (const void*)batch_kernel<true>,
@@ -1789,9 +1914,7 @@ void launch(const Plan& p, void* stream_ptr)
         } else if (p.path == LLAMA_PATH_BOX) {
             set_attributes();
             args[0] = (void*)&p.box;
-            k = p.box_naive ? (const void*)box_naive_kernel<true>
-                : (p.box.h.flags & kBoxStaged) ? (const void*)box_kernel<true, true>
-                                               : (const void*)box_kernel<false, true>;
+            k = p.box_naive ? (const void*)box_naive_kernel<true> : box_kernel_for(p.box, true);
             lds = p.box_naive ? 0 : p.box.h.lds_bytes;
         } else {
             fail(LLAMA_E_INVALID_ARG, "unknown path");
@@ -1832,8 +1955,7 @@ void launch(const Plan& p, void* stream_ptr)
             break;
         }
         set_attributes();
-        const void* k = (p.box.h.flags & kBoxStaged) ? (const void*)box_kernel<true, false>
-                                                     : (const void*)box_kernel<false, false>;
+        const void* k = box_kernel_for(p.box, false);
         void* args[] = {(void*)&p.box};
         check_hip(hipLaunchKernel(k, dim3(grid), dim3(p.threads), args, p.box.h.lds_bytes, stream),
                   "hipLaunchKernel(box_kernel)");

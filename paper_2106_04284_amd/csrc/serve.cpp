@@ -101,6 +101,7 @@ struct Slot {
     hipStream_t stream = nullptr; // one of the server's streams
     uint32_t stream_index = 0;
     hipEvent_t done = nullptr;
+    hipEvent_t uploaded = nullptr; // BATCHED: the work table's upload has finished
     void* dev = nullptr;
     size_t dev_cap = 0;
     void* host = nullptr; // pinned
@@ -130,6 +131,7 @@ struct Server {
     llama_executor exec{};
     uint64_t launch_counter = 0;
     std::vector<hipStream_t> streams;
+    hipStream_t upload = nullptr; // BATCHED: work-table uploads, off the launch streams
     std::vector<Slot> slots;
     // per stream: busy slots in launch order (they finish in that order),
     // free slots, and the bytes of the launches in flight
@@ -227,7 +229,12 @@ void Server::launch_slot(Slot& s, std::vector<Pending>& group)
             ensure_capacity(s, bytes);
             BatchArgs args{};
             t.serialise((uint8_t*)s.host, uint64_t(uintptr_t(s.dev)), args);
-            check_hip(hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice, s.stream), "hipMemcpyAsync(table)");
+            // the upload runs on its own stream, so that it overlaps the
+            // launches already queued on the slot's stream; the launch waits
+            // for it (the slot's table is reused only after its launch ends)
+            check_hip(hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice, upload), "hipMemcpyAsync(table)");
+            check_hip(hipEventRecord(s.uploaded, upload), "hipEventRecord(upload)");
+            check_hip(hipStreamWaitEvent(s.stream, s.uploaded, 0), "hipStreamWaitEvent(upload)");
             const uint32_t w = batch_per_unit(t) ? 0 : batch_wg_per_cu(t.lds_bytes, cfg.threads);
             launch_batch_args(args, batch_grid(t.units, w), cfg.threads, t.lds_bytes, w != 0, s.stream);
         }
@@ -477,6 +484,9 @@ Server* create_server(const llama_server_config* cfg, const llama_executor* exec
             check_hip(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming), "hipEventCreate");
         }
         if (c.policy == LLAMA_SERVE_BATCHED) {
+            check_hip(hipStreamCreateWithFlags(&s->upload, hipStreamNonBlocking), "hipStreamCreate(upload)");
+            for (Slot& sl : s->slots)
+                check_hip(hipEventCreateWithFlags(&sl.uploaded, hipEventDisableTiming), "hipEventCreate");
             const size_t n = s->slots.size();
             check_hip(hipMalloc(&s->table_dev, n * kSlotTableBytes), "hipMalloc(server tables)");
             check_hip(hipHostMalloc(&s->table_host, n * kSlotTableBytes, hipHostMallocDefault),
@@ -488,9 +498,14 @@ Server* create_server(const llama_server_config* cfg, const llama_executor* exec
             }
         }
     } catch (...) {
-        for (Slot& sl : s->slots)
+        for (Slot& sl : s->slots) {
             if (sl.done)
                 hipEventDestroy(sl.done);
+            if (sl.uploaded)
+                hipEventDestroy(sl.uploaded);
+        }
+        if (s->upload)
+            hipStreamDestroy(s->upload);
         if (s->table_dev)
             hipFree(s->table_dev);
         if (s->table_host)
@@ -640,6 +655,12 @@ void destroy_server(Server* s)
         if (sl.host && sl.own_host)
             (void)hipHostFree(sl.host);
         (void)hipEventDestroy(sl.done);
+        if (sl.uploaded)
+            (void)hipEventDestroy(sl.uploaded);
+    }
+    if (s->upload) {
+        (void)hipStreamSynchronize(s->upload);
+        (void)hipStreamDestroy(s->upload);
     }
     if (s->table_dev)
         (void)hipFree(s->table_dev);

@@ -201,6 +201,32 @@ def test_split_2e26_sampled(L, orc, pair):
     assert bad == 0, f"{bad} sampled values differ, first sample {first}"
 
 
+def test_copy_leaves_2e26_kept_mass_full(L, orc):
+    """The benchmark's copy into packed AoS that keeps a leaf (the particle's
+    mass has no source): the kept-gap tile path, with streaming loads and
+    stores at this size.  The destination starts as random bytes; every byte
+    must equal the oracle's copy_leaves of the same start (the kept mass
+    included)."""
+    n = 1 << 26
+    no_mass = W.PARTICLE[:2]  # {pos, vel}: the particle without its mass
+    rs_o, rd_o = orc.Record(no_mass), orc.Record(W.PARTICLE)
+    rs, rd = L.Record(no_mass), L.Record(W.PARTICLE)
+    ms_o, md_o = orc.Mapping(rs_o, "soa_multi", [n]), orc.Mapping(rd_o, "aos_packed", [n])
+    ms, md = L.Mapping(rs, "soa_multi", [n]), L.Mapping(rd, "aos_packed", [n])
+    frm = [0, 1, 2, 3, 4, 5, None]
+    src = [_random_blob(s, 3000 + k) for k, s in enumerate(ms.blob_sizes())]
+    dst = [_random_blob(s, 3100 + k) for k, s in enumerate(md.blob_sizes())]
+    start = [t.cpu().numpy() for t in dst]
+    L.copy_leaves(ms, src, md, dst, frm)
+    torch.cuda.synchronize()
+    want = orc.copy_leaves(ms_o, [t.cpu().numpy() for t in src], md_o, start, frm)
+    for j, (got, w) in enumerate(zip(dst, want)):
+        g = got.cpu().numpy()
+        if not np.array_equal(g, w):
+            bad = np.flatnonzero(g != w)
+            raise AssertionError(f"blob {j}: {bad.size} bytes differ, first at {bad[0]}")
+
+
 LBM_LAYOUTS = [("aos_aligned", 0), ("soa_multi", 0), ("aosoa", 32)]
 LBM_PAIRS = [(a, b) for a in LBM_LAYOUTS for b in LBM_LAYOUTS if a != b]
 

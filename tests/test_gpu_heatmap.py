@@ -191,3 +191,21 @@ def test_plan_log(L, tmp_path):
     lines = [x for x in r.stderr.splitlines() if x.startswith("[llama] ")]
     assert len(lines) == 1 and "path=tile" in lines[0] and " mode=" in lines[0], r.stderr[-2000:]
     assert "read=140000 write=140000" in lines[0]
+
+
+def test_plan_log_kept_gap_tile(L):
+    """A copy between differing records into packed AoS with a leaf that
+    keeps its bytes takes the staged tile that loads the destination region
+    and stores it back (the plan log shows it), not the element-wise path."""
+    code = ("import torch; from paper_2106_04284_amd import llama as L, workloads as W\n"
+            "rs = L.Record(W.PARTICLE[:2]); rd = L.Record(W.PARTICLE)\n"
+            "a = L.Mapping(rs, 'soa_multi', [20000]); b = L.Mapping(rd, 'aos_packed', [20000])\n"
+            "L.copy_leaves(a, a.alloc(fill=1), b, b.alloc(fill=0), [0, 1, 2, 3, 4, 5, None])\n"
+            "torch.cuda.synchronize()\n")
+    env = dict(os.environ, LLAMA_TRACE="1")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [x for x in r.stderr.splitlines() if x.startswith("[llama] ")]
+    assert len(lines) == 1, r.stderr[-2000:]
+    assert "path=tile mode=staged" in lines[0] and "keep_padding" in lines[0], lines[0]
+
