@@ -10,8 +10,10 @@ over the 42 copies; every copy reads a 1.879 GB source layout and writes a
 
 Prints one JSON line: whole-job throughput in GB/s (bytes read plus bytes
 written, 1 GB = 1e9 B), the roofline of the dominant kernel (the TILE kernel,
-timed per launch with HIP events on the launch stream), and the CPU oracle
-timed on a bounded sample of the same workload.
+timed per launch with HIP events on the launch stream), the CPU oracle
+timed on a bounded sample of the same workload, and, under
+extras.batch_1000_arrays, the batching workload below (one graph-captured
+launch against 1,000 naive and 1,000 llama_copy launches on the same GPU).
 
 Other workloads (--workload):
   lbm    128^3 cells of 19 f64 + u32, aligned AoS <-> SoA multi-blob <->
@@ -284,9 +286,15 @@ def _layout_maps(L, rec_name, n, src, dst, cache):
     return L.Mapping(rg, src[0], [n], src[1]), L.Mapping(rg, dst[0], [n], dst[1])
 
 
+TUNE_CACHE = None  # --tune-cache: a tuning-cache file read before and written after class tuning
+
+
 def _tune_classes(L, torch, classes, stream):
-    """Autotunes each (record, layout pair) class once at 2^20 records."""
+    """Autotunes each (record, layout pair) class once at 2^20 records (a
+    class already in the tuning cache is kept)."""
     cache, tuned = {}, 0
+    if TUNE_CACHE and os.path.exists(TUNE_CACHE):
+        L.tune_load(TUNE_CACHE)
     for rec_name, src, dst in sorted(classes):
         ms, md = _layout_maps(L, rec_name, 1 << 20, src, dst, cache)
         if L.tune_lookup(ms, md) is not None:
@@ -297,6 +305,8 @@ def _tune_classes(L, torch, classes, stream):
         L.autotune(ms, sb, md, db, stream=stream, reps=2)
         tuned += 1
         del sb, db
+    if TUNE_CACHE:
+        L.tune_save(TUNE_CACHE)
     return tuned
 
 
@@ -335,7 +345,10 @@ def _timed(torch, stream, fn, reps):
     return statistics.median(ms), min(ms)
 
 
-def bench_batch(L, torch, args, dev, stream):
+def batch_measure(L, torch, args, stream, naive=True):
+    """The 1,000-array batch: the default plan, then the batch's autotuner,
+    then (with `naive`) the same arrays as 1,000 naive and as 1,000
+    llama_copy launches.  Returns the figures and releases the arrays."""
     items, total, tuned = _batch_items(L, torch, stream)
 
     def timed(fn, reps):
@@ -345,33 +358,56 @@ def bench_batch(L, torch, args, dev, stream):
     # batch's autotuner choosing LDS budget, threads and grid on these arrays
     b = L.Batch(items)
     heur_med, _ = timed(lambda: b.launch(stream), 3)
-    log(f"batch: default plan {total / (heur_med * 1e-3) / 1e9:.1f} GB/s; autotuning the batch")
-    tuned_gbs = b.autotune(stream=stream, reps=2) if not args.no_batch_autotune else total / (heur_med * 1e-3) / 1e9
-    th = b.info()["threads"]
-    log(f"batch: autotuned {tuned_gbs:.1f} GB/s (threads {th}, lds {b.info()['lds_bytes']})")
-    med, mn = timed(lambda: b.launch(stream), args.steps)
+    heur_gbs = total / (heur_med * 1e-3) / 1e9
+    log(f"batch: default plan {heur_gbs:.1f} GB/s; autotuning the batch")
+    if not args.no_batch_autotune:
+        b.autotune(stream=stream, reps=2)
     info = b.info()
-    log("batch: timing 1,000 per-array naive launches and 1,000 per-array llama_copy launches")
-    naive_med, _ = timed(lambda: [L.copy_naive(i[0], i[1], i[2], i[3], stream=stream) for i in items], 2)
-    lone_med, _ = timed(lambda: [L.copy(i[0], i[1], i[2], i[3], stream=stream) for i in items], 2)
-    gbs = total / (med * 1e-3) / 1e9
-    return {"metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": 1, "ms_per_step": round(med, 3), "higher_is_better": True, "scaling": "weak",
+    log(f"batch: plan of {info['threads']} threads, {info['lds_bytes']} B of LDS")
+    med, mn = timed(lambda: b.launch(stream), args.steps)
+    out = {"bytes": total, "arrays": len(items), "tuned_classes": tuned, "info": info, "ms": med, "ms_min": mn,
+           "gbs": total / (med * 1e-3) / 1e9, "default_gbs": heur_gbs, "default_ms": heur_med}
+    if naive:
+        log("batch: timing 1,000 per-array naive launches and 1,000 per-array llama_copy launches")
+        out["naive_ms"], _ = timed(lambda: [L.copy_naive(i[0], i[1], i[2], i[3], stream=stream) for i in items], 2)
+        out["lone_ms"], _ = timed(lambda: [L.copy(i[0], i[1], i[2], i[3], stream=stream) for i in items], 2)
+    b.close()
+    del items, b
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def batch_extras(m):
+    """The batch figures as they appear in a bench line."""
+    gbs = lambda ms: round(m["bytes"] / (ms * 1e-3) / 1e9, 1)  # noqa: E731
+    ex = {"batched_gbs": round(m["gbs"], 1), "batched_ms": round(m["ms"], 3), "batched_ms_min": round(m["ms_min"], 3),
+          "hbm_peak_frac": round(m["gbs"] / HBM_PEAK_GBS, 4), "default_plan_gbs": round(m["default_gbs"], 1),
+          "autotuned_vs_default": round(m["default_ms"] / m["ms"], 3)}
+    if "naive_ms" in m:
+        ex.update({"naive_per_array_gbs": gbs(m["naive_ms"]), "llama_copy_per_array_gbs": gbs(m["lone_ms"]),
+                   "batched_vs_naive": round(m["naive_ms"] / m["ms"], 2),
+                   "batched_vs_per_array_copy": round(m["lone_ms"] / m["ms"], 2)})
+    return ex
+
+
+BATCH_WORKLOAD = ("batching: 1,000 arrays, record counts log-uniform 1e3..1e7, particle or mixed "
+                  "{f64[3],f32[4],i32[2],u8} record, random ordered layout pair of 42; one hipGraph-captured launch")
+
+
+def bench_batch(L, torch, args, dev, stream):
+    m = batch_measure(L, torch, args, stream, naive=not args.no_naive)
+    info = m["info"]
+    return {"metric": METRIC, "value": round(m["gbs"], 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": 1, "ms_per_step": round(m["ms"], 3), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-            "config": {"workload": "batching: 1,000 arrays, record counts log-uniform 1e3..1e7, particle or mixed "
-                                   "{f64[3],f32[4],i32[2],u8} record, random ordered layout pair of 42; one "
-                                   "hipGraph-captured launch",
-                       "bytes_per_step": total, "arrays": len(items), "threads": th, "work_units": info["work_units"],
-                       "workgroups": info["workgroups"], "wg_per_cu": info["wg_per_cu"],
-                       "lds_bytes": info["lds_bytes"], "tuned_classes": tuned},
-            "hbm_peak_frac": round(gbs / HBM_PEAK_GBS, 4),
-            "extras": {"batched_ms_min": round(mn, 3),
-                       "default_plan_gbs": round(total / (heur_med * 1e-3) / 1e9, 1),
-                       "autotuned_vs_default": round(heur_med / med, 3),
-                       "naive_per_array_gbs": round(total / (naive_med * 1e-3) / 1e9, 1),
-                       "llama_copy_per_array_gbs": round(total / (lone_med * 1e-3) / 1e9, 1),
-                       "batched_vs_naive": round(naive_med / med, 2),
-                       "batched_vs_per_array_copy": round(lone_med / med, 2)},
+            "config": {"workload": BATCH_WORKLOAD,
+                       "bytes_per_step": m["bytes"], "arrays": m["arrays"], "threads": info["threads"],
+                       "work_units": info["work_units"], "workgroups": info["workgroups"],
+                       "wg_per_cu": info["wg_per_cu"], "lds_bytes": info["lds_bytes"],
+                       "tuned_classes": m["tuned_classes"]},
+            "hbm_peak_frac": round(m["gbs"] / HBM_PEAK_GBS, 4),
+            "extras": batch_extras(m),
             "device": dev.name}
 
 
@@ -804,8 +840,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-naive", action="store_true")
     ap.add_argument("--no-batch-autotune", action="store_true", help="batch: keep the default plan")
+    ap.add_argument("--no-batch", action="store_true", help="particle: leave out the 1,000-array batch extras")
+    ap.add_argument("--tune-cache", default=None, help="tuning-cache file: read before class tuning, written after")
     ap.add_argument("--details", default=None, help="write per-pair results to this JSON file")
     args = ap.parse_args()
+    global TUNE_CACHE
+    TUNE_CACHE = args.tune_cache
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the layout copy shards by record range with no exchange between "
@@ -927,6 +967,16 @@ def main():
         ours = statistics.median(per_pair[p]["gbs_median"] for p in naive_pairs)
         extras["naive_kernel_gbs"] = round(statistics.median(nv.values()), 1)
         extras["tile_vs_naive_speedup"] = round(ours / statistics.median(nv.values()), 2)
+
+    if args.workload == "particle" and not args.no_batch:
+        # the batching workload (1,000 arrays, one graph-captured launch)
+        # against per-array naive and llama_copy launches, on the same GPU
+        del blobs
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        bm = batch_measure(L, torch, args, stream, naive=not args.no_naive)
+        extras["batch_1000_arrays"] = {"workload": BATCH_WORKLOAD, "bytes_per_launch": bm["bytes"], **batch_extras(bm)}
+        log(f"batch: {bm['gbs']:.1f} GB/s")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -450,16 +450,40 @@ typedef struct {
                                size of the Infinity Cache); bit 1 (LLAMA_HINT_STREAM_STORES) when
                                the destination's 16-byte stores do (TILE, destinations of 1 GiB or
                                more) */
+    uint32_t plan_flags;    /* TILE: LLAMA_PLAN_* bits */
+    uint32_t source_chunks; /* TILE with LLAMA_PLAN_GATHERED_SOURCE: chunks of one virtual source block */
 } llama_plan_info;
 
 #define LLAMA_HINT_STREAM_LOADS 1u
 #define LLAMA_HINT_STREAM_STORES 2u
+
+/* llama_plan_info.plan_flags */
+/* The tile's source is gathered from several parts of a Split source (sec.
+ * 3.7): every tile loads the records' chunks from each part (a whole AoSoA
+ * or AoS block, or the values of one SoA leaf) into one staged region, so a
+ * destination part fed by several source parts is written by one copy. */
+#define LLAMA_PLAN_GATHERED_SOURCE 1u
+/* The tile loads each destination region and stores it back whole: the
+ * bytes it does not own (kept padding, leaves without a source, leaves that
+ * another part copy writes) keep their values but are written again, so
+ * nothing else may write that destination while the copy runs. */
+#define LLAMA_PLAN_KEEPS_DESTINATION 2u
 
 /* What a copy of this pair with these options would launch, without blobs:
  * the plan assumes distinct blobs aligned to 256 bytes (a real copy plans for
  * its actual blob addresses, which can change alignment-dependent choices). */
 int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, const llama_copy_options* options,
                llama_plan_info* info);
+
+/* Every launch that llama_copy_ex (src_leaf NULL) or llama_copy_leaves
+ * (src_leaf: its leaf map) would enqueue for this pair with these options, in
+ * order, without blobs (distinct blobs aligned to 256 bytes are assumed, as
+ * by llama_plan): a copy with a Split side lists its part copies, a box copy
+ * its box launch and tail fill.  infos[0 .. *count - 1] receive the plans;
+ * more launches than `capacity` fail with LLAMA_E_INVALID_ARG (*count 0).
+ * Errors as the copy itself would report them for its descriptors. */
+int llama_plan_copy(const llama_mapping_desc* src, const llama_mapping_desc* dst, const uint32_t* src_leaf,
+                    const llama_copy_options* options, llama_plan_info* infos, uint32_t capacity, uint32_t* count);
 
 /* ------------------------------------------------------------------------ */
 /* Autotuning                                                               */

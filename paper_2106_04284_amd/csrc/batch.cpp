@@ -155,6 +155,8 @@ void BatchTable::add_plan(const Plan& p)
         }
     classes |= 1u << cls;
     BatchItem it{};
+    if (p.path == LLAMA_PATH_TILE && (p.tile.h.flags & kTileVirtualSrc))
+        fail(LLAMA_E_UNSUPPORTED, "a source gathered from several parts runs as its own copy");
     if (p.path == LLAMA_PATH_TILE) {
         it.kind = kItemTile;
         it.count = p.tile.h.num_entries;

@@ -150,6 +150,44 @@ int llama_mapping_offset(const llama_mapping_desc* mapping, const uint64_t* coor
     });
 }
 
+namespace {
+
+void fill_info(const Plan& p, llama_plan_info* info)
+{
+    std::memset(info, 0, sizeof(*info));
+    info->path = p.path;
+    info->threads = p.threads;
+    info->tile_records = p.path == LLAMA_PATH_TILE  ? (1u << p.tile.h.log2_tile)
+                         : p.path == LLAMA_PATH_BOX ? (1u << p.box.h.qlog_sum)
+                                                    : 0;
+    info->lds_bytes = p.lds_bytes;
+    info->workgroups = p.workgroups;
+    info->runs = p.path == LLAMA_PATH_STREAM ? p.stream.num_runs : 0;
+    info->wg_per_cu = p.wg_per_cu;
+    info->tiles = p.tiles;
+    info->read_bytes = p.read_bytes;
+    info->write_bytes = p.write_bytes;
+    info->tile_mode = 0;
+    info->cache_hints = 0;
+    info->plan_flags = 0;
+    if (p.path == LLAMA_PATH_TILE) {
+        const uint32_t f = p.tile.h.flags;
+        info->tile_mode = (f & kTileDirectStore)   ? LLAMA_TILE_DIRECT_STORE
+                          : (f & kTileDirectLoad)  ? LLAMA_TILE_DIRECT_LOAD
+                          : (f & kTileGatherStore) ? LLAMA_TILE_GATHER_STORE
+                                                   : LLAMA_TILE_STAGED;
+        info->cache_hints = ((f & kTileStreamLoads) ? LLAMA_HINT_STREAM_LOADS : 0u) |
+                            ((f & kTileStreamStores) ? LLAMA_HINT_STREAM_STORES : 0u);
+        info->plan_flags = ((f & kTileVirtualSrc) ? LLAMA_PLAN_GATHERED_SOURCE : 0u) |
+                           ((f & kTilePreserve) ? LLAMA_PLAN_KEEPS_DESTINATION : 0u);
+        info->source_chunks = (f & kTileVirtualSrc) ? p.tile.h.slots : 0u;
+    } else if (p.path == LLAMA_PATH_STREAM) {
+        info->cache_hints = (p.stream.flags & kStreamLoadsOnce) ? LLAMA_HINT_STREAM_LOADS : 0u;
+    }
+}
+
+} // namespace
+
 int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, const llama_copy_options* options,
                llama_plan_info* info)
 {
@@ -165,115 +203,97 @@ int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, con
         } else {
             p = make_plan(rq, options);
         }
-        std::memset(info, 0, sizeof(*info));
-        info->path = p.path;
-        info->threads = p.threads;
-        info->tile_records = p.path == LLAMA_PATH_TILE  ? (1u << p.tile.h.log2_tile)
-                             : p.path == LLAMA_PATH_BOX ? (1u << p.box.h.qlog_sum)
-                                                        : 0;
-        info->lds_bytes = p.lds_bytes;
-        info->workgroups = p.workgroups;
-        info->runs = p.path == LLAMA_PATH_STREAM ? p.stream.num_runs : 0;
-        info->wg_per_cu = p.wg_per_cu;
-        info->tiles = p.tiles;
-        info->read_bytes = p.read_bytes;
-        info->write_bytes = p.write_bytes;
-        info->tile_mode = 0;
-        info->cache_hints = 0;
-        if (p.path == LLAMA_PATH_TILE) {
-            const uint32_t f = p.tile.h.flags;
-            info->tile_mode = (f & kTileDirectStore)   ? LLAMA_TILE_DIRECT_STORE
-                              : (f & kTileDirectLoad)  ? LLAMA_TILE_DIRECT_LOAD
-                              : (f & kTileGatherStore) ? LLAMA_TILE_GATHER_STORE
-                                                       : LLAMA_TILE_STAGED;
-            info->cache_hints = ((f & kTileStreamLoads) ? LLAMA_HINT_STREAM_LOADS : 0u) |
-                                ((f & kTileStreamStores) ? LLAMA_HINT_STREAM_STORES : 0u);
-        } else if (p.path == LLAMA_PATH_STREAM) {
-            info->cache_hints = (p.stream.flags & kStreamLoadsOnce) ? LLAMA_HINT_STREAM_LOADS : 0u;
-        }
+        fill_info(p, info);
     });
 }
 
 namespace {
 
+// The launches of llama_copy_ex, in order (without `need_blobs`: plans only,
+// for distinct blobs aligned to 256 bytes).
+std::vector<Plan> copy_plans(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                             const llama_blob* dst_blobs, const llama_copy_options* options, bool need_blobs)
+{
+    Request rq = make_request(src, src_blobs, dst, dst_blobs, need_blobs, true);
+    if (needs_box(rq)) {
+        // records at different linear indices: the whole extents as one box
+        if (src->kind == LLAMA_SPLIT || dst->kind == LLAMA_SPLIT)
+            fail(LLAMA_E_UNSUPPORTED, "Split copies take views with equal linear indices");
+        const uint64_t zero[LLAMA_MAX_RANK] = {};
+        return make_box_plans(rq, zero, zero, rq.dst.extents, true, options);
+    }
+    if (src->kind != LLAMA_SPLIT && dst->kind != LLAMA_SPLIT)
+        return {make_plan(rq, options)};
+    // a Split side: one copy per destination part and source part sharing
+    // leaves (or one from every source part feeding a destination part), in
+    // order on the stream; every plan is made before the first launch
+    std::vector<Plan> plans;
+    for (const SubCopy& c : split_copies(src, dst, rq, true, options)) {
+        if (c.gathered) {
+            // one tile copy from every source part feeding this destination part
+            plans.push_back(*c.plan);
+            continue;
+        }
+        if (c.naive && c.rq.dst.lanes == 1 && c.rq.dst.gaps.empty() && c.rq.dst.npad == c.rq.dst.n) {
+            // into AoS records another part copy has already written
+            // whole: a staged tile that keeps every byte outside these
+            // leaves (taken as gaps) by storing each loaded region back
+            Request kept = c.rq;
+            std::vector<std::pair<uint64_t, uint64_t>> cover;
+            for (size_t k = 0; k < kept.record.leaves.size(); k++)
+                cover.push_back({kept.dst.base[k], kept.record.leaves[k].size});
+            std::sort(cover.begin(), cover.end());
+            uint64_t cur = 0;
+            for (const auto& cv : cover) {
+                if (cv.first > cur)
+                    kept.dst.gaps.push_back({cur, cv.first - cur});
+                cur = std::max(cur, cv.first + cv.second);
+            }
+            if (kept.dst.block > cur)
+                kept.dst.gaps.push_back({cur, kept.dst.block - cur});
+            kept.dst.partial = false;
+            llama_copy_options o = options ? *options : llama_copy_options{0, 0, 0, 0, 0};
+            o.flags |= LLAMA_COPY_PRESERVE_PADDING;
+            bool planned = false;
+            try {
+                plans.push_back(make_plan(kept, &o));
+                planned = true;
+            } catch (const Error&) {
+                // too many gap entries: element-wise below
+            }
+            if (planned)
+                continue;
+        }
+        if (c.naive) {
+            // a tile plan that stores 16-byte granules of its own leaves
+            // straight from the staged source (direct store, no padding
+            // gaps) writes no other byte of the part's blocks either
+            try {
+                Plan t = make_plan(c.rq, options);
+                if (t.path == LLAMA_PATH_TILE && (t.tile.h.flags & kTileDirectStore) && c.rq.dst.gaps.empty()) {
+                    plans.push_back(t);
+                    continue;
+                }
+            } catch (const Error&) {
+                // the caller's path or tile size does not fit this part copy
+            }
+            llama_copy_options o = options ? *options : llama_copy_options{0, 0, 0, 0, 0};
+            o.path = LLAMA_PATH_NAIVE;
+            o.tile_records = 0;
+            plans.push_back(make_plan(c.rq, &o));
+        } else {
+            plans.push_back(make_plan(c.rq, options));
+        }
+    }
+    return plans;
+}
+
 // llama_copy_ex's body (also run under the Heatmap's counting)
 void copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
              const llama_blob* dst_blobs, const llama_copy_options* options, void* stream)
 {
-    {
-        Request rq = make_request(src, src_blobs, dst, dst_blobs, true, true);
-        if (needs_box(rq)) {
-            // records at different linear indices: the whole extents as one box
-            if (src->kind == LLAMA_SPLIT || dst->kind == LLAMA_SPLIT)
-                fail(LLAMA_E_UNSUPPORTED, "Split copies take views with equal linear indices");
-            const uint64_t zero[LLAMA_MAX_RANK] = {};
-            for (const Plan& p : make_box_plans(rq, zero, zero, rq.dst.extents, true, options))
-                launch(p, stream);
-            return;
-        }
-        if (src->kind != LLAMA_SPLIT && dst->kind != LLAMA_SPLIT) {
-            Plan p = make_plan(rq, options);
-            launch(p, stream);
-            return;
-        }
-        // a Split side: one copy per pair of parts sharing leaves, in order
-        // on the stream; every plan is made before the first launch
-        std::vector<Plan> plans;
-        for (const SubCopy& c : split_copies(src, dst, rq)) {
-            if (c.naive && c.rq.dst.lanes == 1 && c.rq.dst.gaps.empty() && c.rq.dst.npad == c.rq.dst.n) {
-                // into AoS records another part copy has already written
-                // whole: a staged tile that keeps every byte outside these
-                // leaves (taken as gaps) by storing each loaded region back
-                Request kept = c.rq;
-                std::vector<std::pair<uint64_t, uint64_t>> cover;
-                for (size_t k = 0; k < kept.record.leaves.size(); k++)
-                    cover.push_back({kept.dst.base[k], kept.record.leaves[k].size});
-                std::sort(cover.begin(), cover.end());
-                uint64_t cur = 0;
-                for (const auto& cv : cover) {
-                    if (cv.first > cur)
-                        kept.dst.gaps.push_back({cur, cv.first - cur});
-                    cur = std::max(cur, cv.first + cv.second);
-                }
-                if (kept.dst.block > cur)
-                    kept.dst.gaps.push_back({cur, kept.dst.block - cur});
-                kept.dst.partial = false;
-                llama_copy_options o = options ? *options : llama_copy_options{0, 0, 0, 0, 0};
-                o.flags |= LLAMA_COPY_PRESERVE_PADDING;
-                bool planned = false;
-                try {
-                    plans.push_back(make_plan(kept, &o));
-                    planned = true;
-                } catch (const Error&) {
-                    // too many gap entries: element-wise below
-                }
-                if (planned)
-                    continue;
-            }
-            if (c.naive) {
-                // a tile plan that stores 16-byte granules of its own leaves
-                // straight from the staged source (direct store, no padding
-                // gaps) writes no other byte of the part's blocks either
-                try {
-                    Plan t = make_plan(c.rq, options);
-                    if (t.path == LLAMA_PATH_TILE && (t.tile.h.flags & kTileDirectStore) && c.rq.dst.gaps.empty()) {
-                        plans.push_back(t);
-                        continue;
-                    }
-                } catch (const Error&) {
-                    // the caller's path or tile size does not fit this part copy
-                }
-                llama_copy_options o = options ? *options : llama_copy_options{0, 0, 0, 0, 0};
-                o.path = LLAMA_PATH_NAIVE;
-                o.tile_records = 0;
-                plans.push_back(make_plan(c.rq, &o));
-            } else {
-                plans.push_back(make_plan(c.rq, options));
-            }
-        }
-        for (const Plan& p : plans)
-            launch(p, stream);
-    }
+    for (const Plan& p : copy_plans(src, src_blobs, dst, dst_blobs, options, true))
+        launch(p, stream);
 }
 
 // the blob sizes a mapping needs
@@ -303,6 +323,25 @@ void add_counted(CountBlob* list, uint32_t& n, const llama_mapping_desc* m, cons
 }
 
 } // namespace
+
+int llama_plan_copy(const llama_mapping_desc* src, const llama_mapping_desc* dst, const uint32_t* src_leaf,
+                    const llama_copy_options* options, llama_plan_info* infos, uint32_t capacity, uint32_t* count)
+{
+    return guarded([&] {
+        need(count, "count");
+        *count = 0;
+        const std::vector<Plan> plans = src_leaf ? leaves_plans(src, nullptr, dst, nullptr, src_leaf, options, false)
+                                                 : copy_plans(src, nullptr, dst, nullptr, options, false);
+        if (plans.size() > capacity)
+            fail(LLAMA_E_INVALID_ARG, "the copy makes " + std::to_string(plans.size()) + " launches, capacity is " +
+                                          std::to_string(capacity));
+        if (!plans.empty())
+            need(infos, "infos");
+        for (size_t k = 0; k < plans.size(); k++)
+            fill_info(plans[k], &infos[k]);
+        *count = uint32_t(plans.size());
+    });
+}
 
 int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
                   const llama_blob* dst_blobs, const llama_copy_options* options, void* stream)

@@ -455,6 +455,13 @@ Request make_request(const llama_mapping_desc* src, const llama_blob* src_blobs,
 
 namespace {
 
+// lanes as far as the copy can tell: a side whose single block holds every
+// record behaves as unblocked
+uint64_t effective_lanes(const Side& s)
+{
+    return (s.lanes == 0 || s.lanes >= s.n) ? 0 : s.lanes;
+}
+
 // the side of part `p` that holds only leaves `pick` (a subset of p.leaves,
 // both in leaf order)
 Side restrict_side(const Part& p, const std::vector<uint32_t>& pick)
@@ -473,9 +480,125 @@ Side restrict_side(const Part& p, const std::vector<uint32_t>& pick)
     return s;
 }
 
+using PartLeaves = std::vector<std::pair<const Part*, std::vector<uint32_t>>>;
+
+// One copy into destination part P from all the source parts that feed it
+// (`from`, each with the leaves it gives).  When every source part is
+// field-major (SoA), the source is one plain field-major side over their
+// blobs, planned like any copy.  When the record-major source parts share
+// one lane count L, the source is a side of virtual blocks of L records,
+// each assembled from the parts' chunks (a whole part block, or L values of
+// an SoA leaf), which only the tile kernel reads (kTileVirtualSrc); chunks
+// must be whole 16-byte granules at 16-byte aligned addresses.  Returns false
+// (and the part copies run one source part at a time) when neither applies
+// or no plan fits `opt`.
+bool gathered_copy(const PartLeaves& from, const Part& P, const Request& whole, const llama_copy_options* opt,
+                   SubCopy& out)
+{
+    Request rq;
+    rq.record = sub_record(whole.record, P.leaves);
+    rq.dst = restrict_side(P, P.leaves);
+    rq.dst_ptr.assign(whole.dst_ptr.begin() + P.first_blob,
+                      whole.dst_ptr.begin() + P.first_blob + P.side.blob_size.size());
+    uint64_t L = 0;
+    for (const auto& fq : from) {
+        if (fq.first->side.kind == LLAMA_ONE)
+            return false; // a broadcast part: element-wise only
+        const uint64_t l = effective_lanes(fq.first->side);
+        if (l != 0 && L != 0 && l != L)
+            return false;
+        if (l != 0)
+            L = l;
+    }
+    const size_t F = P.leaves.size();
+    std::vector<uint32_t> blob_of(whole.record.leaves.size(), 0);
+    std::vector<uint64_t> base_of(whole.record.leaves.size(), 0);
+    Side s = from[0].first->side;
+    s.partial = false;
+    s.gaps.clear();
+    s.leaf_lanes.clear();
+    s.leaf_block.clear();
+    s.blob_size.clear();
+    if (L == 0) {
+        // every part field-major: their leaf spans as one SoA side
+        s.kind = LLAMA_SOA_MULTI;
+        s.lanes = 0;
+        s.block = 0;
+        s.npad = s.n;
+        for (const auto& fq : from) {
+            const Part& Q = *fq.first;
+            for (uint32_t f : fq.second) {
+                const size_t k = size_t(std::find(Q.leaves.begin(), Q.leaves.end(), f) - Q.leaves.begin());
+                blob_of[f] = uint32_t(rq.src_ptr.size());
+                base_of[f] = Q.side.base[k];
+                rq.src_ptr.push_back(whole.src_ptr[Q.first_blob + Q.side.blob[k]]);
+                s.blob_size.push_back(Q.side.blob_size[Q.side.blob[k]]);
+            }
+        }
+    } else {
+        uint64_t off = 0;
+        for (const auto& fq : from) {
+            const Part& Q = *fq.first;
+            if (effective_lanes(Q.side) != 0) {
+                // a record-major part: its whole block (one blob)
+                const uint64_t addr = whole.src_ptr[Q.first_blob];
+                if (Q.side.block % 16 != 0 || addr % 16 != 0 || Q.side.block > UINT32_MAX)
+                    return false;
+                rq.chunks.push_back(SrcChunk{addr, Q.side.block, uint32_t(off), uint32_t(Q.side.block), 0});
+                s.blob_size.push_back(Q.side.blob_size[0]);
+                for (uint32_t f : fq.second) {
+                    const size_t k = size_t(std::find(Q.leaves.begin(), Q.leaves.end(), f) - Q.leaves.begin());
+                    base_of[f] = off + Q.side.base[k];
+                }
+                off += Q.side.block;
+            } else {
+                // a field-major part: L values of each leaf
+                for (uint32_t f : fq.second) {
+                    const size_t k = size_t(std::find(Q.leaves.begin(), Q.leaves.end(), f) - Q.leaves.begin());
+                    const uint32_t size = whole.record.leaves[f].size;
+                    const uint64_t addr = whole.src_ptr[Q.first_blob + Q.side.blob[k]] + Q.side.base[k];
+                    const uint64_t bytes = L * size;
+                    if (bytes % 16 != 0 || addr % 16 != 0 || bytes > UINT32_MAX)
+                        return false;
+                    rq.chunks.push_back(SrcChunk{addr, bytes, uint32_t(off), uint32_t(bytes), size});
+                    s.blob_size.push_back(Q.side.n * size);
+                    base_of[f] = off;
+                    off += bytes;
+                }
+            }
+            if (off > UINT32_MAX || rq.chunks.size() > size_t(kTileMaxChunks))
+                return false;
+        }
+        s.kind = LLAMA_AOSOA;
+        s.lanes = L;
+        s.block = off;
+        s.npad = (s.n + L - 1) / L * L;
+        rq.src_ptr.assign(1, 0);
+    }
+    s.blob.assign(F, 0);
+    s.base.assign(F, 0);
+    for (size_t j = 0; j < F; j++) {
+        s.blob[j] = blob_of[P.leaves[j]];
+        s.base[j] = base_of[P.leaves[j]];
+    }
+    rq.src = s;
+    try {
+        if (!rq.chunks.empty() && opt && opt->path != LLAMA_PATH_AUTO && opt->path != LLAMA_PATH_TILE)
+            return false;
+        out.plan = std::make_shared<Plan>(make_plan(rq, opt));
+    } catch (const Error&) {
+        return false;
+    }
+    out.rq = std::move(rq);
+    out.gathered = true;
+    out.naive = false;
+    return true;
+}
+
 } // namespace
 
-std::vector<SubCopy> split_copies(const llama_mapping_desc* src, const llama_mapping_desc* dst, const Request& whole)
+std::vector<SubCopy> split_copies(const llama_mapping_desc* src, const llama_mapping_desc* dst, const Request& whole,
+                                  bool gather, const llama_copy_options* options)
 {
     const std::vector<Part> sp = parts_of(src, whole.record);
     const std::vector<Part> dp = parts_of(dst, whole.record);
@@ -491,6 +614,13 @@ std::vector<SubCopy> split_copies(const llama_mapping_desc* src, const llama_map
                                   std::back_inserter(both));
             if (!both.empty())
                 from.emplace_back(&Q, std::move(both));
+        }
+        if (gather && from.size() > 1) {
+            SubCopy g;
+            if (gathered_copy(from, P, whole, options, g)) {
+                out.push_back(std::move(g));
+                continue;
+            }
         }
         // An AoS part fed by several source parts: the copy with the most
         // bytes goes first and writes whole records, taking every byte its
@@ -554,13 +684,6 @@ std::vector<SubCopy> split_copies(const llama_mapping_desc* src, const llama_map
 // ---------------------------------------------------------------------------
 
 namespace {
-
-// lanes as far as the copy can tell: a side whose single block holds every
-// record behaves as unblocked
-uint64_t effective_lanes(const Side& s)
-{
-    return (s.lanes == 0 || s.lanes >= s.n) ? 0 : s.lanes;
-}
 
 bool same_placement(const Side& a, const Side& b)
 {
@@ -714,7 +837,10 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
 {
     const Record& r = rq.record;
     const size_t F = r.leaves.size();
-    if (F + rq.dst.gaps.size() > size_t(kTileMaxEntries))
+    const size_t C = rq.chunks.size(); // a source gathered from several parts
+    if (F + rq.dst.gaps.size() + C > size_t(kTileMaxEntries))
+        return false;
+    if (C && (rq.src.lanes > T || rq.src.block % 16 != 0))
         return false;
     TileArgs& ta = p.tile;
     std::memset(&ta, 0, sizeof(ta));
@@ -769,6 +895,25 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
         e.move = log2_move(uint64_t(e.dst_pos) | e.size | dst_rm_bits) | (1u << 31);
     }
     a.num_entries = uint32_t(k);
+    if (C) {
+        // the chunks of a virtual source block follow the entries and gaps
+        const uint64_t gpb = rq.src.block / 16;
+        if ((uint64_t(T) / rq.src.lanes) * gpb * gpb >= (uint64_t(1) << 32))
+            return false; // mulhi division exact only below this
+        for (size_t c = 0; c < C; c++) {
+            const SrcChunk& ch = rq.chunks[c];
+            TileEntry& e = ta.e[k + c];
+            e.src_addr = ch.addr;
+            e.dst_addr = ch.block_stride;
+            e.src_pos = ch.offset;
+            e.dst_pos = 0;
+            e.size = ch.bytes;
+            e.move = ch.per_record;
+        }
+        a.slots = uint32_t(C);
+        a.flags |= kTileVirtualSrc;
+        a.src.pad = uint32_t(((uint64_t(1) << 32) + gpb - 1) / gpb);
+    }
     // Lane runs: on a field-major side every leaf's values of a tile are one
     // span; on an AoSoA side whose blocks are multiples of 16 bytes they are
     // runs of L values, and when L * size is a multiple of 16 no 16-byte
@@ -884,7 +1029,7 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
         // travels after the entries in the argument block
         const uint64_t share = rq.dst.lanes == 1 ? 4 : 16;
         const uint64_t table_bytes = (table.size() * 4 + 15) / 16 * 16;
-        const uint64_t room = uint64_t(kTileMaxEntries - a.num_entries) * (sizeof(TileEntry) / 4);
+        const uint64_t room = uint64_t(kTileMaxEntries - a.num_entries - C) * (sizeof(TileEntry) / 4);
         // words at odd positions (read funnel-shifted) pay off into AoS and
         // into AoSoA with long lane runs: from the packed 49-byte record +60%
         // into aligned AoS, +7% and +21% into AoSoA32 and AoSoA64, but -9%
@@ -902,7 +1047,7 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
             a.dst.lds_bytes = uint32_t(table_bytes);
             a.lds_bytes = uint32_t(sb + table_bytes);
             ta.gather = g;
-            std::memcpy(&ta.e[a.num_entries], table.data(), table.size() * 4);
+            std::memcpy(&ta.e[a.num_entries + C], table.data(), table.size() * 4);
             for (size_t f = 0; f < F; f++)
                 ta.e[f].dst_pos = uint32_t(rq.dst.base[f]); // the value of lane 0 in a destination block
         }
@@ -914,7 +1059,7 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
     // (a kept destination padding needs the destination region loaded first)
     if (preserve)
         a.flags |= kTilePreserve;
-    bool dload = !direct && !(a.flags & kTileGatherStore) && !preserve && !(p.flags_in & kPlanNoDirect);
+    bool dload = !direct && !(a.flags & kTileGatherStore) && !preserve && !(p.flags_in & kPlanNoDirect) && C == 0;
     uint32_t slots = 0;
     std::vector<uint32_t> first(F, 0);
     for (size_t f = 0; f < F && dload; f++) {
@@ -1052,7 +1197,7 @@ Plan make_plan(const Request& rq, const llama_copy_options* opt)
     if (needs_box(rq))
         fail(LLAMA_E_UNSUPPORTED, "the two views place records at different linear indices (differing "
                                   "linearizers, or Morton holes): copy them with llama_copy or llama_copy_box");
-    if (!opt || (opt->path == LLAMA_PATH_AUTO && opt->tile_records == 0)) {
+    if (rq.chunks.empty() && (!opt || (opt->path == LLAMA_PATH_AUTO && opt->tile_records == 0))) {
         llama_copy_options tuned;
         if (tune_lookup(tune_key(rq), tuned)) {
             if (opt && opt->threads)
@@ -1104,6 +1249,12 @@ Plan make_plan_raw(const Request& rq, const llama_copy_options* opt)
             fail(LLAMA_E_UNSUPPORTED, "a One source is copied element-wise only");
         fill_naive(rq, p);
         return p;
+    }
+    if (!rq.chunks.empty()) {
+        // a gathered source exists only for the tile kernel
+        if (want != LLAMA_PATH_AUTO && want != LLAMA_PATH_TILE)
+            fail(LLAMA_E_UNSUPPORTED, "a source gathered from several parts is copied by the TILE path only");
+        want = LLAMA_PATH_TILE;
     }
     if (want == LLAMA_PATH_AUTO || want == LLAMA_PATH_STREAM) {
         if (fill_stream(rq, p))

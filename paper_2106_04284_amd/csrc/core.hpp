@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "llama_mi355x.h"
@@ -88,11 +89,26 @@ Side make_side(const llama_mapping_desc* m, const Record& r);
 // the linear index of coordinate c on side s (its linearizer)
 uint64_t linearize(const Side& s, const uint64_t* c);
 
+// One chunk of a virtual source block (a source gathered from several parts,
+// kTileVirtualSrc): a whole block of a record-major part, or the L values of
+// one leaf of a field-major part.
+struct SrcChunk {
+    uint64_t addr;         // device address of the chunk in virtual block 0
+    uint64_t block_stride; // device bytes from one virtual block to the next
+    uint32_t offset;       // byte offset in a virtual block
+    uint32_t bytes;
+    uint32_t per_record;   // 0: a whole part block; else the leaf's bytes per record
+};
+
 // A validated copy request: both sides plus device addresses.
 struct Request {
     Record record;
     Side src, dst;
     std::vector<uint64_t> src_ptr, dst_ptr; // device addresses of the blobs
+    // non-empty: the source is gathered from several parts, and src is a
+    // record-major side of virtual blocks whose leaves sit at their chunk's
+    // place (planned as TILE only)
+    std::vector<SrcChunk> chunks;
 };
 
 // Checks a side's blob array (sizes, NULL pointers, address overflow) and
@@ -108,17 +124,31 @@ Request make_request(const llama_mapping_desc* src, const llama_blob* src_blobs,
 // hold, from the source part to the destination part.  `naive`: it writes part
 // of the records of a record-major destination part, so only the element-wise
 // path writes nothing but its own leaves.
+struct Plan;
 struct SubCopy {
     Request rq;
     bool naive = false;
+    // a copy from several source parts at once, already planned (`plan`)
+    bool gathered = false;
+    std::shared_ptr<Plan> plan;
 };
 // The part-to-part copies of `whole` (made with allow_split), destination part
 // by destination part; a plain side is one part holding every leaf.  The
-// padding of a destination part is written by the first copy into it.
-std::vector<SubCopy> split_copies(const llama_mapping_desc* src, const llama_mapping_desc* dst, const Request& whole);
+// padding of a destination part is written by the first copy into it.  With
+// `gather`, a destination part fed by several source parts is copied by one
+// tile copy whose source gathers those parts (when their layouts allow it and
+// a plan with `options` exists), instead of one copy per source part.
+std::vector<SubCopy> split_copies(const llama_mapping_desc* src, const llama_mapping_desc* dst, const Request& whole,
+                                  bool gather = false, const llama_copy_options* options = nullptr);
 
-// llama_copy_leaves (leaves.cpp): validates, plans and enqueues the copy
-// between differing records.
+// llama_copy_leaves (leaves.cpp): validates and plans the copy between
+// differing records (without `need_blobs`: plans only, for distinct blobs
+// aligned to 256 bytes).
+struct Plan;
+std::vector<Plan> leaves_plans(const llama_mapping_desc* src, const llama_blob* src_blobs,
+                               const llama_mapping_desc* dst, const llama_blob* dst_blobs, const uint32_t* src_leaf,
+                               const llama_copy_options* options, bool need_blobs);
+// ... and enqueues its launches.
 void copy_leaves(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
                  const llama_blob* dst_blobs, const uint32_t* src_leaf, const llama_copy_options* options,
                  void* stream);

@@ -106,8 +106,9 @@ struct TileHeader {
     uint32_t num_entries; // leaves, then gaps
     uint32_t lds_bytes;
     uint32_t flags;       // kTileDirectStore, kTileDirectLoad, kTilePreserve, kTileGatherStore,
-                          // kTileStreamStores, kTileStreamLoads
-    uint32_t slots;       // kTileDirectLoad: granule slots of a tile (a multiple of 64)
+                          // kTileStreamStores, kTileStreamLoads, kTileGatherOdd, kTileVirtualSrc
+    uint32_t slots;       // kTileDirectLoad: granule slots of a tile (a multiple of 64);
+                          // kTileVirtualSrc: the chunks after the entries
     TileSide src, dst;
 };
 
@@ -157,9 +158,31 @@ constexpr uint32_t kTileStreamLoads = 32;
 // the common case keeps its registers.
 constexpr uint32_t kTileGatherOdd = 64;
 
+// A source gathered from several parts (a Split source, sec. 3.7): the tile's
+// source region is a run of virtual blocks of L records and K bytes (h.src
+// describes them as a record-major side with lanes L and block K), and every
+// virtual block is assembled from chunks that each come from one contiguous
+// global range: a whole block of an AoSoA (or AoS) part with L lanes, or the
+// L values of one leaf of an SoA part.  The chunks (h.slots of them, in the
+// order of their place in a virtual block) follow the entries and gaps as
+// TileEntry-sized records read with these meanings:
+//   src_addr: global address of the chunk in virtual block 0 of tile 0;
+//   dst_addr: global bytes from one virtual block to the next;
+//   src_pos:  byte offset of the chunk in a virtual block (a multiple of 16);
+//   dst_pos:  unused;
+//   size:     bytes of the chunk (a multiple of 16);
+//   move:     0 for a whole part block, else the bytes per record of a leaf
+//             chunk, which is read only for records with values.
+// Tile t starts T / L virtual blocks after tile t - 1.  h.src.pad holds
+// ceil(2^32 / (K / 16)) for the division of a granule index by the granules
+// per virtual block.  Direct load is never combined with it.
+constexpr uint32_t kTileVirtualSrc = 128;
+constexpr uint32_t kTileMaxChunks = 32;
+
 // The gather geometry follows the entries, so that the header and entries
 // keep their offsets in the argument block (entries 16-byte aligned; a
-// header grown by 24 bytes measured 3-5% slower for the other modes).
+// header grown by 24 bytes measured 3-5% slower for the other modes).  The
+// word table follows the entries, gaps and chunks.
 struct TileArgs {
     TileHeader h;
     TileEntry e[kTileMaxEntries];

@@ -193,6 +193,41 @@ __device__ __forceinline__ void load_span(uint64_t gstart, uint32_t len, uint32_
     }
 }
 
+// The source region of tile t gathered from several parts (kTileVirtualSrc):
+// ceil(nv / L) virtual blocks of K bytes, granule by granule.  LDS granule q
+// of the region lies in virtual block b = q / (K / 16); the last chunk that
+// starts at or before the granule's byte in the block gives its global
+// address.  A leaf chunk's granules past the tile's records with values are
+// not loaded (the remap never reads those bytes), so no load reaches past the
+// end of an SoA part's leaf; part blocks are whole in their blob.
+template <bool kOnce, bool kCount, typename Entries>
+__device__ __forceinline__ void load_virtual(const TileHeader& h, Entries ent, uint64_t t, uint32_t nv, uint32_t wave,
+                                             uint32_t nwaves, uint32_t lane, uint32_t lds_base)
+{
+    const uint32_t gpb = uint32_t(h.src.block >> 4);
+    const uint32_t L = uint32_t(h.src.lanes);
+    const uint32_t nvb = (nv + L - 1u) >> h.src.log2_lanes;
+    const uint32_t G = nvb * gpb;
+    const uint64_t tile_blocks = uint64_t(t) << (h.log2_tile - h.src.log2_lanes);
+    for (uint32_t c = wave; c * 64u < G; c += nwaves) {
+        const uint32_t q = c * 64u + lane;
+        const uint32_t b = __umulhi(q, h.src.pad); // q / gpb
+        const uint32_t off = (q - b * gpb) * 16u;  // byte of the granule in its virtual block
+        uint64_t ga = 0;
+        uint32_t rel = 0, valid = 0;
+        for (uint32_t k = 0; k < h.slots; k++) {
+            const auto& ch = ent(h.num_entries + k);
+            if (off >= ch.src_pos) {
+                rel = off - ch.src_pos;
+                ga = ch.src_addr + (tile_blocks + b) * ch.dst_addr + rel;
+                valid = ch.move ? min(ch.size, (nv - b * L) * ch.move) : ch.size;
+            }
+        }
+        if (q < G && rel < valid)
+            lds_dma16<kOnce, kCount>(ga, uniform(lds_base + h.src.lds_base + c * 1024u));
+    }
+}
+
 // Stores LDS bytes lds_region + (gstart & 15) .. into [gstart, gstart + len):
 // whole granules with 16-byte stores, the partial first and last granule byte
 // by byte so that no byte outside the span is written.  Granule gi goes to
@@ -599,6 +634,9 @@ constexpr uint32_t kModeStreamStores = 8;
 constexpr uint32_t kModeStreamLoads = 16;
 // added to a mode: every global load and store is counted (Heatmap)
 constexpr uint32_t kModeCount = 32;
+// added to a mode: the source region is gathered from several parts
+// (kTileVirtualSrc)
+constexpr uint32_t kModeVirtualSrc = 64;
 
 template <uint32_t ModeBits, typename Entries>
 __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint64_t t, uint8_t* lds,
@@ -608,6 +646,7 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     constexpr bool kStream = (ModeBits & kModeStreamStores) != 0;
     constexpr bool kOnce = (ModeBits & kModeStreamLoads) != 0;
     constexpr bool kCount = (ModeBits & kModeCount) != 0;
+    constexpr bool kVirtual = (ModeBits & kModeVirtualSrc) != 0;
     const bool dload = Mode == kModeDirectLoad || (Mode == kModeAny && (h.flags & kTileDirectLoad));
     const bool dstore = Mode == kModeDirectStore || (Mode == kModeAny && (h.flags & kTileDirectStore));
     const bool gstore = Mode == kModeGatherStore || Mode == kModeGatherOdd ||
@@ -631,7 +670,9 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
         else
             direct_load_tile<false, kOnce, kCount>(h, ent, t, i0, nv, nd, lds);
     } else if (nv > 0) {
-        if (h.src.mode == kRecordMajor) {
+        if (kVirtual) {
+            load_virtual<kOnce, kCount>(h, ent, t, nv, wave, nwaves, lane, lds_base);
+        } else if (h.src.mode == kRecordMajor) {
             const uint32_t len = uint32_t(((uint64_t(nv) + h.src.lanes - 1) >> h.src.log2_lanes) * h.src.block);
             load_span<kOnce, kCount>(h.src.span_base + t * h.src.tile_bytes, len, h.src.lds_base, wave, nwaves, 0, lane, lds_base);
         } else {
@@ -747,8 +788,10 @@ __global__ void __launch_bounds__(1024) tile_kernel(const TileArgs a)
         t = x * q + min(x, rem) + k;
         stride = nt;
     }
-    if (Mode == kModeGatherStore || Mode == kModeGatherOdd) // the word table follows the entries
-        gather_table(a.h, a.gather, reinterpret_cast<const uint32_t*>(a.e + a.h.num_entries), lds);
+    if (Mode == kModeGatherStore || Mode == kModeGatherOdd) // the word table follows the entries (and chunks)
+        gather_table(a.h, a.gather,
+                     reinterpret_cast<const uint32_t*>(a.e + a.h.num_entries + ((ModeBits & kModeVirtualSrc) ? a.h.slots : 0u)),
+                     lds);
     for (; t < nt; t += stride) {
         tile_body<ModeBits>(a.h, ent, t, lds, &a.gather);
         if (t + stride < nt)
@@ -763,8 +806,10 @@ __global__ void __launch_bounds__(1024) tile_count_kernel(const TileArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     auto ent = [&](uint32_t k) -> const TileEntry& { return a.e[k]; };
-    if (Mode == kModeGatherStore || Mode == kModeGatherOdd)
-        gather_table(a.h, a.gather, reinterpret_cast<const uint32_t*>(a.e + a.h.num_entries), lds);
+    if ((Mode & 7u) == kModeGatherStore || (Mode & 7u) == kModeGatherOdd)
+        gather_table(a.h, a.gather,
+                     reinterpret_cast<const uint32_t*>(a.e + a.h.num_entries + ((Mode & kModeVirtualSrc) ? a.h.slots : 0u)),
+                     lds);
     for (uint64_t t = blockIdx.x; t < a.h.num_tiles; t += gridDim.x) {
         tile_body<Mode | kModeCount>(a.h, ent, t, lds, &a.gather);
         if (t + gridDim.x < a.h.num_tiles)
@@ -1808,6 +1853,21 @@ const void* const kTileCountKernels[kTileModes] = {
     (const void*)tile_count_kernel<kModeDirectLoad>, (const void*)tile_count_kernel<kModeGatherStore>,
     (const void*)tile_count_kernel<kModeGatherOdd>};
 
+// the same with the source gathered from several parts (kTileVirtualSrc);
+// never with direct load
+constexpr uint32_t kV = kModeVirtualSrc;
+const void* const kTileVirtualKernels[3 * kTileModes] = {
+    (const void*)tile_kernel<kModeStaged | kV>, (const void*)tile_kernel<kModeDirectStore | kV>, nullptr,
+    (const void*)tile_kernel<kModeGatherStore | kV>, (const void*)tile_kernel<kModeGatherOdd | kV>,
+    (const void*)tile_kernel<kModeStaged | kV | kLd>, (const void*)tile_kernel<kModeDirectStore | kV | kLd>, nullptr,
+    (const void*)tile_kernel<kModeGatherStore | kV | kLd>, (const void*)tile_kernel<kModeGatherOdd | kV | kLd>,
+    (const void*)tile_kernel<kModeStaged | kV | kLdSt>, (const void*)tile_kernel<kModeDirectStore | kV | kLdSt>, nullptr,
+    (const void*)tile_kernel<kModeGatherStore | kV | kLdSt>, (const void*)tile_kernel<kModeGatherOdd | kV | kLdSt>};
+
+const void* const kTileVirtualCountKernels[kTileModes] = {
+    (const void*)tile_count_kernel<kModeStaged | kV>, (const void*)tile_count_kernel<kModeDirectStore | kV>, nullptr,
+    (const void*)tile_count_kernel<kModeGatherStore | kV>, (const void*)tile_count_kernel<kModeGatherOdd | kV>};
+
 // box_kernel<R, staged, counted>: index (R == 8) * 4 + staged * 2 + counted
 const void* const kBoxKernels[8] = {
     (const void*)box_kernel<4, false, false>, (const void*)box_kernel<4, false, true>,
@@ -1905,7 +1965,9 @@ void launch(const Plan& p, void* stream_ptr)
                                   : (f & kTileDirectStore) ? kModeDirectStore
                                   : (f & kTileGatherStore) ? ((f & kTileGatherOdd) ? kModeGatherOdd : kModeGatherStore)
                                                            : kModeStaged;
-            k = kTileCountKernels[mode - 1];
+            k = (f & kTileVirtualSrc) ? kTileVirtualCountKernels[mode - 1] : kTileCountKernels[mode - 1];
+            if (!k)
+                fail(LLAMA_E_INVALID_ARG, "a gathered source never loads directly");
             lds = p.tile.h.lds_bytes;
         } else if (p.path == LLAMA_PATH_STREAM) {
             k = (const void*)stream_count_kernel;
@@ -1934,7 +1996,9 @@ void launch(const Plan& p, void* stream_ptr)
         // streaming stores come with streaming loads (a destination of 1 GiB
         // or more has a source of far more than 256 MB in every layout pair)
         const uint32_t variant = (f & kTileStreamStores) ? 2 : (f & kTileStreamLoads) ? 1 : 0;
-        const void* k = kTileKernels[(mode - 1) + kTileModes * variant];
+        const void* k = ((f & kTileVirtualSrc) ? kTileVirtualKernels : kTileKernels)[(mode - 1) + kTileModes * variant];
+        if (!k)
+            fail(LLAMA_E_INVALID_ARG, "a gathered source never loads directly");
         void* args[] = {(void*)&p.tile};
         check_hip(hipLaunchKernel(k, dim3(grid), dim3(p.threads), args, p.tile.h.lds_bytes, stream),
                   "hipLaunchKernel(tile_kernel)");

@@ -32,9 +32,9 @@ bool overlap(uint64_t a, uint64_t an, uint64_t b, uint64_t bn)
 
 } // namespace
 
-void copy_leaves(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
-                 const llama_blob* dst_blobs, const uint32_t* src_leaf, const llama_copy_options* options,
-                 void* stream)
+std::vector<Plan> leaves_plans(const llama_mapping_desc* src, const llama_blob* src_blobs,
+                               const llama_mapping_desc* dst, const llama_blob* dst_blobs, const uint32_t* src_leaf,
+                               const llama_copy_options* options, bool need_blobs)
 {
     if (!src || !dst)
         fail(LLAMA_E_INVALID_ARG, "mapping descriptor is NULL");
@@ -91,8 +91,16 @@ void copy_leaves(const llama_mapping_desc* src, const llama_blob* src_blobs, con
         rq.dst.base.push_back(sd.base[k]);
     }
     rq.dst.partial = to.size() != rd.leaves.size();
-    blob_ptrs("source", ss, src_blobs, rq.src_ptr);
-    blob_ptrs("destination", sd, dst_blobs, rq.dst_ptr);
+    if (need_blobs) {
+        blob_ptrs("source", ss, src_blobs, rq.src_ptr);
+        blob_ptrs("destination", sd, dst_blobs, rq.dst_ptr);
+    } else {
+        // plans only: distinct blobs aligned to 256 bytes, as llama_plan assumes
+        for (size_t b = 0; b < ss.blob_size.size(); b++)
+            rq.src_ptr.push_back((uint64_t(b) + 1) << 40);
+        for (size_t b = 0; b < sd.blob_size.size(); b++)
+            rq.dst_ptr.push_back((uint64_t(b) + 1 + 4096) << 40);
+    }
     for (size_t a = 0; a < rq.dst_ptr.size(); a++) {
         for (size_t b = 0; b < rq.src_ptr.size(); b++)
             if (overlap(rq.dst_ptr[a], sd.blob_size[a], rq.src_ptr[b], ss.blob_size[b]))
@@ -132,10 +140,8 @@ void copy_leaves(const llama_mapping_desc* src, const llama_blob* src_blobs, con
         } catch (const Error&) {
             // too many gap entries for this build's kernels: go on below
         }
-        if (planned) {
-            launch(t, stream);
-            return;
-        }
+        if (planned)
+            return {t};
     }
     if (rq.dst.partial && sd.lanes >= 1) {
         // a record-major destination written in part: only a direct store
@@ -149,17 +155,22 @@ void copy_leaves(const llama_mapping_desc* src, const llama_blob* src_blobs, con
         } catch (const Error&) {
             // the caller's path or tile size does not fit; go element-wise
         }
-        if (direct) {
-            launch(t, stream);
-            return;
-        }
+        if (direct)
+            return {t};
         llama_copy_options o = options ? *options : llama_copy_options{0, 0, 0, 0, 0};
         o.path = LLAMA_PATH_NAIVE;
         o.tile_records = 0;
-        launch(make_plan(rq, &o), stream);
-        return;
+        return {make_plan(rq, &o)};
     }
-    launch(make_plan(rq, options), stream);
+    return {make_plan(rq, options)};
+}
+
+void copy_leaves(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
+                 const llama_blob* dst_blobs, const uint32_t* src_leaf, const llama_copy_options* options,
+                 void* stream)
+{
+    for (const Plan& p : leaves_plans(src, src_blobs, dst, dst_blobs, src_leaf, options, true))
+        launch(p, stream);
 }
 
 } // namespace llama

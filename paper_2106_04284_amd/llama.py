@@ -99,7 +99,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("path", ctypes.c_uint32), ("tile_records", ctypes.c_uint32), ("threads", ctypes.c_uint32),
                 ("lds_bytes", ctypes.c_uint32), ("workgroups", ctypes.c_uint64), ("runs", ctypes.c_uint32),
                 ("wg_per_cu", ctypes.c_uint32), ("tiles", ctypes.c_uint64), ("read_bytes", ctypes.c_uint64),
-                ("write_bytes", ctypes.c_uint64), ("tile_mode", ctypes.c_uint32), ("cache_hints", ctypes.c_uint32)]
+                ("write_bytes", ctypes.c_uint64), ("tile_mode", ctypes.c_uint32), ("cache_hints", ctypes.c_uint32),
+                ("plan_flags", ctypes.c_uint32), ("source_chunks", ctypes.c_uint32)]
 
 
 class CopyItem(ctypes.Structure):
@@ -138,6 +139,9 @@ _SIGNATURES = {
                                             ctypes.POINTER(ctypes.c_uint64)]),
     "llama_plan": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(MappingDesc),
                                   ctypes.POINTER(CopyOptions), ctypes.POINTER(PlanInfo)]),
+    "llama_plan_copy": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(MappingDesc),
+                                       ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(CopyOptions),
+                                       ctypes.POINTER(PlanInfo), ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]),
     "llama_copy": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob), ctypes.POINTER(MappingDesc),
                                   ctypes.POINTER(Blob), ctypes.c_void_p]),
     "llama_copy_naive": (ctypes.c_int, [ctypes.POINTER(MappingDesc), ctypes.POINTER(Blob),
@@ -490,17 +494,43 @@ def copy_naive(src: Mapping, src_blobs, dst: Mapping, dst_blobs, stream=None):
                                  _blobs(dst_blobs), _stream(stream)))
 
 
-def plan(src: Mapping, dst: Mapping, path=PATH_AUTO, tile_records=0, threads=0, wg_per_cu=0, flags=0) -> dict:
-    """llama_plan: what a copy of this pair would launch."""
-    info = PlanInfo()
-    o = _options(path, tile_records, threads, wg_per_cu, flags)
-    check(lib().llama_plan(ctypes.byref(src.desc), ctypes.byref(dst.desc), ctypes.byref(o), ctypes.byref(info)))
+PLAN_GATHERED_SOURCE = 1
+PLAN_KEEPS_DESTINATION = 2
+
+
+def _info_dict(info: PlanInfo) -> dict:
     return {"path": PATH_NAMES.get(info.path, "?"), "tile_records": info.tile_records, "threads": info.threads,
             "lds_bytes": info.lds_bytes, "workgroups": info.workgroups, "runs": info.runs,
             "wg_per_cu": info.wg_per_cu, "tiles": info.tiles,
             "read_bytes": info.read_bytes, "write_bytes": info.write_bytes,
             "tile_mode": TILE_MODE_NAMES.get(info.tile_mode), "stream_loads": bool(info.cache_hints & 1),
-            "stream_stores": bool(info.cache_hints & 2)}
+            "stream_stores": bool(info.cache_hints & 2),
+            "gathered_source": bool(info.plan_flags & PLAN_GATHERED_SOURCE),
+            "keeps_destination": bool(info.plan_flags & PLAN_KEEPS_DESTINATION),
+            "source_chunks": info.source_chunks}
+
+
+def plan(src: Mapping, dst: Mapping, path=PATH_AUTO, tile_records=0, threads=0, wg_per_cu=0, flags=0) -> dict:
+    """llama_plan: what a copy of this pair would launch."""
+    info = PlanInfo()
+    o = _options(path, tile_records, threads, wg_per_cu, flags)
+    check(lib().llama_plan(ctypes.byref(src.desc), ctypes.byref(dst.desc), ctypes.byref(o), ctypes.byref(info)))
+    return _info_dict(info)
+
+
+def plan_copy(src: Mapping, dst: Mapping, src_leaf=None, path=PATH_AUTO, tile_records=0, threads=0, wg_per_cu=0,
+              flags=0, capacity=64) -> list:
+    """llama_plan_copy: every launch of llama_copy_ex (or, with `src_leaf`,
+    llama_copy_leaves) for this pair, in order."""
+    infos = (PlanInfo * capacity)()
+    count = ctypes.c_uint32()
+    o = _options(path, tile_records, threads, wg_per_cu, flags)
+    leaf = None
+    if src_leaf is not None:
+        leaf = (ctypes.c_uint32 * len(src_leaf))(*[NO_LEAF if x is None else int(x) for x in src_leaf])
+    check(lib().llama_plan_copy(ctypes.byref(src.desc), ctypes.byref(dst.desc), leaf, ctypes.byref(o), infos,
+                                capacity, ctypes.byref(count)))
+    return [_info_dict(infos[k]) for k in range(count.value)]
 
 
 # --------------------------------------------------------------------------

@@ -626,3 +626,50 @@ def test_copy_leaves_validation():
     small = (L.Blob * 6)(*[L.Blob(ctypes.cast(x, ctypes.c_void_p), 4) for x in bufs[1:]])
     assert rc(a, sb, b, small, list(range(6))) == L.E_BLOB_TOO_SMALL
     assert rc(a, sb, b, (L.Blob * 6)(*([blob(bufs[0])] * 6)), list(range(6))) == L.E_OVERLAP
+
+
+def test_plan_copy_lists_every_launch():
+    """llama_plan_copy: the launches of a copy in order, without blobs.  A
+    plain pair is one launch equal to llama_plan's; a Split destination part
+    fed by an AoSoA32 part and SoA leaves is one tile copy with a gathered
+    source (sec. 3.7), and by SoA parts one copy from a merged field-major
+    side; an AoS part and 4-byte SoA leaves cannot be gathered and take a
+    kept-gap tile after the first part copy; a copy between differing
+    records into packed AoS that keeps a leaf takes the kept-gap tile too;
+    too small a capacity is an error."""
+    rg = L.Record(W.PARTICLE)
+    n = 1 << 20
+    aos = L.Mapping(rg, "aos_packed", [n])
+    soa = L.Mapping(rg, "soa_multi", [n])
+    q32 = L.Mapping(rg, "aosoa", [n], 32)
+    one = L.plan_copy(aos, soa)
+    assert len(one) == 1 and one[0] == L.plan(aos, soa)
+    s1 = L.Mapping(rg, "split", [n], split=(0, 3, ("aosoa", 32), ("soa_multi", 0)))
+    g = L.plan_copy(s1, aos)
+    assert len(g) == 1 and g[0]["path"] == "tile" and g[0]["gathered_source"] and g[0]["source_chunks"] == 5
+    assert not g[0]["keeps_destination"]
+    assert g[0]["read_bytes"] == n * 28 and g[0]["write_bytes"] == n * 28
+    # a tile smaller than the 32-record virtual block: part copies again
+    small = L.plan_copy(s1, aos, tile_records=16)
+    assert len(small) == 2 and not any(p["gathered_source"] for p in small) and small[1]["keeps_destination"]
+    # SoA parts: one copy from one field-major side
+    s3 = L.Mapping(rg, "split", [n], split=(0, 3, ("soa_multi", 0), ("soa_single", 0)))
+    m = L.plan_copy(s3, aos)
+    assert len(m) == 1 and not m[0]["gathered_source"] and m[0]["path"] == "tile"
+    # an aligned AoS part (one-record blocks) with 4-byte SoA leaves: not gathered
+    s4 = L.Mapping(rg, "split", [n], split=(0, 3, ("aos_aligned", 0), ("soa_multi", 0)))
+    k = L.plan_copy(s4, aos)
+    assert len(k) == 2 and not k[0]["keeps_destination"] and k[1]["keeps_destination"]
+    # a Split destination: one launch per destination part here
+    d = L.plan_copy(q32, s1)
+    assert len(d) == 2 and all(p["path"] != "naive" for p in d)
+    # differing records: keep the mass of a packed AoS destination
+    rs = L.Record(W.PARTICLE[:2])
+    lv = L.plan_copy(L.Mapping(rs, "soa_multi", [n]), aos, src_leaf=[0, 1, 2, 3, 4, 5, None])
+    assert len(lv) == 1 and lv[0]["tile_mode"] == "staged" and lv[0]["keeps_destination"]
+    with pytest.raises(L.LlamaError) as e:
+        L.plan_copy(s1, aos, capacity=0)
+    assert e.value.status == L.E_INVALID_ARG
+    with pytest.raises(L.LlamaError) as e:
+        L.plan_copy(s1, aos, path=L.PATH_STREAM)
+    assert e.value.status == L.E_UNSUPPORTED

@@ -173,6 +173,42 @@ def test_split_copy_misaligned_blobs(L, orc, offs):
         _run(L, orc, W.PARTICLE, s, d, [5003], seed=90 + k, src_off=src_off, dst_off=dst_off)
 
 
+GATHERED = [(name, split, dst, n) for name in ("particle", "mixed", "lbm")
+            for split in (("split", (0, 3, ("aosoa", 32), ("soa_multi", 0))),
+                          ("split", (1, 2, ("aosoa", 8), ("soa_multi", 0))),
+                          ("split", (0, 1, ("aosoa", 64), ("aosoa", 64))),
+                          ("split", (0, 2, ("soa_multi", 0), ("soa_single", 0))))
+            for dst in (("aos_packed", 0), ("aos_aligned", 0), ("aosoa", 8), ("aosoa", 32))
+            for n in (1, 31, 33, 4099)]
+
+
+@pytest.mark.parametrize("case", GATHERED, ids=lambda c: f"{c[0]}-{_id(('', c[1], c[2], [c[3]]))}")
+def test_split_source_gathered(L, orc, case):
+    """A destination part fed by several source parts, copied by one tile
+    copy whose source gathers the parts (AoSoA parts of one lane count and SoA
+    leaves as chunks of a virtual block, or SoA parts as one field-major side)
+    where the layouts allow it, else part by part: the oracle's bytes either
+    way, at record counts below, at and past one virtual block."""
+    name, split, dst, n = case
+    print(f"split gathered {case}", flush=True)
+    _run(L, orc, W.RECORDS[name], split, dst, [n], seed=n + 3)
+
+
+@pytest.mark.parametrize("opts", [dict(flags=1), dict(keep=True), dict(threads=64), dict(tile_records=16),
+                                  dict(tile_records=4096), dict(wg_per_cu=2)],
+                         ids=["no_direct", "keep", "t64", "T16", "T4096", "persistent"])
+def test_split_source_gathered_options(L, orc, opts):
+    """Options reach the gathered copy (a tile smaller than a virtual block
+    falls back to part copies); kept padding keeps the destination's gaps."""
+    opts = dict(opts)
+    keep = opts.pop("keep", False)
+    src = ("split", (0, 3, ("aosoa", 32), ("soa_multi", 0)))
+    for k, (rec, dst, n) in enumerate([(W.PARTICLE, ("aos_packed", 0), 5003), (W.MIXED, ("aos_aligned", 0), 2049),
+                                       (W.LBM, ("aosoa", 16), 777)]):
+        print(f"split gathered options {opts} keep={keep} case {k}", flush=True)
+        _run(L, orc, rec, src, dst, [n], seed=50 + k, keep=keep, **opts)
+
+
 ONE_CASES = [(name, dst, n) for name in ("particle", "mixed", "lbm", "listing1")
              for dst in PLAIN for n in (1, 3001)]
 
