@@ -468,6 +468,11 @@ typedef struct {
  * another part copy writes) keep their values but are written again, so
  * nothing else may write that destination while the copy runs. */
 #define LLAMA_PLAN_KEEPS_DESTINATION 2u
+/* The tile's destination is scattered over several parts of a Split
+ * destination (sec. 3.7): one source part feeding several destination parts
+ * (AoSoA parts of one lane count, SoA leaves) is read once, and each leaf's
+ * 16-byte granules are stored into its own part. */
+#define LLAMA_PLAN_SCATTERED_DESTINATION 4u
 
 /* What a copy of this pair with these options would launch, without blobs:
  * the plan assumes distinct blobs aligned to 256 bytes (a real copy plans for

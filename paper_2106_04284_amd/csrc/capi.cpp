@@ -179,7 +179,8 @@ void fill_info(const Plan& p, llama_plan_info* info)
         info->cache_hints = ((f & kTileStreamLoads) ? LLAMA_HINT_STREAM_LOADS : 0u) |
                             ((f & kTileStreamStores) ? LLAMA_HINT_STREAM_STORES : 0u);
         info->plan_flags = ((f & kTileVirtualSrc) ? LLAMA_PLAN_GATHERED_SOURCE : 0u) |
-                           ((f & kTilePreserve) ? LLAMA_PLAN_KEEPS_DESTINATION : 0u);
+                           ((f & kTilePreserve) ? LLAMA_PLAN_KEEPS_DESTINATION : 0u) |
+                           ((f & kTileVirtualDst) ? LLAMA_PLAN_SCATTERED_DESTINATION : 0u);
         info->source_chunks = (f & kTileVirtualSrc) ? p.tile.h.slots : 0u;
     } else if (p.path == LLAMA_PATH_STREAM) {
         info->cache_hints = (p.stream.flags & kStreamLoadsOnce) ? LLAMA_HINT_STREAM_LOADS : 0u;

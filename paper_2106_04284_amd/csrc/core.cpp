@@ -495,9 +495,17 @@ using PartLeaves = std::vector<std::pair<const Part*, std::vector<uint32_t>>>;
 bool gathered_copy(const PartLeaves& from, const Part& P, const Request& whole, const llama_copy_options* opt,
                    SubCopy& out)
 {
+    // the leaves the parts give P: all of P's, or (a field-major part that
+    // another copy also feeds) some
+    std::vector<uint32_t> given;
+    for (const auto& fq : from)
+        given.insert(given.end(), fq.second.begin(), fq.second.end());
+    std::sort(given.begin(), given.end());
     Request rq;
-    rq.record = sub_record(whole.record, P.leaves);
-    rq.dst = restrict_side(P, P.leaves);
+    rq.record = sub_record(whole.record, given);
+    rq.dst = restrict_side(P, given);
+    if (rq.dst.partial && effective_lanes(P.side) != 0)
+        return false;
     rq.dst_ptr.assign(whole.dst_ptr.begin() + P.first_blob,
                       whole.dst_ptr.begin() + P.first_blob + P.side.blob_size.size());
     uint64_t L = 0;
@@ -510,7 +518,7 @@ bool gathered_copy(const PartLeaves& from, const Part& P, const Request& whole, 
         if (l != 0)
             L = l;
     }
-    const size_t F = P.leaves.size();
+    const size_t F = given.size();
     std::vector<uint32_t> blob_of(whole.record.leaves.size(), 0);
     std::vector<uint64_t> base_of(whole.record.leaves.size(), 0);
     Side s = from[0].first->side;
@@ -578,13 +586,109 @@ bool gathered_copy(const PartLeaves& from, const Part& P, const Request& whole, 
     s.blob.assign(F, 0);
     s.base.assign(F, 0);
     for (size_t j = 0; j < F; j++) {
-        s.blob[j] = blob_of[P.leaves[j]];
-        s.base[j] = base_of[P.leaves[j]];
+        s.blob[j] = blob_of[given[j]];
+        s.base[j] = base_of[given[j]];
     }
     rq.src = s;
     try {
         if (!rq.chunks.empty() && opt && opt->path != LLAMA_PATH_AUTO && opt->path != LLAMA_PATH_TILE)
             return false;
+        out.plan = std::make_shared<Plan>(make_plan(rq, opt));
+    } catch (const Error&) {
+        return false;
+    }
+    out.rq = std::move(rq);
+    out.gathered = true;
+    out.naive = false;
+    return true;
+}
+
+// One copy from source part Q into several destination parts (`to`: each
+// with the leaves Q gives it; a record-major part takes all its leaves from
+// Q, a field-major part may take only some).  When every such part is
+// field-major, the destination is one plain field-major side over their
+// blobs, planned like any copy.  When the record-major ones share one lane
+// count L, the destination is scattered: each leaf's runs of L values go to
+// its own part (a direct-store tile, kTileVirtualDst), which needs runs of at
+// least 128 bytes (whole 16-byte granules) at 16-byte aligned addresses and
+// no padding gaps.  Returns false (and the part copies run one destination
+// part at a time) when neither applies or no plan fits `opt`.
+bool scattered_copy(const Part& Q, const PartLeaves& to, const Request& whole, const llama_copy_options* opt,
+                    SubCopy& out)
+{
+    uint64_t L = 0;
+    std::vector<uint32_t> leaves;
+    for (const auto& pl : to) {
+        const Part* P = pl.first;
+        const uint64_t l = effective_lanes(P->side);
+        // a part taken as field-major must have no tail lanes to fill (an
+        // AoSoA part whose one block outlasts the records has them)
+        if (P->side.kind == LLAMA_ONE || !P->side.gaps.empty() || (l != 0 && L != 0 && l != L) ||
+            (l == 0 && P->side.npad != P->side.n))
+            return false;
+        if (l != 0)
+            L = l;
+        leaves.insert(leaves.end(), pl.second.begin(), pl.second.end());
+    }
+    std::sort(leaves.begin(), leaves.end());
+    Request rq;
+    rq.record = sub_record(whole.record, leaves);
+    rq.src = restrict_side(Q, leaves);
+    rq.src_ptr.assign(whole.src_ptr.begin() + Q.first_blob, whole.src_ptr.begin() + Q.first_blob + Q.side.blob_size.size());
+    Side d = to[0].first->side;
+    d.partial = false;
+    d.gaps.clear();
+    d.leaf_lanes.clear();
+    d.leaf_block.clear();
+    d.blob_size.clear();
+    d.blob.assign(leaves.size(), 0);
+    d.base.assign(leaves.size(), 0);
+    if (L != 0) {
+        rq.dst_stride.assign(leaves.size(), 0);
+        rq.dst_values_only.assign(leaves.size(), 0);
+    }
+    uint64_t run_bytes = 0;
+    for (const auto& pl : to) {
+        const Part* P = pl.first;
+        const uint32_t first = uint32_t(rq.dst_ptr.size());
+        for (size_t b = 0; b < P->side.blob_size.size(); b++) {
+            rq.dst_ptr.push_back(whole.dst_ptr[P->first_blob + b]);
+            d.blob_size.push_back(P->side.blob_size[b]);
+        }
+        const bool field = effective_lanes(P->side) == 0;
+        for (uint32_t f : pl.second) {
+            const size_t k = size_t(std::find(P->leaves.begin(), P->leaves.end(), f) - P->leaves.begin());
+            const size_t j = size_t(std::lower_bound(leaves.begin(), leaves.end(), f) - leaves.begin());
+            d.blob[j] = first + P->side.blob[k];
+            d.base[j] = P->side.base[k];
+            if (L == 0)
+                continue;
+            const uint32_t size = whole.record.leaves[f].size;
+            const uint64_t stride = field ? L * size : P->side.block;
+            if ((L * size) % 16 != 0 || L * size < 128 || stride % 16 != 0 || stride > UINT32_MAX ||
+                (rq.dst_ptr[d.blob[j]] + d.base[j]) % 16 != 0)
+                return false;
+            rq.dst_stride[j] = uint32_t(stride);
+            rq.dst_values_only[j] = field ? 1 : 0;
+            run_bytes += L * size;
+        }
+    }
+    if (L == 0) {
+        // every part field-major: their leaf spans as one SoA side
+        d.kind = LLAMA_SOA_MULTI;
+        d.lanes = 0;
+        d.block = 0;
+        d.npad = d.n;
+    } else {
+        d.kind = LLAMA_AOSOA;
+        d.lanes = L;
+        d.block = (run_bytes + 15) / 16 * 16; // the bytes of L records, as a staged region would hold them
+        d.npad = (d.n + L - 1) / L * L;
+        if (opt && opt->path != LLAMA_PATH_AUTO && opt->path != LLAMA_PATH_TILE)
+            return false;
+    }
+    rq.dst = d;
+    try {
         out.plan = std::make_shared<Plan>(make_plan(rq, opt));
     } catch (const Error&) {
         return false;
@@ -603,18 +707,48 @@ std::vector<SubCopy> split_copies(const llama_mapping_desc* src, const llama_map
     const std::vector<Part> sp = parts_of(src, whole.record);
     const std::vector<Part> dp = parts_of(dst, whole.record);
     std::vector<SubCopy> out;
-    for (const Part& P : dp) {
+    // per destination part, the source parts that share leaves with it, with
+    // those leaves
+    std::vector<PartLeaves> feeds(dp.size());
+    for (size_t p = 0; p < dp.size(); p++) {
+        const Part& P = dp[p];
         if (P.side.kind == LLAMA_ONE)
             fail(LLAMA_E_UNSUPPORTED, "a One part holds a single record and cannot receive a copy of many");
-        // the source parts that share leaves with P, with those leaves
-        std::vector<std::pair<const Part*, std::vector<uint32_t>>> from;
         for (const Part& Q : sp) {
             std::vector<uint32_t> both;
             std::set_intersection(P.leaves.begin(), P.leaves.end(), Q.leaves.begin(), Q.leaves.end(),
                                   std::back_inserter(both));
             if (!both.empty())
-                from.emplace_back(&Q, std::move(both));
+                feeds[p].emplace_back(&Q, std::move(both));
         }
+    }
+    // a source part that feeds several destination parts: one copy into all
+    // the record-major ones it alone feeds and the field-major ones it feeds
+    // (it then reads its blobs once); those feeds are done
+    if (gather) {
+        for (const Part& Q : sp) {
+            PartLeaves to;
+            std::vector<size_t> idx;
+            for (size_t p = 0; p < dp.size(); p++)
+                for (const auto& fq : feeds[p])
+                    if (fq.first == &Q && (feeds[p].size() == 1 || effective_lanes(dp[p].side) == 0)) {
+                        to.emplace_back(&dp[p], fq.second);
+                        idx.push_back(p);
+                    }
+            SubCopy g;
+            if (to.size() > 1 && scattered_copy(Q, to, whole, options, g)) {
+                out.push_back(std::move(g));
+                for (size_t p : idx)
+                    feeds[p].erase(std::find_if(feeds[p].begin(), feeds[p].end(),
+                                                [&](const auto& fq) { return fq.first == &Q; }));
+            }
+        }
+    }
+    for (size_t p = 0; p < dp.size(); p++) {
+        if (feeds[p].empty())
+            continue;
+        const Part& P = dp[p];
+        PartLeaves from = feeds[p];
         if (gather && from.size() > 1) {
             SubCopy g;
             if (gathered_copy(from, P, whole, options, g)) {
@@ -939,6 +1073,8 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
                  (a.dst.mode == kFieldMajor ? e.dst_addr % sz == 0 : (e.dst_addr & 15) == 0) &&
                  lowbit(src_bits | 16) >= sz;
     }
+    if (!rq.dst_stride.empty() && (!direct || a.dst.mode != kRecordMajor))
+        return false; // a scattered destination is stored by the direct-store tile only
     if (direct) {
         a.flags |= kTileDirectStore;
         a.dst.lds_bytes = 0;
@@ -947,7 +1083,15 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
             TileEntry& e = ta.e[f];
             const uint32_t phase = a.dst.mode == kFieldMajor ? uint32_t((e.dst_addr & 15) / e.size) : 0u;
             e.move = (e.move & ~(7u | kMoveSplit | (0xFFu << 20))) | log2_exact(e.size) | (phase << 20);
+            if (!rq.dst_stride.empty()) {
+                // the leaf's runs in its own part
+                e.dst_pos = rq.dst_stride[f];
+                if (rq.dst_values_only[f])
+                    e.move |= kMoveValuesOnly;
+            }
         }
+        if (!rq.dst_stride.empty())
+            a.flags |= kTileVirtualDst;
     }
     const bool preserve = preserve_padding(rq, p);
     // gather store: a record-major destination, every tile span 16-byte
@@ -1197,7 +1341,7 @@ Plan make_plan(const Request& rq, const llama_copy_options* opt)
     if (needs_box(rq))
         fail(LLAMA_E_UNSUPPORTED, "the two views place records at different linear indices (differing "
                                   "linearizers, or Morton holes): copy them with llama_copy or llama_copy_box");
-    if (rq.chunks.empty() && (!opt || (opt->path == LLAMA_PATH_AUTO && opt->tile_records == 0))) {
+    if (rq.chunks.empty() && rq.dst_stride.empty() && (!opt || (opt->path == LLAMA_PATH_AUTO && opt->tile_records == 0))) {
         llama_copy_options tuned;
         if (tune_lookup(tune_key(rq), tuned)) {
             if (opt && opt->threads)
@@ -1250,10 +1394,13 @@ Plan make_plan_raw(const Request& rq, const llama_copy_options* opt)
         fill_naive(rq, p);
         return p;
     }
-    if (!rq.chunks.empty()) {
-        // a gathered source exists only for the tile kernel
+    if (!rq.chunks.empty() || !rq.dst_stride.empty()) {
+        // a gathered source or scattered destination exists only for the tile kernel
         if (want != LLAMA_PATH_AUTO && want != LLAMA_PATH_TILE)
-            fail(LLAMA_E_UNSUPPORTED, "a source gathered from several parts is copied by the TILE path only");
+            fail(LLAMA_E_UNSUPPORTED, "copies gathered from or scattered to several parts take the TILE path only");
+        if (!rq.chunks.empty() && !rq.dst_stride.empty())
+            fail(LLAMA_E_UNSUPPORTED, "a copy gathers several source parts or scatters to several destination "
+                                      "parts, not both");
         want = LLAMA_PATH_TILE;
     }
     if (want == LLAMA_PATH_AUTO || want == LLAMA_PATH_STREAM) {

@@ -109,6 +109,13 @@ struct Request {
     // record-major side of virtual blocks whose leaves sit at their chunk's
     // place (planned as TILE only)
     std::vector<SrcChunk> chunks;
+    // non-empty: the destination is scattered over several parts, and dst is
+    // a record-major side of L lanes whose leaf j's runs of L values lie
+    // dst_stride[j] bytes apart in its own part (planned as a direct-store
+    // tile only); dst_values_only[j]: an SoA leaf, written for records with
+    // values only
+    std::vector<uint32_t> dst_stride;
+    std::vector<uint8_t> dst_values_only;
 };
 
 // Checks a side's blob array (sizes, NULL pointers, address overflow) and
@@ -128,7 +135,8 @@ struct Plan;
 struct SubCopy {
     Request rq;
     bool naive = false;
-    // a copy from several source parts at once, already planned (`plan`)
+    // a copy from several source parts at once, or into several destination
+    // parts at once, already planned (`plan`)
     bool gathered = false;
     std::shared_ptr<Plan> plan;
 };

@@ -106,7 +106,8 @@ struct TileHeader {
     uint32_t num_entries; // leaves, then gaps
     uint32_t lds_bytes;
     uint32_t flags;       // kTileDirectStore, kTileDirectLoad, kTilePreserve, kTileGatherStore,
-                          // kTileStreamStores, kTileStreamLoads, kTileGatherOdd, kTileVirtualSrc
+                          // kTileStreamStores, kTileStreamLoads, kTileGatherOdd, kTileVirtualSrc,
+                          // kTileVirtualDst
     uint32_t slots;       // kTileDirectLoad: granule slots of a tile (a multiple of 64);
                           // kTileVirtualSrc: the chunks after the entries
     TileSide src, dst;
@@ -178,6 +179,16 @@ constexpr uint32_t kTileGatherOdd = 64;
 // per virtual block.  Direct load is never combined with it.
 constexpr uint32_t kTileVirtualSrc = 128;
 constexpr uint32_t kTileMaxChunks = 32;
+
+// A destination scattered over several parts (a Split destination, sec.
+// 3.7), stored in direct-store mode only: every leaf's values of a tile are
+// runs of L values (L * size a multiple of 16 bytes) in its own part, one run
+// per L records, `dst_pos` bytes apart (an AoSoA part's block, or L values of
+// an SoA leaf); dst_addr is the leaf's first value.  A leaf of an SoA part
+// (kMoveValuesOnly in `move`) ends at the last record with values; an AoSoA
+// part's tail lanes are zero.
+constexpr uint32_t kTileVirtualDst = 256;
+constexpr uint32_t kMoveValuesOnly = 1u << 30;
 
 // The gather geometry follows the entries, so that the header and entries
 // keep their offsets in the argument block (entries 16-byte aligned; a

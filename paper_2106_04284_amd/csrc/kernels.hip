@@ -433,23 +433,35 @@ __device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t s
 }
 
 // Direct store of a tile: every leaf in turn, at the width of its values.
-template <bool kDstRecordMajor, bool kStream, bool kCount, typename Entries>
+// kVirtualDst: each leaf's runs of L values lie in its own part, e.dst_pos
+// bytes apart (kTileVirtualDst).
+template <bool kDstRecordMajor, bool kStream, bool kCount, bool kVirtualDst = false, typename Entries>
 __device__ __forceinline__ void direct_store_tile(const TileHeader& h, Entries ent, uint64_t t, uint64_t i0,
                                                   uint32_t nv, uint32_t nd, uint32_t tid, uint32_t nthr,
                                                   const uint8_t* lds)
 {
     for (uint32_t f = 0; f < h.num_leaves; f++) {
         const auto& e = ent(f);
-        const uint64_t gdst = leaf_tile_base<kDstRecordMajor>(e.dst_addr, h.dst, t, i0, e.size);
+        TileSide d = h.dst;
+        uint64_t gdst;
+        uint32_t ne = nd;
+        if constexpr (kVirtualDst) {
+            d.block = e.dst_pos;
+            gdst = e.dst_addr + t * (uint64_t(e.dst_pos) << (h.log2_tile - h.dst.log2_lanes));
+            if (e.move & kMoveValuesOnly)
+                ne = nv;
+        } else {
+            gdst = leaf_tile_base<kDstRecordMajor>(e.dst_addr, h.dst, t, i0, e.size);
+        }
         const uint32_t rot = (e.move >> 8) & 4095u;
         const uint32_t ph = (e.move >> 20) & 15u;
         const uint32_t sp = e.src_pos;
         switch (e.move & 7u) {
-        case 4: direct_store_leaf<u32x4, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
-        case 3: direct_store_leaf<uint64_t, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
-        case 2: direct_store_leaf<uint32_t, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
-        case 1: direct_store_leaf<uint16_t, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
-        default: direct_store_leaf<uint8_t, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, h.dst, gdst, nv, nd, tid, nthr, rot, ph); break;
+        case 4: direct_store_leaf<u32x4, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, d, gdst, nv, ne, tid, nthr, rot, ph); break;
+        case 3: direct_store_leaf<uint64_t, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, d, gdst, nv, ne, tid, nthr, rot, ph); break;
+        case 2: direct_store_leaf<uint32_t, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, d, gdst, nv, ne, tid, nthr, rot, ph); break;
+        case 1: direct_store_leaf<uint16_t, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, d, gdst, nv, ne, tid, nthr, rot, ph); break;
+        default: direct_store_leaf<uint8_t, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, d, gdst, nv, ne, tid, nthr, rot, ph); break;
         }
     }
 }
@@ -637,6 +649,9 @@ constexpr uint32_t kModeCount = 32;
 // added to a mode: the source region is gathered from several parts
 // (kTileVirtualSrc)
 constexpr uint32_t kModeVirtualSrc = 64;
+// added to kModeDirectStore: the destination is scattered over several parts
+// (kTileVirtualDst)
+constexpr uint32_t kModeVirtualDst = 128;
 
 template <uint32_t ModeBits, typename Entries>
 __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint64_t t, uint8_t* lds,
@@ -647,6 +662,7 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     constexpr bool kOnce = (ModeBits & kModeStreamLoads) != 0;
     constexpr bool kCount = (ModeBits & kModeCount) != 0;
     constexpr bool kVirtual = (ModeBits & kModeVirtualSrc) != 0;
+    constexpr bool kVirtualDst = (ModeBits & kModeVirtualDst) != 0;
     const bool dload = Mode == kModeDirectLoad || (Mode == kModeAny && (h.flags & kTileDirectLoad));
     const bool dstore = Mode == kModeDirectStore || (Mode == kModeAny && (h.flags & kTileDirectStore));
     const bool gstore = Mode == kModeGatherStore || Mode == kModeGatherOdd ||
@@ -718,7 +734,9 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     if (dstore) {
         // ---- 2'. gather each destination granule from the source region and
         //          store it; no destination region, no second barrier
-        if (h.dst.mode == kRecordMajor)
+        if (kVirtualDst)
+            direct_store_tile<true, kStream, kCount, true>(h, ent, t, i0, nv, ns, tid, nthr, lds);
+        else if (h.dst.mode == kRecordMajor)
             direct_store_tile<true, kStream, kCount>(h, ent, t, i0, nv, ns, tid, nthr, lds);
         else
             direct_store_tile<false, kStream, kCount>(h, ent, t, i0, nv, ns, tid, nthr, lds);
@@ -1864,6 +1882,14 @@ const void* const kTileVirtualKernels[3 * kTileModes] = {
     (const void*)tile_kernel<kModeStaged | kV | kLdSt>, (const void*)tile_kernel<kModeDirectStore | kV | kLdSt>, nullptr,
     (const void*)tile_kernel<kModeGatherStore | kV | kLdSt>, (const void*)tile_kernel<kModeGatherOdd | kV | kLdSt>};
 
+// direct store into a destination scattered over several parts
+// (kTileVirtualDst): plain, nontemporal loads, nontemporal loads and stores;
+// then the counted variant
+constexpr uint32_t kVD = kModeDirectStore | kModeVirtualDst;
+const void* const kTileScatterKernels[4] = {(const void*)tile_kernel<kVD>, (const void*)tile_kernel<kVD | kLd>,
+                                            (const void*)tile_kernel<kVD | kLdSt>,
+                                            (const void*)tile_count_kernel<kVD>};
+
 const void* const kTileVirtualCountKernels[kTileModes] = {
     (const void*)tile_count_kernel<kModeStaged | kV>, (const void*)tile_count_kernel<kModeDirectStore | kV>, nullptr,
     (const void*)tile_count_kernel<kModeGatherStore | kV>, (const void*)tile_count_kernel<kModeGatherOdd | kV>};
@@ -1966,8 +1992,10 @@ void launch(const Plan& p, void* stream_ptr)
                                   : (f & kTileGatherStore) ? ((f & kTileGatherOdd) ? kModeGatherOdd : kModeGatherStore)
                                                            : kModeStaged;
             k = (f & kTileVirtualSrc) ? kTileVirtualCountKernels[mode - 1] : kTileCountKernels[mode - 1];
+            if (f & kTileVirtualDst)
+                k = mode == kModeDirectStore && !(f & kTileVirtualSrc) ? kTileScatterKernels[3] : nullptr;
             if (!k)
-                fail(LLAMA_E_INVALID_ARG, "a gathered source never loads directly");
+                fail(LLAMA_E_INVALID_ARG, "no kernel variant for this combination of gathered parts");
             lds = p.tile.h.lds_bytes;
         } else if (p.path == LLAMA_PATH_STREAM) {
             k = (const void*)stream_count_kernel;
@@ -1997,8 +2025,10 @@ void launch(const Plan& p, void* stream_ptr)
         // or more has a source of far more than 256 MB in every layout pair)
         const uint32_t variant = (f & kTileStreamStores) ? 2 : (f & kTileStreamLoads) ? 1 : 0;
         const void* k = ((f & kTileVirtualSrc) ? kTileVirtualKernels : kTileKernels)[(mode - 1) + kTileModes * variant];
+        if (f & kTileVirtualDst)
+            k = mode == kModeDirectStore && !(f & kTileVirtualSrc) ? kTileScatterKernels[variant] : nullptr;
         if (!k)
-            fail(LLAMA_E_INVALID_ARG, "a gathered source never loads directly");
+            fail(LLAMA_E_INVALID_ARG, "no kernel variant for this combination of gathered parts");
         void* args[] = {(void*)&p.tile};
         check_hip(hipLaunchKernel(k, dim3(grid), dim3(p.threads), args, p.tile.h.lds_bytes, stream),
                   "hipLaunchKernel(tile_kernel)");

@@ -496,6 +496,7 @@ def copy_naive(src: Mapping, src_blobs, dst: Mapping, dst_blobs, stream=None):
 
 PLAN_GATHERED_SOURCE = 1
 PLAN_KEEPS_DESTINATION = 2
+PLAN_SCATTERED_DESTINATION = 4
 
 
 def _info_dict(info: PlanInfo) -> dict:
@@ -507,6 +508,7 @@ def _info_dict(info: PlanInfo) -> dict:
             "stream_stores": bool(info.cache_hints & 2),
             "gathered_source": bool(info.plan_flags & PLAN_GATHERED_SOURCE),
             "keeps_destination": bool(info.plan_flags & PLAN_KEEPS_DESTINATION),
+            "scattered_destination": bool(info.plan_flags & PLAN_SCATTERED_DESTINATION),
             "source_chunks": info.source_chunks}
 
 

@@ -660,9 +660,19 @@ def test_plan_copy_lists_every_launch():
     s4 = L.Mapping(rg, "split", [n], split=(0, 3, ("aos_aligned", 0), ("soa_multi", 0)))
     k = L.plan_copy(s4, aos)
     assert len(k) == 2 and not k[0]["keeps_destination"] and k[1]["keeps_destination"]
-    # a Split destination: one launch per destination part here
-    d = L.plan_copy(q32, s1)
-    assert len(d) == 2 and all(p["path"] != "naive" for p in d)
+    # a Split destination fed by one source part: one copy scattering into
+    # both parts; from a plain AoSoA32 source as well
+    d = L.plan_copy(aos, s1)
+    assert len(d) == 1 and d[0]["scattered_destination"] and d[0]["tile_mode"] == "direct_store"
+    assert len(L.plan_copy(q32, s1)) == 1
+    # an aligned AoS part feeding AoSoA32 positions and an SoA mass, its SoA
+    # velocities feeding the SoA velocities: one scattered copy, one stream
+    s2 = L.Mapping(rg, "split", [n], split=(3, 3, ("soa_multi", 0), ("aos_aligned", 0)))
+    d2 = L.plan_copy(s2, s1)
+    assert len(d2) == 2 and d2[0]["scattered_destination"] and d2[1]["path"] == "stream"
+    assert d2[0]["read_bytes"] == n * 16
+    # without direct store there is no scattered copy
+    assert not any(p["scattered_destination"] for p in L.plan_copy(aos, s1, flags=L.COPY_NO_DIRECT))
     # differing records: keep the mass of a packed AoS destination
     rs = L.Record(W.PARTICLE[:2])
     lv = L.plan_copy(L.Mapping(rs, "soa_multi", [n]), aos, src_leaf=[0, 1, 2, 3, 4, 5, None])

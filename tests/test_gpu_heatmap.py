@@ -152,7 +152,9 @@ def test_trace_sums_per_leaf(L, orc):
 def test_heatmap_split_parts(L, orc):
     """A copy into a Split destination writes each byte once when each of its
     parts comes from one source part, or from several source parts gathered
-    into one tile copy (SoA parts; AoSoA and SoA parts of one lane count).
+    into one tile copy (SoA parts; AoSoA and SoA parts of one lane count), or
+    when one source part feeds several destination parts through one copy
+    that scatters its stores.
     An AoS part fed by an AoS part and 4-byte SoA leaves cannot be gathered
     (a one-record virtual block would hold 4-byte chunks, not whole 16-byte
     granules): its second part copy rewrites the first one's bytes (read and
@@ -165,7 +167,10 @@ def test_heatmap_split_parts(L, orc):
               True),
              (("split", (0, 3, ("soa_multi", 0), ("soa_single", 0))), ("aos_packed", 0), True),
              (("split", (0, 3, ("aosoa", 32), ("soa_multi", 0))), ("aos_packed", 0), True),
-             (("split", (0, 3, ("aos_aligned", 0), ("soa_multi", 0))), ("aos_packed", 0), False)]
+             (("split", (0, 3, ("aos_aligned", 0), ("soa_multi", 0))), ("aos_packed", 0), False),
+             (("aos_packed", 0), ("split", (0, 3, ("aosoa", 32), ("soa_multi", 0))), True),
+             (("split", (3, 3, ("soa_multi", 0), ("aos_aligned", 0))),
+              ("split", (0, 3, ("aosoa", 32), ("soa_multi", 0))), True)]
     for a, b, once in cases:
         def mk(mod, r, lay):
             return mod.Mapping(r, "split", [n], split=lay[1]) if lay[0] == "split" else mod.Mapping(r, lay[0], [n], lay[1])

@@ -209,6 +209,43 @@ def test_split_source_gathered_options(L, orc, opts):
         _run(L, orc, rec, src, dst, [n], seed=50 + k, keep=keep, **opts)
 
 
+SCATTERED = [(name, src, split, n) for name in ("particle", "mixed", "lbm")
+             for src in (("aos_packed", 0), ("aos_aligned", 0), ("aosoa", 8), ("soa_single", 0),
+                         ("split", (3, 3, ("soa_multi", 0), ("aos_aligned", 0))))
+             for split in (("split", (0, 3, ("aosoa", 32), ("soa_multi", 0))),
+                           ("split", (1, 2, ("soa_single", 0), ("aosoa", 64))),
+                           ("split", (0, 2, ("soa_multi", 0), ("soa_single", 0))))
+             for n in (1, 33, 4099)]
+
+
+@pytest.mark.parametrize("case", SCATTERED, ids=lambda c: f"{c[0]}-{_id(('', c[1], c[2], [c[3]]))}")
+def test_split_destination_scattered(L, orc, case):
+    """A source part feeding several destination parts, copied by one tile
+    copy whose stores scatter each leaf's granules into its own part (AoSoA
+    parts of one lane count, SoA leaves), or into one field-major side (SoA
+    parts), where the layouts allow it, else part by part: the oracle's
+    bytes either way, AoSoA tail lanes zero and nothing past an SoA leaf's
+    last record written."""
+    name, src, split, n = case
+    print(f"split scattered {case}", flush=True)
+    _run(L, orc, W.RECORDS[name], src, split, [n], seed=n + 5)
+
+
+@pytest.mark.parametrize("opts", [dict(flags=1), dict(keep=True), dict(threads=256), dict(tile_records=16),
+                                  dict(tile_records=2048), dict(wg_per_cu=3)],
+                         ids=["no_direct", "keep", "t256", "T16", "T2048", "persistent"])
+def test_split_destination_scattered_options(L, orc, opts):
+    """Options reach the scattered copy (no direct store, or a tile smaller
+    than the destination's lanes, falls back to part copies)."""
+    opts = dict(opts)
+    keep = opts.pop("keep", False)
+    dst = ("split", (0, 3, ("aosoa", 32), ("soa_multi", 0)))
+    for k, (rec, src, n) in enumerate([(W.PARTICLE, ("aos_packed", 0), 5003), (W.MIXED, ("aos_aligned", 0), 2049),
+                                       (W.LBM, ("split", (3, 3, ("soa_multi", 0), ("aos_aligned", 0))), 777)]):
+        print(f"split scattered options {opts} keep={keep} case {k}", flush=True)
+        _run(L, orc, rec, src, dst, [n], seed=60 + k, keep=keep, **opts)
+
+
 ONE_CASES = [(name, dst, n) for name in ("particle", "mixed", "lbm", "listing1")
              for dst in PLAIN for n in (1, 3001)]
 
