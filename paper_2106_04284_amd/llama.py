@@ -584,7 +584,7 @@ class _Items:
         self.arr = (CopyItem * max(len(items), 1))()
         for k, (src, sblobs, dst, dblobs) in enumerate(items):
             sb, db = _blobs(sblobs), _blobs(dblobs)
-            self.keep += [src, dst, sb, db]
+            self.keep += [src, dst, sb, db, sblobs, dblobs]  # the blob tensors live as long as the items
             self.arr[k] = CopyItem(ctypes.pointer(src.desc), ctypes.cast(sb, ctypes.POINTER(Blob)),
                                    ctypes.pointer(dst.desc), ctypes.cast(db, ctypes.POINTER(Blob)))
         self.n = len(items)
@@ -711,10 +711,19 @@ class Server:
         check(lib().llama_server_create_ex(ctypes.byref(cfg), ctypes.byref(self._exec), ctypes.byref(self._h)))
 
     def submit(self, src: Mapping, src_blobs, dst: Mapping, dst_blobs) -> int:
-        it = _Items([(src, src_blobs, dst, dst_blobs)])
+        return self.submit_prepared(Server.prepare(src, src_blobs, dst, dst_blobs))
+
+    @staticmethod
+    def prepare(src: Mapping, src_blobs, dst: Mapping, dst_blobs):
+        """The request's C structures, built once: submit_prepared then only
+        calls llama_server_submit (a client that replays many requests keeps
+        their marshalling out of its timing)."""
+        return _Items([(src, src_blobs, dst, dst_blobs)])
+
+    def submit_prepared(self, prepared) -> int:
         t = ctypes.c_uint64()
-        check(lib().llama_server_submit(self._h, it.arr, ctypes.byref(t)))
-        self._keep[t.value] = (it, src_blobs, dst_blobs)
+        check(lib().llama_server_submit(self._h, prepared.arr, ctypes.byref(t)))
+        self._keep[t.value] = prepared
         return t.value
 
     def poll(self, ticket):
