@@ -16,6 +16,8 @@ extras.batch_1000_arrays, the batching workload below (one graph-captured
 launch against 1,000 naive and 1,000 llama_copy launches on the same GPU).
 
 Other workloads (--workload):
+  pairs  the 42 layout pairs of one record (--record, --records; per-pair
+         figures with --details);
   lbm    128^3 cells of 19 f64 + u32, aligned AoS <-> SoA multi-blob <->
          AoSoA32, each copy started cold (1 GiB read before it);
   batch  1,000 arrays of log-uniform size and mixed record types as one
@@ -841,8 +843,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="particle",
-                    choices=["particle", "lbm", "split", "leaves", "batch", "serve", "pic", "box", "linearize",
-                             "transfer"])
+                    choices=["particle", "pairs", "lbm", "split", "leaves", "batch", "serve", "pic", "box",
+                             "linearize", "transfer"])
+    ap.add_argument("--record", default="mixed", choices=sorted(W.RECORDS), help="pairs: the record")
+    ap.add_argument("--records", type=int, default=1 << 23, help="pairs: records per layout")
     ap.add_argument("--requests", type=int, default=20000, help="serve: measured requests (after 200 warm-up)")
     ap.add_argument("--rho", type=float, default=0.8, help="serve: offered load as a fraction of batched GB/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -899,6 +903,19 @@ def main():
                    "42 ordered pairs of packed AoS, aligned AoS, SoA single-blob, SoA multi-blob, AoSoA8/32/64"
         dtype = "u32"
         cpu_n = 1 << 19
+        cpu_full = n
+    elif args.workload == "pairs":
+        # every ordered pair of the seven layouts for one record at a given
+        # size (per-pair figures with --details)
+        n = args.records
+        record, extents = W.RECORDS[args.record], [n]
+        layouts = W.LAYOUTS
+        pairs = [(a, b) for a in layouts for b in layouts if a != b]
+        values = W.typed_random_values(W.leaf_types(record), n, W.BASE_SEED + 7)
+        workload = f"{args.record} record, {n} records, 42 ordered pairs of packed AoS, aligned AoS, SoA " \
+                   "single-blob, SoA multi-blob, AoSoA8/32/64"
+        dtype = "u8"
+        cpu_n = min(n, 1 << 17)
         cpu_full = n
     elif args.workload == "split":
         # Split mappings (sec. 3.7) of the particle: positions as AoSoA32 with

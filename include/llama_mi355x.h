@@ -197,28 +197,41 @@ typedef struct {
  *  - src_blobs / dst_blobs hold blob_count entries of their mapping.
  *  - No source range may overlap a destination range.
  *  - Every byte of every destination blob up to the mapping's blob size is
- *    written exactly once (a Split destination part fed by several source
- *    parts excepted, see below): leaf values from the source, and zero for
+ *    written exactly once (a Split destination part fed by several copies
+ *    excepted, see below): leaf values from the source, and zero for
  *    the destination's padding (alignment gaps of aligned AoS, lanes past the
  *    last record in the last AoSoA block, Morton indices that no coordinate
  *    reaches).  llama_copy_heatmap counts it.
  *  - A data space with zero records enqueues nothing and returns LLAMA_OK.
- *  - A Split on either side runs as one copy per pair of parts that share
- *    leaves, in order on `stream`.  Into a record-major destination part
- *    (AoS, AoSoA) fed by several source parts, the copy with the most bytes
- *    writes whole records first (the other leaves' bytes as zeros, or kept
- *    with LLAMA_COPY_PRESERVE_PADDING); each later copy into an AoS part
- *    without padding reads the part's records into LDS, replaces its own
- *    leaves and stores the records back whole, so those bytes are written
- *    more than once and nothing else may write the destination while the
- *    copy runs.  A later copy into another record-major part stores only its
- *    own leaves (a direct-store tile, else the element-wise path).  Every
- *    other pair is planned like a plain copy.  Batches and the
- *    batched server policy take a Split item as its pairs, side by side,
- *    unless one of them writes part of the records of a record-major
- *    destination part or reads a One part (LLAMA_E_UNSUPPORTED); the other
- *    server policies run its pairs in order.  Plans, autotuning and servers
- *    with an executor take plain mappings only (LLAMA_E_UNSUPPORTED). */
+ *  - A Split on either side runs as a few tile copies, in order on `stream`
+ *    (llama_plan_copy lists them):
+ *     - a destination part fed by several source parts is one copy whose
+ *       source gathers those parts, when the record-major ones share one
+ *       lane count and every chunk (a part block, or that many values of an
+ *       SoA leaf) is whole 16-byte granules at a 16-byte aligned address, or
+ *       when all are SoA (LLAMA_PLAN_GATHERED_SOURCE);
+ *     - a source part feeding several destination parts (each taking all its
+ *       leaves from it, or SoA) is one copy whose stores scatter over those
+ *       parts, when the record-major ones are AoSoA parts of one lane count
+ *       with runs of 128 bytes or more at 16-byte aligned addresses, or all
+ *       are SoA (LLAMA_PLAN_SCATTERED_DESTINATION);
+ *     - every other pair of parts that share leaves is one copy.  Into a
+ *       record-major destination part (AoS, AoSoA) fed by several such
+ *       copies, the one with the most bytes writes whole records first (the
+ *       other leaves' bytes as zeros, or kept with
+ *       LLAMA_COPY_PRESERVE_PADDING); each later copy into an AoS part
+ *       without padding reads the part's records into LDS, replaces its own
+ *       leaves and stores the records back whole
+ *       (LLAMA_PLAN_KEEPS_DESTINATION), so those bytes are written more than
+ *       once and nothing else may write the destination while the copy
+ *       runs.  A later copy into another record-major part stores only its
+ *       own leaves (a direct-store tile, else the element-wise path).
+ *    Batches and the batched server policy take a Split item as one copy per
+ *    pair of parts, side by side, unless one of them writes part of the
+ *    records of a record-major destination part or reads a One part
+ *    (LLAMA_E_UNSUPPORTED); the other server policies run its copies in
+ *    order.  llama_plan, autotuning and servers with an executor take plain
+ *    mappings only (LLAMA_E_UNSUPPORTED). */
 int llama_copy(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,
                const llama_blob* dst_blobs, void* stream);
 
@@ -258,7 +271,10 @@ typedef struct {
 
 /* TILE: move a misaligned value byte by byte (by default a 2-, 4- or 8-byte
  * value of a packed record of odd size is read whole from the words that hold
- * it and written in pieces of the destination's alignment). */
+ * it and written in pieces of the destination's alignment), and take neither
+ * the direct store of such values from their aligned words nor the direct
+ * load that writes them (or 1- and 2-byte leaves) into the region in pieces:
+ * those pairs stage both regions. */
 #define LLAMA_COPY_NO_SPLIT 2u
 
 /* Keep the destination's padding bytes (aligned-AoS gaps and record tails,

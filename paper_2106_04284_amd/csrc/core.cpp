@@ -1064,14 +1064,22 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
     // destination's lane runs start 16-byte aligned, a field-major leaf span
     // may start at any multiple of its size (its phase in the granule grid:
     // the partial first and last granules are written value by value)
+    // A source value aligned below its size (a packed record of odd size) is
+    // read from the aligned words that hold it (kTileSplitSrc), for leaves of
+    // 2, 4 and 8 bytes, unless LLAMA_COPY_NO_SPLIT; a scattered destination
+    // keeps aligned reads.
+    const bool split_ok = !(p.flags_in & kPlanNoSplit) && rq.dst_stride.empty();
     bool direct = rq.dst.gaps.empty() && !(p.flags_in & kPlanNoDirect);
+    bool split_src = false;
     for (size_t f = 0; f < F && direct; f++) {
         const TileEntry& e = ta.e[f];
         const uint32_t sz = e.size;
         const uint64_t src_bits = uint64_t(e.src_pos) | sz | src_rm_bits;
+        const bool aligned = lowbit(src_bits | 16) >= sz;
         direct = sz <= 16 && (sz & (sz - 1)) == 0 && granule_runs(a.dst, sz) &&
                  (a.dst.mode == kFieldMajor ? e.dst_addr % sz == 0 : (e.dst_addr & 15) == 0) &&
-                 lowbit(src_bits | 16) >= sz;
+                 (aligned || (split_ok && sz >= 2 && sz <= 8));
+        split_src = split_src || !aligned;
     }
     if (!rq.dst_stride.empty() && (!direct || a.dst.mode != kRecordMajor))
         return false; // a scattered destination is stored by the direct-store tile only
@@ -1079,10 +1087,15 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
         a.flags |= kTileDirectStore;
         a.dst.lds_bytes = 0;
         a.lds_bytes = sb;
+        if (split_src)
+            a.flags |= kTileSplitSrc;
         for (size_t f = 0; f < F; f++) { // the width is the leaf size; the phase replaces the split bits
             TileEntry& e = ta.e[f];
             const uint32_t phase = a.dst.mode == kFieldMajor ? uint32_t((e.dst_addr & 15) / e.size) : 0u;
-            e.move = (e.move & ~(7u | kMoveSplit | (0xFFu << 20))) | log2_exact(e.size) | (phase << 20);
+            // the source alignment (kTileSplitSrc)
+            const uint32_t rd = log2_move(uint64_t(e.src_pos) | e.size | src_rm_bits);
+            e.move = (e.move & ~(7u | kMoveSplit | (0xFFu << 20))) | log2_exact(e.size) | (phase << 20) |
+                     (split_src ? std::min<uint32_t>(rd, 7u) << 24 : 0u);
             if (!rq.dst_stride.empty()) {
                 // the leaf's runs in its own part
                 e.dst_pos = rq.dst_stride[f];
@@ -1203,28 +1216,37 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
     // (a kept destination padding needs the destination region loaded first)
     if (preserve)
         a.flags |= kTilePreserve;
+    // (leaves of 1 or 2 bytes, and destination values aligned below their
+    // size, are written into the region in pieces: kTileSplitDst, unless
+    // LLAMA_COPY_NO_SPLIT)
     bool dload = !direct && !(a.flags & kTileGatherStore) && !preserve && !(p.flags_in & kPlanNoDirect) && C == 0;
+    bool split_dst = false;
     uint32_t slots = 0;
-    std::vector<uint32_t> first(F, 0);
+    std::vector<uint32_t> first(F, 0), wr_of(F, 0);
     for (size_t f = 0; f < F && dload; f++) {
         const TileEntry& e = ta.e[f];
         const uint32_t sz = e.size;
         const uint64_t dst_bits = uint64_t(e.dst_pos) | (a.dst.mode == kRecordMajor ? rq.dst.block : 0);
-        dload = (sz == 4 || sz == 8 || sz == 16) && granule_runs(a.src, sz) && (e.src_addr & 15) == 0 &&
-                (lowbit(dst_bits | 16) >= sz);
+        const bool aligned = lowbit(dst_bits | 16) >= sz;
+        const bool whole = sz == 4 || sz == 8 || sz == 16;
+        dload = (sz == 1 || sz == 2 || whole) && granule_runs(a.src, sz) && (e.src_addr & 15) == 0 &&
+                ((aligned && whole) || (!(p.flags_in & kPlanNoSplit) && (sz <= 8 || aligned)));
+        split_dst = split_dst || !aligned || !whole;
+        wr_of[f] = std::min<uint32_t>(log2_move(dst_bits | sz), 7u);
         first[f] = slots;
-        const uint32_t granules = uint32_t((uint64_t(T) * sz) / 16);
+        const uint32_t granules = uint32_t((uint64_t(T) * sz + 15) / 16);
         slots += (granules + 63) / 64 * 64;
     }
     if (dload && slots <= kDirectLoadSlots * p.threads && p.threads % 64 == 0) {
-        a.flags |= kTileDirectLoad;
+        a.flags |= kTileDirectLoad | (split_dst ? kTileSplitDst : 0u);
         a.slots = slots;
         for (size_t f = 0; f < k; f++) {
             TileEntry& e = ta.e[f];
             e.dst_pos -= sb; // the destination region moves to the start of LDS
             if (f < F) {
                 e.src_pos = first[f];
-                e.move = log2_exact(e.size) | (e.move & ~(7u | kMoveSplit));
+                e.move = log2_exact(e.size) | (e.move & ~(7u | kMoveSplit | (7u << 24))) |
+                         (split_dst ? wr_of[f] << 24 : 0u);
             }
         }
         a.src.lds_bytes = 0;

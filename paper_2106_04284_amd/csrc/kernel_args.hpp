@@ -107,7 +107,7 @@ struct TileHeader {
     uint32_t lds_bytes;
     uint32_t flags;       // kTileDirectStore, kTileDirectLoad, kTilePreserve, kTileGatherStore,
                           // kTileStreamStores, kTileStreamLoads, kTileGatherOdd, kTileVirtualSrc,
-                          // kTileVirtualDst
+                          // kTileVirtualDst, kTileSplitSrc, kTileSplitDst
     uint32_t slots;       // kTileDirectLoad: granule slots of a tile (a multiple of 64);
                           // kTileVirtualSrc: the chunks after the entries
     TileSide src, dst;
@@ -189,6 +189,16 @@ constexpr uint32_t kTileMaxChunks = 32;
 // part's tail lanes are zero.
 constexpr uint32_t kTileVirtualDst = 256;
 constexpr uint32_t kMoveValuesOnly = 1u << 30;
+
+// Direct store from a source whose values sit below their size's alignment (a
+// packed record of odd size): leaves of 2, 4 or 8 bytes whose source position
+// is aligned to 2^a < size only carry a in bits 24-26 of `move` and are read
+// from the aligned 4-byte words that hold them.
+constexpr uint32_t kTileSplitSrc = 512;
+// Direct load into a destination region whose values sit below their size's
+// alignment, or with leaves of 1 or 2 bytes: every value is written into the
+// region in pieces of its alignment (bits 24-26 of `move`: log2 of it).
+constexpr uint32_t kTileSplitDst = 1024;
 
 // The gather geometry follows the entries, so that the header and entries
 // keep their offsets in the argument block (entries 16-byte aligned; a

@@ -398,10 +398,13 @@ __device__ __forceinline__ T src_value(const uint8_t* lds, uint32_t sp, const Ti
 // values past the 16-byte grid (the granules stay on the grid) and a granule
 // that passes record nd are stored value by value, only for records 0 .. nd
 // - 1 of the tile.  `gdst` is the leaf's tile base on side d.
-template <typename T, bool kDstRecordMajor, bool kStream, bool kCount>
+// kSplit: source values sit at positions aligned to 2^rd bytes only (a packed
+// record of odd size) and are read from the aligned words that hold them.
+template <typename T, bool kDstRecordMajor, bool kStream, bool kCount, bool kSplit = false>
 __device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t sp, const TileSide& s,
                                                   const TileSide& d, uint64_t gdst, uint32_t nv, uint32_t nd,
-                                                  uint32_t tid, uint32_t nthr, uint32_t rot, uint32_t ph)
+                                                  uint32_t tid, uint32_t nthr, uint32_t rot, uint32_t ph,
+                                                  uint32_t rd = 4)
 {
     constexpr uint32_t per = 16 / sizeof(T);
     const uint32_t G = (nd + ph + per - 1) / per;
@@ -415,7 +418,12 @@ __device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t s
 #pragma unroll
         for (uint32_t j = 0; j < per; j++) {
             const int32_t r = r0 + int32_t(j);
-            u.t[j] = r >= 0 && uint32_t(r) < nv ? src_value<T>(lds, sp, s, uint32_t(r), sizeof(T)) : T{};
+            if constexpr (kSplit && sizeof(T) >= 2 && sizeof(T) <= 8)
+                u.t[j] = r >= 0 && uint32_t(r) < nv
+                             ? read_split<T>(lds, sp + (uint32_t(r) >> s.pos_lg) * s.pos_k + (uint32_t(r) & s.pos_m) * sizeof(T), rd)
+                             : T{};
+            else
+                u.t[j] = r >= 0 && uint32_t(r) < nv ? src_value<T>(lds, sp, s, uint32_t(r), sizeof(T)) : T{};
         }
         constexpr uint32_t lg = sizeof(T) == 16 ? 4 : sizeof(T) == 8 ? 3 : sizeof(T) == 4 ? 2 : sizeof(T) == 2 ? 1 : 0;
         const uint64_t a = leaf_granule_addr<kDstRecordMajor>(gbase, d, g, lg);
@@ -435,7 +443,10 @@ __device__ __forceinline__ void direct_store_leaf(const uint8_t* lds, uint32_t s
 // Direct store of a tile: every leaf in turn, at the width of its values.
 // kVirtualDst: each leaf's runs of L values lie in its own part, e.dst_pos
 // bytes apart (kTileVirtualDst).
-template <bool kDstRecordMajor, bool kStream, bool kCount, bool kVirtualDst = false, typename Entries>
+// kSplit: leaves whose source positions are aligned below their size (bits
+// 24-26 of `move`: log2 of that alignment) are read from aligned words.
+template <bool kDstRecordMajor, bool kStream, bool kCount, bool kVirtualDst = false, bool kSplit = false,
+          typename Entries>
 __device__ __forceinline__ void direct_store_tile(const TileHeader& h, Entries ent, uint64_t t, uint64_t i0,
                                                   uint32_t nv, uint32_t nd, uint32_t tid, uint32_t nthr,
                                                   const uint8_t* lds)
@@ -456,6 +467,17 @@ __device__ __forceinline__ void direct_store_tile(const TileHeader& h, Entries e
         const uint32_t rot = (e.move >> 8) & 4095u;
         const uint32_t ph = (e.move >> 20) & 15u;
         const uint32_t sp = e.src_pos;
+        if constexpr (kSplit) {
+            const uint32_t rd = (e.move >> 24) & 7u;
+            switch (e.move & 7u) {
+            case 4: direct_store_leaf<u32x4, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, d, gdst, nv, ne, tid, nthr, rot, ph); break;
+            case 3: direct_store_leaf<uint64_t, kDstRecordMajor, kStream, kCount, true>(lds, sp, h.src, d, gdst, nv, ne, tid, nthr, rot, ph, rd); break;
+            case 2: direct_store_leaf<uint32_t, kDstRecordMajor, kStream, kCount, true>(lds, sp, h.src, d, gdst, nv, ne, tid, nthr, rot, ph, rd); break;
+            case 1: direct_store_leaf<uint16_t, kDstRecordMajor, kStream, kCount, true>(lds, sp, h.src, d, gdst, nv, ne, tid, nthr, rot, ph, rd); break;
+            default: direct_store_leaf<uint8_t, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, d, gdst, nv, ne, tid, nthr, rot, ph); break;
+            }
+            continue;
+        }
         switch (e.move & 7u) {
         case 4: direct_store_leaf<u32x4, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, d, gdst, nv, ne, tid, nthr, rot, ph); break;
         case 3: direct_store_leaf<uint64_t, kDstRecordMajor, kStream, kCount>(lds, sp, h.src, d, gdst, nv, ne, tid, nthr, rot, ph); break;
@@ -471,7 +493,10 @@ __device__ __forceinline__ void direct_store_tile(const TileHeader& h, Entries e
 // flight together), then writes the values to the destination region.
 // Records in [nv, nd) (AoSoA lanes past the last record) and gap entries are
 // zero-filled.
-template <bool kSrcRecordMajor, bool kOnce, bool kCount, typename Entries>
+// kSplit (kTileSplitDst): leaves of 1 and 2 bytes too, and destination
+// positions aligned below the leaf size (bits 24-26 of `move`: log2 of that
+// alignment), written in pieces of that alignment.
+template <bool kSrcRecordMajor, bool kOnce, bool kCount, bool kSplit = false, typename Entries>
 __device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries ent, uint64_t t, uint64_t i0,
                                                  uint32_t nv, uint32_t nd, uint8_t* lds)
 {
@@ -508,6 +533,35 @@ __device__ __forceinline__ void direct_load_tile(const TileHeader& h, Entries en
         if (g * 16u >= nv * size)
             continue;
         const uint32_t d0 = e.dst_pos + (r0 >> h.dst.pos_lg) * h.dst.pos_k + (r0 & h.dst.pos_m) * size;
+        if constexpr (kSplit) {
+            const uint32_t wr = (e.move >> 24) & 7u;
+            const uint32_t w[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
+            auto pos = [&](uint32_t r) { return e.dst_pos + (r >> h.dst.pos_lg) * h.dst.pos_k + (r & h.dst.pos_m) * size; };
+            if (size == 16) {
+                *(u32x4*)(lds + d0) = v[j];
+            } else if (size == 8) {
+#pragma unroll
+                for (uint32_t k = 0; k < 2; k++)
+                    if (r0 + k < nv)
+                        write_split<uint64_t>(lds, pos(r0 + k), (uint64_t(w[2 * k + 1]) << 32) | w[2 * k], wr);
+            } else if (size == 4) {
+#pragma unroll
+                for (uint32_t k = 0; k < 4; k++)
+                    if (r0 + k < nv)
+                        write_split<uint32_t>(lds, pos(r0 + k), w[k], wr);
+            } else if (size == 2) {
+#pragma unroll
+                for (uint32_t k = 0; k < 8; k++)
+                    if (r0 + k < nv)
+                        write_split<uint16_t>(lds, pos(r0 + k), uint16_t(w[k >> 1] >> (16u * (k & 1u))), wr);
+            } else {
+#pragma unroll
+                for (uint32_t k = 0; k < 16; k++)
+                    if (r0 + k < nv)
+                        lds[pos(r0 + k)] = uint8_t(w[k >> 2] >> (8u * (k & 3u)));
+            }
+            continue;
+        }
         if (size == 16) {
             *(u32x4*)(lds + d0) = v[j];
         } else if (size == 8) {
@@ -652,6 +706,12 @@ constexpr uint32_t kModeVirtualSrc = 64;
 // added to kModeDirectStore: the destination is scattered over several parts
 // (kTileVirtualDst)
 constexpr uint32_t kModeVirtualDst = 128;
+// added to kModeDirectStore: source values aligned below their size are read
+// from aligned words (kTileSplitSrc)
+constexpr uint32_t kModeSplitSrc = 256;
+// added to kModeDirectLoad: leaves of 1 and 2 bytes, and destination values
+// aligned below their size, written in pieces (kTileSplitDst)
+constexpr uint32_t kModeSplitDst = 512;
 
 template <uint32_t ModeBits, typename Entries>
 __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint64_t t, uint8_t* lds,
@@ -663,6 +723,11 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     constexpr bool kCount = (ModeBits & kModeCount) != 0;
     constexpr bool kVirtual = (ModeBits & kModeVirtualSrc) != 0;
     constexpr bool kVirtualDst = (ModeBits & kModeVirtualDst) != 0;
+    constexpr bool kSplitSrc = (ModeBits & kModeSplitSrc) != 0;
+    constexpr bool kSplitDst = (ModeBits & kModeSplitDst) != 0;
+    // the batch kernel (kModeAny) takes split reads and writes from the plan
+    const bool split_src = kSplitSrc || (Mode == kModeAny && (h.flags & kTileSplitSrc));
+    const bool split_dst = kSplitDst || (Mode == kModeAny && (h.flags & kTileSplitDst));
     const bool dload = Mode == kModeDirectLoad || (Mode == kModeAny && (h.flags & kTileDirectLoad));
     const bool dstore = Mode == kModeDirectStore || (Mode == kModeAny && (h.flags & kTileDirectStore));
     const bool gstore = Mode == kModeGatherStore || Mode == kModeGatherOdd ||
@@ -681,10 +746,16 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
 
     // ---- 1. source span(s) -> LDS
     if (dload) {
-        if (h.src.mode == kRecordMajor)
-            direct_load_tile<true, kOnce, kCount>(h, ent, t, i0, nv, nd, lds);
-        else
-            direct_load_tile<false, kOnce, kCount>(h, ent, t, i0, nv, nd, lds);
+        if (Mode == kModeAny && split_dst) {
+            if (h.src.mode == kRecordMajor)
+                direct_load_tile<true, kOnce, kCount, true>(h, ent, t, i0, nv, nd, lds);
+            else
+                direct_load_tile<false, kOnce, kCount, true>(h, ent, t, i0, nv, nd, lds);
+        } else if (h.src.mode == kRecordMajor) {
+            direct_load_tile<true, kOnce, kCount, kSplitDst>(h, ent, t, i0, nv, nd, lds);
+        } else {
+            direct_load_tile<false, kOnce, kCount, kSplitDst>(h, ent, t, i0, nv, nd, lds);
+        }
     } else if (nv > 0) {
         if (kVirtual) {
             load_virtual<kOnce, kCount>(h, ent, t, nv, wave, nwaves, lane, lds_base);
@@ -736,10 +807,14 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
         //          store it; no destination region, no second barrier
         if (kVirtualDst)
             direct_store_tile<true, kStream, kCount, true>(h, ent, t, i0, nv, ns, tid, nthr, lds);
+        else if (Mode == kModeAny && split_src && h.dst.mode == kRecordMajor)
+            direct_store_tile<true, kStream, kCount, false, true>(h, ent, t, i0, nv, ns, tid, nthr, lds);
+        else if (Mode == kModeAny && split_src)
+            direct_store_tile<false, kStream, kCount, false, true>(h, ent, t, i0, nv, ns, tid, nthr, lds);
         else if (h.dst.mode == kRecordMajor)
-            direct_store_tile<true, kStream, kCount>(h, ent, t, i0, nv, ns, tid, nthr, lds);
+            direct_store_tile<true, kStream, kCount, false, kSplitSrc>(h, ent, t, i0, nv, ns, tid, nthr, lds);
         else
-            direct_store_tile<false, kStream, kCount>(h, ent, t, i0, nv, ns, tid, nthr, lds);
+            direct_store_tile<false, kStream, kCount, false, kSplitSrc>(h, ent, t, i0, nv, ns, tid, nthr, lds);
         return;
     }
 
@@ -1890,6 +1965,15 @@ const void* const kTileScatterKernels[4] = {(const void*)tile_kernel<kVD>, (cons
                                             (const void*)tile_kernel<kVD | kLdSt>,
                                             (const void*)tile_count_kernel<kVD>};
 
+// direct store with split source reads (kTileSplitSrc) and direct load with
+// split destination writes (kTileSplitDst): plain, nontemporal loads,
+// nontemporal loads and stores; then the counted variant
+constexpr uint32_t kSS = kModeDirectStore | kModeSplitSrc, kSD = kModeDirectLoad | kModeSplitDst;
+const void* const kTileSplitSrcKernels[4] = {(const void*)tile_kernel<kSS>, (const void*)tile_kernel<kSS | kLd>,
+                                             (const void*)tile_kernel<kSS | kLdSt>, (const void*)tile_count_kernel<kSS>};
+const void* const kTileSplitDstKernels[4] = {(const void*)tile_kernel<kSD>, (const void*)tile_kernel<kSD | kLd>,
+                                             (const void*)tile_kernel<kSD | kLdSt>, (const void*)tile_count_kernel<kSD>};
+
 const void* const kTileVirtualCountKernels[kTileModes] = {
     (const void*)tile_count_kernel<kModeStaged | kV>, (const void*)tile_count_kernel<kModeDirectStore | kV>, nullptr,
     (const void*)tile_count_kernel<kModeGatherStore | kV>, (const void*)tile_count_kernel<kModeGatherOdd | kV>};
@@ -1994,6 +2078,10 @@ void launch(const Plan& p, void* stream_ptr)
             k = (f & kTileVirtualSrc) ? kTileVirtualCountKernels[mode - 1] : kTileCountKernels[mode - 1];
             if (f & kTileVirtualDst)
                 k = mode == kModeDirectStore && !(f & kTileVirtualSrc) ? kTileScatterKernels[3] : nullptr;
+            if (f & kTileSplitSrc)
+                k = mode == kModeDirectStore && !(f & (kTileVirtualSrc | kTileVirtualDst)) ? kTileSplitSrcKernels[3] : nullptr;
+            if (f & kTileSplitDst)
+                k = mode == kModeDirectLoad && !(f & kTileVirtualSrc) ? kTileSplitDstKernels[3] : nullptr;
             if (!k)
                 fail(LLAMA_E_INVALID_ARG, "no kernel variant for this combination of gathered parts");
             lds = p.tile.h.lds_bytes;
@@ -2027,6 +2115,11 @@ void launch(const Plan& p, void* stream_ptr)
         const void* k = ((f & kTileVirtualSrc) ? kTileVirtualKernels : kTileKernels)[(mode - 1) + kTileModes * variant];
         if (f & kTileVirtualDst)
             k = mode == kModeDirectStore && !(f & kTileVirtualSrc) ? kTileScatterKernels[variant] : nullptr;
+        if (f & kTileSplitSrc)
+            k = mode == kModeDirectStore && !(f & (kTileVirtualSrc | kTileVirtualDst)) ? kTileSplitSrcKernels[variant]
+                                                                                     : nullptr;
+        if (f & kTileSplitDst)
+            k = mode == kModeDirectLoad && !(f & kTileVirtualSrc) ? kTileSplitDstKernels[variant] : nullptr;
         if (!k)
             fail(LLAMA_E_INVALID_ARG, "no kernel variant for this combination of gathered parts");
         void* args[] = {(void*)&p.tile};

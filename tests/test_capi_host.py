@@ -246,10 +246,16 @@ def test_tile_modes():
     assert mode("mixed", A, AA) == "gather_store"
     assert mode("mixed", A, Q32) == "gather_store"
     assert mode("mixed", A, Q8) == "staged"
-    assert mode("mixed", M, A) == "staged"
+    # from SoA the source loads into registers and each value is written into
+    # the packed region in pieces of its alignment (the u8 leaf byte by byte);
+    # into SoA each value is read from the aligned words that hold it
+    assert mode("mixed", M, A) == "direct_load"
+    assert mode("mixed", A, M) == "direct_store"
+    assert mode("mixed", M, A, flags=L.COPY_NO_SPLIT) == "staged"
+    assert mode("mixed", A, M, flags=L.COPY_NO_SPLIT) == "staged"
     # into AoSoA, listing 1's u16 and bool lanes make a quarter of the words
-    # composite: staged; the mixed record's u8 lanes are 2% of the words
-    assert mode("listing1", M, Q8) == "staged"
+    # composite: no gather; from SoA its u16 and bool leaves load directly
+    assert mode("listing1", M, Q8) == "direct_load"
     assert mode("listing1", AA, Q32) == "staged"
     assert mode("mixed", M, Q32) == "gather_store"
     # LDS with composite words: the source region (leaf spans of 256 records)

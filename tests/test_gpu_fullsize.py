@@ -111,14 +111,19 @@ def test_particle_2e26_full(L, particle_2e26_layouts, src):
 
 # destinations of 1 GiB or more take nontemporal stores; the particle pairs
 # above run them in the direct-store and gather-store modes, these cases in
-# the staged mode (from SoA into the packed 49-byte mixed record, most words
-# straddle two values), the gather-store mode from that packed record (whole
-# words at odd positions read funnel-shifted), with composite words (the mixed record's
-# u8 leaf shares words with other lanes or padding) and the direct-load mode
-# (a destination 4 bytes past 16-byte alignment cannot gather: a field-major
-# source then loads into registers; the plan without blobs, which assumes
-# aligned blobs, gathers)
-STREAM_STORE_CASES = [("mixed", 1 << 25, ("soa_multi", 0), ("aos_packed", 0), 0, "staged"),
+# the staged mode (from AoSoA8 into the packed 49-byte mixed record, most
+# words straddle two values), the direct-load mode writing that packed record
+# in pieces from SoA (its u8 leaf and values at odd positions), the
+# direct-store mode reading it from aligned words into SoA, the gather-store
+# mode from that packed record (whole words at odd positions read
+# funnel-shifted), with composite words (the mixed record's u8 leaf shares
+# words with other lanes or padding) and the direct-load mode (a destination
+# 4 bytes past 16-byte alignment cannot gather: a field-major source then
+# loads into registers; the plan without blobs, which assumes aligned blobs,
+# gathers)
+STREAM_STORE_CASES = [("mixed", 1 << 25, ("aosoa", 8), ("aos_packed", 0), 0, "staged"),
+                      ("mixed", 1 << 25, ("soa_multi", 0), ("aos_packed", 0), 0, "direct_load"),
+                      ("mixed", 1 << 25, ("aos_packed", 0), ("soa_single", 0), 0, "direct_store"),
                       ("mixed", 1 << 25, ("aos_packed", 0), ("aosoa", 64), 0, "gather_store"),
                       ("mixed", 1 << 25, ("aosoa", 8), ("aos_aligned", 0), 0, "gather_store"),
                       ("mixed", 1 << 25, ("soa_multi", 0), ("aosoa", 32), 0, "gather_store"),

@@ -240,6 +240,38 @@ def test_gather_store(L, orc, case, run, offsets):
              **opts)
 
 
+# values aligned below their size: the direct store reads them from the
+# aligned LDS words that hold them (a packed record of odd size into SoA or
+# long-run AoSoA), the direct load writes them into the packed region in
+# pieces (and 1- and 2-byte leaves byte or half by half), from SoA or
+# long-run AoSoA
+SPLIT_DIRECT_CASES = [("mixed", ("aos_packed", 0), ("soa_single", 0), "direct_store"),
+                      ("mixed", ("aos_packed", 0), ("soa_multi", 0), "direct_store"),
+                      ("listing1", ("aos_packed", 0), ("soa_multi", 0), "direct_store"),
+                      ("mixed", ("soa_multi", 0), ("aos_packed", 0), "direct_load"),
+                      ("mixed", ("soa_single", 0), ("aos_packed", 0), "direct_load"),
+                      ("listing1", ("soa_multi", 0), ("aos_packed", 0), "direct_load"),
+                      ("listing1", ("soa_multi", 0), ("aosoa", 8), "direct_load"),
+                      ("listing1", ("soa_single", 0), ("aosoa", 64), "direct_load")]
+SPLIT_DIRECT_RUNS = [(1, {}), (77, {}), (1031, {}), (4099, {"tile_records": 16}), (20000, {"threads": 1024}),
+                     (30011, {"tile_records": 64, "wg_per_cu": 1})]
+
+
+@pytest.mark.parametrize("case", SPLIT_DIRECT_CASES,
+                         ids=[f"{c[0]}-{_name(c[1])}-{_name(c[2])}" for c in SPLIT_DIRECT_CASES])
+@pytest.mark.parametrize("run", SPLIT_DIRECT_RUNS, ids=[f"n{n}-{'-'.join(f'{k}{v}' for k, v in o.items())}"
+                                                        for n, o in SPLIT_DIRECT_RUNS])
+@pytest.mark.parametrize("offsets", [(0, 0), (16, 32), (0, 5)])
+def test_split_direct_modes(L, orc, case, run, offsets):
+    name, a, b, mode = case
+    n, opts = run
+    r = L.Record(W.RECORDS[name])
+    if offsets == (0, 0) and n % 16 == 0:  # (odd counts put single-blob SoA spans off the granule grid)
+        assert L.plan(L.Mapping(r, a[0], [n], a[1]), L.Mapping(r, b[0], [n], b[1]), **opts)["tile_mode"] == mode
+    run_case(L, orc, W.RECORDS[name], a, b, [n], seed=n + offsets[1], src_off=offsets[0], dst_off=offsets[1],
+             **opts)
+
+
 # field-major destinations whose leaf spans start off the 16-byte grid (an
 # odd record count in a single-blob SoA, or a blob 4, 8 or 12 bytes in): the
 # direct store writes the partial first and last granules of every span value
