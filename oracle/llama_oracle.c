@@ -27,6 +27,12 @@
  *               field (multi-blob) or all fields in one blob (single-blob),
  *               without padding between the sub-arrays (sec. 4.4 notes that
  *               SoA inserts no padding between its sub-arrays).
+ *      SoA, aligned sub-arrays
+ *               single-blob SoA whose every sub-array starts at a multiple of
+ *               A bytes (`lanes` holds A, 0 meaning 256), the bytes between
+ *               them being padding: the "with padding" SoA that sec. 4.4
+ *               notes LLAMA's SoA cannot yet produce, and that sec. 3.9
+ *               names as the other side of a copy between related mappings.
  *      AoSoA L  like AoS but each field repeated L times before the next
  *               field; the linear index i splits as (i / L, i mod L)
  *               (sec. 4.1).
@@ -57,8 +63,11 @@
  *     selects a subtree, whose leaves are contiguous in depth-first order),
  *     the two parts keep separate blobs, and a part may itself be a Split
  *     over its own leaves (the nesting of sec. 3.7's mapping listing);
+ *   - aligned SoA: leaf f's sub-array starts at the first multiple of A at or
+ *     after the end of leaf f - 1's; the blob ends with the last sub-array;
  *   - destination bytes that no (coordinate, leaf) pair maps to (alignment gaps
- *     of aligned AoS, unused lanes of the last AoSoA block) are set to zero.
+ *     of aligned AoS, unused lanes of the last AoSoA block, the padding between
+ *     aligned SoA sub-arrays) are set to zero.
  *
  * Arithmetic: plain unsigned 64-bit integers, plain '/' and '%'.  No shifts,
  * masks, tiling, blocking or reordering.  The one exception is
@@ -84,6 +93,7 @@
 #define ORC_AOSOA 4
 #define ORC_SPLIT 5
 #define ORC_ONE 6
+#define ORC_SOA_ALIGNED 7
 
 /* most leaves a record mapped by Split may have */
 #define ORC_SPLIT_MAX_LEAVES 1024
@@ -104,7 +114,7 @@ typedef struct orc_mapping_s {
     int32_t kind;
     int32_t rank;
     uint64_t extents[ORC_MAX_RANK];
-    uint64_t lanes; /* AoSoA only */
+    uint64_t lanes; /* AoSoA: lanes L; aligned SoA: sub-array alignment A (0: 256) */
     /* Split only: leaves [first, first + count) form the selected part,
      * mapped by part_kind[0] (lanes part_lanes[0]); the other leaves by
      * part_kind[1] (lanes part_lanes[1]); a part of kind Split takes its
@@ -448,6 +458,18 @@ static int split_leaf(const orc_mapping* m, int f, int* part)
     return f < m->first ? f : f - m->count;
 }
 
+/* aligned SoA: where leaf f's sub-array starts, n records per sub-array;
+ * each sub-array starts at the first multiple of A at or after the end of the
+ * one before it */
+static uint64_t soa_aligned_start(const orc_mapping* m, const orc_record* r, uint64_t n, int f)
+{
+    uint64_t a = m->lanes ? m->lanes : 256;
+    uint64_t start = 0;
+    for (int g = 0; g < f; g++)
+        start = round_up(start + n * r->size[g], a);
+    return start;
+}
+
 int orc_blob_count(const orc_mapping* m, const orc_record* r)
 {
     if (m->kind == ORC_SPLIT) {
@@ -483,6 +505,8 @@ uint64_t orc_blob_size(const orc_mapping* m, const orc_record* r, int blob)
         return n * orc_packed_size(r);
     case ORC_SOA_MULTI:
         return n * r->size[blob];
+    case ORC_SOA_ALIGNED: /* up to the end of the last sub-array */
+        return soa_aligned_start(m, r, n, r->nleaves - 1) + n * r->size[r->nleaves - 1];
     case ORC_AOSOA: {
         uint64_t blocks = (n + m->lanes - 1) / m->lanes;
         return blocks * m->lanes * orc_packed_size(r);
@@ -532,6 +556,10 @@ int orc_blob_nr_and_offset(const orc_mapping* m, const orc_record* r, const uint
         *blob = (uint64_t)f;
         *offset = i * r->size[f];
         return ORC_OK;
+    case ORC_SOA_ALIGNED: /* sub-array of leaf f at its aligned start */
+        *blob = 0;
+        *offset = soa_aligned_start(m, r, n, f) + i * r->size[f];
+        return ORC_OK;
     case ORC_AOSOA: { /* block i / L; inside it leaf f's L values, lane i mod L */
         uint64_t L = m->lanes;
         uint64_t block = i / L;
@@ -559,6 +587,8 @@ static int valid_plain(int32_t kind, uint64_t lanes)
 {
     if (kind == ORC_ONE)
         return 1;
+    if (kind == ORC_SOA_ALIGNED) /* an alignment of 1 .. 2^20 bytes, a power of two, or 0 */
+        return lanes <= ((uint64_t)1 << 20) && (lanes & (lanes - 1)) == 0;
     if (kind < ORC_AOS_PACKED || kind > ORC_AOSOA)
         return 0;
     return kind != ORC_AOSOA || lanes != 0;

@@ -13,8 +13,10 @@ Records are given in the neutral nested form used by the workload definitions:
 a record is a list of members; a member is an elemental type name, a nested
 list (a nested record), or a ``(member, count)`` pair for a static array.
 Mappings are ``(kind, extents, lanes)`` with kind one of ``aos_packed``,
-``aos_aligned``, ``soa_single``, ``soa_multi``, ``aosoa``, ``one`` (every
-coordinate at the same single packed record), or ``split`` with
+``aos_aligned``, ``soa_single``, ``soa_multi``, ``soa_aligned`` (single-blob
+SoA whose sub-arrays start at multiples of ``lanes`` bytes, 0 meaning 256),
+``aosoa``, ``one`` (every coordinate at the same single packed record), or
+``split`` with
 ``split=(first, count, (kind, lanes), (kind, lanes))``: leaves
 ``[first, first + count)`` mapped by the first plain mapping, the others by the
 second (sec. 3.7 Split).
@@ -35,7 +37,8 @@ MAX_RANK = 8
 MAX_LEAVES = 4096
 
 LINEARIZERS = {"row": 0, "col": 1, "morton": 2}
-KINDS = {"aos_packed": 0, "aos_aligned": 1, "soa_single": 2, "soa_multi": 3, "aosoa": 4, "split": 5, "one": 6}
+KINDS = {"aos_packed": 0, "aos_aligned": 1, "soa_single": 2, "soa_multi": 3, "aosoa": 4, "split": 5, "one": 6,
+         "soa_aligned": 7}
 
 
 class _Record(ctypes.Structure):

@@ -20,7 +20,7 @@ from hypothesis import given, settings, strategies as st, HealthCheck
 from paper_2106_04284_amd import workloads as W
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-KINDS = ["aos_packed", "aos_aligned", "soa_single", "soa_multi", "aosoa"]
+KINDS = ["aos_packed", "aos_aligned", "soa_single", "soa_multi", "soa_aligned", "aosoa"]
 SIZES = {"u8": 1, "i8": 1, "bool": 1, "u16": 2, "i16": 2, "u32": 4, "i32": 4, "f32": 4,
          "u64": 8, "i64": 8, "f64": 8}
 
@@ -36,7 +36,8 @@ def _golden(name):
 
 
 def _layouts(lanes=(1, 2, 4, 8, 32, 64)):
-    out = [(k, 0) for k in KINDS if k != "aosoa"]
+    out = [(k, 0) for k in KINDS if k != "aosoa"]  # aligned SoA: 0 means sub-arrays 256-byte aligned
+    out += [("soa_aligned", 16)]
     out += [("aosoa", L) for L in lanes]
     return out
 
@@ -88,6 +89,17 @@ def _serialise(types, values, kind, n, lanes):
     if kind == "soa_single":
         out = bytearray()
         for f in range(len(types)):
+            for i in range(n):
+                out += val(i, f)
+        return [bytes(out)]
+    if kind == "soa_aligned":
+        # one blob; before every sub-array but the first, zeros up to the
+        # next multiple of the alignment (lanes, 0 meaning 256)
+        a = lanes or 256
+        out = bytearray()
+        for f in range(len(types)):
+            while f and len(out) % a:
+                out.append(0)
             for i in range(n):
                 out += val(i, f)
         return [bytes(out)]
@@ -277,6 +289,34 @@ def test_soa_blobs_equal_concatenation(orc):
 # equivalences the paper states or implies
 # --------------------------------------------------------------------------
 
+@pytest.mark.parametrize("name", ["particle", "mixed", "lbm", "listing1"])
+@pytest.mark.parametrize("n", [1, 7, 64, 300])
+@pytest.mark.parametrize("align", [1, 4, 16, 256, 4096])
+def test_aligned_soa_against_numpy_padding(orc, name, n, align):
+    """SoA with aligned sub-arrays (the padded SoA of sec. 4.4 and sec. 3.9):
+    the per-leaf arrays, each zero-padded by numpy to a multiple of the
+    alignment except the last, concatenated; with alignment 1 it is the
+    single-blob SoA, and every sub-array start is a multiple of the
+    alignment."""
+    rec = W.RECORDS[name]
+    types = W.leaf_types(rec)
+    vals = _unique_leaf_values(types, n, 5 + n)
+    arrays = [np.ascontiguousarray(v).view(np.uint8).reshape(-1) for v in vals]
+    parts = [np.pad(a, (0, (-a.size) % align)) for a in arrays[:-1]] + [arrays[-1]]
+    want = np.concatenate(parts)
+    got = _build(orc, rec, "soa_aligned", [n], align, vals)
+    assert len(got) == 1 and np.array_equal(got[0], want)
+    if align == 1:
+        single = _build(orc, rec, "soa_single", [n], 0, vals)
+        assert np.array_equal(got[0], single[0])
+    r = orc.Record(rec)
+    m = orc.Mapping(r, "soa_aligned", [n], align)
+    starts = np.cumsum([0] + [p.size for p in parts[:-1]])
+    for f in range(r.nleaves):
+        assert m.blob_nr_and_offset([0], f) == (0, int(starts[f])) and starts[f] % align == 0
+        assert m.blob_nr_and_offset([n - 1], f) == (0, int(starts[f]) + (n - 1) * r.sizes[f])
+
+
 @pytest.mark.parametrize("name", ["particle", "mixed", "lbm"])
 @pytest.mark.parametrize("n", [1, 7, 64, 300])
 def test_soa_is_aosoa_with_n_lanes(orc, name, n):
@@ -340,7 +380,10 @@ def test_exactly_once_and_padding_complement(orc, name):
         counts = orc.write_counts(m)
         assert all(int(c.max(initial=0)) <= 1 for c in counts), (kind, lanes)
         assert sum(int(c.sum()) for c in counts) == data_bytes
-        pad_expected = {"aos_packed": 0, "soa_single": 0, "soa_multi": 0,
+        # aligned SoA: the zeros the serialiser appends between sub-arrays
+        soa_pad = len(_serialise(W.leaf_types(W.RECORDS[name]), _unique_leaf_values(W.leaf_types(W.RECORDS[name]), n, 1),
+                                 "soa_aligned", n, lanes)[0]) - data_bytes
+        pad_expected = {"aos_packed": 0, "soa_single": 0, "soa_multi": 0, "soa_aligned": soa_pad,
                         "aos_aligned": n * (r.aligned_size - r.packed_size),
                         "aosoa": (-(-n // max(lanes, 1)) * max(lanes, 1) - n) * r.packed_size}[kind]
         assert sum(int((c == 0).sum()) for c in counts) == pad_expected
@@ -461,7 +504,7 @@ def test_random_records_against_serialiser(orc, rec, n, lanes, kind, seed):
     if len(types) > 24:
         return
     vals = _unique_leaf_values(types, n, seed)
-    got = _build(orc, rec, kind, [n], lanes if kind == "aosoa" else 0, vals)
+    got = _build(orc, rec, kind, [n], lanes if kind in ("aosoa", "soa_aligned") else 0, vals)
     want = _serialise(types, vals, kind, n, lanes)
     assert [bytes(b) for b in got] == want
 
