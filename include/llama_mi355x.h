@@ -113,9 +113,17 @@ typedef enum {
                               ceil(N/lanes)*lanes*S */
     LLAMA_SPLIT = 5,       /* two of the other kinds over two parts of the record (sec. 3.7
                               Split); see llama_split_desc */
-    LLAMA_ONE = 6          /* every array coordinate at the same single record, packed: 1 blob
+    LLAMA_ONE = 6,         /* every array coordinate at the same single record, packed: 1 blob
                               of S (sec. 3.7 One).  A copy reads it as a broadcast, element-wise;
                               it is never a copy's destination (LLAMA_E_UNSUPPORTED) */
+    LLAMA_SOA_ALIGNED = 7  /* SoA in 1 blob whose sub-arrays start at multiples of `lanes` bytes
+                              (a power of two up to 2^20; 0 means 256): leaf f's N values start
+                              at the first multiple at or after the end of leaf f-1's, the bytes
+                              between sub-arrays are padding (zero in a destination, or kept
+                              with LLAMA_COPY_PRESERVE_PADDING), and the blob ends with the last
+                              sub-array.  The padded SoA that sec. 4.4 notes SoA cannot produce
+                              yet; sec. 3.9 names copies between a mapping with and without such
+                              padding.  Not for llama_copy_transfer (LLAMA_E_UNSUPPORTED) */
 } llama_mapping_kind;
 
 /* A Split mapping (sec. 3.7): the leaves [first_leaf, first_leaf + leaf_count)
@@ -158,7 +166,8 @@ typedef struct {
     uint32_t kind;                    /* llama_mapping_kind */
     uint32_t rank;                    /* 1 .. LLAMA_MAX_RANK */
     uint64_t extents[LLAMA_MAX_RANK]; /* extents[0 .. rank-1]; zero extents allowed */
-    uint32_t lanes;                   /* LLAMA_AOSOA: lanes per block, a power of two; else ignored */
+    uint32_t lanes;                   /* LLAMA_AOSOA: lanes per block, a power of two; LLAMA_SOA_ALIGNED:
+                                         the sub-array alignment in bytes; else ignored */
     uint32_t linearizer;              /* llama_linearizer (0: row-major); Split and its parts: row-major
                                          only; One: ignored */
     const llama_split_desc* split;    /* LLAMA_SPLIT: the split (required); else ignored */

@@ -465,8 +465,8 @@ static uint64_t soa_aligned_start(const orc_mapping* m, const orc_record* r, uin
 {
     uint64_t a = m->lanes ? m->lanes : 256;
     uint64_t start = 0;
-    for (int g = 0; g < f; g++)
-        start = round_up(start + n * r->size[g], a);
+    for (int g = 1; g <= f; g++) /* after the sub-array of leaf g - 1 */
+        start = round_up(start + n * r->size[g - 1], a);
     return start;
 }
 

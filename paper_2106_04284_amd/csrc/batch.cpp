@@ -145,6 +145,8 @@ void BatchTable::add(const Request& rq, uint32_t threads, uint32_t tile_records,
 
 void BatchTable::add_plan(const Plan& p)
 {
+    if (p.then) // the zero fill of an aligned SoA destination's padding: an item of its own
+        add_plan(*p.then);
     read_bytes += p.read_bytes;
     write_bytes += p.write_bytes;
     if (p.path == LLAMA_PATH_EMPTY)

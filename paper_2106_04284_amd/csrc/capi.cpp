@@ -221,7 +221,10 @@ std::vector<Plan> copy_plans(const llama_mapping_desc* src, const llama_blob* sr
         if (src->kind == LLAMA_SPLIT || dst->kind == LLAMA_SPLIT)
             fail(LLAMA_E_UNSUPPORTED, "Split copies take views with equal linear indices");
         const uint64_t zero[LLAMA_MAX_RANK] = {};
-        return make_box_plans(rq, zero, zero, rq.dst.extents, true, options);
+        std::vector<Plan> ps = make_box_plans(rq, zero, zero, rq.dst.extents, true, options);
+        if (!rq.dst.blob_gaps.empty() && !(options && (options->flags & LLAMA_COPY_PRESERVE_PADDING)))
+            ps.push_back(zero_fill_plan(rq)); // the padding between aligned SoA sub-arrays
+        return ps;
     }
     if (src->kind != LLAMA_SPLIT && dst->kind != LLAMA_SPLIT)
         return {make_plan(rq, options)};
@@ -333,14 +336,18 @@ int llama_plan_copy(const llama_mapping_desc* src, const llama_mapping_desc* dst
         *count = 0;
         const std::vector<Plan> plans = src_leaf ? leaves_plans(src, nullptr, dst, nullptr, src_leaf, options, false)
                                                  : copy_plans(src, nullptr, dst, nullptr, options, false);
-        if (plans.size() > capacity)
-            fail(LLAMA_E_INVALID_ARG, "the copy makes " + std::to_string(plans.size()) + " launches, capacity is " +
+        std::vector<const Plan*> all; // with the launches chained after each plan
+        for (const Plan& p : plans)
+            for (const Plan* q = &p; q; q = q->then.get())
+                all.push_back(q);
+        if (all.size() > capacity)
+            fail(LLAMA_E_INVALID_ARG, "the copy makes " + std::to_string(all.size()) + " launches, capacity is " +
                                           std::to_string(capacity));
-        if (!plans.empty())
+        if (!all.empty())
             need(infos, "infos");
-        for (size_t k = 0; k < plans.size(); k++)
-            fill_info(plans[k], &infos[k]);
-        *count = uint32_t(plans.size());
+        for (size_t k = 0; k < all.size(); k++)
+            fill_info(*all[k], &infos[k]);
+        *count = uint32_t(all.size());
     });
 }
 

@@ -183,7 +183,7 @@ std::vector<Part> parts_of(const llama_mapping_desc* m, const Record& r, int dep
                                       std::to_string(F) + " leaves");
     uint32_t first_blob = 0;
     for (int k = 0; k < 2; k++) {
-        if (sd->kind[k] > LLAMA_ONE)
+        if (sd->kind[k] > LLAMA_SOA_ALIGNED)
             fail(LLAMA_E_INVALID_ARG, "split: part " + std::to_string(k) + " has no valid mapping kind");
         std::vector<uint32_t> leaves;
         for (size_t f = 0; f < F; f++) {
@@ -245,6 +245,10 @@ Side split_side(const llama_mapping_desc* m, const Record& r)
             s.leaf_block[f] = p.side.block;
         }
         s.blob_size.insert(s.blob_size.end(), p.side.blob_size.begin(), p.side.blob_size.end());
+        for (Side::BlobGap g : p.side.blob_gaps) {
+            g.blob += p.first_blob;
+            s.blob_gaps.push_back(g);
+        }
     }
     return s;
 }
@@ -255,7 +259,7 @@ Side make_side(const llama_mapping_desc* m, const Record& r)
 {
     if (!m)
         fail(LLAMA_E_INVALID_ARG, "mapping descriptor is NULL");
-    if (m->kind > LLAMA_ONE)
+    if (m->kind > LLAMA_SOA_ALIGNED)
         fail(LLAMA_E_INVALID_ARG, "mapping kind " + std::to_string(m->kind) + " is not a llama_mapping_kind");
     if (m->rank < 1 || m->rank > LLAMA_MAX_RANK)
         fail(LLAMA_E_INVALID_ARG, "mapping rank must be 1..8");
@@ -332,6 +336,28 @@ Side make_side(const llama_mapping_desc* m, const Record& r)
             s.blob_size.push_back(mul(n, r.leaves[f].size, "blob size"));
         }
         break;
+    case LLAMA_SOA_ALIGNED: {
+        // each sub-array at the first multiple of the alignment at or after
+        // the end of the one before; the bytes between them are padding
+        const uint64_t a = m->lanes ? m->lanes : 256;
+        if (!is_pow2(a) || a > (uint64_t(1) << 20))
+            fail(LLAMA_E_INVALID_ARG, "aligned SoA: the sub-array alignment must be a power of two up to 2^20, got " +
+                                          std::to_string(m->lanes));
+        s.lanes = 0;
+        uint64_t cur = 0;
+        for (size_t f = 0; f < F; f++) {
+            if (f > 0) {
+                const uint64_t start = round_up(cur, a);
+                if (start > cur)
+                    s.blob_gaps.push_back({0, cur, start - cur});
+                cur = start;
+            }
+            s.base[f] = cur;
+            cur = add(cur, mul(n, r.leaves[f].size, "SoA sub-array size"), "blob size");
+        }
+        s.blob_size = {cur};
+        break;
+    }
     case LLAMA_ONE:
         // blocked with L = 1 and K = 0: every record at the one packed record
         s.lanes = 1;
@@ -524,6 +550,7 @@ bool gathered_copy(const PartLeaves& from, const Part& P, const Request& whole, 
     Side s = from[0].first->side;
     s.partial = false;
     s.gaps.clear();
+    s.blob_gaps.clear();
     s.leaf_lanes.clear();
     s.leaf_block.clear();
     s.blob_size.clear();
@@ -623,8 +650,8 @@ bool scattered_copy(const Part& Q, const PartLeaves& to, const Request& whole, c
         const uint64_t l = effective_lanes(P->side);
         // a part taken as field-major must have no tail lanes to fill (an
         // AoSoA part whose one block outlasts the records has them)
-        if (P->side.kind == LLAMA_ONE || !P->side.gaps.empty() || (l != 0 && L != 0 && l != L) ||
-            (l == 0 && P->side.npad != P->side.n))
+        if (P->side.kind == LLAMA_ONE || !P->side.gaps.empty() || !P->side.blob_gaps.empty() ||
+            (l != 0 && L != 0 && l != L) || (l == 0 && P->side.npad != P->side.n))
             return false;
         if (l != 0)
             L = l;
@@ -638,6 +665,7 @@ bool scattered_copy(const Part& Q, const PartLeaves& to, const Request& whole, c
     Side d = to[0].first->side;
     d.partial = false;
     d.gaps.clear();
+    d.blob_gaps.clear();
     d.leaf_lanes.clear();
     d.leaf_block.clear();
     d.blob_size.clear();
@@ -783,6 +811,7 @@ std::vector<SubCopy> split_copies(const llama_mapping_desc* src, const llama_map
             if (padding_written) {
                 // the alignment gaps of this destination part are written once
                 c.rq.dst.gaps.clear();
+                c.rq.dst.blob_gaps.clear();
             } else if (whole_first) {
                 // every byte of the record outside these leaves becomes a gap
                 std::vector<std::pair<uint64_t, uint64_t>> cover;
@@ -824,7 +853,7 @@ bool same_placement(const Side& a, const Side& b)
     if (a.partial || b.partial)
         return false;
     if (effective_lanes(a) != effective_lanes(b) || a.blob_size != b.blob_size || a.blob != b.blob ||
-        a.base != b.base || a.npad != b.npad || a.gaps != b.gaps)
+        a.base != b.base || a.npad != b.npad || a.gaps != b.gaps || a.blob_gaps != b.blob_gaps)
         return false;
     return effective_lanes(a) == 0 || a.block == b.block;
 }
@@ -860,7 +889,7 @@ bool stream_runs(const Request& rq, RunList& out, bool preserve)
     const size_t F = r.leaves.size();
     if (!d.gaps.empty())
         return false;
-    if (same_placement(s, d)) {
+    if (same_placement(s, d) && d.blob_gaps.empty()) {
         // identical layouts: whole blobs, except the lanes past the last
         // record of an AoSoA block, which become zero runs
         uint64_t L = d.lanes;
@@ -891,6 +920,10 @@ bool stream_runs(const Request& rq, RunList& out, bool preserve)
         if (!preserve)
             out.add(0, da + d.n * sz, (d.npad - d.n) * sz);
     }
+    // the padding between aligned SoA sub-arrays
+    if (!preserve)
+        for (const Side::BlobGap& g : d.blob_gaps)
+            out.add(0, rq.dst_ptr[g.blob] + g.offset, g.length);
     return true;
 }
 
@@ -1355,10 +1388,61 @@ namespace {
 Plan make_plan_raw(const Request& rq, const llama_copy_options* opt);
 }
 
-// The plan for `opt`; when the caller leaves the path and tile size to the
-// library, a tuning-cache entry for this class of copies supplies them (the
-// caller's threads and wg_per_cu still win).
+namespace {
+Plan make_plan_tuned(const Request& rq, const llama_copy_options* opt);
+}
+
+// The zero fill of the padding between a destination's aligned SoA
+// sub-arrays: STREAM plans of zero runs, chained through `then` when there
+// are more runs than one launch takes.
+Plan zero_fill_plan(const Request& rq)
+{
+    RunList rl;
+    for (const Side::BlobGap& g : rq.dst.blob_gaps)
+        rl.add(0, rq.dst_ptr[g.blob] + g.offset, g.length);
+    Plan first;
+    Plan* cur = &first;
+    for (size_t k0 = 0; k0 < rl.runs.size(); k0 += size_t(kStreamMaxRuns)) {
+        if (k0) {
+            cur->then = std::make_shared<Plan>();
+            cur = cur->then.get();
+        }
+        const size_t k1 = std::min(rl.runs.size(), k0 + size_t(kStreamMaxRuns));
+        cur->path = LLAMA_PATH_STREAM;
+        cur->threads = kDefaultThreads;
+        std::memset(&cur->stream, 0, sizeof(cur->stream));
+        uint64_t chunks = 0;
+        for (size_t k = k0; k < k1; k++) {
+            StreamRun run = rl.runs[k];
+            run.first_chunk = chunks;
+            chunks += (run.bytes + (uint64_t(1) << kStreamChunkLog2) - 1) >> kStreamChunkLog2;
+            cur->stream.r[k - k0] = run;
+            cur->write_bytes += run.bytes;
+        }
+        cur->stream.num_runs = uint32_t(k1 - k0);
+        cur->stream.num_chunks = chunks;
+        cur->workgroups = chunks;
+    }
+    return first;
+}
+
+// The plan for `opt` (and, into an aligned SoA destination whose path does
+// not zero its padding itself, the zero fill after it).
 Plan make_plan(const Request& rq, const llama_copy_options* opt)
+{
+    Plan p = make_plan_tuned(rq, opt);
+    if (!rq.dst.blob_gaps.empty() && p.path != LLAMA_PATH_EMPTY && p.path != LLAMA_PATH_STREAM &&
+        !(p.flags_in & kPlanPreserve))
+        p.then = std::make_shared<Plan>(zero_fill_plan(rq));
+    return p;
+}
+
+namespace {
+
+// When the caller leaves the path and tile size to the library, a
+// tuning-cache entry for this class of copies supplies them (the caller's
+// threads and wg_per_cu still win).
+Plan make_plan_tuned(const Request& rq, const llama_copy_options* opt)
 {
     if (needs_box(rq))
         fail(LLAMA_E_UNSUPPORTED, "the two views place records at different linear indices (differing "
@@ -1380,8 +1464,6 @@ Plan make_plan(const Request& rq, const llama_copy_options* opt)
     }
     return make_plan_raw(rq, opt);
 }
-
-namespace {
 
 Plan make_plan_raw(const Request& rq, const llama_copy_options* opt)
 {

@@ -73,7 +73,15 @@ struct Side {
     // a side of one part-to-part copy whose leaves leave other bytes of its
     // records to other copies: never treated as one whole-blob copy
     bool partial = false;
-    bool has_padding() const { return !gaps.empty() || npad != n; }
+    // LLAMA_SOA_ALIGNED: the byte ranges between sub-arrays (blob, offset,
+    // length), padding that belongs to no record
+    struct BlobGap {
+        uint32_t blob;
+        uint64_t offset, length;
+        bool operator==(const BlobGap& o) const { return blob == o.blob && offset == o.offset && length == o.length; }
+    };
+    std::vector<BlobGap> blob_gaps;
+    bool has_padding() const { return !gaps.empty() || npad != n || !blob_gaps.empty(); }
     uint64_t offset(uint64_t i, uint32_t f, const Record& r) const
     {
         const uint64_t L = leaf_lanes.empty() ? lanes : leaf_lanes[f];
@@ -176,9 +184,15 @@ struct Plan {
     NaiveArgs naive{};   // path == NAIVE
     BoxArgs box{};       // path == BOX (box_naive: its element-wise baseline)
     bool box_naive = false;
+    // a launch that follows this one: the zero fill of the padding between a
+    // destination's aligned SoA sub-arrays (a STREAM plan of zero runs)
+    std::shared_ptr<Plan> then;
 };
 
 Plan make_plan(const Request& rq, const llama_copy_options* opt);
+// the zero fill of the padding between a destination's aligned SoA
+// sub-arrays (rq.dst.blob_gaps), as STREAM plans chained through `then`
+Plan zero_fill_plan(const Request& rq);
 
 // A copy whose records sit at different linear indices on the two sides
 // (differing linearizers, or Morton indices that no coordinate reaches): it

@@ -2054,7 +2054,20 @@ void set_counting(const CountTable* table, void* stream)
     t_counting = true;
 }
 
+namespace {
+void launch_one(const Plan& p, void* stream_ptr);
+}
+
+// A plan's launch, then the launches chained after it (the zero fill of an
+// aligned SoA destination's padding).
 void launch(const Plan& p, void* stream_ptr)
+{
+    for (const Plan* q = &p; q; q = q->then.get())
+        launch_one(*q, stream_ptr);
+}
+
+namespace {
+void launch_one(const Plan& p, void* stream_ptr)
 {
     hipStream_t stream = (hipStream_t)stream_ptr;
     if (p.path == LLAMA_PATH_EMPTY || p.workgroups == 0)
@@ -2153,6 +2166,7 @@ void launch(const Plan& p, void* stream_ptr)
     }
     check_hip(hipGetLastError(), "kernel launch");
 }
+} // namespace
 
 void trace_leaves(const llama_mapping_desc* m, uint32_t* const* counters, uint64_t* sums, void* stream_ptr)
 {

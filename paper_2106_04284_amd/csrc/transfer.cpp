@@ -162,8 +162,9 @@ void copy_transfer(const llama_mapping_desc* src, const llama_blob* src_blobs, u
         fail(LLAMA_E_INVALID_ARG, "one view must be in host memory and the other in device memory "
                                   "(device views: llama_copy)");
     Request rq = make_request(src, nullptr, dst, nullptr, false);
-    if (src->kind == LLAMA_SPLIT || dst->kind == LLAMA_SPLIT || src->kind == LLAMA_ONE)
-        fail(LLAMA_E_UNSUPPORTED, "transfers take plain mappings (no Split, no One source)");
+    if (src->kind == LLAMA_SPLIT || dst->kind == LLAMA_SPLIT || src->kind == LLAMA_ONE ||
+        src->kind == LLAMA_SOA_ALIGNED || dst->kind == LLAMA_SOA_ALIGNED)
+        fail(LLAMA_E_UNSUPPORTED, "transfers take plain mappings (no Split, no One source, no aligned SoA)");
     if (needs_box(rq))
         fail(LLAMA_E_UNSUPPORTED, "transfers take views with equal linear indices (the same linearizer)");
     check_host_blobs("source", rq.src, src_blobs, rq.src_ptr);

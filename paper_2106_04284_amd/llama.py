@@ -19,9 +19,9 @@ LIB_PATH = os.path.join(PKG, "libllama_mi355x.so")
 
 MAX_RANK = 8
 
-AOS_PACKED, AOS_ALIGNED, SOA_SINGLE, SOA_MULTI, AOSOA, SPLIT, ONE = 0, 1, 2, 3, 4, 5, 6
+AOS_PACKED, AOS_ALIGNED, SOA_SINGLE, SOA_MULTI, AOSOA, SPLIT, ONE, SOA_ALIGNED = 0, 1, 2, 3, 4, 5, 6, 7
 KINDS = {"aos_packed": AOS_PACKED, "aos_aligned": AOS_ALIGNED, "soa_single": SOA_SINGLE,
-         "soa_multi": SOA_MULTI, "aosoa": AOSOA, "split": SPLIT, "one": ONE}
+         "soa_multi": SOA_MULTI, "aosoa": AOSOA, "split": SPLIT, "one": ONE, "soa_aligned": SOA_ALIGNED}
 
 PATH_AUTO, PATH_STREAM, PATH_TILE, PATH_NAIVE, PATH_EMPTY, PATH_BOX = 0, 1, 2, 3, 4, 5
 PATH_NAMES = {PATH_STREAM: "stream", PATH_TILE: "tile", PATH_NAIVE: "naive", PATH_EMPTY: "empty", PATH_BOX: "box"}

@@ -493,7 +493,8 @@ def test_split_mapping_host(orc):
                             assert m.offset(coord, f) == o.blob_nr_and_offset(coord, f), (name, sp, ext, i, f)
     rg = L.Record(W.PARTICLE)
     ok = ("soa_multi", 0), ("aos_packed", 0)
-    for bad in [(0, 7, *ok), (5, 3, *ok), (0, 0, *ok), (1, 2, (7, 0), ok[1]), (1, 2, ("aosoa", 3), ok[1]),
+    for bad in [(0, 7, *ok), (5, 3, *ok), (0, 0, *ok), (1, 2, (8, 0), ok[1]), (1, 2, ("aosoa", 3), ok[1]),
+                (1, 2, ("soa_aligned", 3), ok[1]),
                 (1, 2, ("split", (0, 2, *ok)), ok[1])]:
         with pytest.raises(L.LlamaError) as e:
             L.Mapping(rg, "split", [10], split=bad).blob_sizes()
@@ -688,4 +689,42 @@ def test_plan_copy_lists_every_launch():
     assert e.value.status == L.E_INVALID_ARG
     with pytest.raises(L.LlamaError) as e:
         L.plan_copy(s1, aos, path=L.PATH_STREAM)
+    assert e.value.status == L.E_UNSUPPORTED
+
+
+def test_aligned_soa_host(orc):
+    """LLAMA_SOA_ALIGNED: blob sizes and every offset equal the oracle's for
+    four records, alignments 1..4096 (0: 256) and ragged counts; a bad
+    alignment is rejected; a copy into it whose path does not zero the padding
+    (a tile copy) is followed by a zero-fill launch of one run per gap (none
+    with kept padding), while a long-run copy zeroes the gaps in its own runs;
+    transfers refuse it."""
+    for name in ("particle", "mixed", "lbm", "listing1"):
+        rec = W.RECORDS[name]
+        rg, ro = L.Record(rec), orc.Record(rec)
+        for n in (0, 1, 77, 1000003):
+            for a in (0, 1, 2, 16, 256, 4096):
+                m, o = L.Mapping(rg, "soa_aligned", [n], a), orc.Mapping(ro, "soa_aligned", [n], a)
+                assert m.blob_sizes() == o.blob_sizes(), (name, n, a)
+                for i in sorted({0, n // 2, n - 1}) if n else []:
+                    for f in range(ro.nleaves):
+                        assert m.offset([i], f) == o.blob_nr_and_offset([i], f), (name, n, a, i, f)
+    rg = L.Record(W.MIXED)
+    for bad in (3, 1 << 21):
+        with pytest.raises(L.LlamaError) as e:
+            L.Mapping(rg, "soa_aligned", [10], bad).blob_sizes()
+        assert e.value.status == L.E_INVALID_ARG
+    n = 1000003
+    aos, q = L.Mapping(rg, "aos_packed", [n]), L.Mapping(rg, "soa_aligned", [n], 256)
+    ps = L.plan_copy(aos, q)
+    gaps = 9  # between the 10 sub-arrays, none of which ends on a 256-byte boundary at this count
+    assert [p["path"] for p in ps] == ["tile", "stream"] and ps[1]["runs"] == gaps
+    assert ps[1]["write_bytes"] == q.blob_size(0) - n * 49
+    assert len(L.plan_copy(aos, q, flags=L.COPY_PRESERVE_PADDING)) == 1
+    s = L.plan_copy(L.Mapping(rg, "soa_single", [n]), q)
+    assert len(s) == 1 and s[0]["path"] == "stream" and s[0]["runs"] == 10 + gaps
+    assert L.plan_copy(q, aos)[0]["path"] == "tile" and len(L.plan_copy(q, aos)) == 1
+    # transfers refuse it (before touching any blob)
+    with pytest.raises(L.LlamaError) as e:
+        L.copy_transfer(aos, [(1 << 40, aos.blob_size(0))], q, [(2 << 40, q.blob_size(0))], True, stream=0)
     assert e.value.status == L.E_UNSUPPORTED

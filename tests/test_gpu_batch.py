@@ -287,6 +287,38 @@ def test_batch_with_split_items(L, orc):
     assert e.value.status == L.E_UNSUPPORTED
 
 
+def test_batch_with_aligned_soa_items(L, orc):
+    """Items into and out of SoA with aligned sub-arrays: a tiled item's zero
+    fill of the padding between sub-arrays joins the batch as an item of its
+    own; over two graph replays the destinations equal the oracle's, padding
+    zero."""
+    g = random.Random(46)
+    lay = [("aos_packed", 0), ("aos_aligned", 0), ("soa_multi", 0), ("aosoa", 32), ("soa_aligned", 64),
+           ("soa_aligned", 0)]
+    items, want = [], []
+    for k in range(18):
+        name = g.choice(["particle", "mixed"])
+        a, b = g.choice(lay), g.choice(lay)
+        if a[0] != "soa_aligned" and b[0] != "soa_aligned":
+            b = ("soa_aligned", 256)
+        n = g.choice([1, 77, 4099, 30011])
+        ro, rg = orc.Record(W.RECORDS[name]), L.Record(W.RECORDS[name])
+        ms_o, md_o = orc.Mapping(ro, a[0], [n], a[1]), orc.Mapping(ro, b[0], [n], b[1])
+        src = [W.random_bytes(x, 700 + k * 13 + j) for j, x in enumerate(ms_o.blob_sizes())]
+        want.append(orc.copy(ms_o, src, md_o))
+        ms, md = L.Mapping(rg, a[0], [n], a[1]), L.Mapping(rg, b[0], [n], b[1])
+        items.append((ms, [torch.from_numpy(x).cuda() for x in src], md, md.alloc(fill=0xCD)))
+    print("aligned soa batch: 18 items", flush=True)
+    b = L.Batch(items)
+    for rep in range(2):
+        refill(items, 0xCD if rep == 0 else 0x77)
+        torch.cuda.synchronize()
+        b.launch()
+        torch.cuda.synchronize()
+        check(items, want)
+    b.close()
+
+
 def test_batch_autotune_keeps_result(L, orc):
     """llama_batch_autotune re-plans the batch (LDS budget, threads, grid);
     every candidate must write the same bytes, and the tuned batch, replayed

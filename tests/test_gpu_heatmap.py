@@ -106,6 +106,20 @@ def test_every_destination_byte_written_as_defined(L, orc, name, a):
             _run(L, orc, name, a, b, 3001, 17, opts)
 
 
+@pytest.mark.parametrize("name", ["particle", "mixed", "listing1"])
+@pytest.mark.parametrize("align", [16, 0, 4096])
+def test_aligned_soa_written_as_defined(L, orc, name, align):
+    """Aligned SoA on either side of every plain layout: the padding between
+    sub-arrays gets one zero write (the tile's zero-fill launch, or a stream
+    run), none with kept padding."""
+    q = ("soa_aligned", align)
+    for b in LAYOUTS:
+        for opts in ({}, {"flags": L.COPY_PRESERVE_PADDING}, {"path": L.PATH_NAIVE}):
+            _run(L, orc, name, b, q, 1001, 23, opts)
+            _run(L, orc, name, q, b, 1001, 29, opts)
+    _run(L, orc, name, q, ("soa_aligned", 64), 1001, 31, {})
+
+
 @pytest.mark.parametrize("name", ["lbm", "listing1"])
 def test_heatmap_other_records(L, orc, name):
     g = random.Random(3)

@@ -327,3 +327,64 @@ def test_special_float_patterns_survive(L, orc):
             assert np.array_equal(t.cpu().numpy().view(np.uint32), v)
         for special in W.SPECIAL_U32:
             assert any((t.cpu().numpy().view(np.uint32) == special).any() for t in back)
+
+
+# --------------------------------------------------------------------------
+# SoA with aligned sub-arrays (the padded SoA of sec. 4.4; sec. 3.9 names
+# copies between a mapping with and without that padding): against every
+# other layout both ways, alignments of 16 bytes, 256 (the default) and
+# 4096, record counts that leave padding between the sub-arrays, blobs at
+# odd offsets, kept padding and the option sets
+# --------------------------------------------------------------------------
+
+ALIGNED = [("soa_aligned", 16), ("soa_aligned", 0), ("soa_aligned", 4096)]
+ALIGNED_PAIRS = ([(a, b) for a in ALIGNED for b in LAYOUTS] + [(b, a) for a in ALIGNED for b in LAYOUTS] +
+                 [(a, b) for a in ALIGNED for b in ALIGNED])
+
+
+@pytest.mark.parametrize("pair", ALIGNED_PAIRS, ids=[f"{_name(a)}{a[1] if a[0] == 'soa_aligned' else ''}-"
+                                                     f"{_name(b)}{b[1] if b[0] == 'soa_aligned' else ''}"
+                                                     for a, b in ALIGNED_PAIRS])
+@pytest.mark.parametrize("name", ["particle", "mixed", "lbm", "listing1"])
+def test_aligned_soa_pairs(L, orc, pair, name):
+    n = {"particle": 4099, "mixed": 777, "lbm": 301, "listing1": 1031}[name]
+    print(f"aligned soa {name} {pair} n={n}", flush=True)
+    run_case(L, orc, W.RECORDS[name], pair[0], pair[1], [n], seed=n + 3)
+
+
+@pytest.mark.parametrize("case", [dict(keep=True), dict(flags=L_NO_DIRECT), dict(path=2, tile_records=16),
+                                  dict(path=3), dict(threads=1024), dict(src_off=5, dst_off=3),
+                                  dict(src_off=16, dst_off=4)],
+                         ids=["keep", "no_direct", "T16", "naive", "t1024", "off5-3", "off16-4"])
+def test_aligned_soa_options(L, orc, case):
+    """The padding between sub-arrays is zero after every path (tile, then the
+    zero-fill launch; stream runs; the element-wise kernel, then the zero
+    fill), and keeps its bytes with LLAMA_COPY_PRESERVE_PADDING."""
+    case = dict(case)
+    offs = dict(src_off=case.pop("src_off", 0), dst_off=case.pop("dst_off", 0))
+    for k, (rec, a, b, n) in enumerate([(W.MIXED, ("aos_packed", 0), ("soa_aligned", 64), 2001),
+                                        (W.PARTICLE, ("soa_aligned", 256), ("aosoa", 32), 5003),
+                                        (W.LBM, ("soa_multi", 0), ("soa_aligned", 4096), 333),
+                                        (W.LISTING1, ("soa_aligned", 16), ("soa_aligned", 1024), 999)]):
+        print(f"aligned soa options {case} {offs} pair {k}", flush=True)
+        run_case(L, orc, rec, a, b, [n], seed=40 + k, **offs, **case)
+
+
+def test_aligned_soa_extents_and_linearizers(L, orc):
+    """Rank 3 and a column-major view: the box kernel copies the records and
+    the zero fill follows it for the aligned SoA destination."""
+    ro, rg = orc.Record(W.MIXED), L.Record(W.MIXED)
+    ext = [7, 5, 9]
+    for lin_s, lin_d in (("row", "row"), ("col", "row"), ("row", "morton")):
+        ms_o = orc.Mapping(ro, "aos_aligned", ext, 0, linearizer=lin_s)
+        md_o = orc.Mapping(ro, "soa_aligned", ext, 128, linearizer=lin_d)
+        ms = L.Mapping(rg, "aos_aligned", ext, 0, linearizer=lin_s)
+        md = L.Mapping(rg, "soa_aligned", ext, 128, linearizer=lin_d)
+        src = [W.random_bytes(s, 91) for s in ms_o.blob_sizes()]
+        want = orc.copy(ms_o, src, md_o)
+        sd = [torch.from_numpy(x).cuda() for x in src]
+        dd = md.alloc(fill=0xCD)
+        L.copy(ms, sd, md, dd)
+        torch.cuda.synchronize()
+        for g, w in zip(dd, want):
+            assert np.array_equal(g.cpu().numpy(), w), (lin_s, lin_d)

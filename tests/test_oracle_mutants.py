@@ -60,9 +60,10 @@ MUTANTS = {
                                  "            for (uint64_t o = 0; o < sz; o++)\n                if (!owned[b][o])\n                    (void)0;"),
     "copy_writes_counts_kept_leaves": ("                    if (!from || from[f] >= 0)\n                        counts[b][o + k]++;",
                                        "                    counts[b][o + k]++;"),
-    "soa_aligned_no_rounding": ("start = round_up(start + n * r->size[g], a);", "start = start + n * r->size[g];"),
-    "soa_aligned_rounds_to_leaf_size": ("start = round_up(start + n * r->size[g], a);",
-                                        "start = round_up(start + n * r->size[g], r->size[g]);"),
+    "soa_aligned_no_rounding": ("start = round_up(start + n * r->size[g - 1], a);",
+                                "start = start + n * r->size[g - 1];"),
+    "soa_aligned_rounds_to_leaf_size": ("start = round_up(start + n * r->size[g - 1], a);",
+                                        "start = round_up(start + n * r->size[g - 1], r->size[g - 1]);"),
     "soa_aligned_default_alignment": ("uint64_t a = m->lanes ? m->lanes : 256;", "uint64_t a = m->lanes ? m->lanes : 128;"),
     "threaded_piece_starts_at_origin": ("delinearize(src, lo, coord);", "(void)lo;"),
     "threaded_last_piece_drops_tail": ("uint64_t hi = k + 1 == pieces ? n : n / (uint64_t)pieces * (uint64_t)(k + 1);",
