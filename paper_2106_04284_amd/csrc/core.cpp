@@ -1195,11 +1195,25 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
                 }
         }
         std::vector<uint32_t> table(gwords), bytes;
+        // With q = 0 every source byte of super-block b lies kq bytes past its
+        // place in super-block 0, whatever its leaf, so 4 source bytes that
+        // are consecutive in super-block 0 are consecutive in every one.  Into
+        // AoS (no lanes past the last record: a tile's span holds records
+        // with values only) such a word is read whole even where it spans
+        // two leaves of a record (a packed record whose leaves keep their
+        // aligned offsets: only the words across record boundaries stay
+        // composite).
+        const bool contiguous_whole = g.q == 0 && rq.dst.lanes == 1 && (g.kq & 3u) == 0;
         for (uint64_t w = 0; w < gwords; w++) {
             const uint32_t* x = &src_of[4 * w];
             // the word's position modulo 4 is the same in every super-block
             const bool steady = (g.kq & 3u) == 0 && (g.q == 0 || ((x[0] >> 18) & 31u) >= 2);
-            if ((x[0] >> 31) == 0 && x[1] == x[0] + 1 && x[2] == x[0] + 2 && x[3] == x[0] + 3 && steady) {
+            const bool bytes_follow = ((x[0] | x[1] | x[2] | x[3]) >> 31) == 0 &&
+                                      (x[1] & 0x3FFFFu) == (x[0] & 0x3FFFFu) + 1 &&
+                                      (x[2] & 0x3FFFFu) == (x[0] & 0x3FFFFu) + 2 &&
+                                      (x[3] & 0x3FFFFu) == (x[0] & 0x3FFFFu) + 3;
+            if (((x[0] >> 31) == 0 && x[1] == x[0] + 1 && x[2] == x[0] + 2 && x[3] == x[0] + 3 && steady) ||
+                (contiguous_whole && bytes_follow)) {
                 table[w] = x[0] | ((x[0] & 3u) ? 1u << 30 : 0u); // bit 30: read funnel-shifted
             } else if (((x[0] & x[1] & x[2] & x[3]) >> 31) != 0) {
                 table[w] = 1u << 31;
