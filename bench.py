@@ -406,7 +406,7 @@ def bench_batch(L, torch, args, dev, stream):
             "config": {"workload": BATCH_WORKLOAD,
                        "bytes_per_step": m["bytes"], "arrays": m["arrays"], "threads": info["threads"],
                        "work_units": info["work_units"], "workgroups": info["workgroups"],
-                       "wg_per_cu": info["wg_per_cu"], "lds_bytes": info["lds_bytes"],
+                       "wg_per_cu": info["wg_per_cu"], "lds_bytes": info["lds_bytes"], "launches": info["launches"],
                        "tuned_classes": m["tuned_classes"]},
             "hbm_peak_frac": round(m["gbs"] / HBM_PEAK_GBS, 4),
             "extras": batch_extras(m),

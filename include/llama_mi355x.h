@@ -602,8 +602,11 @@ typedef struct {
     uint64_t write_bytes;  /* destination blob bytes of all items */
     uint32_t threads;      /* threads per workgroup */
     uint32_t wg_per_cu;    /* persistent grid: workgroups per compute unit; 0: one workgroup per work unit */
-    uint32_t workgroups;   /* grid size */
-    uint32_t lds_bytes;    /* LDS per workgroup */
+    uint32_t workgroups;   /* grid size (one launch per tile mode: all launches together) */
+    uint32_t lds_bytes;    /* LDS per workgroup (one launch per tile mode: the largest) */
+    uint32_t launches;     /* kernel launches per batch launch: 1, or one per tile mode when the
+                              table is sorted by mode (each mode in its own compiled kernel) */
+    uint32_t reserved;
 } llama_batch_info;
 
 int llama_batch_create(size_t n, const llama_copy_item* items, const llama_copy_options* options,
@@ -619,8 +622,10 @@ int llama_batch_get_info(const llama_batch* batch, llama_batch_info* info);
  * item's plan may take (8, 16, 31 or 48 KiB: each item then takes the largest
  * tile that fits, so this sets the tile shapes and the LDS depth of every
  * workgroup), 128, 256 or 512 threads per workgroup (the waves that share a
- * tile), and the grid (the default rule, or a persistent grid of 2, 4 or 8
- * workgroups per compute unit).  Every candidate first runs on destinations
+ * tile), and the grid (the default rule, a persistent grid of 2, 4 or 8
+ * workgroups per compute unit, or the table sorted by tile mode and run as
+ * one launch per mode, each mode in its own compiled kernel with one
+ * workgroup per work unit).  Every candidate first runs on destinations
  * filled with a pattern and must write the bytes the current plan writes
  * (compared by a 64-bit hash of every destination); then it is timed, best of
  * `reps` launches (0: 3).  A tile size fixed at creation stays fixed.

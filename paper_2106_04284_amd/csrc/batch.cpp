@@ -214,6 +214,40 @@ TableLayout table_layout(const BatchTable& t)
 }
 } // namespace
 
+std::vector<BatchRange> BatchTable::sort_by_mode()
+{
+    std::vector<size_t> order(items.size());
+    for (size_t k = 0; k < order.size(); k++)
+        order[k] = k;
+    std::vector<uint32_t> key(items.size());
+    for (size_t k = 0; k < items.size(); k++)
+        key[k] = batch_mode_key(items[k]);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return key[a] < key[b]; });
+    std::vector<BatchItem> sorted;
+    sorted.reserve(items.size());
+    std::vector<BatchRange> ranges;
+    unit_begin.clear();
+    units = 0;
+    for (size_t k : order) {
+        const BatchItem& it = items[k];
+        if (ranges.empty() || ranges.back().key != key[k])
+            ranges.push_back(BatchRange{key[k], units, 0, 0});
+        BatchRange& r = ranges.back();
+        r.units += it.h.num_tiles;
+        if (it.kind == kItemTile)
+            r.lds_bytes = std::max(r.lds_bytes, it.h.lds_bytes);
+        unit_begin.push_back(units);
+        units += it.h.num_tiles;
+        sorted.push_back(it);
+    }
+    items = std::move(sorted);
+    std::vector<BatchRange> nonempty;
+    for (const BatchRange& r : ranges)
+        if (r.units)
+            nonempty.push_back(r);
+    return nonempty;
+}
+
 size_t BatchTable::bytes() const
 {
     return table_layout(*this).total;
@@ -341,9 +375,13 @@ BatchTable build_batch_table(size_t n, const llama_copy_item* items, const llama
 namespace {
 
 // Fills `b` (counts, grid) from table `t` and uploads the table into a new
-// device allocation, freeing the previous one.
-void install_table(Batch* b, const BatchTable& t, uint32_t wg_per_cu)
+// device allocation, freeing the previous one.  by_mode: the table sorted by
+// tile mode, one launch per mode (wg_per_cu is then ignored).
+void install_table(Batch* b, BatchTable t, uint32_t wg_per_cu, bool by_mode)
 {
+    b->ranges.clear();
+    if (by_mode)
+        b->ranges = t.sort_by_mode();
     b->total_units = t.units;
     b->lds_bytes = t.lds_bytes;
     b->items = t.items.size();
@@ -351,7 +389,7 @@ void install_table(Batch* b, const BatchTable& t, uint32_t wg_per_cu)
     b->stream_items = t.stream_items;
     b->read_bytes = t.read_bytes;
     b->write_bytes = t.write_bytes;
-    b->wg_per_cu = wg_per_cu ? wg_per_cu : batch_per_unit(t) ? 0 : batch_wg_per_cu(t.lds_bytes, b->threads);
+    b->wg_per_cu = by_mode ? 0 : wg_per_cu ? wg_per_cu : batch_per_unit(t) ? 0 : batch_wg_per_cu(t.lds_bytes, b->threads);
     b->grid = batch_grid(t.units, b->wg_per_cu);
     const size_t total = t.bytes();
     std::vector<uint8_t> host(total);
@@ -385,7 +423,7 @@ Batch* create_batch(size_t n, const llama_copy_item* items, const llama_copy_opt
     b->tile_records = opt ? opt->tile_records : 0u;
     b->threads = threads;
     check_hip(hipGetDevice(&b->device), "hipGetDevice");
-    install_table(b.get(), t, opt ? opt->wg_per_cu : 0);
+    install_table(b.get(), t, opt ? opt->wg_per_cu : 0, kBatchByModeDefault && !(opt && opt->wg_per_cu));
     return b.release();
 }
 
@@ -451,15 +489,17 @@ void autotune_batch(Batch* b, void* stream_ptr, int reps, double* best_gbs)
         const uint64_t want = hash(0x5A);
         struct Cand {
             uint32_t budget, threads, wg;
+            bool by_mode;
         };
-        Cand best{b->lds_budget, b->threads, b->wg_per_cu};
+        Cand best{b->lds_budget, b->threads, b->wg_per_cu, !b->ranges.empty()};
         double best_ms = time_it();
         // LDS per tiled item (the tile each item takes), threads, and the grid
         // (0: the default rule, else a persistent grid of that many
         // workgroups per compute unit)
+        // (grid 17: one launch per tile mode over a table sorted by mode)
         const uint32_t budgets[] = {8 * 1024, 16 * 1024, kBatchLdsBytes, 48 * 1024};
         const uint32_t threads[] = {128, 256, 512};
-        const uint32_t grids[] = {0, 2, 4, 8};
+        const uint32_t grids[] = {0, 2, 4, 8, 17};
         for (uint32_t bud : budgets)
             for (uint32_t th : threads)
                 for (uint32_t wg : grids) {
@@ -472,13 +512,13 @@ void autotune_batch(Batch* b, void* stream_ptr, int reps, double* best_gbs)
                     }
                     b->threads = th;
                     b->lds_budget = bud;
-                    install_table(b, t, wg);
+                    install_table(b, t, wg == 17 ? 0 : wg, wg == 17);
                     if (hash(0xA5) != want)
                         fail(LLAMA_E_HIP, "a batch tuning candidate wrote different bytes");
                     const double ms = time_it();
                     if (ms < best_ms) {
                         best_ms = ms;
-                        best = {bud, th, wg};
+                        best = {bud, th, wg == 17 ? 0 : wg, wg == 17};
                     }
                 }
         // re-plan with the fastest
@@ -487,7 +527,7 @@ void autotune_batch(Batch* b, void* stream_ptr, int reps, double* best_gbs)
             t.add(rq, best.threads, b->tile_records, b->flags, best.budget);
         b->threads = best.threads;
         b->lds_budget = best.budget;
-        install_table(b, t, best.wg);
+        install_table(b, t, best.wg, best.by_mode);
         if (best_gbs)
             *best_gbs = double(b->read_bytes + b->write_bytes) / (best_ms * 1e-3) / 1e9;
     } catch (...) {
@@ -500,7 +540,10 @@ void autotune_batch(Batch* b, void* stream_ptr, int reps, double* best_gbs)
 void copy_batch_noalloc(size_t n, const llama_copy_item* items, void* stream)
 {
     uint32_t threads = 0;
-    const BatchTable t = build_batch_table(n, items, nullptr, threads);
+    BatchTable t = build_batch_table(n, items, nullptr, threads);
+    std::vector<BatchRange> ranges;
+    if (kBatchByModeDefault)
+        ranges = t.sort_by_mode();
     if (t.units == 0)
         return;
     const size_t total = t.bytes();
@@ -519,6 +562,10 @@ void copy_batch_noalloc(size_t n, const llama_copy_item* items, void* stream)
     check_hip(hipMemcpyAsync((void*)uintptr_t(dev_table), host.data(), total, hipMemcpyHostToDevice,
                              (hipStream_t)stream),
               "hipMemcpyAsync(batch table into the static buffer)");
+    if (!ranges.empty()) {
+        launch_batch_ranges(args, ranges, threads, stream);
+        return;
+    }
     const uint32_t wg = batch_per_unit(t) ? 0 : batch_wg_per_cu(t.lds_bytes, threads);
     launch_batch_args(args, batch_grid(t.units, wg), threads, t.lds_bytes, wg != 0, stream);
 }

@@ -576,6 +576,8 @@ int llama_batch_get_info(const llama_batch* batch, llama_batch_info* info)
         info->wg_per_cu = b.wg_per_cu;
         info->workgroups = b.grid;
         info->lds_bytes = b.lds_bytes;
+        info->launches = b.ranges.empty() ? 1u : uint32_t(b.ranges.size());
+        info->reserved = 0;
     });
 }
 

@@ -692,7 +692,8 @@ enum : uint32_t {
     kModeDirectStore = 2,
     kModeDirectLoad = 3,
     kModeGatherStore = 4,
-    kModeGatherOdd = 5 // gather store with kTileGatherOdd
+    kModeGatherOdd = 5, // gather store with kTileGatherOdd
+    kModeStreamUnits = 6 // the batch kernel over long-run items only
 };
 // added to a mode: the tile's 16-byte destination stores are nontemporal
 constexpr uint32_t kModeStreamStores = 8;
@@ -1018,17 +1019,20 @@ __global__ void __launch_bounds__(1024) stream_count_kernel(const StreamArgs a)
 // Runs work unit g of item j (begin[j] <= g < begin[j + 1]).
 // `table_item`: the item whose gather word table the workgroup's LDS holds
 // (the table is copied when a unit of another gathering item comes).
-template <bool kOnce>
+template <bool kOnce, uint32_t Mode = kModeAny>
 __device__ __forceinline__ void batch_unit(const BatchArgs& a, const CONSTANT uint64_t* begin, uint32_t j,
                                            uint64_t g, uint8_t* lds, uint32_t& table_item)
 {
     const CONSTANT BatchItem* it = (const CONSTANT BatchItem*)a.items + j;
     const uint64_t u = g - begin[j];
-    if (it->kind == kItemTile) {
+    // a launch for one tile mode holds tile items only, a launch for
+    // kModeStreamUnits long-run items only (a table sorted by mode)
+    constexpr bool kGatherMode = (Mode & 7u) == kModeGatherStore || (Mode & 7u) == kModeGatherOdd;
+    if (Mode != kModeStreamUnits && (Mode != kModeAny || it->kind == kItemTile)) {
         const TileHeader h = load_const(&it->h);
         const CONSTANT TileEntry* entries = (const CONSTANT TileEntry*)a.entries + it->first;
         TileGather gg{};
-        if (h.flags & kTileGatherStore) {
+        if (kGatherMode || (Mode == kModeAny && (h.flags & kTileGatherStore))) {
             gg = load_const(&it->gather);
             if (table_item != j) {
                 // the previous unit's barrier has ended every read of the
@@ -1039,7 +1043,7 @@ __device__ __forceinline__ void batch_unit(const BatchArgs& a, const CONSTANT ui
         } else if (h.lds_bytes > 0) {
             table_item = ~0u; // this unit's regions may cover the table
         }
-        tile_body<kModeAny | (kOnce ? kModeStreamLoads : 0u)>(
+        tile_body<Mode | (kOnce ? kModeStreamLoads : 0u)>(
             h, [&](uint32_t k) -> const CONSTANT TileEntry& { return entries[k]; }, u, lds, &gg);
     } else {
         const CONSTANT StreamRun* runs = (const CONSTANT StreamRun*)a.runs + it->first;
@@ -1094,6 +1098,40 @@ __global__ void __launch_bounds__(1024) batch_unit_kernel(const BatchArgs a)
         }
         batch_unit<kOnce>(a, begin, lo, g, lds, table_item);
         if (g + stride < nt)
+            __syncthreads();
+    }
+}
+
+// One launch per tile mode over a table sorted by mode: workgroup k runs
+// unit first + k of a range whose items all take one mode (Mode, or kModeAny
+// for long-run items), so each mode runs in its own compiled body and
+// register allocation, with the range's own LDS reservation.
+template <bool kOnce, uint32_t Mode>
+__global__ void __launch_bounds__(1024) batch_mode_kernel(const BatchArgs a, uint64_t first, uint64_t count)
+{
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    const CONSTANT uint64_t* begin = (const CONSTANT uint64_t*)a.unit_begin;
+    uint64_t k = blockIdx.x, stride = gridDim.x;
+    if (gridDim.x == count) { // each XCD takes one contiguous eighth of the range
+        const uint64_t b = blockIdx.x, x = b & 7u, kk = b >> 3, q = count >> 3, rem = count & 7u;
+        k = x * q + min(x, rem) + kk;
+        stride = count;
+    }
+    const CONSTANT uint32_t* hint = (const CONSTANT uint32_t*)a.hint;
+    uint32_t table_item = ~0u;
+    for (; k < count; k += stride) {
+        const uint64_t g = first + k;
+        const uint64_t c = g >> kBatchHintLog2;
+        uint32_t lo = hint[c], hi = min(hint[c + 1] + 1u, a.num_items);
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (begin[mid] <= g)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        batch_unit<kOnce, Mode>(a, begin, lo, g, lds, table_item);
+        if (k + stride < count)
             __syncthreads();
     }
 }
@@ -1992,6 +2030,9 @@ const void* box_kernel_for(const BoxArgs& b, bool counted)
 
 bool g_attr_set = false;
 
+template <bool kOnce>
+const void* batch_mode_kernel_for(uint32_t key);
+
 void set_attributes()
 {
     if (g_attr_set)
@@ -2005,6 +2046,18 @@ void set_attributes()
     for (const void* k : kBoxKernels)
         check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes)),
                   "hipFuncSetAttribute(box_kernel)");
+    for (const void* const* table : {kTileVirtualKernels, kTileVirtualCountKernels, kTileScatterKernels,
+                                     kTileSplitSrcKernels, kTileSplitDstKernels})
+        for (size_t j = 0; j < (table == kTileVirtualKernels ? 3 * kTileModes : table == kTileVirtualCountKernels ? kTileModes : 4); j++)
+            if (table[j])
+                check_hip(hipFuncSetAttribute(table[j], hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes)),
+                          "hipFuncSetAttribute(tile_kernel variant)");
+    for (uint32_t key : {uint32_t(kModeAny), uint32_t(kModeStreamUnits), uint32_t(kModeStaged), uint32_t(kModeDirectStore),
+                         kModeDirectStore | kModeSplitSrc, uint32_t(kModeDirectLoad), kModeDirectLoad | kModeSplitDst,
+                         uint32_t(kModeGatherStore), uint32_t(kModeGatherOdd)})
+        for (const void* k : {batch_mode_kernel_for<false>(key), batch_mode_kernel_for<true>(key)})
+            check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes)),
+                      "hipFuncSetAttribute(batch_mode_kernel)");
     for (const void* k : {(const void*)batch_kernel<false>, (const void*)batch_kernel<true>,
                           (const void*)batch_unit_kernel<false>, (const void*)batch_unit_kernel<true>})
         check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(kHardLdsBytes - 64)),
@@ -2271,9 +2324,66 @@ uint64_t scratch_address()
     return g_scratch_addr[dev];
 }
 
+namespace {
+// batch_mode_kernel by mode key (kModeAny for long-run items; a tile mode,
+// with kModeSplitSrc or kModeSplitDst) and nontemporal loads
+template <bool kOnce>
+const void* batch_mode_kernel_for(uint32_t key)
+{
+    switch (key) {
+    case kModeAny: return (const void*)batch_mode_kernel<kOnce, kModeAny>;
+    case kModeStreamUnits: return (const void*)batch_mode_kernel<kOnce, kModeStreamUnits>;
+    case kModeStaged: return (const void*)batch_mode_kernel<kOnce, kModeStaged>;
+    case kModeDirectStore: return (const void*)batch_mode_kernel<kOnce, kModeDirectStore>;
+    case kModeDirectStore | kModeSplitSrc: return (const void*)batch_mode_kernel<kOnce, kModeDirectStore | kModeSplitSrc>;
+    case kModeDirectLoad: return (const void*)batch_mode_kernel<kOnce, kModeDirectLoad>;
+    case kModeDirectLoad | kModeSplitDst: return (const void*)batch_mode_kernel<kOnce, kModeDirectLoad | kModeSplitDst>;
+    case kModeGatherStore: return (const void*)batch_mode_kernel<kOnce, kModeGatherStore>;
+    case kModeGatherOdd: return (const void*)batch_mode_kernel<kOnce, kModeGatherOdd>;
+    default: return nullptr;
+    }
+}
+} // namespace
+
+uint32_t batch_mode_key(const BatchItem& it)
+{
+    if (it.kind != kItemTile)
+        return kModeStreamUnits;
+    const uint32_t f = it.h.flags;
+    if (f & kTileDirectLoad)
+        return kModeDirectLoad | ((f & kTileSplitDst) ? kModeSplitDst : 0u);
+    if (f & kTileDirectStore)
+        return kModeDirectStore | ((f & kTileSplitSrc) ? kModeSplitSrc : 0u);
+    if (f & kTileGatherStore)
+        return (f & kTileGatherOdd) ? kModeGatherOdd : kModeGatherStore;
+    return kModeStaged;
+}
+
+void launch_batch_ranges(const BatchArgs& b_args, const std::vector<BatchRange>& ranges, uint32_t threads,
+                         void* stream)
+{
+    set_attributes();
+    const bool once = (b_args.flags & kBatchLoadsOnce) != 0;
+    for (const BatchRange& r : ranges) {
+        const void* k = once ? batch_mode_kernel_for<true>(r.key) : batch_mode_kernel_for<false>(r.key);
+        if (!k)
+            fail(LLAMA_E_INVALID_ARG, "no batch kernel for tile mode key " + std::to_string(r.key));
+        BatchArgs args = b_args;
+        uint64_t first = r.first_unit, count = r.units;
+        void* kargs[] = {(void*)&args, (void*)&first, (void*)&count};
+        const uint32_t grid = uint32_t(std::min<uint64_t>(count, kBatchMaxGrid));
+        check_hip(hipLaunchKernel(k, dim3(grid), dim3(threads), kargs, r.lds_bytes, (hipStream_t)stream),
+                  "hipLaunchKernel(batch by mode)");
+        check_hip(hipGetLastError(), "batch kernel launch");
+    }
+}
+
 void launch_batch_kernel(const Batch& b, void* stream)
 {
-    launch_batch_args(b.args, b.grid, b.threads, b.lds_bytes, b.wg_per_cu != 0, stream);
+    if (b.ranges.empty())
+        launch_batch_args(b.args, b.grid, b.threads, b.lds_bytes, b.wg_per_cu != 0, stream);
+    else
+        launch_batch_ranges(b.args, b.ranges, b.threads, stream);
 }
 
 } // namespace llama

@@ -112,7 +112,7 @@ class BatchInfo(ctypes.Structure):
     _fields_ = [("items", ctypes.c_uint64), ("tile_items", ctypes.c_uint64), ("stream_items", ctypes.c_uint64),
                 ("work_units", ctypes.c_uint64), ("read_bytes", ctypes.c_uint64), ("write_bytes", ctypes.c_uint64),
                 ("threads", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32), ("workgroups", ctypes.c_uint32),
-                ("lds_bytes", ctypes.c_uint32)]
+                ("lds_bytes", ctypes.c_uint32), ("launches", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class HeatmapDesc(ctypes.Structure):

@@ -132,14 +132,16 @@ ONE_CLASS = [("particle", ("soa_single", 0), ("aosoa", 32)), ("particle", ("aos_
 @pytest.mark.parametrize("case", ONE_CLASS, ids=[f"{c[0]}-{c[1][0]}{c[1][1] or ''}-{c[2][0]}{c[2][1] or ''}"
                                                  for c in ONE_CLASS])
 def test_one_class_batch_runs_one_workgroup_per_unit(L, orc, case):
-    """Items that share one LDS class (frames of one layout pair) run one
-    workgroup per work unit; a batch with items of several classes runs a
-    persistent grid.  Both leave the oracle's bytes, over two graph replays."""
+    """Items of one layout pair (one tile mode) run one launch, one workgroup
+    per work unit; a batch with items of several tile modes sorts its table
+    by mode and runs one launch per mode, and with a persistent grid
+    (wg_per_cu) one launch of the dispatching kernel.  All leave the oracle's
+    bytes, over graph replays."""
     name, a, b = case
     items, want = make_items_pair(L, orc, 41, 30, 5000, name, a, b)
     bt = L.Batch(items)
     info = bt.info()
-    assert info["wg_per_cu"] == 0 and info["workgroups"] == info["work_units"]
+    assert info["wg_per_cu"] == 0 and info["workgroups"] == info["work_units"] and info["launches"] == 1
     torch.cuda.synchronize()
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -147,15 +149,19 @@ def test_one_class_batch_runs_one_workgroup_per_unit(L, orc, case):
         bt.launch()
     stream.synchronize()
     check(items, want)
-    # adding items of another class makes the batch persistent
+    # adding items of other modes: one launch per mode, or one persistent launch
     more, more_want = make_items(L, orc, 43, count=12, nmax=5000)
     mixed_batch = L.Batch(items + more)
-    assert mixed_batch.info()["wg_per_cu"] > 0
-    torch.cuda.synchronize()
-    with torch.cuda.stream(stream):
-        mixed_batch.launch()
-    stream.synchronize()
-    check(items + more, want + more_want)
+    assert mixed_batch.info()["launches"] > 1 and mixed_batch.info()["wg_per_cu"] == 0
+    persistent = L.Batch(items + more, wg_per_cu=4)
+    assert persistent.info()["launches"] == 1 and persistent.info()["wg_per_cu"] == 4
+    for bt2, fill in ((mixed_batch, 0x11), (persistent, 0x22), (mixed_batch, 0x33)):
+        refill(items + more, fill)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            bt2.launch()
+        stream.synchronize()
+        check(items + more, want + more_want)
 
 
 def make_items_pair(L, orc, seed, count, nmax, name, a, b):
