@@ -206,14 +206,21 @@ def time_pairs(L, torch, maps, blobs, pairs, steps, warmup, stream, flush=None):
             L.copy(maps[a], blobs[a], maps[b], blobs[b], stream=stream)
     torch.cuda.synchronize()
     ev = {p: [] for p in pairs}
+    # every event exists before the clock starts: creating one is host work
+    # that, between two copies, can leave the GPU idle
+    pending = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps * len(pairs))]
+    for e0, e1 in pending:  # the runtime creates an event at its first record
+        e0.record(stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     start.record(stream)
     for k in range(steps):
         for a, b in pairs:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
+            e0, e1 = pending.pop()
             if flush is not None:
                 with torch.cuda.stream(stream):
                     flush.sum(dtype=torch.int64)  # reads it: evicts without leaving dirty lines

@@ -295,6 +295,11 @@ typedef struct {
  * runs.  Without padding in the destination the flag changes nothing. */
 #define LLAMA_COPY_PRESERVE_PADDING 4u
 
+/* TILE: do not take LLAMA_TILE_GATHER_STORE.  Where the gather store would
+ * apply, the planner tries the direct load, else stages both regions.  Only the
+ * speed changes; llama_autotune tries it per copy class. */
+#define LLAMA_COPY_NO_GATHER 8u
+
 /* llama_copy with explicit kernel parameters.  The result does not depend on
  * the options; only the speed does. */
 int llama_copy_ex(const llama_mapping_desc* src, const llama_blob* src_blobs, const llama_mapping_desc* dst,

@@ -204,6 +204,8 @@ int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, con
         } else {
             p = make_plan(rq, options);
         }
+        if (trace_enabled())
+            trace_plan(p);
         fill_info(p, info);
     });
 }

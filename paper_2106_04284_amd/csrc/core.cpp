@@ -1194,62 +1194,80 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
                     src_of[b] = p0 | (run << 18) | (jj << 23);
                 }
         }
-        std::vector<uint32_t> table(gwords), bytes;
-        // With q = 0 every source byte of super-block b lies kq bytes past its
-        // place in super-block 0, whatever its leaf, so 4 source bytes that
-        // are consecutive in super-block 0 are consecutive in every one.  Into
-        // AoS (no lanes past the last record: a tile's span holds records
-        // with values only) such a word is read whole even where it spans
-        // two leaves of a record (a packed record whose leaves keep their
-        // aligned offsets: only the words across record boundaries stay
-        // composite).
-        const bool contiguous_whole = g.q == 0 && rq.dst.lanes == 1 && (g.kq & 3u) == 0;
-        for (uint64_t w = 0; w < gwords; w++) {
+        // Every destination word becomes pieces: the bytes that read as one
+        // 4-byte window of the source region in every super-block (consecutive
+        // source bytes of one run shift, or of any leaf when q = 0, where
+        // every byte of super-block b lies kq * b past its place in
+        // super-block 0).  A piece is one entry: p0, the source byte that the
+        // word's byte 0 lines up with, its run and the word bytes it gives.
+        // A word of one piece (or none: padding) is its own table entry; a
+        // word of two pieces points to a pair of entries, of three or four to
+        // a group of four, placed after the word entries.
+        std::vector<uint32_t> table(gwords), quads, pairs;
+        bool pieces_ok = true;
+        for (uint64_t w = 0; w < gwords && pieces_ok; w++) {
             const uint32_t* x = &src_of[4 * w];
-            // the word's position modulo 4 is the same in every super-block
-            const bool steady = (g.kq & 3u) == 0 && (g.q == 0 || ((x[0] >> 18) & 31u) >= 2);
-            const bool bytes_follow = ((x[0] | x[1] | x[2] | x[3]) >> 31) == 0 &&
-                                      (x[1] & 0x3FFFFu) == (x[0] & 0x3FFFFu) + 1 &&
-                                      (x[2] & 0x3FFFFu) == (x[0] & 0x3FFFFu) + 2 &&
-                                      (x[3] & 0x3FFFFu) == (x[0] & 0x3FFFFu) + 3;
-            if (((x[0] >> 31) == 0 && x[1] == x[0] + 1 && x[2] == x[0] + 2 && x[3] == x[0] + 3 && steady) ||
-                (contiguous_whole && bytes_follow)) {
-                table[w] = x[0] | ((x[0] & 3u) ? 1u << 30 : 0u); // bit 30: read funnel-shifted
-            } else if (((x[0] & x[1] & x[2] & x[3]) >> 31) != 0) {
-                table[w] = 1u << 31;
+            uint32_t piece[4], n = 0;
+            for (uint32_t k = 0; k < 4; k++) {
+                if (x[k] >> 31) // padding: no piece, the byte stays zero
+                    continue;
+                const uint32_t pos = x[k] & 0x3FFFFu, run = g.q == 0 ? 0u : (x[k] >> 18) & 31u;
+                if (pos < k || pos - k >= (1u << 18)) {
+                    pieces_ok = false; // the window would start before the region
+                    break;
+                }
+                const uint32_t key = (pos - k) | (run << 18);
+                uint32_t j = 0;
+                while (j < n && (piece[j] & 0x7FFFFFu) != key)
+                    j++;
+                if (j == n)
+                    piece[n++] = key;
+                piece[j] |= 1u << (23 + k);
+            }
+            if (!pieces_ok)
+                break;
+            if (n <= 1) {
+                table[w] = n ? piece[0] : 0u;
+            } else if (n == 2) {
+                table[w] = (1u << 30) | uint32_t(pairs.size());
+                pairs.insert(pairs.end(), piece, piece + 2);
             } else {
-                table[w] = (3u << 30) | uint32_t(bytes.size() / 4);
-                bytes.insert(bytes.end(), x, x + 4);
+                while (n < 4)
+                    piece[n++] = 0u; // gives no byte
+                table[w] = (2u << 30) | uint32_t(quads.size());
+                quads.insert(quads.end(), piece, piece + 4);
             }
         }
-        table.insert(table.end(), bytes.begin(), bytes.end());
-        const uint64_t composite = bytes.size() / 4;
+        // groups of four at a 16-byte boundary, then the pairs; a group's
+        // entry holds its index in the table
+        const uint32_t quads_at = uint32_t((gwords + 3) & ~uint64_t(3));
+        const uint32_t pairs_at = quads_at + uint32_t(quads.size());
+        for (uint64_t w = 0; w < gwords; w++)
+            if ((table[w] >> 30) == 1u)
+                table[w] += pairs_at;
+            else if ((table[w] >> 30) == 2u)
+                table[w] += quads_at;
+        table.resize(quads_at, 0u);
+        table.insert(table.end(), quads.begin(), quads.end());
+        table.insert(table.end(), pairs.begin(), pairs.end());
         g.table = uint32_t(table.size());
-        // composite words read 4 bytes each: into AoS the gather still beats
-        // the staged mode with a quarter of the words composite (listing 1's
-        // aligned record: +75%), into AoSoA it loses beyond about 1/16 (the
-        // u16 and bool lanes of listing 1: -15 to -35%; the mixed record's u8
-        // lanes, 2% of the words: within a few percent either way); the table
-        // travels after the entries in the argument block
-        const uint64_t share = rq.dst.lanes == 1 ? 4 : 16;
+        // a word of two pieces costs about two reads of one, of four about
+        // four; the gather store takes the tile while the table fits the
+        // argument block and LDS and its words average at most
+        // kGatherMaxReadsPct / 100 reads
+        const uint64_t cost = gwords + pairs.size() / 2 + 3 * (quads.size() / 4);
+        const uint64_t base = (uint64_t(sb) + 15) & ~uint64_t(15); // the table, 16-byte aligned
         const uint64_t table_bytes = (table.size() * 4 + 15) / 16 * 16;
         const uint64_t room = uint64_t(kTileMaxEntries - a.num_entries - C) * (sizeof(TileEntry) / 4);
-        // words at odd positions (read funnel-shifted) pay off into AoS and
-        // into AoSoA with long lane runs: from the packed 49-byte record +60%
-        // into aligned AoS, +7% and +21% into AoSoA32 and AoSoA64, but -9%
-        // into AoSoA8
-        bool shifted = false;
-        for (uint64_t w = 0; w < gwords && !shifted; w++)
-            shifted = (table[w] >> 30) == 1u;
-        const bool odd_ok = !shifted || rq.dst.lanes == 1 || rq.dst.lanes >= 32;
-        if (composite * share <= gwords && table.size() <= room && odd_ok &&
-            uint64_t(sb) + table_bytes <= std::min<uint64_t>(lds_limit, kHardLdsBytes)) {
+        if (pieces_ok && !(p.flags_in & kPlanNoGather) && cost * 100 <= gwords * kGatherMaxReadsPct &&
+            table.size() <= room && table.size() < (1u << 16) &&
+            base + table_bytes <= std::min<uint64_t>(lds_limit, kHardLdsBytes)) {
             a.flags |= kTileGatherStore;
-            if (shifted || rq.dst.block % 4 != 0)
+            if (rq.dst.block % 4 != 0)
                 a.flags |= kTileGatherOdd;
-            a.dst.lds_base = sb;
+            a.dst.lds_base = uint32_t(base);
             a.dst.lds_bytes = uint32_t(table_bytes);
-            a.lds_bytes = uint32_t(sb + table_bytes);
+            a.lds_bytes = uint32_t(base + table_bytes);
             ta.gather = g;
             std::memcpy(&ta.e[a.num_entries + C], table.data(), table.size() * 4);
             for (size_t f = 0; f < F; f++)
@@ -1553,6 +1571,24 @@ Plan make_plan_raw(const Request& rq, const llama_copy_options* opt)
                     p = q;
             }
         }
+        if (ok && (p.tile.h.flags & kTileGatherStore) && rq.dst.lanes >= 32 && p.tile.h.src.mode == kFieldMajor) {
+            // into AoSoA lane runs of 32 records or more from a field-major
+            // source, loading the source granules into registers beats reading
+            // them word by word (the mixed record from SoA into AoSoA32 and
+            // AoSoA64: 5-11%)
+            Plan q = p;
+            q.flags_in |= kPlanNoGather;
+            uint32_t slots = 0;
+            for (const Leaf& l : rq.record.leaves)
+                slots += uint32_t((uint64_t(t) * l.size / 16 + 63) / 64 * 64);
+            q.threads = threads ? threads
+                                : std::max(nthreads(t), (slots + kDirectLoadSlots * 64 - 1) / (kDirectLoadSlots * 64) * 64);
+            if (q.threads <= 1024 && fill_tile(rq, t, T ? kHardLdsBytes : kMaxLdsBytes, q) &&
+                (q.tile.h.flags & kTileDirectLoad)) {
+                q.flags_in = p.flags_in;
+                p = q;
+            }
+        }
         if (ok && !threads && (p.tile.h.flags & kTileGatherStore) && p.threads < 256 &&
             (p.threads < 192 || p.tile.h.src.mode == kRecordMajor)) {
             // a gathering tile assembles every destination word on its own:
@@ -1637,6 +1673,14 @@ void trace_plan(const Plan& p)
                                         : " mode=staged";
         mode += " tile=" + std::to_string(1u << p.tile.h.log2_tile) + " entries=" +
                 std::to_string(p.tile.h.num_entries) + " lds=" + std::to_string(p.tile.h.lds_bytes);
+        if (f & kTileGatherStore) { // words per super-block, and their reads of one piece each
+            const uint32_t chunks = (f & kTileVirtualSrc) ? p.tile.h.slots : 0u;
+            const uint32_t* tab = reinterpret_cast<const uint32_t*>(&p.tile.e[p.tile.h.num_entries + chunks]);
+            uint64_t cost = 0;
+            for (uint32_t w = 0; w < p.tile.gather.words; w++)
+                cost += (tab[w] >> 30) == 0u ? 1u : (tab[w] >> 30) == 1u ? 2u : 4u;
+            mode += " words=" + std::to_string(p.tile.gather.words) + " reads=" + std::to_string(cost);
+        }
         if (f & kTilePreserve)
             mode += " keep_padding";
         if (f & kTileStreamLoads)

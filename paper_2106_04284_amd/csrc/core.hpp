@@ -220,9 +220,11 @@ void copy_box(const llama_mapping_desc* src, const llama_blob* src_blobs, const 
 constexpr uint32_t kPlanNoDirect = LLAMA_COPY_NO_DIRECT;
 constexpr uint32_t kPlanNoSplit = LLAMA_COPY_NO_SPLIT;
 constexpr uint32_t kPlanPreserve = LLAMA_COPY_PRESERVE_PADDING;
-constexpr uint32_t kCopyFlags = LLAMA_COPY_NO_DIRECT | LLAMA_COPY_NO_SPLIT | LLAMA_COPY_PRESERVE_PADDING; // every bit
+constexpr uint32_t kPlanNoGather = LLAMA_COPY_NO_GATHER;
+constexpr uint32_t kCopyFlags =
+    LLAMA_COPY_NO_DIRECT | LLAMA_COPY_NO_SPLIT | LLAMA_COPY_PRESERVE_PADDING | LLAMA_COPY_NO_GATHER; // every bit
 // the flags that change only speed, which the tuner may choose and cache
-constexpr uint32_t kTuneFlags = LLAMA_COPY_NO_DIRECT | LLAMA_COPY_NO_SPLIT;
+constexpr uint32_t kTuneFlags = LLAMA_COPY_NO_DIRECT | LLAMA_COPY_NO_SPLIT | LLAMA_COPY_NO_GATHER;
 
 // LLAMA_TRACE set in the environment (to anything but "0"): every launch
 // writes one line describing its plan to stderr

@@ -65,24 +65,24 @@ constexpr uint32_t kMoveSplit = 1u << 3;
 // kTileGatherStore: where the words of the destination find their sources.
 // The word table covers a super-block: 1, 2 or 4 destination blocks (2^lg
 // records), enough that its bytes, and the source bytes that its records
-// advance by, are whole 4-byte words.  Entry w describes 4-byte word w of
-// super-block 0:
-//   bit 31 clear:     a whole word of one value: the LDS byte p0 of its
-//                     source for super-block 0 (bits 0-17), log2 of the bytes
-//                     of 2^lg values of its leaf (bits 18-22), its record
-//                     j < 2^lg in the super-block (bits 23-29), and bit 30
-//                     when p0 is not a multiple of 4 (the word is then read as
-//                     the two aligned words that hold it, funnel-shifted);
-//   bits 31-30 = 10:  padding (zero);
-//   bits 31-30 = 11:  a composite word (its bytes come from different values
-//                     or padding): bits 0-15 index c, and entries words + 4c
-//                     .. words + 4c + 3 of the table give its 4 bytes' sources
-//                     in the same form (bit 31: a zero byte).
-// A word is whole when its 4 bytes are consecutive bytes of one value whose
-// position modulo 4 is the same in every super-block.  The table follows the
-// entries: in the argument block at entry num_entries (reinterpreted as
-// 32-bit words), in a batch after the item's entries.  A source of
-// super-block b lies at LDS byte
+// advance by, are whole 4-byte words.  A word's bytes come in pieces: bytes
+// that are one 4-byte window of the source region in every super-block.  A
+// piece entry holds the LDS byte p0 that the word's byte 0 lines up with in
+// super-block 0 (bits 0-17; the window is read from the two aligned words
+// that hold it), log2 of the bytes of 2^lg values of its leaf (run, bits
+// 18-22; 0 when q = 0) and the word bytes it gives (bits 23-26).  Entry w of
+// the table describes word w of super-block 0:
+//   bits 31-30 = 00:  the word is one piece, this entry (no byte: padding);
+//   bits 31-30 = 01:  two pieces, the entries at table index bits 0-15;
+//   bits 31-30 = 10:  three or four pieces, the four entries at index bits
+//                     0-15 (16-byte aligned; an unused one gives no byte).
+// The word entries are padded to a multiple of 4; the groups of four follow,
+// then the pairs.  Records without values (tail lanes of the last AoSoA
+// block) are cleared in the source region before the tile's words are read.
+// The table follows the entries: in the argument block at entry num_entries
+// (reinterpreted as 32-bit words), in a batch after the item's entries; in
+// LDS it sits at dst.lds_base, 16-byte aligned.  A piece of super-block b lies
+// at LDS byte
 //   p0 + (b >> q) * kq + ((b & (2^q - 1)) << run)
 // (a source with at most 2^lg lanes per block: q = 0 and kq the source bytes
 // of 2^lg records; a source with more: q = log2 of its lanes over 2^lg (31
@@ -94,7 +94,7 @@ struct TileGather {
     uint32_t magic; // ceil(2^32 / words): u / words == mulhi(u, magic) for u * words < 2^32
     uint32_t q, lg; // lg: log2 of the records of a super-block
     uint32_t kq;
-    uint32_t table; // 32-bit words of the table: words + 4 per composite word
+    uint32_t table; // 32-bit words of the table: word entries, groups of four, pairs
 };
 
 struct TileHeader {
@@ -146,6 +146,14 @@ constexpr uint32_t kTilePreserve = 4;
 constexpr uint32_t kTileGatherStore = 8;
 constexpr uint32_t kGatherMaxWords = 4096; // word table entries (16 KiB of LDS without composite words)
 constexpr uint32_t kGatherMaxLanes = 128;
+// the gather store takes a tile while its words average at most
+// kGatherMaxReadsPct / 100 piece reads (a word of two pieces reads 2, of three
+// or four 4).  Measured against the staged mode and the direct load: 1.00 to
+// 1.38 reads gain 3-140% (particle, lattice-Boltzmann, mixed and listing 1
+// records), 1.48 breaks even (listing 1 aligned into packed AoS), 1.52 and
+// more lose 11-39% (listing 1's u16 and bool lanes into AoSoA, the 49-byte
+// packed mixed record from SoA or AoSoA)
+constexpr uint32_t kGatherMaxReadsPct = 145;
 
 // The tile's 16-byte destination stores carry the nontemporal hint: set for
 // destinations several times larger than the 256 MB Infinity Cache.

@@ -604,23 +604,50 @@ __device__ __forceinline__ void gather_table(const TileHeader& h, const TileGath
         tab[k] = table[k];
 }
 
-// LDS byte of a gather source (a word-table entry of a whole word, or a byte
-// entry of a composite word) in destination block blk.
-__device__ __forceinline__ uint32_t gather_pos(uint32_t x, uint32_t blk, const TileGather& gg)
+// One piece of a destination word (a word-table entry, or an entry of a group
+// of pieces): the 4 source bytes at LDS byte p = p0 + (blk >> q) * kq +
+// ((blk & (2^q - 1)) << run) in destination super-block blk, read from the two
+// aligned words that hold them, with the bytes the piece does not give
+// cleared.  Bits 0-17: p0 (the source byte that the word's byte 0 lines up
+// with), 18-22: run, 23-26: the word bytes the piece gives.
+__device__ __forceinline__ uint32_t gather_piece(uint32_t x, uint32_t bq, uint32_t bm, const uint8_t* lds)
 {
-    return (x & 0x3FFFFu) + (blk >> gg.q) * gg.kq + ((blk & ((1u << gg.q) - 1u)) << ((x >> 18) & 31u));
+    const uint32_t p = (x & 0x3FFFFu) + bq + (bm << ((x >> 18) & 31u));
+    const uint32_t* wp = (const uint32_t*)(lds + (p & ~3u));
+    const uint32_t v = __builtin_amdgcn_alignbyte(wp[1], wp[0], p & 3u);
+    // bit k of the 4-bit byte mask to all of byte k
+    const uint32_t m = ((((x >> 23) & 15u) * 0x204081u) & 0x01010101u) * 0xFFu;
+    return v & m;
+}
+
+// Records without values in a tile's source region ([nv, nd): the tail lanes
+// of the last AoSoA block) read as zero, so that the gather store needs no
+// per-record test: their leaf bytes in LDS are cleared.
+template <typename Entries>
+__device__ __forceinline__ void zero_source_records(const TileHeader& h, Entries ent, uint32_t nv, uint32_t nd,
+                                                    uint32_t tid, uint32_t nthr, uint8_t* lds)
+{
+    for (uint32_t f = 0; f < h.num_leaves; f++) {
+        const auto& e = ent(f);
+        for (uint32_t r = nv + tid; r < nd; r += nthr) {
+            const uint32_t p = e.src_pos + (r >> h.src.pos_lg) * h.src.pos_k + (r & h.src.pos_m) * e.size;
+            for (uint32_t b = 0; b < e.size; b++)
+                lds[p + b] = 0;
+        }
+    }
 }
 
 // Gather store of one tile: every thread assembles 16-byte granules of the
-// destination span word by word from the source region and stores them;
-// padding and records >= nv are zero.
+// destination span word by word from the source region and stores them.  A
+// word is one piece (its entry in the table), two or four pieces (a group of
+// entries the table points to); padding bytes belong to no piece and stay
+// zero, and so do records without values (cleared in the source region).
 template <bool kStream, bool kOdd, bool kCount>
-__device__ __forceinline__ void gather_store_tile(const TileHeader& h, const TileGather& gg, uint64_t t, uint32_t nv,
-                                                  uint32_t nd, uint32_t tid, uint32_t nthr, const uint8_t* lds)
+__device__ __forceinline__ void gather_store_tile(const TileHeader& h, const TileGather& gg, uint64_t t, uint32_t nd,
+                                                  uint32_t tid, uint32_t nthr, const uint8_t* lds)
 {
     const uint32_t* tab = (const uint32_t*)(lds + h.dst.lds_base);
-    const uint32_t* btab = tab + gg.words; // the byte sources of composite words
-    const uint32_t lgd = gg.lg;            // records per super-block, log2
+    const uint32_t qm = (1u << gg.q) - 1u;
     // the span's bytes; a block of odd size can end it inside a word
     const uint32_t span = uint32_t(((uint64_t(nd) + h.dst.lanes - 1) >> h.dst.log2_lanes) * h.dst.block);
     const uint32_t words = (span + 3u) >> 2;
@@ -632,24 +659,18 @@ __device__ __forceinline__ void gather_store_tile(const TileHeader& h, const Til
 #pragma unroll
         for (uint32_t c = 0; c < 4; c++) {
             const uint32_t e = tab[w];
-            uint32_t x = 0;
-            if ((e >> 31) == 0) {
-                if ((blk << lgd) + ((e >> 23) & 127u) < nv) {
-                    const uint32_t p = gather_pos(e, blk, gg);
-                    if (kOdd && (e & (1u << 30))) { // at p mod 4 = 1..3: the two aligned words that hold it
-                        const uint32_t* wp = (const uint32_t*)(lds + (p & ~3u));
-                        x = uint32_t(((uint64_t(wp[1]) << 32) | wp[0]) >> ((p & 3u) * 8u));
-                    } else {
-                        x = *(const uint32_t*)(lds + p);
-                    }
-                }
-            } else if ((e >> 30) == 3u) {
-#pragma unroll
-                for (uint32_t k = 0; k < 4; k++) {
-                    const uint32_t be = btab[4u * (e & 0xFFFFu) + k];
-                    if ((be >> 31) == 0 && (blk << lgd) + ((be >> 23) & 127u) < nv)
-                        x |= uint32_t(lds[gather_pos(be, blk, gg)]) << (8u * k);
-                }
+            const uint32_t bq = (blk >> gg.q) * gg.kq, bm = blk & qm;
+            const uint32_t kind = e >> 30;
+            uint32_t x;
+            if (kind == 0u) {
+                x = gather_piece(e, bq, bm, lds);
+            } else if (kind == 1u) { // two pieces
+                const uint2 g = *(const uint2*)(tab + (e & 0xFFFFu));
+                x = gather_piece(g.x, bq, bm, lds) | gather_piece(g.y, bq, bm, lds);
+            } else { // four pieces
+                const u32x4 g = *(const u32x4*)(tab + (e & 0xFFFFu));
+                x = gather_piece(g.x, bq, bm, lds) | gather_piece(g.y, bq, bm, lds) |
+                    gather_piece(g.z, bq, bm, lds) | gather_piece(g.w, bq, bm, lds);
             }
             v[c] = x;
             if (++w == gg.words) {
@@ -796,10 +817,14 @@ __device__ __forceinline__ void tile_body(const TileHeader& h, Entries ent, uint
     if (gstore) {
         // ---- 2'''. assemble every destination granule word by word from
         //           the source region and store it; no destination region
+        if (nv < nd) {
+            zero_source_records(h, ent, nv, nd, tid, nthr, lds);
+            __syncthreads();
+        }
         if (Mode == kModeGatherOdd || (Mode == kModeAny && (h.flags & kTileGatherOdd)))
-            gather_store_tile<kStream, true, kCount>(h, *gg, t, nv, nd, tid, nthr, lds);
+            gather_store_tile<kStream, true, kCount>(h, *gg, t, nd, tid, nthr, lds);
         else
-            gather_store_tile<kStream, false, kCount>(h, *gg, t, nv, nd, tid, nthr, lds);
+            gather_store_tile<kStream, false, kCount>(h, *gg, t, nd, tid, nthr, lds);
         return;
     }
 

@@ -187,7 +187,7 @@ void autotune(const Request& rq, void* stream_ptr, int reps, llama_copy_options&
     for (uint32_t T = 16; T <= 4096; T *= 2)
         for (uint32_t th : {64u, 128u, 256u})
             if (T / 4 <= 4 * th && T >= th / 4)
-                for (uint32_t flags : {0u, LLAMA_COPY_NO_DIRECT})
+                for (uint32_t flags : {0u, LLAMA_COPY_NO_DIRECT, LLAMA_COPY_NO_GATHER})
                     cands.push_back({LLAMA_PATH_TILE, T, th, 0, flags});
     for (const llama_copy_options& c : cands) {
         Plan p;
@@ -201,6 +201,13 @@ void autotune(const Request& rq, void* stream_ptr, int reps, llama_copy_options&
             llama_copy_options d = c;
             d.flags = 0;
             if (!(make_plan(rq, &d).tile.h.flags & (kTileDirectStore | kTileDirectLoad | kTileGatherStore)))
+                continue;
+        }
+        // likewise without the gather store where the default takes none
+        if ((c.flags & LLAMA_COPY_NO_GATHER) && p.path == LLAMA_PATH_TILE) {
+            llama_copy_options d = c;
+            d.flags = 0;
+            if (!(make_plan(rq, &d).tile.h.flags & kTileGatherStore))
                 continue;
         }
         if (run_and_hash(rq, p, stream, 0x5A) != want)

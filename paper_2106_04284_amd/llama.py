@@ -362,6 +362,7 @@ def _stream(stream):
 COPY_NO_DIRECT = 1
 COPY_NO_SPLIT = 2
 COPY_PRESERVE_PADDING = 4
+COPY_NO_GATHER = 8
 
 
 def _options(path=PATH_AUTO, tile_records=0, threads=0, wg_per_cu=0, flags=0):

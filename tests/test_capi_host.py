@@ -204,9 +204,10 @@ def test_default_tile_sizes():
 def test_tile_modes():
     """The tile mode the planner takes: a destination in 16-byte granules of
     one leaf stores from registers; a record-major destination in 4-byte
-    words gathers word by word from the staged source (at most a quarter of
-    the words composite, read byte by byte); a source in granules of one leaf
-    loads into registers; anything else stages both sides.  LLAMA_COPY_NO_DIRECT stages every tile, and a destination whose
+    words gathers word by word from the staged source (each word read as the
+    pieces of it that are one 4-byte window of the source, at most 1.45 reads
+    per word on average); a source in granules of one leaf loads into
+    registers; anything else stages both sides.  LLAMA_COPY_NO_DIRECT stages every tile, and a destination whose
     padding is kept never gathers."""
     def plan(name, a, b, n=1 << 20, **kw):
         r = L.Record(W.RECORDS[name])
@@ -233,19 +234,21 @@ def test_tile_modes():
     assert mode("particle", A, S, n=1000003) == "direct_store"
     assert mode("mixed", AA, S, n=1000003) == "direct_store"
     # a u8 leaf (mixed) or u16 / bool leaves (listing1) share words with
-    # other leaves or padding: those words are composite, read byte by byte
+    # other leaves or padding: those words read two or four pieces
     assert mode("mixed", M, AA) == "gather_store"
     assert mode("mixed", AA, Q8) == "gather_store"
     assert mode("listing1", M, AA) == "gather_store"
-    # the 49-byte packed mixed record: 4 records are whole words, and its
-    # values at odd positions keep their position modulo 4 from one group of
-    # 4 records to the next, so both directions gather (read funnel-shifted)
-    # into AoS and into AoSoA with long lane runs; from SoA into it the words
-    # that straddle two values are too many
+    # the 49-byte packed mixed record: 4 records are whole words.  A word
+    # across two of its values is one piece where the source keeps the bytes
+    # in order (AoS), so both directions between AoS and AoSoA gather; from
+    # SoA or AoSoA most of its words read two pieces (1.65 reads per word):
+    # SoA loads directly, AoSoA stages
     assert mode("mixed", AA, A) == "gather_store"
     assert mode("mixed", A, AA) == "gather_store"
     assert mode("mixed", A, Q32) == "gather_store"
-    assert mode("mixed", A, Q8) == "staged"
+    assert mode("mixed", A, Q8) == "gather_store"
+    assert mode("mixed", Q8, A) == "staged"
+    assert mode("mixed", Q32, A) == "staged"
     # from SoA the source loads into registers and each value is written into
     # the packed region in pieces of its alignment (the u8 leaf byte by byte);
     # into SoA each value is read from the aligned words that hold it
@@ -253,17 +256,25 @@ def test_tile_modes():
     assert mode("mixed", A, M) == "direct_store"
     assert mode("mixed", M, A, flags=L.COPY_NO_SPLIT) == "staged"
     assert mode("mixed", A, M, flags=L.COPY_NO_SPLIT) == "staged"
-    # into AoSoA, listing 1's u16 and bool lanes make a quarter of the words
-    # composite: no gather; from SoA its u16 and bool leaves load directly
-    assert mode("listing1", M, Q8) == "direct_load"
+    # into AoSoA from AoS, listing 1's u16 and bool lanes make words of two
+    # and four pieces (1.52 reads per word): staged; from SoA every lane run
+    # is one piece: gather into AoSoA8, and into lane runs of 32 records or
+    # more the source loads directly
     assert mode("listing1", AA, Q32) == "staged"
-    assert mode("mixed", M, Q32) == "gather_store"
-    # LDS with composite words: the source region (leaf spans of 256 records)
-    # plus the word table of a 56-byte aligned record (14 words: 12 whole, the
-    # u8 word composite with its 4 byte sources, one padding word)
+    assert mode("listing1", A, Q8) == "staged"
+    assert mode("listing1", M, Q8) == "gather_store"
+    assert mode("listing1", M, ("aosoa", 64)) == "direct_load"
+    assert mode("mixed", M, Q32) == "direct_load"
+    assert mode("mixed", M, Q32, flags=L.COPY_NO_GATHER) == "direct_load"
+    assert mode("mixed", M, Q8, flags=L.COPY_NO_GATHER) == "direct_load"
+    assert mode("mixed", Q32, AA, flags=L.COPY_NO_GATHER) == "staged"
+    # LDS of a gathering tile: the source region (leaf spans of 256 records)
+    # plus the word table of a 56-byte aligned record (14 word entries, padded
+    # to 16: 12 whole words, the u8 word one piece with its padding, one
+    # padding word)
     p = plan("mixed", M, AA)
     spans = 3 * ((256 * 8 + 30) // 16 * 16) + 6 * ((256 * 4 + 30) // 16 * 16) + (256 + 30) // 16 * 16
-    assert p["tile_records"] == 256 and p["lds_bytes"] == spans + ((14 + 4) * 4 + 15) // 16 * 16
+    assert p["tile_records"] == 256 and p["lds_bytes"] == spans + 16 * 4
     assert mode("particle", A, Q8, flags=L.COPY_NO_DIRECT) == "staged"
     assert mode("lbm", M, AA, flags=L.COPY_PRESERVE_PADDING) == "staged"
     assert mode("particle", A, Q8, n=1031, flags=L.COPY_PRESERVE_PADDING) == "staged"  # 1031 = 128 * 8 + 7

@@ -126,7 +126,9 @@ STREAM_STORE_CASES = [("mixed", 1 << 25, ("aosoa", 8), ("aos_packed", 0), 0, "st
                       ("mixed", 1 << 25, ("aos_packed", 0), ("soa_single", 0), 0, "direct_store"),
                       ("mixed", 1 << 25, ("aos_packed", 0), ("aosoa", 64), 0, "gather_store"),
                       ("mixed", 1 << 25, ("aosoa", 8), ("aos_aligned", 0), 0, "gather_store"),
-                      ("mixed", 1 << 25, ("soa_multi", 0), ("aosoa", 32), 0, "gather_store"),
+                      ("mixed", 1 << 25, ("soa_multi", 0), ("aosoa", 32), 0, "direct_load"),
+                      ("mixed", 1 << 25, ("aosoa", 32), ("aosoa", 8), 0, "gather_store"),
+                      ("mixed", 1 << 25, ("aos_aligned", 0), ("aos_packed", 0), 0, "gather_store"),
                       ("particle", 1 << 26, ("soa_multi", 0), ("aos_packed", 0), 4, "gather_store")]
 
 

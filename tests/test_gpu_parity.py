@@ -251,7 +251,7 @@ SPLIT_DIRECT_CASES = [("mixed", ("aos_packed", 0), ("soa_single", 0), "direct_st
                       ("mixed", ("soa_multi", 0), ("aos_packed", 0), "direct_load"),
                       ("mixed", ("soa_single", 0), ("aos_packed", 0), "direct_load"),
                       ("listing1", ("soa_multi", 0), ("aos_packed", 0), "direct_load"),
-                      ("listing1", ("soa_multi", 0), ("aosoa", 8), "direct_load"),
+                      ("listing1", ("soa_multi", 0), ("aosoa", 32), "direct_load"),
                       ("listing1", ("soa_single", 0), ("aosoa", 64), "direct_load")]
 SPLIT_DIRECT_RUNS = [(1, {}), (77, {}), (1031, {}), (4099, {"tile_records": 16}), (20000, {"threads": 1024}),
                      (30011, {"tile_records": 64, "wg_per_cu": 1})]
