@@ -1201,8 +1201,8 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
         // super-block 0).  A piece is one entry: p0, the source byte that the
         // word's byte 0 lines up with, its run and the word bytes it gives.
         // A word of one piece (or none: padding) is its own table entry; a
-        // word of two pieces points to a pair of entries, of three or four to
-        // a group of four, placed after the word entries.
+        // word of two pieces points to a pair of entries; a word of three or
+        // four to the sources of its 4 bytes, placed after the word entries.
         std::vector<uint32_t> table(gwords), quads, pairs;
         bool pieces_ok = true;
         for (uint64_t w = 0; w < gwords && pieces_ok; w++) {
@@ -1231,11 +1231,11 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
             } else if (n == 2) {
                 table[w] = (1u << 30) | uint32_t(pairs.size());
                 pairs.insert(pairs.end(), piece, piece + 2);
-            } else {
-                while (n < 4)
-                    piece[n++] = 0u; // gives no byte
+            } else { // byte by byte: the source byte of each (bit 31: a zero byte)
                 table[w] = (2u << 30) | uint32_t(quads.size());
-                quads.insert(quads.end(), piece, piece + 4);
+                for (uint32_t k = 0; k < 4; k++)
+                    quads.push_back((x[k] >> 31) ? 1u << 31
+                                                 : (x[k] & 0x3FFFFu) | ((g.q == 0 ? 0u : (x[k] >> 18) & 31u) << 18));
             }
         }
         // groups of four at a 16-byte boundary, then the pairs; a group's
@@ -1294,7 +1294,12 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
         const uint64_t dst_bits = uint64_t(e.dst_pos) | (a.dst.mode == kRecordMajor ? rq.dst.block : 0);
         const bool aligned = lowbit(dst_bits | 16) >= sz;
         const bool whole = sz == 4 || sz == 8 || sz == 16;
-        dload = (sz == 1 || sz == 2 || whole) && granule_runs(a.src, sz) && (e.src_addr & 15) == 0 &&
+        // (a 1- or 2-byte leaf, a small share of a record, also loads from
+        // AoSoA lane runs of 32 bytes and more)
+        const bool runs = granule_runs(a.src, sz) ||
+                          (sz <= 2 && a.src.mode == kRecordMajor && rq.src.block % 16 == 0 &&
+                           rq.src.lanes * sz >= 32 && (rq.src.lanes * sz) % 16 == 0);
+        dload = (sz == 1 || sz == 2 || whole) && runs && (e.src_addr & 15) == 0 &&
                 ((aligned && whole) || (!(p.flags_in & kPlanNoSplit) && (sz <= 8 || aligned)));
         split_dst = split_dst || !aligned || !whole;
         wr_of[f] = std::min<uint32_t>(log2_move(dst_bits | sz), 7u);

@@ -74,8 +74,10 @@ constexpr uint32_t kMoveSplit = 1u << 3;
 // the table describes word w of super-block 0:
 //   bits 31-30 = 00:  the word is one piece, this entry (no byte: padding);
 //   bits 31-30 = 01:  two pieces, the entries at table index bits 0-15;
-//   bits 31-30 = 10:  three or four pieces, the four entries at index bits
-//                     0-15 (16-byte aligned; an unused one gives no byte).
+//   bits 31-30 = 10:  three or four pieces: four entries at index bits 0-15
+//                     (16-byte aligned) give its bytes one by one, entry k the
+//                     LDS byte p0 of byte k in super-block 0 and its run in
+//                     the same bits (bit 31: a zero byte).
 // The word entries are padded to a multiple of 4; the groups of four follow,
 // then the pairs.  Records without values (tail lanes of the last AoSoA
 // block) are cleared in the source region before the tile's words are read.
@@ -150,10 +152,10 @@ constexpr uint32_t kGatherMaxLanes = 128;
 // kGatherMaxReadsPct / 100 piece reads (a word of two pieces reads 2, of three
 // or four 4).  Measured against the staged mode and the direct load: 1.00 to
 // 1.38 reads gain 3-140% (particle, lattice-Boltzmann, mixed and listing 1
-// records), 1.48 breaks even (listing 1 aligned into packed AoS), 1.52 and
-// more lose 11-39% (listing 1's u16 and bool lanes into AoSoA, the 49-byte
-// packed mixed record from SoA or AoSoA)
-constexpr uint32_t kGatherMaxReadsPct = 145;
+// records), 1.48 gains 9% (listing 1 aligned into packed AoS), 1.52 and more
+// lose 11-39% (listing 1's u16 and bool lanes into AoSoA, the 49-byte packed
+// mixed record from SoA or AoSoA)
+constexpr uint32_t kGatherMaxReadsPct = 150;
 
 // The tile's 16-byte destination stores carry the nontemporal hint: set for
 // destinations several times larger than the 256 MB Infinity Cache.

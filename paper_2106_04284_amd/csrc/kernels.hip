@@ -620,6 +620,15 @@ __device__ __forceinline__ uint32_t gather_piece(uint32_t x, uint32_t bq, uint32
     return v & m;
 }
 
+// One byte of a word of three or four pieces: the LDS byte p0 + (blk >> q) *
+// kq + ((blk & (2^q - 1)) << run) (p0 in bits 0-17, run in bits 18-22), or
+// zero (bit 31).
+__device__ __forceinline__ uint32_t gather_byte(uint32_t b, uint32_t bq, uint32_t bm, const uint8_t* lds)
+{
+    const uint32_t v = lds[(b & 0x3FFFFu) + bq + (bm << ((b >> 18) & 31u))];
+    return (b >> 31) ? 0u : v;
+}
+
 // Records without values in a tile's source region ([nv, nd): the tail lanes
 // of the last AoSoA block) read as zero, so that the gather store needs no
 // per-record test: their leaf bytes in LDS are cleared.
@@ -661,16 +670,25 @@ __device__ __forceinline__ void gather_store_tile(const TileHeader& h, const Til
             const uint32_t e = tab[w];
             const uint32_t bq = (blk >> gg.q) * gg.kq, bm = blk & qm;
             const uint32_t kind = e >> 30;
-            uint32_t x;
-            if (kind == 0u) {
-                x = gather_piece(e, bq, bm, lds);
-            } else if (kind == 1u) { // two pieces
-                const uint2 g = *(const uint2*)(tab + (e & 0xFFFFu));
-                x = gather_piece(g.x, bq, bm, lds) | gather_piece(g.y, bq, bm, lds);
-            } else { // four pieces
+            uint32_t x, e1 = kind == 0u ? e : 0u;
+            if (__any(kind == 1u)) {
+                // a wave with words of two pieces reads two for every word
+                // (a second piece of a one-piece word gives no byte), in one
+                // path instead of two divergent ones
+                const uint2 g = *(const uint2*)(tab + (kind == 1u ? (e & 0xFFFFu) : 0u));
+                uint32_t e2 = 0u;
+                if (kind == 1u) {
+                    e1 = g.x;
+                    e2 = g.y;
+                }
+                x = gather_piece(e1, bq, bm, lds) | gather_piece(e2, bq, bm, lds);
+            } else {
+                x = gather_piece(e1, bq, bm, lds);
+            }
+            if (kind == 2u) { // three or four pieces: byte by byte
                 const u32x4 g = *(const u32x4*)(tab + (e & 0xFFFFu));
-                x = gather_piece(g.x, bq, bm, lds) | gather_piece(g.y, bq, bm, lds) |
-                    gather_piece(g.z, bq, bm, lds) | gather_piece(g.w, bq, bm, lds);
+                x = gather_byte(g.x, bq, bm, lds) | (gather_byte(g.y, bq, bm, lds) << 8) |
+                    (gather_byte(g.z, bq, bm, lds) << 16) | (gather_byte(g.w, bq, bm, lds) << 24);
             }
             v[c] = x;
             if (++w == gg.words) {

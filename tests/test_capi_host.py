@@ -242,13 +242,14 @@ def test_tile_modes():
     # across two of its values is one piece where the source keeps the bytes
     # in order (AoS), so both directions between AoS and AoSoA gather; from
     # SoA or AoSoA most of its words read two pieces (1.65 reads per word):
-    # SoA loads directly, AoSoA stages
+    # SoA and AoSoA32 load directly (the u8 leaf from lane runs of 32
+    # bytes), AoSoA8 (8-byte u8 runs) stages
     assert mode("mixed", AA, A) == "gather_store"
     assert mode("mixed", A, AA) == "gather_store"
     assert mode("mixed", A, Q32) == "gather_store"
     assert mode("mixed", A, Q8) == "gather_store"
     assert mode("mixed", Q8, A) == "staged"
-    assert mode("mixed", Q32, A) == "staged"
+    assert mode("mixed", Q32, A) == "direct_load"
     # from SoA the source loads into registers and each value is written into
     # the packed region in pieces of its alignment (the u8 leaf byte by byte);
     # into SoA each value is read from the aligned words that hold it
@@ -267,7 +268,8 @@ def test_tile_modes():
     assert mode("mixed", M, Q32) == "direct_load"
     assert mode("mixed", M, Q32, flags=L.COPY_NO_GATHER) == "direct_load"
     assert mode("mixed", M, Q8, flags=L.COPY_NO_GATHER) == "direct_load"
-    assert mode("mixed", Q32, AA, flags=L.COPY_NO_GATHER) == "staged"
+    assert mode("mixed", Q32, AA, flags=L.COPY_NO_GATHER) == "direct_load"
+    assert mode("mixed", Q8, AA, flags=L.COPY_NO_GATHER) == "staged"
     # LDS of a gathering tile: the source region (leaf spans of 256 records)
     # plus the word table of a 56-byte aligned record (14 word entries, padded
     # to 16: 12 whole words, the u8 word one piece with its padding, one
