@@ -7,6 +7,7 @@ import os
 import random
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -305,6 +306,35 @@ def test_tile_modes():
     p = plan("particle", A, Q8)
     assert p["tile_records"] == 512
     assert p["lds_bytes"] == (512 * 28 + 30) // 16 * 16 + 8 * 28
+
+
+_GATHER_READS = r"""
+import sys
+from paper_2106_04284_amd import llama as L, workloads as W
+for name, a, b in [("particle", ("aos_packed", 0), ("aosoa", 8)), ("mixed", ("soa_multi", 0), ("aos_aligned", 0)),
+                   ("mixed", ("aos_packed", 0), ("aosoa", 8)), ("listing1", ("soa_multi", 0), ("aos_aligned", 0))]:
+    r = L.Record(W.RECORDS[name])
+    print("PAIR", name, a[0], a[1], b[0], b[1], file=sys.stderr, flush=True)
+    L.plan(L.Mapping(r, a[0], [1 << 20], a[1]), L.Mapping(r, b[0], [1 << 20], b[1]))
+"""
+
+
+def test_gather_piece_reads():
+    """The gather store's cost model, read from the plan log: every word of a
+    destination super-block reads one piece, two (a word across two values
+    or records) or four bytes one by one (three or four pieces).  Counted by
+    hand from the layouts: AoSoA8 particles from packed AoS, 56 words of one
+    piece each (each lane run's words are one value's bytes); the mixed
+    record's 56-byte aligned record from SoA, 14 words of one piece (its u8
+    word is one piece and three padding bytes); the mixed record's AoSoA8
+    from packed AoS, 98 words of which the two u8-lane words take 4 bytes
+    from 4 records (98 + 2 x 3 reads); listing 1's 32-byte aligned record
+    from SoA, 8 words of which the three bools share one (8 + 3 reads)."""
+    env = dict(os.environ, LLAMA_TRACE="1")
+    out = subprocess.run([sys.executable, "-c", _GATHER_READS], env=env, capture_output=True, text=True,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))), check=True).stderr
+    got = re.findall(r"mode=gather_\w+ .*?words=(\d+) reads=(\d+)", out)
+    assert [(int(w), int(r)) for w, r in got] == [(56, 56), (14, 14), (98, 104), (8, 11)], out
 
 
 @pytest.mark.parametrize("name", ["particle", "mixed", "lbm", "listing1"])
