@@ -9,8 +9,8 @@
 //     stay within the budget and no admitted range conflicts with a range in
 //     flight; a group closes once its bytes reach group_bytes; the admitted
 //     requests form one work table, uploaded from pinned memory and run by
-//     the persistent batch kernel on that slot's stream (a group of one
-//     request is launched as that request's own copy).
+//     the batch kernels on that slot's stream, one launch per tile mode (a
+//     group of one request is launched as that request's own copy).
 // Each stream holds up to `depth` launches, so the next launches wait on the
 // device while one runs, and launches on different streams overlap.  Batched:
 // requests never wait to be batched.  A request of group_bytes or more runs
@@ -225,6 +225,9 @@ void Server::launch_slot(Slot& s, std::vector<Pending>& group)
                 t.add(c.rq, cfg.threads, 0);
         }
         if (t.units > 0) {
+            // one launch per tile mode, each mode's own compiled body, like a
+            // batch (the default of llama_batch_create)
+            const std::vector<BatchRange> ranges = kBatchByModeDefault ? t.sort_by_mode() : std::vector<BatchRange>{};
             const size_t bytes = t.bytes();
             ensure_capacity(s, bytes);
             BatchArgs args{};
@@ -235,8 +238,12 @@ void Server::launch_slot(Slot& s, std::vector<Pending>& group)
             check_hip(hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice, upload), "hipMemcpyAsync(table)");
             check_hip(hipEventRecord(s.uploaded, upload), "hipEventRecord(upload)");
             check_hip(hipStreamWaitEvent(s.stream, s.uploaded, 0), "hipStreamWaitEvent(upload)");
-            const uint32_t w = batch_per_unit(t) ? 0 : batch_wg_per_cu(t.lds_bytes, cfg.threads);
-            launch_batch_args(args, batch_grid(t.units, w), cfg.threads, t.lds_bytes, w != 0, s.stream);
+            if (!ranges.empty()) {
+                launch_batch_ranges(args, ranges, cfg.threads, s.stream);
+            } else {
+                const uint32_t w = batch_per_unit(t) ? 0 : batch_wg_per_cu(t.lds_bytes, cfg.threads);
+                launch_batch_args(args, batch_grid(t.units, w), cfg.threads, t.lds_bytes, w != 0, s.stream);
+            }
         }
     } else {
         llama_copy_options o{cfg.policy == LLAMA_SERVE_NAIVE ? uint32_t(LLAMA_PATH_NAIVE) : uint32_t(LLAMA_PATH_AUTO),
