@@ -50,7 +50,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 # CPUs this process may run on, read before any OpenMP runtime pins the thread
-AFFINITY_CPUS = len(os.sched_getaffinity(0))
+START_CPUS = os.sched_getaffinity(0)
+AFFINITY_CPUS = len(START_CPUS)
 # the threaded CPU oracle runs one thread per core, each pinned (sec. 4 setup);
 # OpenMP reads these when it starts
 os.environ.setdefault("OMP_PROC_BIND", "close")
@@ -600,9 +601,18 @@ def _serve_run(L, setup, policy, rate, **server_options):
 def bench_serve(L, torch, args, dev):
     """Poisson requests replayed against the server with three policies:
     continuous batching, one naive kernel per request, one llama_copy per
-    request.  Arrival rate: rho (0.5 and 0.8) times the GB/s of the batching
-    workload's single launch, measured first in the same process."""
+    request.  Arrival rate: rho (0.5 and 0.8) times the service capacity, the
+    GB/s of the batched server at saturation (every request submitted at
+    once), measured first in the same process.  (Taken from the batching
+    workload's single launch instead, the offered load followed a 3-launch
+    median that varied by 5% from run to run, and at 80% the latency with
+    it: p50 0.4 or 3 ms on one box.)"""
     import time as _t
+    # the OpenMP settings above bind the main thread to one core once torch
+    # starts its OpenMP runtime; the server's engine thread would inherit that
+    # core and share it with the replay loop below (at 80% load: p50 2.1
+    # instead of 0.27 ms, p99 7-9 instead of 1.9-2.1 ms)
+    os.sched_setaffinity(0, START_CPUS)
     stream = torch.cuda.current_stream()
     items, total, _ = _batch_items(L, torch, stream)
     b = L.Batch(items)
@@ -612,7 +622,7 @@ def bench_serve(L, torch, args, dev):
     del items, b
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    log(f"serve: batching workload runs at {batch_gbs:.1f} GB/s; it sets the arrival rates")
+    log(f"serve: batching workload runs at {batch_gbs:.1f} GB/s")
     setup = _serve_setup(L, torch, args.requests)
     reqs, warm, count = setup["reqs"], setup["warm"], args.requests
 
@@ -628,14 +638,15 @@ def bench_serve(L, torch, args, dev):
     log(f"serve: per-request llama_copy at saturation {capacity_per_request['gbs']} GB/s")
     by_rho = {}
     policies = [("batched", 0), ("naive", 1), ("per_request", 2)]
+    service_gbs = capacity["gbs"]
     for n_rho, rho in enumerate(sorted({0.5, args.rho})):
-        rate = rho * batch_gbs * 1e9 / mean_bytes
+        rate = rho * service_gbs * 1e9 / mean_bytes
         log(f"serve: offered load rho={rho} -> {rate:.0f} requests/s")
         # the policies in rotated order from one load to the next, so that no
         # policy always runs first (or right after the naive one's backlog)
         order = policies[n_rho % 3:] + policies[:n_rho % 3]
         res = {name: run(pol, rate) for name, pol in order}
-        by_rho[rho] = {"rate_per_s": round(rate, 1), "offered_gbs": round(rho * batch_gbs, 1),
+        by_rho[rho] = {"rate_per_s": round(rate, 1), "offered_gbs": round(rho * service_gbs, 1),
                        "order": [name for name, _ in order], **res}
     out = by_rho[args.rho]
     return {"metric": METRIC, "value": out["batched"]["gbs"], "unit": "GB/s", "n_gpus": 1, "steps": count,
@@ -644,7 +655,8 @@ def bench_serve(L, torch, args, dev):
             "config": {"workload": "serving: Poisson arrivals, payload log-uniform 64 KB..1 GB, particle or mixed "
                                    "record, random ordered layout pair of 42, HBM admission budget 64 GB",
                        "rho": args.rho, "rate_per_s": out["rate_per_s"], "requests": count, "warmup_requests": warm,
-                       "mean_request_bytes": round(mean_bytes), "batching_workload_gbs": round(batch_gbs, 1)},
+                       "mean_request_bytes": round(mean_bytes), "service_capacity_gbs": service_gbs,
+                       "batching_workload_gbs": round(batch_gbs, 1)},
             "p50_ms": out["batched"]["p50_ms"], "p99_ms": out["batched"]["p99_ms"],
             "extras": {"server_saturation_gbs": capacity["gbs"], "saturation_batched": capacity,
                        "saturation_per_request": capacity_per_request,
