@@ -130,6 +130,9 @@ def cpu_baseline(record, layouts, pairs, n_single, n_full, budget_single_s=6.0, 
     core) over pairs at the full n_full records, and host memcpy of one full
     layout at 1 and at all threads (the reference line of sec. 4.2)."""
     from oracle import oracle as orc
+    # the calling thread is the OpenMP team's first thread: it takes the
+    # first core, the others one core each
+    os.sched_setaffinity(0, {min(START_CPUS)})
     ro = orc.Record(record)
     threads = orc.max_threads()
 
@@ -608,11 +611,6 @@ def bench_serve(L, torch, args, dev):
     median that varied by 5% from run to run, and at 80% the latency with
     it: p50 0.4 or 3 ms on one box.)"""
     import time as _t
-    # the OpenMP settings above bind the main thread to one core once torch
-    # starts its OpenMP runtime; the server's engine thread would inherit that
-    # core and share it with the replay loop below (at 80% load: p50 2.1
-    # instead of 0.27 ms, p99 7-9 instead of 1.9-2.1 ms)
-    os.sched_setaffinity(0, START_CPUS)
     stream = torch.cuda.current_stream()
     items, total, _ = _batch_items(L, torch, stream)
     b = L.Batch(items)
@@ -884,6 +882,12 @@ def main():
         sys.exit(2)
 
     import torch
+    # the OpenMP settings above bind the main thread to one core once torch
+    # starts its OpenMP runtime; every thread started later (the HIP
+    # runtime's, a server's engine thread) would inherit that one core (the
+    # serving replay at 80% load: p50 2.1 instead of 0.27 ms, p99 7-9
+    # instead of 1.9-2.1 ms)
+    os.sched_setaffinity(0, START_CPUS)
     from paper_2106_04284_amd import llama as L
     L.lib()  # fails loudly when the HIP library has not been built
     if not torch.cuda.is_available():
