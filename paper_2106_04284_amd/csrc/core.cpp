@@ -1180,9 +1180,9 @@ bool fill_tile(const Request& rq, uint32_t T, uint32_t lds_limit, Plan& p)
             g.q = a.src.log2_lanes - g.lg;
             g.kq = uint32_t(rq.src.block);
         }
-        // the kernel's word classification: the source of every byte of
-        // destination super-block 0 (LDS byte for super-block 0, log2 of the
-        // bytes of recs values, record), then a kind per word
+        // the source of every byte of destination super-block 0 (LDS byte
+        // for super-block 0, log2 of the bytes of recs values, record; bit
+        // 31: padding), from which each word's pieces follow
         std::vector<uint32_t> src_of(gwords * 4, 1u << 31);
         for (size_t f = 0; f < F; f++) {
             const TileEntry& e = ta.e[f];

@@ -146,15 +146,16 @@ constexpr uint32_t kTilePreserve = 4;
 // source with more lanes per block than the destination (field-major
 // included) needs leaf sizes that are powers of two.
 constexpr uint32_t kTileGatherStore = 8;
-constexpr uint32_t kGatherMaxWords = 4096; // word table entries (16 KiB of LDS without composite words)
+constexpr uint32_t kGatherMaxWords = 4096; // words per super-block (16 KiB of word entries in LDS)
 constexpr uint32_t kGatherMaxLanes = 128;
 // the gather store takes a tile while its words average at most
 // kGatherMaxReadsPct / 100 piece reads (a word of two pieces reads 2, of three
-// or four 4).  Measured against the staged mode and the direct load: 1.00 to
-// 1.38 reads gain 3-140% (particle, lattice-Boltzmann, mixed and listing 1
-// records), 1.48 gains 9% (listing 1 aligned into packed AoS), 1.52 and more
-// lose 11-39% (listing 1's u16 and bool lanes into AoSoA, the 49-byte packed
-// mixed record from SoA or AoSoA)
+// or four 4).  Measured against the mode taken without it (staged or direct
+// load): 1.00 to 1.38 reads gain up to 140% (particle, lattice-Boltzmann,
+// mixed and listing 1 records; one pair -1%), 1.48 gains 22% (listing 1
+// aligned into packed AoS), 1.52 gives -17 to +9% (listing 1's u16 and bool
+// lanes into AoSoA), 1.65 and more lose 24-27% to the direct load (the
+// 49-byte packed mixed record and listing 1's from SoA or AoSoA)
 constexpr uint32_t kGatherMaxReadsPct = 150;
 
 // The tile's 16-byte destination stores carry the nontemporal hint: set for
@@ -163,10 +164,10 @@ constexpr uint32_t kTileStreamStores = 16;
 // The tile's source loads carry the nontemporal hint: set for sources at
 // least as large as the Infinity Cache.
 constexpr uint32_t kTileStreamLoads = 32;
-// A gathering tile whose table has whole words at odd positions (read
-// funnel-shifted) or whose destination blocks are not whole words (a span
-// can end inside a word): the gather runs in its own kernel variant, so that
-// the common case keeps its registers.
+// A gathering tile whose destination blocks are not whole words (a packed
+// record of odd size: a span can end inside a word, whose bytes are written
+// one by one): the gather runs in its own kernel variant, so that the common
+// case keeps its registers.
 constexpr uint32_t kTileGatherOdd = 64;
 
 // A source gathered from several parts (a Split source, sec. 3.7): the tile's
