@@ -506,7 +506,9 @@ typedef struct {
 
 /* What a copy of this pair with these options would launch, without blobs:
  * the plan assumes distinct blobs aligned to 256 bytes (a real copy plans for
- * its actual blob addresses, which can change alignment-dependent choices). */
+ * its actual blob addresses, which can change alignment-dependent choices).
+ * With the environment variable LLAMA_TRACE set (and not "0"), the plan is
+ * also printed to stderr, as every launch's plan is. */
 int llama_plan(const llama_mapping_desc* src, const llama_mapping_desc* dst, const llama_copy_options* options,
                llama_plan_info* info);
 
